@@ -1,0 +1,261 @@
+"""Seeded synthetic hair workloads shared by the oracle tests, the GPU tests and the benchmark.
+
+This module only *makes inputs*: strand polylines, per-strand width and absorption, the
+cluster assignment fed to the LoD builder, cameras and lights.  It holds none of the
+rendering method's arithmetic (no projection, coverage, scattering or compositing), so both
+the CPU oracle and the HIP path can consume its arrays without sharing method code.
+
+The paper measures on artist and captured grooms that are not available here; these
+generators stand in for them with the shapes and scales the paper describes (tens of
+thousands to a few hundred thousand strands, 16-64 segments each, roots on a scalp-like
+sphere cap, 1024^2-class images; paper Sec. 6 "Hairstyles", "Real-time performance").
+
+Recipe (all float64, stored float32):
+  * rng = numpy Generator(PCG64(seed)); draws in this order: U[n], V[n] for the roots,
+    then for each step (step-major, all strands at once) a standard normal (n, 3) block,
+    then (optionally) one standard normal z[n] for the absorption spread.
+  * roots on a sphere cap of radius 0.1 about +y, area-uniform:
+    cos(theta) = 1 - U (1 - cos(cap)), azimuth = 2 pi V; first direction = outward normal.
+  * per step: d <- normalize(d + 0.3 N(0, I3) + (0, -0.2, 0)); x <- x + 0.01 d.
+  * width 80e-6 m (a diameter); sigma_a = (0.3, 0.6, 1.2), optionally times exp(0.2 z).
+  * material: eta 1.55, longitudinal shift -3 deg, beta_m = beta_n = 0.3 rad.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "Material", "Asset", "Camera", "Light", "make_asset", "kmeans_assign",
+    "camera_for", "ring_cameras", "default_lights", "config", "CONFIGS",
+]
+
+
+@dataclass
+class Material:
+    eta: float = 1.55
+    alpha: float = math.radians(-3.0)   # longitudinal shift (radians)
+    beta_m: float = 0.3                  # longitudinal width (radians, std dev)
+    beta_n: float = 0.3                  # azimuthal width (radians, std dev)
+
+    def as_array(self) -> np.ndarray:
+        return np.array([self.eta, self.alpha, self.beta_m, self.beta_n], dtype=np.float32)
+
+
+@dataclass
+class Asset:
+    """Strand polylines in structure-of-arrays form.
+
+    xyz:     float32 [3, n_strands * (segs + 1)]  (x row, y row, z row), world metres.
+             Vertex k of strand s sits at column s * (segs + 1) + k.
+    width:   float32 [n_strands]  fibre diameter (m).
+    sigma_a: float32 [3, n_strands] absorption per unit fibre radius (RGB rows).
+    """
+    n_strands: int
+    segs: int
+    xyz: np.ndarray
+    width: np.ndarray
+    sigma_a: np.ndarray
+    material: Material = field(default_factory=Material)
+
+    @property
+    def verts_per_strand(self) -> int:
+        return self.segs + 1
+
+    @property
+    def n_segments(self) -> int:
+        return self.n_strands * self.segs
+
+    def roots(self) -> np.ndarray:
+        v = self.verts_per_strand
+        return self.xyz[:, 0::v].T.astype(np.float64)
+
+    def first_tangents(self) -> np.ndarray:
+        v = self.verts_per_strand
+        d = (self.xyz[:, 1::v] - self.xyz[:, 0::v]).T.astype(np.float64)
+        return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+    def aabb(self):
+        return self.xyz.min(axis=1).astype(np.float64), self.xyz.max(axis=1).astype(np.float64)
+
+
+@dataclass
+class Camera:
+    """Pinhole camera. rot is row-major world->view; the view looks along -z, y up.
+
+    Pixel (i, j) has its centre at (i + 0.5, j + 0.5); x grows right, y grows down.
+    """
+    pos: np.ndarray          # float32 [3]
+    rot: np.ndarray          # float32 [3, 3]
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    width: int
+    height: int
+    z_near: float = 0.01
+
+    def packed(self) -> np.ndarray:
+        """float32[18]: pos(3) rot(9) fx fy cx cy z_near pad  (W, H travel as ints)."""
+        out = np.zeros(18, dtype=np.float32)
+        out[0:3] = self.pos
+        out[3:12] = np.asarray(self.rot, dtype=np.float32).reshape(9)
+        out[12:17] = (self.fx, self.fy, self.cx, self.cy, self.z_near)
+        return out
+
+
+@dataclass
+class Light:
+    kind: int                # 0 = directional (vec = unit direction toward the light), 1 = point (vec = position)
+    vec: np.ndarray          # float32 [3]
+    rgb: np.ndarray          # float32 [3]: irradiance E (directional) or intensity I (point)
+
+
+def _normalize(v: np.ndarray) -> np.ndarray:
+    return v / np.linalg.norm(v, axis=-1, keepdims=True)
+
+
+def make_asset(n_strands: int, segs: int, cap_deg: float = 90.0, seed: int = 0,
+               sigma_spread: bool = False, material: Material | None = None) -> Asset:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = int(n_strands)
+    U = rng.random(n)
+    V = rng.random(n)
+    cos_cap = math.cos(math.radians(cap_deg))
+    cos_t = 1.0 - U * (1.0 - cos_cap)
+    sin_t = np.sqrt(np.maximum(0.0, 1.0 - cos_t * cos_t))
+    az = 2.0 * math.pi * V
+    normal = np.stack([sin_t * np.cos(az), cos_t, sin_t * np.sin(az)], axis=1)
+    x = 0.1 * normal
+    d = normal.copy()
+    verts = np.empty((n, segs + 1, 3), dtype=np.float64)
+    verts[:, 0] = x
+    drift = np.array([0.0, -0.2, 0.0])
+    for k in range(segs):
+        d = _normalize(d + 0.3 * rng.standard_normal((n, 3)) + drift)
+        x = x + 0.01 * d
+        verts[:, k + 1] = x
+    xyz = np.ascontiguousarray(verts.reshape(n * (segs + 1), 3).T.astype(np.float32))
+    width = np.full(n, 80e-6, dtype=np.float32)
+    base = np.array([0.3, 0.6, 1.2])
+    if sigma_spread:
+        z = rng.standard_normal(n)
+        sig = base[:, None] * np.exp(0.2 * z)[None, :]
+    else:
+        sig = np.repeat(base[:, None], n, axis=1)
+    return Asset(n, segs, xyz, width, np.ascontiguousarray(sig.astype(np.float32)),
+                 material or Material())
+
+
+def kmeans_assign(asset: Asset, k: int, seed: int, iters: int = 25) -> np.ndarray:
+    """Cluster assignment used as the LoD builder's input (int32 [n_strands], dense labels).
+
+    Features: [root / 0.1, first-segment tangent] (6-D, float64).  k-means++ seeding drawn
+    from PCG64(seed), then `iters` Lloyd iterations; distance ties go to the lower centre
+    index (argmin); empty clusters are dropped and labels renumbered densely in order.
+    """
+    feats = np.concatenate([asset.roots() / 0.1, asset.first_tangents()], axis=1)
+    n = feats.shape[0]
+    k = min(int(k), n)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    centres = np.empty((k, feats.shape[1]))
+    first = int(rng.integers(n))
+    centres[0] = feats[first]
+    d2 = ((feats - centres[0]) ** 2).sum(1)
+    for c in range(1, k):
+        tot = d2.sum()
+        if tot <= 0.0:
+            idx = int(rng.integers(n))
+        else:
+            r = rng.random() * tot
+            idx = int(np.searchsorted(np.cumsum(d2), r, side="right"))
+            idx = min(idx, n - 1)
+        centres[c] = feats[idx]
+        d2 = np.minimum(d2, ((feats - centres[c]) ** 2).sum(1))
+
+    def assign(cent):
+        lab = np.empty(n, dtype=np.int64)
+        cn = (cent ** 2).sum(1)
+        step = max(1, int(2e7 // max(1, k)))
+        for s in range(0, n, step):
+            f = feats[s:s + step]
+            dist = (f ** 2).sum(1)[:, None] - 2.0 * f @ cent.T + cn[None, :]
+            lab[s:s + step] = np.argmin(dist, axis=1)
+        return lab
+
+    lab = assign(centres)
+    for _ in range(iters):
+        cnt = np.bincount(lab, minlength=k).astype(np.float64)
+        sums = np.zeros_like(centres)
+        np.add.at(sums, lab, feats)
+        nz = cnt > 0
+        centres[nz] = sums[nz] / cnt[nz, None]
+        lab = assign(centres)
+    used = np.unique(lab)
+    remap = np.full(k, -1, dtype=np.int64)
+    remap[used] = np.arange(used.size)
+    return remap[lab].astype(np.int32)
+
+
+def _look_at(pos: np.ndarray, target: np.ndarray) -> np.ndarray:
+    back = _normalize(pos - target)
+    up = np.array([0.0, 1.0, 0.0])
+    right = _normalize(np.cross(up, back))
+    up2 = np.cross(back, right)
+    return np.stack([right, up2, back])
+
+
+def camera_for(asset: Asset, width: int, height: int, azimuth: float = 0.0,
+               fill: float = 0.9, fov_y_deg: float = 30.0) -> Camera:
+    """Frame the asset's AABB: its bounding sphere spans `fill` of the half-height."""
+    lo, hi = asset.aabb()
+    centre = 0.5 * (lo + hi)
+    radius = 0.5 * float(np.linalg.norm(hi - lo))
+    half = math.radians(fov_y_deg) / 2.0
+    dist = radius / (fill * math.tan(half))
+    pos = centre + dist * np.array([math.sin(azimuth), 0.0, math.cos(azimuth)])
+    rot = _look_at(pos, centre)
+    fy = (height / 2.0) / math.tan(half)
+    return Camera(pos.astype(np.float32), rot.astype(np.float32), float(np.float32(fy)),
+                  float(np.float32(fy)), width / 2.0, height / 2.0, width, height, 0.01)
+
+
+def ring_cameras(asset: Asset, n: int, width: int, height: int) -> list[Camera]:
+    return [camera_for(asset, width, height, azimuth=2.0 * math.pi * k / n) for k in range(n)]
+
+
+def default_lights(asset: Asset, with_point: bool) -> list[Light]:
+    lo, hi = asset.aabb()
+    centre = 0.5 * (lo + hi)
+    d = np.array([0.5, 0.6, 0.6])
+    d = d / np.linalg.norm(d)
+    lights = [Light(0, d.astype(np.float32), np.ones(3, dtype=np.float32))]
+    if with_point:
+        p = centre + np.array([-0.3, 0.1, -0.4])
+        lights.append(Light(1, p.astype(np.float32), np.full(3, 0.25, dtype=np.float32)))
+    return lights
+
+
+# The five workloads.  Sizes follow the paper's scales (Sec. 6); the generator recipe is above.
+CONFIGS = {
+    1: dict(strands=1_000, segs=16, cap=60.0, res=(256, 256), point=False, spread=False),
+    2: dict(strands=100_000, segs=32, cap=90.0, res=(1920, 1080), point=True, spread=True),
+    3: dict(strands=150_000, segs=64, cap=90.0, res=(1920, 1080), point=True, spread=True,
+            levels=(10_000, 1_000, 100)),
+    4: dict(strands=50_000, segs=32, cap=90.0, res=(512, 512), point=False, spread=False,
+            levels=(500,), views=8),
+    5: dict(assets=((10_000, 16), (100_000, 32), (300_000, 48)), cap=90.0, point=True, spread=True,
+            resolutions=((1280, 720), (1920, 1080), (3840, 2160))),
+}
+
+
+def config(cfg: int, scale: float = 1.0):
+    """(asset, camera, lights) for configs 1-4; `scale` shrinks the strand count for tests."""
+    c = CONFIGS[cfg]
+    n = max(1, int(round(c["strands"] * scale)))
+    asset = make_asset(n, c["segs"], c["cap"], seed=1000 + cfg, sigma_spread=c["spread"])
+    w, h = c["res"]
+    cam = camera_for(asset, w, h)
+    return asset, cam, default_lights(asset, c["point"])

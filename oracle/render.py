@@ -1,0 +1,275 @@
+"""Per-fragment radiance and depth-ordered compositing (oracle).
+
+  * Radiance of a fragment: L = sum over lights of E * f(omega_i, omega_o, h) * cos(theta_i)
+    (Sec. 3, the fibre rendering equation with a directional or point light: f cos^2 theta_i
+    d theta_i d phi_i = f cos theta_i d omega_i).  A directional light has irradiance E; a
+    point light E = I / |x_L - x|^2.  No shadowing between hairs.
+  * Shading frame: u = unit segment tangent, omega_o toward the camera from the fragment's
+    world point (perspective-correct parameter t_w = t izB / iz), x^ = normalize(omega_o -
+    (omega_o . u) u), y^ = u x x^, sin theta = omega . u, phi = phi_o - phi_i =
+    -atan2(omega_i . y^, omega_i . x^) (phi = 0 when |omega_o - (omega_o . u) u| < 1e-7).
+  * Cross-section offset of a fragment: h = clamp(sigma sgn(e x d) delta / (hw + 1/2), -1, 1),
+    delta the pixel centre's distance to the segment line in pixels and sigma the
+    per-segment sign making h > 0 toward y^: h runs over [-1, 1] across the fragment
+    footprint (half-width hw + 1/2), as a strip coordinate does across a rasterised strip.
+  * Coverage alpha = clamp(min(delta + hw, 1/2) - max(delta - hw, -1/2), 0, 1): a unit box
+    filter across the strip.
+  * Compositing: fragments of a pixel in ascending (key, segment id), front to back,
+    C = sum_k T_k alpha_k L_k, T_0 = 1, T_{k+1} = T_k (1 - alpha_k); output (C, 1 - T_N),
+    premultiplied over transparent black.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import raster as rs
+from .aggregate import ellipse_chord, ellipse_support, f_ours, hair_counts
+from .fiber import angles, f_single
+
+DT = torch.float64
+
+
+@dataclass
+class LevelGeom:
+    """Segments of one LoD level, one row per segment (global segment id = row index)."""
+    kind: str                  # "strand" or "cluster"
+    pA: np.ndarray             # f32 [3, S]
+    pB: np.ndarray             # f32 [3, S]
+    sigma_a: np.ndarray        # f32 [S, 3]
+    width: np.ndarray = None   # f32 [S] strand diameter
+    ahat: np.ndarray = None    # f32 [3, S]
+    a_len: np.ndarray = None   # f32 [S]
+    b_len: np.ndarray = None   # f32 [S]
+    n_total: np.ndarray = None  # i32 [S]
+    r: np.ndarray = None       # f32 [S]
+    cluster: np.ndarray = None  # i64 [S] cluster of each segment
+    seg_in_cluster: np.ndarray = None
+
+
+def strand_level(asset) -> LevelGeom:
+    V, S, n = asset.verts_per_strand, asset.segs, asset.n_strands
+    cols = (np.arange(n)[:, None] * V + np.arange(S)[None, :]).reshape(-1)
+    strand = np.repeat(np.arange(n), S)
+    return LevelGeom("strand", asset.xyz[:, cols].copy(), asset.xyz[:, cols + 1].copy(),
+                     asset.sigma_a.T[strand].copy(), width=asset.width[strand].copy())
+
+
+def cluster_level(lod) -> LevelGeom:
+    K, V, _ = lod["centers"].shape
+    S = V - 1
+    c = lod["centers"]
+    pA = c[:, :-1].reshape(K * S, 3).T.copy()
+    pB = c[:, 1:].reshape(K * S, 3).T.copy()
+    cl = np.repeat(np.arange(K), S)
+    return LevelGeom("cluster", pA, pB, lod["sigma_a"].T[cl].copy(),
+                     ahat=lod["ahat"].reshape(K * S, 3).T.copy(),
+                     a_len=lod["axes"][:, :, 0].reshape(-1).copy(), b_len=lod["axes"][:, :, 1].reshape(-1).copy(),
+                     n_total=lod["n_total"][cl].copy(), r=lod["r"][cl].copy(), cluster=cl,
+                     seg_in_cluster=np.tile(np.arange(S), K))
+
+
+@dataclass
+class Raster:
+    XA: np.ndarray
+    YA: np.ndarray
+    XB: np.ndarray
+    YB: np.ndarray
+    izA: np.ndarray
+    izB: np.ndarray
+    hw: np.ndarray          # f32 half-width (px)
+    hw_fx: np.ndarray
+    vis: np.ndarray
+    sign: np.ndarray        # +-1 per segment
+    # fragments, sorted by (pixel, key, seg)
+    seg: np.ndarray
+    pix: np.ndarray
+    key: np.ndarray
+    t_num: np.ndarray
+    t_den: np.ndarray
+    cross: np.ndarray
+    W: int
+    H: int
+
+
+def segment_records(geom: LevelGeom, cam):
+    c = rs.cam_arrays(cam)
+    XA, YA, zA, izA, okA = rs.project_points(geom.pA, c)
+    XB, YB, zB, izB, okB = rs.project_points(geom.pB, c)
+    if geom.kind == "strand":
+        hw = rs.strand_halfwidth(zA, zB, geom.width, c)
+    else:
+        hw = rs.cluster_halfwidth(geom.pA, geom.pB, zA, zB, geom.ahat, geom.a_len, geom.b_len, c)
+    hw_fx, vis = rs.finalize_segments(XA, YA, XB, YB, okA, okB, hw)
+    return c, XA, YA, XB, YB, izA, izB, hw.astype(np.float32), hw_fx, vis
+
+
+def rasterize(geom: LevelGeom, cam, pix_filter=None) -> Raster:
+    c, XA, YA, XB, YB, izA, izB, hw, hw_fx, vis = segment_records(geom, cam)
+    sign = rs.h_sign(geom.pA, geom.pB, c, XA, YA, XB, YB)
+    seg, pi, pj = rs.candidate_pixels(XA, YA, XB, YB, hw_fx, vis, c["W"], c["H"], pix_filter=pix_filter)
+    ok, t_num, t_den, cross = rs.coverage(XA, YA, XB, YB, hw_fx, seg, pi, pj)
+    seg, pi, pj, t_num, t_den, cross = seg[ok], pi[ok], pj[ok], t_num[ok], t_den[ok], cross[ok]
+    key, _, _ = rs.depth_key(t_num, t_den, izA[seg], izB[seg])
+    pix = pj * c["W"] + pi
+    order = np.lexsort((seg, key, pix))
+    return Raster(XA, YA, XB, YB, izA, izB, hw, hw_fx, vis, sign,
+                  seg[order], pix[order], key[order], t_num[order], t_den[order], cross[order],
+                  c["W"], c["H"])
+
+
+def _t(x):
+    return torch.as_tensor(np.asarray(x, dtype=np.float64), dtype=DT)
+
+
+def _normalize(v):
+    return v / torch.linalg.norm(v, dim=-1, keepdim=True)
+
+
+def fragment_alpha_h(ras: Raster, hw):
+    """alpha and h per fragment (float64).  hw: per-fragment half-width tensor (px)."""
+    cross = _t(ras.cross)
+    delta = torch.abs(cross) / torch.sqrt(_t(ras.t_den)) / 16.0
+    alpha = torch.clamp(torch.minimum(delta + hw, torch.full_like(hw, 0.5))
+                        - torch.maximum(delta - hw, torch.full_like(hw, -0.5)), 0.0, 1.0)
+    sgn = torch.sign(cross) * _t(ras.sign[ras.seg])
+    h = torch.clamp(sgn * delta / (hw + 0.5), -1.0, 1.0)
+    return alpha, h
+
+
+def shading_inputs(geom: LevelGeom, ras: Raster, cam):
+    """World point, tangent u and view direction per fragment (float64)."""
+    s = ras.seg
+    pA = _t(geom.pA[:, s].T)
+    pB = _t(geom.pB[:, s].T)
+    t = _t(ras.t_num) / _t(ras.t_den)
+    izA = _t(ras.izA[s])
+    izB = _t(ras.izB[s])
+    iz = izA + t * (izB - izA)
+    tw = t * izB / iz
+    xw = pA + tw[:, None] * (pB - pA)
+    u = _normalize(pB - pA)
+    wo = _normalize(_t(np.asarray(cam.pos, dtype=np.float32))[None, :] - xw)
+    return xw, u, wo
+
+
+def frame(u, wo):
+    """x^, y^ and the degenerate mask (|omega_o perp| < 1e-7)."""
+    sin_to = (wo * u).sum(-1)
+    wp = wo - sin_to[:, None] * u
+    nrm = torch.linalg.norm(wp, dim=-1)
+    degen = nrm < 1e-7
+    # any vector orthogonal to u serves when the view runs along the fibre
+    helper = torch.zeros_like(u)
+    j = torch.argmin(torch.abs(u), dim=-1)
+    helper[torch.arange(u.shape[0]), j] = 1.0
+    hp = helper - (helper * u).sum(-1, keepdim=True) * u
+    wp = torch.where(degen[:, None], hp, wp)
+    xh = _normalize(wp)
+    yh = torch.linalg.cross(u, xh, dim=-1)
+    return xh, yh, degen, sin_to
+
+
+def light_dirs(light, xw):
+    vec = _t(np.asarray(light.vec, dtype=np.float32))
+    rgb = _t(np.asarray(light.rgb, dtype=np.float32))
+    if light.kind == 0:
+        wi = vec.expand_as(xw)
+        E = rgb.expand(xw.shape[0], 3)
+    else:
+        d = vec[None, :] - xw
+        dist2 = (d * d).sum(-1)
+        wi = d / torch.sqrt(dist2)[:, None]
+        E = rgb[None, :] / dist2[:, None]
+    return wi, E
+
+
+def fragment_radiance(geom: LevelGeom, ras: Raster, cam, lights, mat, params=None):
+    """(alpha [F], L [F, 3]) in float64.
+
+    params (cluster levels, for the gradient oracle): dict of torch tensors
+    'a_len', 'b_len' [S], 'r' [S], 'sigma_a' [S, 3], and 'hw' [S] (the half-width recomputed
+    from them); default: the level's stored values and the float32 half-width.
+    """
+    s = ras.seg
+    xw, u, wo = shading_inputs(geom, ras, cam)
+    xh, yh, degen, sin_to = frame(u, wo)
+    if params is None:
+        hw = _t(ras.hw[s])
+        sig = _t(geom.sigma_a[s])
+    else:
+        hw = params["hw"][s]
+        sig = params["sigma_a"][s]
+    alpha, h = fragment_alpha_h(ras, hw)
+    if geom.kind == "cluster":
+        ahat = _t(geom.ahat[:, s].T)
+        bhat = torch.linalg.cross(u, ahat, dim=-1)
+        if params is None:
+            a_len, b_len, r = _t(geom.a_len[s]), _t(geom.b_len[s]), _t(geom.r[s])
+        else:
+            a_len, b_len, r = params["a_len"][s], params["b_len"][s], params["r"][s]
+        n_total = _t(geom.n_total[s])
+        W = ellipse_support(a_len, b_len, ahat, bhat, yh)
+    L = torch.zeros(len(s), 3, dtype=DT)
+    for light in lights:
+        wi, E = light_dirs(light, xw)
+        sin_ti = (wi * u).sum(-1)
+        phi = -torch.atan2((wi * yh).sum(-1), (wi * xh).sum(-1))
+        phi = torch.where(degen, torch.zeros_like(phi), phi)
+        _, _, th, xd = angles(sin_ti, sin_to)
+        sc = torch.clamp(sin_ti, -1.0, 1.0)
+        cos_ti = torch.sqrt((1.0 - sc) * (1.0 + sc))
+        if geom.kind == "strand":
+            f = f_single(th, xd, phi, h, sig, mat)
+        else:
+            Dp = wi - sin_ti[:, None] * u
+            dn = torch.linalg.norm(Dp, dim=-1)
+            D = Dp / torch.where(dn > 1e-7, dn, torch.ones_like(dn))[:, None]
+            s_star = ellipse_chord(h, W, xh, yh, ahat, bhat, a_len, b_len, D)
+            s_star = torch.where(dn > 1e-7, s_star, torch.zeros_like(s_star))
+            rho, n_F, n_B = hair_counts(phi, s_star, n_total, r, a_len, b_len)
+            f = f_ours(th, xd, phi, h, sig, mat, n_total, rho, n_F, n_B)
+        L = L + E * f * cos_ti[:, None]
+    return alpha, L
+
+
+def composite(ras: Raster, alpha, L):
+    """Front-to-back over per pixel; returns (rgba [H, W, 4] float64 tensor)."""
+    npx = ras.W * ras.H
+    pix = torch.as_tensor(ras.pix, dtype=torch.int64)
+    C = torch.zeros(npx, 3, dtype=DT)
+    T = torch.ones(npx, dtype=DT)
+    if len(ras.pix):
+        first = np.ones(len(ras.pix), dtype=bool)
+        first[1:] = ras.pix[1:] != ras.pix[:-1]
+        start = np.maximum.accumulate(np.where(first, np.arange(len(ras.pix)), 0))
+        rank = np.arange(len(ras.pix)) - start
+        for k in range(int(rank.max()) + 1):
+            sel = torch.as_tensor(np.nonzero(rank == k)[0])
+            p = pix[sel]
+            a = alpha[sel]
+            C = C.index_add(0, p, T[p][:, None] * a[:, None] * L[sel])
+            T = T.index_copy(0, p, T[p] * (1.0 - a))
+    rgba = torch.cat([C, (1.0 - T)[:, None]], dim=1)
+    return rgba.reshape(ras.H, ras.W, 4)
+
+
+def render(geom: LevelGeom, cam, lights, mat, pix_filter=None):
+    """Oracle frame: returns (rgba float64 [H, W, 4] numpy, Raster)."""
+    ras = rasterize(geom, cam, pix_filter=pix_filter)
+    alpha, L = fragment_radiance(geom, ras, cam, lights, mat)
+    return composite(ras, alpha, L).numpy(), ras
+
+
+def select_level(geoms, cam, eps_w: float = 2.0):
+    """Per-request LoD: the coarsest level whose widest visible thick hair (2 hw) is at most
+    eps_w pixels (Sec. 5.1 step 5 with the threshold of Sec. 6, eps_w = 2 px); level 0 (the
+    strands) when none is.  geoms: list ordered finer -> coarser."""
+    for lvl in range(len(geoms) - 1, 0, -1):
+        _, _, _, _, _, _, _, hw, _, vis = segment_records(geoms[lvl], cam)
+        w = 2.0 * hw[vis].astype(np.float64)
+        if w.size == 0 or float(w.max()) <= eps_w:
+            return lvl
+    return 0
