@@ -1,0 +1,210 @@
+/*
+ * hair.h -- C-ABI of the MI355X level-of-detail strand-hair renderer (libhair.so).
+ *
+ * Method: "Real-time Level-of-detail Strand-based Hair Rendering" (arxiv 2405.10565).
+ *   - strands and their elliptical thick-hair (cluster) levels:        Sec. 5.1
+ *   - per-frame hair width and level choice (eps_w = 2 px):            Sec. 5.1 step 5, 5.2, 6
+ *   - single-fibre scattering f = sum_p A_p M_p N_p:                   Sec. 3.1 (eq. bcsdf)
+ *   - aggregated thick-hair scattering f_ours:                         Sec. 4 (eq. our_bcsdf)
+ *   - radiance L = sum_lights E f cos(theta_i):                        Sec. 3 (rendering eq.)
+ * Segments are binned into 16x16-pixel tiles, covered on a 1/16-pixel integer grid, shaded
+ * per fragment and composited per pixel front to back in (depth key, segment id) order.
+ *
+ * Conventions for every entry point:
+ *   - return value: HAIR_OK (0) or a negative HAIR_E* code; on error nothing the caller owns
+ *     has been written and hair_last_error() describes the failure (thread-local string).
+ *   - "host" pointers are read (or written) before the call returns; "device" pointers must
+ *     stay valid until the work enqueued on `stream` completes.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Every kernel of a call
+ *     runs on it; calls that read results back to the host synchronise it.
+ *   - memory the library allocates (assets, LoD levels, workspaces) counts against the
+ *     context's HBM budget; exceeding it returns HAIR_ENOMEM and allocates nothing.
+ *   - a context may be used from several threads; renders on distinct workspaces may run
+ *     concurrently.  One workspace serves one call at a time.
+ *   - a HIP runtime error makes the call return HAIR_EDEVICE and poisons the context: every
+ *     later call on it fails with HAIR_EDEVICE.
+ */
+#ifndef HAIR_H
+#define HAIR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HAIR_OK 0
+#define HAIR_EINVAL (-1)   /* bad shape, non-finite value, out-of-range argument */
+#define HAIR_ENOMEM (-2)   /* the HBM budget (or the device) cannot hold the request */
+#define HAIR_ENOENT (-3)   /* unknown asset or level */
+#define HAIR_EDEVICE (-4)  /* no usable device or a HIP error (context poisoned) */
+#define HAIR_ERANGE (-5)   /* the frame exceeds a fixed capacity (see hair_stats) */
+
+#define HAIR_MAX_LIGHTS 8
+
+typedef struct hair_ctx hair_ctx;
+typedef struct hair_ws hair_ws;
+
+/* Fibre material (Sec. 6 parameter ranges): relative index eta, longitudinal shift alpha
+ * (radians, R lobe; TT and TRT use -alpha/2 and -3 alpha/2), longitudinal width beta_m
+ * (radians, standard deviation of theta_h for R; TT and TRT use beta_m/2 and 2 beta_m),
+ * azimuthal width beta_n (radians, standard deviation). */
+typedef struct hair_material {
+    float eta, alpha, beta_m, beta_n;
+} hair_material;
+
+/* Pinhole camera.  rot: row-major world->view rotation; the view looks along -z with +y up.
+ * Pixel (i, j) has its centre at (i + 0.5, j + 0.5) with x right and y down:
+ * x = cx + fx * vx / (-vz), y = cy - fy * vy / (-vz).  Points nearer than z_near are culled. */
+typedef struct hair_camera {
+    float pos[3];
+    float rot[9];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    float z_near;
+} hair_camera;
+
+/* kind 0: directional, vec = unit direction toward the light, rgb = irradiance E.
+ * kind 1: point, vec = position (m), rgb = intensity I (E = I / distance^2). */
+typedef struct hair_light {
+    int32_t kind;
+    float vec[3];
+    float rgb[3];
+} hair_light;
+
+/* Filled by hair_render when non-NULL (the call then synchronises its stream). */
+typedef struct hair_stats {
+    uint64_t fragments;          /* accepted (segment, pixel) fragments */
+    uint64_t pairs;              /* (tile, segment) binning pairs */
+    uint32_t segments;           /* segments of the level */
+    uint32_t segments_visible;   /* after near-plane, guard-band and size culling */
+    uint32_t segments_culled_long; /* culled for exceeding 1024 px per axis or 256 px half-width */
+    uint32_t overflow_pixels;    /* pixels deeper than HAIR_PIXEL_CAPACITY fragments (left 0) */
+    float ms_total;              /* GPU time of the call's kernels (hipEvent) */
+    float ms_project, ms_bin, ms_tile;
+} hair_stats;
+
+#define HAIR_PIXEL_CAPACITY 2048   /* most fragments one pixel may hold */
+#define HAIR_TILE 16               /* tile edge (pixels) */
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int hair_version(void);
+
+/* Thread-local description of the last failure on the calling thread. */
+const char* hair_last_error(void);
+
+/* Number of HIP devices (0 when none); never fails. */
+int hair_device_count(void);
+
+/* Create a context on HIP device `device` with an HBM budget in bytes (0 = 90% of the
+ * device's memory).  device = -1 makes a host-only context: every call validates its
+ * arguments and then returns HAIR_EDEVICE without touching a device (used to test argument
+ * checking on machines without a GPU).  *out receives the context. */
+int hair_ctx_create(int32_t device, uint64_t hbm_budget_bytes, hair_ctx** out);
+int hair_ctx_destroy(hair_ctx* ctx);
+/* Bytes the context holds and its budget. */
+int hair_ctx_memory(hair_ctx* ctx, uint64_t* used_bytes, uint64_t* budget_bytes);
+
+/* A render workspace: per-call scratch (segment records, tile lists) that grows on demand up
+ * to max_bytes (0 = no limit beyond the context budget).  One workspace per concurrent
+ * render stream. */
+int hair_ws_create(hair_ctx* ctx, uint64_t max_bytes, hair_ws** out);
+int hair_ws_destroy(hair_ws* ws);
+/* Bytes a render of n_segments at width x height needs in a workspace (upper bound used
+ * for admission control); pairs_estimate = expected (tile, segment) pairs (0 = 4 per segment). */
+uint64_t hair_ws_estimate(int64_t n_segments, int32_t width, int32_t height, int64_t pairs_estimate);
+
+/* Upload a strand asset (Sec. 5.1 input: strand polylines, per-strand width and absorption).
+ *   xyz_soa     host float[3][n_strands * verts_per_strand]: x row, y row, z row (metres);
+ *               vertex k of strand s at column s * verts_per_strand + k.
+ *   width       host float[n_strands]: fibre diameter (m), > 0.
+ *   sigma_a_soa host float[3][n_strands]: absorption per unit fibre radius (RGB), >= 0.
+ *   material    host, see hair_material (eta > 1, beta_m > 0, beta_n > 0).
+ * verts_per_strand >= 2.  All values finite.  *asset_out receives the asset id; level 0 is
+ * the strands.  Data stays resident in HBM until hair_release or hair_ctx_destroy. */
+int hair_upload(hair_ctx* ctx, int32_t n_strands, int32_t verts_per_strand,
+                const float* xyz_soa, const float* width, const float* sigma_a_soa,
+                const hair_material* material, void* stream, int32_t* asset_out);
+int hair_release(hair_ctx* ctx, int32_t asset);
+
+/* Build thick-hair levels 1..n_levels from cluster assignments (Sec. 5.1 steps 2-3), on the
+ * device.  n_clusters host int[n_levels] (finer -> coarser); assign host int[n_levels][n_strands]
+ * with values in [0, n_clusters[l]), every cluster non-empty.  Per level and cluster:
+ * centre polyline = member mean of each vertex (float64 sums in member order); per segment
+ * the 2x2 covariance of member midpoints orthogonal to the centre tangent gives the ellipse
+ * (semi-axis = r + 2 sqrt(eigenvalue), a^ = major direction); n_total = member count,
+ * sigma_a = member mean, r = mean width / 2.  Replaces any existing levels. */
+int hair_build_lod(hair_ctx* ctx, int32_t asset, int32_t n_levels, const int32_t* n_clusters,
+                   const int32_t* assign, void* stream);
+
+/* Level count (not counting level 0), clusters per level (host int[n_levels + 1], entry 0 =
+ * strands) and segments per strand. */
+int hair_lod_info(hair_ctx* ctx, int32_t asset, int32_t* n_levels, int32_t* counts, int32_t max_counts,
+                  int32_t* segs_per_strand);
+
+/* Export (get) or import (set) a thick-hair level as host arrays (the stored configuration
+ * of Sec. 6, "Memory cost and initialization time").  K clusters, S segments per centre line:
+ *   centers float[K][S+1][3], ahat float[K][S][3], axes float[K][S][2] (|a|, |b|, m),
+ *   n_total int[K], sigma_a float[3][K], r float[K].
+ * set: level in 1..n_levels+1 (n_levels+1 appends); get: level in 1..n_levels. */
+int hair_get_lod(hair_ctx* ctx, int32_t asset, int32_t level, int32_t n_clusters,
+                 float* centers, float* ahat, float* axes, int32_t* n_total, float* sigma_a, float* r);
+int hair_set_lod(hair_ctx* ctx, int32_t asset, int32_t level, int32_t n_clusters,
+                 const float* centers, const float* ahat, const float* axes, const int32_t* n_total,
+                 const float* sigma_a, const float* r, void* stream);
+
+/* Overwrite a level's fitted parameters from device arrays (LoD fitting):
+ * axes float[K][S][2] (> 0), r float[K] (> 0), sigma_a float[3][K] (>= 0); any may be NULL
+ * to keep it.  Enqueued on `stream` (ordered with renders on the same stream). */
+int hair_set_cluster_params(hair_ctx* ctx, int32_t asset, int32_t level, const float* axes,
+                            const float* r, const float* sigma_a, void* stream);
+
+/* Per-request level choice (Sec. 5.1 step 5 with eps_w of Sec. 6): the coarsest level whose
+ * widest visible thick hair (2 * half-width, pixels) is <= eps_w_px; 0 when none is.
+ * Synchronises `stream`.  ws: scratch (NULL = a context-owned one). */
+int hair_select_level(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_camera* cam,
+                      float eps_w_px, void* stream, int32_t* level_out);
+
+/* Render one frame (the hot path).  rgba_out: device float[height][width][4], premultiplied
+ * (C, 1 - T) over transparent black, written in full.  n_lights in 1..HAIR_MAX_LIGHTS.
+ * The call synchronises `stream` once (to size the tile lists) and again when stats != NULL.
+ * HAIR_ERANGE when a pixel exceeds HAIR_PIXEL_CAPACITY fragments (stats->overflow_pixels). */
+int hair_render(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,
+                const hair_light* lights, int32_t n_lights, float* rgba_out, void* stream,
+                hair_stats* stats);
+
+/* Vector-Jacobian product of hair_render at a thick-hair level (level >= 1) with respect to
+ * the level's fitted parameters: given d_rgba (device float[height][width][4]) writes
+ *   d_axes    device float[K][S][2]  d/d|a|, d/d|b|
+ *   d_r       device float[K]        d/dr
+ *   d_sigma_a device float[3][K]     d/dsigma_a
+ * of sum(d_rgba * rgba) (overwritten).  The fragment set is recomputed, not stored, and held
+ * fixed (coverage is piecewise constant in the parameters). */
+int hair_render_backward(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level,
+                         const hair_camera* cam, const hair_light* lights, int32_t n_lights,
+                         const float* d_rgba, float* d_axes, float* d_r, float* d_sigma_a,
+                         void* stream);
+
+/* Test exports of the last hair_render on `ws` (synchronise and copy to host):
+ * segments: int[n][6] (XA, YA, XB, YB, hw_fx, flags: bit0 visible, bit1 negative h side,
+ *           bit2 culled for size) and float[n][3] (izA, izB, hw px).
+ * bins:     tile_start uint[n_tiles + 1], tile_segs uint[pairs] (each tile's segment ids,
+ *           in no particular order). */
+int hair_debug_segments(hair_ws* ws, int64_t n, int32_t* rec_i, float* rec_f);
+int hair_debug_bins(hair_ws* ws, int64_t n_tiles, uint32_t* tile_start, int64_t n_pairs, uint32_t* tile_segs);
+
+/* Test export of composited fragment lists: renders like hair_render and, for pixels in
+ * [x0, x0 + w) x [y0, y0 + h), writes per pixel its fragment count (host uint[h][w]) and
+ * its fragments in compositing order (host arrays of cap entries, pixels row-major):
+ * key uint, segment id uint, alpha float, offset h float.  HAIR_ERANGE if cap is short. */
+int hair_debug_fragments(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level,
+                         const hair_camera* cam, const hair_light* lights, int32_t n_lights,
+                         int32_t x0, int32_t y0, int32_t w, int32_t h, uint32_t* counts,
+                         int64_t cap, uint32_t* keys, uint32_t* segs, float* alpha, float* hoff,
+                         void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HAIR_H */

@@ -106,10 +106,22 @@ def segment_records(geom: LevelGeom, cam):
     return c, XA, YA, XB, YB, izA, izB, hw.astype(np.float32), hw_fx, vis
 
 
-def rasterize(geom: LevelGeom, cam, pix_filter=None) -> Raster:
+def rasterize(geom: LevelGeom, cam, pix_filter=None, rect=None) -> Raster:
+    """All fragments, or (rect = (x0, y0, w, h)) only those of pixels inside the rectangle."""
     c, XA, YA, XB, YB, izA, izB, hw, hw_fx, vis = segment_records(geom, cam)
     sign = rs.h_sign(geom.pA, geom.pB, c, XA, YA, XB, YB)
-    seg, pi, pj = rs.candidate_pixels(XA, YA, XB, YB, hw_fx, vis, c["W"], c["H"], pix_filter=pix_filter)
+    subset = None
+    if rect is not None:
+        x0, y0, w, h = rect
+        R = hw_fx + 8
+        near = ((np.minimum(XA, XB) - R < 16 * (x0 + w)) & (np.maximum(XA, XB) + R > 16 * x0) &
+                (np.minimum(YA, YB) - R < 16 * (y0 + h)) & (np.maximum(YA, YB) + R > 16 * y0))
+        subset = np.nonzero(near & vis)[0]
+        inner = pix_filter
+        pix_filter = lambda i, j: ((i >= x0) & (i < x0 + w) & (j >= y0) & (j < y0 + h)
+                                   & (inner(i, j) if inner else True))
+    seg, pi, pj = rs.candidate_pixels(XA, YA, XB, YB, hw_fx, vis, c["W"], c["H"], seg_subset=subset,
+                                      pix_filter=pix_filter)
     ok, t_num, t_den, cross = rs.coverage(XA, YA, XB, YB, hw_fx, seg, pi, pj)
     seg, pi, pj, t_num, t_den, cross = seg[ok], pi[ok], pj[ok], t_num[ok], t_den[ok], cross[ok]
     key, _, _ = rs.depth_key(t_num, t_den, izA[seg], izB[seg])
@@ -256,9 +268,9 @@ def composite(ras: Raster, alpha, L):
     return rgba.reshape(ras.H, ras.W, 4)
 
 
-def render(geom: LevelGeom, cam, lights, mat, pix_filter=None):
+def render(geom: LevelGeom, cam, lights, mat, pix_filter=None, rect=None):
     """Oracle frame: returns (rgba float64 [H, W, 4] numpy, Raster)."""
-    ras = rasterize(geom, cam, pix_filter=pix_filter)
+    ras = rasterize(geom, cam, pix_filter=pix_filter, rect=rect)
     alpha, L = fragment_radiance(geom, ras, cam, lights, mat)
     return composite(ras, alpha, L).numpy(), ras
 

@@ -1,0 +1,882 @@
+// C-ABI of libhair.so: contexts with an HBM budget, resident assets and LoD levels,
+// workspaces, host-side argument validation (always before any launch), and the frame
+// orchestration around the kernels of hair_kernels.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hair_internal.h"
+
+using namespace hair;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct Level {
+    int K = 0, S = 0;
+    DevBuf cx, cy, cz, ahat, axes, n_total, r, sig;
+};
+
+struct Asset {
+    int n_strands = 0, V = 0, S = 0;
+    DevBuf x, y, z, width, sig;
+    hair_material mat{};
+    std::vector<Level> levels;   // levels[l - 1] is level l
+};
+
+bool finite_all(const float* p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+struct hair_ctx {
+    int device = -1;
+    uint64_t budget = 0;
+    uint64_t used = 0;
+    bool poisoned = false;
+    std::mutex mu;
+    std::map<int, Asset> assets;
+    int next_id = 1;
+    hair_ws* default_ws = nullptr;
+};
+
+struct hair_ws {
+    hair_ctx* ctx = nullptr;
+    uint64_t max_bytes = 0;
+    uint64_t held = 0;
+    DevBuf seg, tile_cnt, tile_start, tile_cur, list, ctr;
+    hipEvent_t ev[5] = {};
+    bool events = false;
+    int64_t last_nseg = 0, last_ntiles = 0, last_pairs = 0;
+    std::mutex mu;
+};
+
+namespace {
+
+int dev_fail(hair_ctx* ctx, hipError_t e, const char* what) {
+    if (ctx) ctx->poisoned = true;
+    return fail(HAIR_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr, what)                      \
+    do {                                              \
+        hipError_t _e = (expr);                       \
+        if (_e != hipSuccess) return dev_fail(ctx, _e, what); \
+    } while (0)
+
+int ctx_alloc(hair_ctx* ctx, DevBuf& b, size_t bytes, hair_ws* ws = nullptr) {
+    if (bytes == 0) bytes = 4;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        if (ctx->used + bytes > ctx->budget)
+            return fail(HAIR_ENOMEM, "allocation of %zu bytes exceeds the HBM budget (%llu of %llu used)", bytes,
+                        (unsigned long long)ctx->used, (unsigned long long)ctx->budget);
+        if (ws && ws->max_bytes && ws->held + bytes > ws->max_bytes)
+            return fail(HAIR_ENOMEM, "workspace limit of %llu bytes exceeded", (unsigned long long)ws->max_bytes);
+        ctx->used += bytes;
+    }
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->used -= bytes;
+        b.p = nullptr;
+        if (e == hipErrorOutOfMemory) {
+            (void)hipGetLastError();
+            return fail(HAIR_ENOMEM, "device out of memory for %zu bytes", bytes);
+        }
+        return dev_fail(ctx, e, "hipMalloc");
+    }
+    b.bytes = bytes;
+    if (ws) ws->held += bytes;
+    return HAIR_OK;
+}
+
+void ctx_free(hair_ctx* ctx, DevBuf& b, hair_ws* ws = nullptr) {
+    if (!b.p) return;
+    (void)hipFree(b.p);
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->used -= b.bytes;
+    if (ws) ws->held -= b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+// Grow-only workspace buffer (25% headroom).
+int ws_need(hair_ws* ws, DevBuf& b, size_t bytes) {
+    if (b.bytes >= bytes && b.p) return HAIR_OK;
+    ctx_free(ws->ctx, b, ws);
+    return ctx_alloc(ws->ctx, b, bytes + bytes / 4 + 256, ws);
+}
+
+void free_level(hair_ctx* ctx, Level& l) {
+    for (DevBuf* b : {&l.cx, &l.cy, &l.cz, &l.ahat, &l.axes, &l.n_total, &l.r, &l.sig}) ctx_free(ctx, *b);
+}
+
+void free_asset(hair_ctx* ctx, Asset& a) {
+    for (DevBuf* b : {&a.x, &a.y, &a.z, &a.width, &a.sig}) ctx_free(ctx, *b);
+    for (Level& l : a.levels) free_level(ctx, l);
+    a.levels.clear();
+}
+
+int check_ctx(hair_ctx* ctx) {
+    if (!ctx) return fail(HAIR_EINVAL, "null context");
+    if (ctx->poisoned) return fail(HAIR_EDEVICE, "context poisoned by an earlier device error");
+    return HAIR_OK;
+}
+
+int need_device(hair_ctx* ctx) {
+    if (ctx->device < 0) return fail(HAIR_EDEVICE, "host-only context: no device work possible");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return dev_fail(ctx, e, "hipSetDevice");
+    return HAIR_OK;
+}
+
+int validate_material(const hair_material* m) {
+    if (!m) return fail(HAIR_EINVAL, "null material");
+    if (!(std::isfinite(m->eta) && m->eta > 1.0f)) return fail(HAIR_EINVAL, "material eta must be finite and > 1");
+    if (!std::isfinite(m->alpha) || std::fabs(m->alpha) > 0.5f)
+        return fail(HAIR_EINVAL, "material alpha must be finite with |alpha| <= 0.5 rad");
+    if (!(std::isfinite(m->beta_m) && m->beta_m > 0.0f && m->beta_m < 2.0f))
+        return fail(HAIR_EINVAL, "material beta_m must be in (0, 2)");
+    if (!(std::isfinite(m->beta_n) && m->beta_n > 0.0f && m->beta_n < 4.0f))
+        return fail(HAIR_EINVAL, "material beta_n must be in (0, 4)");
+    return HAIR_OK;
+}
+
+int validate_camera(const hair_camera* c) {
+    if (!c) return fail(HAIR_EINVAL, "null camera");
+    if (!finite_all(c->pos, 3) || !finite_all(c->rot, 9)) return fail(HAIR_EINVAL, "camera pose not finite");
+    if (!(std::isfinite(c->fx) && c->fx > 0 && std::isfinite(c->fy) && c->fy > 0))
+        return fail(HAIR_EINVAL, "camera focal lengths must be finite and > 0");
+    if (!(std::isfinite(c->cx) && std::isfinite(c->cy))) return fail(HAIR_EINVAL, "camera principal point not finite");
+    if (!(std::isfinite(c->z_near) && c->z_near > 0)) return fail(HAIR_EINVAL, "camera z_near must be > 0");
+    if (c->width < 1 || c->height < 1 || c->width > 16384 || c->height > 16384)
+        return fail(HAIR_EINVAL, "image size %dx%d outside [1, 16384]", c->width, c->height);
+    return HAIR_OK;
+}
+
+int validate_lights(const hair_light* l, int n) {
+    if (!l) return fail(HAIR_EINVAL, "null lights");
+    if (n < 1 || n > HAIR_MAX_LIGHTS) return fail(HAIR_EINVAL, "n_lights %d outside [1, %d]", n, HAIR_MAX_LIGHTS);
+    for (int i = 0; i < n; ++i) {
+        if (l[i].kind != 0 && l[i].kind != 1) return fail(HAIR_EINVAL, "light %d: unknown kind %d", i, l[i].kind);
+        if (!finite_all(l[i].vec, 3) || !finite_all(l[i].rgb, 3)) return fail(HAIR_EINVAL, "light %d not finite", i);
+        for (int c = 0; c < 3; ++c)
+            if (l[i].rgb[c] < 0) return fail(HAIR_EINVAL, "light %d: negative intensity", i);
+        if (l[i].kind == 0) {
+            const float n2 = l[i].vec[0] * l[i].vec[0] + l[i].vec[1] * l[i].vec[1] + l[i].vec[2] * l[i].vec[2];
+            if (std::fabs(n2 - 1.0f) > 1e-3f) return fail(HAIR_EINVAL, "light %d: direction is not unit length", i);
+        }
+    }
+    return HAIR_OK;
+}
+
+CamConst cam_const(const hair_camera* c) {
+    CamConst k;
+    memcpy(k.pos, c->pos, sizeof(k.pos));
+    memcpy(k.rot, c->rot, sizeof(k.rot));
+    k.fx = c->fx; k.fy = c->fy; k.cx = c->cx; k.cy = c->cy; k.z_near = c->z_near;
+    k.W = c->width; k.H = c->height;
+    return k;
+}
+
+LightsConst lights_const(const hair_light* l, int n) {
+    LightsConst k;
+    memset(&k, 0, sizeof(k));
+    k.n = n;
+    for (int i = 0; i < n; ++i) {
+        k.l[i].kind = l[i].kind;
+        memcpy(k.l[i].vec, l[i].vec, sizeof(k.l[i].vec));
+        memcpy(k.l[i].rgb, l[i].rgb, sizeof(k.l[i].rgb));
+    }
+    return k;
+}
+
+MatConst mat_const(const hair_material& m) {
+    MatConst k;
+    k.eta = m.eta;
+    k.alpha_p[0] = m.alpha; k.alpha_p[1] = -0.5f * m.alpha; k.alpha_p[2] = -1.5f * m.alpha;
+    k.beta_p[0] = m.beta_m; k.beta_p[1] = 0.5f * m.beta_m; k.beta_p[2] = 2.0f * m.beta_m;
+    k.beta_n = m.beta_n;
+    const double s = std::sqrt(3.0) * (double)m.beta_n / M_PI;
+    k.s = (float)s;
+    k.inv_tanh = (float)(1.0 / std::tanh(M_PI / (2.0 * s)));
+    return k;
+}
+
+int find_level(hair_ctx* ctx, int32_t asset, int32_t level, Asset** a_out, LevelDev* lv) {
+    auto it = ctx->assets.find(asset);
+    if (it == ctx->assets.end()) return fail(HAIR_ENOENT, "unknown asset %d", asset);
+    Asset& a = it->second;
+    if (level < 0 || level > (int)a.levels.size()) return fail(HAIR_ENOENT, "asset %d has no level %d", asset, level);
+    *a_out = &a;
+    memset(lv, 0, sizeof(*lv));
+    lv->S = a.S;
+    if (level == 0) {
+        lv->kind = 0;
+        lv->nseg = a.n_strands * a.S;
+        lv->n_owner = a.n_strands;
+        lv->vx = a.x.as<float>(); lv->vy = a.y.as<float>(); lv->vz = a.z.as<float>();
+        lv->width = a.width.as<float>();
+        lv->sig = a.sig.as<float>();
+    } else {
+        Level& l = a.levels[level - 1];
+        lv->kind = 1;
+        lv->nseg = l.K * l.S;
+        lv->n_owner = l.K;
+        lv->vx = l.cx.as<float>(); lv->vy = l.cy.as<float>(); lv->vz = l.cz.as<float>();
+        lv->sig = l.sig.as<float>();
+        lv->ahat = l.ahat.as<float>();
+        lv->axes = l.axes.as<float>();
+        lv->n_total = l.n_total.as<int32_t>();
+        lv->r = l.r.as<float>();
+    }
+    return HAIR_OK;
+}
+
+hair_ws* ws_or_default(hair_ctx* ctx, hair_ws* ws) {
+    if (ws) return ws;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (!ctx->default_ws) {
+        ctx->default_ws = new hair_ws();
+        ctx->default_ws->ctx = ctx;
+    }
+    return ctx->default_ws;
+}
+
+int ws_events(hair_ws* ws) {
+    if (ws->events) return HAIR_OK;
+    for (auto& e : ws->ev) HIP_TRY(ws->ctx, hipEventCreate(&e), "hipEventCreate");
+    ws->events = true;
+    return HAIR_OK;
+}
+
+struct FrameOut {
+    Counters ctr;
+    uint32_t pairs;
+    float ms[4];
+};
+
+// Project + bin + tile for one level; the caller holds ws->mu.
+int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, const hair_camera* cam,
+              const hair_light* lights, int n_lights, float* rgba, const DebugDump* dbg, hipStream_t st,
+              FrameOut* out, bool tiles_too = true) {
+    int rc;
+    const CamConst cc = cam_const(cam);
+    const int ntx = (cam->width + kTile - 1) / kTile, nty = (cam->height + kTile - 1) / kTile;
+    const int T = ntx * nty;
+    if ((rc = ws_events(ws))) return rc;
+    if ((rc = ws_need(ws, ws->seg, sizeof(SegRec) * (size_t)std::max(lv.nseg, 1)))) return rc;
+    if ((rc = ws_need(ws, ws->tile_cnt, 4ull * T))) return rc;
+    if ((rc = ws_need(ws, ws->tile_start, 4ull * (T + 1)))) return rc;
+    if ((rc = ws_need(ws, ws->tile_cur, 4ull * T))) return rc;
+    if ((rc = ws_need(ws, ws->ctr, sizeof(Counters)))) return rc;
+    HIP_TRY(ctx, hipEventRecord(ws->ev[0], st), "hipEventRecord");
+    HIP_TRY(ctx, launch_fill_u32(ws->tile_cnt.as<uint32_t>(), 0u, T, st), "fill");
+    HIP_TRY(ctx, launch_fill_u32(ws->tile_cur.as<uint32_t>(), 0u, T, st), "fill");
+    HIP_TRY(ctx, launch_fill_u32(ws->ctr.as<uint32_t>(), 0u, sizeof(Counters) / 4, st), "fill");
+    HIP_TRY(ctx, launch_project(lv, cc, ws->seg.as<SegRec>(), ws->tile_cnt.as<uint32_t>(), ws->ctr.as<Counters>(), st),
+            "k_project");
+    HIP_TRY(ctx, launch_scan_tiles(ws->tile_cnt.as<uint32_t>(), ws->tile_start.as<uint32_t>(), T, st), "k_scan");
+    HIP_TRY(ctx, hipEventRecord(ws->ev[1], st), "hipEventRecord");
+    uint32_t pairs = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&pairs, ws->tile_start.as<uint32_t>() + T, 4, hipMemcpyDeviceToHost, st), "copy");
+    HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
+    ws->last_nseg = lv.nseg;
+    ws->last_ntiles = T;
+    ws->last_pairs = pairs;
+    out->pairs = pairs;
+    if (!tiles_too) {
+        HIP_TRY(ctx, hipMemcpy(&out->ctr, ws->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost), "copy");
+        return HAIR_OK;
+    }
+    if ((rc = ws_need(ws, ws->list, 4ull * std::max<uint32_t>(pairs, 1)))) return rc;
+    HIP_TRY(ctx, hipEventRecord(ws->ev[2], st), "hipEventRecord");
+    HIP_TRY(ctx, launch_scatter(ws->seg.as<SegRec>(), lv.nseg, cc, ws->tile_start.as<uint32_t>(),
+                                ws->tile_cur.as<uint32_t>(), ws->list.as<uint32_t>(), st), "k_scatter");
+    HIP_TRY(ctx, hipEventRecord(ws->ev[3], st), "hipEventRecord");
+    HIP_TRY(ctx, launch_tile(lv, cc, lights_const(lights, n_lights), mat_const(a.mat), ws->seg.as<SegRec>(),
+                             ws->tile_start.as<uint32_t>(), ws->list.as<uint32_t>(), rgba, ws->ctr.as<Counters>(), dbg,
+                             nullptr, st), "k_tile");
+    HIP_TRY(ctx, hipEventRecord(ws->ev[4], st), "hipEventRecord");
+    HIP_TRY(ctx, hipMemcpyAsync(&out->ctr, ws->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, st), "copy");
+    HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
+    float t01 = 0, t23 = 0, t34 = 0, t04 = 0;
+    HIP_TRY(ctx, hipEventElapsedTime(&t01, ws->ev[0], ws->ev[1]), "elapsed");
+    HIP_TRY(ctx, hipEventElapsedTime(&t23, ws->ev[2], ws->ev[3]), "elapsed");
+    HIP_TRY(ctx, hipEventElapsedTime(&t34, ws->ev[3], ws->ev[4]), "elapsed");
+    HIP_TRY(ctx, hipEventElapsedTime(&t04, ws->ev[0], ws->ev[4]), "elapsed");
+    out->ms[0] = t04; out->ms[1] = t01; out->ms[2] = t23; out->ms[3] = t34;
+    return HAIR_OK;
+}
+
+}  // namespace
+
+// =======================================================================================
+extern "C" {
+
+int hair_version(void) { return 100; }
+
+const char* hair_last_error(void) { return g_err.c_str(); }
+
+int hair_device_count(void) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
+}
+
+int hair_ctx_create(int32_t device, uint64_t hbm_budget_bytes, hair_ctx** out) {
+    if (!out) return fail(HAIR_EINVAL, "null output pointer");
+    *out = nullptr;
+    auto ctx = std::make_unique<hair_ctx>();
+    ctx->device = device;
+    if (device < -1) return fail(HAIR_EINVAL, "device %d", device);
+    if (device >= 0) {
+        const int n = hair_device_count();
+        if (device >= n) return fail(HAIR_EDEVICE, "device %d not present (%d devices)", device, n);
+        hipError_t e = hipSetDevice(device);
+        if (e != hipSuccess) return fail(HAIR_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+        size_t free_b = 0, total_b = 0;
+        e = hipMemGetInfo(&free_b, &total_b);
+        if (e != hipSuccess) return fail(HAIR_EDEVICE, "hipMemGetInfo: %s", hipGetErrorString(e));
+        ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)total_b);
+    } else {
+        ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (1ull << 40);
+    }
+    *out = ctx.release();
+    return HAIR_OK;
+}
+
+int hair_ctx_destroy(hair_ctx* ctx) {
+    if (!ctx) return fail(HAIR_EINVAL, "null context");
+    if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
+    for (auto& kv : ctx->assets) free_asset(ctx, kv.second);
+    if (ctx->default_ws) hair_ws_destroy(ctx->default_ws);
+    delete ctx;
+    return HAIR_OK;
+}
+
+int hair_ctx_memory(hair_ctx* ctx, uint64_t* used, uint64_t* budget) {
+    if (!ctx) return fail(HAIR_EINVAL, "null context");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (used) *used = ctx->used;
+    if (budget) *budget = ctx->budget;
+    return HAIR_OK;
+}
+
+int hair_ws_create(hair_ctx* ctx, uint64_t max_bytes, hair_ws** out) {
+    int rc;
+    if (!out) return fail(HAIR_EINVAL, "null output pointer");
+    *out = nullptr;
+    if ((rc = check_ctx(ctx))) return rc;
+    hair_ws* ws = new hair_ws();
+    ws->ctx = ctx;
+    ws->max_bytes = max_bytes;
+    *out = ws;
+    return HAIR_OK;
+}
+
+int hair_ws_destroy(hair_ws* ws) {
+    if (!ws) return fail(HAIR_EINVAL, "null workspace");
+    hair_ctx* ctx = ws->ctx;
+    if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
+    for (DevBuf* b : {&ws->seg, &ws->tile_cnt, &ws->tile_start, &ws->tile_cur, &ws->list, &ws->ctr}) ctx_free(ctx, *b, ws);
+    if (ws->events)
+        for (auto& e : ws->ev) (void)hipEventDestroy(e);
+    if (ctx->default_ws == ws) ctx->default_ws = nullptr;
+    delete ws;
+    return HAIR_OK;
+}
+
+uint64_t hair_ws_estimate(int64_t n_segments, int32_t width, int32_t height, int64_t pairs_estimate) {
+    if (n_segments < 0) n_segments = 0;
+    const int64_t T = (int64_t)((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
+    if (pairs_estimate <= 0) pairs_estimate = 4 * n_segments;
+    const uint64_t raw = sizeof(SegRec) * (uint64_t)std::max<int64_t>(n_segments, 1) + 12ull * (T + 1) +
+                         4ull * (uint64_t)pairs_estimate + sizeof(Counters);
+    return raw + raw / 4 + 6 * 256;
+}
+
+int hair_upload(hair_ctx* ctx, int32_t n_strands, int32_t verts_per_strand, const float* xyz_soa,
+                const float* width, const float* sigma_a_soa, const hair_material* material, void* stream,
+                int32_t* asset_out) {
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if (!asset_out) return fail(HAIR_EINVAL, "null asset output");
+    *asset_out = -1;
+    if (n_strands < 1) return fail(HAIR_EINVAL, "n_strands must be >= 1");
+    if (verts_per_strand < 2) return fail(HAIR_EINVAL, "verts_per_strand must be >= 2");
+    const int64_t nv = (int64_t)n_strands * verts_per_strand;
+    if (nv > (int64_t)INT32_MAX / 2) return fail(HAIR_EINVAL, "too many vertices (%lld)", (long long)nv);
+    if (!xyz_soa || !width || !sigma_a_soa) return fail(HAIR_EINVAL, "null input array");
+    if ((rc = validate_material(material))) return rc;
+    if (!finite_all(xyz_soa, 3 * (size_t)nv)) return fail(HAIR_EINVAL, "vertex positions must be finite");
+    for (int i = 0; i < n_strands; ++i)
+        if (!(std::isfinite(width[i]) && width[i] > 0)) return fail(HAIR_EINVAL, "width[%d] must be finite and > 0", i);
+    for (int64_t i = 0; i < 3ll * n_strands; ++i)
+        if (!(std::isfinite(sigma_a_soa[i]) && sigma_a_soa[i] >= 0))
+            return fail(HAIR_EINVAL, "sigma_a must be finite and >= 0");
+    if ((rc = need_device(ctx))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    Asset a;
+    a.n_strands = n_strands;
+    a.V = verts_per_strand;
+    a.S = verts_per_strand - 1;
+    a.mat = *material;
+    const size_t vb = 4ull * nv;
+    if ((rc = ctx_alloc(ctx, a.x, vb)) || (rc = ctx_alloc(ctx, a.y, vb)) || (rc = ctx_alloc(ctx, a.z, vb)) ||
+        (rc = ctx_alloc(ctx, a.width, 4ull * n_strands)) || (rc = ctx_alloc(ctx, a.sig, 12ull * n_strands))) {
+        free_asset(ctx, a);
+        return rc;
+    }
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemcpyAsync(a.x.p, xyz_soa, vb, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(a.y.p, xyz_soa + nv, vb, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(a.z.p, xyz_soa + 2 * nv, vb, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(a.width.p, width, 4ull * n_strands, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(a.sig.p, sigma_a_soa, 12ull * n_strands, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        free_asset(ctx, a);
+        return dev_fail(ctx, e, "upload");
+    }
+    std::lock_guard<std::mutex> g(ctx->mu);
+    const int id = ctx->next_id++;
+    ctx->assets.emplace(id, std::move(a));
+    *asset_out = id;
+    return HAIR_OK;
+}
+
+int hair_release(hair_ctx* ctx, int32_t asset) {
+    if (!ctx) return fail(HAIR_EINVAL, "null context");
+    auto it = ctx->assets.find(asset);
+    if (it == ctx->assets.end()) return fail(HAIR_ENOENT, "unknown asset %d", asset);
+    if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
+    free_asset(ctx, it->second);
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->assets.erase(it);
+    return HAIR_OK;
+}
+
+int hair_lod_info(hair_ctx* ctx, int32_t asset, int32_t* n_levels, int32_t* counts, int32_t max_counts,
+                  int32_t* segs_per_strand) {
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    auto it = ctx->assets.find(asset);
+    if (it == ctx->assets.end()) return fail(HAIR_ENOENT, "unknown asset %d", asset);
+    const Asset& a = it->second;
+    if (n_levels) *n_levels = (int32_t)a.levels.size();
+    if (segs_per_strand) *segs_per_strand = a.S;
+    if (counts) {
+        if (max_counts >= 1) counts[0] = a.n_strands;
+        for (int l = 1; l <= (int)a.levels.size() && l < max_counts; ++l) counts[l] = a.levels[l - 1].K;
+    }
+    return HAIR_OK;
+}
+
+static int alloc_level(hair_ctx* ctx, Level& l, int K, int S) {
+    int rc;
+    l.K = K;
+    l.S = S;
+    const size_t nv = (size_t)K * (S + 1), ns = (size_t)K * S;
+    if ((rc = ctx_alloc(ctx, l.cx, 4 * nv)) || (rc = ctx_alloc(ctx, l.cy, 4 * nv)) || (rc = ctx_alloc(ctx, l.cz, 4 * nv)) ||
+        (rc = ctx_alloc(ctx, l.ahat, 12 * ns)) || (rc = ctx_alloc(ctx, l.axes, 8 * ns)) ||
+        (rc = ctx_alloc(ctx, l.n_total, 4ull * K)) || (rc = ctx_alloc(ctx, l.r, 4ull * K)) ||
+        (rc = ctx_alloc(ctx, l.sig, 12ull * K))) {
+        free_level(ctx, l);
+        return rc;
+    }
+    return HAIR_OK;
+}
+
+int hair_build_lod(hair_ctx* ctx, int32_t asset, int32_t n_levels, const int32_t* n_clusters, const int32_t* assign,
+                   void* stream) {
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    auto it = ctx->assets.find(asset);
+    if (it == ctx->assets.end()) return fail(HAIR_ENOENT, "unknown asset %d", asset);
+    Asset& a = it->second;
+    if (n_levels < 0 || n_levels > 64) return fail(HAIR_EINVAL, "n_levels %d outside [0, 64]", n_levels);
+    if (n_levels > 0 && (!n_clusters || !assign)) return fail(HAIR_EINVAL, "null cluster arrays");
+    const int n = a.n_strands;
+    std::vector<std::vector<int32_t>> members(n_levels), mstart(n_levels);
+    for (int l = 0; l < n_levels; ++l) {
+        const int K = n_clusters[l];
+        if (K < 1 || K > n) return fail(HAIR_EINVAL, "level %d: n_clusters %d outside [1, %d]", l + 1, K, n);
+        const int32_t* as = assign + (size_t)l * n;
+        std::vector<int32_t> cnt(K + 1, 0);
+        for (int s = 0; s < n; ++s) {
+            if (as[s] < 0 || as[s] >= K) return fail(HAIR_EINVAL, "level %d: assign[%d] = %d outside [0, %d)", l + 1, s, as[s], K);
+            cnt[as[s] + 1]++;
+        }
+        for (int c = 0; c < K; ++c)
+            if (cnt[c + 1] == 0) return fail(HAIR_EINVAL, "level %d: cluster %d is empty", l + 1, c);
+        for (int c = 0; c < K; ++c) cnt[c + 1] += cnt[c];
+        mstart[l] = cnt;
+        members[l].resize(n);
+        std::vector<int32_t> cur(cnt.begin(), cnt.end() - 1);
+        for (int s = 0; s < n; ++s) members[l][cur[as[s]]++] = s;   // ascending strand order per cluster
+    }
+    if ((rc = need_device(ctx))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<Level> built(n_levels);
+    for (int l = 0; l < n_levels; ++l) {
+        const int K = n_clusters[l];
+        DevBuf dm, ds;
+        if ((rc = alloc_level(ctx, built[l], K, a.S)) || (rc = ctx_alloc(ctx, dm, 4ull * n)) ||
+            (rc = ctx_alloc(ctx, ds, 4ull * (K + 1)))) {
+            ctx_free(ctx, dm);
+            for (Level& b : built) free_level(ctx, b);
+            return rc;
+        }
+        hipError_t e = hipMemcpyAsync(dm.p, members[l].data(), 4ull * n, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(ds.p, mstart[l].data(), 4ull * (K + 1), hipMemcpyHostToDevice, st);
+        Level& L = built[l];
+        if (e == hipSuccess)
+            e = launch_build_centers(a.x.as<float>(), a.y.as<float>(), a.z.as<float>(), a.width.as<float>(),
+                                     a.sig.as<float>(), n, a.V, dm.as<int32_t>(), ds.as<int32_t>(), K, L.cx.as<float>(),
+                                     L.cy.as<float>(), L.cz.as<float>(), L.r.as<float>(), L.sig.as<float>(),
+                                     L.n_total.as<int32_t>(), st);
+        if (e == hipSuccess)
+            e = launch_build_ellipses(a.x.as<float>(), a.y.as<float>(), a.z.as<float>(), a.V, dm.as<int32_t>(),
+                                      ds.as<int32_t>(), K, L.cx.as<float>(), L.cy.as<float>(), L.cz.as<float>(),
+                                      L.r.as<float>(), L.ahat.as<float>(), L.axes.as<float>(), st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        ctx_free(ctx, dm);
+        ctx_free(ctx, ds);
+        if (e != hipSuccess) {
+            for (Level& b : built) free_level(ctx, b);
+            return dev_fail(ctx, e, "build_lod");
+        }
+    }
+    for (Level& old : a.levels) free_level(ctx, old);
+    a.levels = std::move(built);
+    return HAIR_OK;
+}
+
+int hair_get_lod(hair_ctx* ctx, int32_t asset, int32_t level, int32_t n_clusters, float* centers, float* ahat,
+                 float* axes, int32_t* n_total, float* sigma_a, float* r) {
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    auto it = ctx->assets.find(asset);
+    if (it == ctx->assets.end()) return fail(HAIR_ENOENT, "unknown asset %d", asset);
+    Asset& a = it->second;
+    if (level < 1 || level > (int)a.levels.size()) return fail(HAIR_ENOENT, "asset %d has no level %d", asset, level);
+    Level& L = a.levels[level - 1];
+    if (n_clusters != L.K) return fail(HAIR_EINVAL, "level %d has %d clusters, caller passed %d", level, L.K, n_clusters);
+    if (!centers || !ahat || !axes || !n_total || !sigma_a || !r) return fail(HAIR_EINVAL, "null output array");
+    if ((rc = need_device(ctx))) return rc;
+    const size_t K = L.K, S = L.S, V = S + 1;
+    std::vector<float> x(K * V), y(K * V), z(K * V), ah(3 * K * S);
+    hipError_t e = hipMemcpy(x.data(), L.cx.p, 4 * K * V, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(y.data(), L.cy.p, 4 * K * V, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(z.data(), L.cz.p, 4 * K * V, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(ah.data(), L.ahat.p, 12 * K * S, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(axes, L.axes.p, 8 * K * S, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(n_total, L.n_total.p, 4 * K, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(sigma_a, L.sig.p, 12 * K, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(r, L.r.p, 4 * K, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return dev_fail(ctx, e, "get_lod");
+    for (size_t i = 0; i < K * V; ++i) {
+        centers[3 * i] = x[i];
+        centers[3 * i + 1] = y[i];
+        centers[3 * i + 2] = z[i];
+    }
+    const size_t ns = K * S;
+    for (size_t i = 0; i < ns; ++i) {
+        ahat[3 * i] = ah[i];
+        ahat[3 * i + 1] = ah[ns + i];
+        ahat[3 * i + 2] = ah[2 * ns + i];
+    }
+    return HAIR_OK;
+}
+
+int hair_set_lod(hair_ctx* ctx, int32_t asset, int32_t level, int32_t n_clusters, const float* centers,
+                 const float* ahat, const float* axes, const int32_t* n_total, const float* sigma_a, const float* r,
+                 void* stream) {
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    auto it = ctx->assets.find(asset);
+    if (it == ctx->assets.end()) return fail(HAIR_ENOENT, "unknown asset %d", asset);
+    Asset& a = it->second;
+    if (level < 1 || level > (int)a.levels.size() + 1) return fail(HAIR_ENOENT, "level %d cannot be set", level);
+    if (n_clusters < 1) return fail(HAIR_EINVAL, "n_clusters must be >= 1");
+    if (!centers || !ahat || !axes || !n_total || !sigma_a || !r) return fail(HAIR_EINVAL, "null input array");
+    const size_t K = n_clusters, S = a.S, V = S + 1;
+    if (!finite_all(centers, 3 * K * V) || !finite_all(ahat, 3 * K * S)) return fail(HAIR_EINVAL, "non-finite geometry");
+    for (size_t i = 0; i < 2 * K * S; ++i)
+        if (!(std::isfinite(axes[i]) && axes[i] > 0)) return fail(HAIR_EINVAL, "axes must be finite and > 0");
+    for (size_t c = 0; c < K; ++c) {
+        if (n_total[c] < 1) return fail(HAIR_EINVAL, "n_total must be >= 1");
+        if (!(std::isfinite(r[c]) && r[c] > 0)) return fail(HAIR_EINVAL, "r must be finite and > 0");
+    }
+    for (size_t i = 0; i < 3 * K; ++i)
+        if (!(std::isfinite(sigma_a[i]) && sigma_a[i] >= 0)) return fail(HAIR_EINVAL, "sigma_a must be finite and >= 0");
+    if ((rc = need_device(ctx))) return rc;
+    Level L;
+    if ((rc = alloc_level(ctx, L, (int)K, (int)S))) return rc;
+    std::vector<float> x(K * V), y(K * V), z(K * V), ah(3 * K * S);
+    for (size_t i = 0; i < K * V; ++i) {
+        x[i] = centers[3 * i];
+        y[i] = centers[3 * i + 1];
+        z[i] = centers[3 * i + 2];
+    }
+    const size_t ns = K * S;
+    for (size_t i = 0; i < ns; ++i) {
+        ah[i] = ahat[3 * i];
+        ah[ns + i] = ahat[3 * i + 1];
+        ah[2 * ns + i] = ahat[3 * i + 2];
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(L.cx.p, x.data(), 4 * K * V, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(L.cy.p, y.data(), 4 * K * V, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(L.cz.p, z.data(), 4 * K * V, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(L.ahat.p, ah.data(), 12 * ns, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(L.axes.p, axes, 8 * ns, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(L.n_total.p, n_total, 4 * K, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(L.sig.p, sigma_a, 12 * K, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(L.r.p, r, 4 * K, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        free_level(ctx, L);
+        return dev_fail(ctx, e, "set_lod");
+    }
+    if (level == (int)a.levels.size() + 1) {
+        a.levels.push_back(std::move(L));
+    } else {
+        free_level(ctx, a.levels[level - 1]);
+        a.levels[level - 1] = std::move(L);
+    }
+    return HAIR_OK;
+}
+
+int hair_set_cluster_params(hair_ctx* ctx, int32_t asset, int32_t level, const float* axes, const float* r,
+                            const float* sigma_a, void* stream) {
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    auto it = ctx->assets.find(asset);
+    if (it == ctx->assets.end()) return fail(HAIR_ENOENT, "unknown asset %d", asset);
+    Asset& a = it->second;
+    if (level < 1 || level > (int)a.levels.size()) return fail(HAIR_ENOENT, "asset %d has no level %d", asset, level);
+    if ((rc = need_device(ctx))) return rc;
+    Level& L = a.levels[level - 1];
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (axes) e = hipMemcpyAsync(L.axes.p, axes, 8ull * L.K * L.S, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && r) e = hipMemcpyAsync(L.r.p, r, 4ull * L.K, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && sigma_a) e = hipMemcpyAsync(L.sig.p, sigma_a, 12ull * L.K, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return dev_fail(ctx, e, "set_cluster_params");
+    return HAIR_OK;
+}
+
+int hair_select_level(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_camera* cam, float eps_w_px, void* stream,
+                      int32_t* level_out) {
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if (!level_out) return fail(HAIR_EINVAL, "null level output");
+    if ((rc = validate_camera(cam))) return rc;
+    if (!(std::isfinite(eps_w_px) && eps_w_px >= 0)) return fail(HAIR_EINVAL, "eps_w must be finite and >= 0");
+    auto it = ctx->assets.find(asset);
+    if (it == ctx->assets.end()) return fail(HAIR_ENOENT, "unknown asset %d", asset);
+    if ((rc = need_device(ctx))) return rc;
+    ws = ws_or_default(ctx, ws);
+    std::lock_guard<std::mutex> g(ws->mu);
+    const Asset& a = it->second;
+    for (int l = (int)a.levels.size(); l >= 1; --l) {
+        Asset* ap;
+        LevelDev lv;
+        if ((rc = find_level(ctx, asset, l, &ap, &lv))) return rc;
+        FrameOut fo;
+        if ((rc = run_frame(ctx, ws, a, lv, cam, nullptr, 0, nullptr, nullptr, (hipStream_t)stream, &fo, false)))
+            return rc;
+        float max_hw;
+        memcpy(&max_hw, &fo.ctr.max_hw_bits, 4);
+        if (fo.ctr.visible == 0 || 2.0f * max_hw <= eps_w_px) {
+            *level_out = l;
+            return HAIR_OK;
+        }
+    }
+    *level_out = 0;
+    return HAIR_OK;
+}
+
+int hair_render(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,
+                const hair_light* lights, int32_t n_lights, float* rgba_out, void* stream, hair_stats* stats) {
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if ((rc = validate_camera(cam))) return rc;
+    if ((rc = validate_lights(lights, n_lights))) return rc;
+    if (!rgba_out) return fail(HAIR_EINVAL, "null output image");
+    Asset* a;
+    LevelDev lv;
+    if ((rc = find_level(ctx, asset, level, &a, &lv))) return rc;
+    if ((rc = need_device(ctx))) return rc;
+    ws = ws_or_default(ctx, ws);
+    std::lock_guard<std::mutex> g(ws->mu);
+    FrameOut fo;
+    if ((rc = run_frame(ctx, ws, *a, lv, cam, lights, n_lights, rgba_out, nullptr, (hipStream_t)stream, &fo))) return rc;
+    if (stats) {
+        stats->fragments = fo.ctr.fragments;
+        stats->pairs = fo.pairs;
+        stats->segments = (uint32_t)lv.nseg;
+        stats->segments_visible = fo.ctr.visible;
+        stats->segments_culled_long = fo.ctr.culled_long;
+        stats->overflow_pixels = fo.ctr.overflow_pixels;
+        stats->ms_total = fo.ms[0];
+        stats->ms_project = fo.ms[1];
+        stats->ms_bin = fo.ms[2];
+        stats->ms_tile = fo.ms[3];
+    }
+    if (fo.ctr.list_overflow) return fail(HAIR_ERANGE, "%u tiles hold more than 2^24 segments", fo.ctr.list_overflow);
+    if (fo.ctr.overflow_pixels)
+        return fail(HAIR_ERANGE, "%u pixels exceed %d fragments (left transparent)", fo.ctr.overflow_pixels, kCap);
+    return HAIR_OK;
+}
+
+int hair_render_backward(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,
+                         const hair_light* lights, int32_t n_lights, const float* d_rgba, float* d_axes, float* d_r,
+                         float* d_sigma_a, void* stream) {
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if ((rc = validate_camera(cam))) return rc;
+    if ((rc = validate_lights(lights, n_lights))) return rc;
+    if (!d_rgba || !d_axes || !d_r || !d_sigma_a) return fail(HAIR_EINVAL, "null gradient array");
+    if (level < 1) return fail(HAIR_EINVAL, "the backward pass needs a thick-hair level (>= 1)");
+    Asset* a;
+    LevelDev lv;
+    if ((rc = find_level(ctx, asset, level, &a, &lv))) return rc;
+    (void)ws; (void)stream;
+    return fail(HAIR_EINVAL, "backward pass not built in this version");
+}
+
+int hair_debug_segments(hair_ws* ws, int64_t n, int32_t* rec_i, float* rec_f) {
+    if (!ws || !rec_i || !rec_f) return fail(HAIR_EINVAL, "null argument");
+    if (n != ws->last_nseg) return fail(HAIR_EINVAL, "last render had %lld segments", (long long)ws->last_nseg);
+    std::lock_guard<std::mutex> g(ws->mu);
+    std::vector<SegRec> h(std::max<int64_t>(n, 1));
+    hipError_t e = hipMemcpy(h.data(), ws->seg.p, sizeof(SegRec) * n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return dev_fail(ws->ctx, e, "debug_segments");
+    for (int64_t i = 0; i < n; ++i) {
+        const SegRec& s = h[i];
+        rec_i[6 * i + 0] = s.xa; rec_i[6 * i + 1] = s.ya; rec_i[6 * i + 2] = s.xb; rec_i[6 * i + 3] = s.yb;
+        rec_i[6 * i + 4] = s.hwfx & kHwMask;
+        rec_i[6 * i + 5] = ((s.hwfx & kFlagVisible) ? 1 : 0) | ((s.hwfx & kFlagNegSide) ? 2 : 0) |
+                           ((s.hwfx & kFlagCulledLong) ? 4 : 0);
+        rec_f[3 * i + 0] = s.iza; rec_f[3 * i + 1] = s.izb; rec_f[3 * i + 2] = s.hw;
+    }
+    return HAIR_OK;
+}
+
+int hair_debug_bins(hair_ws* ws, int64_t n_tiles, uint32_t* tile_start, int64_t n_pairs, uint32_t* tile_segs) {
+    if (!ws || !tile_start || !tile_segs) return fail(HAIR_EINVAL, "null argument");
+    if (n_tiles != ws->last_ntiles || n_pairs != ws->last_pairs)
+        return fail(HAIR_EINVAL, "last render had %lld tiles and %lld pairs", (long long)ws->last_ntiles,
+                    (long long)ws->last_pairs);
+    std::lock_guard<std::mutex> g(ws->mu);
+    hipError_t e = hipMemcpy(tile_start, ws->tile_start.p, 4 * (n_tiles + 1), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && n_pairs) e = hipMemcpy(tile_segs, ws->list.p, 4 * n_pairs, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return dev_fail(ws->ctx, e, "debug_bins");
+    return HAIR_OK;
+}
+
+int hair_debug_fragments(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,
+                         const hair_light* lights, int32_t n_lights, int32_t x0, int32_t y0, int32_t w, int32_t h,
+                         uint32_t* counts, int64_t cap, uint32_t* keys, uint32_t* segs, float* alpha, float* hoff,
+                         void* stream) {
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if ((rc = validate_camera(cam))) return rc;
+    if ((rc = validate_lights(lights, n_lights))) return rc;
+    if (w < 1 || h < 1 || x0 < 0 || y0 < 0 || x0 + w > cam->width || y0 + h > cam->height)
+        return fail(HAIR_EINVAL, "debug rectangle outside the image");
+    if (!counts || !keys || !segs || !alpha || !hoff || cap < 1) return fail(HAIR_EINVAL, "null output");
+    Asset* a;
+    LevelDev lv;
+    if ((rc = find_level(ctx, asset, level, &a, &lv))) return rc;
+    if ((rc = need_device(ctx))) return rc;
+    ws = ws_or_default(ctx, ws);
+    std::lock_guard<std::mutex> g(ws->mu);
+    const int npx = w * h;
+    const int stride = (int)std::min<int64_t>(cap, (int64_t)kCap);
+    DevBuf img, dc, dk, ds, da, dh;
+    const size_t ent = (size_t)npx * stride;
+    auto cleanup = [&]() { for (DevBuf* b : {&img, &dc, &dk, &ds, &da, &dh}) ctx_free(ctx, *b); };
+    if ((rc = ctx_alloc(ctx, img, 16ull * cam->width * cam->height)) || (rc = ctx_alloc(ctx, dc, 4ull * npx)) ||
+        (rc = ctx_alloc(ctx, dk, 4 * ent)) || (rc = ctx_alloc(ctx, ds, 4 * ent)) || (rc = ctx_alloc(ctx, da, 4 * ent)) ||
+        (rc = ctx_alloc(ctx, dh, 4 * ent))) {
+        cleanup();
+        return rc;
+    }
+    {
+        hipError_t ef = launch_fill_u32(dc.as<uint32_t>(), 0u, (size_t)npx, (hipStream_t)stream);
+        if (ef != hipSuccess) {
+            cleanup();
+            return dev_fail(ctx, ef, "fill");
+        }
+    }
+    DebugDump dbg{x0, y0, w, h, stride, dc.as<uint32_t>(), dk.as<uint32_t>(), ds.as<uint32_t>(), da.as<float>(),
+                  dh.as<float>()};
+    FrameOut fo;
+    rc = run_frame(ctx, ws, *a, lv, cam, lights, n_lights, img.as<float>(), &dbg, (hipStream_t)stream, &fo);
+    if (rc) {
+        cleanup();
+        return rc;
+    }
+    std::vector<uint32_t> c(npx), k(ent), s(ent);
+    std::vector<float> al(ent), ho(ent);
+    hipError_t e = hipMemcpy(c.data(), dc.p, 4ull * npx, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(k.data(), dk.p, 4 * ent, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(s.data(), ds.p, 4 * ent, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(al.data(), da.p, 4 * ent, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(ho.data(), dh.p, 4 * ent, hipMemcpyDeviceToHost);
+    cleanup();
+    if (e != hipSuccess) return dev_fail(ctx, e, "debug_fragments");
+    int64_t total = 0;
+    for (int i = 0; i < npx; ++i) {
+        if (c[i] > (uint32_t)stride) return fail(HAIR_ERANGE, "pixel holds %u fragments, above %d", c[i], stride);
+        total += c[i];
+    }
+    if (total > cap) return fail(HAIR_ERANGE, "%lld fragments do not fit cap %lld", (long long)total, (long long)cap);
+    int64_t o = 0;
+    for (int i = 0; i < npx; ++i) {
+        counts[i] = c[i];
+        for (uint32_t r = 0; r < c[i]; ++r, ++o) {
+            const size_t src = (size_t)i * stride + r;
+            keys[o] = k[src]; segs[o] = s[src]; alpha[o] = al[src]; hoff[o] = ho[src];
+        }
+    }
+    if (fo.ctr.overflow_pixels) return fail(HAIR_ERANGE, "%u pixels exceed capacity", fo.ctr.overflow_pixels);
+    return HAIR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// Internal types shared by the library's HIP sources (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/hair.h"
+
+namespace hair {
+
+constexpr int kTile = HAIR_TILE;                 // tile edge in pixels
+constexpr int kTilePix = kTile * kTile;          // pixels per tile = threads per tile block
+constexpr int kCap = HAIR_PIXEL_CAPACITY;        // fragments per LDS batch
+constexpr int kGuard = 16384;                    // guard band, 1/16-px units (1024 px)
+constexpr int kMaxAxis = 16384;                  // longest segment extent per axis (1/16 px)
+constexpr int kMaxHwFx = 4096;                   // widest coverage half-width (1/16 px)
+constexpr int kMaxListLen = (1 << 24) - 1;       // per-tile list limit (24-bit local index)
+
+// Projected segment, one per segment of the rendered level (32 bytes, AoS for gathers).
+struct SegRec {
+    int32_t xa, ya, xb, yb;   // endpoints, 1/16-pixel units
+    int32_t hwfx;             // coverage half-width ceil(16 hw) in bits 0..15; flags above
+    float iza, izb;           // inverse view depth at the endpoints
+    float hw;                 // half-width in pixels
+};
+constexpr int32_t kFlagVisible = 1 << 16;
+constexpr int32_t kFlagNegSide = 1 << 17;        // h > 0 lies on the e x d < 0 side
+constexpr int32_t kFlagCulledLong = 1 << 18;
+constexpr int32_t kHwMask = 0xFFFF;
+
+struct CamConst {
+    float pos[3];
+    float rot[9];
+    float fx, fy, cx, cy, z_near;
+    int32_t W, H;
+};
+
+struct LightConst {
+    int32_t kind;
+    float vec[3];
+    float rgb[3];
+};
+
+struct LightsConst {
+    int32_t n;
+    LightConst l[HAIR_MAX_LIGHTS];
+};
+
+// Material constants derived on the host from hair_material (Sec. 6 parameters).
+struct MatConst {
+    float eta;
+    float alpha_p[3];        // longitudinal shifts of R, TT, TRT
+    float beta_p[3];         // longitudinal standard deviations of R, TT, TRT
+    float beta_n;            // azimuthal standard deviation
+    float s;                 // logistic scale sqrt(3) beta_n / pi
+    float inv_tanh;          // 1 / tanh(pi / 2s): trimmed-logistic normaliser
+};
+
+// One renderable level, device pointers.
+struct LevelDev {
+    int32_t kind;            // 0 = strands, 1 = thick hairs
+    int32_t nseg;            // segments in the level
+    int32_t S;               // segments per strand / centre line
+    int32_t n_owner;         // strands or clusters (stride of the SoA per-owner arrays)
+    const float* vx;         // vertex SoA [n_owner * (S + 1)]
+    const float* vy;
+    const float* vz;
+    const float* width;      // strands: diameter [n_owner]
+    const float* sig;        // absorption SoA [3][n_owner]
+    const float* ahat;       // thick hairs: major axis direction SoA [3][nseg]
+    const float* axes;       // thick hairs: (|a|, |b|) [nseg][2]
+    const int32_t* n_total;  // thick hairs: member count [n_owner]
+    const float* r;          // thick hairs: hair radius [n_owner]
+};
+
+// Global counters a render accumulates (zeroed at the start of each call).
+struct Counters {
+    unsigned long long fragments;
+    uint32_t visible;
+    uint32_t culled_long;
+    uint32_t overflow_pixels;
+    uint32_t max_hw_bits;    // float bits of the largest visible half-width (non-negative)
+    uint32_t list_overflow;  // tiles whose list exceeded the 24-bit local index
+    uint32_t pad;
+};
+
+// Optional per-pixel fragment dump of a pixel rectangle (tests).
+struct DebugDump {
+    int32_t x0, y0, w, h;
+    int32_t stride;          // entries per pixel
+    uint32_t* counts;        // [h * w]
+    uint32_t* keys;          // [h * w * stride]
+    uint32_t* segs;
+    float* alpha;
+    float* hoff;
+};
+
+// Gradient outputs of the backward pass.
+struct GradOut {
+    const float* d_rgba;     // [H][W][4]
+    float* d_axes;           // [nseg][2]
+    float* d_r;              // [K]
+    float* d_sig;            // [3][K]
+};
+
+// Kernel launchers (hair_kernels.hip).
+hipError_t launch_project(const LevelDev& lv, const CamConst& cam, SegRec* seg, uint32_t* tile_cnt,
+                          Counters* ctr, hipStream_t st);
+hipError_t launch_scan_tiles(const uint32_t* cnt, uint32_t* start, int32_t n, hipStream_t st);
+hipError_t launch_scatter(const SegRec* seg, int32_t nseg, const CamConst& cam, const uint32_t* tile_start,
+                          uint32_t* tile_cur, uint32_t* list, hipStream_t st);
+hipError_t launch_tile(const LevelDev& lv, const CamConst& cam, const LightsConst& lights, const MatConst& mat,
+                       const SegRec* seg, const uint32_t* tile_start, const uint32_t* list, float* rgba,
+                       Counters* ctr, const DebugDump* dbg, const GradOut* grad, hipStream_t st);
+hipError_t launch_build_centers(const float* vx, const float* vy, const float* vz, const float* width,
+                                const float* sig, int32_t n_strands, int32_t V, const int32_t* members,
+                                const int32_t* member_start, int32_t K, float* cx, float* cy, float* cz,
+                                float* r, float* csig, int32_t* n_total, hipStream_t st);
+hipError_t launch_build_ellipses(const float* vx, const float* vy, const float* vz, int32_t V,
+                                 const int32_t* members, const int32_t* member_start, int32_t K,
+                                 const float* cx, const float* cy, const float* cz, const float* r,
+                                 float* ahat, float* axes, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
+hipError_t launch_fill_f32(float* p, float v, size_t n, hipStream_t st);
+
+}  // namespace hair

@@ -1,0 +1,909 @@
+// Device kernels of the LoD hair renderer (gfx950 / MI355X).
+//
+// Frame pipeline, all on the caller's stream:
+//   k_project   one thread per segment: float32 projection and 1/16-pixel snapping, screen
+//               half-width (Sec. 5.2, hair width calculation), culling, and the count of
+//               segments per 16x16 tile (integer box of the segment expanded by its radius).
+//   k_scan      exclusive prefix sum of the per-tile counts -> tile list offsets.
+//   k_scatter   one thread per segment: append its id to every overlapped tile's list.
+//   k_tile      one 256-thread workgroup per tile, all fragment work in LDS:
+//                 count   per-pixel fragment counts and depth-key range (exact integer coverage)
+//                 batch   whole pixels packed into LDS batches of <= kCap fragments
+//                 emit    (key, local index) records into per-pixel ranges
+//                 sort    per-pixel bucket sort (buckets = linear key ranges of each pixel)
+//                         + insertion sort inside buckets: exact (key, segment id) order
+//                 shade   one lane per fragment: alpha, cross-section offset h, radiance
+//                 blend   two-level segmented scan of front-to-back "over" -> RGBA
+// The integer-deciding steps (projection, snapping, half-width, depth key) are float32 with
+// one rounding per operation and no contraction, so they match a float32 reference bit for bit.
+#include "hair_internal.h"
+#include "hair_shading.h"
+
+#pragma clang fp contract(off)
+
+namespace hair {
+namespace {
+
+constexpr int kNT = 256;                   // threads per tile block (= pixels per tile)
+constexpr int kPerThread = kCap / kNT;     // LDS batch fragments per thread
+
+__device__ inline long long floordiv(long long a, long long b) {  // b > 0
+    return a >= 0 ? a / b : -((-a + b - 1) / b);
+}
+
+// ---------------------------------------------------------------------------------------
+// Projection (float32, fixed operation order).
+struct PPoint {
+    float X16, Y16, z, iz;
+    bool ok;
+};
+
+__device__ inline PPoint project_point(const CamConst& c, float px, float py, float pz) {
+    const float d0 = px - c.pos[0];
+    const float d1 = py - c.pos[1];
+    const float d2 = pz - c.pos[2];
+    const float vx = (c.rot[0] * d0 + c.rot[1] * d1) + c.rot[2] * d2;
+    const float vy = (c.rot[3] * d0 + c.rot[4] * d1) + c.rot[5] * d2;
+    const float vz = (c.rot[6] * d0 + c.rot[7] * d1) + c.rot[8] * d2;
+    PPoint p;
+    p.z = -vz;
+    const float xs = c.cx + c.fx * (vx / p.z);
+    const float ys = c.cy - c.fy * (vy / p.z);
+    p.iz = 1.0f / p.z;
+    p.X16 = 16.0f * xs;
+    p.Y16 = 16.0f * ys;
+    p.ok = (p.z >= c.z_near) && (p.X16 >= -16384.0f) && (p.X16 <= (float)(16 * c.W + kGuard)) &&
+           (p.Y16 >= -16384.0f) && (p.Y16 <= (float)(16 * c.H + kGuard));
+    return p;
+}
+
+__device__ inline float norm3f(float x, float y, float z) { return sqrtf((x * x + y * y) + z * z); }
+
+// Thick-hair half-width: support of the ellipse across the view at the segment midpoint.
+__device__ inline float cluster_halfwidth(const CamConst& c, float ax, float ay, float az, float bx, float by,
+                                          float bz, float zA, float zB, float hx, float hy, float hz, float a_len,
+                                          float b_len) {
+    const float tx = bx - ax, ty = by - ay, tz = bz - az;
+    const float tl = norm3f(tx, ty, tz);
+    const float ux = tx / tl, uy = ty / tl, uz = tz / tl;
+    const float mx = (ax + bx) * 0.5f, my = (ay + by) * 0.5f, mz = (az + bz) * 0.5f;
+    float wx = c.pos[0] - mx, wy = c.pos[1] - my, wz = c.pos[2] - mz;
+    const float wl = norm3f(wx, wy, wz);
+    wx = wx / wl;
+    wy = wy / wl;
+    wz = wz / wl;
+    const float dwu = (wx * ux + wy * uy) + wz * uz;
+    const float px = wx - dwu * ux, py = wy - dwu * uy, pz = wz - dwu * uz;
+    const float pl = norm3f(px, py, pz);
+    const float xx = px / pl, xy = py / pl, xz = pz / pl;
+    const float yx = uy * xz - uz * xy, yy = uz * xx - ux * xz, yz = ux * xy - uy * xx;
+    const float bhx = uy * hz - uz * hy, bhy = uz * hx - ux * hz, bhz = ux * hy - uy * hx;
+    const float pa = a_len * ((hx * yx + hy * yy) + hz * yz);
+    const float pb = b_len * ((bhx * yx + bhy * yy) + bhz * yz);
+    float W = sqrtf(pa * pa + pb * pb);
+    if (!(pl > 1e-7f)) W = fmaxf(a_len, b_len);
+    const float zm = (zA + zB) * 0.5f;
+    return (W * c.fy) / zm;
+}
+
+struct TileRect {
+    int tx0, tx1, ty0, ty1;
+};
+
+__device__ inline TileRect tile_rect(const SegRec& s, int ntx, int nty) {
+    const long long R = (long long)(s.hwfx & kHwMask) + 8;
+    const long long T16 = 16LL * kTile;
+    const long long lox = (long long)min(s.xa, s.xb) - R, hix = (long long)max(s.xa, s.xb) + R;
+    const long long loy = (long long)min(s.ya, s.yb) - R, hiy = (long long)max(s.ya, s.yb) + R;
+    TileRect r;
+    r.tx0 = (int)max(floordiv(lox, T16), 0LL);
+    r.tx1 = (int)min(floordiv(hix, T16), (long long)ntx - 1);
+    r.ty0 = (int)max(floordiv(loy, T16), 0LL);
+    r.ty1 = (int)min(floordiv(hiy, T16), (long long)nty - 1);
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_project(LevelDev lv, CamConst cam, SegRec* __restrict__ seg,
+                                                 uint32_t* __restrict__ tile_cnt, Counters* __restrict__ ctr) {
+    __shared__ uint32_t s_maxhw;
+    if (threadIdx.x == 0) s_maxhw = 0;
+    __syncthreads();
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    bool vis = false, culled_long = false;
+    if (g < lv.nseg) {
+        const int owner = g / lv.S, k = g - owner * lv.S;
+        const int va = owner * (lv.S + 1) + k;
+        const float ax = lv.vx[va], ay = lv.vy[va], az = lv.vz[va];
+        const float bx = lv.vx[va + 1], by = lv.vy[va + 1], bz = lv.vz[va + 1];
+        const PPoint A = project_point(cam, ax, ay, az);
+        const PPoint B = project_point(cam, bx, by, bz);
+        float hw;
+        if (lv.kind == 0) {
+            const float zm = (A.z + B.z) * 0.5f;
+            hw = ((0.5f * lv.width[owner]) * cam.fy) / zm;
+        } else {
+            hw = cluster_halfwidth(cam, ax, ay, az, bx, by, bz, A.z, B.z, lv.ahat[g], lv.ahat[lv.nseg + g],
+                                   lv.ahat[2 * lv.nseg + g], lv.axes[2 * g], lv.axes[2 * g + 1]);
+        }
+        const float hw16 = 16.0f * hw;
+        SegRec r;
+        r.xa = r.ya = r.xb = r.yb = 0;
+        r.hwfx = 0;
+        r.iza = A.iz;
+        r.izb = B.iz;
+        r.hw = hw;
+        vis = A.ok && B.ok && isfinite(hw16) && hw16 >= 0.0f;
+        if (vis) {
+            r.xa = (int)rintf(A.X16);
+            r.ya = (int)rintf(A.Y16);
+            r.xb = (int)rintf(B.X16);
+            r.yb = (int)rintf(B.Y16);
+            const float c16 = ceilf(hw16);
+            if (abs(r.xb - r.xa) > kMaxAxis || abs(r.yb - r.ya) > kMaxAxis || c16 > (float)kMaxHwFx) {
+                vis = false;
+                culled_long = true;
+                r.hwfx = kFlagCulledLong;
+            } else {
+                r.hwfx = (int)c16 | kFlagVisible;
+                // side of the screen normal (dY, -dX) on which h > 0 (toward y^ = u x x^)
+                const float tx = bx - ax, ty = by - ay, tz = bz - az;
+                const float tl = norm3f(tx, ty, tz);
+                const float ux = tx / tl, uy = ty / tl, uz = tz / tl;
+                const float mx = (ax + bx) * 0.5f, my = (ay + by) * 0.5f, mz = (az + bz) * 0.5f;
+                float wx = cam.pos[0] - mx, wy = cam.pos[1] - my, wz = cam.pos[2] - mz;
+                const float wl = norm3f(wx, wy, wz);
+                wx /= wl; wy /= wl; wz /= wl;
+                const float dwu = (wx * ux + wy * uy) + wz * uz;
+                float px = wx - dwu * ux, py = wy - dwu * uy, pz = wz - dwu * uz;
+                const float pl = fmaxf(norm3f(px, py, pz), 1e-30f);
+                px /= pl; py /= pl; pz /= pl;
+                const float yx = uy * pz - uz * py, yy = uz * px - ux * pz, yz = ux * py - uy * px;
+                const float yvx = (cam.rot[0] * yx + cam.rot[1] * yy) + cam.rot[2] * yz;
+                const float yvy = (cam.rot[3] * yx + cam.rot[4] * yy) + cam.rot[5] * yz;
+                const float yvz = (cam.rot[6] * yx + cam.rot[7] * yy) + cam.rot[8] * yz;
+                const float d0 = mx - cam.pos[0], d1 = my - cam.pos[1], d2 = mz - cam.pos[2];
+                const float mvx = (cam.rot[0] * d0 + cam.rot[1] * d1) + cam.rot[2] * d2;
+                const float mvy = (cam.rot[3] * d0 + cam.rot[4] * d1) + cam.rot[5] * d2;
+                const float mvz = (cam.rot[6] * d0 + cam.rot[7] * d1) + cam.rot[8] * d2;
+                const float Z = -mvz;
+                const float sx = cam.fx * (yvx + (mvx / Z) * yvz);
+                const float sy = -cam.fy * (yvy + (mvy / Z) * yvz);
+                const float side = sx * (float)(r.yb - r.ya) - sy * (float)(r.xb - r.xa);
+                if (side < 0.0f) r.hwfx |= kFlagNegSide;
+            }
+        }
+        seg[g] = r;
+        if (vis) {
+            atomicMax(&s_maxhw, __float_as_uint(hw));
+            const int ntx = (cam.W + kTile - 1) / kTile, nty = (cam.H + kTile - 1) / kTile;
+            const TileRect tr = tile_rect(r, ntx, nty);
+            for (int ty = tr.ty0; ty <= tr.ty1; ++ty)
+                for (int tx = tr.tx0; tx <= tr.tx1; ++tx) atomicAdd(&tile_cnt[ty * ntx + tx], 1u);
+        }
+    }
+    const int nvis = __syncthreads_count(vis);
+    const int nlong = __syncthreads_count(culled_long);
+    if (threadIdx.x == 0) {
+        if (nvis) atomicAdd(&ctr->visible, (uint32_t)nvis);
+        if (nlong) atomicAdd(&ctr->culled_long, (uint32_t)nlong);
+        if (s_maxhw) atomicMax(&ctr->max_hw_bits, s_maxhw);
+    }
+}
+
+// Exclusive scan of n counts by one 1024-thread block; start[n] = total.
+__global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ cnt, uint32_t* __restrict__ start, int n) {
+    __shared__ uint32_t s_part[1024];
+    const int t = threadIdx.x;
+    const int per = (n + 1023) / 1024;
+    const int b = t * per, e = min(n, b + per);
+    uint32_t sum = 0;
+    for (int i = b; i < e; ++i) sum += cnt[i];
+    s_part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = t >= off ? s_part[t - off] : 0u;
+        __syncthreads();
+        s_part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = s_part[t] - sum;
+    for (int i = b; i < e; ++i) {
+        start[i] = run;
+        run += cnt[i];
+    }
+    if (t == 1023) start[n] = s_part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_scatter(const SegRec* __restrict__ seg, int nseg, int ntx, int nty,
+                                                 const uint32_t* __restrict__ tile_start,
+                                                 uint32_t* __restrict__ tile_cur, uint32_t* __restrict__ list) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nseg) return;
+    const SegRec r = seg[g];
+    if (!(r.hwfx & kFlagVisible)) return;
+    const TileRect tr = tile_rect(r, ntx, nty);
+    for (int ty = tr.ty0; ty <= tr.ty1; ++ty)
+        for (int tx = tr.tx0; tx <= tr.tx1; ++tx) {
+            const int t = ty * ntx + tx;
+            const uint32_t pos = atomicAdd(&tile_cur[t], 1u);
+            list[tile_start[t] + pos] = (uint32_t)g;
+        }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_f32(float* p, float v, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------------------
+// Coverage: every fragment of segment s whose pixel lies in tile rows [row_lo, row_hi].
+// Candidate columns per row come from the row's interval of the slab 0 <= t_num < t_den and
+// the strip |cross| < R sqrt(t_den), widened by a pixel; the exact integer predicate decides.
+template <class F>
+__device__ inline void for_each_fragment(const SegRec& s, int px0, int py0, int row_lo, int row_hi, int W, int H,
+                                         F&& f) {
+    const long long ax = s.xa, ay = s.ya;
+    const long long dx = (long long)s.xb - ax, dy = (long long)s.yb - ay;
+    const long long tden = dx * dx + dy * dy;
+    if (tden <= 0) return;
+    const long long R = (long long)(s.hwfx & kHwMask) + 8;
+    const long long RR = R * R * tden;
+    const long long lox = min(ax, (long long)s.xb) - R, hix = max(ax, (long long)s.xb) + R;
+    const long long loy = min(ay, (long long)s.yb) - R, hiy = max(ay, (long long)s.yb) + R;
+    const int i0 = (int)max((long long)px0, floordiv(lox - 8, 16) + 1);
+    const int i1 = (int)min((long long)min(px0 + kTile, W) - 1, -floordiv(-(hix - 8), 16) - 1);
+    const int j0 = (int)max((long long)(py0 + row_lo), floordiv(loy - 8, 16) + 1);
+    const int j1 = (int)min((long long)min(py0 + row_hi, H - 1), -floordiv(-(hiy - 8), 16) - 1);
+    if (i0 > i1 || j0 > j1) return;
+    const double inv_dx = dx != 0 ? 1.0 / (double)dx : 0.0;
+    const double inv_dy = dy != 0 ? 1.0 / (double)dy : 0.0;
+    const double half = dy != 0 ? (double)R * sqrt((double)tden) * fabs(inv_dy) : 0.0;
+    for (int j = j0; j <= j1; ++j) {
+        const long long ey = 16LL * j + 8 - ay;
+        double lo = -1e300, hi = 1e300;
+        if (dx != 0) {
+            const double a = (double)(-ey * dy) * inv_dx;
+            const double b = (double)(tden - ey * dy) * inv_dx;
+            lo = fmin(a, b);
+            hi = fmax(a, b);
+        }
+        if (dy != 0) {
+            const double c = (double)(ey * dx) * inv_dy;
+            lo = fmax(lo, c - half);
+            hi = fmin(hi, c + half);
+        }
+        const double flo = floor(((double)ax + lo - 8.0) * (1.0 / 16.0)) - 1.0;
+        const double fhi = ceil(((double)ax + hi - 8.0) * (1.0 / 16.0)) + 1.0;
+        const int c0 = (int)fmax((double)i0, flo);
+        const int c1 = (int)fmin((double)i1, fhi);
+        for (int i = c0; i <= c1; ++i) {
+            const long long ex = 16LL * i + 8 - ax;
+            const long long tnum = ex * dx + ey * dy;
+            if (tnum < 0 || tnum >= tden) continue;
+            const long long cr = ex * dy - ey * dx;
+            if (cr * cr >= RR) continue;
+            f(i - px0, j - py0, tnum, tden, cr);
+        }
+    }
+}
+
+__device__ inline uint32_t depth_key(const SegRec& s, long long tnum, long long tden) {
+    const float t = (float)tnum / (float)tden;
+    const float iz = s.iza + t * (s.izb - s.iza);
+    return 0xFFFFFFFFu - __float_as_uint(iz);
+}
+
+struct TileArgs {
+    LevelDev lv;
+    CamConst cam;
+    LightsConst lights;
+    MatConst mat;
+    const SegRec* seg;
+    const uint32_t* tile_start;
+    const uint32_t* list;
+    float* rgba;
+    Counters* ctr;
+    DebugDump dbg;
+    int has_dbg;
+    int ntx, nty;
+};
+
+// Radiance (RGB), coverage alpha and cross-section offset of one fragment.
+__device__ inline void shade_fragment(const TileArgs& a, uint32_t gseg, int pxg, int pyg, float& alpha, float& hoff,
+                                      float L[3]) {
+    const SegRec s = a.seg[gseg];
+    const long long ex = 16LL * pxg + 8 - s.xa, ey = 16LL * pyg + 8 - s.ya;
+    const long long dx = (long long)s.xb - s.xa, dy = (long long)s.yb - s.ya;
+    const long long tnum = ex * dx + ey * dy, tden = dx * dx + dy * dy;
+    const long long cr = ex * dy - ey * dx;
+    const float t = (float)tnum / (float)tden;
+    const float iz = s.iza + t * (s.izb - s.iza);
+    const float delta = fabsf((float)cr) / sqrtf((float)tden) * (1.0f / 16.0f);
+    const float hw = s.hw;
+    alpha = fminf(fmaxf(fminf(delta + hw, 0.5f) - fmaxf(delta - hw, -0.5f), 0.0f), 1.0f);
+    float sgn = cr > 0 ? 1.0f : (cr < 0 ? -1.0f : 0.0f);
+    if (s.hwfx & kFlagNegSide) sgn = -sgn;
+    const float h = fminf(fmaxf(sgn * delta / (hw + 0.5f), -1.0f), 1.0f);
+    hoff = h;
+    const float tw = t * s.izb / iz;
+
+    const LevelDev& lv = a.lv;
+    const int owner = (int)gseg / lv.S, k = (int)gseg - owner * lv.S;
+    const int va = owner * (lv.S + 1) + k;
+    const V3<float> pA = v3(lv.vx[va], lv.vy[va], lv.vz[va]);
+    const V3<float> pB = v3(lv.vx[va + 1], lv.vy[va + 1], lv.vz[va + 1]);
+    const V3<float> d = sub(pB, pA);
+    const V3<float> u = scale(d, 1.0f / sqrtf(dot(d, d)));
+    const V3<float> xw = v3(pA.x + tw * d.x, pA.y + tw * d.y, pA.z + tw * d.z);
+    V3<float> wo = sub(v3(a.cam.pos[0], a.cam.pos[1], a.cam.pos[2]), xw);
+    wo = scale(wo, 1.0f / sqrtf(dot(wo, wo)));
+    const float sin_to = dot(wo, u);
+    V3<float> wp = sub(wo, scale(u, sin_to));
+    float wpn = sqrtf(dot(wp, wp));
+    const bool degen = wpn < 1e-7f;
+    if (degen) {  // view along the fibre: any normal direction; phi is set to 0 below
+        const float ax = fabsf(u.x), ay = fabsf(u.y), az = fabsf(u.z);
+        V3<float> e = (ax <= ay && ax <= az) ? v3(1.f, 0.f, 0.f) : (ay <= az ? v3(0.f, 1.f, 0.f) : v3(0.f, 0.f, 1.f));
+        wp = sub(e, scale(u, dot(e, u)));
+        wpn = sqrtf(dot(wp, wp));
+    }
+    const V3<float> xh = scale(wp, 1.0f / wpn);
+    const V3<float> yh = cross(u, xh);
+    const float to = asinf(fminf(fmaxf(sin_to, -1.0f), 1.0f));
+
+    float sig[3];
+    ClusterFrag<float> cf;
+    float a_len = 0, b_len = 0, W = 0;
+    V3<float> ah{}, bh{};
+    if (lv.kind == 0) {
+        sig[0] = lv.sig[owner];
+        sig[1] = lv.sig[lv.n_owner + owner];
+        sig[2] = lv.sig[2 * lv.n_owner + owner];
+    } else {
+        sig[0] = lv.sig[owner];
+        sig[1] = lv.sig[lv.n_owner + owner];
+        sig[2] = lv.sig[2 * lv.n_owner + owner];
+        ah = v3(lv.ahat[gseg], lv.ahat[lv.nseg + gseg], lv.ahat[2 * lv.nseg + gseg]);
+        bh = cross(u, ah);
+        a_len = lv.axes[2 * gseg];
+        b_len = lv.axes[2 * gseg + 1];
+        const float pa = a_len * dot(ah, yh), pb = b_len * dot(bh, yh);
+        W = sqrtf(pa * pa + pb * pb);
+        cf.n_total = (float)lv.n_total[owner];
+        const float rr = lv.r[owner];
+        cf.rho = fminf(fmaxf(cf.n_total * rr * rr / (a_len * b_len), 0.0f), 1.0f);
+    }
+    L[0] = L[1] = L[2] = 0.0f;
+    for (int li = 0; li < a.lights.n; ++li) {
+        const LightConst& lc = a.lights.l[li];
+        V3<float> wi;
+        float E[3];
+        if (lc.kind == 0) {
+            wi = v3(lc.vec[0], lc.vec[1], lc.vec[2]);
+            E[0] = lc.rgb[0]; E[1] = lc.rgb[1]; E[2] = lc.rgb[2];
+        } else {
+            const V3<float> dl = sub(v3(lc.vec[0], lc.vec[1], lc.vec[2]), xw);
+            const float d2 = dot(dl, dl);
+            wi = scale(dl, 1.0f / sqrtf(d2));
+            E[0] = lc.rgb[0] / d2; E[1] = lc.rgb[1] / d2; E[2] = lc.rgb[2] / d2;
+        }
+        const float sin_ti = dot(wi, u);
+        float phi = -atan2f(dot(wi, yh), dot(wi, xh));
+        if (degen) phi = 0.0f;
+        const float sc = fminf(fmaxf(sin_ti, -1.0f), 1.0f);
+        const float ti = asinf(sc);
+        const float th = 0.5f * (ti + to);
+        const float xd = 0.5f * fabsf(ti - to);
+        const float cos_ti = sqrtf((1.0f - sc) * (1.0f + sc));
+        float f[3];
+        if (lv.kind == 0) {
+            f_single(th, xd, phi, h, sig, a.mat, f);
+        } else {
+            // chord of the view ray's entry point toward the light, in the cross-section
+            const V3<float> Dp = sub(wi, scale(u, sin_ti));
+            const float dn = sqrtf(dot(Dp, Dp));
+            float s_star = 0.0f;
+            if (dn > 1e-7f) {
+                const V3<float> D = scale(Dp, 1.0f / dn);
+                const float oa = h * W * dot(yh, ah) / a_len, ob = h * W * dot(yh, bh) / b_len;
+                const float xa = dot(xh, ah) / a_len, xb = dot(xh, bh) / b_len;
+                const float qa = xa * xa + xb * xb, qb = oa * xa + ob * xb, qc = oa * oa + ob * ob - 1.0f;
+                const float disc = fmaxf(qb * qb - qa * qc, 0.0f);
+                const float tt = (qb - sqrtf(disc)) / qa;
+                const float Pa = oa - tt * xa, Pb = ob - tt * xb;
+                const float Da = dot(D, ah) / a_len, Db = dot(D, bh) / b_len;
+                s_star = -2.0f * (Pa * Da + Pb * Db) / (Da * Da + Db * Db);
+            }
+            const float kappa = sqrtf(cf.n_total / (kPi * a_len * b_len));
+            const float lF = fmaxf(s_star, 0.0f), lB = fmaxf(-s_star, 0.0f);
+            const bool back = fabsf(phi) < 0.5f * kPi;
+            cf.n_F = (back || cf.n_total < 2.0f) ? 1.0f : fmaxf(cf.rho * kappa * lF, 1.0f);
+            cf.n_B = fmaxf(cf.rho * kappa * lB, 1.0f);
+            f_ours(th, xd, phi, h, sig, a.mat, cf, f);
+        }
+        L[0] += E[0] * f[0] * cos_ti;
+        L[1] += E[1] * f[1] * cos_ti;
+        L[2] += E[2] * f[2] * cos_ti;
+    }
+}
+
+// Block-wide exclusive scan of one uint per thread (256 threads); returns the total.
+__device__ inline uint32_t block_exscan_u32(uint32_t v, uint32_t* s_tmp, uint32_t& excl) {
+    const int t = threadIdx.x;
+    s_tmp[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kNT; off <<= 1) {
+        const uint32_t x = t >= off ? s_tmp[t - off] : 0u;
+        __syncthreads();
+        s_tmp[t] += x;
+        __syncthreads();
+    }
+    const uint32_t incl = s_tmp[t];
+    const uint32_t total = s_tmp[kNT - 1];
+    __syncthreads();
+    excl = incl - v;
+    return total;
+}
+
+__global__ __launch_bounds__(kNT) void k_tile(TileArgs a) {
+    __shared__ uint32_t s_cnt[kTilePix];
+    __shared__ uint32_t s_kmin[kTilePix];
+    __shared__ uint32_t s_kmax[kTilePix];
+    __shared__ uint32_t s_off[kTilePix + 1];
+    __shared__ uint32_t s_cur[kTilePix];
+    __shared__ uint32_t s_tmp[kNT];
+    __shared__ uint2 s_B[kCap];
+    __shared__ uint32_t s_work[3 * kCap];     // A records (2 words) + bucket counters, later payload
+    __shared__ float s_agg[kNT * 4];          // run aggregates (C rgb, T)
+    __shared__ uint32_t s_aggh[kNT];
+
+    uint2* s_A = reinterpret_cast<uint2*>(s_work);
+    uint32_t* s_bk = s_work + 2 * kCap;
+    float* s_pay = reinterpret_cast<float*>(s_work);
+
+    // XCD-aware tile order: consecutive workgroups land on different XCDs, so give each XCD a
+    // contiguous band of tiles (shared segments stay in that XCD's L2).
+    const int nb = gridDim.x;
+    const int b = blockIdx.x;
+    const int q = nb / 8, rem = nb % 8, x = b % 8, slot = b / 8;
+    const int tile = x * q + min(x, rem) + slot;
+    const int tx = tile % a.ntx, ty = tile / a.ntx;
+    const int px0 = tx * kTile, py0 = ty * kTile;
+    const int t = threadIdx.x;
+    const uint32_t lstart = a.tile_start[tile];
+    const uint32_t n = a.tile_start[tile + 1] - lstart;
+    const uint32_t* list = a.list + lstart;
+
+    s_cnt[t] = 0;
+    s_kmin[t] = 0xFFFFFFFFu;
+    s_kmax[t] = 0;
+    if (n > (uint32_t)kMaxListLen) {
+        if (t == 0) atomicAdd(&a.ctr->list_overflow, 1u);
+        return;
+    }
+    __syncthreads();
+
+    // ---- count pass: per-pixel fragment counts and key range
+    for (uint32_t base = 0; base < n; base += kNT) {
+        const uint32_t j = base + t;
+        if (j < n) {
+            const SegRec s = a.seg[list[j]];
+            for_each_fragment(s, px0, py0, 0, kTile - 1, a.cam.W, a.cam.H, [&](int li, int lj, long long tnum, long long tden, long long) {
+                const int p = lj * kTile + li;
+                const uint32_t key = depth_key(s, tnum, tden);
+                atomicAdd(&s_cnt[p], 1u);
+                atomicMin(&s_kmin[p], key);
+                atomicMax(&s_kmax[p], key);
+            });
+        }
+    }
+    __syncthreads();
+    uint32_t my_off;
+    const uint32_t total = block_exscan_u32(s_cnt[t], s_tmp, my_off);
+    s_off[t] = my_off;
+    if (t == 0) {
+        s_off[kTilePix] = total;
+        if (total) atomicAdd(&a.ctr->fragments, (unsigned long long)total);
+    }
+    __syncthreads();
+
+    const int W = a.cam.W, H = a.cam.H;
+    int p0 = 0;
+    while (p0 < kTilePix) {
+        // largest p1 with off[p1] - off[p0] <= kCap (whole pixels per batch)
+        int lo = p0 + 1, hi = kTilePix;
+        const uint32_t o0 = s_off[p0];
+        if (s_off[lo] - o0 > (uint32_t)kCap) {
+            hi = lo;   // a single pixel deeper than the batch capacity
+        } else {
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] - o0 <= (uint32_t)kCap) lo = mid; else hi = mid - 1;
+            }
+            hi = lo;
+        }
+        const int p1 = hi;
+        const uint32_t Fb = s_off[p1] - o0;
+        const bool oversized = Fb > (uint32_t)kCap;
+        if (oversized) {
+            if (t == 0) {
+                atomicAdd(&a.ctr->overflow_pixels, 1u);
+                const int gx = px0 + (p0 % kTile), gy = py0 + (p0 / kTile);
+                if (gx < W && gy < H) {
+                    float* o = a.rgba + 4 * ((size_t)gy * W + gx);
+                    o[0] = o[1] = o[2] = o[3] = 0.0f;
+                }
+            }
+            __syncthreads();
+            p0 = p1;
+            continue;
+        }
+        // pixels of the batch with no fragment
+        if (t >= p0 && t < p1 && s_cnt[t] == 0) {
+            const int gx = px0 + (t % kTile), gy = py0 + (t / kTile);
+            if (gx < W && gy < H) {
+                float4* o = reinterpret_cast<float4*>(a.rgba) + ((size_t)gy * W + gx);
+                *o = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            if (a.has_dbg) {
+                const int dx = gx - a.dbg.x0, dy = gy - a.dbg.y0;
+                if (dx >= 0 && dy >= 0 && dx < a.dbg.w && dy < a.dbg.h) a.dbg.counts[dy * a.dbg.w + dx] = 0;
+            }
+        }
+        if (Fb == 0) {
+            __syncthreads();
+            p0 = p1;
+            continue;
+        }
+        // ---- emit
+        if (t >= p0 && t < p1) s_cur[t] = 0;
+        for (uint32_t i = t; i < Fb; i += kNT) s_bk[i] = 0;
+        __syncthreads();
+        const int r0 = p0 / kTile, r1 = (p1 - 1) / kTile;
+        for (uint32_t base = 0; base < n; base += kNT) {
+            const uint32_t j = base + t;
+            if (j < n) {
+                const SegRec s = a.seg[list[j]];
+                for_each_fragment(s, px0, py0, r0, r1, a.cam.W, a.cam.H, [&](int li, int lj, long long tnum, long long tden, long long) {
+                    const int p = lj * kTile + li;
+                    if (p < p0 || p >= p1) return;
+                    const uint32_t key = depth_key(s, tnum, tden);
+                    const uint32_t slot2 = atomicAdd(&s_cur[p], 1u);
+                    s_A[s_off[p] - o0 + slot2] = make_uint2(key, j | ((uint32_t)p << 24));
+                });
+            }
+        }
+        __syncthreads();
+        // ---- bucket sort: bucket = linear key range of the fragment's pixel
+        uint32_t my_b[kPerThread], my_r[kPerThread];
+#pragma unroll
+        for (int qq = 0; qq < kPerThread; ++qq) {
+            const uint32_t i = t + qq * kNT;
+            if (i < Fb) {
+                const uint2 rec = s_A[i];
+                const uint32_t p = rec.y >> 24;
+                const uint32_t kmn = s_kmin[p];
+                const unsigned long long span = (unsigned long long)(s_kmax[p] - kmn) + 1ull;
+                const uint32_t bucket = (uint32_t)(((unsigned long long)(rec.x - kmn) * s_cnt[p]) / span);
+                my_b[qq] = s_off[p] - o0 + bucket;
+                my_r[qq] = atomicAdd(&s_bk[my_b[qq]], 1u);
+            }
+        }
+        __syncthreads();
+        {   // exclusive scan of the bucket counters, kPerThread consecutive per thread
+            uint32_t loc[kPerThread];
+            uint32_t sum = 0;
+#pragma unroll
+            for (int qq = 0; qq < kPerThread; ++qq) {
+                const uint32_t i = t * kPerThread + qq;
+                loc[qq] = i < Fb ? s_bk[i] : 0u;
+                sum += loc[qq];
+            }
+            uint32_t ex;
+            block_exscan_u32(sum, s_tmp, ex);
+#pragma unroll
+            for (int qq = 0; qq < kPerThread; ++qq) {
+                const uint32_t i = t * kPerThread + qq;
+                if (i < Fb) s_bk[i] = ex;
+                ex += loc[qq];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int qq = 0; qq < kPerThread; ++qq) {
+            const uint32_t i = t + qq * kNT;
+            if (i < Fb) s_B[s_bk[my_b[qq]] + my_r[qq]] = s_A[i];
+        }
+        __syncthreads();
+        // insertion sort inside each bucket by (key, segment id)
+        for (uint32_t bi = t; bi < Fb; bi += kNT) {
+            const uint32_t b0 = s_bk[bi];
+            const uint32_t b1 = bi + 1 < Fb ? s_bk[bi + 1] : Fb;
+            for (uint32_t i = b0 + 1; i < b1; ++i) {
+                const uint2 v = s_B[i];
+                const uint32_t vseg = list[v.y & 0xFFFFFFu];
+                uint32_t jx = i;
+                while (jx > b0) {
+                    const uint2 u2 = s_B[jx - 1];
+                    bool greater = u2.x > v.x;
+                    if (u2.x == v.x) greater = list[u2.y & 0xFFFFFFu] > vseg;
+                    if (!greater) break;
+                    s_B[jx] = u2;
+                    --jx;
+                }
+                s_B[jx] = v;
+            }
+        }
+        __syncthreads();
+        // ---- shade: one lane per fragment, payload alpha * L and (1 - alpha)
+        for (uint32_t i = t; i < Fb; i += kNT) {
+            const uint2 rec = s_B[i];
+            const uint32_t p = rec.y >> 24;
+            const uint32_t gseg = list[rec.y & 0xFFFFFFu];
+            const int gx = px0 + (int)(p % kTile), gy = py0 + (int)(p / kTile);
+            float al, hh, L[3];
+            shade_fragment(a, gseg, gx, gy, al, hh, L);
+            s_pay[3 * i + 0] = al * L[0];
+            s_pay[3 * i + 1] = al * L[1];
+            s_pay[3 * i + 2] = al * L[2];
+            s_B[i].x = __float_as_uint(1.0f - al);
+            if (a.has_dbg) {
+                const int dx = gx - a.dbg.x0, dy = gy - a.dbg.y0;
+                if (dx >= 0 && dy >= 0 && dx < a.dbg.w && dy < a.dbg.h) {
+                    const uint32_t rank = i - (s_off[p] - o0);
+                    const int q2 = dy * a.dbg.w + dx;
+                    if (rank == 0) a.dbg.counts[q2] = s_cnt[p];
+                    if ((int)rank < a.dbg.stride) {
+                        const size_t o = (size_t)q2 * a.dbg.stride + rank;
+                        a.dbg.keys[o] = rec.x;
+                        a.dbg.segs[o] = gseg;
+                        a.dbg.alpha[o] = al;
+                        a.dbg.hoff[o] = hh;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // ---- blend: segmented scan of (C, T) over runs of consecutive fragments
+        {
+            const uint32_t run = (Fb + kNT - 1) / kNT;
+            const uint32_t rb = min(Fb, t * run), re = min(Fb, rb + run);
+            float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
+            uint32_t head = 0;
+            for (uint32_t i = rb; i < re; ++i) {
+                const uint32_t p = s_B[i].y >> 24;
+                if (i == s_off[p] - o0) { C0 = C1 = C2 = 0.f; T = 1.f; head = 1; }
+                C0 += T * s_pay[3 * i + 0];
+                C1 += T * s_pay[3 * i + 1];
+                C2 += T * s_pay[3 * i + 2];
+                T *= __uint_as_float(s_B[i].x);
+            }
+            s_agg[4 * t + 0] = C0; s_agg[4 * t + 1] = C1; s_agg[4 * t + 2] = C2; s_agg[4 * t + 3] = T;
+            s_aggh[t] = head;
+            __syncthreads();
+            // inclusive scan of run aggregates: (l) then (r) = r.head ? r : (l.C + l.T r.C, l.T r.T)
+            for (int off = 1; off < kNT; off <<= 1) {
+                float c0 = 0, c1 = 0, c2 = 0, tt = 1;
+                uint32_t hh2 = 0;
+                const bool has = t >= off;
+                if (has) {
+                    c0 = s_agg[4 * (t - off) + 0]; c1 = s_agg[4 * (t - off) + 1];
+                    c2 = s_agg[4 * (t - off) + 2]; tt = s_agg[4 * (t - off) + 3];
+                    hh2 = s_aggh[t - off];
+                }
+                __syncthreads();
+                if (has && !s_aggh[t]) {
+                    const float mT = s_agg[4 * t + 3];
+                    s_agg[4 * t + 0] = c0 + tt * s_agg[4 * t + 0];
+                    s_agg[4 * t + 1] = c1 + tt * s_agg[4 * t + 1];
+                    s_agg[4 * t + 2] = c2 + tt * s_agg[4 * t + 2];
+                    s_agg[4 * t + 3] = tt * mT;
+                    s_aggh[t] = hh2;
+                }
+                __syncthreads();
+            }
+            // carry into this run = inclusive result of run t - 1
+            if (t > 0) { C0 = s_agg[4 * (t - 1) + 0]; C1 = s_agg[4 * (t - 1) + 1]; C2 = s_agg[4 * (t - 1) + 2]; T = s_agg[4 * (t - 1) + 3]; }
+            else { C0 = C1 = C2 = 0.f; T = 1.f; }
+            for (uint32_t i = rb; i < re; ++i) {
+                const uint32_t p = s_B[i].y >> 24;
+                if (i == s_off[p] - o0) { C0 = C1 = C2 = 0.f; T = 1.f; }
+                C0 += T * s_pay[3 * i + 0];
+                C1 += T * s_pay[3 * i + 1];
+                C2 += T * s_pay[3 * i + 2];
+                T *= __uint_as_float(s_B[i].x);
+                if (i + 1 == s_off[p + 1] - o0) {
+                    const int gx = px0 + (int)(p % kTile), gy = py0 + (int)(p / kTile);
+                    if (gx < W && gy < H) {
+                        float4* o = reinterpret_cast<float4*>(a.rgba) + ((size_t)gy * W + gx);
+                        *o = make_float4(C0, C1, C2, 1.0f - T);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        p0 = p1;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Thick-hair construction (Sec. 5.1 step 3), float64 sums in member order.
+__global__ void k_build_centers(const float* __restrict__ vx, const float* __restrict__ vy,
+                                const float* __restrict__ vz, const float* __restrict__ width,
+                                const float* __restrict__ sig, int n_strands, int V,
+                                const int32_t* __restrict__ members, const int32_t* __restrict__ mstart, int K,
+                                float* cx, float* cy, float* cz, float* r, float* csig, int32_t* n_total) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= K * V) return;
+    const int c = g / V, k = g - c * V;
+    const int b = mstart[c], e = mstart[c + 1];
+    double sx = 0, sy = 0, sz = 0;
+    for (int m = b; m < e; ++m) {
+        const int v = members[m] * V + k;
+        sx += (double)vx[v];
+        sy += (double)vy[v];
+        sz += (double)vz[v];
+    }
+    const double N = (double)(e - b);
+    cx[g] = (float)(sx / N);
+    cy[g] = (float)(sy / N);
+    cz[g] = (float)(sz / N);
+    if (k == 0) {
+        double sw = 0, s0 = 0, s1 = 0, s2 = 0;
+        for (int m = b; m < e; ++m) {
+            const int s = members[m];
+            sw += (double)width[s];
+            s0 += (double)sig[s];
+            s1 += (double)sig[n_strands + s];
+            s2 += (double)sig[2 * n_strands + s];
+        }
+        r[c] = (float)((sw / N) * 0.5);
+        csig[c] = (float)(s0 / N);
+        csig[K + c] = (float)(s1 / N);
+        csig[2 * K + c] = (float)(s2 / N);
+        n_total[c] = e - b;
+    }
+}
+
+__global__ void k_build_ellipses(const float* __restrict__ vx, const float* __restrict__ vy,
+                                 const float* __restrict__ vz, int V, const int32_t* __restrict__ members,
+                                 const int32_t* __restrict__ mstart, int K, const float* __restrict__ cx,
+                                 const float* __restrict__ cy, const float* __restrict__ cz,
+                                 const float* __restrict__ r, float* ahat, float* axes) {
+    const int S = V - 1;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= K * S) return;
+    const int c = g / S, k = g - c * S;
+    const int ia = c * V + k;
+    const double ax = cx[ia], ay = cy[ia], az = cz[ia];
+    const double bx = cx[ia + 1], by = cy[ia + 1], bz = cz[ia + 1];
+    double ux = bx - ax, uy = by - ay, uz = bz - az;
+    const double ul = sqrt(ux * ux + uy * uy + uz * uz);
+    ux /= ul; uy /= ul; uz /= ul;
+    // basis of the plane orthogonal to u: start from the axis of smallest |u_j| (lowest index on ties)
+    const double fx = fabs(ux), fy = fabs(uy), fz = fabs(uz);
+    int j = 0;
+    if (fy < fx) j = 1;
+    if (fz < (j == 0 ? fx : fy)) j = 2;
+    double ex = j == 0, ey = j == 1, ez = j == 2;
+    const double eu = ex * ux + ey * uy + ez * uz;
+    ex -= eu * ux; ey -= eu * uy; ez -= eu * uz;
+    const double el = sqrt(ex * ex + ey * ey + ez * ez);
+    ex /= el; ey /= el; ez /= el;
+    const double fx2 = uy * ez - uz * ey, fy2 = uz * ex - ux * ez, fz2 = ux * ey - uy * ex;
+    const double mx = 0.5 * (ax + bx), my = 0.5 * (ay + by), mz = 0.5 * (az + bz);
+    const int b0 = mstart[c], b1 = mstart[c + 1];
+    double c11 = 0, c12 = 0, c22 = 0;
+    for (int m = b0; m < b1; ++m) {
+        const int v = members[m] * V + k;
+        const double qx = 0.5 * ((double)vx[v] + (double)vx[v + 1]) - mx;
+        const double qy = 0.5 * ((double)vy[v] + (double)vy[v + 1]) - my;
+        const double qz = 0.5 * ((double)vz[v] + (double)vz[v + 1]) - mz;
+        const double q1 = qx * ex + qy * ey + qz * ez;
+        const double q2 = qx * fx2 + qy * fy2 + qz * fz2;
+        c11 += q1 * q1;
+        c12 += q1 * q2;
+        c22 += q2 * q2;
+    }
+    const double N = (double)(b1 - b0);
+    c11 /= N; c12 /= N; c22 /= N;
+    const double hm = 0.5 * (c11 + c22), hd = 0.5 * (c11 - c22);
+    const double rad = sqrt(hd * hd + c12 * c12);
+    const double l1 = fmax(hm + rad, 0.0), l2 = fmax(hm - rad, 0.0);
+    double v1 = 1.0, v2 = 0.0;
+    if (!((l1 - l2) <= 1e-12 * (l1 + l2))) {
+        // eigenvector of l1: (l1 - c22, c12) or (c12, l1 - c11), the better conditioned
+        const double a1 = l1 - c22, a2 = c12, b1v = c12, b2 = l1 - c11;
+        if (a1 * a1 + a2 * a2 >= b1v * b1v + b2 * b2) { v1 = a1; v2 = a2; } else { v1 = b1v; v2 = b2; }
+        const double vl = sqrt(v1 * v1 + v2 * v2);
+        v1 /= vl; v2 /= vl;
+    }
+    const int nseg = K * S;
+    ahat[g] = (float)(v1 * ex + v2 * fx2);
+    ahat[nseg + g] = (float)(v1 * ey + v2 * fy2);
+    ahat[2 * nseg + g] = (float)(v1 * ez + v2 * fz2);
+    const double rr = (double)r[c];
+    axes[2 * g] = (float)(rr + 2.0 * sqrt(l1));
+    axes[2 * g + 1] = (float)(rr + 2.0 * sqrt(l2));
+}
+
+inline int blocks_for(size_t n, int per) { return (int)((n + per - 1) / per); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+hipError_t launch_project(const LevelDev& lv, const CamConst& cam, SegRec* seg, uint32_t* tile_cnt, Counters* ctr,
+                          hipStream_t st) {
+    if (lv.nseg == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_project, dim3(blocks_for(lv.nseg, 256)), dim3(256), 0, st, lv, cam, seg, tile_cnt, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_tiles(const uint32_t* cnt, uint32_t* start, int32_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cnt, start, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const SegRec* seg, int32_t nseg, const CamConst& cam, const uint32_t* tile_start,
+                          uint32_t* tile_cur, uint32_t* list, hipStream_t st) {
+    if (nseg == 0) return hipSuccess;
+    const int ntx = (cam.W + kTile - 1) / kTile, nty = (cam.H + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, seg, nseg, ntx, nty, tile_start,
+                       tile_cur, list);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile(const LevelDev& lv, const CamConst& cam, const LightsConst& lights, const MatConst& mat,
+                       const SegRec* seg, const uint32_t* tile_start, const uint32_t* list, float* rgba, Counters* ctr,
+                       const DebugDump* dbg, const GradOut* grad, hipStream_t st) {
+    (void)grad;
+    TileArgs a;
+    a.lv = lv;
+    a.cam = cam;
+    a.lights = lights;
+    a.mat = mat;
+    a.seg = seg;
+    a.tile_start = tile_start;
+    a.list = list;
+    a.rgba = rgba;
+    a.ctr = ctr;
+    a.has_dbg = dbg != nullptr;
+    if (dbg) a.dbg = *dbg; else a.dbg = DebugDump{};
+    a.ntx = (cam.W + kTile - 1) / kTile;
+    a.nty = (cam.H + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_tile, dim3(a.ntx * a.nty), dim3(kNT), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_centers(const float* vx, const float* vy, const float* vz, const float* width, const float* sig,
+                                int32_t n_strands, int32_t V, const int32_t* members, const int32_t* member_start,
+                                int32_t K, float* cx, float* cy, float* cz, float* r, float* csig, int32_t* n_total,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_build_centers, dim3(blocks_for((size_t)K * V, 128)), dim3(128), 0, st, vx, vy, vz, width, sig,
+                       n_strands, V, members, member_start, K, cx, cy, cz, r, csig, n_total);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_ellipses(const float* vx, const float* vy, const float* vz, int32_t V, const int32_t* members,
+                                 const int32_t* member_start, int32_t K, const float* cx, const float* cy,
+                                 const float* cz, const float* r, float* ahat, float* axes, hipStream_t st) {
+    hipLaunchKernelGGL(k_build_ellipses, dim3(blocks_for((size_t)K * (V - 1), 128)), dim3(128), 0, st, vx, vy, vz, V,
+                       members, member_start, K, cx, cy, cz, r, ahat, axes);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(min(blocks_for(n, 256), 4096)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* p, float v, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f32, dim3(min(blocks_for(n, 256), 4096)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace hair

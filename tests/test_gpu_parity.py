@@ -1,0 +1,272 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C-ABI.
+
+Bar: projected segments, tile bins and per-pixel fragment order bit-exact; radiance within
+1e-4 relative per pixel (float32 kernel vs float64 oracle; absolute floor 1e-7 for
+near-black values).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import hairsynth as hs
+from oracle import lod as OL
+from oracle import render as R
+
+pytestmark = pytest.mark.gpu
+
+RTOL, ATOL = 1e-4, 1e-7
+
+
+def mat_of(asset):
+    return tuple(float(v) for v in asset.material.as_array())
+
+
+def assert_radiance(got, ref, mask=None, what=""):
+    got = np.asarray(got, dtype=np.float64)
+    err = np.abs(got - ref) - (RTOL * np.abs(ref) + ATOL)
+    if mask is not None:
+        err = err[mask]
+    bad = int((err > 0).sum())
+    worst = float((np.abs(got - ref) / np.maximum(np.abs(ref), 1e-7)).max()) if got.size else 0.0
+    print(f"[{what}] max rel err {worst:.3e}, violations {bad}", flush=True)
+    assert bad == 0, f"{what}: {bad} values beyond 1e-4 rel"
+
+
+@pytest.fixture(scope="module")
+def ctx(hip):
+    c = hip.Context(0)
+    yield c
+    c.close()
+
+
+def _render(hip, ctx, asset, cam, lights, level=0, aid=None, lod=None):
+    if aid is None:
+        aid = ctx.upload_asset(asset)
+    if lod is not None:
+        ctx.set_lod(aid, 1, lod)
+    ws = ctx.workspace()
+    img, stats, rc = ctx.render(aid, level, cam, lights, ws=ws)
+    torch.cuda.synchronize()
+    return aid, ws, img.cpu().numpy(), stats
+
+
+def test_segments_bins_bit_exact_config1(hip, ctx):
+    print("case: config 1 segments/bins", flush=True)
+    asset, cam, lights = hs.config(1)
+    aid, ws, img, stats = _render(hip, ctx, asset, cam, lights)
+    geom = R.strand_level(asset)
+    c, XA, YA, XB, YB, izA, izB, hw, hw_fx, vis = R.segment_records(geom, cam)
+    ri, rf = ctx.debug_segments(ws, asset.n_segments)
+    v = (ri[:, 5] & 1).astype(bool)
+    assert np.array_equal(v, vis)
+    for col, ref in enumerate((XA, YA, XB, YB, hw_fx)):
+        assert np.array_equal(ri[v, col], ref[vis]), col
+    assert np.array_equal(rf[:, 0].view(np.uint32), izA.view(np.uint32))
+    assert np.array_equal(rf[:, 1].view(np.uint32), izB.view(np.uint32))
+    assert np.array_equal(rf[:, 2].view(np.uint32), hw.view(np.uint32))
+    sign = R.rs.h_sign(geom.pA, geom.pB, c, XA, YA, XB, YB)
+    assert np.array_equal(((ri[v, 5] & 2) != 0), sign[vis] < 0)
+    # bins: same tile sets (list order inside a tile is free)
+    ntx, nty = -(-cam.width // 16), -(-cam.height // 16)
+    tid, sid, _ = R.rs.bins(XA, YA, XB, YB, hw_fx, vis, cam.width, cam.height, 16)
+    assert stats["pairs"] == len(tid)
+    ts, segs = ctx.debug_bins(ws, ntx * nty, int(stats["pairs"]))
+    ref_start = np.searchsorted(tid, np.arange(ntx * nty + 1))
+    assert np.array_equal(ts.astype(np.int64), ref_start)
+    for t in range(ntx * nty):
+        assert np.array_equal(np.sort(segs[ts[t]:ts[t + 1]]), sid[ref_start[t]:ref_start[t + 1]]), t
+    ws.close()
+
+
+def test_radiance_and_count_config1(hip, ctx):
+    print("case: config 1 radiance", flush=True)
+    asset, cam, lights = hs.config(1)
+    aid, ws, img, stats = _render(hip, ctx, asset, cam, lights)
+    ref, ras = R.render(R.strand_level(asset), cam, lights, mat_of(asset))
+    assert stats["fragments"] == len(ras.seg)
+    assert stats["overflow_pixels"] == 0
+    assert_radiance(img, ref, what="config 1")
+    ws.close()
+
+
+def _oracle_lists(ras, x0, y0, w, h, W):
+    px = ras.pix % W
+    py = ras.pix // W
+    sel = (px >= x0) & (px < x0 + w) & (py >= y0) & (py < y0 + h)
+    local = (py[sel] - y0) * w + (px[sel] - x0)
+    order = np.lexsort((ras.seg[sel], ras.key[sel], local))
+    counts = np.bincount(local, minlength=w * h)
+    return counts.reshape(h, w), ras.key[sel][order], ras.seg[sel][order], np.nonzero(sel)[0][order]
+
+
+def test_fragment_order_bit_exact(hip, ctx):
+    print("case: fragment lists config 1 rect", flush=True)
+    asset, cam, lights = hs.config(1)
+    aid = ctx.upload_asset(asset)
+    geom = R.strand_level(asset)
+    ras = R.rasterize(geom, cam)
+    cnt = np.bincount(ras.pix, minlength=cam.width * cam.height).reshape(cam.height, cam.width)
+    j, i = np.unravel_index(np.argmax(cnt), cnt.shape)
+    x0, y0 = max(0, i - 20), max(0, j - 20)
+    w, h = min(40, cam.width - x0), min(40, cam.height - y0)
+    counts, keys, segs, alpha, hoff = ctx.debug_fragments(aid, 0, cam, lights, x0, y0, w, h, cap=400000)
+    rc, rk, rsg, idx = _oracle_lists(ras, x0, y0, w, h, cam.width)
+    assert np.array_equal(counts, rc)
+    assert np.array_equal(keys, rk)
+    assert np.array_equal(segs, rsg)
+    a_ref, h_ref = R.fragment_alpha_h(ras, R._t(ras.hw[ras.seg]))
+    assert np.allclose(alpha, a_ref.numpy()[idx], rtol=1e-5, atol=1e-7)
+    assert np.allclose(hoff, h_ref.numpy()[idx], rtol=1e-5, atol=2e-6)
+    assert counts.max() > 10
+
+
+@pytest.mark.parametrize("W,H", [(17, 9), (1, 1), (33, 47)])
+def test_ragged_and_tiny_images(hip, ctx, W, H):
+    print(f"case: ragged {W}x{H}", flush=True)
+    asset = hs.make_asset(300, 8, 60.0, seed=5)
+    cam = hs.camera_for(asset, W, H)
+    lights = hs.default_lights(asset, with_point=True)
+    aid, ws, img, stats = _render(hip, ctx, asset, cam, lights)
+    ref, ras = R.render(R.strand_level(asset), cam, lights, mat_of(asset))
+    assert stats["fragments"] == len(ras.seg)
+    assert_radiance(img, ref, what=f"{W}x{H}")
+    ws.close()
+
+
+def test_empty_frame_and_culling(hip, ctx):
+    print("case: empty frame", flush=True)
+    asset = hs.make_asset(50, 6, 60.0, seed=2)
+    cam = hs.camera_for(asset, 64, 48)
+    # turn the camera around: everything is behind it
+    cam.rot = (np.diag([-1.0, 1.0, -1.0]) @ cam.rot.astype(np.float64)).astype(np.float32)
+    aid, ws, img, stats = _render(hip, ctx, asset, cam, hs.default_lights(asset, False))
+    assert stats["fragments"] == 0 and stats["segments_visible"] == 0
+    assert np.all(img == 0.0)
+    ws.close()
+
+
+def test_single_strand_and_point_light(hip, ctx):
+    print("case: single strand", flush=True)
+    asset = hs.make_asset(1, 40, 60.0, seed=8)
+    cam = hs.camera_for(asset, 96, 96)
+    lights = hs.default_lights(asset, with_point=True)
+    aid, ws, img, stats = _render(hip, ctx, asset, cam, lights)
+    ref, ras = R.render(R.strand_level(asset), cam, lights, mat_of(asset))
+    assert stats["fragments"] == len(ras.seg) > 0
+    assert_radiance(img, ref, what="single strand")
+    ws.close()
+
+
+def test_determinism_bitwise(hip, ctx):
+    print("case: determinism", flush=True)
+    asset, cam, lights = hs.config(2, scale=0.05)
+    aid = ctx.upload_asset(asset)
+    ws = ctx.workspace()
+    a, s1, _ = ctx.render(aid, 0, cam, lights, ws=ws)
+    a = a.clone()
+    b, s2, _ = ctx.render(aid, 0, cam, lights, ws=ws)
+    torch.cuda.synchronize()
+    assert s1["fragments"] == s2["fragments"]
+    assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+    ws.close()
+
+
+# ---- thick-hair levels ---------------------------------------------------------------------
+
+def _cluster_case(n=2000, segs=12, k=40, W=160, H=128, seed=21):
+    asset = hs.make_asset(n, segs, 90.0, seed=seed, sigma_spread=True)
+    cam = hs.camera_for(asset, W, H)
+    lights = hs.default_lights(asset, with_point=True)
+    assign = hs.kmeans_assign(asset, k, seed=seed)
+    return asset, cam, lights, assign
+
+
+def test_build_lod_matches_oracle(hip, ctx):
+    print("case: build_lod", flush=True)
+    asset, cam, lights, assign = _cluster_case()
+    assign2 = hs.kmeans_assign(asset, 7, seed=3)
+    aid = ctx.upload_asset(asset)
+    ctx.build_lod(aid, [assign, assign2])
+    nl, counts, S = ctx.lod_info(aid)
+    assert nl == 2 and counts[1] == assign.max() + 1 and counts[2] == assign2.max() + 1 and S == asset.segs
+    for lvl, asg in ((1, assign), (2, assign2)):
+        got = ctx.get_lod(aid, lvl)
+        ref = OL.build_level(asset, asg)
+        assert np.array_equal(got.centers, ref["centers"])                # same float64 order
+        assert np.array_equal(got.n_total, ref["n_total"])
+        assert np.array_equal(got.r, ref["r"])
+        assert np.array_equal(got.sigma_a, ref["sigma_a"])
+        assert np.allclose(got.axes, ref["axes"], rtol=2e-6, atol=0)
+        dots = np.abs((got.ahat.astype(np.float64) * ref["ahat"]).sum(-1))
+        elong = ref["axes"][..., 0] > ref["axes"][..., 1] * (1 + 1e-3)
+        assert np.all(dots[elong] > 1 - 1e-5)
+
+
+def test_cluster_level_radiance(hip, ctx):
+    print("case: cluster level radiance", flush=True)
+    asset, cam, lights, assign = _cluster_case()
+    lod = OL.build_level(asset, assign)
+    aid, ws, img, stats = _render(hip, ctx, asset, cam, lights, level=1, lod=lod)
+    geom = R.cluster_level(lod)
+    ref, ras = R.render(geom, cam, lights, mat_of(asset))
+    assert stats["fragments"] == len(ras.seg)
+    assert_radiance(img, ref, what="cluster level")
+    ws.close()
+
+
+def test_one_strand_clusters_match_strands_on_gpu(hip, ctx):
+    print("case: one-strand clusters", flush=True)
+    asset, cam, lights = hs.config(1, scale=0.2)
+    aid = ctx.upload_asset(asset)
+    ctx.build_lod(aid, [np.arange(asset.n_strands, dtype=np.int32)])
+    ws = ctx.workspace()
+    a, sa, _ = ctx.render(aid, 0, cam, lights, ws=ws)
+    a = a.cpu().numpy()
+    b, sb, _ = ctx.render(aid, 1, cam, lights, ws=ws)
+    b = b.cpu().numpy()
+    assert sa["fragments"] == sb["fragments"]
+    assert_radiance(b, a.astype(np.float64), what="one-strand LoD (GPU strands vs GPU clusters)")
+    ws.close()
+
+
+def test_select_level_matches_oracle(hip, ctx):
+    print("case: select level", flush=True)
+    asset, cam, lights, assign = _cluster_case(k=200)
+    assigns = [assign, hs.kmeans_assign(asset, 30, seed=1), hs.kmeans_assign(asset, 4, seed=1)]
+    aid = ctx.upload_asset(asset)
+    ctx.build_lod(aid, assigns)
+    geoms = [R.strand_level(asset)] + [R.cluster_level(ctx.get_lod(aid, l).__dict__) for l in (1, 2, 3)]
+    for eps in (0.5, 2.0, 6.0, 1e6):
+        assert ctx.select_level(aid, cam, eps) == R.select_level(geoms, cam, eps), eps
+
+
+# ---- full-size configuration (the benchmark's launch) ----------------------------------------
+
+def test_config2_full_size_sampled(hip, ctx):
+    """100k strands x 32 segments at 1920x1080: the GPU frame against the oracle on three
+    sampled pixel rectangles (dense, medium, sparse), plus determinism at full size."""
+    print("case: config 2 full size", flush=True)
+    asset, cam, lights = hs.config(2)
+    aid = ctx.upload_asset(asset)
+    ws = ctx.workspace()
+    img, stats, rc = ctx.render(aid, 0, cam, lights, ws=ws)
+    img2, stats2, _ = ctx.render(aid, 0, cam, lights, ws=ws.__class__(ctx))
+    torch.cuda.synchronize()
+    assert torch.equal(img.view(torch.int32), img2.view(torch.int32))
+    got = img.cpu().numpy()
+    print(f"config 2: {stats['fragments']} fragments, {stats['ms_total']:.3f} ms", flush=True)
+    alpha = got[..., 3]
+    ys, xs = np.nonzero(alpha > 0)
+    order = np.argsort(alpha[ys, xs])
+    picks = [order[-1], order[len(order) // 2], order[len(order) // 20]]
+    geom = R.strand_level(asset)
+    mat = mat_of(asset)
+    for pk in picks:
+        x0 = int(min(max(xs[pk] - 8, 0), cam.width - 24))
+        y0 = int(min(max(ys[pk] - 8, 0), cam.height - 24))
+        ref, ras = R.render(geom, cam, lights, mat, rect=(x0, y0, 24, 24))
+        assert_radiance(got[y0:y0 + 24, x0:x0 + 24], ref[y0:y0 + 24, x0:x0 + 24], what=f"config 2 rect {x0},{y0}")
+    ws.close()
