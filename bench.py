@@ -1,0 +1,180 @@
+"""Benchmark: strand-hair frames through the HIP library on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload: 100,000 strands x 32 segments (3.2 M segments, seeded synthetic generator), one
+directional and one point light, 1920 x 1080, strand level (the finest LoD level the
+per-request level choice returns for this asset).  A step is one request through the hot
+path: per-request level choice, projection, tile binning, coverage, per-pixel sort,
+shading and compositing; inputs are resident in HBM before the timed region.
+
+Prints one JSON line: Mfragments/s over the timed steps (fragments counted by the library,
+equal to the CPU oracle's count), frame ms (mean, p50, p99), the roofline of the dominant
+kernel (k_tile, measured with HIP events on its launch stream) and the CPU oracle timed on
+a bounded sample of the same frame.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "hair-100k-strands-32seg-1920x1080-2lights"
+METRIC = "Mfragments/s + frame ms (100k strands, 1080p); served p50/p99 latency"
+
+# Algorithmic operations per fragment, counted from the definition (step by step, each
+# add / mul / div / sqrt / compare / min / max / int op = 1; exp, asin, atan2, sin, cos =
+# one transcendental each).  Strand level.
+OPS_BASE = 18 + 7 + 18 + 35 + 32 + 11 + 8      # coverage, key, alpha+h, point+tangent, frame, blend, sort
+TRANS_BASE = 1                                  # asin(theta_o)
+OPS_DIR_LIGHT = 171                             # angles 25 + f_single 137 + accumulate 9
+OPS_POINT_LIGHT = 186                           # + 15: direction, distance, 1/d^2
+TRANS_PER_LIGHT = 15                            # atan2, asin(theta_i), sin, cos, 2 asin, 3 exp, 3 x (2 exp)
+TRANS_WEIGHT = 4                                # transcendental unit issues at 1/4 rate
+PEAK_LANE_OPS = 256 * 64 * 2.4e9                # 256 CUs x 64 lanes x 2.4 GHz (one op per lane per cycle)
+PEAK_HBM = 8.0e12
+
+KERNEL_SOURCES = ["paper_2405_10565_amd/csrc/hair_kernels.hip", "paper_2405_10565_amd/csrc/hair_shading.h",
+                  "paper_2405_10565_amd/csrc/hair_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile_hair_100k_1080p_traffic.txt")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """Bytes per k_tile launch from the committed counter summary, if it matches this source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_hash") != kernel_hash():
+        return None
+    try:
+        return float(vals["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def alg_ops(fragments: int, n_dir: int, n_point: int):
+    ops = fragments * (OPS_BASE + n_dir * OPS_DIR_LIGHT + n_point * OPS_POINT_LIGHT)
+    trans = fragments * (TRANS_BASE + (n_dir + n_point) * TRANS_PER_LIGHT)
+    return ops, trans
+
+
+def cpu_baseline(asset, cam, lights, rows: int = 16):
+    """The oracle, single-threaded, on a centre band of the frame."""
+    import torch
+    torch.set_num_threads(1)
+    from oracle import render as R
+    mat = tuple(float(v) for v in asset.material.as_array())
+    y0 = cam.height // 2 - rows // 2
+    t0 = time.perf_counter()
+    _, ras = R.render(R.strand_level(asset), cam, lights, mat, rect=(0, y0, cam.width, rows))
+    dt = time.perf_counter() - t0
+    return {"value": round(len(ras.seg) / dt / 1e6, 5), "unit": "Mfragments/s", "cores": 1, "kind": "oracle",
+            "sample": f"rows {y0}-{y0 + rows - 1} of the 1920x1080 frame ({len(ras.seg)} fragments, "
+                      f"{dt:.1f} s wall, torch/numpy float64 on 1 thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the renderer's multi-GPU split is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import hairsynth as hs
+    from paper_2405_10565_amd import binding as B
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    asset, cam, lights = hs.config(2)
+    ctx = B.Context(0)
+    aid = ctx.upload_asset(asset)
+    ws = ctx.workspace()
+    out = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device="cuda:0")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        level = ctx.select_level(aid, cam, 2.0, ws=ws, stream=stream)
+        _, st, _ = ctx.render(aid, level, cam, lights, out=out, ws=ws, stream=stream)
+        return st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    frames = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        frames.append(step())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    frags = sum(f["fragments"] for f in frames)
+    ms_frame = np.array([f["ms_total"] for f in frames])
+    ms_tile = np.array([f["ms_tile"] for f in frames])
+    n_dir = sum(1 for l in lights if l.kind == 0)
+    n_pt = len(lights) - n_dir
+    f1 = frames[0]["fragments"]
+    ops, trans = alg_ops(f1, n_dir, n_pt)
+    t_tile = float(ms_tile.mean()) * 1e-3
+    achieved = (ops + TRANS_WEIGHT * trans) / t_tile
+    traffic = read_traffic()
+    res = {
+        "metric": METRIC,
+        "value": round(frags / wall / 1e6, 3),
+        "unit": "Mfragments/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded generator; paper grooms not available)",
+        "config": {"workload": WORKLOAD, "strands": asset.n_strands, "segments": asset.n_segments,
+                   "width": cam.width, "height": cam.height, "lights": len(lights), "level": 0,
+                   "fragments_per_frame": f1, "pairs_per_frame": frames[0]["pairs"]},
+        "frame_ms": {"gpu_mean": round(float(ms_frame.mean()), 4), "gpu_p50": round(float(np.percentile(ms_frame, 50)), 4),
+                     "gpu_p99": round(float(np.percentile(ms_frame, 99)), 4),
+                     "project": round(float(np.mean([f["ms_project"] for f in frames])), 4),
+                     "bin": round(float(np.mean([f["ms_bin"] for f in frames])), 4),
+                     "tile": round(float(ms_tile.mean()), 4)},
+        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_LANE_OPS / 1e12, 2),
+                     "unit": "Tops/s", "frac": round(achieved / PEAK_LANE_OPS, 4),
+                     "traffic": traffic, "kernel": "k_tile",
+                     "ops_per_launch": int(ops + TRANS_WEIGHT * trans)},
+        "cpu_baseline": None,
+    }
+    ws.close()
+    ctx.close()
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(asset, cam, lights)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -13,7 +13,8 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhair.so")
+# HAIR_LIBRARY may name another build of the same library (e.g. an instrumented one).
+LIB_PATH = os.environ.get("HAIR_LIBRARY", os.path.join(HERE, "libhair.so"))
 
 HAIR_OK, HAIR_EINVAL, HAIR_ENOMEM, HAIR_ENOENT, HAIR_EDEVICE, HAIR_ERANGE = 0, -1, -2, -3, -4, -5
 HAIR_MAX_LIGHTS = 8

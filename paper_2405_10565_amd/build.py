@@ -33,25 +33,28 @@ def flags() -> list[str]:
             "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source for gfx950 and link libhair.so next to this file."""
+def build(verbose: bool = False, out: str = LIB, defines: tuple = ()) -> str:
+    """Compile every HIP source for gfx950 and link libhair.so (default: next to this file).
+
+    defines: extra preprocessor symbols, e.g. ("HAIR_PHASE_STATS",) for per-phase cycle
+    counters printed after each frame (an instrumented build written to `out`)."""
     objs = []
-    build_dir = os.path.join(HERE, "_build")
+    build_dir = os.path.join(os.path.dirname(os.path.abspath(out)), "_build")
     os.makedirs(build_dir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc(), *flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc(), *flags(), *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

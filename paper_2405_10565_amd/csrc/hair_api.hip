@@ -72,7 +72,9 @@ struct hair_ws {
     uint64_t max_bytes = 0;
     uint64_t held = 0;
     DevBuf seg, tile_cnt, tile_start, tile_cur, list, ctr;
-    hipEvent_t ev[5] = {};
+    DevBuf items, item_start, item_base, pix_cnt, pix_kmin, pix_kmax, pix_off;
+    DevBuf tile_tot, frag_base, tile_nb, batch_start, batches, frags;
+    hipEvent_t ev[7] = {};
     bool events = false;
     int64_t last_nseg = 0, last_ntiles = 0, last_pairs = 0;
     std::mutex mu;
@@ -281,10 +283,17 @@ int ws_events(hair_ws* ws) {
 struct FrameOut {
     Counters ctr;
     uint32_t pairs;
+    uint32_t n_batches;
     float ms[4];
 };
 
 // Project + bin + tile for one level; the caller holds ws->mu.
+//   k_project, k_scan                 per-segment records, per-tile counts and list offsets
+//   k_tile_items, k_scan              work items (list chunks) per tile      -> sync 1 (sizes)
+//   k_scatter                         tile lists
+//   k_count, k_tile_prep, k_scan x2   per-pixel counts / key ranges, offsets, batches -> sync 2
+//   k_batch_records, k_emit           batch table, fragment buffer
+//   k_batch                           sort, shade, blend (one workgroup per batch)
 int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, const hair_camera* cam,
               const hair_light* lights, int n_lights, float* rgba, const DebugDump* dbg, hipStream_t st,
               FrameOut* out, bool tiles_too = true) {
@@ -292,23 +301,32 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     const CamConst cc = cam_const(cam);
     const int ntx = (cam->width + kTile - 1) / kTile, nty = (cam->height + kTile - 1) / kTile;
     const int T = ntx * nty;
+    const int TS = T * kSub;   // (tile, sub-counter) slots
+    const size_t TP = (size_t)T * kTilePix;
     if ((rc = ws_events(ws))) return rc;
     if ((rc = ws_need(ws, ws->seg, sizeof(SegRec) * (size_t)std::max(lv.nseg, 1)))) return rc;
-    if ((rc = ws_need(ws, ws->tile_cnt, 4ull * T))) return rc;
-    if ((rc = ws_need(ws, ws->tile_start, 4ull * (T + 1)))) return rc;
-    if ((rc = ws_need(ws, ws->tile_cur, 4ull * T))) return rc;
+    if ((rc = ws_need(ws, ws->tile_cnt, 4ull * TS))) return rc;
+    if ((rc = ws_need(ws, ws->tile_start, 4ull * (TS + 1)))) return rc;
+    if ((rc = ws_need(ws, ws->tile_cur, 4ull * TS))) return rc;
     if ((rc = ws_need(ws, ws->ctr, sizeof(Counters)))) return rc;
+    if ((rc = ws_need(ws, ws->items, 4ull * T))) return rc;
+    if ((rc = ws_need(ws, ws->item_start, 4ull * (T + 1)))) return rc;
+    uint32_t* tile_cnt = ws->tile_cnt.as<uint32_t>();
+    uint32_t* tile_start = ws->tile_start.as<uint32_t>();
     HIP_TRY(ctx, hipEventRecord(ws->ev[0], st), "hipEventRecord");
-    HIP_TRY(ctx, launch_fill_u32(ws->tile_cnt.as<uint32_t>(), 0u, T, st), "fill");
-    HIP_TRY(ctx, launch_fill_u32(ws->tile_cur.as<uint32_t>(), 0u, T, st), "fill");
+    HIP_TRY(ctx, launch_fill_u32(tile_cnt, 0u, TS, st), "fill");
+    HIP_TRY(ctx, launch_fill_u32(ws->tile_cur.as<uint32_t>(), 0u, TS, st), "fill");
     HIP_TRY(ctx, launch_fill_u32(ws->ctr.as<uint32_t>(), 0u, sizeof(Counters) / 4, st), "fill");
-    HIP_TRY(ctx, launch_project(lv, cc, ws->seg.as<SegRec>(), ws->tile_cnt.as<uint32_t>(), ws->ctr.as<Counters>(), st),
-            "k_project");
-    HIP_TRY(ctx, launch_scan_tiles(ws->tile_cnt.as<uint32_t>(), ws->tile_start.as<uint32_t>(), T, st), "k_scan");
+    HIP_TRY(ctx, launch_project(lv, cc, ws->seg.as<SegRec>(), tile_cnt, ws->ctr.as<Counters>(), st), "k_project");
+    HIP_TRY(ctx, launch_scan_tiles(tile_cnt, tile_start, TS, st), "k_scan");
+    HIP_TRY(ctx, launch_tile_items(tile_start, T, ws->items.as<uint32_t>(), st), "k_tile_items");
+    HIP_TRY(ctx, launch_scan_tiles(ws->items.as<uint32_t>(), ws->item_start.as<uint32_t>(), T, st), "k_scan");
     HIP_TRY(ctx, hipEventRecord(ws->ev[1], st), "hipEventRecord");
-    uint32_t pairs = 0;
-    HIP_TRY(ctx, hipMemcpyAsync(&pairs, ws->tile_start.as<uint32_t>() + T, 4, hipMemcpyDeviceToHost, st), "copy");
+    uint32_t sizes1[2] = {0, 0};
+    HIP_TRY(ctx, hipMemcpyAsync(&sizes1[0], tile_start + TS, 4, hipMemcpyDeviceToHost, st), "copy");
+    HIP_TRY(ctx, hipMemcpyAsync(&sizes1[1], ws->item_start.as<uint32_t>() + T, 4, hipMemcpyDeviceToHost, st), "copy");
     HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
+    const uint32_t pairs = sizes1[0], n_items = sizes1[1];
     ws->last_nseg = lv.nseg;
     ws->last_ntiles = T;
     ws->last_pairs = pairs;
@@ -318,22 +336,75 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
         return HAIR_OK;
     }
     if ((rc = ws_need(ws, ws->list, 4ull * std::max<uint32_t>(pairs, 1)))) return rc;
+    if ((rc = ws_need(ws, ws->item_base, 4ull * kTilePix * std::max<uint32_t>(n_items, 1)))) return rc;
+    for (DevBuf* b : {&ws->pix_cnt, &ws->pix_kmin, &ws->pix_kmax, &ws->pix_off})
+        if ((rc = ws_need(ws, *b, 4 * TP))) return rc;
+    for (DevBuf* b : {&ws->tile_tot, &ws->tile_nb})
+        if ((rc = ws_need(ws, *b, 4ull * T))) return rc;
+    for (DevBuf* b : {&ws->frag_base, &ws->batch_start})
+        if ((rc = ws_need(ws, *b, 4ull * (T + 1)))) return rc;
+    FrameBufs f;
+    memset(&f, 0, sizeof(f));
+    f.T = T;
+    f.ntx = ntx;
+    f.seg = ws->seg.as<SegRec>();
+    f.tile_start = tile_start;
+    f.list = ws->list.as<uint32_t>();
+    f.item_start = ws->item_start.as<uint32_t>();
+    f.item_base = ws->item_base.as<uint32_t>();
+    f.pix_cnt = ws->pix_cnt.as<uint32_t>();
+    f.pix_kmin = ws->pix_kmin.as<uint32_t>();
+    f.pix_kmax = ws->pix_kmax.as<uint32_t>();
+    f.pix_off = ws->pix_off.as<uint32_t>();
+    f.tile_tot = ws->tile_tot.as<uint32_t>();
+    f.tile_nb = ws->tile_nb.as<uint32_t>();
+    f.frag_base = ws->frag_base.as<uint32_t>();
+    f.batch_start = ws->batch_start.as<uint32_t>();
+    f.ctr = ws->ctr.as<Counters>();
     HIP_TRY(ctx, hipEventRecord(ws->ev[2], st), "hipEventRecord");
-    HIP_TRY(ctx, launch_scatter(ws->seg.as<SegRec>(), lv.nseg, cc, ws->tile_start.as<uint32_t>(),
-                                ws->tile_cur.as<uint32_t>(), ws->list.as<uint32_t>(), st), "k_scatter");
+    HIP_TRY(ctx, launch_scatter(f.seg, lv.nseg, cc, tile_start, ws->tile_cur.as<uint32_t>(), ws->list.as<uint32_t>(), st),
+            "k_scatter");
+    HIP_TRY(ctx, launch_fill_u32(f.pix_cnt, 0u, TP, st), "fill");
+    HIP_TRY(ctx, launch_fill_u32(f.pix_kmin, 0xFFFFFFFFu, TP, st), "fill");
+    HIP_TRY(ctx, launch_fill_u32(f.pix_kmax, 0u, TP, st), "fill");
+    if (rgba) HIP_TRY(ctx, launch_fill_f32(rgba, 0.0f, 4ull * cam->width * cam->height, st), "fill");
+    HIP_TRY(ctx, launch_count(f, cc, n_items, st), "k_count");
+    HIP_TRY(ctx, launch_tile_prep(f, st), "k_tile_prep");
+    HIP_TRY(ctx, launch_scan_tiles(f.tile_tot, ws->frag_base.as<uint32_t>(), T, st), "k_scan");
+    HIP_TRY(ctx, launch_scan_tiles(f.tile_nb, ws->batch_start.as<uint32_t>(), T, st), "k_scan");
     HIP_TRY(ctx, hipEventRecord(ws->ev[3], st), "hipEventRecord");
-    HIP_TRY(ctx, launch_tile(lv, cc, lights_const(lights, n_lights), mat_const(a.mat), ws->seg.as<SegRec>(),
-                             ws->tile_start.as<uint32_t>(), ws->list.as<uint32_t>(), rgba, ws->ctr.as<Counters>(), dbg,
-                             nullptr, st), "k_tile");
+    uint32_t sizes2[2] = {0, 0};
+    HIP_TRY(ctx, hipMemcpyAsync(&sizes2[0], ws->frag_base.as<uint32_t>() + T, 4, hipMemcpyDeviceToHost, st), "copy");
+    HIP_TRY(ctx, hipMemcpyAsync(&sizes2[1], ws->batch_start.as<uint32_t>() + T, 4, hipMemcpyDeviceToHost, st), "copy");
+    HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
+    const uint32_t n_frags = sizes2[0], n_batches = sizes2[1];
+    if ((rc = ws_need(ws, ws->frags, 8ull * std::max<uint32_t>(n_frags, 1)))) return rc;
+    if ((rc = ws_need(ws, ws->batches, 16ull * std::max<uint32_t>(n_batches, 1)))) return rc;
+    f.frags = ws->frags.as<uint2>();
+    f.batches = ws->batches.as<uint4>();
     HIP_TRY(ctx, hipEventRecord(ws->ev[4], st), "hipEventRecord");
+    HIP_TRY(ctx, launch_batch_records(f, st), "k_batch_records");
+    HIP_TRY(ctx, launch_emit(f, cc, n_items, st), "k_emit");
+    HIP_TRY(ctx, hipEventRecord(ws->ev[5], st), "hipEventRecord");
+    if (rgba)
+        HIP_TRY(ctx, launch_batches(f, lv, cc, lights_const(lights, n_lights), mat_const(a.mat), f.seg, n_batches, rgba,
+                                    dbg, st), "k_batch");
+    HIP_TRY(ctx, hipEventRecord(ws->ev[6], st), "hipEventRecord");
     HIP_TRY(ctx, hipMemcpyAsync(&out->ctr, ws->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, st), "copy");
     HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
-    float t01 = 0, t23 = 0, t34 = 0, t04 = 0;
+    float t01 = 0, t23 = 0, t45 = 0, t56 = 0, t06 = 0;
     HIP_TRY(ctx, hipEventElapsedTime(&t01, ws->ev[0], ws->ev[1]), "elapsed");
     HIP_TRY(ctx, hipEventElapsedTime(&t23, ws->ev[2], ws->ev[3]), "elapsed");
-    HIP_TRY(ctx, hipEventElapsedTime(&t34, ws->ev[3], ws->ev[4]), "elapsed");
-    HIP_TRY(ctx, hipEventElapsedTime(&t04, ws->ev[0], ws->ev[4]), "elapsed");
-    out->ms[0] = t04; out->ms[1] = t01; out->ms[2] = t23; out->ms[3] = t34;
+    HIP_TRY(ctx, hipEventElapsedTime(&t45, ws->ev[4], ws->ev[5]), "elapsed");
+    HIP_TRY(ctx, hipEventElapsedTime(&t56, ws->ev[5], ws->ev[6]), "elapsed");
+    HIP_TRY(ctx, hipEventElapsedTime(&t06, ws->ev[0], ws->ev[6]), "elapsed");
+    out->ms[0] = t06; out->ms[1] = t01; out->ms[2] = t23 + t45; out->ms[3] = t56;
+    out->n_batches = n_batches;
+#ifdef HAIR_PHASE_STATS
+    fprintf(stderr, "phase cycles: count %llu emit %llu sort %llu shade %llu blend %llu | batches %u items %u\n",
+            out->ctr.phase[0], out->ctr.phase[1], out->ctr.phase[2], out->ctr.phase[3], out->ctr.phase[4], n_batches,
+            n_items);
+#endif
     return HAIR_OK;
 }
 
@@ -410,7 +481,10 @@ int hair_ws_destroy(hair_ws* ws) {
     if (!ws) return fail(HAIR_EINVAL, "null workspace");
     hair_ctx* ctx = ws->ctx;
     if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
-    for (DevBuf* b : {&ws->seg, &ws->tile_cnt, &ws->tile_start, &ws->tile_cur, &ws->list, &ws->ctr}) ctx_free(ctx, *b, ws);
+    for (DevBuf* b : {&ws->seg, &ws->tile_cnt, &ws->tile_start, &ws->tile_cur, &ws->list, &ws->ctr, &ws->items,
+                      &ws->item_start, &ws->item_base, &ws->pix_cnt, &ws->pix_kmin, &ws->pix_kmax, &ws->pix_off,
+                      &ws->tile_tot, &ws->frag_base, &ws->tile_nb, &ws->batch_start, &ws->batches, &ws->frags})
+        ctx_free(ctx, *b, ws);
     if (ws->events)
         for (auto& e : ws->ev) (void)hipEventDestroy(e);
     if (ctx->default_ws == ws) ctx->default_ws = nullptr;
@@ -803,9 +877,11 @@ int hair_debug_bins(hair_ws* ws, int64_t n_tiles, uint32_t* tile_start, int64_t 
         return fail(HAIR_EINVAL, "last render had %lld tiles and %lld pairs", (long long)ws->last_ntiles,
                     (long long)ws->last_pairs);
     std::lock_guard<std::mutex> g(ws->mu);
-    hipError_t e = hipMemcpy(tile_start, ws->tile_start.p, 4 * (n_tiles + 1), hipMemcpyDeviceToHost);
+    std::vector<uint32_t> full((size_t)n_tiles * kSub + 1);
+    hipError_t e = hipMemcpy(full.data(), ws->tile_start.p, 4 * full.size(), hipMemcpyDeviceToHost);
     if (e == hipSuccess && n_pairs) e = hipMemcpy(tile_segs, ws->list.p, 4 * n_pairs, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return dev_fail(ws->ctx, e, "debug_bins");
+    for (int64_t t = 0; t <= n_tiles; ++t) tile_start[t] = full[(size_t)t * kSub];
     return HAIR_OK;
 }
 

@@ -15,6 +15,7 @@ constexpr int kGuard = 16384;                    // guard band, 1/16-px units (1
 constexpr int kMaxAxis = 16384;                  // longest segment extent per axis (1/16 px)
 constexpr int kMaxHwFx = 4096;                   // widest coverage half-width (1/16 px)
 constexpr int kMaxListLen = (1 << 24) - 1;       // per-tile list limit (24-bit local index)
+constexpr int kSub = 16;                         // counters per tile (spreads binning atomics)
 
 // Projected segment, one per segment of the rendered level (32 bytes, AoS for gathers).
 struct SegRec {
@@ -82,6 +83,7 @@ struct Counters {
     uint32_t max_hw_bits;    // float bits of the largest visible half-width (non-negative)
     uint32_t list_overflow;  // tiles whose list exceeded the 24-bit local index
     uint32_t pad;
+    unsigned long long phase[8];  // per-phase cycle sums (instrumented builds only)
 };
 
 // Optional per-pixel fragment dump of a pixel rectangle (tests).
@@ -103,15 +105,41 @@ struct GradOut {
     float* d_sig;            // [3][K]
 };
 
+// Device buffers of one frame's tile pipeline (T tiles of kTilePix pixels).
+struct FrameBufs {
+    int32_t T, ntx;
+    const SegRec* seg;
+    const uint32_t* tile_start;   // [T * kSub + 1]: tile t's list is [tile_start[t kSub], tile_start[(t+1) kSub])
+    const uint32_t* list;         // segment ids
+    const uint32_t* item_start;   // [T + 1] exclusive scan of per-tile work items
+    uint32_t* item_base;          // [items][kTilePix] each item's slice of each pixel's range
+    uint32_t* pix_cnt;            // [T][kTilePix] fragments per pixel
+    uint32_t* pix_kmin;           // [T][kTilePix] smallest depth key per pixel
+    uint32_t* pix_kmax;           // [T][kTilePix] largest depth key per pixel
+    uint32_t* pix_off;            // [T][kTilePix] exclusive prefix of pix_cnt within the tile
+    uint32_t* tile_tot;           // [T] fragments per tile
+    uint32_t* tile_nb;            // [T] batches per tile
+    const uint32_t* frag_base;    // [T + 1] exclusive scan of tile_tot
+    const uint32_t* batch_start;  // [T + 1] exclusive scan of tile_nb
+    uint4* batches;               // [batches]: (tile, p0, p1, oversized)
+    uint2* frags;                 // [fragments]: (depth key, local list index | pixel << 24)
+    Counters* ctr;
+};
+
 // Kernel launchers (hair_kernels.hip).
 hipError_t launch_project(const LevelDev& lv, const CamConst& cam, SegRec* seg, uint32_t* tile_cnt,
                           Counters* ctr, hipStream_t st);
 hipError_t launch_scan_tiles(const uint32_t* cnt, uint32_t* start, int32_t n, hipStream_t st);
 hipError_t launch_scatter(const SegRec* seg, int32_t nseg, const CamConst& cam, const uint32_t* tile_start,
                           uint32_t* tile_cur, uint32_t* list, hipStream_t st);
-hipError_t launch_tile(const LevelDev& lv, const CamConst& cam, const LightsConst& lights, const MatConst& mat,
-                       const SegRec* seg, const uint32_t* tile_start, const uint32_t* list, float* rgba,
-                       Counters* ctr, const DebugDump* dbg, const GradOut* grad, hipStream_t st);
+hipError_t launch_tile_items(const uint32_t* tile_start, int T, uint32_t* items, hipStream_t st);
+hipError_t launch_count(const FrameBufs& f, const CamConst& cam, uint32_t n_items, hipStream_t st);
+hipError_t launch_tile_prep(const FrameBufs& f, hipStream_t st);
+hipError_t launch_batch_records(const FrameBufs& f, hipStream_t st);
+hipError_t launch_emit(const FrameBufs& f, const CamConst& cam, uint32_t n_items, hipStream_t st);
+hipError_t launch_batches(const FrameBufs& f, const LevelDev& lv, const CamConst& cam, const LightsConst& lights,
+                          const MatConst& mat, const SegRec* seg, uint32_t n_batches, float* rgba,
+                          const DebugDump* dbg, hipStream_t st);
 hipError_t launch_build_centers(const float* vx, const float* vy, const float* vz, const float* width,
                                 const float* sig, int32_t n_strands, int32_t V, const int32_t* members,
                                 const int32_t* member_start, int32_t K, float* cx, float* cy, float* cz,

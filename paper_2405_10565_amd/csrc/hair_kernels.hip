@@ -1,19 +1,19 @@
 // Device kernels of the LoD hair renderer (gfx950 / MI355X).
 //
 // Frame pipeline, all on the caller's stream:
-//   k_project   one thread per segment: float32 projection and 1/16-pixel snapping, screen
-//               half-width (Sec. 5.2, hair width calculation), culling, and the count of
-//               segments per 16x16 tile (integer box of the segment expanded by its radius).
-//   k_scan      exclusive prefix sum of the per-tile counts -> tile list offsets.
-//   k_scatter   one thread per segment: append its id to every overlapped tile's list.
-//   k_tile      one 256-thread workgroup per tile, all fragment work in LDS:
-//                 count   per-pixel fragment counts and depth-key range (exact integer coverage)
-//                 batch   whole pixels packed into LDS batches of <= kCap fragments
-//                 emit    (key, local index) records into per-pixel ranges
-//                 sort    per-pixel bucket sort (buckets = linear key ranges of each pixel)
-//                         + insertion sort inside buckets: exact (key, segment id) order
-//                 shade   one lane per fragment: alpha, cross-section offset h, radiance
-//                 blend   two-level segmented scan of front-to-back "over" -> RGBA
+//   k_project        one thread per segment: float32 projection and 1/16-pixel snapping, screen
+//                    half-width (Sec. 5.2, hair width calculation), culling, and the count of
+//                    segments per 16x16 tile (integer box of the segment expanded by its radius).
+//   k_scan           exclusive prefix sums (tile list offsets, work items, fragment and batch bases).
+//   k_scatter        one thread per segment: append its id to every overlapped tile's list.
+//   k_count          per (tile, list chunk): exact integer coverage -> per-pixel fragment counts
+//                    and depth-key ranges (LDS-aggregated, then one global atomic per pixel).
+//   k_tile_prep      per tile: pixel offsets, and whole pixels packed into batches of <= kCap.
+//   k_emit           per (tile, list chunk): (key, local index) records into the fragment buffer.
+//   k_batch          one workgroup per batch, all in LDS: exact per-pixel order by a bucket sort
+//                    (buckets = linear key ranges of each pixel) + insertion inside buckets,
+//                    one lane per fragment for shading, front-to-back blending by a two-level
+//                    segmented scan, coalesced RGBA stores.
 // The integer-deciding steps (projection, snapping, half-width, depth key) are float32 with
 // one rounding per operation and no contraction, so they match a float32 reference bit for bit.
 #include "hair_internal.h"
@@ -177,8 +177,9 @@ __global__ __launch_bounds__(256) void k_project(LevelDev lv, CamConst cam, SegR
             atomicMax(&s_maxhw, __float_as_uint(hw));
             const int ntx = (cam.W + kTile - 1) / kTile, nty = (cam.H + kTile - 1) / kTile;
             const TileRect tr = tile_rect(r, ntx, nty);
+            const int sub = (g >> 8) & (kSub - 1);
             for (int ty = tr.ty0; ty <= tr.ty1; ++ty)
-                for (int tx = tr.tx0; tx <= tr.tx1; ++tx) atomicAdd(&tile_cnt[ty * ntx + tx], 1u);
+                for (int tx = tr.tx0; tx <= tr.tx1; ++tx) atomicAdd(&tile_cnt[(ty * ntx + tx) * kSub + sub], 1u);
         }
     }
     const int nvis = __syncthreads_count(vis);
@@ -222,9 +223,10 @@ __global__ __launch_bounds__(256) void k_scatter(const SegRec* __restrict__ seg,
     const SegRec r = seg[g];
     if (!(r.hwfx & kFlagVisible)) return;
     const TileRect tr = tile_rect(r, ntx, nty);
+    const int sub = (g >> 8) & (kSub - 1);
     for (int ty = tr.ty0; ty <= tr.ty1; ++ty)
         for (int tx = tr.tx0; tx <= tr.tx1; ++tx) {
-            const int t = ty * ntx + tx;
+            const int t = (ty * ntx + tx) * kSub + sub;
             const uint32_t pos = atomicAdd(&tile_cur[t], 1u);
             list[tile_start[t] + pos] = (uint32_t)g;
         }
@@ -295,23 +297,17 @@ __device__ inline uint32_t depth_key(const SegRec& s, long long tnum, long long 
     return 0xFFFFFFFFu - __float_as_uint(iz);
 }
 
-struct TileArgs {
+struct ShadeArgs {
     LevelDev lv;
     CamConst cam;
     LightsConst lights;
     MatConst mat;
     const SegRec* seg;
-    const uint32_t* tile_start;
-    const uint32_t* list;
-    float* rgba;
-    Counters* ctr;
-    DebugDump dbg;
-    int has_dbg;
-    int ntx, nty;
 };
 
 // Radiance (RGB), coverage alpha and cross-section offset of one fragment.
-__device__ inline void shade_fragment(const TileArgs& a, uint32_t gseg, int pxg, int pyg, float& alpha, float& hoff,
+template <int KIND>
+__device__ inline void shade_fragment(const ShadeArgs& a, uint32_t gseg, int pxg, int pyg, float& alpha, float& hoff,
                                       float L[3]) {
     const SegRec s = a.seg[gseg];
     const long long ex = 16LL * pxg + 8 - s.xa, ey = 16LL * pyg + 8 - s.ya;
@@ -357,7 +353,7 @@ __device__ inline void shade_fragment(const TileArgs& a, uint32_t gseg, int pxg,
     ClusterFrag<float> cf;
     float a_len = 0, b_len = 0, W = 0;
     V3<float> ah{}, bh{};
-    if (lv.kind == 0) {
+    if (KIND == 0) {
         sig[0] = lv.sig[owner];
         sig[1] = lv.sig[lv.n_owner + owner];
         sig[2] = lv.sig[2 * lv.n_owner + owner];
@@ -398,7 +394,7 @@ __device__ inline void shade_fragment(const TileArgs& a, uint32_t gseg, int pxg,
         const float xd = 0.5f * fabsf(ti - to);
         const float cos_ti = sqrtf((1.0f - sc) * (1.0f + sc));
         float f[3];
-        if (lv.kind == 0) {
+        if (KIND == 0) {
             f_single(th, xd, phi, h, sig, a.mat, f);
         } else {
             // chord of the view ray's entry point toward the light, in the cross-section
@@ -447,285 +443,379 @@ __device__ inline uint32_t block_exscan_u32(uint32_t v, uint32_t* s_tmp, uint32_
     return total;
 }
 
-__global__ __launch_bounds__(kNT) void k_tile(TileArgs a) {
-    __shared__ uint32_t s_cnt[kTilePix];
-    __shared__ uint32_t s_kmin[kTilePix];
-    __shared__ uint32_t s_kmax[kTilePix];
-    __shared__ uint32_t s_off[kTilePix + 1];
-    __shared__ uint32_t s_cur[kTilePix];
-    __shared__ uint32_t s_tmp[kNT];
-    __shared__ uint2 s_B[kCap];
-    __shared__ uint32_t s_work[3 * kCap];     // A records (2 words) + bucket counters, later payload
-    __shared__ float s_agg[kNT * 4];          // run aggregates (C rgb, T)
-    __shared__ uint32_t s_aggh[kNT];
+#ifdef HAIR_PHASE_STATS
+#define PHASE_BEGIN() const unsigned long long ph_t0 = wall_clock64()
+// (the barrier here only makes the timing cover the whole block; correctness never relies on it)
+#define PHASE_END(ctr, i)                                                      \
+    do {                                                                       \
+        __syncthreads();                                                       \
+        if (threadIdx.x == 0) atomicAdd(&(ctr)->phase[i], wall_clock64() - ph_t0); \
+    } while (0)
+#else
+#define PHASE_BEGIN() do {} while (0)
+#define PHASE_END(ctr, i) do {} while (0)
+#endif
 
-    uint2* s_A = reinterpret_cast<uint2*>(s_work);
-    uint32_t* s_bk = s_work + 2 * kCap;
-    float* s_pay = reinterpret_cast<float*>(s_work);
+// Work items of the count and emit kernels: chunks of kNT consecutive entries of a tile list.
+__device__ inline void item_of(const uint32_t* item_start, int T, uint32_t item, int& tile, uint32_t& chunk) {
+    int lo = 0, hi = T - 1;   // last tile with item_start[tile] <= item
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (item_start[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    tile = lo;
+    chunk = item - item_start[lo];
+}
 
-    // XCD-aware tile order: consecutive workgroups land on different XCDs, so give each XCD a
-    // contiguous band of tiles (shared segments stay in that XCD's L2).
-    const int nb = gridDim.x;
-    const int b = blockIdx.x;
-    const int q = nb / 8, rem = nb % 8, x = b % 8, slot = b / 8;
-    const int tile = x * q + min(x, rem) + slot;
-    const int tx = tile % a.ntx, ty = tile / a.ntx;
-    const int px0 = tx * kTile, py0 = ty * kTile;
+__global__ __launch_bounds__(256) void k_tile_items(const uint32_t* __restrict__ tile_start, int T,
+                                                    uint32_t* __restrict__ items) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const uint32_t n = tile_start[(t + 1) * kSub] - tile_start[t * kSub];
+    items[t] = (n + kNT - 1) / kNT;
+}
+
+// Count pass: per-pixel fragment counts and depth-key range of each tile.  Each item adds
+// its LDS-aggregated counts to the tile's pixels and keeps the returned base (its slice of
+// every pixel's range).
+__global__ __launch_bounds__(kNT) void k_count(FrameBufs f, CamConst cam, uint32_t n_items) {
+    __shared__ uint32_t s_cnt[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix];
+    __shared__ int s_tile;
+    __shared__ uint32_t s_chunk;
+    PHASE_BEGIN();
+    const uint32_t item = blockIdx.x;
+    if (item >= n_items) return;
     const int t = threadIdx.x;
-    const uint32_t lstart = a.tile_start[tile];
-    const uint32_t n = a.tile_start[tile + 1] - lstart;
-    const uint32_t* list = a.list + lstart;
-
+    if (t == 0) {
+        int tile;
+        uint32_t chunk;
+        item_of(f.item_start, f.T, item, tile, chunk);
+        s_tile = tile;
+        s_chunk = chunk;
+    }
     s_cnt[t] = 0;
     s_kmin[t] = 0xFFFFFFFFu;
     s_kmax[t] = 0;
-    if (n > (uint32_t)kMaxListLen) {
-        if (t == 0) atomicAdd(&a.ctr->list_overflow, 1u);
-        return;
+    __syncthreads();
+    const int tile = s_tile;
+    const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
+    const uint32_t lstart = f.tile_start[tile * kSub];
+    const uint32_t n = f.tile_start[(tile + 1) * kSub] - lstart;
+    const uint32_t j = s_chunk * kNT + t;
+    if (j < n) {
+        const SegRec s = f.seg[f.list[lstart + j]];
+        for_each_fragment(s, px0, py0, 0, kTile - 1, cam.W, cam.H, [&](int li, int lj, long long tnum, long long tden, long long) {
+            const int p = lj * kTile + li;
+            const uint32_t key = depth_key(s, tnum, tden);
+            atomicAdd(&s_cnt[p], 1u);
+            atomicMin(&s_kmin[p], key);
+            atomicMax(&s_kmax[p], key);
+        });
     }
     __syncthreads();
+    const size_t q = (size_t)tile * kTilePix + t;
+    uint32_t base = 0;
+    if (s_cnt[t]) {
+        base = atomicAdd(&f.pix_cnt[q], s_cnt[t]);
+        atomicMin(&f.pix_kmin[q], s_kmin[t]);
+        atomicMax(&f.pix_kmax[q], s_kmax[t]);
+    }
+    f.item_base[(size_t)item * kTilePix + t] = base;
+    PHASE_END(f.ctr, 0);
+}
 
-    // ---- count pass: per-pixel fragment counts and key range
-    for (uint32_t base = 0; base < n; base += kNT) {
-        const uint32_t j = base + t;
-        if (j < n) {
-            const SegRec s = a.seg[list[j]];
-            for_each_fragment(s, px0, py0, 0, kTile - 1, a.cam.W, a.cam.H, [&](int li, int lj, long long tnum, long long tden, long long) {
-                const int p = lj * kTile + li;
-                const uint32_t key = depth_key(s, tnum, tden);
-                atomicAdd(&s_cnt[p], 1u);
-                atomicMin(&s_kmin[p], key);
-                atomicMax(&s_kmax[p], key);
-            });
-        }
+// Greedy batch packing of whole pixels: from p0 skip empty pixels, then take the longest run
+// [p0, p1) whose fragments fit one LDS batch.  A pixel deeper than a batch is "oversized".
+__device__ inline bool next_batch(const uint32_t* s_cnt, const uint32_t* s_off, int& p0, int& p1, bool& oversized) {
+    while (p0 < kTilePix && s_cnt[p0] == 0) ++p0;
+    if (p0 >= kTilePix) return false;
+    oversized = s_cnt[p0] > (uint32_t)kCap;
+    if (oversized) {
+        p1 = p0 + 1;
+        return true;
     }
+    int lo = p0 + 1, hi = kTilePix;
+    const uint32_t o0 = s_off[p0];
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_off[mid] - o0 <= (uint32_t)kCap) lo = mid; else hi = mid - 1;
+    }
+    p1 = lo;
+    return true;
+}
+
+// Per tile: pixel offsets, fragment total and number of batches.
+__global__ __launch_bounds__(kNT) void k_tile_prep(FrameBufs f) {
+    __shared__ uint32_t s_cnt[kTilePix], s_off[kTilePix + 1], s_tmp[kNT];
+    const int tile = blockIdx.x, t = threadIdx.x;
+    const size_t q = (size_t)tile * kTilePix + t;
+    const uint32_t c = f.pix_cnt[q];
+    s_cnt[t] = c;
+    uint32_t ex;
+    const uint32_t total = block_exscan_u32(c, s_tmp, ex);
+    s_off[t] = ex;
+    f.pix_off[q] = ex;
+    if (t == 0) s_off[kTilePix] = total;
     __syncthreads();
-    uint32_t my_off;
-    const uint32_t total = block_exscan_u32(s_cnt[t], s_tmp, my_off);
-    s_off[t] = my_off;
     if (t == 0) {
-        s_off[kTilePix] = total;
-        if (total) atomicAdd(&a.ctr->fragments, (unsigned long long)total);
+        f.tile_tot[tile] = total;
+        uint32_t nb = 0, over = 0;
+        int p0 = 0, p1;
+        bool oversized;
+        while (next_batch(s_cnt, s_off, p0, p1, oversized)) {
+            ++nb;
+            over += oversized;
+            p0 = p1;
+        }
+        f.tile_nb[tile] = nb;
+        if (total) atomicAdd(&f.ctr->fragments, (unsigned long long)total);
+        if (over) atomicAdd(&f.ctr->overflow_pixels, over);
+    }
+}
+
+__global__ __launch_bounds__(kNT) void k_batch_records(FrameBufs f) {
+    __shared__ uint32_t s_cnt[kTilePix], s_off[kTilePix + 1];
+    const int tile = blockIdx.x, t = threadIdx.x;
+    const size_t q = (size_t)tile * kTilePix + t;
+    s_cnt[t] = f.pix_cnt[q];
+    s_off[t] = f.pix_off[q];
+    if (t == 0) s_off[kTilePix] = f.tile_tot[tile];
+    __syncthreads();
+    if (t == 0) {
+        uint32_t b = f.batch_start[tile];
+        int p0 = 0, p1;
+        bool oversized;
+        while (next_batch(s_cnt, s_off, p0, p1, oversized)) {
+            f.batches[b++] = make_uint4((uint32_t)tile, (uint32_t)p0, (uint32_t)p1, oversized ? 1u : 0u);
+            p0 = p1;
+        }
+    }
+}
+
+// Emit pass: every fragment into the frame's fragment buffer at
+// frag_base[tile] + pix_off[pixel] + (the item's slice of the pixel) + local slot.
+__global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam, uint32_t n_items) {
+    __shared__ uint32_t s_cur[kTilePix], s_pos[kTilePix];
+    __shared__ int s_tile;
+    __shared__ uint32_t s_chunk;
+    PHASE_BEGIN();
+    const uint32_t item = blockIdx.x;
+    if (item >= n_items) return;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        int tile;
+        uint32_t chunk;
+        item_of(f.item_start, f.T, item, tile, chunk);
+        s_tile = tile;
+        s_chunk = chunk;
     }
     __syncthreads();
-
-    const int W = a.cam.W, H = a.cam.H;
-    int p0 = 0;
-    while (p0 < kTilePix) {
-        // largest p1 with off[p1] - off[p0] <= kCap (whole pixels per batch)
-        int lo = p0 + 1, hi = kTilePix;
-        const uint32_t o0 = s_off[p0];
-        if (s_off[lo] - o0 > (uint32_t)kCap) {
-            hi = lo;   // a single pixel deeper than the batch capacity
-        } else {
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_off[mid] - o0 <= (uint32_t)kCap) lo = mid; else hi = mid - 1;
-            }
-            hi = lo;
-        }
-        const int p1 = hi;
-        const uint32_t Fb = s_off[p1] - o0;
-        const bool oversized = Fb > (uint32_t)kCap;
-        if (oversized) {
-            if (t == 0) {
-                atomicAdd(&a.ctr->overflow_pixels, 1u);
-                const int gx = px0 + (p0 % kTile), gy = py0 + (p0 / kTile);
-                if (gx < W && gy < H) {
-                    float* o = a.rgba + 4 * ((size_t)gy * W + gx);
-                    o[0] = o[1] = o[2] = o[3] = 0.0f;
-                }
-            }
-            __syncthreads();
-            p0 = p1;
-            continue;
-        }
-        // pixels of the batch with no fragment
-        if (t >= p0 && t < p1 && s_cnt[t] == 0) {
-            const int gx = px0 + (t % kTile), gy = py0 + (t / kTile);
-            if (gx < W && gy < H) {
-                float4* o = reinterpret_cast<float4*>(a.rgba) + ((size_t)gy * W + gx);
-                *o = make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-            if (a.has_dbg) {
-                const int dx = gx - a.dbg.x0, dy = gy - a.dbg.y0;
-                if (dx >= 0 && dy >= 0 && dx < a.dbg.w && dy < a.dbg.h) a.dbg.counts[dy * a.dbg.w + dx] = 0;
-            }
-        }
-        if (Fb == 0) {
-            __syncthreads();
-            p0 = p1;
-            continue;
-        }
-        // ---- emit
-        if (t >= p0 && t < p1) s_cur[t] = 0;
-        for (uint32_t i = t; i < Fb; i += kNT) s_bk[i] = 0;
-        __syncthreads();
-        const int r0 = p0 / kTile, r1 = (p1 - 1) / kTile;
-        for (uint32_t base = 0; base < n; base += kNT) {
-            const uint32_t j = base + t;
-            if (j < n) {
-                const SegRec s = a.seg[list[j]];
-                for_each_fragment(s, px0, py0, r0, r1, a.cam.W, a.cam.H, [&](int li, int lj, long long tnum, long long tden, long long) {
-                    const int p = lj * kTile + li;
-                    if (p < p0 || p >= p1) return;
-                    const uint32_t key = depth_key(s, tnum, tden);
-                    const uint32_t slot2 = atomicAdd(&s_cur[p], 1u);
-                    s_A[s_off[p] - o0 + slot2] = make_uint2(key, j | ((uint32_t)p << 24));
-                });
-            }
-        }
-        __syncthreads();
-        // ---- bucket sort: bucket = linear key range of the fragment's pixel
-        uint32_t my_b[kPerThread], my_r[kPerThread];
-#pragma unroll
-        for (int qq = 0; qq < kPerThread; ++qq) {
-            const uint32_t i = t + qq * kNT;
-            if (i < Fb) {
-                const uint2 rec = s_A[i];
-                const uint32_t p = rec.y >> 24;
-                const uint32_t kmn = s_kmin[p];
-                const unsigned long long span = (unsigned long long)(s_kmax[p] - kmn) + 1ull;
-                const uint32_t bucket = (uint32_t)(((unsigned long long)(rec.x - kmn) * s_cnt[p]) / span);
-                my_b[qq] = s_off[p] - o0 + bucket;
-                my_r[qq] = atomicAdd(&s_bk[my_b[qq]], 1u);
-            }
-        }
-        __syncthreads();
-        {   // exclusive scan of the bucket counters, kPerThread consecutive per thread
-            uint32_t loc[kPerThread];
-            uint32_t sum = 0;
-#pragma unroll
-            for (int qq = 0; qq < kPerThread; ++qq) {
-                const uint32_t i = t * kPerThread + qq;
-                loc[qq] = i < Fb ? s_bk[i] : 0u;
-                sum += loc[qq];
-            }
-            uint32_t ex;
-            block_exscan_u32(sum, s_tmp, ex);
-#pragma unroll
-            for (int qq = 0; qq < kPerThread; ++qq) {
-                const uint32_t i = t * kPerThread + qq;
-                if (i < Fb) s_bk[i] = ex;
-                ex += loc[qq];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int qq = 0; qq < kPerThread; ++qq) {
-            const uint32_t i = t + qq * kNT;
-            if (i < Fb) s_B[s_bk[my_b[qq]] + my_r[qq]] = s_A[i];
-        }
-        __syncthreads();
-        // insertion sort inside each bucket by (key, segment id)
-        for (uint32_t bi = t; bi < Fb; bi += kNT) {
-            const uint32_t b0 = s_bk[bi];
-            const uint32_t b1 = bi + 1 < Fb ? s_bk[bi + 1] : Fb;
-            for (uint32_t i = b0 + 1; i < b1; ++i) {
-                const uint2 v = s_B[i];
-                const uint32_t vseg = list[v.y & 0xFFFFFFu];
-                uint32_t jx = i;
-                while (jx > b0) {
-                    const uint2 u2 = s_B[jx - 1];
-                    bool greater = u2.x > v.x;
-                    if (u2.x == v.x) greater = list[u2.y & 0xFFFFFFu] > vseg;
-                    if (!greater) break;
-                    s_B[jx] = u2;
-                    --jx;
-                }
-                s_B[jx] = v;
-            }
-        }
-        __syncthreads();
-        // ---- shade: one lane per fragment, payload alpha * L and (1 - alpha)
-        for (uint32_t i = t; i < Fb; i += kNT) {
-            const uint2 rec = s_B[i];
-            const uint32_t p = rec.y >> 24;
-            const uint32_t gseg = list[rec.y & 0xFFFFFFu];
-            const int gx = px0 + (int)(p % kTile), gy = py0 + (int)(p / kTile);
-            float al, hh, L[3];
-            shade_fragment(a, gseg, gx, gy, al, hh, L);
-            s_pay[3 * i + 0] = al * L[0];
-            s_pay[3 * i + 1] = al * L[1];
-            s_pay[3 * i + 2] = al * L[2];
-            s_B[i].x = __float_as_uint(1.0f - al);
-            if (a.has_dbg) {
-                const int dx = gx - a.dbg.x0, dy = gy - a.dbg.y0;
-                if (dx >= 0 && dy >= 0 && dx < a.dbg.w && dy < a.dbg.h) {
-                    const uint32_t rank = i - (s_off[p] - o0);
-                    const int q2 = dy * a.dbg.w + dx;
-                    if (rank == 0) a.dbg.counts[q2] = s_cnt[p];
-                    if ((int)rank < a.dbg.stride) {
-                        const size_t o = (size_t)q2 * a.dbg.stride + rank;
-                        a.dbg.keys[o] = rec.x;
-                        a.dbg.segs[o] = gseg;
-                        a.dbg.alpha[o] = al;
-                        a.dbg.hoff[o] = hh;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        // ---- blend: segmented scan of (C, T) over runs of consecutive fragments
-        {
-            const uint32_t run = (Fb + kNT - 1) / kNT;
-            const uint32_t rb = min(Fb, t * run), re = min(Fb, rb + run);
-            float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
-            uint32_t head = 0;
-            for (uint32_t i = rb; i < re; ++i) {
-                const uint32_t p = s_B[i].y >> 24;
-                if (i == s_off[p] - o0) { C0 = C1 = C2 = 0.f; T = 1.f; head = 1; }
-                C0 += T * s_pay[3 * i + 0];
-                C1 += T * s_pay[3 * i + 1];
-                C2 += T * s_pay[3 * i + 2];
-                T *= __uint_as_float(s_B[i].x);
-            }
-            s_agg[4 * t + 0] = C0; s_agg[4 * t + 1] = C1; s_agg[4 * t + 2] = C2; s_agg[4 * t + 3] = T;
-            s_aggh[t] = head;
-            __syncthreads();
-            // inclusive scan of run aggregates: (l) then (r) = r.head ? r : (l.C + l.T r.C, l.T r.T)
-            for (int off = 1; off < kNT; off <<= 1) {
-                float c0 = 0, c1 = 0, c2 = 0, tt = 1;
-                uint32_t hh2 = 0;
-                const bool has = t >= off;
-                if (has) {
-                    c0 = s_agg[4 * (t - off) + 0]; c1 = s_agg[4 * (t - off) + 1];
-                    c2 = s_agg[4 * (t - off) + 2]; tt = s_agg[4 * (t - off) + 3];
-                    hh2 = s_aggh[t - off];
-                }
-                __syncthreads();
-                if (has && !s_aggh[t]) {
-                    const float mT = s_agg[4 * t + 3];
-                    s_agg[4 * t + 0] = c0 + tt * s_agg[4 * t + 0];
-                    s_agg[4 * t + 1] = c1 + tt * s_agg[4 * t + 1];
-                    s_agg[4 * t + 2] = c2 + tt * s_agg[4 * t + 2];
-                    s_agg[4 * t + 3] = tt * mT;
-                    s_aggh[t] = hh2;
-                }
-                __syncthreads();
-            }
-            // carry into this run = inclusive result of run t - 1
-            if (t > 0) { C0 = s_agg[4 * (t - 1) + 0]; C1 = s_agg[4 * (t - 1) + 1]; C2 = s_agg[4 * (t - 1) + 2]; T = s_agg[4 * (t - 1) + 3]; }
-            else { C0 = C1 = C2 = 0.f; T = 1.f; }
-            for (uint32_t i = rb; i < re; ++i) {
-                const uint32_t p = s_B[i].y >> 24;
-                if (i == s_off[p] - o0) { C0 = C1 = C2 = 0.f; T = 1.f; }
-                C0 += T * s_pay[3 * i + 0];
-                C1 += T * s_pay[3 * i + 1];
-                C2 += T * s_pay[3 * i + 2];
-                T *= __uint_as_float(s_B[i].x);
-                if (i + 1 == s_off[p + 1] - o0) {
-                    const int gx = px0 + (int)(p % kTile), gy = py0 + (int)(p / kTile);
-                    if (gx < W && gy < H) {
-                        float4* o = reinterpret_cast<float4*>(a.rgba) + ((size_t)gy * W + gx);
-                        *o = make_float4(C0, C1, C2, 1.0f - T);
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        p0 = p1;
+    const int tile = s_tile;
+    s_cur[t] = 0;
+    s_pos[t] = f.frag_base[tile] + f.pix_off[(size_t)tile * kTilePix + t] + f.item_base[(size_t)item * kTilePix + t];
+    __syncthreads();
+    const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
+    const uint32_t lstart = f.tile_start[tile * kSub];
+    const uint32_t n = f.tile_start[(tile + 1) * kSub] - lstart;
+    const uint32_t j = s_chunk * kNT + t;
+    if (j < n) {
+        const SegRec s = f.seg[f.list[lstart + j]];
+        for_each_fragment(s, px0, py0, 0, kTile - 1, cam.W, cam.H, [&](int li, int lj, long long tnum, long long tden, long long) {
+            const int p = lj * kTile + li;
+            const uint32_t key = depth_key(s, tnum, tden);
+            const uint32_t slot = atomicAdd(&s_cur[p], 1u);
+            f.frags[s_pos[p] + slot] = make_uint2(key, j | ((uint32_t)p << 24));
+        });
     }
+    PHASE_END(f.ctr, 1);
+}
+
+// One LDS batch of whole pixels: exact per-pixel order, shading, front-to-back blending.
+template <int KIND>
+__global__ __launch_bounds__(kNT) void k_batch(FrameBufs f, ShadeArgs a, float* __restrict__ rgba, DebugDump dbg,
+                                               int has_dbg) {
+    __shared__ uint32_t s_cnt[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix], s_off[kTilePix + 1];
+    __shared__ uint32_t s_tmp[kNT];
+    __shared__ __align__(16) uint2 s_B[kCap];
+    __shared__ __align__(16) uint32_t s_work[3 * kCap];   // staged records (2 words) + bucket counters, later payload
+    __shared__ float s_agg[kNT * 4];          // run aggregates (C rgb, T)
+    __shared__ uint32_t s_aggh[kNT];
+    uint2* s_A = reinterpret_cast<uint2*>(s_work);
+    uint32_t* s_bk = s_work + 2 * kCap;
+    float* s_pay = reinterpret_cast<float*>(s_work);
+    PHASE_BEGIN();
+
+    const uint4 br = f.batches[blockIdx.x];
+    const int tile = (int)br.x, p0 = (int)br.y, p1 = (int)br.z;
+    const int t = threadIdx.x;
+    if (br.w) return;     // oversized pixel: counted in k_tile_prep, left transparent
+    const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
+    const int W = a.cam.W, H = a.cam.H;
+    const uint32_t* list = f.list + f.tile_start[tile * kSub];
+    const size_t q = (size_t)tile * kTilePix + t;
+    const uint32_t tile_off0 = f.pix_off[(size_t)tile * kTilePix + p0];
+    if (t >= p0 && t < p1) {
+        s_cnt[t] = f.pix_cnt[q];
+        s_kmin[t] = f.pix_kmin[q];
+        s_kmax[t] = f.pix_kmax[q];
+        s_off[t] = f.pix_off[q] - tile_off0;
+    }
+    if (t == 0) s_off[p1] = (p1 < kTilePix ? f.pix_off[(size_t)tile * kTilePix + p1] : f.tile_tot[tile]) - tile_off0;
+    __syncthreads();
+    const uint32_t Fb = s_off[p1];
+    const uint2* src = f.frags + f.frag_base[tile] + tile_off0;
+    for (uint32_t i = t; i < Fb; i += kNT) {
+        s_A[i] = src[i];
+        s_bk[i] = 0;
+    }
+    __syncthreads();
+    // ---- bucket sort: bucket = linear key range of the fragment's pixel
+    uint32_t my_b[kPerThread], my_r[kPerThread];
+#pragma unroll
+    for (int qq = 0; qq < kPerThread; ++qq) {
+        const uint32_t i = t + qq * kNT;
+        if (i < Fb) {
+            const uint2 rec = s_A[i];
+            const uint32_t p = rec.y >> 24;
+            const uint32_t kmn = s_kmin[p];
+            const unsigned long long span = (unsigned long long)(s_kmax[p] - kmn) + 1ull;
+            const uint32_t bucket = (uint32_t)(((unsigned long long)(rec.x - kmn) * s_cnt[p]) / span);
+            my_b[qq] = s_off[p] + bucket;
+            my_r[qq] = atomicAdd(&s_bk[my_b[qq]], 1u);
+        }
+    }
+    __syncthreads();
+    {   // exclusive scan of the bucket counters, kPerThread consecutive per thread
+        uint32_t loc[kPerThread];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int qq = 0; qq < kPerThread; ++qq) {
+            const uint32_t i = t * kPerThread + qq;
+            loc[qq] = i < Fb ? s_bk[i] : 0u;
+            sum += loc[qq];
+        }
+        uint32_t ex;
+        block_exscan_u32(sum, s_tmp, ex);
+#pragma unroll
+        for (int qq = 0; qq < kPerThread; ++qq) {
+            const uint32_t i = t * kPerThread + qq;
+            if (i < Fb) s_bk[i] = ex;
+            ex += loc[qq];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int qq = 0; qq < kPerThread; ++qq) {
+        const uint32_t i = t + qq * kNT;
+        if (i < Fb) s_B[s_bk[my_b[qq]] + my_r[qq]] = s_A[i];
+    }
+    __syncthreads();
+    // insertion sort inside each bucket by (key, segment id)
+    for (uint32_t bi = t; bi < Fb; bi += kNT) {
+        const uint32_t b0 = s_bk[bi];
+        const uint32_t b1 = bi + 1 < Fb ? s_bk[bi + 1] : Fb;
+        for (uint32_t i = b0 + 1; i < b1; ++i) {
+            const uint2 v = s_B[i];
+            const uint32_t vseg = list[v.y & 0xFFFFFFu];
+            uint32_t jx = i;
+            while (jx > b0) {
+                const uint2 u2 = s_B[jx - 1];
+                bool greater = u2.x > v.x;
+                if (u2.x == v.x) greater = list[u2.y & 0xFFFFFFu] > vseg;
+                if (!greater) break;
+                s_B[jx] = u2;
+                --jx;
+            }
+            s_B[jx] = v;
+        }
+    }
+    __syncthreads();
+    PHASE_END(f.ctr, 2);
+    // ---- shade: one lane per fragment, payload alpha * L and (1 - alpha)
+    for (uint32_t i = t; i < Fb; i += kNT) {
+        const uint2 rec = s_B[i];
+        const uint32_t p = rec.y >> 24;
+        const uint32_t gseg = list[rec.y & 0xFFFFFFu];
+        const int gx = px0 + (int)(p % kTile), gy = py0 + (int)(p / kTile);
+        float al, hh, L[3];
+        shade_fragment<KIND>(a, gseg, gx, gy, al, hh, L);
+        s_pay[3 * i + 0] = al * L[0];
+        s_pay[3 * i + 1] = al * L[1];
+        s_pay[3 * i + 2] = al * L[2];
+        s_B[i].x = __float_as_uint(1.0f - al);
+        if (has_dbg) {
+            const int dx = gx - dbg.x0, dy = gy - dbg.y0;
+            if (dx >= 0 && dy >= 0 && dx < dbg.w && dy < dbg.h) {
+                const uint32_t rank = i - s_off[p];
+                const int q2 = dy * dbg.w + dx;
+                if (rank == 0) dbg.counts[q2] = s_cnt[p];
+                if ((int)rank < dbg.stride) {
+                    const size_t o = (size_t)q2 * dbg.stride + rank;
+                    dbg.keys[o] = rec.x;
+                    dbg.segs[o] = gseg;
+                    dbg.alpha[o] = al;
+                    dbg.hoff[o] = hh;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    PHASE_END(f.ctr, 3);
+    // ---- blend: segmented scan of (C, T) over runs of consecutive fragments
+    const uint32_t run = (Fb + kNT - 1) / kNT;
+    const uint32_t rb = min(Fb, t * run), re = min(Fb, rb + run);
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
+    uint32_t head = 0;
+    for (uint32_t i = rb; i < re; ++i) {
+        const uint32_t p = s_B[i].y >> 24;
+        if (i == s_off[p]) { C0 = C1 = C2 = 0.f; T = 1.f; head = 1; }
+        C0 += T * s_pay[3 * i + 0];
+        C1 += T * s_pay[3 * i + 1];
+        C2 += T * s_pay[3 * i + 2];
+        T *= __uint_as_float(s_B[i].x);
+    }
+    s_agg[4 * t + 0] = C0; s_agg[4 * t + 1] = C1; s_agg[4 * t + 2] = C2; s_agg[4 * t + 3] = T;
+    s_aggh[t] = head;
+    __syncthreads();
+    // inclusive scan of run aggregates: (l) then (r) = r.head ? r : (l.C + l.T r.C, l.T r.T)
+    for (int off = 1; off < kNT; off <<= 1) {
+        float c0 = 0, c1 = 0, c2 = 0, tt = 1;
+        uint32_t hh2 = 0;
+        const bool has = t >= off;
+        if (has) {
+            c0 = s_agg[4 * (t - off) + 0]; c1 = s_agg[4 * (t - off) + 1];
+            c2 = s_agg[4 * (t - off) + 2]; tt = s_agg[4 * (t - off) + 3];
+            hh2 = s_aggh[t - off];
+        }
+        __syncthreads();
+        if (has && !s_aggh[t]) {
+            const float mT = s_agg[4 * t + 3];
+            s_agg[4 * t + 0] = c0 + tt * s_agg[4 * t + 0];
+            s_agg[4 * t + 1] = c1 + tt * s_agg[4 * t + 1];
+            s_agg[4 * t + 2] = c2 + tt * s_agg[4 * t + 2];
+            s_agg[4 * t + 3] = tt * mT;
+            s_aggh[t] = hh2;
+        }
+        __syncthreads();
+    }
+    if (t > 0) { C0 = s_agg[4 * (t - 1) + 0]; C1 = s_agg[4 * (t - 1) + 1]; C2 = s_agg[4 * (t - 1) + 2]; T = s_agg[4 * (t - 1) + 3]; }
+    else { C0 = C1 = C2 = 0.f; T = 1.f; }
+    for (uint32_t i = rb; i < re; ++i) {
+        const uint32_t p = s_B[i].y >> 24;
+        if (i == s_off[p]) { C0 = C1 = C2 = 0.f; T = 1.f; }
+        C0 += T * s_pay[3 * i + 0];
+        C1 += T * s_pay[3 * i + 1];
+        C2 += T * s_pay[3 * i + 2];
+        T *= __uint_as_float(s_B[i].x);
+        if (i + 1 == s_off[p] + s_cnt[p]) {
+            const int gx = px0 + (int)(p % kTile), gy = py0 + (int)(p / kTile);
+            if (gx < W && gy < H) {
+                float4* o = reinterpret_cast<float4*>(rgba) + ((size_t)gy * W + gx);
+                *o = make_float4(C0, C1, C2, 1.0f - T);
+            }
+        }
+    }
+    PHASE_END(f.ctr, 4);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -855,25 +945,48 @@ hipError_t launch_scatter(const SegRec* seg, int32_t nseg, const CamConst& cam, 
     return hipGetLastError();
 }
 
-hipError_t launch_tile(const LevelDev& lv, const CamConst& cam, const LightsConst& lights, const MatConst& mat,
-                       const SegRec* seg, const uint32_t* tile_start, const uint32_t* list, float* rgba, Counters* ctr,
-                       const DebugDump* dbg, const GradOut* grad, hipStream_t st) {
-    (void)grad;
-    TileArgs a;
+hipError_t launch_tile_items(const uint32_t* tile_start, int T, uint32_t* items, hipStream_t st) {
+    hipLaunchKernelGGL(k_tile_items, dim3(blocks_for(T, 256)), dim3(256), 0, st, tile_start, T, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const FrameBufs& f, const CamConst& cam, uint32_t n_items, hipStream_t st) {
+    if (n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count, dim3(n_items), dim3(kNT), 0, st, f, cam, n_items);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_prep(const FrameBufs& f, hipStream_t st) {
+    hipLaunchKernelGGL(k_tile_prep, dim3(f.T), dim3(kNT), 0, st, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_records(const FrameBufs& f, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_records, dim3(f.T), dim3(kNT), 0, st, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const FrameBufs& f, const CamConst& cam, uint32_t n_items, hipStream_t st) {
+    if (n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_emit, dim3(n_items), dim3(kNT), 0, st, f, cam, n_items);
+    return hipGetLastError();
+}
+
+hipError_t launch_batches(const FrameBufs& f, const LevelDev& lv, const CamConst& cam, const LightsConst& lights,
+                          const MatConst& mat, const SegRec* seg, uint32_t n_batches, float* rgba,
+                          const DebugDump* dbg, hipStream_t st) {
+    if (n_batches == 0) return hipSuccess;
+    ShadeArgs a;
     a.lv = lv;
     a.cam = cam;
     a.lights = lights;
     a.mat = mat;
     a.seg = seg;
-    a.tile_start = tile_start;
-    a.list = list;
-    a.rgba = rgba;
-    a.ctr = ctr;
-    a.has_dbg = dbg != nullptr;
-    if (dbg) a.dbg = *dbg; else a.dbg = DebugDump{};
-    a.ntx = (cam.W + kTile - 1) / kTile;
-    a.nty = (cam.H + kTile - 1) / kTile;
-    hipLaunchKernelGGL(k_tile, dim3(a.ntx * a.nty), dim3(kNT), 0, st, a);
+    DebugDump d = dbg ? *dbg : DebugDump{};
+    if (lv.kind == 0)
+        hipLaunchKernelGGL(k_batch<0>, dim3(n_batches), dim3(kNT), 0, st, f, a, rgba, d, dbg ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_batch<1>, dim3(n_batches), dim3(kNT), 0, st, f, a, rgba, d, dbg ? 1 : 0);
     return hipGetLastError();
 }
 
