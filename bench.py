@@ -10,7 +10,7 @@ shading and compositing; inputs are resident in HBM before the timed region.
 
 Prints one JSON line: Mfragments/s over the timed steps (fragments counted by the library,
 equal to the CPU oracle's count), frame ms (mean, p50, p99), the roofline of the dominant
-kernel (k_tile, measured with HIP events on its launch stream) and the CPU oracle timed on
+kernel (k_batch, measured with HIP events on its launch stream) and the CPU oracle timed on
 a bounded sample of the same frame.
 """
 from __future__ import annotations
@@ -28,10 +28,11 @@ sys.path.insert(0, ROOT)
 WORKLOAD = "hair-100k-strands-32seg-1920x1080-2lights"
 METRIC = "Mfragments/s + frame ms (100k strands, 1080p); served p50/p99 latency"
 
-# Algorithmic operations per fragment, counted from the definition (step by step, each
-# add / mul / div / sqrt / compare / min / max / int op = 1; exp, asin, atan2, sin, cos =
-# one transcendental each).  Strand level.
-OPS_BASE = 18 + 7 + 18 + 35 + 32 + 11 + 8      # coverage, key, alpha+h, point+tangent, frame, blend, sort
+# Algorithmic operations per fragment of the shading kernel k_batch, counted from the
+# definition step by step (each add / mul / div / sqrt / compare / min / max / int op = 1;
+# exp, asin, atan2, sin, cos = one transcendental each).  Strand level.  Coverage (18) and the
+# depth key (7) belong to k_count / k_emit and are not counted here.
+OPS_BASE = 18 + 35 + 32 + 11 + 8                # alpha+h, point+tangent, frame, blend, sort
 TRANS_BASE = 1                                  # asin(theta_o)
 OPS_DIR_LIGHT = 171                             # angles 25 + f_single 137 + accumulate 9
 OPS_POINT_LIGHT = 186                           # + 15: direction, distance, 1/d^2
@@ -42,7 +43,7 @@ PEAK_HBM = 8.0e12
 
 KERNEL_SOURCES = ["paper_2405_10565_amd/csrc/hair_kernels.hip", "paper_2405_10565_amd/csrc/hair_shading.h",
                   "paper_2405_10565_amd/csrc/hair_internal.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile_hair_100k_1080p_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_batch_hair_100k_1080p_traffic.txt")
 
 
 def kernel_hash() -> str:
@@ -76,7 +77,7 @@ def alg_ops(fragments: int, n_dir: int, n_point: int):
     return ops, trans
 
 
-def cpu_baseline(asset, cam, lights, rows: int = 16):
+def cpu_baseline(asset, cam, lights, rows: int = 48):
     """The oracle, single-threaded, on a centre band of the frame."""
     import torch
     torch.set_num_threads(1)
@@ -97,7 +98,18 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": src.numel() * 4, "launches": 5}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the renderer's multi-GPU split is a design note only)", file=sys.stderr)
@@ -165,7 +177,7 @@ def main():
                      "tile": round(float(ms_tile.mean()), 4)},
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_LANE_OPS / 1e12, 2),
                      "unit": "Tops/s", "frac": round(achieved / PEAK_LANE_OPS, 4),
-                     "traffic": traffic, "kernel": "k_tile",
+                     "traffic": traffic, "kernel": "k_batch<0>",
                      "ops_per_launch": int(ops + TRANS_WEIGHT * trans)},
         "cpu_baseline": None,
     }

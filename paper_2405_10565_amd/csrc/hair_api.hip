@@ -71,7 +71,7 @@ struct hair_ws {
     hair_ctx* ctx = nullptr;
     uint64_t max_bytes = 0;
     uint64_t held = 0;
-    DevBuf seg, tile_cnt, tile_start, tile_cur, list, ctr;
+    DevBuf seg, shade, scan_tmp, tile_cnt, tile_start, tile_cur, list, ctr;
     DevBuf items, item_start, item_base, pix_cnt, pix_kmin, pix_kmax, pix_off;
     DevBuf tile_tot, frag_base, tile_nb, batch_start, batches, frags;
     hipEvent_t ev[7] = {};
@@ -305,6 +305,8 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     const size_t TP = (size_t)T * kTilePix;
     if ((rc = ws_events(ws))) return rc;
     if ((rc = ws_need(ws, ws->seg, sizeof(SegRec) * (size_t)std::max(lv.nseg, 1)))) return rc;
+    if ((rc = ws_need(ws, ws->shade, sizeof(ShadeRec) * (size_t)std::max(lv.nseg, 1)))) return rc;
+    if ((rc = ws_need(ws, ws->scan_tmp, 4 * exscan_scratch_words(TS)))) return rc;
     if ((rc = ws_need(ws, ws->tile_cnt, 4ull * TS))) return rc;
     if ((rc = ws_need(ws, ws->tile_start, 4ull * (TS + 1)))) return rc;
     if ((rc = ws_need(ws, ws->tile_cur, 4ull * TS))) return rc;
@@ -317,10 +319,12 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     HIP_TRY(ctx, launch_fill_u32(tile_cnt, 0u, TS, st), "fill");
     HIP_TRY(ctx, launch_fill_u32(ws->tile_cur.as<uint32_t>(), 0u, TS, st), "fill");
     HIP_TRY(ctx, launch_fill_u32(ws->ctr.as<uint32_t>(), 0u, sizeof(Counters) / 4, st), "fill");
-    HIP_TRY(ctx, launch_project(lv, cc, ws->seg.as<SegRec>(), tile_cnt, ws->ctr.as<Counters>(), st), "k_project");
-    HIP_TRY(ctx, launch_scan_tiles(tile_cnt, tile_start, TS, st), "k_scan");
+    uint32_t* scan_tmp = ws->scan_tmp.as<uint32_t>();
+    HIP_TRY(ctx, launch_project(lv, cc, ws->seg.as<SegRec>(), ws->shade.as<ShadeRec>(), tile_cnt, ws->ctr.as<Counters>(),
+                                st), "k_project");
+    HIP_TRY(ctx, launch_exscan(tile_cnt, tile_start, TS, scan_tmp, st), "k_scan");
     HIP_TRY(ctx, launch_tile_items(tile_start, T, ws->items.as<uint32_t>(), st), "k_tile_items");
-    HIP_TRY(ctx, launch_scan_tiles(ws->items.as<uint32_t>(), ws->item_start.as<uint32_t>(), T, st), "k_scan");
+    HIP_TRY(ctx, launch_exscan(ws->items.as<uint32_t>(), ws->item_start.as<uint32_t>(), T, scan_tmp, st), "k_scan");
     HIP_TRY(ctx, hipEventRecord(ws->ev[1], st), "hipEventRecord");
     uint32_t sizes1[2] = {0, 0};
     HIP_TRY(ctx, hipMemcpyAsync(&sizes1[0], tile_start + TS, 4, hipMemcpyDeviceToHost, st), "copy");
@@ -348,6 +352,7 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     f.T = T;
     f.ntx = ntx;
     f.seg = ws->seg.as<SegRec>();
+    f.shade = ws->shade.as<ShadeRec>();
     f.tile_start = tile_start;
     f.list = ws->list.as<uint32_t>();
     f.item_start = ws->item_start.as<uint32_t>();
@@ -370,8 +375,8 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     if (rgba) HIP_TRY(ctx, launch_fill_f32(rgba, 0.0f, 4ull * cam->width * cam->height, st), "fill");
     HIP_TRY(ctx, launch_count(f, cc, n_items, st), "k_count");
     HIP_TRY(ctx, launch_tile_prep(f, st), "k_tile_prep");
-    HIP_TRY(ctx, launch_scan_tiles(f.tile_tot, ws->frag_base.as<uint32_t>(), T, st), "k_scan");
-    HIP_TRY(ctx, launch_scan_tiles(f.tile_nb, ws->batch_start.as<uint32_t>(), T, st), "k_scan");
+    HIP_TRY(ctx, launch_exscan(f.tile_tot, ws->frag_base.as<uint32_t>(), T, scan_tmp, st), "k_scan");
+    HIP_TRY(ctx, launch_exscan(f.tile_nb, ws->batch_start.as<uint32_t>(), T, scan_tmp, st), "k_scan");
     HIP_TRY(ctx, hipEventRecord(ws->ev[3], st), "hipEventRecord");
     uint32_t sizes2[2] = {0, 0};
     HIP_TRY(ctx, hipMemcpyAsync(&sizes2[0], ws->frag_base.as<uint32_t>() + T, 4, hipMemcpyDeviceToHost, st), "copy");
@@ -387,8 +392,8 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     HIP_TRY(ctx, launch_emit(f, cc, n_items, st), "k_emit");
     HIP_TRY(ctx, hipEventRecord(ws->ev[5], st), "hipEventRecord");
     if (rgba)
-        HIP_TRY(ctx, launch_batches(f, lv, cc, lights_const(lights, n_lights), mat_const(a.mat), f.seg, n_batches, rgba,
-                                    dbg, st), "k_batch");
+        HIP_TRY(ctx, launch_batches(f, lv, cc, lights_const(lights, n_lights), mat_const(a.mat), n_batches, rgba, dbg, st),
+                "k_batch");
     HIP_TRY(ctx, hipEventRecord(ws->ev[6], st), "hipEventRecord");
     HIP_TRY(ctx, hipMemcpyAsync(&out->ctr, ws->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, st), "copy");
     HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
@@ -481,7 +486,7 @@ int hair_ws_destroy(hair_ws* ws) {
     if (!ws) return fail(HAIR_EINVAL, "null workspace");
     hair_ctx* ctx = ws->ctx;
     if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
-    for (DevBuf* b : {&ws->seg, &ws->tile_cnt, &ws->tile_start, &ws->tile_cur, &ws->list, &ws->ctr, &ws->items,
+    for (DevBuf* b : {&ws->seg, &ws->shade, &ws->scan_tmp, &ws->tile_cnt, &ws->tile_start, &ws->tile_cur, &ws->list, &ws->ctr, &ws->items,
                       &ws->item_start, &ws->item_base, &ws->pix_cnt, &ws->pix_kmin, &ws->pix_kmax, &ws->pix_off,
                       &ws->tile_tot, &ws->frag_base, &ws->tile_nb, &ws->batch_start, &ws->batches, &ws->frags})
         ctx_free(ctx, *b, ws);

@@ -24,6 +24,14 @@ struct SegRec {
     float iza, izb;           // inverse view depth at the endpoints
     float hw;                 // half-width in pixels
 };
+// Per-segment shading inputs gathered once per frame by k_project (64 bytes, one aligned
+// half cache line per fragment instead of five scattered reads):
+//   q0 = (pA, sigma_r)  q1 = (pB, sigma_g)  q2 = (a^, sigma_b)  q3 = (|a|, |b|, n_total, r)
+// (strands leave a^ and q3 unused).
+struct ShadeRec {
+    float4 q0, q1, q2, q3;
+};
+
 constexpr int32_t kFlagVisible = 1 << 16;
 constexpr int32_t kFlagNegSide = 1 << 17;        // h > 0 lies on the e x d < 0 side
 constexpr int32_t kFlagCulledLong = 1 << 18;
@@ -109,6 +117,7 @@ struct GradOut {
 struct FrameBufs {
     int32_t T, ntx;
     const SegRec* seg;
+    const ShadeRec* shade;
     const uint32_t* tile_start;   // [T * kSub + 1]: tile t's list is [tile_start[t kSub], tile_start[(t+1) kSub])
     const uint32_t* list;         // segment ids
     const uint32_t* item_start;   // [T + 1] exclusive scan of per-tile work items
@@ -127,9 +136,13 @@ struct FrameBufs {
 };
 
 // Kernel launchers (hair_kernels.hip).
-hipError_t launch_project(const LevelDev& lv, const CamConst& cam, SegRec* seg, uint32_t* tile_cnt,
+hipError_t launch_project(const LevelDev& lv, const CamConst& cam, SegRec* seg, ShadeRec* shade, uint32_t* tile_cnt,
                           Counters* ctr, hipStream_t st);
-hipError_t launch_scan_tiles(const uint32_t* cnt, uint32_t* start, int32_t n, hipStream_t st);
+// Exclusive scan of n counts into start[0..n] (start[n] = total); scratch holds
+// 2 * ceil(n / 4096) + 2 words.
+hipError_t launch_exscan(const uint32_t* cnt, uint32_t* start, int32_t n, uint32_t* scratch, hipStream_t st);
+constexpr int kScanChunk = 4096;
+inline size_t exscan_scratch_words(size_t n) { return 2 * ((n + kScanChunk - 1) / kScanChunk) + 2; }
 hipError_t launch_scatter(const SegRec* seg, int32_t nseg, const CamConst& cam, const uint32_t* tile_start,
                           uint32_t* tile_cur, uint32_t* list, hipStream_t st);
 hipError_t launch_tile_items(const uint32_t* tile_start, int T, uint32_t* items, hipStream_t st);
@@ -138,8 +151,7 @@ hipError_t launch_tile_prep(const FrameBufs& f, hipStream_t st);
 hipError_t launch_batch_records(const FrameBufs& f, hipStream_t st);
 hipError_t launch_emit(const FrameBufs& f, const CamConst& cam, uint32_t n_items, hipStream_t st);
 hipError_t launch_batches(const FrameBufs& f, const LevelDev& lv, const CamConst& cam, const LightsConst& lights,
-                          const MatConst& mat, const SegRec* seg, uint32_t n_batches, float* rgba,
-                          const DebugDump* dbg, hipStream_t st);
+                          const MatConst& mat, uint32_t n_batches, float* rgba, const DebugDump* dbg, hipStream_t st);
 hipError_t launch_build_centers(const float* vx, const float* vy, const float* vz, const float* width,
                                 const float* sig, int32_t n_strands, int32_t V, const int32_t* members,
                                 const int32_t* member_start, int32_t K, float* cx, float* cy, float* cz,

@@ -31,6 +31,19 @@ __device__ inline long long floordiv(long long a, long long b) {  // b > 0
     return a >= 0 ? a / b : -((-a + b - 1) / b);
 }
 
+__device__ inline int wave_max(int v) {
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off));
+    return v;
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).  Map block b to
+// work index w so that each XCD takes one contiguous range of work: neighbouring work units
+// (batches of one tile, chunks of one list) then share that XCD's L2.
+__device__ inline uint32_t xcd_contiguous(uint32_t b, uint32_t nb) {
+    const uint32_t q = nb / 8, rem = nb % 8, x = b % 8, slot = b / 8;
+    return x * q + min(x, rem) + slot;
+}
+
 // ---------------------------------------------------------------------------------------
 // Projection (float32, fixed operation order).
 struct PPoint {
@@ -104,12 +117,16 @@ __device__ inline TileRect tile_rect(const SegRec& s, int ntx, int nty) {
 }
 
 __global__ __launch_bounds__(256) void k_project(LevelDev lv, CamConst cam, SegRec* __restrict__ seg,
-                                                 uint32_t* __restrict__ tile_cnt, Counters* __restrict__ ctr) {
+                                                 ShadeRec* __restrict__ shade, uint32_t* __restrict__ tile_cnt,
+                                                 Counters* __restrict__ ctr) {
     __shared__ uint32_t s_maxhw;
     if (threadIdx.x == 0) s_maxhw = 0;
     __syncthreads();
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ntx = (cam.W + kTile - 1) / kTile, nty = (cam.H + kTile - 1) / kTile;
     bool vis = false, culled_long = false;
+    TileRect rect{0, -1, 0, -1};
+    int ntile = 0;
     if (g < lv.nseg) {
         const int owner = g / lv.S, k = g - owner * lv.S;
         const int va = owner * (lv.S + 1) + k;
@@ -117,6 +134,18 @@ __global__ __launch_bounds__(256) void k_project(LevelDev lv, CamConst cam, SegR
         const float bx = lv.vx[va + 1], by = lv.vy[va + 1], bz = lv.vz[va + 1];
         const PPoint A = project_point(cam, ax, ay, az);
         const PPoint B = project_point(cam, bx, by, bz);
+        {
+            ShadeRec& sr = shade[g];
+            sr.q0 = make_float4(ax, ay, az, lv.sig[owner]);
+            sr.q1 = make_float4(bx, by, bz, lv.sig[lv.n_owner + owner]);
+            if (lv.kind == 0) {
+                sr.q2 = make_float4(0.f, 0.f, 0.f, lv.sig[2 * lv.n_owner + owner]);
+            } else {
+                sr.q2 = make_float4(lv.ahat[g], lv.ahat[lv.nseg + g], lv.ahat[2 * lv.nseg + g],
+                                    lv.sig[2 * lv.n_owner + owner]);
+                sr.q3 = make_float4(lv.axes[2 * g], lv.axes[2 * g + 1], (float)lv.n_total[owner], lv.r[owner]);
+            }
+        }
         float hw;
         if (lv.kind == 0) {
             const float zm = (A.z + B.z) * 0.5f;
@@ -173,13 +202,28 @@ __global__ __launch_bounds__(256) void k_project(LevelDev lv, CamConst cam, SegR
             }
         }
         seg[g] = r;
-        if (vis) {
-            atomicMax(&s_maxhw, __float_as_uint(hw));
-            const int ntx = (cam.W + kTile - 1) / kTile, nty = (cam.H + kTile - 1) / kTile;
-            const TileRect tr = tile_rect(r, ntx, nty);
-            const int sub = (g >> 8) & (kSub - 1);
-            for (int ty = tr.ty0; ty <= tr.ty1; ++ty)
-                for (int tx = tr.tx0; tx <= tr.tx1; ++tx) atomicAdd(&tile_cnt[(ty * ntx + tx) * kSub + sub], 1u);
+        if (vis) atomicMax(&s_maxhw, __float_as_uint(hw));
+        rect = tile_rect(r, ntx, nty);
+        if (vis) ntile = (rect.tx1 - rect.tx0 + 1) * (rect.ty1 - rect.ty0 + 1);
+        if (ntile < 0) ntile = 0;
+    }
+    // per-tile counts, one atomic per distinct tile per wave (lanes are consecutive segments
+    // of a few strands and mostly share tiles)
+    {
+        const int sub = (g >> 8) & (kSub - 1);
+        const int nmax = wave_max(ntile);
+        const int nx = max(1, rect.tx1 - rect.tx0 + 1);
+        for (int j = 0; j < nmax; ++j) {
+            const bool has = j < ntile;
+            const int tl = has ? ((rect.ty0 + j / nx) * ntx + rect.tx0 + j % nx) * kSub + sub : -1;
+            unsigned long long rem = __ballot(has);
+            while (rem) {
+                const int leader = __ffsll((long long)rem) - 1;
+                const int tsel = __shfl(tl, leader);
+                const unsigned long long same = __ballot(tl == tsel) & rem;
+                if ((int)__lane_id() == leader) atomicAdd(&tile_cnt[tsel], (uint32_t)__popcll(same));
+                rem &= ~same;
+            }
         }
     }
     const int nvis = __syncthreads_count(vis);
@@ -215,21 +259,79 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ cnt,
     if (t == 1023) start[n] = s_part[1023];
 }
 
+// Multi-block exclusive scan: each 1024-thread block scans kScanChunk counts and leaves its
+// total; the totals are scanned by k_scan; k_scan_add adds each block's base.
+__global__ __launch_bounds__(1024) void k_scan_local(const uint32_t* __restrict__ cnt, uint32_t* __restrict__ out,
+                                                      uint32_t* __restrict__ part, int n) {
+    __shared__ uint32_t s_part[1024];
+    const int t = threadIdx.x;
+    const int b0 = blockIdx.x * kScanChunk + t * 4;
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = b0 + k < n ? cnt[b0 + k] : 0u;
+        sum += v[k];
+    }
+    s_part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t x = t >= off ? s_part[t - off] : 0u;
+        __syncthreads();
+        s_part[t] += x;
+        __syncthreads();
+    }
+    uint32_t run = s_part[t] - sum;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (b0 + k < n) out[b0 + k] = run;
+        run += v[k];
+    }
+    if (t == 1023) part[blockIdx.x] = s_part[1023];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_add(uint32_t* __restrict__ out, const uint32_t* __restrict__ base,
+                                                    int n, int nblocks) {
+    const int i = blockIdx.x * kScanChunk + threadIdx.x * 4;
+    const uint32_t b = base[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (i + k < n) out[i + k] += b;
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = base[nblocks];
+}
+
 __global__ __launch_bounds__(256) void k_scatter(const SegRec* __restrict__ seg, int nseg, int ntx, int nty,
                                                  const uint32_t* __restrict__ tile_start,
                                                  uint32_t* __restrict__ tile_cur, uint32_t* __restrict__ list) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= nseg) return;
-    const SegRec r = seg[g];
-    if (!(r.hwfx & kFlagVisible)) return;
-    const TileRect tr = tile_rect(r, ntx, nty);
-    const int sub = (g >> 8) & (kSub - 1);
-    for (int ty = tr.ty0; ty <= tr.ty1; ++ty)
-        for (int tx = tr.tx0; tx <= tr.tx1; ++tx) {
-            const int t = (ty * ntx + tx) * kSub + sub;
-            const uint32_t pos = atomicAdd(&tile_cur[t], 1u);
-            list[tile_start[t] + pos] = (uint32_t)g;
+    TileRect rect{0, -1, 0, -1};
+    int ntile = 0;
+    if (g < nseg) {
+        const SegRec r = seg[g];
+        if (r.hwfx & kFlagVisible) {
+            rect = tile_rect(r, ntx, nty);
+            ntile = max(0, (rect.tx1 - rect.tx0 + 1) * (rect.ty1 - rect.ty0 + 1));
         }
+    }
+    // one atomic per distinct tile per wave; lanes take consecutive slots in lane order
+    const int sub = (g >> 8) & (kSub - 1);
+    const int nmax = wave_max(ntile);
+    const int nx = max(1, rect.tx1 - rect.tx0 + 1);
+    const unsigned long long lt = (1ull << __lane_id()) - 1ull;
+    for (int j = 0; j < nmax; ++j) {
+        const bool has = j < ntile;
+        const int tl = has ? ((rect.ty0 + j / nx) * ntx + rect.tx0 + j % nx) * kSub + sub : -1;
+        unsigned long long rem = __ballot(has);
+        while (rem) {
+            const int leader = __ffsll((long long)rem) - 1;
+            const int tsel = __shfl(tl, leader);
+            const unsigned long long same = __ballot(tl == tsel) & rem;
+            uint32_t base = 0;
+            if ((int)__lane_id() == leader) base = atomicAdd(&tile_cur[tsel], (uint32_t)__popcll(same));
+            base = __shfl(base, leader);
+            if ((same >> __lane_id()) & 1ull) list[tile_start[tsel] + base + (uint32_t)__popcll(same & lt)] = (uint32_t)g;
+            rem &= ~same;
+        }
+    }
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
@@ -298,11 +400,11 @@ __device__ inline uint32_t depth_key(const SegRec& s, long long tnum, long long 
 }
 
 struct ShadeArgs {
-    LevelDev lv;
     CamConst cam;
     LightsConst lights;
     MatConst mat;
     const SegRec* seg;
+    const ShadeRec* shade;
 };
 
 // Radiance (RGB), coverage alpha and cross-section offset of one fragment.
@@ -310,6 +412,8 @@ template <int KIND>
 __device__ inline void shade_fragment(const ShadeArgs& a, uint32_t gseg, int pxg, int pyg, float& alpha, float& hoff,
                                       float L[3]) {
     const SegRec s = a.seg[gseg];
+    const ShadeRec& srec = a.shade[gseg];
+    const float4 q0 = srec.q0, q1 = srec.q1, q2 = srec.q2;
     const long long ex = 16LL * pxg + 8 - s.xa, ey = 16LL * pyg + 8 - s.ya;
     const long long dx = (long long)s.xb - s.xa, dy = (long long)s.yb - s.ya;
     const long long tnum = ex * dx + ey * dy, tden = dx * dx + dy * dy;
@@ -325,11 +429,8 @@ __device__ inline void shade_fragment(const ShadeArgs& a, uint32_t gseg, int pxg
     hoff = h;
     const float tw = t * s.izb / iz;
 
-    const LevelDev& lv = a.lv;
-    const int owner = (int)gseg / lv.S, k = (int)gseg - owner * lv.S;
-    const int va = owner * (lv.S + 1) + k;
-    const V3<float> pA = v3(lv.vx[va], lv.vy[va], lv.vz[va]);
-    const V3<float> pB = v3(lv.vx[va + 1], lv.vy[va + 1], lv.vz[va + 1]);
+    const V3<float> pA = v3(q0.x, q0.y, q0.z);
+    const V3<float> pB = v3(q1.x, q1.y, q1.z);
     const V3<float> d = sub(pB, pA);
     const V3<float> u = scale(d, 1.0f / sqrtf(dot(d, d)));
     const V3<float> xw = v3(pA.x + tw * d.x, pA.y + tw * d.y, pA.z + tw * d.z);
@@ -349,26 +450,20 @@ __device__ inline void shade_fragment(const ShadeArgs& a, uint32_t gseg, int pxg
     const V3<float> yh = cross(u, xh);
     const float to = asinf(fminf(fmaxf(sin_to, -1.0f), 1.0f));
 
-    float sig[3];
+    float sig[3] = {q0.w, q1.w, q2.w};
     ClusterFrag<float> cf;
     float a_len = 0, b_len = 0, W = 0;
     V3<float> ah{}, bh{};
-    if (KIND == 0) {
-        sig[0] = lv.sig[owner];
-        sig[1] = lv.sig[lv.n_owner + owner];
-        sig[2] = lv.sig[2 * lv.n_owner + owner];
-    } else {
-        sig[0] = lv.sig[owner];
-        sig[1] = lv.sig[lv.n_owner + owner];
-        sig[2] = lv.sig[2 * lv.n_owner + owner];
-        ah = v3(lv.ahat[gseg], lv.ahat[lv.nseg + gseg], lv.ahat[2 * lv.nseg + gseg]);
+    if (KIND == 1) {
+        const float4 q3 = srec.q3;
+        ah = v3(q2.x, q2.y, q2.z);
         bh = cross(u, ah);
-        a_len = lv.axes[2 * gseg];
-        b_len = lv.axes[2 * gseg + 1];
+        a_len = q3.x;
+        b_len = q3.y;
         const float pa = a_len * dot(ah, yh), pb = b_len * dot(bh, yh);
         W = sqrtf(pa * pa + pb * pb);
-        cf.n_total = (float)lv.n_total[owner];
-        const float rr = lv.r[owner];
+        cf.n_total = q3.z;
+        const float rr = q3.w;
         cf.rho = fminf(fmaxf(cf.n_total * rr * rr / (a_len * b_len), 0.0f), 1.0f);
     }
     L[0] = L[1] = L[2] = 0.0f;
@@ -483,7 +578,7 @@ __global__ __launch_bounds__(kNT) void k_count(FrameBufs f, CamConst cam, uint32
     __shared__ int s_tile;
     __shared__ uint32_t s_chunk;
     PHASE_BEGIN();
-    const uint32_t item = blockIdx.x;
+    const uint32_t item = xcd_contiguous(blockIdx.x, gridDim.x);
     if (item >= n_items) return;
     const int t = threadIdx.x;
     if (t == 0) {
@@ -599,7 +694,7 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam, uint32_
     __shared__ int s_tile;
     __shared__ uint32_t s_chunk;
     PHASE_BEGIN();
-    const uint32_t item = blockIdx.x;
+    const uint32_t item = xcd_contiguous(blockIdx.x, gridDim.x);
     if (item >= n_items) return;
     const int t = threadIdx.x;
     if (t == 0) {
@@ -645,7 +740,7 @@ __global__ __launch_bounds__(kNT) void k_batch(FrameBufs f, ShadeArgs a, float* 
     float* s_pay = reinterpret_cast<float*>(s_work);
     PHASE_BEGIN();
 
-    const uint4 br = f.batches[blockIdx.x];
+    const uint4 br = f.batches[xcd_contiguous(blockIdx.x, gridDim.x)];
     const int tile = (int)br.x, p0 = (int)br.y, p1 = (int)br.z;
     const int t = threadIdx.x;
     if (br.w) return;     // oversized pixel: counted in k_tile_prep, left transparent
@@ -924,15 +1019,24 @@ inline int blocks_for(size_t n, int per) { return (int)((n + per - 1) / per); }
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
-hipError_t launch_project(const LevelDev& lv, const CamConst& cam, SegRec* seg, uint32_t* tile_cnt, Counters* ctr,
-                          hipStream_t st) {
+hipError_t launch_project(const LevelDev& lv, const CamConst& cam, SegRec* seg, ShadeRec* shade, uint32_t* tile_cnt,
+                          Counters* ctr, hipStream_t st) {
     if (lv.nseg == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_project, dim3(blocks_for(lv.nseg, 256)), dim3(256), 0, st, lv, cam, seg, tile_cnt, ctr);
+    hipLaunchKernelGGL(k_project, dim3(blocks_for(lv.nseg, 256)), dim3(256), 0, st, lv, cam, seg, shade, tile_cnt, ctr);
     return hipGetLastError();
 }
 
-hipError_t launch_scan_tiles(const uint32_t* cnt, uint32_t* start, int32_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cnt, start, n);
+hipError_t launch_exscan(const uint32_t* cnt, uint32_t* start, int32_t n, uint32_t* scratch, hipStream_t st) {
+    if (n <= kScanChunk) {
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cnt, start, n);
+        return hipGetLastError();
+    }
+    const int nb = (n + kScanChunk - 1) / kScanChunk;
+    uint32_t* part = scratch;            // [nb]
+    uint32_t* base = scratch + nb + 1;   // [nb + 1]
+    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(1024), 0, st, cnt, start, part, n);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, part, base, nb);
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(1024), 0, st, start, base, n, nb);
     return hipGetLastError();
 }
 
@@ -973,15 +1077,14 @@ hipError_t launch_emit(const FrameBufs& f, const CamConst& cam, uint32_t n_items
 }
 
 hipError_t launch_batches(const FrameBufs& f, const LevelDev& lv, const CamConst& cam, const LightsConst& lights,
-                          const MatConst& mat, const SegRec* seg, uint32_t n_batches, float* rgba,
-                          const DebugDump* dbg, hipStream_t st) {
+                          const MatConst& mat, uint32_t n_batches, float* rgba, const DebugDump* dbg, hipStream_t st) {
     if (n_batches == 0) return hipSuccess;
     ShadeArgs a;
-    a.lv = lv;
     a.cam = cam;
     a.lights = lights;
     a.mat = mat;
-    a.seg = seg;
+    a.seg = f.seg;
+    a.shade = f.shade;
     DebugDump d = dbg ? *dbg : DebugDump{};
     if (lv.kind == 0)
         hipLaunchKernelGGL(k_batch<0>, dim3(n_batches), dim3(kNT), 0, st, f, a, rgba, d, dbg ? 1 : 0);
