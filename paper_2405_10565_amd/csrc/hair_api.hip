@@ -296,7 +296,7 @@ struct FrameOut {
 //   k_batch                           sort, shade, blend (one workgroup per batch)
 int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, const hair_camera* cam,
               const hair_light* lights, int n_lights, float* rgba, const DebugDump* dbg, hipStream_t st,
-              FrameOut* out, bool tiles_too = true) {
+              FrameOut* out, bool tiles_too = true, const GradOut* grad = nullptr) {
     int rc;
     const CamConst cc = cam_const(cam);
     const int ntx = (cam->width + kTile - 1) / kTile, nty = (cam->height + kTile - 1) / kTile;
@@ -391,9 +391,16 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     HIP_TRY(ctx, launch_batch_records(f, st), "k_batch_records");
     HIP_TRY(ctx, launch_emit(f, cc, n_items, st), "k_emit");
     HIP_TRY(ctx, hipEventRecord(ws->ev[5], st), "hipEventRecord");
-    if (rgba)
+    if (grad) {
+        HIP_TRY(ctx, launch_fill_f32(grad->d_axes, 0.0f, 2ull * lv.nseg, st), "fill");
+        HIP_TRY(ctx, launch_fill_f32(grad->d_r, 0.0f, (size_t)lv.n_owner, st), "fill");
+        HIP_TRY(ctx, launch_fill_f32(grad->d_sig, 0.0f, 3ull * lv.n_owner, st), "fill");
+        HIP_TRY(ctx, launch_batches_bwd(f, lv, cc, lights_const(lights, n_lights), mat_const(a.mat), n_batches, *grad, st),
+                "k_batch_bwd");
+    } else if (rgba) {
         HIP_TRY(ctx, launch_batches(f, lv, cc, lights_const(lights, n_lights), mat_const(a.mat), n_batches, rgba, dbg, st),
                 "k_batch");
+    }
     HIP_TRY(ctx, hipEventRecord(ws->ev[6], st), "hipEventRecord");
     HIP_TRY(ctx, hipMemcpyAsync(&out->ctr, ws->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, st), "copy");
     HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
@@ -854,8 +861,16 @@ int hair_render_backward(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t leve
     Asset* a;
     LevelDev lv;
     if ((rc = find_level(ctx, asset, level, &a, &lv))) return rc;
-    (void)ws; (void)stream;
-    return fail(HAIR_EINVAL, "backward pass not built in this version");
+    if ((rc = need_device(ctx))) return rc;
+    ws = ws_or_default(ctx, ws);
+    std::lock_guard<std::mutex> g(ws->mu);
+    GradOut grad{d_rgba, d_axes, d_r, d_sigma_a};
+    FrameOut fo;
+    if ((rc = run_frame(ctx, ws, *a, lv, cam, lights, n_lights, nullptr, nullptr, (hipStream_t)stream, &fo, true, &grad)))
+        return rc;
+    if (fo.ctr.overflow_pixels)
+        return fail(HAIR_ERANGE, "%u pixels exceed %d fragments (their gradient is missing)", fo.ctr.overflow_pixels, kCap);
+    return HAIR_OK;
 }
 
 int hair_debug_segments(hair_ws* ws, int64_t n, int32_t* rec_i, float* rec_f) {

@@ -152,6 +152,8 @@ hipError_t launch_batch_records(const FrameBufs& f, hipStream_t st);
 hipError_t launch_emit(const FrameBufs& f, const CamConst& cam, uint32_t n_items, hipStream_t st);
 hipError_t launch_batches(const FrameBufs& f, const LevelDev& lv, const CamConst& cam, const LightsConst& lights,
                           const MatConst& mat, uint32_t n_batches, float* rgba, const DebugDump* dbg, hipStream_t st);
+hipError_t launch_batches_bwd(const FrameBufs& f, const LevelDev& lv, const CamConst& cam, const LightsConst& lights,
+                              const MatConst& mat, uint32_t n_batches, const GradOut& grad, hipStream_t st);
 hipError_t launch_build_centers(const float* vx, const float* vy, const float* vz, const float* width,
                                 const float* sig, int32_t n_strands, int32_t V, const int32_t* members,
                                 const int32_t* member_start, int32_t K, float* cx, float* cy, float* cz,

@@ -18,6 +18,7 @@
 // one rounding per operation and no contraction, so they match a float32 reference bit for bit.
 #include "hair_internal.h"
 #include "hair_shading.h"
+#include "hair_dual.h"
 
 #pragma clang fp contract(off)
 
@@ -407,13 +408,14 @@ struct ShadeArgs {
     const ShadeRec* shade;
 };
 
-// Radiance (RGB), coverage alpha and cross-section offset of one fragment.
-template <int KIND>
-__device__ inline void shade_fragment(const ShadeArgs& a, uint32_t gseg, int pxg, int pyg, float& alpha, float& hoff,
-                                      float L[3]) {
-    const SegRec s = a.seg[gseg];
-    const ShadeRec& srec = a.shade[gseg];
-    const float4 q0 = srec.q0, q1 = srec.q1, q2 = srec.q2;
+// Radiance (RGB), coverage alpha and cross-section offset h of one fragment, written once over
+// the scalar type T: float for rendering, Dual<N> for the backward pass.  T carries the
+// fitted parameters (half-width hw, semi-axes |a|, |b|, hair radius r, absorption); the view
+// geometry (frame, angles) does not depend on them and stays float.
+template <int KIND, class T>
+__device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const float4& q0, const float4& q1,
+                                  const float4& q2, float n_total, int pxg, int pyg, const T& hw, const T& a_len,
+                                  const T& b_len, const T& rr, const T sig[3], T& alpha, T& hoff, T L[3]) {
     const long long ex = 16LL * pxg + 8 - s.xa, ey = 16LL * pyg + 8 - s.ya;
     const long long dx = (long long)s.xb - s.xa, dy = (long long)s.yb - s.ya;
     const long long tnum = ex * dx + ey * dy, tden = dx * dx + dy * dy;
@@ -421,11 +423,10 @@ __device__ inline void shade_fragment(const ShadeArgs& a, uint32_t gseg, int pxg
     const float t = (float)tnum / (float)tden;
     const float iz = s.iza + t * (s.izb - s.iza);
     const float delta = fabsf((float)cr) / sqrtf((float)tden) * (1.0f / 16.0f);
-    const float hw = s.hw;
-    alpha = fminf(fmaxf(fminf(delta + hw, 0.5f) - fmaxf(delta - hw, -0.5f), 0.0f), 1.0f);
+    alpha = m_min(m_max(m_min(hw + delta, T(0.5f)) - m_max(delta - hw, T(-0.5f)), T(0.0f)), T(1.0f));
     float sgn = cr > 0 ? 1.0f : (cr < 0 ? -1.0f : 0.0f);
     if (s.hwfx & kFlagNegSide) sgn = -sgn;
-    const float h = fminf(fmaxf(sgn * delta / (hw + 0.5f), -1.0f), 1.0f);
+    const T h = m_min(m_max((sgn * delta) / (hw + 0.5f), T(-1.0f)), T(1.0f));
     hoff = h;
     const float tw = t * s.izb / iz;
 
@@ -450,23 +451,18 @@ __device__ inline void shade_fragment(const ShadeArgs& a, uint32_t gseg, int pxg
     const V3<float> yh = cross(u, xh);
     const float to = asinf(fminf(fmaxf(sin_to, -1.0f), 1.0f));
 
-    float sig[3] = {q0.w, q1.w, q2.w};
-    ClusterFrag<float> cf;
-    float a_len = 0, b_len = 0, W = 0;
+    ClusterFrag<T> cf;
+    T W;
     V3<float> ah{}, bh{};
     if (KIND == 1) {
-        const float4 q3 = srec.q3;
         ah = v3(q2.x, q2.y, q2.z);
         bh = cross(u, ah);
-        a_len = q3.x;
-        b_len = q3.y;
-        const float pa = a_len * dot(ah, yh), pb = b_len * dot(bh, yh);
-        W = sqrtf(pa * pa + pb * pb);
-        cf.n_total = q3.z;
-        const float rr = q3.w;
-        cf.rho = fminf(fmaxf(cf.n_total * rr * rr / (a_len * b_len), 0.0f), 1.0f);
+        const T pa = a_len * dot(ah, yh), pb = b_len * dot(bh, yh);
+        W = m_sqrt(pa * pa + pb * pb);
+        cf.n_total = T(n_total);
+        cf.rho = m_min(m_max(n_total * rr * rr / (a_len * b_len), T(0.0f)), T(1.0f));
     }
-    L[0] = L[1] = L[2] = 0.0f;
+    L[0] = L[1] = L[2] = T(0.0f);
     for (int li = 0; li < a.lights.n; ++li) {
         const LightConst& lc = a.lights.l[li];
         V3<float> wi;
@@ -488,35 +484,50 @@ __device__ inline void shade_fragment(const ShadeArgs& a, uint32_t gseg, int pxg
         const float th = 0.5f * (ti + to);
         const float xd = 0.5f * fabsf(ti - to);
         const float cos_ti = sqrtf((1.0f - sc) * (1.0f + sc));
-        float f[3];
+        T f[3];
         if (KIND == 0) {
-            f_single(th, xd, phi, h, sig, a.mat, f);
+            f_single(T(th), T(xd), T(phi), h, sig, a.mat, f);
         } else {
             // chord of the view ray's entry point toward the light, in the cross-section
             const V3<float> Dp = sub(wi, scale(u, sin_ti));
             const float dn = sqrtf(dot(Dp, Dp));
-            float s_star = 0.0f;
+            T s_star(0.0f);
             if (dn > 1e-7f) {
                 const V3<float> D = scale(Dp, 1.0f / dn);
-                const float oa = h * W * dot(yh, ah) / a_len, ob = h * W * dot(yh, bh) / b_len;
-                const float xa = dot(xh, ah) / a_len, xb = dot(xh, bh) / b_len;
-                const float qa = xa * xa + xb * xb, qb = oa * xa + ob * xb, qc = oa * oa + ob * ob - 1.0f;
-                const float disc = fmaxf(qb * qb - qa * qc, 0.0f);
-                const float tt = (qb - sqrtf(disc)) / qa;
-                const float Pa = oa - tt * xa, Pb = ob - tt * xb;
-                const float Da = dot(D, ah) / a_len, Db = dot(D, bh) / b_len;
+                const T oa = h * W * dot(yh, ah) / a_len, ob = h * W * dot(yh, bh) / b_len;
+                const T xa = dot(xh, ah) / a_len, xb = dot(xh, bh) / b_len;
+                const T qa = xa * xa + xb * xb, qb = oa * xa + ob * xb, qc = oa * oa + ob * ob - 1.0f;
+                const T disc = m_max(qb * qb - qa * qc, T(0.0f));
+                const T tt = (qb - m_sqrt(disc)) / qa;
+                const T Pa = oa - tt * xa, Pb = ob - tt * xb;
+                const T Da = dot(D, ah) / a_len, Db = dot(D, bh) / b_len;
                 s_star = -2.0f * (Pa * Da + Pb * Db) / (Da * Da + Db * Db);
             }
-            const float kappa = sqrtf(cf.n_total / (kPi * a_len * b_len));
-            const float lF = fmaxf(s_star, 0.0f), lB = fmaxf(-s_star, 0.0f);
+            const T kappa = m_sqrt(n_total / (kPi * a_len * b_len));
+            const T lF = m_max(s_star, T(0.0f)), lB = m_max(-s_star, T(0.0f));
             const bool back = fabsf(phi) < 0.5f * kPi;
-            cf.n_F = (back || cf.n_total < 2.0f) ? 1.0f : fmaxf(cf.rho * kappa * lF, 1.0f);
-            cf.n_B = fmaxf(cf.rho * kappa * lB, 1.0f);
-            f_ours(th, xd, phi, h, sig, a.mat, cf, f);
+            cf.n_F = (back || n_total < 2.0f) ? T(1.0f) : m_max(cf.rho * kappa * lF, T(1.0f));
+            cf.n_B = m_max(cf.rho * kappa * lB, T(1.0f));
+            f_ours(T(th), T(xd), T(phi), h, sig, a.mat, cf, f);
         }
-        L[0] += E[0] * f[0] * cos_ti;
-        L[1] += E[1] * f[1] * cos_ti;
-        L[2] += E[2] * f[2] * cos_ti;
+        L[0] = L[0] + (E[0] * cos_ti) * f[0];
+        L[1] = L[1] + (E[1] * cos_ti) * f[1];
+        L[2] = L[2] + (E[2] * cos_ti) * f[2];
+    }
+}
+
+template <int KIND>
+__device__ inline void shade_fragment(const ShadeArgs& a, uint32_t gseg, int pxg, int pyg, float& alpha, float& hoff,
+                                      float L[3]) {
+    const SegRec s = a.seg[gseg];
+    const ShadeRec& srec = a.shade[gseg];
+    const float4 q0 = srec.q0, q1 = srec.q1, q2 = srec.q2;
+    const float sig[3] = {q0.w, q1.w, q2.w};
+    if (KIND == 0) {
+        shade_core<0, float>(a, s, q0, q1, q2, 1.0f, pxg, pyg, s.hw, 0.f, 0.f, 0.f, sig, alpha, hoff, L);
+    } else {
+        const float4 q3 = srec.q3;
+        shade_core<1, float>(a, s, q0, q1, q2, q3.z, pxg, pyg, s.hw, q3.x, q3.y, q3.w, sig, alpha, hoff, L);
     }
 }
 
@@ -914,6 +925,316 @@ __global__ __launch_bounds__(kNT) void k_batch(FrameBufs f, ShadeArgs a, float* 
 }
 
 // ---------------------------------------------------------------------------------------
+// Backward pass (thick-hair levels): vector-Jacobian product of the frame with respect to
+// each cluster segment's |a|, |b| and its cluster's r and sigma_a.  Per batch:
+//   1. the forward's exact per-pixel order (same bucket sort);
+//   2. alpha_k and L_k per fragment (float);
+//   3. front-to-back prefix T_k and back-to-front suffix (C_k+, S_k+) by two segmented scans;
+//      with dC, dA the pixel's output adjoint:
+//        dLoss/dalpha_k = T_k [dC . (L_k - C_k+) + dA S_k+],   dLoss/dL_k = dC T_k alpha_k;
+//   4. alpha_k and L_k again as Dual<6> (forward-mode partials in |a|, |b|, r, sigma_a rgb)
+//      contracted with the step-3 adjoints; partials summed per list entry in LDS, then one
+//      global atomic per (batch, list entry, parameter).
+constexpr int kNAcc = 1024;          // list entries with LDS accumulators (others go straight to global)
+using Dual6 = Dual<6>;
+
+// d hw / d|a|, d hw / d|b| of the float32 half-width (support of the ellipse across the view at
+// the segment midpoint, times fy / z_mid).
+__device__ inline void halfwidth_partials(const CamConst& c, const SegRec& s, const float4& q0, const float4& q1,
+                                          const float4& q2, float a_len, float b_len, float& da, float& db) {
+    const float tx = q1.x - q0.x, ty = q1.y - q0.y, tz = q1.z - q0.z;
+    const float tl = norm3f(tx, ty, tz);
+    const float ux = tx / tl, uy = ty / tl, uz = tz / tl;
+    const float mx = (q0.x + q1.x) * 0.5f, my = (q0.y + q1.y) * 0.5f, mz = (q0.z + q1.z) * 0.5f;
+    float wx = c.pos[0] - mx, wy = c.pos[1] - my, wz = c.pos[2] - mz;
+    const float wl = norm3f(wx, wy, wz);
+    wx /= wl; wy /= wl; wz /= wl;
+    const float dwu = (wx * ux + wy * uy) + wz * uz;
+    const float px = wx - dwu * ux, py = wy - dwu * uy, pz = wz - dwu * uz;
+    const float pl = norm3f(px, py, pz);
+    const float zm = (1.0f / s.iza + 1.0f / s.izb) * 0.5f;
+    const float k = c.fy / zm;
+    if (!(pl > 1e-7f)) {
+        da = a_len >= b_len ? k : 0.0f;
+        db = a_len >= b_len ? 0.0f : k;
+        return;
+    }
+    const float xx = px / pl, xy = py / pl, xz = pz / pl;
+    const float yx = uy * xz - uz * xy, yy = uz * xx - ux * xz, yz = ux * xy - uy * xx;
+    const float hx = q2.x, hy = q2.y, hz = q2.z;
+    const float bhx = uy * hz - uz * hy, bhy = uz * hx - ux * hz, bhz = ux * hy - uy * hx;
+    const float ca = (hx * yx + hy * yy) + hz * yz;
+    const float cb = (bhx * yx + bhy * yy) + bhz * yz;
+    const float W = sqrtf(a_len * a_len * ca * ca + b_len * b_len * cb * cb);
+    da = W > 0.0f ? k * a_len * ca * ca / W : 0.0f;
+    db = W > 0.0f ? k * b_len * cb * cb / W : 0.0f;
+}
+
+__global__ __launch_bounds__(kNT) void k_batch_bwd(FrameBufs f, ShadeArgs a, GradOut g, int S, int K) {
+    __shared__ uint32_t s_cnt[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix], s_off[kTilePix + 1];
+    __shared__ uint32_t s_tmp[kNT];
+    __shared__ __align__(16) uint2 s_B[kCap];
+    __shared__ __align__(16) float s_work[4 * kCap];     // sort staging, then (alpha, L) -> adjoints
+    __shared__ float s_T[kCap];                          // front-to-back transmittance before each fragment
+    __shared__ float s_acc[6 * kNAcc];                   // per list entry partial sums
+    __shared__ float s_dpix[4 * kTilePix];               // output adjoint of the batch's pixels
+    __shared__ float s_agg[kNT * 4];
+    __shared__ uint32_t s_aggh[kNT];
+    uint2* s_A = reinterpret_cast<uint2*>(s_work);
+    uint32_t* s_bk = reinterpret_cast<uint32_t*>(s_work) + 2 * kCap;
+    float4* s_p4 = reinterpret_cast<float4*>(s_work);
+
+    const uint4 br = f.batches[xcd_contiguous(blockIdx.x, gridDim.x)];
+    const int tile = (int)br.x, p0 = (int)br.y, p1 = (int)br.z;
+    const int t = threadIdx.x;
+    if (br.w) return;
+    const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
+    const int W = a.cam.W, H = a.cam.H;
+    const uint32_t lstart = f.tile_start[tile * kSub];
+    const uint32_t n = f.tile_start[(tile + 1) * kSub] - lstart;
+    const uint32_t* list = f.list + lstart;
+    const size_t q = (size_t)tile * kTilePix + t;
+    const uint32_t tile_off0 = f.pix_off[(size_t)tile * kTilePix + p0];
+    if (t >= p0 && t < p1) {
+        s_cnt[t] = f.pix_cnt[q];
+        s_kmin[t] = f.pix_kmin[q];
+        s_kmax[t] = f.pix_kmax[q];
+        s_off[t] = f.pix_off[q] - tile_off0;
+        const int gx = px0 + (t % kTile), gy = py0 + (t / kTile);
+        const bool in = gx < W && gy < H;
+        const float4 dp = in ? reinterpret_cast<const float4*>(g.d_rgba)[(size_t)gy * W + gx] : make_float4(0, 0, 0, 0);
+        s_dpix[4 * t + 0] = dp.x; s_dpix[4 * t + 1] = dp.y; s_dpix[4 * t + 2] = dp.z; s_dpix[4 * t + 3] = dp.w;
+    }
+    if (t == 0) s_off[p1] = (p1 < kTilePix ? f.pix_off[(size_t)tile * kTilePix + p1] : f.tile_tot[tile]) - tile_off0;
+    for (int i = t; i < 6 * kNAcc; i += kNT) s_acc[i] = 0.0f;
+    __syncthreads();
+    const uint32_t Fb = s_off[p1];
+    const uint2* src = f.frags + f.frag_base[tile] + tile_off0;
+    for (uint32_t i = t; i < Fb; i += kNT) {
+        s_A[i] = src[i];
+        s_bk[i] = 0;
+    }
+    __syncthreads();
+    uint32_t my_b[kPerThread], my_r[kPerThread];
+#pragma unroll
+    for (int qq = 0; qq < kPerThread; ++qq) {
+        const uint32_t i = t + qq * kNT;
+        if (i < Fb) {
+            const uint2 rec = s_A[i];
+            const uint32_t p = rec.y >> 24;
+            const uint32_t kmn = s_kmin[p];
+            const unsigned long long span = (unsigned long long)(s_kmax[p] - kmn) + 1ull;
+            const uint32_t bucket = (uint32_t)(((unsigned long long)(rec.x - kmn) * s_cnt[p]) / span);
+            my_b[qq] = s_off[p] + bucket;
+            my_r[qq] = atomicAdd(&s_bk[my_b[qq]], 1u);
+        }
+    }
+    __syncthreads();
+    {
+        uint32_t loc[kPerThread];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int qq = 0; qq < kPerThread; ++qq) {
+            const uint32_t i = t * kPerThread + qq;
+            loc[qq] = i < Fb ? s_bk[i] : 0u;
+            sum += loc[qq];
+        }
+        uint32_t ex;
+        block_exscan_u32(sum, s_tmp, ex);
+#pragma unroll
+        for (int qq = 0; qq < kPerThread; ++qq) {
+            const uint32_t i = t * kPerThread + qq;
+            if (i < Fb) s_bk[i] = ex;
+            ex += loc[qq];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int qq = 0; qq < kPerThread; ++qq) {
+        const uint32_t i = t + qq * kNT;
+        if (i < Fb) s_B[s_bk[my_b[qq]] + my_r[qq]] = s_A[i];
+    }
+    __syncthreads();
+    for (uint32_t bi = t; bi < Fb; bi += kNT) {
+        const uint32_t b0 = s_bk[bi];
+        const uint32_t b1 = bi + 1 < Fb ? s_bk[bi + 1] : Fb;
+        for (uint32_t i = b0 + 1; i < b1; ++i) {
+            const uint2 v = s_B[i];
+            const uint32_t vseg = list[v.y & 0xFFFFFFu];
+            uint32_t jx = i;
+            while (jx > b0) {
+                const uint2 u2 = s_B[jx - 1];
+                bool greater = u2.x > v.x;
+                if (u2.x == v.x) greater = list[u2.y & 0xFFFFFFu] > vseg;
+                if (!greater) break;
+                s_B[jx] = u2;
+                --jx;
+            }
+            s_B[jx] = v;
+        }
+    }
+    __syncthreads();
+    // ---- 2. alpha and L per fragment (float)
+    for (uint32_t i = t; i < Fb; i += kNT) {
+        const uint2 rec = s_B[i];
+        const uint32_t p = rec.y >> 24;
+        const uint32_t gseg = list[rec.y & 0xFFFFFFu];
+        float al, hh, L[3];
+        shade_fragment<1>(a, gseg, px0 + (int)(p % kTile), py0 + (int)(p / kTile), al, hh, L);
+        s_p4[i] = make_float4(al, L[0], L[1], L[2]);
+    }
+    __syncthreads();
+    // ---- 3a. forward: T before each fragment (segmented exclusive product over runs)
+    const uint32_t run = (Fb + kNT - 1) / kNT;
+    const uint32_t rb = min(Fb, t * run), re = min(Fb, rb + run);
+    {
+        float T = 1.f;
+        uint32_t head = 0;
+        for (uint32_t i = rb; i < re; ++i) {
+            const uint32_t p = s_B[i].y >> 24;
+            if (i == s_off[p]) { T = 1.f; head = 1; }
+            T *= 1.0f - s_p4[i].x;
+        }
+        s_agg[4 * t + 3] = T;
+        s_aggh[t] = head;
+        __syncthreads();
+        for (int off = 1; off < kNT; off <<= 1) {
+            float tt = 1;
+            uint32_t hh2 = 0;
+            const bool has = t >= off;
+            if (has) { tt = s_agg[4 * (t - off) + 3]; hh2 = s_aggh[t - off]; }
+            __syncthreads();
+            if (has && !s_aggh[t]) { s_agg[4 * t + 3] = tt * s_agg[4 * t + 3]; s_aggh[t] = hh2; }
+            __syncthreads();
+        }
+        T = t > 0 ? s_agg[4 * (t - 1) + 3] : 1.f;
+        for (uint32_t i = rb; i < re; ++i) {
+            const uint32_t p = s_B[i].y >> 24;
+            if (i == s_off[p]) T = 1.f;
+            s_T[i] = T;
+            T *= 1.0f - s_p4[i].x;
+        }
+        __syncthreads();
+    }
+    // ---- 3b. backward: suffix composite (C+, S+) after each fragment, then the adjoints
+    {
+        // run aggregate from the run start through its first pixel end (or the whole run)
+        float C0 = 0.f, C1 = 0.f, C2 = 0.f, Sx = 1.f;
+        uint32_t tail = 0;
+        for (uint32_t i = re; i > rb; --i) {
+            const uint32_t k = i - 1;
+            const uint32_t p = s_B[k].y >> 24;
+            if (k + 1 == s_off[p] + s_cnt[p]) { C0 = C1 = C2 = 0.f; Sx = 1.f; tail = 1; }
+            const float4 v = s_p4[k];
+            C0 = v.x * v.y + (1.0f - v.x) * C0;
+            C1 = v.x * v.z + (1.0f - v.x) * C1;
+            C2 = v.x * v.w + (1.0f - v.x) * C2;
+            Sx = (1.0f - v.x) * Sx;
+        }
+        s_agg[4 * t + 0] = C0; s_agg[4 * t + 1] = C1; s_agg[4 * t + 2] = C2; s_agg[4 * t + 3] = Sx;
+        s_aggh[t] = tail;
+        __syncthreads();
+        // right-to-left inclusive scan: R_t = agg_t.tail ? agg_t : agg_t over R_{t+1}
+        for (int off = 1; off < kNT; off <<= 1) {
+            float c0 = 0, c1 = 0, c2 = 0, ss = 1;
+            const bool has = t + off < kNT;
+            if (has) {
+                c0 = s_agg[4 * (t + off) + 0]; c1 = s_agg[4 * (t + off) + 1];
+                c2 = s_agg[4 * (t + off) + 2]; ss = s_agg[4 * (t + off) + 3];
+            }
+            const uint32_t my_tail = s_aggh[t];
+            const uint32_t r_tail = has ? s_aggh[t + off] : 0u;
+            __syncthreads();
+            if (has && !my_tail) {
+                const float mS = s_agg[4 * t + 3];
+                s_agg[4 * t + 0] = s_agg[4 * t + 0] + mS * c0;
+                s_agg[4 * t + 1] = s_agg[4 * t + 1] + mS * c1;
+                s_agg[4 * t + 2] = s_agg[4 * t + 2] + mS * c2;
+                s_agg[4 * t + 3] = mS * ss;
+                s_aggh[t] = r_tail;
+            }
+            __syncthreads();
+        }
+        if (t + 1 < kNT) { C0 = s_agg[4 * (t + 1) + 0]; C1 = s_agg[4 * (t + 1) + 1]; C2 = s_agg[4 * (t + 1) + 2]; Sx = s_agg[4 * (t + 1) + 3]; }
+        else { C0 = C1 = C2 = 0.f; Sx = 1.f; }
+        __syncthreads();
+        for (uint32_t i = re; i > rb; --i) {
+            const uint32_t k = i - 1;
+            const uint32_t p = s_B[k].y >> 24;
+            if (k + 1 == s_off[p] + s_cnt[p]) { C0 = C1 = C2 = 0.f; Sx = 1.f; }
+            const float4 v = s_p4[k];
+            const float Tk = s_T[k];
+            const float dR = s_dpix[4 * p + 0], dG = s_dpix[4 * p + 1], dB = s_dpix[4 * p + 2], dA = s_dpix[4 * p + 3];
+            const float g_alpha = Tk * (dR * (v.y - C0) + dG * (v.z - C1) + dB * (v.w - C2) + dA * Sx);
+            const float ta = Tk * v.x;
+            C0 = v.x * v.y + (1.0f - v.x) * C0;
+            C1 = v.x * v.z + (1.0f - v.x) * C1;
+            C2 = v.x * v.w + (1.0f - v.x) * C2;
+            Sx = (1.0f - v.x) * Sx;
+            s_p4[k] = make_float4(g_alpha, dR * ta, dG * ta, dB * ta);
+        }
+    }
+    __syncthreads();
+    // ---- 4. partials: alpha and L as Dual6, contracted with the adjoints
+    for (uint32_t i = t; i < Fb; i += kNT) {
+        const uint2 rec = s_B[i];
+        const uint32_t p = rec.y >> 24;
+        const uint32_t j = rec.y & 0xFFFFFFu;
+        const uint32_t gseg = list[j];
+        const float4 adj = s_p4[i];
+        const SegRec s = a.seg[gseg];
+        const ShadeRec& srec = a.shade[gseg];
+        const float4 q0 = srec.q0, q1 = srec.q1, q2 = srec.q2, q3 = srec.q3;
+        float dha, dhb;
+        halfwidth_partials(a.cam, s, q0, q1, q2, q3.x, q3.y, dha, dhb);
+        Dual6 hw(s.hw);
+        hw.d[0] = dha;
+        hw.d[1] = dhb;
+        const Dual6 al = Dual6::seed(q3.x, 0), bl = Dual6::seed(q3.y, 1), rr = Dual6::seed(q3.w, 2);
+        const Dual6 sig[3] = {Dual6::seed(q0.w, 3), Dual6::seed(q1.w, 4), Dual6::seed(q2.w, 5)};
+        Dual6 alpha, hoff, L[3];
+        shade_core<1, Dual6>(a, s, q0, q1, q2, q3.z, px0 + (int)(p % kTile), py0 + (int)(p / kTile), hw, al, bl, rr,
+                             sig, alpha, hoff, L);
+        float gp[6];
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+            gp[m] = adj.x * alpha.d[m] + adj.y * L[0].d[m] + adj.z * L[1].d[m] + adj.w * L[2].d[m];
+        if (j < (uint32_t)kNAcc) {
+#pragma unroll
+            for (int m = 0; m < 6; ++m) atomicAdd(&s_acc[m * kNAcc + j], gp[m]);
+        } else {
+            const int owner = (int)gseg / S;
+            atomicAdd(&g.d_axes[2 * gseg], gp[0]);
+            atomicAdd(&g.d_axes[2 * gseg + 1], gp[1]);
+            atomicAdd(&g.d_r[owner], gp[2]);
+            atomicAdd(&g.d_sig[owner], gp[3]);
+            atomicAdd(&g.d_sig[K + owner], gp[4]);
+            atomicAdd(&g.d_sig[2 * K + owner], gp[5]);
+        }
+    }
+    __syncthreads();
+    const uint32_t nacc = min(n, (uint32_t)kNAcc);
+    for (uint32_t j = t; j < nacc; j += kNT) {
+        float v[6];
+        bool any = false;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            v[m] = s_acc[m * kNAcc + j];
+            any |= v[m] != 0.0f;
+        }
+        if (!any) continue;
+        const uint32_t gseg = list[j];
+        const int owner = (int)gseg / S;
+        atomicAdd(&g.d_axes[2 * gseg], v[0]);
+        atomicAdd(&g.d_axes[2 * gseg + 1], v[1]);
+        atomicAdd(&g.d_r[owner], v[2]);
+        atomicAdd(&g.d_sig[owner], v[3]);
+        atomicAdd(&g.d_sig[K + owner], v[4]);
+        atomicAdd(&g.d_sig[2 * K + owner], v[5]);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // Thick-hair construction (Sec. 5.1 step 3), float64 sums in member order.
 __global__ void k_build_centers(const float* __restrict__ vx, const float* __restrict__ vy,
                                 const float* __restrict__ vz, const float* __restrict__ width,
@@ -1090,6 +1411,19 @@ hipError_t launch_batches(const FrameBufs& f, const LevelDev& lv, const CamConst
         hipLaunchKernelGGL(k_batch<0>, dim3(n_batches), dim3(kNT), 0, st, f, a, rgba, d, dbg ? 1 : 0);
     else
         hipLaunchKernelGGL(k_batch<1>, dim3(n_batches), dim3(kNT), 0, st, f, a, rgba, d, dbg ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_batches_bwd(const FrameBufs& f, const LevelDev& lv, const CamConst& cam, const LightsConst& lights,
+                              const MatConst& mat, uint32_t n_batches, const GradOut& grad, hipStream_t st) {
+    if (n_batches == 0) return hipSuccess;
+    ShadeArgs a;
+    a.cam = cam;
+    a.lights = lights;
+    a.mat = mat;
+    a.seg = f.seg;
+    a.shade = f.shade;
+    hipLaunchKernelGGL(k_batch_bwd, dim3(n_batches), dim3(kNT), 0, st, f, a, grad, lv.S, lv.n_owner);
     return hipGetLastError();
 }
 

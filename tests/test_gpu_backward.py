@@ -1,0 +1,143 @@
+"""GPU backward pass (hair_render_backward) against the oracle's autograd gradient and against
+central differences of the GPU forward; autograd wrapper and LoD fitting."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import hairsynth as hs
+from oracle import grad as OG
+from oracle import lod as OL
+from oracle import render as R
+
+pytestmark = pytest.mark.gpu
+
+
+def _scene(seed=11, n=400, segs=6, W=96, H=80, k=8):
+    asset = hs.make_asset(n, segs, 90.0, seed=seed, sigma_spread=True)
+    cam = hs.camera_for(asset, W, H)
+    lights = hs.default_lights(asset, with_point=True)
+    lod = OL.build_level(asset, hs.kmeans_assign(asset, k, seed=seed))
+    return asset, cam, lights, lod
+
+
+@pytest.fixture(scope="module")
+def ctx(hip):
+    c = hip.Context(0)
+    yield c
+    c.close()
+
+
+def _gpu_vjp(ctx, aid, cam, lights, d_rgba, K, S):
+    dev = "cuda:0"
+    d = torch.tensor(d_rgba, dtype=torch.float32, device=dev).contiguous()
+    da = torch.empty((K, S, 2), dtype=torch.float32, device=dev)
+    dr = torch.empty(K, dtype=torch.float32, device=dev)
+    ds = torch.empty((3, K), dtype=torch.float32, device=dev)
+    ctx.render_backward(aid, 1, cam, lights, d, da, dr, ds)
+    torch.cuda.synchronize()
+    return da.cpu().numpy(), dr.cpu().numpy(), ds.cpu().numpy()
+
+
+def _close(got, ref, what):
+    scale = float(np.abs(ref).max())
+    err = np.abs(got - ref)
+    tol = 2e-3 * scale + 2e-3 * np.abs(ref)
+    bad = int((err > tol).sum())
+    print(f"[{what}] max |err| {float(err.max()):.3e} (scale {scale:.3e}), violations {bad}/{ref.size}", flush=True)
+    assert bad == 0, what
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_backward_matches_oracle_gradient(hip, ctx, seed):
+    print(f"case: backward vs oracle seed {seed}", flush=True)
+    asset, cam, lights, lod = _scene(seed=seed)
+    K, S = lod["n_total"].size, asset.segs
+    aid = ctx.upload_asset(asset)
+    ctx.set_lod(aid, 1, lod)
+    rng = np.random.default_rng(seed)
+    d_rgba = rng.normal(size=(cam.height, cam.width, 4))
+    mat = tuple(float(v) for v in asset.material.as_array())
+    geom = R.cluster_level(lod)
+    g_axes, g_r, g_sig, _ = OG.cluster_vjp(geom, cam, lights, mat, d_rgba, K, S)
+    da, dr, ds = _gpu_vjp(ctx, aid, cam, lights, d_rgba, K, S)
+    _close(da, g_axes, "d_axes")
+    _close(dr, g_r, "d_r")
+    _close(ds, g_sig, "d_sigma_a")
+    ctx.release(aid)
+
+
+def test_backward_matches_gpu_central_differences(hip, ctx):
+    """20 parameters, central differences of the GPU forward at h = 1e-3 in log space (one
+    Richardson step); parameters whose perturbation changes a coverage radius are skipped
+    (the adjoint holds the fragment set fixed)."""
+    print("case: backward vs GPU finite differences", flush=True)
+    asset, cam, lights, lod = _scene(seed=13, n=600, segs=8, W=112, H=96, k=10)
+    K, S = lod["n_total"].size, asset.segs
+    aid = ctx.upload_asset(asset)
+    ctx.set_lod(aid, 1, lod)
+    ws = ctx.workspace()
+    rng = np.random.default_rng(3)
+    d_rgba = rng.normal(size=(cam.height, cam.width, 4))
+    da, dr, ds = _gpu_vjp(ctx, aid, cam, lights, d_rgba, K, S)
+    dev = "cuda:0"
+    base = {"axes": lod["axes"].astype(np.float64), "r": lod["r"].astype(np.float64),
+            "sig": lod["sigma_a"].astype(np.float64)}
+    grads = {"axes": da, "r": dr, "sig": ds}
+
+    def render(p):
+        ctx.set_cluster_params(aid, 1, torch.tensor(p["axes"], dtype=torch.float32, device=dev),
+                               torch.tensor(p["r"], dtype=torch.float32, device=dev),
+                               torch.tensor(p["sig"], dtype=torch.float32, device=dev))
+        img, st, _ = ctx.render(aid, 1, cam, lights, ws=ws)
+        ri, _ = ctx.debug_segments(ws, K * S)
+        return float((img.cpu().numpy().astype(np.float64) * d_rgba).sum()), ri[:, 4].copy()
+
+    _, hwfx0 = render(base)
+    h = 1e-3
+    checked, tried = 0, 0
+    results = []
+    while checked < 20 and tried < 200:
+        tried += 1
+        kind = ["axes", "axes", "axes", "r", "sig"][rng.integers(5)]
+        idx = tuple(int(rng.integers(n)) for n in base[kind].shape)
+        vals, same = {}, True
+        for step in (h, 0.5 * h):
+            for sgn in (1, -1):
+                p = {k: v.copy() for k, v in base.items()}
+                p[kind][idx] = base[kind][idx] * math.exp(sgn * step)
+                vals[(step, sgn)], hwfx = render(p)
+                same &= np.array_equal(hwfx, hwfx0)
+        if not same:
+            continue
+        f1 = (vals[(h, 1)] - vals[(h, -1)]) / (2 * h)
+        f2 = (vals[(0.5 * h, 1)] - vals[(0.5 * h, -1)]) / h
+        fd = (4 * f2 - f1) / 3
+        an = float(grads[kind][idx]) * base[kind][idx]
+        results.append((kind, idx, fd, an))
+        checked += 1
+    ctx.set_cluster_params(aid, 1, torch.tensor(base["axes"], dtype=torch.float32, device=dev),
+                           torch.tensor(base["r"], dtype=torch.float32, device=dev),
+                           torch.tensor(base["sig"], dtype=torch.float32, device=dev))
+    assert checked == 20
+    scale = max(abs(r[3]) for r in results)
+    for kind, idx, fd, an in results:
+        print(f"  {kind}{idx}: fd {fd:.5e} adjoint {an:.5e}", flush=True)
+        assert abs(fd - an) <= 2e-2 * abs(an) + 5e-3 * scale, (kind, idx, fd, an)
+    ws.close()
+    ctx.release(aid)
+
+
+def test_autograd_fit_reduces_loss(hip, ctx):
+    print("case: LoD fitting", flush=True)
+    from paper_2405_10565_amd import fit as F
+    asset = hs.make_asset(3000, 12, 90.0, seed=4, sigma_spread=False)
+    cams = hs.ring_cameras(asset, 2, 128, 128)
+    lights = hs.default_lights(asset, with_point=False)
+    aid = ctx.upload_asset(asset)
+    ctx.build_lod(aid, [hs.kmeans_assign(asset, 60, seed=4)])
+    res = F.fit_level(ctx, aid, 1, cams, lights, iters=25, lr=2e-2)
+    print("loss", res.loss_history[0], "->", res.loss_history[-1], flush=True)
+    assert res.loss_history[-1] < 0.8 * res.loss_history[0]
+    ctx.release(aid)
