@@ -149,11 +149,12 @@ def make_asset(n_strands: int, segs: int, cap_deg: float = 90.0, seed: int = 0,
                  material or Material())
 
 
-def kmeans_assign(asset: Asset, k: int, seed: int, iters: int = 25) -> np.ndarray:
+def kmeans_assign(asset: Asset, k: int, seed: int, iters: int = 25, init: str = "kmeans++") -> np.ndarray:
     """Cluster assignment used as the LoD builder's input (int32 [n_strands], dense labels).
 
-    Features: [root / 0.1, first-segment tangent] (6-D, float64).  k-means++ seeding drawn
-    from PCG64(seed), then `iters` Lloyd iterations; distance ties go to the lower centre
+    Features: [root / 0.1, first-segment tangent] (6-D, float64).  Seeding drawn from
+    PCG64(seed): k-means++ (default) or, for large k, k distinct random strands
+    (init="random"); then `iters` Lloyd iterations; distance ties go to the lower centre
     index (argmin); empty clusters are dropped and labels renumbered densely in order.
     """
     feats = np.concatenate([asset.roots() / 0.1, asset.first_tangents()], axis=1)
@@ -161,19 +162,22 @@ def kmeans_assign(asset: Asset, k: int, seed: int, iters: int = 25) -> np.ndarra
     k = min(int(k), n)
     rng = np.random.Generator(np.random.PCG64(seed))
     centres = np.empty((k, feats.shape[1]))
-    first = int(rng.integers(n))
-    centres[0] = feats[first]
-    d2 = ((feats - centres[0]) ** 2).sum(1)
-    for c in range(1, k):
-        tot = d2.sum()
-        if tot <= 0.0:
-            idx = int(rng.integers(n))
-        else:
-            r = rng.random() * tot
-            idx = int(np.searchsorted(np.cumsum(d2), r, side="right"))
-            idx = min(idx, n - 1)
-        centres[c] = feats[idx]
-        d2 = np.minimum(d2, ((feats - centres[c]) ** 2).sum(1))
+    if init == "random":
+        centres[:] = feats[np.sort(rng.choice(n, size=k, replace=False))]
+    else:
+        first = int(rng.integers(n))
+        centres[0] = feats[first]
+        d2 = ((feats - centres[0]) ** 2).sum(1)
+        for c in range(1, k):
+            tot = d2.sum()
+            if tot <= 0.0:
+                idx = int(rng.integers(n))
+            else:
+                r = rng.random() * tot
+                idx = int(np.searchsorted(np.cumsum(d2), r, side="right"))
+                idx = min(idx, n - 1)
+            centres[c] = feats[idx]
+            d2 = np.minimum(d2, ((feats - centres[c]) ** 2).sum(1))
 
     def assign(cent):
         lab = np.empty(n, dtype=np.int64)
@@ -220,6 +224,12 @@ def camera_for(asset: Asset, width: int, height: int, azimuth: float = 0.0,
     fy = (height / 2.0) / math.tan(half)
     return Camera(pos.astype(np.float32), rot.astype(np.float32), float(np.float32(fy)),
                   float(np.float32(fy)), width / 2.0, height / 2.0, width, height, 0.01)
+
+
+def camera_occupancy(asset: Asset, width: int, height: int, occupancy: float, azimuth: float = 0.0) -> Camera:
+    """Camera whose projected bounding sphere covers `occupancy` of the image area."""
+    fill = math.sqrt(occupancy * width * height / math.pi) / (height / 2.0)
+    return camera_for(asset, width, height, azimuth=azimuth, fill=fill)
 
 
 def ring_cameras(asset: Asset, n: int, width: int, height: int) -> list[Camera]:

@@ -79,12 +79,14 @@ typedef struct hair_stats {
     uint32_t segments;           /* segments of the level */
     uint32_t segments_visible;   /* after near-plane, guard-band and size culling */
     uint32_t segments_culled_long; /* culled for exceeding 1024 px per axis or 256 px half-width */
-    uint32_t overflow_pixels;    /* pixels deeper than HAIR_PIXEL_CAPACITY fragments (left 0) */
+    uint32_t overflow_pixels;    /* pixels with more than HAIR_PIXEL_CAPACITY fragments at one depth key (left 0) */
     float ms_total;              /* GPU time of the call's kernels (hipEvent) */
     float ms_project, ms_bin, ms_tile;
+    uint32_t deep_pixels;        /* pixels deeper than one LDS batch, rendered in depth-key slices */
+    uint32_t batches;            /* LDS batches of the frame */
 } hair_stats;
 
-#define HAIR_PIXEL_CAPACITY 2048   /* most fragments one pixel may hold */
+#define HAIR_PIXEL_CAPACITY 2048   /* fragments per LDS batch */
 #define HAIR_TILE 16               /* tile edge (pixels) */
 
 /* Library version (major * 10000 + minor * 100 + patch). */
@@ -167,14 +169,16 @@ int hair_select_level(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_came
 
 /* Render one frame (the hot path).  rgba_out: device float[height][width][4], premultiplied
  * (C, 1 - T) over transparent black, written in full.  n_lights in 1..HAIR_MAX_LIGHTS.
- * The call synchronises `stream` once (to size the tile lists) and again when stats != NULL.
- * HAIR_ERANGE when a pixel exceeds HAIR_PIXEL_CAPACITY fragments (stats->overflow_pixels). */
+ * The call synchronises `stream` three times (twice to size the frame's buffers, once at the
+ * end).  Pixels of any depth are rendered exactly; HAIR_ERANGE only when more than
+ * HAIR_PIXEL_CAPACITY fragments of one pixel share one depth key (stats->overflow_pixels). */
 int hair_render(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,
                 const hair_light* lights, int32_t n_lights, float* rgba_out, void* stream,
                 hair_stats* stats);
 
 /* Vector-Jacobian product of hair_render at a thick-hair level (level >= 1) with respect to
- * the level's fitted parameters: given d_rgba (device float[height][width][4]) writes
+ * the level's fitted parameters (HAIR_ERANGE when a pixel is deeper than one LDS batch of
+ * HAIR_PIXEL_CAPACITY fragments): given d_rgba (device float[height][width][4]) writes
  *   d_axes    device float[K][S][2]  d/d|a|, d/d|b|
  *   d_r       device float[K]        d/dr
  *   d_sigma_a device float[3][K]     d/dsigma_a

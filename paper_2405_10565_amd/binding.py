@@ -54,13 +54,17 @@ class hair_stats(C.Structure):
     _fields_ = [("fragments", C.c_uint64), ("pairs", C.c_uint64), ("segments", C.c_uint32),
                 ("segments_visible", C.c_uint32), ("segments_culled_long", C.c_uint32),
                 ("overflow_pixels", C.c_uint32), ("ms_total", C.c_float), ("ms_project", C.c_float),
-                ("ms_bin", C.c_float), ("ms_tile", C.c_float)]
+                ("ms_bin", C.c_float), ("ms_tile", C.c_float), ("deep_pixels", C.c_uint32),
+                ("batches", C.c_uint32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 def _load():
+    # torch first: its HIP runtime (same soname as the system one) then serves libhair.so too,
+    # so device pointers and streams from torch belong to the runtime the library calls
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run paper_2405_10565_amd.build.build() (hipcc, gfx950)")
     lib = C.CDLL(LIB_PATH)

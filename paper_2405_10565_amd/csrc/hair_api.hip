@@ -506,11 +506,18 @@ int hair_ws_destroy(hair_ws* ws) {
 
 uint64_t hair_ws_estimate(int64_t n_segments, int32_t width, int32_t height, int64_t pairs_estimate) {
     if (n_segments < 0) n_segments = 0;
-    const int64_t T = (int64_t)((width + kTile - 1) / kTile) * ((height + kTile - 1) / kTile);
+    if (width < 1) width = 1;
+    if (height < 1) height = 1;
+    const uint64_t T = (uint64_t)((width + kTile - 1) / kTile) * (uint64_t)((height + kTile - 1) / kTile);
     if (pairs_estimate <= 0) pairs_estimate = 4 * n_segments;
-    const uint64_t raw = sizeof(SegRec) * (uint64_t)std::max<int64_t>(n_segments, 1) + 12ull * (T + 1) +
-                         4ull * (uint64_t)pairs_estimate + sizeof(Counters);
-    return raw + raw / 4 + 6 * 256;
+    const uint64_t P = (uint64_t)pairs_estimate;
+    const uint64_t items = T + P / kTilePix + 1;
+    const uint64_t frags = 8 * P;   // fragments per (tile, segment) pair at strand widths ~ 4-5
+    const uint64_t raw = (sizeof(SegRec) + sizeof(ShadeRec)) * (uint64_t)std::max<int64_t>(n_segments, 1) +
+                         4ull * 3 * (T * kSub + 1) + 4ull * (2 * T + 2) + 4 * P + 4ull * kTilePix * items +
+                         4ull * 4 * T * kTilePix + 4ull * 4 * (T + 1) + 8 * frags + 16 * (T + frags / 512) +
+                         sizeof(Counters) + 4 * exscan_scratch_words(T * kSub);
+    return raw + raw / 4 + 24 * 256;
 }
 
 int hair_upload(hair_ctx* ctx, int32_t n_strands, int32_t verts_per_strand, const float* xyz_soa,
@@ -842,10 +849,13 @@ int hair_render(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const 
         stats->ms_project = fo.ms[1];
         stats->ms_bin = fo.ms[2];
         stats->ms_tile = fo.ms[3];
+        stats->deep_pixels = fo.ctr.deep_pixels;
+        stats->batches = fo.n_batches;
     }
     if (fo.ctr.list_overflow) return fail(HAIR_ERANGE, "%u tiles hold more than 2^24 segments", fo.ctr.list_overflow);
     if (fo.ctr.overflow_pixels)
-        return fail(HAIR_ERANGE, "%u pixels exceed %d fragments (left transparent)", fo.ctr.overflow_pixels, kCap);
+        return fail(HAIR_ERANGE, "%u pixels hold more than %d fragments at one depth key (left transparent)",
+                    fo.ctr.overflow_pixels, kCap);
     return HAIR_OK;
 }
 
@@ -868,8 +878,9 @@ int hair_render_backward(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t leve
     FrameOut fo;
     if ((rc = run_frame(ctx, ws, *a, lv, cam, lights, n_lights, nullptr, nullptr, (hipStream_t)stream, &fo, true, &grad)))
         return rc;
-    if (fo.ctr.overflow_pixels)
-        return fail(HAIR_ERANGE, "%u pixels exceed %d fragments (their gradient is missing)", fo.ctr.overflow_pixels, kCap);
+    if (fo.ctr.deep_pixels || fo.ctr.overflow_pixels)
+        return fail(HAIR_ERANGE, "%u pixels are deeper than one batch of %d fragments (their gradient is missing)",
+                    fo.ctr.deep_pixels + fo.ctr.overflow_pixels, kCap);
     return HAIR_OK;
 }
 
@@ -972,6 +983,7 @@ int hair_debug_fragments(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t leve
         }
     }
     if (fo.ctr.overflow_pixels) return fail(HAIR_ERANGE, "%u pixels exceed capacity", fo.ctr.overflow_pixels);
+    (void)0;
     return HAIR_OK;
 }
 

@@ -90,7 +90,7 @@ struct Counters {
     uint32_t overflow_pixels;
     uint32_t max_hw_bits;    // float bits of the largest visible half-width (non-negative)
     uint32_t list_overflow;  // tiles whose list exceeded the 24-bit local index
-    uint32_t pad;
+    uint32_t deep_pixels;    // pixels deeper than one LDS batch (rendered in depth-key slices)
     unsigned long long phase[8];  // per-phase cycle sums (instrumented builds only)
 };
 

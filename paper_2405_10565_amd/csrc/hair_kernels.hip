@@ -675,7 +675,7 @@ __global__ __launch_bounds__(kNT) void k_tile_prep(FrameBufs f) {
         }
         f.tile_nb[tile] = nb;
         if (total) atomicAdd(&f.ctr->fragments, (unsigned long long)total);
-        if (over) atomicAdd(&f.ctr->overflow_pixels, over);
+        if (over) atomicAdd(&f.ctr->deep_pixels, over);
     }
 }
 
@@ -736,45 +736,43 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam, uint32_
     PHASE_END(f.ctr, 1);
 }
 
-// One LDS batch of whole pixels: exact per-pixel order, shading, front-to-back blending.
-template <int KIND>
-__global__ __launch_bounds__(kNT) void k_batch(FrameBufs f, ShadeArgs a, float* __restrict__ rgba, DebugDump dbg,
-                                               int has_dbg) {
-    __shared__ uint32_t s_cnt[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix], s_off[kTilePix + 1];
-    __shared__ uint32_t s_tmp[kNT];
-    __shared__ __align__(16) uint2 s_B[kCap];
-    __shared__ __align__(16) uint32_t s_work[3 * kCap];   // staged records (2 words) + bucket counters, later payload
-    __shared__ float s_agg[kNT * 4];          // run aggregates (C rgb, T)
-    __shared__ uint32_t s_aggh[kNT];
-    uint2* s_A = reinterpret_cast<uint2*>(s_work);
-    uint32_t* s_bk = s_work + 2 * kCap;
-    float* s_pay = reinterpret_cast<float*>(s_work);
-    PHASE_BEGIN();
+// LDS working set of one batch.
+struct BatchLds {
+    uint32_t* s_cnt;
+    uint32_t* s_kmin;
+    uint32_t* s_kmax;
+    uint32_t* s_off;
+    uint32_t* s_tmp;
+    uint2* s_B;
+    uint2* s_A;
+    uint32_t* s_bk;
+    float* s_pay;
+    float* s_agg;
+    uint32_t* s_aggh;
+};
 
-    const uint4 br = f.batches[xcd_contiguous(blockIdx.x, gridDim.x)];
-    const int tile = (int)br.x, p0 = (int)br.y, p1 = (int)br.z;
+// Exact order, shading and blending of the Fb records staged in s_A (whole pixels whose
+// counts, key ranges and offsets are in s_cnt / s_kmin / s_kmax / s_off).  Finished pixels are
+// written to rgba, or (slice_out != nullptr, a single pixel's key slice) their (C, T) goes to
+// slice_out.  rank0 / cnt_total place a slice inside its pixel for the debug dump.
+template <int KIND>
+__device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, float* __restrict__ rgba,
+                                        const DebugDump& dbg, int has_dbg, const BatchLds& L_, const uint32_t* list,
+                                        int px0, int py0, uint32_t Fb, float* slice_out, uint32_t rank0,
+                                        uint32_t cnt_total) {
+    uint32_t* s_cnt = L_.s_cnt;
+    uint32_t* s_kmin = L_.s_kmin;
+    uint32_t* s_kmax = L_.s_kmax;
+    uint32_t* s_off = L_.s_off;
+    uint32_t* s_tmp = L_.s_tmp;
+    uint2* s_B = L_.s_B;
+    uint2* s_A = L_.s_A;
+    uint32_t* s_bk = L_.s_bk;
+    float* s_pay = L_.s_pay;
+    float* s_agg = L_.s_agg;
+    uint32_t* s_aggh = L_.s_aggh;
     const int t = threadIdx.x;
-    if (br.w) return;     // oversized pixel: counted in k_tile_prep, left transparent
-    const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
     const int W = a.cam.W, H = a.cam.H;
-    const uint32_t* list = f.list + f.tile_start[tile * kSub];
-    const size_t q = (size_t)tile * kTilePix + t;
-    const uint32_t tile_off0 = f.pix_off[(size_t)tile * kTilePix + p0];
-    if (t >= p0 && t < p1) {
-        s_cnt[t] = f.pix_cnt[q];
-        s_kmin[t] = f.pix_kmin[q];
-        s_kmax[t] = f.pix_kmax[q];
-        s_off[t] = f.pix_off[q] - tile_off0;
-    }
-    if (t == 0) s_off[p1] = (p1 < kTilePix ? f.pix_off[(size_t)tile * kTilePix + p1] : f.tile_tot[tile]) - tile_off0;
-    __syncthreads();
-    const uint32_t Fb = s_off[p1];
-    const uint2* src = f.frags + f.frag_base[tile] + tile_off0;
-    for (uint32_t i = t; i < Fb; i += kNT) {
-        s_A[i] = src[i];
-        s_bk[i] = 0;
-    }
-    __syncthreads();
     // ---- bucket sort: bucket = linear key range of the fragment's pixel
     uint32_t my_b[kPerThread], my_r[kPerThread];
 #pragma unroll
@@ -836,7 +834,6 @@ __global__ __launch_bounds__(kNT) void k_batch(FrameBufs f, ShadeArgs a, float* 
         }
     }
     __syncthreads();
-    PHASE_END(f.ctr, 2);
     // ---- shade: one lane per fragment, payload alpha * L and (1 - alpha)
     for (uint32_t i = t; i < Fb; i += kNT) {
         const uint2 rec = s_B[i];
@@ -852,9 +849,9 @@ __global__ __launch_bounds__(kNT) void k_batch(FrameBufs f, ShadeArgs a, float* 
         if (has_dbg) {
             const int dx = gx - dbg.x0, dy = gy - dbg.y0;
             if (dx >= 0 && dy >= 0 && dx < dbg.w && dy < dbg.h) {
-                const uint32_t rank = i - s_off[p];
+                const uint32_t rank = i - s_off[p] + rank0;
                 const int q2 = dy * dbg.w + dx;
-                if (rank == 0) dbg.counts[q2] = s_cnt[p];
+                if (rank == 0) dbg.counts[q2] = cnt_total ? cnt_total : s_cnt[p];
                 if ((int)rank < dbg.stride) {
                     const size_t o = (size_t)q2 * dbg.stride + rank;
                     dbg.keys[o] = rec.x;
@@ -866,7 +863,6 @@ __global__ __launch_bounds__(kNT) void k_batch(FrameBufs f, ShadeArgs a, float* 
         }
     }
     __syncthreads();
-    PHASE_END(f.ctr, 3);
     // ---- blend: segmented scan of (C, T) over runs of consecutive fragments
     const uint32_t run = (Fb + kNT - 1) / kNT;
     const uint32_t rb = min(Fb, t * run), re = min(Fb, rb + run);
@@ -914,14 +910,146 @@ __global__ __launch_bounds__(kNT) void k_batch(FrameBufs f, ShadeArgs a, float* 
         C2 += T * s_pay[3 * i + 2];
         T *= __uint_as_float(s_B[i].x);
         if (i + 1 == s_off[p] + s_cnt[p]) {
-            const int gx = px0 + (int)(p % kTile), gy = py0 + (int)(p / kTile);
-            if (gx < W && gy < H) {
-                float4* o = reinterpret_cast<float4*>(rgba) + ((size_t)gy * W + gx);
-                *o = make_float4(C0, C1, C2, 1.0f - T);
+            if (slice_out) {
+                slice_out[0] = C0; slice_out[1] = C1; slice_out[2] = C2; slice_out[3] = T;
+            } else {
+                const int gx = px0 + (int)(p % kTile), gy = py0 + (int)(p / kTile);
+                if (gx < W && gy < H) {
+                    float4* o = reinterpret_cast<float4*>(rgba) + ((size_t)gy * W + gx);
+                    *o = make_float4(C0, C1, C2, 1.0f - T);
+                }
             }
         }
     }
-    PHASE_END(f.ctr, 4);
+}
+
+// One LDS batch of whole pixels: exact per-pixel order, shading, front-to-back blending.  A
+// pixel deeper than one batch (its own "oversized" batch) is processed in depth-key slices:
+// a histogram over the pixel's key range picks the longest run of bins that fits LDS, those
+// records are gathered and processed exactly, and the slice composites chain front to back.
+template <int KIND>
+__global__ __launch_bounds__(kNT) void k_batch(FrameBufs f, ShadeArgs a, float* __restrict__ rgba, DebugDump dbg,
+                                               int has_dbg) {
+    __shared__ uint32_t s_cnt[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix], s_off[kTilePix + 1];
+    __shared__ uint32_t s_tmp[kNT];
+    __shared__ __align__(16) uint2 s_B[kCap];
+    __shared__ __align__(16) uint32_t s_work[3 * kCap];   // staged records (2 words) + bucket counters, later payload
+    __shared__ float s_agg[kNT * 4];          // run aggregates (C rgb, T)
+    __shared__ uint32_t s_aggh[kNT];
+    __shared__ float s_slice[4];
+    __shared__ unsigned long long s_range[2];
+    __shared__ uint32_t s_slot, s_flag;
+    BatchLds L_{s_cnt, s_kmin, s_kmax, s_off, s_tmp, s_B, reinterpret_cast<uint2*>(s_work), s_work + 2 * kCap,
+                reinterpret_cast<float*>(s_work), s_agg, s_aggh};
+    PHASE_BEGIN();
+
+    const uint4 br = f.batches[xcd_contiguous(blockIdx.x, gridDim.x)];
+    const int tile = (int)br.x, p0 = (int)br.y, p1 = (int)br.z;
+    const int t = threadIdx.x;
+    const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
+    const int W = a.cam.W, H = a.cam.H;
+    const uint32_t* list = f.list + f.tile_start[tile * kSub];
+    const size_t q = (size_t)tile * kTilePix + t;
+    const uint32_t tile_off0 = f.pix_off[(size_t)tile * kTilePix + p0];
+    const uint2* src = f.frags + f.frag_base[tile] + tile_off0;
+    if (!br.w) {
+        if (t >= p0 && t < p1) {
+            s_cnt[t] = f.pix_cnt[q];
+            s_kmin[t] = f.pix_kmin[q];
+            s_kmax[t] = f.pix_kmax[q];
+            s_off[t] = f.pix_off[q] - tile_off0;
+        }
+        if (t == 0) s_off[p1] = (p1 < kTilePix ? f.pix_off[(size_t)tile * kTilePix + p1] : f.tile_tot[tile]) - tile_off0;
+        __syncthreads();
+        const uint32_t Fb = s_off[p1];
+        for (uint32_t i = t; i < Fb; i += kNT) {
+            L_.s_A[i] = src[i];
+            L_.s_bk[i] = 0;
+        }
+        __syncthreads();
+        sort_shade_blend<KIND>(f, a, rgba, dbg, has_dbg, L_, list, px0, py0, Fb, nullptr, 0, 0);
+        PHASE_END(f.ctr, 4);
+        return;
+    }
+    // ---- a pixel deeper than one batch: exact depth-key slices
+    const int p = p0;
+    const size_t qp = (size_t)tile * kTilePix + p;
+    const uint32_t k = f.pix_cnt[qp];
+    const unsigned long long key_end = (unsigned long long)f.pix_kmax[qp] + 1ull;
+    unsigned long long lo = f.pix_kmin[qp];
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;   // carried composite (thread 0)
+    uint32_t done = 0;
+    constexpr uint32_t kBins = kCap;            // histogram in s_bk
+    while (lo < key_end) {
+        unsigned long long range_hi = key_end;
+        // refine until a run of whole bins starting at lo fits one batch
+        while (true) {
+            const unsigned long long width = (range_hi - lo + kBins - 1) / kBins;
+            for (uint32_t i = t; i < kBins; i += kNT) L_.s_bk[i] = 0;
+            __syncthreads();
+            for (uint32_t i = t; i < k; i += kNT) {
+                const unsigned long long key = src[i].x;
+                if (key >= lo && key < range_hi) atomicAdd(&L_.s_bk[(uint32_t)((key - lo) / width)], 1u);
+            }
+            __syncthreads();
+            if (t == 0) {
+                uint32_t acc = 0, nb = 0;
+                const uint32_t used = (uint32_t)((range_hi - lo + width - 1) / width);
+                while (nb < used && acc + L_.s_bk[nb] <= (uint32_t)kCap) acc += L_.s_bk[nb++];
+                if (nb == 0) {
+                    s_flag = width == 1 ? 2u : 1u;     // 1: refine inside the first bin; 2: equal keys overflow
+                    s_range[1] = lo + width;
+                } else {
+                    s_flag = 0;
+                    s_range[1] = min(range_hi, lo + (unsigned long long)nb * width);
+                    s_slot = acc;
+                }
+            }
+            __syncthreads();
+            const uint32_t flag = s_flag;
+            range_hi = s_range[1];
+            __syncthreads();
+            if (flag == 0) break;
+            if (flag == 2) {   // more than kCap fragments share one depth key: unsupported
+                if (t == 0) atomicAdd(&f.ctr->overflow_pixels, 1u);
+                return;
+            }
+        }
+        const uint32_t Fb = s_slot;
+        __syncthreads();
+        if (t == 0) s_slot = 0;
+        __syncthreads();
+        for (uint32_t i = t; i < k; i += kNT) {
+            const uint2 rec = src[i];
+            if ((unsigned long long)rec.x >= lo && (unsigned long long)rec.x < range_hi)
+                L_.s_A[atomicAdd(&s_slot, 1u)] = rec;
+        }
+        __syncthreads();
+        for (uint32_t i = t; i < Fb; i += kNT) L_.s_bk[i] = 0;
+        if (t == 0) {
+            s_cnt[p] = Fb;
+            s_kmin[p] = (uint32_t)lo;
+            s_kmax[p] = (uint32_t)(range_hi - 1);
+            s_off[p] = 0;
+            s_off[p + 1] = Fb;
+        }
+        __syncthreads();
+        sort_shade_blend<KIND>(f, a, rgba, dbg, has_dbg, L_, list, px0, py0, Fb, s_slice, done, k);
+        __syncthreads();
+        if (t == 0) {
+            C0 += T * s_slice[0];
+            C1 += T * s_slice[1];
+            C2 += T * s_slice[2];
+            T *= s_slice[3];
+        }
+        done += Fb;
+        lo = range_hi;
+        __syncthreads();
+    }
+    if (t == 0) {
+        const int gx = px0 + (p % kTile), gy = py0 + (p / kTile);
+        if (gx < W && gy < H) reinterpret_cast<float4*>(rgba)[(size_t)gy * W + gx] = make_float4(C0, C1, C2, 1.0f - T);
+    }
 }
 
 // ---------------------------------------------------------------------------------------

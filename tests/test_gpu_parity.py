@@ -270,3 +270,20 @@ def test_config2_full_size_sampled(hip, ctx):
         ref, ras = R.render(geom, cam, lights, mat, rect=(x0, y0, 24, 24))
         assert_radiance(got[y0:y0 + 24, x0:x0 + 24], ref[y0:y0 + 24, x0:x0 + 24], what=f"config 2 rect {x0},{y0}")
     ws.close()
+
+
+def test_pixels_deeper_than_one_batch(hip, ctx):
+    """A dense asset seen small: pixels hold more fragments than one LDS batch (2048) and are
+    rendered in exact depth-key slices; radiance and count still match the oracle."""
+    print("case: deep pixels", flush=True)
+    asset = hs.make_asset(12000, 16, 60.0, seed=31)
+    cam = hs.camera_for(asset, 40, 40, fill=0.5)
+    lights = hs.default_lights(asset, with_point=True)
+    ref, ras = R.render(R.strand_level(asset), cam, lights, mat_of(asset))
+    depth = np.bincount(ras.pix, minlength=cam.width * cam.height)
+    assert depth.max() > 2048, depth.max()          # at least two key slices
+    aid, ws, img, stats = _render(hip, ctx, asset, cam, lights)
+    assert stats["fragments"] == len(ras.seg)
+    assert stats["deep_pixels"] == int((depth > 2048).sum()) and stats["overflow_pixels"] == 0
+    assert_radiance(img, ref, what="deep pixels")
+    ws.close()
