@@ -224,12 +224,22 @@ LightsConst lights_const(const hair_light* l, int n) {
 MatConst mat_const(const hair_material& m) {
     MatConst k;
     k.eta = m.eta;
+    k.inv_eta2 = (float)(1.0 / ((double)m.eta * (double)m.eta));
     k.alpha_p[0] = m.alpha; k.alpha_p[1] = -0.5f * m.alpha; k.alpha_p[2] = -1.5f * m.alpha;
     k.beta_p[0] = m.beta_m; k.beta_p[1] = 0.5f * m.beta_m; k.beta_p[2] = 2.0f * m.beta_m;
+    for (int p = 0; p < 3; ++p) {
+        const double b = k.beta_p[p];
+        k.g_amp[p] = (float)(0.5 / (b * std::sqrt(2.0 * M_PI)));
+        k.g_k[p] = (float)(1.0 / (2.0 * b * b));
+    }
     k.beta_n = m.beta_n;
     const double s = std::sqrt(3.0) * (double)m.beta_n / M_PI;
     k.s = (float)s;
-    k.inv_tanh = (float)(1.0 / std::tanh(M_PI / (2.0 * s)));
+    k.inv_s = (float)(1.0 / s);
+    k.n_norm = (float)(1.0 / (s * std::tanh(M_PI / (2.0 * s))));
+    const double lo = 1.0 / (1.0 + std::exp(M_PI / s)), hi = 1.0 / (1.0 + std::exp(-M_PI / s));
+    k.cdf_lo = (float)lo;
+    k.cdf_scale = (float)(1.0 / (hi - lo));
     return k;
 }
 

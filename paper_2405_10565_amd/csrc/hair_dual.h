@@ -98,6 +98,10 @@ template <int N> __device__ inline Dual<N> m_asin(const Dual<N>& x) {
     const float c = sqrtf(fmaxf((1.0f - x.v) * (1.0f + x.v), 0.0f));
     return chain(x, asinf(x.v), c > 0.0f ? 1.0f / c : 0.0f);
 }
+template <int N> __device__ inline Dual<N> m_rcp(const Dual<N>& x) {
+    const float r = 1.0f / x.v;
+    return chain(x, r, -r * r);
+}
 template <int N> __device__ inline Dual<N> m_sin(const Dual<N>& x) { return chain(x, sinf(x.v), cosf(x.v)); }
 template <int N> __device__ inline Dual<N> m_cos(const Dual<N>& x) { return chain(x, cosf(x.v), -sinf(x.v)); }
 template <int N> __device__ inline Dual<N> m_tanh(const Dual<N>& x) {

@@ -58,11 +58,16 @@ struct LightsConst {
 // Material constants derived on the host from hair_material (Sec. 6 parameters).
 struct MatConst {
     float eta;
+    float inv_eta2;          // 1 / eta^2
     float alpha_p[3];        // longitudinal shifts of R, TT, TRT
     float beta_p[3];         // longitudinal standard deviations of R, TT, TRT
+    float g_amp[3];          // M_p = g_amp exp(-g_k x^2): 1 / (2 beta_p sqrt(2 pi))
+    float g_k[3];            //                            1 / (2 beta_p^2)
     float beta_n;            // azimuthal standard deviation
     float s;                 // logistic scale sqrt(3) beta_n / pi
-    float inv_tanh;          // 1 / tanh(pi / 2s): trimmed-logistic normaliser
+    float inv_s;             // 1 / s
+    float n_norm;            // trimmed-logistic normaliser 1 / (s tanh(pi / 2s))
+    float cdf_lo, cdf_scale; // trimmed CDF: (sigmoid(x / s) - cdf_lo) * cdf_scale on [-pi, pi]
 };
 
 // One renderable level, device pointers.

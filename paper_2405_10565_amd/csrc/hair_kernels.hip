@@ -416,10 +416,12 @@ template <int KIND, class T>
 __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const float4& q0, const float4& q1,
                                   const float4& q2, float n_total, int pxg, int pyg, const T& hw, const T& a_len,
                                   const T& b_len, const T& rr, const T sig[3], T& alpha, T& hoff, T L[3]) {
-    const long long ex = 16LL * pxg + 8 - s.xa, ey = 16LL * pyg + 8 - s.ya;
-    const long long dx = (long long)s.xb - s.xa, dy = (long long)s.yb - s.ya;
-    const long long tnum = ex * dx + ey * dy, tden = dx * dx + dy * dy;
-    const long long cr = ex * dy - ey * dx;
+    // integer coverage geometry; 32 bits suffice because a covered pixel centre lies within
+    // the segment's box widened by its radius and longer segments (kMaxAxis) are culled
+    const int ex = 16 * pxg + 8 - s.xa, ey = 16 * pyg + 8 - s.ya;
+    const int dx = s.xb - s.xa, dy = s.yb - s.ya;
+    const int tnum = ex * dx + ey * dy, tden = dx * dx + dy * dy;
+    const int cr = ex * dy - ey * dx;
     const float t = (float)tnum / (float)tden;
     const float iz = s.iza + t * (s.izb - s.iza);
     const float delta = fabsf((float)cr) / sqrtf((float)tden) * (1.0f / 16.0f);
@@ -430,37 +432,43 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
     hoff = h;
     const float tw = t * s.izb / iz;
 
+    // fibre frame at the fragment's world point
     const V3<float> pA = v3(q0.x, q0.y, q0.z);
-    const V3<float> pB = v3(q1.x, q1.y, q1.z);
-    const V3<float> d = sub(pB, pA);
-    const V3<float> u = scale(d, 1.0f / sqrtf(dot(d, d)));
+    const V3<float> d = sub(v3(q1.x, q1.y, q1.z), pA);
+    const V3<float> u = scale(d, m_rsqrt(dot(d, d)));
     const V3<float> xw = v3(pA.x + tw * d.x, pA.y + tw * d.y, pA.z + tw * d.z);
     V3<float> wo = sub(v3(a.cam.pos[0], a.cam.pos[1], a.cam.pos[2]), xw);
-    wo = scale(wo, 1.0f / sqrtf(dot(wo, wo)));
-    const float sin_to = dot(wo, u);
-    V3<float> wp = sub(wo, scale(u, sin_to));
-    float wpn = sqrtf(dot(wp, wp));
-    const bool degen = wpn < 1e-7f;
-    if (degen) {  // view along the fibre: any normal direction; phi is set to 0 below
+    wo = scale(wo, m_rsqrt(dot(wo, wo)));
+    const float dwu = dot(wo, u);
+    V3<float> wp = sub(wo, scale(u, dwu));
+    float wpn2 = dot(wp, wp);
+    const bool degen = wpn2 < 1e-14f;
+    if (degen) {  // view along the fibre: any normal direction; phi is set to 0
         const float ax = fabsf(u.x), ay = fabsf(u.y), az = fabsf(u.z);
         V3<float> e = (ax <= ay && ax <= az) ? v3(1.f, 0.f, 0.f) : (ay <= az ? v3(0.f, 1.f, 0.f) : v3(0.f, 0.f, 1.f));
         wp = sub(e, scale(u, dot(e, u)));
-        wpn = sqrtf(dot(wp, wp));
+        wpn2 = dot(wp, wp);
     }
-    const V3<float> xh = scale(wp, 1.0f / wpn);
+    const V3<float> xh = scale(wp, m_rsqrt(wpn2));
     const V3<float> yh = cross(u, xh);
-    const float to = asinf(fminf(fmaxf(sin_to, -1.0f), 1.0f));
+    const float sin_to = fminf(fmaxf(dwu, -1.0f), 1.0f);
+    const float to = m_asin(sin_to);
+    const float cos_to = m_sqrt((1.0f - sin_to) * (1.0f + sin_to));
+    const T gamma_o = m_asin(h);
+    const T cgo = m_sqrt((1.0f - h) * (1.0f + h));
 
     ClusterFrag<T> cf;
-    T W;
+    T W, ia, ib;
     V3<float> ah{}, bh{};
     if (KIND == 1) {
         ah = v3(q2.x, q2.y, q2.z);
         bh = cross(u, ah);
         const T pa = a_len * dot(ah, yh), pb = b_len * dot(bh, yh);
         W = m_sqrt(pa * pa + pb * pb);
+        ia = m_rcp(a_len);
+        ib = m_rcp(b_len);
         cf.n_total = T(n_total);
-        cf.rho = m_min(m_max(n_total * rr * rr / (a_len * b_len), T(0.0f)), T(1.0f));
+        cf.rho = m_min(m_max(n_total * rr * rr * (ia * ib), T(0.0f)), T(1.0f));
     }
     L[0] = L[1] = L[2] = T(0.0f);
     for (int li = 0; li < a.lights.n; ++li) {
@@ -472,47 +480,42 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
             E[0] = lc.rgb[0]; E[1] = lc.rgb[1]; E[2] = lc.rgb[2];
         } else {
             const V3<float> dl = sub(v3(lc.vec[0], lc.vec[1], lc.vec[2]), xw);
-            const float d2 = dot(dl, dl);
-            wi = scale(dl, 1.0f / sqrtf(d2));
-            E[0] = lc.rgb[0] / d2; E[1] = lc.rgb[1] / d2; E[2] = lc.rgb[2] / d2;
+            const float inv = m_rsqrt(dot(dl, dl));
+            wi = scale(dl, inv);
+            const float i2 = inv * inv;
+            E[0] = lc.rgb[0] * i2; E[1] = lc.rgb[1] * i2; E[2] = lc.rgb[2] * i2;
         }
         const float sin_ti = dot(wi, u);
-        float phi = -atan2f(dot(wi, yh), dot(wi, xh));
-        if (degen) phi = 0.0f;
-        const float sc = fminf(fmaxf(sin_ti, -1.0f), 1.0f);
-        const float ti = asinf(sc);
-        const float th = 0.5f * (ti + to);
-        const float xd = 0.5f * fabsf(ti - to);
-        const float cos_ti = sqrtf((1.0f - sc) * (1.0f + sc));
+        const LightView v = light_view(sin_ti, sin_to, to, cos_to, dot(wi, xh), dot(wi, yh), degen, a.mat);
         T f[3];
         if (KIND == 0) {
-            f_single(T(th), T(xd), T(phi), h, sig, a.mat, f);
+            f_single(v, h, gamma_o, cgo, sig, a.mat, f);
         } else {
             // chord of the view ray's entry point toward the light, in the cross-section
             const V3<float> Dp = sub(wi, scale(u, sin_ti));
-            const float dn = sqrtf(dot(Dp, Dp));
+            const float dn2 = dot(Dp, Dp);
             T s_star(0.0f);
-            if (dn > 1e-7f) {
-                const V3<float> D = scale(Dp, 1.0f / dn);
-                const T oa = h * W * dot(yh, ah) / a_len, ob = h * W * dot(yh, bh) / b_len;
-                const T xa = dot(xh, ah) / a_len, xb = dot(xh, bh) / b_len;
+            if (dn2 > 1e-14f) {
+                const V3<float> D = scale(Dp, m_rsqrt(dn2));
+                const T oa = h * W * dot(yh, ah) * ia, ob = h * W * dot(yh, bh) * ib;
+                const T xa = dot(xh, ah) * ia, xb = dot(xh, bh) * ib;
                 const T qa = xa * xa + xb * xb, qb = oa * xa + ob * xb, qc = oa * oa + ob * ob - 1.0f;
                 const T disc = m_max(qb * qb - qa * qc, T(0.0f));
-                const T tt = (qb - m_sqrt(disc)) / qa;
+                const T tt = (qb - m_sqrt(disc)) * m_rcp(qa);
                 const T Pa = oa - tt * xa, Pb = ob - tt * xb;
-                const T Da = dot(D, ah) / a_len, Db = dot(D, bh) / b_len;
-                s_star = -2.0f * (Pa * Da + Pb * Db) / (Da * Da + Db * Db);
+                const T Da = dot(D, ah) * ia, Db = dot(D, bh) * ib;
+                s_star = -2.0f * (Pa * Da + Pb * Db) * m_rcp(Da * Da + Db * Db);
             }
-            const T kappa = m_sqrt(n_total / (kPi * a_len * b_len));
+            const T kappa = m_sqrt(n_total * (1.0f / kPi) * (ia * ib));
             const T lF = m_max(s_star, T(0.0f)), lB = m_max(-s_star, T(0.0f));
-            const bool back = fabsf(phi) < 0.5f * kPi;
+            const bool back = fabsf(v.phi) < 0.5f * kPi;
             cf.n_F = (back || n_total < 2.0f) ? T(1.0f) : m_max(cf.rho * kappa * lF, T(1.0f));
             cf.n_B = m_max(cf.rho * kappa * lB, T(1.0f));
-            f_ours(T(th), T(xd), T(phi), h, sig, a.mat, cf, f);
+            f_ours(v, h, gamma_o, cgo, sig, a.mat, cf, f);
         }
-        L[0] = L[0] + (E[0] * cos_ti) * f[0];
-        L[1] = L[1] + (E[1] * cos_ti) * f[1];
-        L[2] = L[2] + (E[2] * cos_ti) * f[2];
+        L[0] = L[0] + (E[0] * v.cos_ti) * f[0];
+        L[1] = L[1] + (E[1] * v.cos_ti) * f[1];
+        L[2] = L[2] + (E[2] * v.cos_ti) * f[2];
     }
 }
 
@@ -736,6 +739,76 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam, uint32_
     PHASE_END(f.ctr, 1);
 }
 
+// Exact per-pixel order of the Fb records in s_A (whole pixels with counts, key ranges and
+// offsets in s_cnt / s_kmin / s_kmax / s_off) into s_B: bucket sort with one bucket per record,
+// bucket = the record's place in its pixel's linear key range (a monotone map, so sorted
+// buckets give sorted pixels), then insertion sort inside each bucket by (key, segment id).
+// s_bk must hold Fb zeros on entry.  Ends with a barrier.
+__device__ inline void order_batch(uint32_t Fb, const uint32_t* s_cnt, const uint32_t* s_kmin, const uint32_t* s_kmax,
+                                   const uint32_t* s_off, uint32_t* s_tmp, const uint2* s_A, uint2* s_B,
+                                   uint32_t* s_bk, const uint32_t* list) {
+    const int t = threadIdx.x;
+    uint32_t my_b[kPerThread], my_r[kPerThread];
+#pragma unroll
+    for (int qq = 0; qq < kPerThread; ++qq) {
+        const uint32_t i = t + qq * kNT;
+        if (i < Fb) {
+            const uint2 rec = s_A[i];
+            const uint32_t p = rec.y >> 24;
+            const uint32_t kmn = s_kmin[p], cnt = s_cnt[p];
+            const float scale = (float)cnt * __builtin_amdgcn_rcpf((float)(s_kmax[p] - kmn) + 1.0f);
+            const uint32_t bucket = min(cnt - 1u, (uint32_t)((float)(rec.x - kmn) * scale));
+            my_b[qq] = s_off[p] + bucket;
+            my_r[qq] = atomicAdd(&s_bk[my_b[qq]], 1u);
+        }
+    }
+    __syncthreads();
+    {   // exclusive scan of the bucket counters, kPerThread consecutive per thread
+        uint32_t loc[kPerThread];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int qq = 0; qq < kPerThread; ++qq) {
+            const uint32_t i = t * kPerThread + qq;
+            loc[qq] = i < Fb ? s_bk[i] : 0u;
+            sum += loc[qq];
+        }
+        uint32_t ex;
+        block_exscan_u32(sum, s_tmp, ex);
+#pragma unroll
+        for (int qq = 0; qq < kPerThread; ++qq) {
+            const uint32_t i = t * kPerThread + qq;
+            if (i < Fb) s_bk[i] = ex;
+            ex += loc[qq];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int qq = 0; qq < kPerThread; ++qq) {
+        const uint32_t i = t + qq * kNT;
+        if (i < Fb) s_B[s_bk[my_b[qq]] + my_r[qq]] = s_A[i];
+    }
+    __syncthreads();
+    for (uint32_t bi = t; bi < Fb; bi += kNT) {
+        const uint32_t b0 = s_bk[bi];
+        const uint32_t b1 = bi + 1 < Fb ? s_bk[bi + 1] : Fb;
+        for (uint32_t i = b0 + 1; i < b1; ++i) {
+            const uint2 v = s_B[i];
+            const uint32_t vseg = list[v.y & 0xFFFFFFu];
+            uint32_t jx = i;
+            while (jx > b0) {
+                const uint2 u2 = s_B[jx - 1];
+                bool greater = u2.x > v.x;
+                if (u2.x == v.x) greater = list[u2.y & 0xFFFFFFu] > vseg;
+                if (!greater) break;
+                s_B[jx] = u2;
+                --jx;
+            }
+            s_B[jx] = v;
+        }
+    }
+    __syncthreads();
+}
+
 // LDS working set of one batch.
 struct BatchLds {
     uint32_t* s_cnt;
@@ -773,67 +846,7 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
     uint32_t* s_aggh = L_.s_aggh;
     const int t = threadIdx.x;
     const int W = a.cam.W, H = a.cam.H;
-    // ---- bucket sort: bucket = linear key range of the fragment's pixel
-    uint32_t my_b[kPerThread], my_r[kPerThread];
-#pragma unroll
-    for (int qq = 0; qq < kPerThread; ++qq) {
-        const uint32_t i = t + qq * kNT;
-        if (i < Fb) {
-            const uint2 rec = s_A[i];
-            const uint32_t p = rec.y >> 24;
-            const uint32_t kmn = s_kmin[p];
-            const unsigned long long span = (unsigned long long)(s_kmax[p] - kmn) + 1ull;
-            const uint32_t bucket = (uint32_t)(((unsigned long long)(rec.x - kmn) * s_cnt[p]) / span);
-            my_b[qq] = s_off[p] + bucket;
-            my_r[qq] = atomicAdd(&s_bk[my_b[qq]], 1u);
-        }
-    }
-    __syncthreads();
-    {   // exclusive scan of the bucket counters, kPerThread consecutive per thread
-        uint32_t loc[kPerThread];
-        uint32_t sum = 0;
-#pragma unroll
-        for (int qq = 0; qq < kPerThread; ++qq) {
-            const uint32_t i = t * kPerThread + qq;
-            loc[qq] = i < Fb ? s_bk[i] : 0u;
-            sum += loc[qq];
-        }
-        uint32_t ex;
-        block_exscan_u32(sum, s_tmp, ex);
-#pragma unroll
-        for (int qq = 0; qq < kPerThread; ++qq) {
-            const uint32_t i = t * kPerThread + qq;
-            if (i < Fb) s_bk[i] = ex;
-            ex += loc[qq];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int qq = 0; qq < kPerThread; ++qq) {
-        const uint32_t i = t + qq * kNT;
-        if (i < Fb) s_B[s_bk[my_b[qq]] + my_r[qq]] = s_A[i];
-    }
-    __syncthreads();
-    // insertion sort inside each bucket by (key, segment id)
-    for (uint32_t bi = t; bi < Fb; bi += kNT) {
-        const uint32_t b0 = s_bk[bi];
-        const uint32_t b1 = bi + 1 < Fb ? s_bk[bi + 1] : Fb;
-        for (uint32_t i = b0 + 1; i < b1; ++i) {
-            const uint2 v = s_B[i];
-            const uint32_t vseg = list[v.y & 0xFFFFFFu];
-            uint32_t jx = i;
-            while (jx > b0) {
-                const uint2 u2 = s_B[jx - 1];
-                bool greater = u2.x > v.x;
-                if (u2.x == v.x) greater = list[u2.y & 0xFFFFFFu] > vseg;
-                if (!greater) break;
-                s_B[jx] = u2;
-                --jx;
-            }
-            s_B[jx] = v;
-        }
-    }
-    __syncthreads();
+    order_batch(Fb, s_cnt, s_kmin, s_kmax, s_off, s_tmp, s_A, s_B, s_bk, list);
     // ---- shade: one lane per fragment, payload alpha * L and (1 - alpha)
     for (uint32_t i = t; i < Fb; i += kNT) {
         const uint2 rec = s_B[i];
@@ -1143,65 +1156,7 @@ __global__ __launch_bounds__(kNT) void k_batch_bwd(FrameBufs f, ShadeArgs a, Gra
         s_bk[i] = 0;
     }
     __syncthreads();
-    uint32_t my_b[kPerThread], my_r[kPerThread];
-#pragma unroll
-    for (int qq = 0; qq < kPerThread; ++qq) {
-        const uint32_t i = t + qq * kNT;
-        if (i < Fb) {
-            const uint2 rec = s_A[i];
-            const uint32_t p = rec.y >> 24;
-            const uint32_t kmn = s_kmin[p];
-            const unsigned long long span = (unsigned long long)(s_kmax[p] - kmn) + 1ull;
-            const uint32_t bucket = (uint32_t)(((unsigned long long)(rec.x - kmn) * s_cnt[p]) / span);
-            my_b[qq] = s_off[p] + bucket;
-            my_r[qq] = atomicAdd(&s_bk[my_b[qq]], 1u);
-        }
-    }
-    __syncthreads();
-    {
-        uint32_t loc[kPerThread];
-        uint32_t sum = 0;
-#pragma unroll
-        for (int qq = 0; qq < kPerThread; ++qq) {
-            const uint32_t i = t * kPerThread + qq;
-            loc[qq] = i < Fb ? s_bk[i] : 0u;
-            sum += loc[qq];
-        }
-        uint32_t ex;
-        block_exscan_u32(sum, s_tmp, ex);
-#pragma unroll
-        for (int qq = 0; qq < kPerThread; ++qq) {
-            const uint32_t i = t * kPerThread + qq;
-            if (i < Fb) s_bk[i] = ex;
-            ex += loc[qq];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int qq = 0; qq < kPerThread; ++qq) {
-        const uint32_t i = t + qq * kNT;
-        if (i < Fb) s_B[s_bk[my_b[qq]] + my_r[qq]] = s_A[i];
-    }
-    __syncthreads();
-    for (uint32_t bi = t; bi < Fb; bi += kNT) {
-        const uint32_t b0 = s_bk[bi];
-        const uint32_t b1 = bi + 1 < Fb ? s_bk[bi + 1] : Fb;
-        for (uint32_t i = b0 + 1; i < b1; ++i) {
-            const uint2 v = s_B[i];
-            const uint32_t vseg = list[v.y & 0xFFFFFFu];
-            uint32_t jx = i;
-            while (jx > b0) {
-                const uint2 u2 = s_B[jx - 1];
-                bool greater = u2.x > v.x;
-                if (u2.x == v.x) greater = list[u2.y & 0xFFFFFFu] > vseg;
-                if (!greater) break;
-                s_B[jx] = u2;
-                --jx;
-            }
-            s_B[jx] = v;
-        }
-    }
-    __syncthreads();
+    order_batch(Fb, s_cnt, s_kmin, s_kmax, s_off, s_tmp, s_A, s_B, s_bk, list);
     // ---- 2. alpha and L per fragment (float)
     for (uint32_t i = t; i < Fb; i += kNT) {
         const uint2 rec = s_B[i];

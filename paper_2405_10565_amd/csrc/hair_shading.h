@@ -17,41 +17,77 @@
 // |phi| < pi/2, A_B = A_1+ + A_1 + A_3 with d_1+ = 0.6, N_B = [|phi| < pi/2] / pi,
 // S = P_s a_F + max(0, 1 - P_m - P_s) for |phi| < pi/2 with c_m = 0.2, and n = 1 for
 // |phi| < pi/2 or a single-hair cluster.
+//
+// Float arithmetic: the scattering terms use the hardware exp2 / reciprocal / square-root
+// instructions and fitted polynomials for arcsine and arctangent (coefficients and error
+// bounds in hair_fastmath_coef.h); every such step is within a few float32 ulps, far inside the
+// renderer's radiance tolerance.  The view angles enter through sin / cos products (x_d from
+// cos(theta_i - theta_o) by the half-angle identities), so no trigonometric call remains.
 #pragma once
 
 #include "hair_internal.h"
+#include "hair_fastmath_coef.h"
 
 namespace hair {
 
 constexpr float kPi = 3.14159265358979323846f;
+constexpr float kHalfPi = 1.57079632679489661923f;
 constexpr float kTwoPi = 6.28318530717958647692f;
+constexpr float kInvTwoPi = 0.15915494309189533577f;
 constexpr float kInvSqrt2Pi = 0.39894228040143267794f;
+constexpr float kLog2e = 1.44269504088896340736f;
 constexpr float kSqrt3 = 1.73205080756887729353f;
 constexpr float kD1Plus = 0.6f;     // Sec. 4, A_1+ path-series constant
 constexpr float kCm = 0.2f;         // Sec. 4, multiple-hair shadowing constant
 
-// 8-point Gauss-Legendre rule on [-1, 1] (standard published nodes and weights).
-__constant__ static const float kGLx[8] = {-0.9602898564975363f, -0.7966664774136267f, -0.5255324099163290f,
-                                           -0.1834346424956498f, 0.1834346424956498f,  0.5255324099163290f,
-                                           0.7966664774136267f,  0.9602898564975363f};
-__constant__ static const float kGLw[8] = {0.1012285362903763f, 0.2223810344533745f, 0.3137066458778873f,
-                                           0.3626837833783620f, 0.3626837833783620f, 0.3137066458778873f,
-                                           0.2223810344533745f, 0.1012285362903763f};
+// ---- float function set; the dual-number type provides the same names ----
+__device__ inline float m_exp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
+__device__ inline float m_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline float m_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline float m_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// ---- scalar function set; the dual-number type provides the same names ----
-__device__ inline float m_exp(float x) { return expf(x); }
-__device__ inline float m_sqrt(float x) { return sqrtf(x); }
-__device__ inline float m_asin(float x) { return asinf(x); }
-__device__ inline float m_atan2(float y, float x) { return atan2f(y, x); }
-__device__ inline float m_sin(float x) { return sinf(x); }
-__device__ inline float m_cos(float x) { return cosf(x); }
+// arcsine on [-1, 1]: polynomial on [0, 1/2], asin(x) = pi/2 - 2 asin(sqrt((1 - x) / 2)) above
+__device__ inline float m_asin(float x) {
+    const float ax = fabsf(x);
+    const bool big = ax > 0.5f;
+    const float t = big ? 0.5f * (1.0f - ax) : ax * ax;
+    const float z = big ? __builtin_amdgcn_sqrtf(t) : ax;
+    float p = kAsinP[4];
+    p = p * t + kAsinP[3];
+    p = p * t + kAsinP[2];
+    p = p * t + kAsinP[1];
+    p = p * t + kAsinP[0];
+    float r = z + (z * t) * p;
+    r = big ? kHalfPi - 2.0f * r : r;
+    return copysignf(r, x);
+}
+
+// atan2 by octant reduction to atan(a), a in [0, 1]
+__device__ inline float m_atan2(float y, float x) {
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+    const float a = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+    const float t = a * a;
+    float q = kAtanQ[8];
+#pragma unroll
+    for (int i = 7; i >= 0; --i) q = q * t + kAtanQ[i];
+    float r = a * q;
+    r = ay > ax ? kHalfPi - r : r;
+    r = x < 0.0f ? kPi - r : r;
+    return copysignf(r, y);
+}
+
 __device__ inline float m_tanh(float x) { return tanhf(x); }
 __device__ inline float m_abs(float x) { return fabsf(x); }
-__device__ inline float m_pow(float x, float y) { return powf(x, y); }
+// x^y for x >= 0 (0^0 = 1)
+__device__ inline float m_pow(float x, float y) {
+    if (y == 0.0f) return 1.0f;
+    if (x == 0.0f) return 0.0f;
+    return __builtin_amdgcn_exp2f(y * __builtin_amdgcn_logf(x));
+}
 __device__ inline float m_min(float a, float b) { return fminf(a, b); }
 __device__ inline float m_max(float a, float b) { return fmaxf(a, b); }
 __device__ inline float m_val(float x) { return x; }
-__device__ inline float m_const(float x, float) { return x; }
 
 template <class T> struct V3 { T x, y, z; };
 template <class T> __device__ inline V3<T> v3(T x, T y, T z) { return {x, y, z}; }
@@ -64,64 +100,93 @@ template <class T, class S> __device__ inline V3<T> scale(const V3<T>& a, S s) {
 
 template <class T> __device__ inline T clampv(T x, float lo, float hi) { return m_min(m_max(x, T(lo)), T(hi)); }
 
+// Gaussian of standard deviation beta at x
 template <class T> __device__ inline T gaussian(T beta, T x) {
-    return m_exp(-(x * x) / (2.0f * beta * beta)) * kInvSqrt2Pi / beta;
+    const T ib = m_rcp(beta);
+    return m_exp(-0.5f * (x * x) * (ib * ib)) * kInvSqrt2Pi * ib;
 }
 
-__device__ inline float wrap_pi(float x) { return x - kTwoPi * floorf((x + kPi) / kTwoPi); }
+__device__ inline float wrap_pi(float x) { return x - kTwoPi * floorf((x + kPi) * kInvTwoPi); }
 
 template <class T> __device__ inline T wrap_pi(T x) {
-    float k = floorf((m_val(x) + kPi) / kTwoPi);
+    float k = floorf((m_val(x) + kPi) * kInvTwoPi);
     return x - kTwoPi * k;
 }
 
-template <class T> __device__ inline T trimmed_logistic(T x, T s, T inv_tanh) {
-    T e = m_exp(-m_abs(x) / s);
+// logistic density of scale s trimmed to [-pi, pi]; norm = 1 / (s tanh(pi / 2s))
+template <class T> __device__ inline T trimmed_logistic(T x, T inv_s, T norm) {
+    T e = m_exp(-m_abs(x) * inv_s);
     T one_e = 1.0f + e;
-    return e / (s * one_e * one_e) * inv_tanh;
+    return e * norm * m_rcp(one_e * one_e);
 }
 
-template <class T> __device__ inline T logistic_cdf_trimmed(T x, T s) {
-    T lo = 1.0f / (1.0f + m_exp(kPi / s));
-    T hi = 1.0f / (1.0f + m_exp(-kPi / s));
-    return (1.0f / (1.0f + m_exp(-x / s)) - lo) / (hi - lo);
+// Antiderivative of the 2 pi-periodic trimmed logistic of the material's scale s:
+// k + (sigmoid(y / s) - lo) / (hi - lo), y = x - 2 pi k in [-pi, pi).
+template <class T> __device__ inline T periodic_cdf(T x, const MatConst& m) {
+    float k = floorf((m_val(x) + kPi) * kInvTwoPi);
+    T y = x - kTwoPi * k;
+    return T(k) + (m_rcp(1.0f + m_exp(-y * m.inv_s)) - m.cdf_lo) * m.cdf_scale;
 }
 
-// Antiderivative of the 2 pi-periodic trimmed logistic.
-template <class T> __device__ inline T periodic_cdf(T x, T s) {
-    float k = floorf((m_val(x) + kPi) / kTwoPi);
-    return T(k) + logistic_cdf_trimmed(x - kTwoPi * k, s);
-}
-
-template <class T> __device__ inline T fresnel(T cos_i, float eta) {
-    T sin2_t = (1.0f - cos_i * cos_i) / (eta * eta);
+template <class T> __device__ inline T fresnel(T cos_i, const MatConst& m) {
+    T sin2_t = (1.0f - cos_i * cos_i) * m.inv_eta2;
     T cos_t = m_sqrt(1.0f - sin2_t);
-    T rs = (cos_i - eta * cos_t) / (cos_i + eta * cos_t);
-    T rp = (eta * cos_i - cos_t) / (eta * cos_i + cos_t);
+    T ec = m.eta * cos_t, ei = m.eta * cos_i;
+    T rs = (cos_i - ec) * m_rcp(cos_i + ec);
+    T rp = (ei - cos_t) * m_rcp(ei + cos_t);
     return 0.5f * (rs * rs + rp * rp);
 }
 
-// Attenuations of R, TT, TRT (RGB) and the refraction angles at offset h.
+// View/light geometry of one fragment and light (independent of the fitted parameters).
+struct LightView {
+    float theta_h;     // (theta_i + theta_o) / 2
+    float cos_ti;      // cos theta_i (irradiance foreshortening)
+    float phi;         // relative azimuth
+    float cos_phi;
+    float sxd2, cxd;   // sin^2 x_d, cos x_d
+    float inv_eta_p;   // 1 / eta' (Bravais index at x_d)
+    float inv_ctt;     // 1 / cos theta_t, sin theta_t = sin x_d / eta
+};
+
+// sin_ti / sin_to: sines of the longitudinal angles; x, y: light direction in the normal plane
+__device__ inline LightView light_view(float sin_ti, float sin_to, float theta_o, float cos_to, float wx, float wy,
+                                       bool degen, const MatConst& m) {
+    LightView v;
+    const float si = fminf(fmaxf(sin_ti, -1.0f), 1.0f);
+    const float ci = m_sqrt((1.0f - si) * (1.0f + si));
+    v.cos_ti = ci;
+    v.theta_h = 0.5f * (m_asin(si) + theta_o);
+    const float c = fminf(fmaxf(ci * cos_to + si * sin_to, -1.0f), 1.0f);   // cos(theta_i - theta_o)
+    v.sxd2 = 0.5f * (1.0f - c);
+    v.cxd = m_sqrt(0.5f * (1.0f + c));
+    v.inv_eta_p = v.cxd * m_rsqrt(m.eta * m.eta - v.sxd2);
+    v.inv_ctt = m_rsqrt(1.0f - v.sxd2 * m.inv_eta2);
+    const float r2 = wx * wx + wy * wy;
+    if (degen || !(r2 > 0.0f)) {
+        v.phi = 0.0f;
+        v.cos_phi = 1.0f;
+    } else {
+        v.phi = -m_atan2(wy, wx);
+        v.cos_phi = wx * m_rsqrt(r2);
+    }
+    return v;
+}
+
+// Attenuations of R, TT, TRT (RGB) and the refraction angle at offset h (incidence angle
+// gamma_o = asin h, cos gamma_o given).
 template <class T> struct Atten {
     T A[3][3];      // [lobe][channel]
-    T gamma_o, gamma_t;
+    T gamma_t;
 };
 
 template <class T>
-__device__ inline Atten<T> attenuation(T x_d, T h, const T sig[3], float eta) {
+__device__ inline Atten<T> attenuation(const LightView& v, T h, T cgo, const T sig[3], const MatConst& m) {
     Atten<T> o;
-    T sxd = m_sin(x_d);
-    T cxd = m_max(m_cos(x_d), T(0.0f));
-    T eta_p = m_sqrt(eta * eta - sxd * sxd) / cxd;
-    o.gamma_o = m_asin(h);
-    T cgo = m_sqrt((1.0f - h) * (1.0f + h));
-    T sgt = h / eta_p;
+    T sgt = h * v.inv_eta_p;
     o.gamma_t = m_asin(sgt);
     T cgt = m_sqrt(1.0f - sgt * sgt);
-    T stt = sxd / eta;
-    T ctt = m_sqrt(1.0f - stt * stt);
-    T F = fresnel(cxd * cgo, eta);
-    T path = 2.0f * cgt / ctt;
+    T F = fresnel(v.cxd * cgo, m);
+    T path = 2.0f * cgt * v.inv_ctt;
     T one_f = 1.0f - F;
     T one_f2 = one_f * one_f;
     for (int c = 0; c < 3; ++c) {
@@ -137,35 +202,36 @@ template <class T> __device__ inline T exit_azimuth(int p, T gamma_o, T gamma_t)
     return (2.0f * p) * gamma_t - 2.0f * gamma_o + p * kPi;
 }
 
-// Single-fibre BCSDF, RGB.
+// Single-fibre BCSDF, RGB (gamma_o = asin h, cgo = cos gamma_o).
 template <class T>
-__device__ inline void f_single(T theta_h, T x_d, T phi, T h, const T sig[3], const MatConst& m, T out[3]) {
-    Atten<T> at = attenuation(x_d, h, sig, m.eta);
-    T s = T(m.s), inv_tanh = T(m.inv_tanh);
+__device__ inline void f_single(const LightView& v, T h, T gamma_o, T cgo, const T sig[3], const MatConst& m,
+                                T out[3]) {
+    Atten<T> at = attenuation(v, h, cgo, sig, m);
+    const T inv_s = T(m.inv_s), norm = T(m.n_norm);
     out[0] = out[1] = out[2] = T(0.0f);
     for (int p = 0; p < 3; ++p) {
-        T M = 0.5f * gaussian(T(m.beta_p[p]), theta_h - m.alpha_p[p]);
-        T N = trimmed_logistic(wrap_pi(phi - exit_azimuth(p, at.gamma_o, at.gamma_t)), s, inv_tanh);
+        const float x = v.theta_h - m.alpha_p[p];
+        const float M = m.g_amp[p] * m_exp(-m.g_k[p] * (x * x));
+        T N = trimmed_logistic(wrap_pi(v.phi - exit_azimuth(p, gamma_o, at.gamma_t)), inv_s, norm);
         T MN = M * N;
         for (int c = 0; c < 3; ++c) out[c] = out[c] + at.A[p][c] * MN;
     }
 }
 
-// Hemisphere albedos a_F, a_B (RGB) and variances sigma_f^2, sigma_b^2 at x_d.
+// Hemisphere albedos a_F, a_B (RGB) and variances sigma_f^2, sigma_b^2 at the light's x_d.
 template <class T>
-__device__ inline void hemisphere_stats(T x_d, const T sig[3], const MatConst& m, T aF[3], T aB[3], T& var_f,
-                                        T& var_b) {
-    T s = T(m.s);
+__device__ inline void hemisphere_stats(const LightView& v, const T sig[3], const MatConst& m, T aF[3], T aB[3],
+                                        T& var_f, T& var_b) {
     T wF[3], wB[3];
     for (int c = 0; c < 3; ++c) aF[c] = aB[c] = T(0.0f);
     for (int p = 0; p < 3; ++p) wF[p] = wB[p] = T(0.0f);
     for (int k = 0; k < 8; ++k) {
-        T hk = T(kGLx[k]);
-        Atten<T> at = attenuation(x_d, hk, sig, m.eta);
+        const T go = T(kGLgo[k]);
+        Atten<T> at = attenuation(v, T(kGLx[k]), T(kGLcgo[k]), sig, m);
         float wk = 0.5f * kGLw[k];
         for (int p = 0; p < 3; ++p) {
-            T mu = exit_azimuth(p, at.gamma_o, at.gamma_t);
-            T back = periodic_cdf(T(0.5f * kPi) - mu, s) - periodic_cdf(T(-0.5f * kPi) - mu, s);
+            T mu = exit_azimuth(p, go, at.gamma_t);
+            T back = periodic_cdf(T(kHalfPi) - mu, m) - periodic_cdf(T(-kHalfPi) - mu, m);
             T PF = 1.0f - back;
             T sumF = T(0.0f), sumB = T(0.0f);
             for (int c = 0; c < 3; ++c) {
@@ -201,23 +267,24 @@ template <class T> struct ClusterFrag {
 
 // Aggregated BCSDF, RGB.
 template <class T>
-__device__ inline void f_ours(T theta_h, T x_d, T phi, T h, const T sig[3], const MatConst& m,
+__device__ inline void f_ours(const LightView& v, T h, T gamma_o, T cgo, const T sig[3], const MatConst& m,
                               const ClusterFrag<T>& cf, T out[3]) {
-    const bool back_hemi = m_abs(m_val(phi)) < 0.5f * kPi;
+    const bool back_hemi = fabsf(v.phi) < 0.5f * kPi;
     const bool multi = m_val(cf.n_total) >= 2.0f;
     T aF[3], aB[3], var_f, var_b;
-    hemisphere_stats(x_d, sig, m, aF, aB, var_f, var_b);
-    Atten<T> at = attenuation(x_d, h, sig, m.eta);
+    hemisphere_stats(v, sig, m, aF, aB, var_f, var_b);
+    Atten<T> at = attenuation(v, h, cgo, sig, m);
     T nm1 = cf.n_F - 1.0f;
     T extra = nm1 * var_f;
     T s_bar = kSqrt3 * m_sqrt(T(m.beta_n * m.beta_n) + extra) / kPi;
-    T inv_tanh = 1.0f / m_tanh(kPi / (2.0f * s_bar));
+    T inv_sb = m_rcp(s_bar);
+    T norm = m_rcp(s_bar * m_tanh(kPi * 0.5f * inv_sb));
     T fwd[3];
     for (int c = 0; c < 3; ++c) fwd[c] = m_pow(aF[c], nm1);
     for (int c = 0; c < 3; ++c) out[c] = T(0.0f);
     for (int p = 0; p < 3; ++p) {
-        T M = 0.5f * gaussian(m_sqrt(T(m.beta_p[p] * m.beta_p[p]) + extra), theta_h - m.alpha_p[p]);
-        T N = trimmed_logistic(wrap_pi(phi - exit_azimuth(p, at.gamma_o, at.gamma_t)), s_bar, inv_tanh);
+        T M = 0.5f * gaussian(m_sqrt(T(m.beta_p[p] * m.beta_p[p]) + extra), T(v.theta_h - m.alpha_p[p]));
+        T N = trimmed_logistic(wrap_pi(v.phi - exit_azimuth(p, gamma_o, at.gamma_t)), inv_sb, norm);
         T MN = M * N;
         for (int c = 0; c < 3; ++c) out[c] = out[c] + fwd[c] * at.A[p][c] * MN;
     }
@@ -226,10 +293,10 @@ __device__ inline void f_ours(T theta_h, T x_d, T phi, T h, const T sig[3], cons
         T m1 = T(0.0f), m3 = T(0.0f), m1p = T(0.0f);
         for (int c = 0; c < 3; ++c) {
             T aF2 = aF[c] * aF[c];
-            T om = 1.0f - aF2;
-            A1[c] = aB[c] * aF2 / om;
-            A3[c] = aB[c] * aB[c] * aB[c] * aF2 / (om * om * om);
-            A1p[c] = kD1Plus * aB[c] * aF[c] * (1.0f - m_pow(aF[c], 2.0f * cf.n_B)) / om;
+            T iom = m_rcp(1.0f - aF2);
+            A1[c] = aB[c] * aF2 * iom;
+            A3[c] = aB[c] * aB[c] * aB[c] * aF2 * (iom * iom * iom);
+            A1p[c] = kD1Plus * aB[c] * aF[c] * (1.0f - m_pow(aF[c], 2.0f * cf.n_B)) * iom;
             m1 = m1 + A1[c] * (1.0f / 3.0f);
             m3 = m3 + A3[c] * (1.0f / 3.0f);
             m1p = m1p + A1p[c] * (1.0f / 3.0f);
@@ -237,13 +304,13 @@ __device__ inline void f_ours(T theta_h, T x_d, T phi, T h, const T sig[3], cons
         T varB = (m1 * (var_b + 2.0f * var_f) + m3 * (3.0f * var_b + 2.0f * var_f) +
                   m1p * (var_b + (2.0f * cf.n_B - 1.0f) * var_f)) / (m1 + m3 + m1p);
         if (back_hemi) {
-            T MB = 0.5f * gaussian(m_sqrt(varB), theta_h) * (1.0f / kPi);
+            T MB = 0.5f * gaussian(m_sqrt(varB), T(v.theta_h)) * (1.0f / kPi);
             for (int c = 0; c < 3; ++c) out[c] = out[c] + (A1p[c] + A1[c] + A3[c]) * MB;
         }
     }
     if (back_hemi && multi) {
         T one_rho = 1.0f - cf.rho;
-        T Ps = one_rho * (1.0f - m_cos(phi));
+        T Ps = one_rho * (1.0f - v.cos_phi);
         T Pn = m_max(1.0f - kCm * one_rho - Ps, T(0.0f));
         for (int c = 0; c < 3; ++c) out[c] = (Ps * aF[c] + Pn) * out[c];
     }
