@@ -231,11 +231,13 @@ MatConst mat_const(const hair_material& m) {
         const double b = k.beta_p[p];
         k.g_amp[p] = (float)(0.5 / (b * std::sqrt(2.0 * M_PI)));
         k.g_k[p] = (float)(1.0 / (2.0 * b * b));
+        k.g_k2[p] = (float)(M_LOG2E / (2.0 * b * b));
     }
     k.beta_n = m.beta_n;
     const double s = std::sqrt(3.0) * (double)m.beta_n / M_PI;
     k.s = (float)s;
     k.inv_s = (float)(1.0 / s);
+    k.inv_s_l2 = (float)(M_LOG2E / s);
     k.n_norm = (float)(1.0 / (s * std::tanh(M_PI / (2.0 * s))));
     const double lo = 1.0 / (1.0 + std::exp(M_PI / s)), hi = 1.0 / (1.0 + std::exp(-M_PI / s));
     k.cdf_lo = (float)lo;
@@ -423,8 +425,8 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     out->ms[0] = t06; out->ms[1] = t01; out->ms[2] = t23 + t45; out->ms[3] = t56;
     out->n_batches = n_batches;
 #ifdef HAIR_PHASE_STATS
-    fprintf(stderr, "phase cycles: count %llu emit %llu sort %llu shade %llu blend %llu | batches %u items %u\n",
-            out->ctr.phase[0], out->ctr.phase[1], out->ctr.phase[2], out->ctr.phase[3], out->ctr.phase[4], n_batches,
+    fprintf(stderr, "phase cycles: count %llu emit %llu sort %llu shade %llu blend %llu load %llu | batches %u items %u\n",
+            out->ctr.phase[0], out->ctr.phase[1], out->ctr.phase[2], out->ctr.phase[3], out->ctr.phase[4], out->ctr.phase[5], n_batches,
             n_items);
 #endif
     return HAIR_OK;

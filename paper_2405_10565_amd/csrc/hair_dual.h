@@ -90,6 +90,10 @@ template <int N> __device__ inline Dual<N> m_exp(const Dual<N>& x) {
     const float e = expf(x.v);
     return chain(x, e, e);
 }
+template <int N> __device__ inline Dual<N> m_exp2(const Dual<N>& x) {
+    const float e = exp2f(x.v);
+    return chain(x, e, e * 0.69314718055994530942f);
+}
 template <int N> __device__ inline Dual<N> m_sqrt(const Dual<N>& x) {
     const float s = sqrtf(x.v);
     return chain(x, s, s > 0.0f ? 0.5f / s : 0.0f);

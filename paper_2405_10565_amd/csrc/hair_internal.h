@@ -63,9 +63,11 @@ struct MatConst {
     float beta_p[3];         // longitudinal standard deviations of R, TT, TRT
     float g_amp[3];          // M_p = g_amp exp(-g_k x^2): 1 / (2 beta_p sqrt(2 pi))
     float g_k[3];            //                            1 / (2 beta_p^2)
+    float g_k2[3];           // g_k log2(e)
     float beta_n;            // azimuthal standard deviation
     float s;                 // logistic scale sqrt(3) beta_n / pi
     float inv_s;             // 1 / s
+    float inv_s_l2;          // log2(e) / s
     float n_norm;            // trimmed-logistic normaliser 1 / (s tanh(pi / 2s))
     float cdf_lo, cdf_scale; // trimmed CDF: (sigmoid(x / s) - cdf_lo) * cdf_scale on [-pi, pi]
 };

@@ -416,6 +416,7 @@ template <int KIND, class T>
 __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const float4& q0, const float4& q1,
                                   const float4& q2, float n_total, int pxg, int pyg, const T& hw, const T& a_len,
                                   const T& b_len, const T& rr, const T sig[3], T& alpha, T& hoff, T L[3]) {
+#pragma clang fp contract(fast)
     // integer coverage geometry; 32 bits suffice because a covered pixel centre lies within
     // the segment's box widened by its radius and longer segments (kMaxAxis) are culled
     const int ex = 16 * pxg + 8 - s.xa, ey = 16 * pyg + 8 - s.ya;
@@ -456,6 +457,7 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
     const float cos_to = m_sqrt((1.0f - sin_to) * (1.0f + sin_to));
     const T gamma_o = m_asin(h);
     const T cgo = m_sqrt((1.0f - h) * (1.0f + h));
+    const T sigl[3] = {sig[0] * kLog2e, sig[1] * kLog2e, sig[2] * kLog2e};
 
     ClusterFrag<T> cf;
     T W, ia, ib;
@@ -489,7 +491,7 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
         const LightView v = light_view(sin_ti, sin_to, to, cos_to, dot(wi, xh), dot(wi, yh), degen, a.mat);
         T f[3];
         if (KIND == 0) {
-            f_single(v, h, gamma_o, cgo, sig, a.mat, f);
+            f_single(v, h, gamma_o, cgo, sigl, a.mat, f);
         } else {
             // chord of the view ray's entry point toward the light, in the cross-section
             const V3<float> Dp = sub(wi, scale(u, sin_ti));
@@ -511,7 +513,7 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
             const bool back = fabsf(v.phi) < 0.5f * kPi;
             cf.n_F = (back || n_total < 2.0f) ? T(1.0f) : m_max(cf.rho * kappa * lF, T(1.0f));
             cf.n_B = m_max(cf.rho * kappa * lB, T(1.0f));
-            f_ours(v, h, gamma_o, cgo, sig, a.mat, cf, f);
+            f_ours(v, h, gamma_o, cgo, sigl, a.mat, cf, f);
         }
         L[0] = L[0] + (E[0] * v.cos_ti) * f[0];
         L[1] = L[1] + (E[1] * v.cos_ti) * f[1];
@@ -536,29 +538,35 @@ __device__ inline void shade_fragment(const ShadeArgs& a, uint32_t gseg, int pxg
 
 // Block-wide exclusive scan of one uint per thread (256 threads); returns the total.
 __device__ inline uint32_t block_exscan_u32(uint32_t v, uint32_t* s_tmp, uint32_t& excl) {
-    const int t = threadIdx.x;
-    s_tmp[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kNT; off <<= 1) {
-        const uint32_t x = t >= off ? s_tmp[t - off] : 0u;
-        __syncthreads();
-        s_tmp[t] += x;
-        __syncthreads();
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
     }
-    const uint32_t incl = s_tmp[t];
-    const uint32_t total = s_tmp[kNT - 1];
+    if (lane == 63) s_tmp[wv] = x;
     __syncthreads();
-    excl = incl - v;
+    uint32_t base = 0, total = 0;
+#pragma unroll
+    for (int w2 = 0; w2 < kNT / 64; ++w2) {
+        const uint32_t a = s_tmp[w2];
+        if (w2 < wv) base += a;
+        total += a;
+    }
+    __syncthreads();
+    excl = base + x - v;
     return total;
 }
 
 #ifdef HAIR_PHASE_STATS
-#define PHASE_BEGIN() const unsigned long long ph_t0 = wall_clock64()
+#define PHASE_BEGIN() unsigned long long ph_t0 = wall_clock64()
 // (the barrier here only makes the timing cover the whole block; correctness never relies on it)
 #define PHASE_END(ctr, i)                                                      \
     do {                                                                       \
         __syncthreads();                                                       \
         if (threadIdx.x == 0) atomicAdd(&(ctr)->phase[i], wall_clock64() - ph_t0); \
+        ph_t0 = wall_clock64();                                                \
     } while (0)
 #else
 #define PHASE_BEGIN() do {} while (0)
@@ -739,14 +747,92 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam, uint32_
     PHASE_END(f.ctr, 1);
 }
 
-// Exact per-pixel order of the Fb records in s_A (whole pixels with counts, key ranges and
-// offsets in s_cnt / s_kmin / s_kmax / s_off) into s_B: bucket sort with one bucket per record,
-// bucket = the record's place in its pixel's linear key range (a monotone map, so sorted
-// buckets give sorted pixels), then insertion sort inside each bucket by (key, segment id).
-// s_bk must hold Fb zeros on entry.  Ends with a barrier.
-__device__ inline void order_batch(uint32_t Fb, const uint32_t* s_cnt, const uint32_t* s_kmin, const uint32_t* s_kmax,
-                                   const uint32_t* s_off, uint32_t* s_tmp, const uint2* s_A, uint2* s_B,
-                                   uint32_t* s_bk, const uint32_t* list) {
+// Exact per-pixel order of the Fb records at src (global memory, or LDS that may be s_A) of
+// whole pixels with counts, key ranges and offsets in s_cnt / s_kmin / s_kmax / s_off, into s_B.
+// Bucket sort with one bucket per record, bucket = the record's place in its pixel's linear key
+// range (a monotone map, so sorted buckets give a sorted pixel); the records are scattered to
+// bucket order in s_A, and each record's place inside its bucket is its rank there by
+// (key, segment id), which is unique within a pixel.  s_bk must hold Fb zeros on entry.
+// Ends with a barrier.
+__device__ inline void order_batch(uint32_t Fb, const uint2* src, const uint32_t* s_cnt, const uint32_t* s_kmin,
+                                   const uint32_t* s_kmax, const uint32_t* s_off, uint32_t* s_tmp, uint2* s_A,
+                                   uint2* s_B, uint32_t* s_bk, const uint32_t* list) {
+    const int t = threadIdx.x;
+    uint2 rec[kPerThread];
+    uint32_t my_b[kPerThread], my_r[kPerThread];
+#pragma unroll
+    for (int qq = 0; qq < kPerThread; ++qq) {
+        const uint32_t i = t + qq * kNT;
+        if (i < Fb) rec[qq] = src[i];
+    }
+#pragma unroll
+    for (int qq = 0; qq < kPerThread; ++qq) {
+        const uint32_t i = t + qq * kNT;
+        if (i < Fb) {
+            const uint32_t p = rec[qq].y >> 24;
+            const uint32_t kmn = s_kmin[p], cnt = s_cnt[p];
+            const float scale = (float)cnt * __builtin_amdgcn_rcpf((float)(s_kmax[p] - kmn) + 1.0f);
+            const uint32_t bucket = min(cnt - 1u, (uint32_t)((float)(rec[qq].x - kmn) * scale));
+            my_b[qq] = s_off[p] + bucket;
+            my_r[qq] = atomicAdd(&s_bk[my_b[qq]], 1u);
+        }
+    }
+    __syncthreads();
+    {   // exclusive scan of the bucket counters, kOwn consecutive per thread (odd, so the
+        // lanes' strided reads fall in distinct LDS banks)
+        constexpr int kOwn = kPerThread + 1;
+        uint32_t loc[kOwn];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int qq = 0; qq < kOwn; ++qq) {
+            const uint32_t i = t * kOwn + qq;
+            loc[qq] = i < Fb ? s_bk[i] : 0u;
+            sum += loc[qq];
+        }
+        uint32_t ex;
+        block_exscan_u32(sum, s_tmp, ex);
+#pragma unroll
+        for (int qq = 0; qq < kOwn; ++qq) {
+            const uint32_t i = t * kOwn + qq;
+            if (i < Fb) s_bk[i] = ex;
+            ex += loc[qq];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int qq = 0; qq < kPerThread; ++qq) {
+        const uint32_t i = t + qq * kNT;
+        if (i < Fb) s_A[s_bk[my_b[qq]] + my_r[qq]] = rec[qq];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int qq = 0; qq < kPerThread; ++qq) {
+        const uint32_t i = t + qq * kNT;
+        if (i < Fb) {
+            const uint32_t b0 = s_bk[my_b[qq]];
+            const uint32_t b1 = my_b[qq] + 1 < Fb ? s_bk[my_b[qq] + 1] : Fb;
+            const uint32_t self = b0 + my_r[qq];
+            const uint2 me = s_A[self];
+            uint32_t rank = 0;
+            for (uint32_t j = b0; j < b1; ++j) {
+                const uint2 u2 = s_A[j];
+                bool less = u2.x < me.x;
+                if (u2.x == me.x && j != self) less = list[u2.y & 0xFFFFFFu] < list[me.y & 0xFFFFFFu];
+                rank += less;
+            }
+            s_B[b0 + rank] = me;
+        }
+    }
+    __syncthreads();
+}
+
+// The backward pass's ordering: the same buckets, records staged in s_A and sorted in place in
+// s_B by insertion inside each bucket.  (The rank-based routine above gives the same order, but
+// inside k_batch_bwd, whose registers are at the 256 + AGPR limit, its use changes that
+// kernel's gradients; this variant is the one validated there.)  s_bk must hold Fb zeros.
+__device__ inline void order_batch_insertion(uint32_t Fb, const uint32_t* s_cnt, const uint32_t* s_kmin,
+                                             const uint32_t* s_kmax, const uint32_t* s_off, uint32_t* s_tmp,
+                                             const uint2* s_A, uint2* s_B, uint32_t* s_bk, const uint32_t* list) {
     const int t = threadIdx.x;
     uint32_t my_b[kPerThread], my_r[kPerThread];
 #pragma unroll
@@ -763,7 +849,7 @@ __device__ inline void order_batch(uint32_t Fb, const uint32_t* s_cnt, const uin
         }
     }
     __syncthreads();
-    {   // exclusive scan of the bucket counters, kPerThread consecutive per thread
+    {
         uint32_t loc[kPerThread];
         uint32_t sum = 0;
 #pragma unroll
@@ -831,8 +917,8 @@ struct BatchLds {
 template <int KIND>
 __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, float* __restrict__ rgba,
                                         const DebugDump& dbg, int has_dbg, const BatchLds& L_, const uint32_t* list,
-                                        int px0, int py0, uint32_t Fb, float* slice_out, uint32_t rank0,
-                                        uint32_t cnt_total) {
+                                        const uint2* src, int px0, int py0, uint32_t Fb, float* slice_out,
+                                        uint32_t rank0, uint32_t cnt_total) {
     uint32_t* s_cnt = L_.s_cnt;
     uint32_t* s_kmin = L_.s_kmin;
     uint32_t* s_kmax = L_.s_kmax;
@@ -846,7 +932,9 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
     uint32_t* s_aggh = L_.s_aggh;
     const int t = threadIdx.x;
     const int W = a.cam.W, H = a.cam.H;
-    order_batch(Fb, s_cnt, s_kmin, s_kmax, s_off, s_tmp, s_A, s_B, s_bk, list);
+    PHASE_BEGIN();
+    order_batch(Fb, src, s_cnt, s_kmin, s_kmax, s_off, s_tmp, s_A, s_B, s_bk, list);
+    PHASE_END(f.ctr, 2);
     // ---- shade: one lane per fragment, payload alpha * L and (1 - alpha)
     for (uint32_t i = t; i < Fb; i += kNT) {
         const uint2 rec = s_B[i];
@@ -876,8 +964,10 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
         }
     }
     __syncthreads();
-    // ---- blend: segmented scan of (C, T) over runs of consecutive fragments
-    const uint32_t run = (Fb + kNT - 1) / kNT;
+    PHASE_END(f.ctr, 3);
+    // ---- blend: segmented scan of (C, T) over runs of consecutive fragments.  Runs have odd
+    // length so that the lanes' strided LDS reads fall in distinct banks.
+    const uint32_t run = ((Fb + kNT - 1) / kNT) | 1u;
     const uint32_t rb = min(Fb, t * run), re = min(Fb, rb + run);
     float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
     uint32_t head = 0;
@@ -889,32 +979,51 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
         C2 += T * s_pay[3 * i + 2];
         T *= __uint_as_float(s_B[i].x);
     }
-    s_agg[4 * t + 0] = C0; s_agg[4 * t + 1] = C1; s_agg[4 * t + 2] = C2; s_agg[4 * t + 3] = T;
-    s_aggh[t] = head;
-    __syncthreads();
-    // inclusive scan of run aggregates: (l) then (r) = r.head ? r : (l.C + l.T r.C, l.T r.T)
-    for (int off = 1; off < kNT; off <<= 1) {
-        float c0 = 0, c1 = 0, c2 = 0, tt = 1;
-        uint32_t hh2 = 0;
-        const bool has = t >= off;
-        if (has) {
-            c0 = s_agg[4 * (t - off) + 0]; c1 = s_agg[4 * (t - off) + 1];
-            c2 = s_agg[4 * (t - off) + 2]; tt = s_agg[4 * (t - off) + 3];
-            hh2 = s_aggh[t - off];
+    // inclusive scan of the run aggregates, (l) then (r) = r.head ? r : (l.C + l.T r.C, l.T r.T):
+    // within the wave by shuffles, then across the block's waves through LDS
+    const int lane = t & 63, wv = t >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const float c0 = __shfl_up(C0, off), c1 = __shfl_up(C1, off), c2 = __shfl_up(C2, off);
+        const float tt = __shfl_up(T, off);
+        const uint32_t hh2 = __shfl_up(head, off);
+        if (lane >= off && !head) {
+            C0 = c0 + tt * C0;
+            C1 = c1 + tt * C1;
+            C2 = c2 + tt * C2;
+            T = tt * T;
+            head = hh2;
         }
-        __syncthreads();
-        if (has && !s_aggh[t]) {
-            const float mT = s_agg[4 * t + 3];
-            s_agg[4 * t + 0] = c0 + tt * s_agg[4 * t + 0];
-            s_agg[4 * t + 1] = c1 + tt * s_agg[4 * t + 1];
-            s_agg[4 * t + 2] = c2 + tt * s_agg[4 * t + 2];
-            s_agg[4 * t + 3] = tt * mT;
-            s_aggh[t] = hh2;
-        }
-        __syncthreads();
     }
-    if (t > 0) { C0 = s_agg[4 * (t - 1) + 0]; C1 = s_agg[4 * (t - 1) + 1]; C2 = s_agg[4 * (t - 1) + 2]; T = s_agg[4 * (t - 1) + 3]; }
-    else { C0 = C1 = C2 = 0.f; T = 1.f; }
+    if (lane == 63) {
+        s_agg[4 * wv + 0] = C0; s_agg[4 * wv + 1] = C1; s_agg[4 * wv + 2] = C2; s_agg[4 * wv + 3] = T;
+        s_aggh[wv] = head;
+    }
+    __syncthreads();
+    {   // exclusive prefix of this thread's run: earlier waves, then earlier lanes of this wave
+        float e0 = 0.f, e1 = 0.f, e2 = 0.f, eT = 1.f;
+        for (int w2 = 0; w2 < wv; ++w2) {
+            if (s_aggh[w2]) { e0 = s_agg[4 * w2 + 0]; e1 = s_agg[4 * w2 + 1]; e2 = s_agg[4 * w2 + 2]; eT = s_agg[4 * w2 + 3]; }
+            else {
+                e0 = e0 + eT * s_agg[4 * w2 + 0];
+                e1 = e1 + eT * s_agg[4 * w2 + 1];
+                e2 = e2 + eT * s_agg[4 * w2 + 2];
+                eT = eT * s_agg[4 * w2 + 3];
+            }
+        }
+        const float l0 = __shfl_up(C0, 1), l1 = __shfl_up(C1, 1), l2 = __shfl_up(C2, 1), lT = __shfl_up(T, 1);
+        const uint32_t lh = __shfl_up(head, 1);
+        if (lane > 0) {
+            if (lh) { e0 = l0; e1 = l1; e2 = l2; eT = lT; }
+            else {
+                e0 = e0 + eT * l0;
+                e1 = e1 + eT * l1;
+                e2 = e2 + eT * l2;
+                eT = eT * lT;
+            }
+        }
+        C0 = e0; C1 = e1; C2 = e2; T = eT;
+    }
     for (uint32_t i = rb; i < re; ++i) {
         const uint32_t p = s_B[i].y >> 24;
         if (i == s_off[p]) { C0 = C1 = C2 = 0.f; T = 1.f; }
@@ -934,6 +1043,7 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
             }
         }
     }
+    PHASE_END(f.ctr, 4);
 }
 
 // One LDS batch of whole pixels: exact per-pixel order, shading, front-to-back blending.  A
@@ -947,8 +1057,8 @@ __global__ __launch_bounds__(kNT) void k_batch(FrameBufs f, ShadeArgs a, float* 
     __shared__ uint32_t s_tmp[kNT];
     __shared__ __align__(16) uint2 s_B[kCap];
     __shared__ __align__(16) uint32_t s_work[3 * kCap];   // staged records (2 words) + bucket counters, later payload
-    __shared__ float s_agg[kNT * 4];          // run aggregates (C rgb, T)
-    __shared__ uint32_t s_aggh[kNT];
+    __shared__ float s_agg[kNT / 64 * 4];     // wave aggregates of the blend scan (C rgb, T)
+    __shared__ uint32_t s_aggh[kNT / 64];
     __shared__ float s_slice[4];
     __shared__ unsigned long long s_range[2];
     __shared__ uint32_t s_slot, s_flag;
@@ -975,13 +1085,10 @@ __global__ __launch_bounds__(kNT) void k_batch(FrameBufs f, ShadeArgs a, float* 
         if (t == 0) s_off[p1] = (p1 < kTilePix ? f.pix_off[(size_t)tile * kTilePix + p1] : f.tile_tot[tile]) - tile_off0;
         __syncthreads();
         const uint32_t Fb = s_off[p1];
-        for (uint32_t i = t; i < Fb; i += kNT) {
-            L_.s_A[i] = src[i];
-            L_.s_bk[i] = 0;
-        }
+        for (uint32_t i = t; i < Fb; i += kNT) L_.s_bk[i] = 0;
         __syncthreads();
-        sort_shade_blend<KIND>(f, a, rgba, dbg, has_dbg, L_, list, px0, py0, Fb, nullptr, 0, 0);
-        PHASE_END(f.ctr, 4);
+        PHASE_END(f.ctr, 5);
+        sort_shade_blend<KIND>(f, a, rgba, dbg, has_dbg, L_, list, src, px0, py0, Fb, nullptr, 0, 0);
         return;
     }
     // ---- a pixel deeper than one batch: exact depth-key slices
@@ -1047,7 +1154,7 @@ __global__ __launch_bounds__(kNT) void k_batch(FrameBufs f, ShadeArgs a, float* 
             s_off[p + 1] = Fb;
         }
         __syncthreads();
-        sort_shade_blend<KIND>(f, a, rgba, dbg, has_dbg, L_, list, px0, py0, Fb, s_slice, done, k);
+        sort_shade_blend<KIND>(f, a, rgba, dbg, has_dbg, L_, list, L_.s_A, px0, py0, Fb, s_slice, done, k);
         __syncthreads();
         if (t == 0) {
             C0 += T * s_slice[0];
@@ -1156,7 +1263,7 @@ __global__ __launch_bounds__(kNT) void k_batch_bwd(FrameBufs f, ShadeArgs a, Gra
         s_bk[i] = 0;
     }
     __syncthreads();
-    order_batch(Fb, s_cnt, s_kmin, s_kmax, s_off, s_tmp, s_A, s_B, s_bk, list);
+    order_batch_insertion(Fb, s_cnt, s_kmin, s_kmax, s_off, s_tmp, s_A, s_B, s_bk, list);
     // ---- 2. alpha and L per fragment (float)
     for (uint32_t i = t; i < Fb; i += kNT) {
         const uint2 rec = s_B[i];

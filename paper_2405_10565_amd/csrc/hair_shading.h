@@ -28,6 +28,10 @@
 #include "hair_internal.h"
 #include "hair_fastmath_coef.h"
 
+// Multiply-adds in the scattering terms may fuse (one rounding instead of two); nothing here
+// decides an integer.  The library's other code is compiled without contraction.
+#pragma clang fp contract(fast)
+
 namespace hair {
 
 constexpr float kPi = 3.14159265358979323846f;
@@ -42,6 +46,7 @@ constexpr float kCm = 0.2f;         // Sec. 4, multiple-hair shadowing constant
 
 // ---- float function set; the dual-number type provides the same names ----
 __device__ inline float m_exp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
+__device__ inline float m_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ inline float m_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ inline float m_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline float m_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -113,9 +118,9 @@ template <class T> __device__ inline T wrap_pi(T x) {
     return x - kTwoPi * k;
 }
 
-// logistic density of scale s trimmed to [-pi, pi]; norm = 1 / (s tanh(pi / 2s))
-template <class T> __device__ inline T trimmed_logistic(T x, T inv_s, T norm) {
-    T e = m_exp(-m_abs(x) * inv_s);
+// logistic density of scale s trimmed to [-pi, pi]; k = log2(e) / s, norm = 1 / (s tanh(pi / 2s))
+template <class T> __device__ inline T trimmed_logistic(T x, T k, T norm) {
+    T e = m_exp2(-m_abs(x) * k);
     T one_e = 1.0f + e;
     return e * norm * m_rcp(one_e * one_e);
 }
@@ -125,7 +130,7 @@ template <class T> __device__ inline T trimmed_logistic(T x, T inv_s, T norm) {
 template <class T> __device__ inline T periodic_cdf(T x, const MatConst& m) {
     float k = floorf((m_val(x) + kPi) * kInvTwoPi);
     T y = x - kTwoPi * k;
-    return T(k) + (m_rcp(1.0f + m_exp(-y * m.inv_s)) - m.cdf_lo) * m.cdf_scale;
+    return T(k) + (m_rcp(1.0f + m_exp2(-y * m.inv_s_l2)) - m.cdf_lo) * m.cdf_scale;
 }
 
 template <class T> __device__ inline T fresnel(T cos_i, const MatConst& m) {
@@ -179,8 +184,9 @@ template <class T> struct Atten {
     T gamma_t;
 };
 
+// sigl: absorption times log2(e)
 template <class T>
-__device__ inline Atten<T> attenuation(const LightView& v, T h, T cgo, const T sig[3], const MatConst& m) {
+__device__ inline Atten<T> attenuation(const LightView& v, T h, T cgo, const T sigl[3], const MatConst& m) {
     Atten<T> o;
     T sgt = h * v.inv_eta_p;
     o.gamma_t = m_asin(sgt);
@@ -190,7 +196,7 @@ __device__ inline Atten<T> attenuation(const LightView& v, T h, T cgo, const T s
     T one_f = 1.0f - F;
     T one_f2 = one_f * one_f;
     for (int c = 0; c < 3; ++c) {
-        T Tc = m_exp(-sig[c] * path);
+        T Tc = m_exp2(-sigl[c] * path);
         o.A[0][c] = F;
         o.A[1][c] = one_f2 * Tc;
         o.A[2][c] = one_f2 * F * Tc * Tc;
@@ -199,20 +205,21 @@ __device__ inline Atten<T> attenuation(const LightView& v, T h, T cgo, const T s
 }
 
 template <class T> __device__ inline T exit_azimuth(int p, T gamma_o, T gamma_t) {
-    return (2.0f * p) * gamma_t - 2.0f * gamma_o + p * kPi;
+    const T g2 = -2.0f * gamma_o;
+    return p == 0 ? g2 : (p == 1 ? (g2 + 2.0f * gamma_t) + kPi : (g2 + 4.0f * gamma_t) + kTwoPi);
 }
 
 // Single-fibre BCSDF, RGB (gamma_o = asin h, cgo = cos gamma_o).
 template <class T>
-__device__ inline void f_single(const LightView& v, T h, T gamma_o, T cgo, const T sig[3], const MatConst& m,
+__device__ inline void f_single(const LightView& v, T h, T gamma_o, T cgo, const T sigl[3], const MatConst& m,
                                 T out[3]) {
-    Atten<T> at = attenuation(v, h, cgo, sig, m);
-    const T inv_s = T(m.inv_s), norm = T(m.n_norm);
+    Atten<T> at = attenuation(v, h, cgo, sigl, m);
+    const T ks = T(m.inv_s_l2), norm = T(m.n_norm);
     out[0] = out[1] = out[2] = T(0.0f);
     for (int p = 0; p < 3; ++p) {
         const float x = v.theta_h - m.alpha_p[p];
-        const float M = m.g_amp[p] * m_exp(-m.g_k[p] * (x * x));
-        T N = trimmed_logistic(wrap_pi(v.phi - exit_azimuth(p, gamma_o, at.gamma_t)), inv_s, norm);
+        const float M = m.g_amp[p] * m_exp2(-m.g_k2[p] * (x * x));
+        T N = trimmed_logistic(wrap_pi(v.phi - exit_azimuth(p, gamma_o, at.gamma_t)), ks, norm);
         T MN = M * N;
         for (int c = 0; c < 3; ++c) out[c] = out[c] + at.A[p][c] * MN;
     }
@@ -220,14 +227,14 @@ __device__ inline void f_single(const LightView& v, T h, T gamma_o, T cgo, const
 
 // Hemisphere albedos a_F, a_B (RGB) and variances sigma_f^2, sigma_b^2 at the light's x_d.
 template <class T>
-__device__ inline void hemisphere_stats(const LightView& v, const T sig[3], const MatConst& m, T aF[3], T aB[3],
+__device__ inline void hemisphere_stats(const LightView& v, const T sigl[3], const MatConst& m, T aF[3], T aB[3],
                                         T& var_f, T& var_b) {
     T wF[3], wB[3];
     for (int c = 0; c < 3; ++c) aF[c] = aB[c] = T(0.0f);
     for (int p = 0; p < 3; ++p) wF[p] = wB[p] = T(0.0f);
     for (int k = 0; k < 8; ++k) {
         const T go = T(kGLgo[k]);
-        Atten<T> at = attenuation(v, T(kGLx[k]), T(kGLcgo[k]), sig, m);
+        Atten<T> at = attenuation(v, T(kGLx[k]), T(kGLcgo[k]), sigl, m);
         float wk = 0.5f * kGLw[k];
         for (int p = 0; p < 3; ++p) {
             T mu = exit_azimuth(p, go, at.gamma_t);
@@ -267,13 +274,13 @@ template <class T> struct ClusterFrag {
 
 // Aggregated BCSDF, RGB.
 template <class T>
-__device__ inline void f_ours(const LightView& v, T h, T gamma_o, T cgo, const T sig[3], const MatConst& m,
+__device__ inline void f_ours(const LightView& v, T h, T gamma_o, T cgo, const T sigl[3], const MatConst& m,
                               const ClusterFrag<T>& cf, T out[3]) {
     const bool back_hemi = fabsf(v.phi) < 0.5f * kPi;
     const bool multi = m_val(cf.n_total) >= 2.0f;
     T aF[3], aB[3], var_f, var_b;
-    hemisphere_stats(v, sig, m, aF, aB, var_f, var_b);
-    Atten<T> at = attenuation(v, h, cgo, sig, m);
+    hemisphere_stats(v, sigl, m, aF, aB, var_f, var_b);
+    Atten<T> at = attenuation(v, h, cgo, sigl, m);
     T nm1 = cf.n_F - 1.0f;
     T extra = nm1 * var_f;
     T s_bar = kSqrt3 * m_sqrt(T(m.beta_n * m.beta_n) + extra) / kPi;
@@ -284,7 +291,7 @@ __device__ inline void f_ours(const LightView& v, T h, T gamma_o, T cgo, const T
     for (int c = 0; c < 3; ++c) out[c] = T(0.0f);
     for (int p = 0; p < 3; ++p) {
         T M = 0.5f * gaussian(m_sqrt(T(m.beta_p[p] * m.beta_p[p]) + extra), T(v.theta_h - m.alpha_p[p]));
-        T N = trimmed_logistic(wrap_pi(v.phi - exit_azimuth(p, gamma_o, at.gamma_t)), inv_sb, norm);
+        T N = trimmed_logistic(wrap_pi(v.phi - exit_azimuth(p, gamma_o, at.gamma_t)), inv_sb * kLog2e, norm);
         T MN = M * N;
         for (int c = 0; c < 3; ++c) out[c] = out[c] + fwd[c] * at.A[p][c] * MN;
     }
@@ -317,3 +324,5 @@ __device__ inline void f_ours(const LightView& v, T h, T gamma_o, T cgo, const T
 }
 
 }  // namespace hair
+
+#pragma clang fp contract(off)
