@@ -71,7 +71,7 @@ struct hair_ws {
     hair_ctx* ctx = nullptr;
     uint64_t max_bytes = 0;
     uint64_t held = 0;
-    DevBuf seg, shade, scan_tmp, tile_cnt, tile_start, tile_cur, list, ctr;
+    DevBuf seg, shade, scan_tmp, tile_cnt, tile_start, bin_m, bin_blk, list, ctr;
     DevBuf items, item_start, item_base, pix_cnt, pix_kmin, pix_kmax, pix_off;
     DevBuf tile_tot, frag_base, tile_nb, batch_start, batches, frags;
     hipEvent_t ev[7] = {};
@@ -300,9 +300,10 @@ struct FrameOut {
 };
 
 // Project + bin + tile for one level; the caller holds ws->mu.
-//   k_project, k_scan                 per-segment records, per-tile counts and list offsets
+//   k_project                         per-segment records (projection, half-width, culling)
+//   k_bin_count, k_bin_offsets, k_scan per-block tile counts, their column scan, list offsets
 //   k_tile_items, k_scan              work items (list chunks) per tile      -> sync 1 (sizes)
-//   k_scatter                         tile lists
+//   k_scatter                         tile lists (per-block LDS cursors)
 //   k_count, k_tile_prep, k_scan x2   per-pixel counts / key ranges, offsets, batches -> sync 2
 //   k_batch_records, k_emit           batch table, fragment buffer
 //   k_batch                           sort, shade, blend (one workgroup per batch)
@@ -313,33 +314,32 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     const CamConst cc = cam_const(cam);
     const int ntx = (cam->width + kTile - 1) / kTile, nty = (cam->height + kTile - 1) / kTile;
     const int T = ntx * nty;
-    const int TS = T * kSub;   // (tile, sub-counter) slots
     const size_t TP = (size_t)T * kTilePix;
+    const BinPlan plan = bin_plan(lv.nseg, T);
     if ((rc = ws_events(ws))) return rc;
     if ((rc = ws_need(ws, ws->seg, sizeof(SegRec) * (size_t)std::max(lv.nseg, 1)))) return rc;
     if ((rc = ws_need(ws, ws->shade, sizeof(ShadeRec) * (size_t)std::max(lv.nseg, 1)))) return rc;
-    if ((rc = ws_need(ws, ws->scan_tmp, 4 * exscan_scratch_words(TS)))) return rc;
-    if ((rc = ws_need(ws, ws->tile_cnt, 4ull * TS))) return rc;
-    if ((rc = ws_need(ws, ws->tile_start, 4ull * (TS + 1)))) return rc;
-    if ((rc = ws_need(ws, ws->tile_cur, 4ull * TS))) return rc;
+    if ((rc = ws_need(ws, ws->scan_tmp, 4 * exscan_scratch_words(T)))) return rc;
+    if ((rc = ws_need(ws, ws->tile_cnt, 4ull * T))) return rc;
+    if ((rc = ws_need(ws, ws->tile_start, 4ull * (T + 1)))) return rc;
+    if ((rc = ws_need(ws, ws->bin_m, 4ull * plan.nb * T))) return rc;
+    if ((rc = ws_need(ws, ws->bin_blk, 16ull * plan.nb))) return rc;
     if ((rc = ws_need(ws, ws->ctr, sizeof(Counters)))) return rc;
     if ((rc = ws_need(ws, ws->items, 4ull * T))) return rc;
     if ((rc = ws_need(ws, ws->item_start, 4ull * (T + 1)))) return rc;
-    uint32_t* tile_cnt = ws->tile_cnt.as<uint32_t>();
     uint32_t* tile_start = ws->tile_start.as<uint32_t>();
-    HIP_TRY(ctx, hipEventRecord(ws->ev[0], st), "hipEventRecord");
-    HIP_TRY(ctx, launch_fill_u32(tile_cnt, 0u, TS, st), "fill");
-    HIP_TRY(ctx, launch_fill_u32(ws->tile_cur.as<uint32_t>(), 0u, TS, st), "fill");
-    HIP_TRY(ctx, launch_fill_u32(ws->ctr.as<uint32_t>(), 0u, sizeof(Counters) / 4, st), "fill");
     uint32_t* scan_tmp = ws->scan_tmp.as<uint32_t>();
-    HIP_TRY(ctx, launch_project(lv, cc, ws->seg.as<SegRec>(), ws->shade.as<ShadeRec>(), tile_cnt, ws->ctr.as<Counters>(),
-                                st), "k_project");
-    HIP_TRY(ctx, launch_exscan(tile_cnt, tile_start, TS, scan_tmp, st), "k_scan");
+    HIP_TRY(ctx, hipEventRecord(ws->ev[0], st), "hipEventRecord");
+    HIP_TRY(ctx, launch_fill_u32(ws->ctr.as<uint32_t>(), 0u, sizeof(Counters) / 4, st), "fill");
+    HIP_TRY(ctx, launch_project(lv, cc, ws->seg.as<SegRec>(), ws->shade.as<ShadeRec>(), st), "k_project");
+    HIP_TRY(ctx, launch_bins(ws->seg.as<SegRec>(), lv.nseg, cc, plan, ws->bin_m.as<uint32_t>(), ws->bin_blk.as<uint4>(),
+                             ws->tile_cnt.as<uint32_t>(), tile_start, ws->ctr.as<Counters>(), scan_tmp, st),
+            "k_bin_count");
     HIP_TRY(ctx, launch_tile_items(tile_start, T, ws->items.as<uint32_t>(), st), "k_tile_items");
     HIP_TRY(ctx, launch_exscan(ws->items.as<uint32_t>(), ws->item_start.as<uint32_t>(), T, scan_tmp, st), "k_scan");
     HIP_TRY(ctx, hipEventRecord(ws->ev[1], st), "hipEventRecord");
     uint32_t sizes1[2] = {0, 0};
-    HIP_TRY(ctx, hipMemcpyAsync(&sizes1[0], tile_start + TS, 4, hipMemcpyDeviceToHost, st), "copy");
+    HIP_TRY(ctx, hipMemcpyAsync(&sizes1[0], tile_start + T, 4, hipMemcpyDeviceToHost, st), "copy");
     HIP_TRY(ctx, hipMemcpyAsync(&sizes1[1], ws->item_start.as<uint32_t>() + T, 4, hipMemcpyDeviceToHost, st), "copy");
     HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
     const uint32_t pairs = sizes1[0], n_items = sizes1[1];
@@ -379,7 +379,7 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     f.batch_start = ws->batch_start.as<uint32_t>();
     f.ctr = ws->ctr.as<Counters>();
     HIP_TRY(ctx, hipEventRecord(ws->ev[2], st), "hipEventRecord");
-    HIP_TRY(ctx, launch_scatter(f.seg, lv.nseg, cc, tile_start, ws->tile_cur.as<uint32_t>(), ws->list.as<uint32_t>(), st),
+    HIP_TRY(ctx, launch_scatter(f.seg, lv.nseg, cc, plan, tile_start, ws->bin_m.as<uint32_t>(), ws->list.as<uint32_t>(), st),
             "k_scatter");
     HIP_TRY(ctx, launch_fill_u32(f.pix_cnt, 0u, TP, st), "fill");
     HIP_TRY(ctx, launch_fill_u32(f.pix_kmin, 0xFFFFFFFFu, TP, st), "fill");
@@ -505,7 +505,7 @@ int hair_ws_destroy(hair_ws* ws) {
     if (!ws) return fail(HAIR_EINVAL, "null workspace");
     hair_ctx* ctx = ws->ctx;
     if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
-    for (DevBuf* b : {&ws->seg, &ws->shade, &ws->scan_tmp, &ws->tile_cnt, &ws->tile_start, &ws->tile_cur, &ws->list, &ws->ctr, &ws->items,
+    for (DevBuf* b : {&ws->seg, &ws->shade, &ws->scan_tmp, &ws->tile_cnt, &ws->tile_start, &ws->bin_m, &ws->bin_blk, &ws->list, &ws->ctr, &ws->items,
                       &ws->item_start, &ws->item_base, &ws->pix_cnt, &ws->pix_kmin, &ws->pix_kmax, &ws->pix_off,
                       &ws->tile_tot, &ws->frag_base, &ws->tile_nb, &ws->batch_start, &ws->batches, &ws->frags})
         ctx_free(ctx, *b, ws);
@@ -525,10 +525,13 @@ uint64_t hair_ws_estimate(int64_t n_segments, int32_t width, int32_t height, int
     const uint64_t P = (uint64_t)pairs_estimate;
     const uint64_t items = T + P / kTilePix + 1;
     const uint64_t frags = 8 * P;   // fragments per (tile, segment) pair at strand widths ~ 4-5
+    // per-block tile counts (4 B per block and tile) and statistics (16 B per block, bounded by T)
+    const uint64_t bin_nb = (uint64_t)bin_plan((int32_t)std::min<int64_t>(n_segments, INT32_MAX), (int32_t)T).nb;
     const uint64_t raw = (sizeof(SegRec) + sizeof(ShadeRec)) * (uint64_t)std::max<int64_t>(n_segments, 1) +
-                         4ull * 3 * (T * kSub + 1) + 4ull * (2 * T + 2) + 4 * P + 4ull * kTilePix * items +
+                         4ull * (2 * T + 1) + 20ull * bin_nb * T +
+                         4ull * (2 * T + 2) + 4 * P + 4ull * kTilePix * items +
                          4ull * 4 * T * kTilePix + 4ull * 4 * (T + 1) + 8 * frags + 16 * (T + frags / 512) +
-                         sizeof(Counters) + 4 * exscan_scratch_words(T * kSub);
+                         sizeof(Counters) + 4 * exscan_scratch_words(T);
     return raw + raw / 4 + 24 * 256;
 }
 
@@ -920,11 +923,9 @@ int hair_debug_bins(hair_ws* ws, int64_t n_tiles, uint32_t* tile_start, int64_t 
         return fail(HAIR_EINVAL, "last render had %lld tiles and %lld pairs", (long long)ws->last_ntiles,
                     (long long)ws->last_pairs);
     std::lock_guard<std::mutex> g(ws->mu);
-    std::vector<uint32_t> full((size_t)n_tiles * kSub + 1);
-    hipError_t e = hipMemcpy(full.data(), ws->tile_start.p, 4 * full.size(), hipMemcpyDeviceToHost);
+    hipError_t e = hipMemcpy(tile_start, ws->tile_start.p, 4 * (size_t)(n_tiles + 1), hipMemcpyDeviceToHost);
     if (e == hipSuccess && n_pairs) e = hipMemcpy(tile_segs, ws->list.p, 4 * n_pairs, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return dev_fail(ws->ctx, e, "debug_bins");
-    for (int64_t t = 0; t <= n_tiles; ++t) tile_start[t] = full[(size_t)t * kSub];
     return HAIR_OK;
 }
 

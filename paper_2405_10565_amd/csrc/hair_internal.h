@@ -15,7 +15,8 @@ constexpr int kGuard = 16384;                    // guard band, 1/16-px units (1
 constexpr int kMaxAxis = 16384;                  // longest segment extent per axis (1/16 px)
 constexpr int kMaxHwFx = 4096;                   // widest coverage half-width (1/16 px)
 constexpr int kMaxListLen = (1 << 24) - 1;       // per-tile list limit (24-bit local index)
-constexpr int kSub = 16;                         // counters per tile (spreads binning atomics)
+constexpr int kBinThreads = 512;                 // threads per binning block
+constexpr int kMaxLdsTiles = 36864;              // per-tile LDS counters of one binning pass (144 KiB)
 
 // Projected segment, one per segment of the rendered level (32 bytes, AoS for gathers).
 struct SegRec {
@@ -125,7 +126,7 @@ struct FrameBufs {
     int32_t T, ntx;
     const SegRec* seg;
     const ShadeRec* shade;
-    const uint32_t* tile_start;   // [T * kSub + 1]: tile t's list is [tile_start[t kSub], tile_start[(t+1) kSub])
+    const uint32_t* tile_start;   // [T + 1]: tile t's list is [tile_start[t], tile_start[t + 1])
     const uint32_t* list;         // segment ids
     const uint32_t* item_start;   // [T + 1] exclusive scan of per-tile work items
     uint32_t* item_base;          // [items][kTilePix] each item's slice of each pixel's range
@@ -143,15 +144,26 @@ struct FrameBufs {
 };
 
 // Kernel launchers (hair_kernels.hip).
-hipError_t launch_project(const LevelDev& lv, const CamConst& cam, SegRec* seg, ShadeRec* shade, uint32_t* tile_cnt,
-                          Counters* ctr, hipStream_t st);
+hipError_t launch_project(const LevelDev& lv, const CamConst& cam, SegRec* seg, ShadeRec* shade, hipStream_t st);
 // Exclusive scan of n counts into start[0..n] (start[n] = total); scratch holds
 // 2 * ceil(n / 4096) + 2 words.
 hipError_t launch_exscan(const uint32_t* cnt, uint32_t* start, int32_t n, uint32_t* scratch, hipStream_t st);
 constexpr int kScanChunk = 4096;
 inline size_t exscan_scratch_words(size_t n) { return 2 * ((n + kScanChunk - 1) / kScanChunk) + 2; }
-hipError_t launch_scatter(const SegRec* seg, int32_t nseg, const CamConst& cam, const uint32_t* tile_start,
-                          uint32_t* tile_cur, uint32_t* list, hipStream_t st);
+// Binning blocks: nb blocks of kBinThreads own per_block consecutive segments each; tiles are
+// counted in passes of `range` tiles.  The per-block count matrix M holds nb * T words.
+struct BinPlan {
+    int nb, per_block, range;
+};
+BinPlan bin_plan(int32_t nseg, int32_t T);
+// M (nb * T words), blk (nb entries), tot (T words), tile_start (T + 1 words): per-block counts
+// and segment statistics, tile totals and list offsets of the projected segments; ctr receives
+// the visible / culled counts and the largest half-width.
+hipError_t launch_bins(const SegRec* seg, int32_t nseg, const CamConst& cam, const BinPlan& p, uint32_t* M,
+                       uint4* blk, uint32_t* tot, uint32_t* tile_start, Counters* ctr, uint32_t* scan_tmp,
+                       hipStream_t st);
+hipError_t launch_scatter(const SegRec* seg, int32_t nseg, const CamConst& cam, const BinPlan& p,
+                          const uint32_t* tile_start, const uint32_t* M, uint32_t* list, hipStream_t st);
 hipError_t launch_tile_items(const uint32_t* tile_start, int T, uint32_t* items, hipStream_t st);
 hipError_t launch_count(const FrameBufs& f, const CamConst& cam, uint32_t n_items, hipStream_t st);
 hipError_t launch_tile_prep(const FrameBufs& f, hipStream_t st);

@@ -16,6 +16,8 @@
 //                    segmented scan, coalesced RGBA stores.
 // The integer-deciding steps (projection, snapping, half-width, depth key) are float32 with
 // one rounding per operation and no contraction, so they match a float32 reference bit for bit.
+#include <algorithm>
+
 #include "hair_internal.h"
 #include "hair_shading.h"
 #include "hair_dual.h"
@@ -28,9 +30,7 @@ namespace {
 constexpr int kNT = 256;                   // threads per tile block (= pixels per tile)
 constexpr int kPerThread = kCap / kNT;     // LDS batch fragments per thread
 
-__device__ inline long long floordiv(long long a, long long b) {  // b > 0
-    return a >= 0 ? a / b : -((-a + b - 1) / b);
-}
+static_assert(kTile == 16, "the shifts below assume 16-pixel tiles in 1/16-pixel units");
 
 __device__ inline int wave_max(int v) {
     for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off));
@@ -104,30 +104,24 @@ struct TileRect {
     int tx0, tx1, ty0, ty1;
 };
 
+// Tiles overlapped by the segment's integer box widened by its radius (x >> 8 = floor(x / 256),
+// a 16-pixel tile in 1/16-pixel units; coordinates of a visible segment fit 32 bits).
 __device__ inline TileRect tile_rect(const SegRec& s, int ntx, int nty) {
-    const long long R = (long long)(s.hwfx & kHwMask) + 8;
-    const long long T16 = 16LL * kTile;
-    const long long lox = (long long)min(s.xa, s.xb) - R, hix = (long long)max(s.xa, s.xb) + R;
-    const long long loy = (long long)min(s.ya, s.yb) - R, hiy = (long long)max(s.ya, s.yb) + R;
+    const int R = (s.hwfx & kHwMask) + 8;
+    const int lox = min(s.xa, s.xb) - R, hix = max(s.xa, s.xb) + R;
+    const int loy = min(s.ya, s.yb) - R, hiy = max(s.ya, s.yb) + R;
     TileRect r;
-    r.tx0 = (int)max(floordiv(lox, T16), 0LL);
-    r.tx1 = (int)min(floordiv(hix, T16), (long long)ntx - 1);
-    r.ty0 = (int)max(floordiv(loy, T16), 0LL);
-    r.ty1 = (int)min(floordiv(hiy, T16), (long long)nty - 1);
+    r.tx0 = max(lox >> 8, 0);
+    r.tx1 = min(hix >> 8, ntx - 1);
+    r.ty0 = max(loy >> 8, 0);
+    r.ty1 = min(hiy >> 8, nty - 1);
     return r;
 }
 
 __global__ __launch_bounds__(256) void k_project(LevelDev lv, CamConst cam, SegRec* __restrict__ seg,
-                                                 ShadeRec* __restrict__ shade, uint32_t* __restrict__ tile_cnt,
-                                                 Counters* __restrict__ ctr) {
-    __shared__ uint32_t s_maxhw;
-    if (threadIdx.x == 0) s_maxhw = 0;
-    __syncthreads();
+                                                 ShadeRec* __restrict__ shade) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    const int ntx = (cam.W + kTile - 1) / kTile, nty = (cam.H + kTile - 1) / kTile;
-    bool vis = false, culled_long = false;
-    TileRect rect{0, -1, 0, -1};
-    int ntile = 0;
+    bool vis = false;
     if (g < lv.nseg) {
         const int owner = g / lv.S, k = g - owner * lv.S;
         const int va = owner * (lv.S + 1) + k;
@@ -171,7 +165,6 @@ __global__ __launch_bounds__(256) void k_project(LevelDev lv, CamConst cam, SegR
             const float c16 = ceilf(hw16);
             if (abs(r.xb - r.xa) > kMaxAxis || abs(r.yb - r.ya) > kMaxAxis || c16 > (float)kMaxHwFx) {
                 vis = false;
-                culled_long = true;
                 r.hwfx = kFlagCulledLong;
             } else {
                 r.hwfx = (int)c16 | kFlagVisible;
@@ -203,36 +196,6 @@ __global__ __launch_bounds__(256) void k_project(LevelDev lv, CamConst cam, SegR
             }
         }
         seg[g] = r;
-        if (vis) atomicMax(&s_maxhw, __float_as_uint(hw));
-        rect = tile_rect(r, ntx, nty);
-        if (vis) ntile = (rect.tx1 - rect.tx0 + 1) * (rect.ty1 - rect.ty0 + 1);
-        if (ntile < 0) ntile = 0;
-    }
-    // per-tile counts, one atomic per distinct tile per wave (lanes are consecutive segments
-    // of a few strands and mostly share tiles)
-    {
-        const int sub = (g >> 8) & (kSub - 1);
-        const int nmax = wave_max(ntile);
-        const int nx = max(1, rect.tx1 - rect.tx0 + 1);
-        for (int j = 0; j < nmax; ++j) {
-            const bool has = j < ntile;
-            const int tl = has ? ((rect.ty0 + j / nx) * ntx + rect.tx0 + j % nx) * kSub + sub : -1;
-            unsigned long long rem = __ballot(has);
-            while (rem) {
-                const int leader = __ffsll((long long)rem) - 1;
-                const int tsel = __shfl(tl, leader);
-                const unsigned long long same = __ballot(tl == tsel) & rem;
-                if ((int)__lane_id() == leader) atomicAdd(&tile_cnt[tsel], (uint32_t)__popcll(same));
-                rem &= ~same;
-            }
-        }
-    }
-    const int nvis = __syncthreads_count(vis);
-    const int nlong = __syncthreads_count(culled_long);
-    if (threadIdx.x == 0) {
-        if (nvis) atomicAdd(&ctr->visible, (uint32_t)nvis);
-        if (nlong) atomicAdd(&ctr->culled_long, (uint32_t)nlong);
-        if (s_maxhw) atomicMax(&ctr->max_hw_bits, s_maxhw);
     }
 }
 
@@ -300,39 +263,137 @@ __global__ __launch_bounds__(1024) void k_scan_add(uint32_t* __restrict__ out, c
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = base[nblocks];
 }
 
-__global__ __launch_bounds__(256) void k_scatter(const SegRec* __restrict__ seg, int nseg, int ntx, int nty,
-                                                 const uint32_t* __restrict__ tile_start,
-                                                 uint32_t* __restrict__ tile_cur, uint32_t* __restrict__ list) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    TileRect rect{0, -1, 0, -1};
-    int ntile = 0;
-    if (g < nseg) {
+// Tile binning without device-wide atomics.  Block b owns the contiguous segment range
+// [b per_block, (b + 1) per_block) and counts, in LDS, its segments per tile of the range
+// [t0, t0 + nt) (the whole image unless it has more than kMaxLdsTiles tiles); the counts form
+// row b of M [nb][T].  A column-wise exclusive scan of M gives each block its place inside
+// every tile list, and the scatter pass appends each segment at its block's LDS cursors.
+template <class F>
+__device__ inline void for_each_tile_in_range(const SegRec& r, int ntx, int nty, int t0, int nt, F&& f) {
+    if (!(r.hwfx & kFlagVisible)) return;
+    const TileRect rc = tile_rect(r, ntx, nty);
+    for (int ty = rc.ty0; ty <= rc.ty1; ++ty)
+        for (int tx = rc.tx0; tx <= rc.tx1; ++tx) {
+            const int l = ty * ntx + tx - t0;
+            if ((unsigned)l < (unsigned)nt) f(l);
+        }
+}
+
+// The first pass also leaves per-block segment statistics in blk[b] = (visible, culled as too
+// long, bits of the largest visible half-width) for k_bin_offsets to reduce.
+__global__ __launch_bounds__(kBinThreads) void k_bin_count(const SegRec* __restrict__ seg, int nseg, int per_block,
+                                                           int ntx, int nty, int t0, int nt,
+                                                           uint32_t* __restrict__ M, uint4* __restrict__ blk) {
+    extern __shared__ uint32_t s_tc[];
+    __shared__ uint32_t s_maxhw;
+    const int T = ntx * nty;
+    for (int i = threadIdx.x; i < nt; i += kBinThreads) s_tc[i] = 0;
+    if (threadIdx.x == 0) s_maxhw = 0;
+    __syncthreads();
+    const int g0 = blockIdx.x * per_block, g1 = min(nseg, g0 + per_block);
+    uint32_t nvis = 0, nlong = 0, maxhw = 0;
+    for (int g = g0 + (int)threadIdx.x; g < g1; g += kBinThreads) {
         const SegRec r = seg[g];
         if (r.hwfx & kFlagVisible) {
-            rect = tile_rect(r, ntx, nty);
-            ntile = max(0, (rect.tx1 - rect.tx0 + 1) * (rect.ty1 - rect.ty0 + 1));
+            ++nvis;
+            maxhw = max(maxhw, __float_as_uint(r.hw));
+        }
+        nlong += (r.hwfx & kFlagCulledLong) ? 1u : 0u;
+        for_each_tile_in_range(r, ntx, nty, t0, nt, [&](int l) { atomicAdd(&s_tc[l], 1u); });
+    }
+    if (t0 == 0) {
+        if (maxhw) atomicMax(&s_maxhw, maxhw);
+        uint32_t v = nvis, c = nlong;
+        for (int off = 32; off >= 1; off >>= 1) {
+            v += __shfl_xor(v, off);
+            c += __shfl_xor(c, off);
+        }
+        __shared__ uint32_t s_v[kBinThreads / 64], s_c[kBinThreads / 64];
+        if ((threadIdx.x & 63) == 0) {
+            s_v[threadIdx.x >> 6] = v;
+            s_c[threadIdx.x >> 6] = c;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tv = 0, tc = 0;
+            for (int w = 0; w < kBinThreads / 64; ++w) {
+                tv += s_v[w];
+                tc += s_c[w];
+            }
+            blk[blockIdx.x] = make_uint4(tv, tc, s_maxhw, 0u);
         }
     }
-    // one atomic per distinct tile per wave; lanes take consecutive slots in lane order
-    const int sub = (g >> 8) & (kSub - 1);
-    const int nmax = wave_max(ntile);
-    const int nx = max(1, rect.tx1 - rect.tx0 + 1);
-    const unsigned long long lt = (1ull << __lane_id()) - 1ull;
-    for (int j = 0; j < nmax; ++j) {
-        const bool has = j < ntile;
-        const int tl = has ? ((rect.ty0 + j / nx) * ntx + rect.tx0 + j % nx) * kSub + sub : -1;
-        unsigned long long rem = __ballot(has);
-        while (rem) {
-            const int leader = __ffsll((long long)rem) - 1;
-            const int tsel = __shfl(tl, leader);
-            const unsigned long long same = __ballot(tl == tsel) & rem;
-            uint32_t base = 0;
-            if ((int)__lane_id() == leader) base = atomicAdd(&tile_cur[tsel], (uint32_t)__popcll(same));
-            base = __shfl(base, leader);
-            if ((same >> __lane_id()) & 1ull) list[tile_start[tsel] + base + (uint32_t)__popcll(same & lt)] = (uint32_t)g;
-            rem &= ~same;
+    __syncthreads();
+    uint32_t* row = M + (size_t)blockIdx.x * T + t0;
+    for (int i = threadIdx.x; i < nt; i += kBinThreads) row[i] = s_tc[i];
+}
+
+// Column-wise exclusive scan of M: M[b][t] <- sum of M[b'][t] over b' < b, tot[t] = column sum.
+// A block takes 64 tiles (one per lane) and its 16 waves split the rows into 16 ranges: each
+// wave sums its range, the range offsets come from LDS, and a second walk writes the prefixes.
+// Block 0 also reduces the per-block segment statistics into ctr.
+__global__ __launch_bounds__(1024) void k_bin_offsets(uint32_t* __restrict__ M, int nb, int T,
+                                                      uint32_t* __restrict__ tot, const uint4* __restrict__ blk,
+                                                      Counters* __restrict__ ctr) {
+    __shared__ uint32_t s_part[16][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int t = blockIdx.x * 64 + lane;
+    const int rows = (nb + 15) / 16, r0 = min(nb, w * rows), r1 = min(nb, r0 + rows);
+    uint32_t sum = 0;
+    if (t < T) {
+#pragma unroll 8
+        for (int b = r0; b < r1; ++b) sum += M[(size_t)b * T + t];
+    }
+    s_part[w][lane] = sum;
+    __syncthreads();
+    uint32_t run = 0, total = 0;
+    for (int w2 = 0; w2 < 16; ++w2) {
+        const uint32_t v = s_part[w2][lane];
+        if (w2 < w) run += v;
+        total += v;
+    }
+    if (t < T) {
+        for (int b = r0; b < r1; ++b) {
+            const size_t q = (size_t)b * T + t;
+            const uint32_t v = M[q];
+            M[q] = run;
+            run += v;
+        }
+        if (w == 0) tot[t] = total;
+    }
+    if (blockIdx.x == 0 && w == 0) {
+        uint32_t v = 0, c = 0, m = 0;
+        for (int b = lane; b < nb; b += 64) {
+            const uint4 x = blk[b];
+            v += x.x;
+            c += x.y;
+            m = max(m, x.z);
+        }
+        for (int off = 32; off >= 1; off >>= 1) {
+            v += __shfl_xor(v, off);
+            c += __shfl_xor(c, off);
+            m = max(m, (uint32_t)__shfl_xor((int)m, off));
+        }
+        if (lane == 0) {
+            ctr->visible = v;
+            ctr->culled_long = c;
+            ctr->max_hw_bits = m;
         }
     }
+}
+
+__global__ __launch_bounds__(kBinThreads) void k_scatter(const SegRec* __restrict__ seg, int nseg, int per_block,
+                                                         int ntx, int nty, int t0, int nt,
+                                                         const uint32_t* __restrict__ tile_start,
+                                                         const uint32_t* __restrict__ M, uint32_t* __restrict__ list) {
+    extern __shared__ uint32_t s_tc[];
+    const int T = ntx * nty;
+    const uint32_t* row = M + (size_t)blockIdx.x * T + t0;
+    for (int i = threadIdx.x; i < nt; i += kBinThreads) s_tc[i] = tile_start[t0 + i] + row[i];
+    __syncthreads();
+    const int g0 = blockIdx.x * per_block, g1 = min(nseg, g0 + per_block);
+    for (int g = g0 + (int)threadIdx.x; g < g1; g += kBinThreads)
+        for_each_tile_in_range(seg[g], ntx, nty, t0, nt, [&](int l) { list[atomicAdd(&s_tc[l], 1u)] = (uint32_t)g; });
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
@@ -349,24 +410,28 @@ __global__ void k_fill_f32(float* p, float v, size_t n) {
 template <class F>
 __device__ inline void for_each_fragment(const SegRec& s, int px0, int py0, int row_lo, int row_hi, int W, int H,
                                          F&& f) {
-    const long long ax = s.xa, ay = s.ya;
-    const long long dx = (long long)s.xb - ax, dy = (long long)s.yb - ay;
-    const long long tden = dx * dx + dy * dy;
+    // 32-bit integers are exact here: endpoints lie inside the guard band, |dx|, |dy| <= kMaxAxis
+    // (longer segments are culled), the radius is <= kMaxHwFx + 8 and every candidate pixel centre
+    // lies in the segment's box widened by the radius, so |ex|, |ey| < 2^15 and each product
+    // below stays under 2^31; cr^2 and R^2 t_den are compared in 64 bits.  x >> 4 is floor(x / 16).
+    const int ax = s.xa, ay = s.ya;
+    const int dx = s.xb - ax, dy = s.yb - ay;
+    const int tden = dx * dx + dy * dy;
     if (tden <= 0) return;
-    const long long R = (long long)(s.hwfx & kHwMask) + 8;
-    const long long RR = R * R * tden;
-    const long long lox = min(ax, (long long)s.xb) - R, hix = max(ax, (long long)s.xb) + R;
-    const long long loy = min(ay, (long long)s.yb) - R, hiy = max(ay, (long long)s.yb) + R;
-    const int i0 = (int)max((long long)px0, floordiv(lox - 8, 16) + 1);
-    const int i1 = (int)min((long long)min(px0 + kTile, W) - 1, -floordiv(-(hix - 8), 16) - 1);
-    const int j0 = (int)max((long long)(py0 + row_lo), floordiv(loy - 8, 16) + 1);
-    const int j1 = (int)min((long long)min(py0 + row_hi, H - 1), -floordiv(-(hiy - 8), 16) - 1);
+    const int R = (s.hwfx & kHwMask) + 8;
+    const unsigned long long RR = (unsigned long long)(unsigned)(R * R) * (unsigned)tden;
+    const int lox = min(ax, s.xb) - R, hix = max(ax, s.xb) + R;
+    const int loy = min(ay, s.yb) - R, hiy = max(ay, s.yb) + R;
+    const int i0 = max(px0, ((lox - 8) >> 4) + 1);
+    const int i1 = min(min(px0 + kTile, W) - 1, ((hix - 8 + 15) >> 4) - 1);
+    const int j0 = max(py0 + row_lo, ((loy - 8) >> 4) + 1);
+    const int j1 = min(min(py0 + row_hi, H - 1), ((hiy - 8 + 15) >> 4) - 1);
     if (i0 > i1 || j0 > j1) return;
     const double inv_dx = dx != 0 ? 1.0 / (double)dx : 0.0;
     const double inv_dy = dy != 0 ? 1.0 / (double)dy : 0.0;
     const double half = dy != 0 ? (double)R * sqrt((double)tden) * fabs(inv_dy) : 0.0;
     for (int j = j0; j <= j1; ++j) {
-        const long long ey = 16LL * j + 8 - ay;
+        const int ey = 16 * j + 8 - ay;
         double lo = -1e300, hi = 1e300;
         if (dx != 0) {
             const double a = (double)(-ey * dy) * inv_dx;
@@ -383,18 +448,20 @@ __device__ inline void for_each_fragment(const SegRec& s, int px0, int py0, int 
         const double fhi = ceil(((double)ax + hi - 8.0) * (1.0 / 16.0)) + 1.0;
         const int c0 = (int)fmax((double)i0, flo);
         const int c1 = (int)fmin((double)i1, fhi);
+        const int ey_dy = ey * dy, ey_dx = ey * dx;
         for (int i = c0; i <= c1; ++i) {
-            const long long ex = 16LL * i + 8 - ax;
-            const long long tnum = ex * dx + ey * dy;
+            const int ex = 16 * i + 8 - ax;
+            const int tnum = ex * dx + ey_dy;
             if (tnum < 0 || tnum >= tden) continue;
-            const long long cr = ex * dy - ey * dx;
-            if (cr * cr >= RR) continue;
+            const int cr = ex * dy - ey_dx;
+            const unsigned acr = (unsigned)abs(cr);
+            if ((unsigned long long)acr * acr >= RR) continue;
             f(i - px0, j - py0, tnum, tden, cr);
         }
     }
 }
 
-__device__ inline uint32_t depth_key(const SegRec& s, long long tnum, long long tden) {
+__device__ inline uint32_t depth_key(const SegRec& s, int tnum, int tden) {
     const float t = (float)tnum / (float)tden;
     const float iz = s.iza + t * (s.izb - s.iza);
     return 0xFFFFFFFFu - __float_as_uint(iz);
@@ -588,7 +655,7 @@ __global__ __launch_bounds__(256) void k_tile_items(const uint32_t* __restrict__
                                                     uint32_t* __restrict__ items) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= T) return;
-    const uint32_t n = tile_start[(t + 1) * kSub] - tile_start[t * kSub];
+    const uint32_t n = tile_start[t + 1] - tile_start[t];
     items[t] = (n + kNT - 1) / kNT;
 }
 
@@ -616,12 +683,12 @@ __global__ __launch_bounds__(kNT) void k_count(FrameBufs f, CamConst cam, uint32
     __syncthreads();
     const int tile = s_tile;
     const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
-    const uint32_t lstart = f.tile_start[tile * kSub];
-    const uint32_t n = f.tile_start[(tile + 1) * kSub] - lstart;
+    const uint32_t lstart = f.tile_start[tile];
+    const uint32_t n = f.tile_start[tile + 1] - lstart;
     const uint32_t j = s_chunk * kNT + t;
     if (j < n) {
         const SegRec s = f.seg[f.list[lstart + j]];
-        for_each_fragment(s, px0, py0, 0, kTile - 1, cam.W, cam.H, [&](int li, int lj, long long tnum, long long tden, long long) {
+        for_each_fragment(s, px0, py0, 0, kTile - 1, cam.W, cam.H, [&](int li, int lj, int tnum, int tden, int) {
             const int p = lj * kTile + li;
             const uint32_t key = depth_key(s, tnum, tden);
             atomicAdd(&s_cnt[p], 1u);
@@ -732,12 +799,12 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam, uint32_
     s_pos[t] = f.frag_base[tile] + f.pix_off[(size_t)tile * kTilePix + t] + f.item_base[(size_t)item * kTilePix + t];
     __syncthreads();
     const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
-    const uint32_t lstart = f.tile_start[tile * kSub];
-    const uint32_t n = f.tile_start[(tile + 1) * kSub] - lstart;
+    const uint32_t lstart = f.tile_start[tile];
+    const uint32_t n = f.tile_start[tile + 1] - lstart;
     const uint32_t j = s_chunk * kNT + t;
     if (j < n) {
         const SegRec s = f.seg[f.list[lstart + j]];
-        for_each_fragment(s, px0, py0, 0, kTile - 1, cam.W, cam.H, [&](int li, int lj, long long tnum, long long tden, long long) {
+        for_each_fragment(s, px0, py0, 0, kTile - 1, cam.W, cam.H, [&](int li, int lj, int tnum, int tden, int) {
             const int p = lj * kTile + li;
             const uint32_t key = depth_key(s, tnum, tden);
             const uint32_t slot = atomicAdd(&s_cur[p], 1u);
@@ -1071,7 +1138,7 @@ __global__ __launch_bounds__(kNT) void k_batch(FrameBufs f, ShadeArgs a, float* 
     const int t = threadIdx.x;
     const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
     const int W = a.cam.W, H = a.cam.H;
-    const uint32_t* list = f.list + f.tile_start[tile * kSub];
+    const uint32_t* list = f.list + f.tile_start[tile];
     const size_t q = (size_t)tile * kTilePix + t;
     const uint32_t tile_off0 = f.pix_off[(size_t)tile * kTilePix + p0];
     const uint2* src = f.frags + f.frag_base[tile] + tile_off0;
@@ -1238,8 +1305,8 @@ __global__ __launch_bounds__(kNT) void k_batch_bwd(FrameBufs f, ShadeArgs a, Gra
     if (br.w) return;
     const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
     const int W = a.cam.W, H = a.cam.H;
-    const uint32_t lstart = f.tile_start[tile * kSub];
-    const uint32_t n = f.tile_start[(tile + 1) * kSub] - lstart;
+    const uint32_t lstart = f.tile_start[tile];
+    const uint32_t n = f.tile_start[tile + 1] - lstart;
     const uint32_t* list = f.list + lstart;
     const size_t q = (size_t)tile * kTilePix + t;
     const uint32_t tile_off0 = f.pix_off[(size_t)tile * kTilePix + p0];
@@ -1530,11 +1597,47 @@ inline int blocks_for(size_t n, int per) { return (int)((n + per - 1) / per); }
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
-hipError_t launch_project(const LevelDev& lv, const CamConst& cam, SegRec* seg, ShadeRec* shade, uint32_t* tile_cnt,
-                          Counters* ctr, hipStream_t st) {
+hipError_t launch_project(const LevelDev& lv, const CamConst& cam, SegRec* seg, ShadeRec* shade, hipStream_t st) {
     if (lv.nseg == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_project, dim3(blocks_for(lv.nseg, 256)), dim3(256), 0, st, lv, cam, seg, shade, tile_cnt, ctr);
+    hipLaunchKernelGGL(k_project, dim3(blocks_for(lv.nseg, 256)), dim3(256), 0, st, lv, cam, seg, shade);
     return hipGetLastError();
+}
+
+BinPlan bin_plan(int32_t nseg, int32_t T) {
+    BinPlan p;
+    p.range = std::min(T, kMaxLdsTiles);
+    const int bytes = 4 * p.range;
+    const int per_cu = std::max(1, std::min(2, (160 * 1024) / (bytes + 2048)));
+    long nb = 256L * per_cu;
+    nb = std::min(nb, std::max(32L, (long)((1 << 24) / std::max(T, 1))));
+    nb = std::min(nb, std::max(1L, (long)((nseg + kBinThreads - 1) / kBinThreads)));
+    p.nb = (int)std::max(1L, nb);
+    p.per_block = (nseg + p.nb - 1) / p.nb;
+    return p;
+}
+
+// Dynamic LDS above 64 KiB is declared to the runtime first (gfx950 has 160 KiB per CU); a
+// runtime that needs no declaration may refuse the call, and the launch itself then decides.
+static hipError_t allow_lds(const void* fn, int bytes) {
+    if (bytes > 64 * 1024 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess)
+        (void)hipGetLastError();
+    return hipSuccess;
+}
+
+hipError_t launch_bins(const SegRec* seg, int32_t nseg, const CamConst& cam, const BinPlan& p, uint32_t* M,
+                       uint4* blk, uint32_t* tot, uint32_t* tile_start, Counters* ctr, uint32_t* scan_tmp,
+                       hipStream_t st) {
+    const int ntx = (cam.W + kTile - 1) / kTile, nty = (cam.H + kTile - 1) / kTile, T = ntx * nty;
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_bin_count), 4 * p.range);
+    if (e != hipSuccess) return e;
+    for (int t0 = 0; t0 < T; t0 += p.range) {
+        const int nt = std::min(p.range, T - t0);
+        hipLaunchKernelGGL(k_bin_count, dim3(p.nb), dim3(kBinThreads), 4 * nt, st, seg, nseg, p.per_block, ntx, nty,
+                           t0, nt, M, blk);
+    }
+    hipLaunchKernelGGL(k_bin_offsets, dim3(blocks_for(T, 64)), dim3(1024), 0, st, M, p.nb, T, tot, blk, ctr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_exscan(tot, tile_start, T, scan_tmp, st);
 }
 
 hipError_t launch_exscan(const uint32_t* cnt, uint32_t* start, int32_t n, uint32_t* scratch, hipStream_t st) {
@@ -1551,12 +1654,17 @@ hipError_t launch_exscan(const uint32_t* cnt, uint32_t* start, int32_t n, uint32
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const SegRec* seg, int32_t nseg, const CamConst& cam, const uint32_t* tile_start,
-                          uint32_t* tile_cur, uint32_t* list, hipStream_t st) {
+hipError_t launch_scatter(const SegRec* seg, int32_t nseg, const CamConst& cam, const BinPlan& p,
+                          const uint32_t* tile_start, const uint32_t* M, uint32_t* list, hipStream_t st) {
     if (nseg == 0) return hipSuccess;
-    const int ntx = (cam.W + kTile - 1) / kTile, nty = (cam.H + kTile - 1) / kTile;
-    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, seg, nseg, ntx, nty, tile_start,
-                       tile_cur, list);
+    const int ntx = (cam.W + kTile - 1) / kTile, nty = (cam.H + kTile - 1) / kTile, T = ntx * nty;
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_scatter), 4 * p.range);
+    if (e != hipSuccess) return e;
+    for (int t0 = 0; t0 < T; t0 += p.range) {
+        const int nt = std::min(p.range, T - t0);
+        hipLaunchKernelGGL(k_scatter, dim3(p.nb), dim3(kBinThreads), 4 * nt, st, seg, nseg, p.per_block, ntx, nty, t0,
+                           nt, tile_start, M, list);
+    }
     return hipGetLastError();
 }
 

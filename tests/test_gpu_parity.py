@@ -287,3 +287,34 @@ def test_pixels_deeper_than_one_batch(hip, ctx):
     assert stats["deep_pixels"] == int((depth > 2048).sum()) and stats["overflow_pixels"] == 0
     assert_radiance(img, ref, what="deep pixels")
     ws.close()
+
+
+@pytest.mark.parametrize("W,H", [(3840, 2160), (4112, 2320)])
+def test_large_images_binning(hip, ctx, W, H):
+    """Tile binning at 4K (per-block tile counters above 64 KiB of LDS) and on an image with
+    more tiles than one binning pass holds (37,265 > 36,864: two passes).  The hair is framed
+    low so that it crosses the pass boundary; bins, fragment count and a rectangle of radiance
+    across the boundary match the oracle."""
+    import dataclasses
+    print(f"case: large image {W}x{H}", flush=True)
+    asset = hs.make_asset(3000, 16, 90.0, seed=41)
+    cam = hs.camera_for(asset, W, H)
+    cam = dataclasses.replace(cam, cy=cam.cy + 0.35 * H)
+    lights = hs.default_lights(asset, with_point=True)
+    geom = R.strand_level(asset)
+    c, XA, YA, XB, YB, izA, izB, hw, hw_fx, vis = R.segment_records(geom, cam)
+    tid, sid, _ = R.rs.bins(XA, YA, XB, YB, hw_fx, vis, W, H, 16)
+    aid, ws, img, stats = _render(hip, ctx, asset, cam, lights)
+    T = -(-W // 16) * -(-H // 16)
+    assert stats["pairs"] == len(tid)
+    ts, segs = ctx.debug_bins(ws, T, int(stats["pairs"]))
+    ref_start = np.searchsorted(tid, np.arange(T + 1))
+    assert np.array_equal(ts.astype(np.int64), ref_start)
+    got_sorted = np.concatenate([np.sort(segs[ts[t]:ts[t + 1]]) for t in range(T)]) if len(tid) else segs
+    assert np.array_equal(got_sorted, sid)
+    assert stats["fragments"] == len(R.rasterize(geom, cam).seg)
+    x0, y0 = 1800, 2270 if H > 2300 else 1800
+    y0 = min(y0, H - 24)
+    ref, ras = R.render(geom, cam, lights, mat_of(asset), rect=(x0, y0, 24, 24))
+    assert_radiance(img[y0:y0 + 24, x0:x0 + 24], ref[y0:y0 + 24, x0:x0 + 24], what=f"{W}x{H} rect")
+    ws.close()
