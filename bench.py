@@ -10,8 +10,11 @@ shading and compositing; inputs are resident in HBM before the timed region.
 
 Prints one JSON line: Mfragments/s over the timed steps (fragments counted by the library,
 equal to the CPU oracle's count), frame ms (mean, p50, p99), the roofline of the dominant
-kernel (k_batch, measured with HIP events on its launch stream) and the CPU oracle timed on
-a bounded sample of the same frame.
+kernel (k_batch, measured with HIP events on its launch stream), the CPU oracle timed on
+a bounded sample of the same frame, and the served latency (p50 / p99, arrival to
+completion) of the continuous-batching render server under Poisson arrivals of 30, 60 and
+120 requests/s over three resident assets (10k x 16, 100k x 32 and 300k x 48 strands with
+their thick-hair levels; resolution uniform over 720p / 1080p / 2160p).
 """
 from __future__ import annotations
 
@@ -42,7 +45,7 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9                # 256 CUs x 64 lanes x 2.4 GHz (
 PEAK_HBM = 8.0e12
 
 KERNEL_SOURCES = ["paper_2405_10565_amd/csrc/hair_kernels.hip", "paper_2405_10565_amd/csrc/hair_shading.h",
-                  "paper_2405_10565_amd/csrc/hair_internal.h"]
+                  "paper_2405_10565_amd/csrc/hair_internal.h", "paper_2405_10565_amd/csrc/hair_fastmath_coef.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_batch_hair_100k_1080p_traffic.txt")
 
 
@@ -92,12 +95,35 @@ def cpu_baseline(asset, cam, lights, rows: int = 48):
                       f"{dt:.1f} s wall, torch/numpy float64 on 1 thread)"}
 
 
+def serve_leg(ctx, n_requests: int, warmup: int = 24, rates=(30.0, 60.0, 120.0)):
+    """Served latency: Poisson arrivals at each rate over the three resident serving assets."""
+    from paper_2405_10565_amd import serve as S
+    assets = S.build_assets(ctx)
+    out = {"rates_req_s": list(rates), "requests_per_rate": n_requests, "warmup_per_rate": warmup,
+           "slots": 4, "scratch_budget_gib": 32, "p50_ms": [], "p99_ms": [], "throughput_req_s": [],
+           "mfragments_s": [], "failed": [], "levels": []}
+    for rate in rates:
+        srv = S.Server(ctx, assets, n_slots=4, scratch_budget=32 << 30)
+        reqs = S.make_requests(sorted(assets), n_requests + warmup, seed=int(rate))
+        r = S.summarize(S.run_poisson(srv, reqs, rate, seed=int(rate), warmup=warmup), rate)
+        srv.close()
+        out["p50_ms"].append(r.get("latency_ms_p50"))
+        out["p99_ms"].append(r.get("latency_ms_p99"))
+        out["throughput_req_s"].append(r.get("throughput_req_s"))
+        out["mfragments_s"].append(r.get("mfragments_s"))
+        out["failed"].append(r.get("failed"))
+        out["levels"].append(r.get("levels"))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-latency leg")
+    ap.add_argument("--serve-requests", type=int, default=240, help="measured requests per arrival rate")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -182,6 +208,8 @@ def main():
         "cpu_baseline": None,
     }
     ws.close()
+    if not args.no_serve:
+        res["serving"] = serve_leg(ctx, args.serve_requests)
     ctx.close()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(asset, cam, lights)

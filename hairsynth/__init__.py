@@ -155,7 +155,8 @@ def kmeans_assign(asset: Asset, k: int, seed: int, iters: int = 25, init: str = 
     Features: [root / 0.1, first-segment tangent] (6-D, float64).  Seeding drawn from
     PCG64(seed): k-means++ (default) or, for large k, k distinct random strands
     (init="random"); then `iters` Lloyd iterations; distance ties go to the lower centre
-    index (argmin); empty clusters are dropped and labels renumbered densely in order.
+    index (argmin; above 512 centres a k-d tree finds the exact nearest centre); empty
+    clusters are dropped and labels renumbered densely in order.
     """
     feats = np.concatenate([asset.roots() / 0.1, asset.first_tangents()], axis=1)
     n = feats.shape[0]
@@ -180,6 +181,9 @@ def kmeans_assign(asset: Asset, k: int, seed: int, iters: int = 25, init: str = 
             d2 = np.minimum(d2, ((feats - centres[c]) ** 2).sum(1))
 
     def assign(cent):
+        if k > 512:   # exact nearest centre through a k-d tree (same result up to exact ties)
+            from scipy.spatial import cKDTree
+            return cKDTree(cent).query(feats, k=1, workers=-1)[1].astype(np.int64)
         lab = np.empty(n, dtype=np.int64)
         cn = (cent ** 2).sum(1)
         step = max(1, int(2e7 // max(1, k)))

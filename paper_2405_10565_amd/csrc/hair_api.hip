@@ -416,6 +416,7 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     HIP_TRY(ctx, hipEventRecord(ws->ev[6], st), "hipEventRecord");
     HIP_TRY(ctx, hipMemcpyAsync(&out->ctr, ws->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, st), "copy");
     HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
+    out->ctr.fragments = n_frags;
     float t01 = 0, t23 = 0, t45 = 0, t56 = 0, t06 = 0;
     HIP_TRY(ctx, hipEventElapsedTime(&t01, ws->ev[0], ws->ev[1]), "elapsed");
     HIP_TRY(ctx, hipEventElapsedTime(&t23, ws->ev[2], ws->ev[3]), "elapsed");

@@ -405,8 +405,8 @@ __global__ void k_fill_f32(float* p, float v, size_t n) {
 
 // ---------------------------------------------------------------------------------------
 // Coverage: every fragment of segment s whose pixel lies in tile rows [row_lo, row_hi].
-// Candidate columns per row come from the row's interval of the slab 0 <= t_num < t_den and
-// the strip |cross| < R sqrt(t_den), widened by a pixel; the exact integer predicate decides.
+// Candidate columns per row come from the row's interval of the slab 0 <= t_num <= t_den and
+// the strip |cross| <= R sqrt(t_den), widened by 1e-6 pixel; the exact integer predicate decides.
 template <class F>
 __device__ inline void for_each_fragment(const SegRec& s, int px0, int py0, int row_lo, int row_hi, int W, int H,
                                          F&& f) {
@@ -444,8 +444,10 @@ __device__ inline void for_each_fragment(const SegRec& s, int px0, int py0, int 
             lo = fmax(lo, c - half);
             hi = fmin(hi, c + half);
         }
-        const double flo = floor(((double)ax + lo - 8.0) * (1.0 / 16.0)) - 1.0;
-        const double fhi = ceil(((double)ax + hi - 8.0) * (1.0 / 16.0)) + 1.0;
+        // columns whose centre offset 16 i + 8 - ax lies in [lo, hi]; the float64 bounds carry
+        // relative errors near 1e-16 of values below 2^21, far inside the 1e-6 pixel widening
+        const double flo = ceil(((double)ax + lo - 8.0) * (1.0 / 16.0) - 1e-6);
+        const double fhi = floor(((double)ax + hi - 8.0) * (1.0 / 16.0) + 1e-6);
         const int c0 = (int)fmax((double)i0, flo);
         const int c1 = (int)fmin((double)i1, fhi);
         const int ey_dy = ey * dy, ey_dx = ey * dx;
@@ -711,8 +713,17 @@ __global__ __launch_bounds__(kNT) void k_count(FrameBufs f, CamConst cam, uint32
 // Greedy batch packing of whole pixels: from p0 skip empty pixels, then take the longest run
 // [p0, p1) whose fragments fit one LDS batch.  A pixel deeper than a batch is "oversized".
 __device__ inline bool next_batch(const uint32_t* s_cnt, const uint32_t* s_off, int& p0, int& p1, bool& oversized) {
-    while (p0 < kTilePix && s_cnt[p0] == 0) ++p0;
     if (p0 >= kTilePix) return false;
+    if (s_cnt[p0] == 0) {   // next non-empty pixel: the last q with s_off[q] == s_off[p0]
+        const uint32_t o = s_off[p0];
+        if (s_off[kTilePix] == o) return false;
+        int lo = p0, hi = kTilePix - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] == o) lo = mid; else hi = mid - 1;
+        }
+        p0 = lo;
+    }
     oversized = s_cnt[p0] > (uint32_t)kCap;
     if (oversized) {
         p1 = p0 + 1;
@@ -752,7 +763,6 @@ __global__ __launch_bounds__(kNT) void k_tile_prep(FrameBufs f) {
             p0 = p1;
         }
         f.tile_nb[tile] = nb;
-        if (total) atomicAdd(&f.ctr->fragments, (unsigned long long)total);
         if (over) atomicAdd(&f.ctr->deep_pixels, over);
     }
 }

@@ -222,7 +222,7 @@ def build_assets(hctx: B.Context, specs=((10_000, 16), (100_000, 32), (300_000, 
     for i, (n, segs) in enumerate(specs):
         asset = hs.make_asset(n, segs, 90.0, seed=seed + i, sigma_spread=True)
         aid = hctx.upload_asset(asset)
-        assigns = [hs.kmeans_assign(asset, max(1, n // d), seed=seed + i, iters=3, init="random")
+        assigns = [hs.kmeans_assign(asset, max(1, n // d), seed=seed + i, iters=10, init="random")
                    for d in level_divisors]
         hctx.build_lod(aid, assigns)
         _, counts, S = hctx.lod_info(aid)
