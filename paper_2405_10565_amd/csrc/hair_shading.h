@@ -226,16 +226,20 @@ __device__ inline void f_single(const LightView& v, T h, T gamma_o, T cgo, const
 }
 
 // Hemisphere albedos a_F, a_B (RGB) and variances sigma_f^2, sigma_b^2 at the light's x_d.
+// The 8-node rule is symmetric in h and so is each node's contribution (h -> -h flips the
+// sign of gamma_o, gamma_t and of every exit azimuth, which leaves the attenuations and, by
+// F(-x) = 1 - F(x) of the periodic CDF, the back-hemisphere mass unchanged): the four nodes
+// h > 0 are evaluated with doubled weights.
 template <class T>
 __device__ inline void hemisphere_stats(const LightView& v, const T sigl[3], const MatConst& m, T aF[3], T aB[3],
                                         T& var_f, T& var_b) {
     T wF[3], wB[3];
     for (int c = 0; c < 3; ++c) aF[c] = aB[c] = T(0.0f);
     for (int p = 0; p < 3; ++p) wF[p] = wB[p] = T(0.0f);
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 4; k < 8; ++k) {
         const T go = T(kGLgo[k]);
         Atten<T> at = attenuation(v, T(kGLx[k]), T(kGLcgo[k]), sigl, m);
-        float wk = 0.5f * kGLw[k];
+        float wk = kGLw[k];   // 2 x (1/2 of the node weight on [-1, 1])
         for (int p = 0; p < 3; ++p) {
             T mu = exit_azimuth(p, go, at.gamma_t);
             T back = periodic_cdf(T(kHalfPi) - mu, m) - periodic_cdf(T(-kHalfPi) - mu, m);

@@ -201,3 +201,24 @@ def test_reciprocity_at_fixed_counts():
                                                  SIG, MAT, nt, rho, nF, nB)[0]
             return tot
         assert torch.allclose(avg(ti, to, phi), avg(to, ti, -phi), rtol=1e-11)
+
+
+def test_gauss_legendre_average_symmetric_in_h():
+    """Nodes h and -h contribute equally to a_F / a_B (same attenuation, same front mass by
+    F(-x) = 1 - F(x) of the periodic logistic CDF); the device sums the four h > 0 nodes with
+    doubled weights."""
+    import oracle.fiber as Fb
+    s = Fb.logistic_scale(0.3)
+    xd = torch.linspace(0.0, 1.4, 9, dtype=torch.float64)
+    sig = torch.tensor([0.3, 0.6, 1.2], dtype=torch.float64)
+    h = ag.GL_NODES.to(torch.float64)
+    for i in range(4):
+        hp, hm = h[7 - i], h[i]
+        assert float(hp) == -float(hm)
+        Ap, gop, gtp = Fb.attenuation(xd, hp * torch.ones_like(xd), sig, 1.55)
+        Am, gom, gtm = Fb.attenuation(xd, hm * torch.ones_like(xd), sig, 1.55)
+        assert torch.allclose(Ap, Am, rtol=0, atol=1e-15)
+        for p in range(3):
+            fp = ag.front_mass(Fb.exit_azimuth(p, gop, gtp), s)
+            fm = ag.front_mass(Fb.exit_azimuth(p, gom, gtm), s)
+            assert torch.allclose(fp, fm, rtol=0, atol=1e-12)
