@@ -158,7 +158,33 @@ def kmeans_assign(asset: Asset, k: int, seed: int, iters: int = 25, init: str = 
     index (argmin; above 512 centres a k-d tree finds the exact nearest centre); empty
     clusters are dropped and labels renumbered densely in order.
     """
-    feats = np.concatenate([asset.roots() / 0.1, asset.first_tangents()], axis=1)
+    return _kmeans(strand_features(asset), k, seed, iters, init)
+
+
+def strand_features(asset: Asset) -> np.ndarray:
+    return np.concatenate([asset.roots() / 0.1, asset.first_tangents()], axis=1)
+
+
+def kmeans_hierarchy(asset: Asset, ks, seed: int, iters: int = 25, init: str = "kmeans++") -> list:
+    """Nested assignments for the levels finer -> coarser (ks descending): the finest level is
+    k-means on the strand features; each coarser level is k-means on the previous level's
+    cluster mean features, so every cluster lies inside one cluster of each coarser level."""
+    feats = strand_features(asset)
+    lab = _kmeans(feats, ks[0], seed, iters, init)
+    out = [lab]
+    for li, k in enumerate(ks[1:], start=1):
+        K = int(lab.max()) + 1
+        cnt = np.bincount(lab, minlength=K).astype(np.float64)
+        cf = np.zeros((K, feats.shape[1]))
+        np.add.at(cf, lab, feats)
+        cf /= cnt[:, None]
+        top = _kmeans(cf, k, seed + li, iters, init)
+        lab = top[lab].astype(np.int32)
+        out.append(lab)
+    return out
+
+
+def _kmeans(feats: np.ndarray, k: int, seed: int, iters: int, init: str) -> np.ndarray:
     n = feats.shape[0]
     k = min(int(k), n)
     rng = np.random.Generator(np.random.PCG64(seed))

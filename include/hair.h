@@ -176,6 +176,33 @@ int hair_render(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const 
                 const hair_light* lights, int32_t n_lights, float* rgba_out, void* stream,
                 hair_stats* stats);
 
+/* Per-group, per-segment LoD (Sec. 5.1 step 5; Sec. 5.2 "Dynamic LoD selection",
+ * eq. lod_select).  Available when hair_build_lod built 1..7 levels that nest: every cluster
+ * of a finer level lies inside one cluster of the coarsest level.  Those coarsest clusters
+ * are the G groups; a frame chooses a level L(g, k) in 0..n_levels (0 = the strands) for every
+ * group g and segment index k and renders, for each (g, k), the k-th segments of the level's
+ * owners (strands or clusters) inside g.  levels: device int32[G][S] (caller-owned).
+ * The width of (g, k) at level l is the largest 2 * half-width (pixels) over those segments
+ * that are visible (0 when none is).
+ * hair_lod_groups: G, or HAIR_EINVAL when the asset has no nested hierarchy. */
+int hair_lod_groups(hair_ctx* ctx, int32_t asset, int32_t* n_groups);
+
+/* Initial levels: for every (g, k) the coarsest level l >= 1 whose width is <= eps_w_px,
+ * else 0.  Writes levels; synchronises `stream`. */
+int hair_lod_init(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_camera* cam,
+                  float eps_w_px, int32_t* levels, void* stream);
+
+/* Render one frame at the per-(g, k) levels (mixed strands and thick hairs, each shaded by
+ * its own model); same output, synchronisation and errors as hair_render (HAIR_EINVAL when a
+ * levels entry lies outside [0, n_levels]; stats->segments counts the rendered segments).
+ * With eps_w_px > 0 the levels are then updated in place for the next frame (deferred
+ * selection): with w the width at the frame's level L and w_c the width one level coarser,
+ * L - 1 (not below 0) if w > eps_w_px, L + 1 if L < n_levels and w_c <= eps_w_px, else L.
+ * eps_w_px <= 0 leaves levels unchanged. */
+int hair_render_mixed(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_camera* cam,
+                      const hair_light* lights, int32_t n_lights, int32_t* levels, float eps_w_px,
+                      float* rgba_out, void* stream, hair_stats* stats);
+
 /* Vector-Jacobian product of hair_render at a thick-hair level (level >= 1) with respect to
  * the level's fitted parameters (HAIR_ERANGE when a pixel is deeper than one LDS batch of
  * HAIR_PIXEL_CAPACITY fragments): given d_rgba (device float[height][width][4]) writes
@@ -191,7 +218,8 @@ int hair_render_backward(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t leve
 
 /* Test exports of the last hair_render on `ws` (synchronise and copy to host):
  * segments: int[n][6] (XA, YA, XB, YB, hw_fx, flags: bit0 visible, bit1 negative h side,
- *           bit2 culled for size) and float[n][3] (izA, izB, hw px).
+ *           bit2 culled for size, bit3 thick hair of a mixed frame) and float[n][3]
+ *           (izA, izB, hw px).
  * bins:     tile_start uint[n_tiles + 1], tile_segs uint[pairs] (each tile's segment ids,
  *           in no particular order). */
 int hair_debug_segments(hair_ws* ws, int64_t n, int32_t* rec_i, float* rec_f);

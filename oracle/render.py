@@ -35,7 +35,7 @@ DT = torch.float64
 @dataclass
 class LevelGeom:
     """Segments of one LoD level, one row per segment (global segment id = row index)."""
-    kind: str                  # "strand" or "cluster"
+    kind: str                  # "strand", "cluster" or "mixed" (per-row `thick` decides)
     pA: np.ndarray             # f32 [3, S]
     pB: np.ndarray             # f32 [3, S]
     sigma_a: np.ndarray        # f32 [S, 3]
@@ -47,6 +47,7 @@ class LevelGeom:
     r: np.ndarray = None       # f32 [S]
     cluster: np.ndarray = None  # i64 [S] cluster of each segment
     seg_in_cluster: np.ndarray = None
+    thick: np.ndarray = None   # bool [S]: mixed frames, rows that are thick hairs
 
 
 def strand_level(asset) -> LevelGeom:
@@ -100,8 +101,14 @@ def segment_records(geom: LevelGeom, cam):
     XB, YB, zB, izB, okB = rs.project_points(geom.pB, c)
     if geom.kind == "strand":
         hw = rs.strand_halfwidth(zA, zB, geom.width, c)
-    else:
+    elif geom.kind == "cluster":
         hw = rs.cluster_halfwidth(geom.pA, geom.pB, zA, zB, geom.ahat, geom.a_len, geom.b_len, c)
+    else:   # mixed: each row by its own kind
+        t = geom.thick
+        hw = np.empty(zA.shape, dtype=np.float32)
+        hw[~t] = rs.strand_halfwidth(zA[~t], zB[~t], geom.width[~t], c)
+        hw[t] = rs.cluster_halfwidth(geom.pA[:, t], geom.pB[:, t], zA[t], zB[t], geom.ahat[:, t], geom.a_len[t],
+                                     geom.b_len[t], c)
     hw_fx, vis = rs.finalize_segments(XA, YA, XB, YB, okA, okB, hw)
     return c, XA, YA, XB, YB, izA, izB, hw.astype(np.float32), hw_fx, vis
 
@@ -198,6 +205,24 @@ def light_dirs(light, xw):
     return wi, E
 
 
+def _mixed_radiance(geom: LevelGeom, ras: Raster, cam, lights, mat):
+    """Mixed frames: strand fragments by f_single, thick-hair fragments by f_ours."""
+    from dataclasses import replace
+    thick_f = geom.thick[ras.seg]
+    alpha = torch.zeros(len(ras.seg), dtype=DT)
+    L = torch.zeros(len(ras.seg), 3, dtype=DT)
+    for kind, m in (("strand", ~thick_f), ("cluster", thick_f)):
+        if not m.any():
+            continue
+        sub = replace(ras, seg=ras.seg[m], pix=ras.pix[m], key=ras.key[m], t_num=ras.t_num[m], t_den=ras.t_den[m],
+                      cross=ras.cross[m])
+        a, l = fragment_radiance(replace(geom, kind=kind), sub, cam, lights, mat)
+        idx = torch.as_tensor(np.nonzero(m)[0])
+        alpha[idx] = a
+        L[idx] = l
+    return alpha, L
+
+
 def fragment_radiance(geom: LevelGeom, ras: Raster, cam, lights, mat, params=None):
     """(alpha [F], L [F, 3]) in float64.
 
@@ -205,6 +230,8 @@ def fragment_radiance(geom: LevelGeom, ras: Raster, cam, lights, mat, params=Non
     'a_len', 'b_len' [S], 'r' [S], 'sigma_a' [S, 3], and 'hw' [S] (the half-width recomputed
     from them); default: the level's stored values and the float32 half-width.
     """
+    if geom.kind == "mixed":
+        return _mixed_radiance(geom, ras, cam, lights, mat)
     s = ras.seg
     xw, u, wo = shading_inputs(geom, ras, cam)
     xh, yh, degen, sin_to = frame(u, wo)

@@ -26,7 +26,7 @@ EXPORTS = [
     "hair_ctx_memory", "hair_ws_create", "hair_ws_destroy", "hair_ws_estimate", "hair_upload", "hair_release",
     "hair_build_lod", "hair_lod_info", "hair_get_lod", "hair_set_lod", "hair_set_cluster_params",
     "hair_select_level", "hair_render", "hair_render_backward", "hair_debug_segments", "hair_debug_bins",
-    "hair_debug_fragments",
+    "hair_debug_fragments", "hair_lod_groups", "hair_lod_init", "hair_render_mixed",
 ]
 
 
@@ -94,6 +94,10 @@ def _load():
                          C.POINTER(hair_stats)], C.c_int),
         "hair_render_backward": ([P, P, I32, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32, P, P, P, P, P],
                                  C.c_int),
+        "hair_lod_groups": ([P, I32, ip], C.c_int),
+        "hair_lod_init": ([P, P, I32, C.POINTER(hair_camera), F, P, P], C.c_int),
+        "hair_render_mixed": ([P, P, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32, P, F, P, P,
+                               C.POINTER(hair_stats)], C.c_int),
         "hair_debug_segments": ([P, I64, ip, fp], C.c_int),
         "hair_debug_bins": ([P, I64, up, I64, up], C.c_int),
         "hair_debug_fragments": ([P, P, I32, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32, I32, I32, I32,
@@ -291,6 +295,40 @@ class Context:
         st = hair_stats()
         rc = lib.hair_render(self.handle, ws.handle if ws else None, asset, level, C.byref(c), la, nl,
                              C.c_void_p(out.data_ptr()), _stream_ptr(stream), C.byref(st))
+        if raise_on_error:
+            check(rc)
+        return out, st.as_dict(), rc
+
+    def lod_groups(self, asset: int) -> int:
+        out = C.c_int32()
+        check(lib.hair_lod_groups(self.handle, asset, C.byref(out)))
+        return out.value
+
+    def lod_init(self, asset: int, cam, eps_w: float, levels, ws: Workspace | None = None, stream=None):
+        """Initial per-(group, segment) levels into `levels` (torch int32 [G, S] on the device)."""
+        import torch
+        assert levels.is_cuda and levels.dtype == torch.int32 and levels.is_contiguous()
+        c = make_camera(cam)
+        check(lib.hair_lod_init(self.handle, ws.handle if ws else None, asset, C.byref(c), float(eps_w),
+                                C.c_void_p(levels.data_ptr()), _stream_ptr(stream)))
+        return levels
+
+    def render_mixed(self, asset: int, cam, lights, levels, eps_w: float = 0.0, out=None, ws: Workspace | None = None,
+                     stream=None, raise_on_error: bool = True):
+        """Mixed-level frame at `levels` (torch int32 [G, S]); eps_w > 0 updates them in place
+        for the next frame.  Returns (out, stats dict, status code)."""
+        import torch
+        assert levels.is_cuda and levels.dtype == torch.int32 and levels.is_contiguous()
+        c = make_camera(cam)
+        la, nl = make_lights(lights)
+        if out is None:
+            out = torch.empty((c.height, c.width, 4), dtype=torch.float32, device=f"cuda:{self.device}")
+        assert out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+        assert tuple(out.shape) == (c.height, c.width, 4)
+        st = hair_stats()
+        rc = lib.hair_render_mixed(self.handle, ws.handle if ws else None, asset, C.byref(c), la, nl,
+                                   C.c_void_p(levels.data_ptr()), float(eps_w), C.c_void_p(out.data_ptr()),
+                                   _stream_ptr(stream), C.byref(st))
         if raise_on_error:
             check(rc)
         return out, st.as_dict(), rc

@@ -41,11 +41,20 @@ struct Level {
     DevBuf cx, cy, cz, ahat, axes, n_total, r, sig;
 };
 
+// Nested hierarchy for per-group level choice: groups = clusters of the coarsest level; per
+// level l (0 = strands) its owners listed by group (CSR, ascending owner ids per group).
+struct Hierarchy {
+    bool nested = false;
+    int G = 0;
+    std::vector<DevBuf> grp_start, grp_owner;   // [n_levels + 1]
+};
+
 struct Asset {
     int n_strands = 0, V = 0, S = 0;
     DevBuf x, y, z, width, sig;
     hair_material mat{};
     std::vector<Level> levels;   // levels[l - 1] is level l
+    Hierarchy hier;
 };
 
 bool finite_all(const float* p, size_t n) {
@@ -71,7 +80,7 @@ struct hair_ws {
     hair_ctx* ctx = nullptr;
     uint64_t max_bytes = 0;
     uint64_t held = 0;
-    DevBuf seg, shade, scan_tmp, tile_cnt, tile_start, bin_m, bin_blk, list, ctr;
+    DevBuf seg, shade, scan_tmp, tile_cnt, tile_start, bin_m, bin_blk, list, ctr, sel_cnt, sel_start, sel, sel_tmp;
     DevBuf items, item_start, item_base, pix_cnt, pix_kmin, pix_kmax, pix_off;
     DevBuf tile_tot, frag_base, tile_nb, batch_start, batches, frags;
     hipEvent_t ev[7] = {};
@@ -141,10 +150,20 @@ void free_level(hair_ctx* ctx, Level& l) {
     for (DevBuf* b : {&l.cx, &l.cy, &l.cz, &l.ahat, &l.axes, &l.n_total, &l.r, &l.sig}) ctx_free(ctx, *b);
 }
 
+void free_hierarchy(hair_ctx* ctx, Hierarchy& h) {
+    for (DevBuf& b : h.grp_start) ctx_free(ctx, b);
+    for (DevBuf& b : h.grp_owner) ctx_free(ctx, b);
+    h.grp_start.clear();
+    h.grp_owner.clear();
+    h.nested = false;
+    h.G = 0;
+}
+
 void free_asset(hair_ctx* ctx, Asset& a) {
     for (DevBuf* b : {&a.x, &a.y, &a.z, &a.width, &a.sig}) ctx_free(ctx, *b);
     for (Level& l : a.levels) free_level(ctx, l);
     a.levels.clear();
+    free_hierarchy(ctx, a.hier);
 }
 
 int check_ctx(hair_ctx* ctx) {
@@ -309,7 +328,8 @@ struct FrameOut {
 //   k_batch                           sort, shade, blend (one workgroup per batch)
 int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, const hair_camera* cam,
               const hair_light* lights, int n_lights, float* rgba, const DebugDump* dbg, hipStream_t st,
-              FrameOut* out, bool tiles_too = true, const GradOut* grad = nullptr) {
+              FrameOut* out, bool tiles_too = true, const GradOut* grad = nullptr, const HierDev* hier = nullptr,
+              const uint32_t* sel = nullptr) {
     int rc;
     const CamConst cc = cam_const(cam);
     const int ntx = (cam->width + kTile - 1) / kTile, nty = (cam->height + kTile - 1) / kTile;
@@ -331,7 +351,11 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     uint32_t* scan_tmp = ws->scan_tmp.as<uint32_t>();
     HIP_TRY(ctx, hipEventRecord(ws->ev[0], st), "hipEventRecord");
     HIP_TRY(ctx, launch_fill_u32(ws->ctr.as<uint32_t>(), 0u, sizeof(Counters) / 4, st), "fill");
-    HIP_TRY(ctx, launch_project(lv, cc, ws->seg.as<SegRec>(), ws->shade.as<ShadeRec>(), st), "k_project");
+    if (hier)
+        HIP_TRY(ctx, launch_project_mixed(*hier, sel, lv.nseg, cc, ws->seg.as<SegRec>(), ws->shade.as<ShadeRec>(), st),
+                "k_project_mixed");
+    else
+        HIP_TRY(ctx, launch_project(lv, cc, ws->seg.as<SegRec>(), ws->shade.as<ShadeRec>(), st), "k_project");
     HIP_TRY(ctx, launch_bins(ws->seg.as<SegRec>(), lv.nseg, cc, plan, ws->bin_m.as<uint32_t>(), ws->bin_blk.as<uint4>(),
                              ws->tile_cnt.as<uint32_t>(), tile_start, ws->ctr.as<Counters>(), scan_tmp, st),
             "k_bin_count");
@@ -506,7 +530,7 @@ int hair_ws_destroy(hair_ws* ws) {
     if (!ws) return fail(HAIR_EINVAL, "null workspace");
     hair_ctx* ctx = ws->ctx;
     if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
-    for (DevBuf* b : {&ws->seg, &ws->shade, &ws->scan_tmp, &ws->tile_cnt, &ws->tile_start, &ws->bin_m, &ws->bin_blk, &ws->list, &ws->ctr, &ws->items,
+    for (DevBuf* b : {&ws->seg, &ws->shade, &ws->scan_tmp, &ws->tile_cnt, &ws->tile_start, &ws->bin_m, &ws->bin_blk, &ws->sel_cnt, &ws->sel_start, &ws->sel, &ws->sel_tmp, &ws->list, &ws->ctr, &ws->items,
                       &ws->item_start, &ws->item_base, &ws->pix_cnt, &ws->pix_kmin, &ws->pix_kmax, &ws->pix_off,
                       &ws->tile_tot, &ws->frag_base, &ws->tile_nb, &ws->batch_start, &ws->batches, &ws->frags})
         ctx_free(ctx, *b, ws);
@@ -628,6 +652,56 @@ static int alloc_level(hair_ctx* ctx, Level& l, int K, int S) {
     return HAIR_OK;
 }
 
+// Groups and per-level owner lists when the levels are nested (each cluster's members lie in
+// one cluster of the coarsest level) and few enough for mixed frames; otherwise none.
+int build_hierarchy(hair_ctx* ctx, Asset& a, int n_levels, const int32_t* n_clusters, const int32_t* assign,
+                    hipStream_t st) {
+    if (n_levels < 1 || n_levels > kMaxMixedLevels) return HAIR_OK;
+    const int n = a.n_strands;
+    const int G = n_clusters[n_levels - 1];
+    const int32_t* top = assign + (size_t)(n_levels - 1) * n;
+    // group of every owner of every level
+    std::vector<std::vector<int32_t>> group(n_levels + 1);
+    group[0].assign(top, top + n);
+    for (int l = 1; l <= n_levels; ++l) {
+        const int32_t* as = assign + (size_t)(l - 1) * n;
+        group[l].assign(n_clusters[l - 1], -1);
+        for (int s = 0; s < n; ++s) {
+            int32_t& g = group[l][as[s]];
+            if (g < 0) g = top[s];
+            else if (g != top[s]) return HAIR_OK;   // not nested
+        }
+    }
+    Hierarchy h;
+    h.G = G;
+    h.grp_start.resize(n_levels + 1);
+    h.grp_owner.resize(n_levels + 1);
+    int rc = HAIR_OK;
+    for (int l = 0; l <= n_levels && rc == HAIR_OK; ++l) {
+        const std::vector<int32_t>& gr = group[l];
+        std::vector<int32_t> start(G + 1, 0), owner(gr.size());
+        for (int32_t g : gr) start[g + 1]++;
+        for (int g = 0; g < G; ++g) start[g + 1] += start[g];
+        std::vector<int32_t> cur(start.begin(), start.end() - 1);
+        for (size_t o = 0; o < gr.size(); ++o) owner[cur[gr[o]]++] = (int32_t)o;
+        if ((rc = ctx_alloc(ctx, h.grp_start[l], 4ull * (G + 1))) ||
+            (rc = ctx_alloc(ctx, h.grp_owner[l], 4ull * std::max<size_t>(owner.size(), 1))))
+            break;
+        hipError_t e = hipMemcpyAsync(h.grp_start[l].p, start.data(), 4ull * (G + 1), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h.grp_owner[l].p, owner.data(), 4ull * owner.size(), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = dev_fail(ctx, e, "build_lod hierarchy");
+    }
+    if (rc != HAIR_OK) {
+        free_hierarchy(ctx, h);
+        return rc;
+    }
+    h.nested = true;
+    a.hier = std::move(h);
+    return HAIR_OK;
+}
+
 int hair_build_lod(hair_ctx* ctx, int32_t asset, int32_t n_levels, const int32_t* n_clusters, const int32_t* assign,
                    void* stream) {
     int rc;
@@ -690,7 +764,8 @@ int hair_build_lod(hair_ctx* ctx, int32_t asset, int32_t n_levels, const int32_t
     }
     for (Level& old : a.levels) free_level(ctx, old);
     a.levels = std::move(built);
-    return HAIR_OK;
+    free_hierarchy(ctx, a.hier);
+    return build_hierarchy(ctx, a, n_levels, n_clusters, assign, st);
 }
 
 int hair_get_lod(hair_ctx* ctx, int32_t asset, int32_t level, int32_t n_clusters, float* centers, float* ahat,
@@ -786,6 +861,7 @@ int hair_set_lod(hair_ctx* ctx, int32_t asset, int32_t level, int32_t n_clusters
         free_level(ctx, a.levels[level - 1]);
         a.levels[level - 1] = std::move(L);
     }
+    free_hierarchy(ctx, a.hier);   // memberships of a level set from arrays are unknown
     return HAIR_OK;
 }
 
@@ -839,6 +915,21 @@ int hair_select_level(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_came
     return HAIR_OK;
 }
 
+static void fill_stats(hair_stats* stats, const FrameOut& fo, uint32_t nseg) {
+    stats->fragments = fo.ctr.fragments;
+    stats->pairs = fo.pairs;
+    stats->segments = nseg;
+    stats->segments_visible = fo.ctr.visible;
+    stats->segments_culled_long = fo.ctr.culled_long;
+    stats->overflow_pixels = fo.ctr.overflow_pixels;
+    stats->ms_total = fo.ms[0];
+    stats->ms_project = fo.ms[1];
+    stats->ms_bin = fo.ms[2];
+    stats->ms_tile = fo.ms[3];
+    stats->deep_pixels = fo.ctr.deep_pixels;
+    stats->batches = fo.n_batches;
+}
+
 int hair_render(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,
                 const hair_light* lights, int32_t n_lights, float* rgba_out, void* stream, hair_stats* stats) {
     int rc;
@@ -854,20 +945,111 @@ int hair_render(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const 
     std::lock_guard<std::mutex> g(ws->mu);
     FrameOut fo;
     if ((rc = run_frame(ctx, ws, *a, lv, cam, lights, n_lights, rgba_out, nullptr, (hipStream_t)stream, &fo))) return rc;
-    if (stats) {
-        stats->fragments = fo.ctr.fragments;
-        stats->pairs = fo.pairs;
-        stats->segments = (uint32_t)lv.nseg;
-        stats->segments_visible = fo.ctr.visible;
-        stats->segments_culled_long = fo.ctr.culled_long;
-        stats->overflow_pixels = fo.ctr.overflow_pixels;
-        stats->ms_total = fo.ms[0];
-        stats->ms_project = fo.ms[1];
-        stats->ms_bin = fo.ms[2];
-        stats->ms_tile = fo.ms[3];
-        stats->deep_pixels = fo.ctr.deep_pixels;
-        stats->batches = fo.n_batches;
+    if (stats) fill_stats(stats, fo, (uint32_t)lv.nseg);
+    if (fo.ctr.list_overflow) return fail(HAIR_ERANGE, "%u tiles hold more than 2^24 segments", fo.ctr.list_overflow);
+    if (fo.ctr.overflow_pixels)
+        return fail(HAIR_ERANGE, "%u pixels hold more than %d fragments at one depth key (left transparent)",
+                    fo.ctr.overflow_pixels, kCap);
+    return HAIR_OK;
+}
+
+// The asset's nested hierarchy as device views (levels 0..n_levels).
+static int mixed_hierarchy(hair_ctx* ctx, int32_t asset, Asset** a_out, HierDev* h) {
+    auto it = ctx->assets.find(asset);
+    if (it == ctx->assets.end()) return fail(HAIR_ENOENT, "unknown asset %d", asset);
+    Asset& a = it->second;
+    if (!a.hier.nested)
+        return fail(HAIR_EINVAL, "asset %d has no nested LoD hierarchy (hair_build_lod with 1..%d levels whose "
+                    "clusters each lie inside one cluster of the coarsest level)", asset, kMaxMixedLevels);
+    memset(h, 0, sizeof(*h));
+    h->n_levels = (int)a.levels.size();
+    h->G = a.hier.G;
+    h->S = a.S;
+    for (int l = 0; l <= h->n_levels; ++l) {
+        Asset* dummy;
+        int rc = find_level(ctx, asset, l, &dummy, &h->lv[l]);
+        if (rc) return rc;
+        if (h->lv[l].nseg >= (1 << 28)) return fail(HAIR_ERANGE, "level %d has 2^28 segments or more", l);
+        h->grp_start[l] = a.hier.grp_start[l].as<int32_t>();
+        h->grp_owner[l] = a.hier.grp_owner[l].as<int32_t>();
     }
+    *a_out = &a;
+    return HAIR_OK;
+}
+
+int hair_lod_groups(hair_ctx* ctx, int32_t asset, int32_t* n_groups) {
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if (!n_groups) return fail(HAIR_EINVAL, "null output");
+    Asset* a;
+    HierDev h;
+    if ((rc = mixed_hierarchy(ctx, asset, &a, &h))) return rc;
+    *n_groups = h.G;
+    return HAIR_OK;
+}
+
+int hair_lod_init(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_camera* cam, float eps_w_px, int32_t* levels,
+                  void* stream) {
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if ((rc = validate_camera(cam))) return rc;
+    if (!levels) return fail(HAIR_EINVAL, "null levels");
+    if (!(std::isfinite(eps_w_px) && eps_w_px > 0)) return fail(HAIR_EINVAL, "eps_w must be finite and > 0");
+    Asset* a;
+    HierDev h;
+    if ((rc = mixed_hierarchy(ctx, asset, &a, &h))) return rc;
+    if ((rc = need_device(ctx))) return rc;
+    (void)ws;
+    HIP_TRY(ctx, launch_lod_init(h, cam_const(cam), eps_w_px, levels, (hipStream_t)stream), "k_lod_init");
+    HIP_TRY(ctx, hipStreamSynchronize((hipStream_t)stream), "sync");
+    return HAIR_OK;
+}
+
+int hair_render_mixed(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_camera* cam, const hair_light* lights,
+                      int32_t n_lights, int32_t* levels, float eps_w_px, float* rgba_out, void* stream,
+                      hair_stats* stats) {
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if ((rc = validate_camera(cam))) return rc;
+    if ((rc = validate_lights(lights, n_lights))) return rc;
+    if (!rgba_out || !levels) return fail(HAIR_EINVAL, "null output image or levels");
+    if (!std::isfinite(eps_w_px)) return fail(HAIR_EINVAL, "eps_w must be finite");
+    Asset* a;
+    HierDev h;
+    if ((rc = mixed_hierarchy(ctx, asset, &a, &h))) return rc;
+    if ((rc = need_device(ctx))) return rc;
+    ws = ws_or_default(ctx, ws);
+    std::lock_guard<std::mutex> g(ws->mu);
+    hipStream_t st = (hipStream_t)stream;
+    const int GS = h.G * h.S;
+    if ((rc = ws_need(ws, ws->sel_cnt, 4ull * (GS + 1))) || (rc = ws_need(ws, ws->sel_start, 4ull * (GS + 1))) ||
+        (rc = ws_need(ws, ws->sel_tmp, 4 * exscan_scratch_words(GS))))
+        return rc;
+    uint32_t* cnt = ws->sel_cnt.as<uint32_t>();
+    HIP_TRY(ctx, launch_fill_u32(cnt + GS, 0u, 1, st), "fill");
+    HIP_TRY(ctx, launch_select(h, levels, cnt, ws->sel_start.as<uint32_t>(), ws->sel_tmp.as<uint32_t>(), st),
+            "k_sel_count");
+    uint32_t nsel = 0, bad = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&nsel, ws->sel_start.as<uint32_t>() + GS, 4, hipMemcpyDeviceToHost, st), "copy");
+    HIP_TRY(ctx, hipMemcpyAsync(&bad, cnt + GS, 4, hipMemcpyDeviceToHost, st), "copy");
+    HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
+    if (bad) return fail(HAIR_EINVAL, "%u entries of levels lie outside [0, %d]", bad, h.n_levels);
+    if ((rc = ws_need(ws, ws->sel, 4ull * std::max<uint32_t>(nsel, 1)))) return rc;
+    HIP_TRY(ctx, launch_select_fill(h, levels, ws->sel_start.as<uint32_t>(), ws->sel.as<uint32_t>(), st), "k_sel_fill");
+    LevelDev lv;
+    memset(&lv, 0, sizeof(lv));
+    lv.kind = 2;
+    lv.nseg = (int32_t)nsel;
+    lv.S = a->S;
+    FrameOut fo;
+    if ((rc = run_frame(ctx, ws, *a, lv, cam, lights, n_lights, rgba_out, nullptr, st, &fo, true, nullptr, &h,
+                        ws->sel.as<uint32_t>())))
+        return rc;
+    if (eps_w_px > 0) {
+        HIP_TRY(ctx, launch_lod_update(h, cam_const(cam), eps_w_px, levels, st), "k_lod_update");
+        HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
+    }
+    if (stats) fill_stats(stats, fo, nsel);
     if (fo.ctr.list_overflow) return fail(HAIR_ERANGE, "%u tiles hold more than 2^24 segments", fo.ctr.list_overflow);
     if (fo.ctr.overflow_pixels)
         return fail(HAIR_ERANGE, "%u pixels hold more than %d fragments at one depth key (left transparent)",
@@ -912,7 +1094,7 @@ int hair_debug_segments(hair_ws* ws, int64_t n, int32_t* rec_i, float* rec_f) {
         rec_i[6 * i + 0] = s.xa; rec_i[6 * i + 1] = s.ya; rec_i[6 * i + 2] = s.xb; rec_i[6 * i + 3] = s.yb;
         rec_i[6 * i + 4] = s.hwfx & kHwMask;
         rec_i[6 * i + 5] = ((s.hwfx & kFlagVisible) ? 1 : 0) | ((s.hwfx & kFlagNegSide) ? 2 : 0) |
-                           ((s.hwfx & kFlagCulledLong) ? 4 : 0);
+                           ((s.hwfx & kFlagCulledLong) ? 4 : 0) | ((s.hwfx & kFlagThick) ? 8 : 0);
         rec_f[3 * i + 0] = s.iza; rec_f[3 * i + 1] = s.izb; rec_f[3 * i + 2] = s.hw;
     }
     return HAIR_OK;

@@ -36,6 +36,7 @@ struct ShadeRec {
 constexpr int32_t kFlagVisible = 1 << 16;
 constexpr int32_t kFlagNegSide = 1 << 17;        // h > 0 lies on the e x d < 0 side
 constexpr int32_t kFlagCulledLong = 1 << 18;
+constexpr int32_t kFlagThick = 1 << 19;          // mixed frames: a thick-hair segment
 constexpr int32_t kHwMask = 0xFFFF;
 
 struct CamConst {
@@ -88,6 +89,17 @@ struct LevelDev {
     const float* axes;       // thick hairs: (|a|, |b|) [nseg][2]
     const int32_t* n_total;  // thick hairs: member count [n_owner]
     const float* r;          // thick hairs: hair radius [n_owner]
+};
+
+// A nested LoD hierarchy for per-group, per-segment level choice: levels 0 (strands) ..
+// n_levels (coarsest), groups = clusters of the coarsest level, and each level's owners listed
+// by group (grp_owner[l][grp_start[l][g] .. grp_start[l][g + 1]), ascending owner ids).
+constexpr int kMaxMixedLevels = 7;               // cluster levels a mixed frame may use
+struct HierDev {
+    int32_t n_levels, G, S;
+    LevelDev lv[kMaxMixedLevels + 1];
+    const int32_t* grp_start[kMaxMixedLevels + 1];
+    const int32_t* grp_owner[kMaxMixedLevels + 1];
 };
 
 // Global counters a render accumulates (zeroed at the start of each call).
@@ -165,6 +177,16 @@ hipError_t launch_bins(const SegRec* seg, int32_t nseg, const CamConst& cam, con
 hipError_t launch_scatter(const SegRec* seg, int32_t nseg, const CamConst& cam, const BinPlan& p,
                           const uint32_t* tile_start, const uint32_t* M, uint32_t* list, hipStream_t st);
 hipError_t launch_tile_items(const uint32_t* tile_start, int T, uint32_t* items, hipStream_t st);
+// Per-group LoD: initial levels, deferred update in place, and a mixed frame's selection
+// (cnt and sel_start: G*S and G*S + 1 words; sel: one entry per selected segment).
+hipError_t launch_lod_init(const HierDev& h, const CamConst& cam, float eps_w, int32_t* levels, hipStream_t st);
+hipError_t launch_lod_update(const HierDev& h, const CamConst& cam, float eps_w, int32_t* levels, hipStream_t st);
+hipError_t launch_select(const HierDev& h, const int32_t* levels, uint32_t* cnt, uint32_t* sel_start,
+                         uint32_t* scan_tmp, hipStream_t st);
+hipError_t launch_select_fill(const HierDev& h, const int32_t* levels, const uint32_t* sel_start, uint32_t* sel,
+                              hipStream_t st);
+hipError_t launch_project_mixed(const HierDev& h, const uint32_t* sel, int32_t nsel, const CamConst& cam, SegRec* seg,
+                                ShadeRec* shade, hipStream_t st);
 hipError_t launch_count(const FrameBufs& f, const CamConst& cam, uint32_t n_items, hipStream_t st);
 hipError_t launch_tile_prep(const FrameBufs& f, hipStream_t st);
 hipError_t launch_batch_records(const FrameBufs& f, hipStream_t st);

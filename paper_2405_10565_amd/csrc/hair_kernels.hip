@@ -118,85 +118,179 @@ __device__ inline TileRect tile_rect(const SegRec& s, int ntx, int nty) {
     return r;
 }
 
+// Segment g of level lv: its screen record (projection, snapping, half-width, culling, side of
+// h > 0) and, when sr is given, its shading record.
+__device__ inline SegRec project_segment(const LevelDev& lv, int g, const CamConst& cam, ShadeRec* sr) {
+    const int owner = g / lv.S, k = g - owner * lv.S;
+    const int va = owner * (lv.S + 1) + k;
+    const float ax = lv.vx[va], ay = lv.vy[va], az = lv.vz[va];
+    const float bx = lv.vx[va + 1], by = lv.vy[va + 1], bz = lv.vz[va + 1];
+    const PPoint A = project_point(cam, ax, ay, az);
+    const PPoint B = project_point(cam, bx, by, bz);
+    if (sr) {
+        sr->q0 = make_float4(ax, ay, az, lv.sig[owner]);
+        sr->q1 = make_float4(bx, by, bz, lv.sig[lv.n_owner + owner]);
+        if (lv.kind == 0) {
+            sr->q2 = make_float4(0.f, 0.f, 0.f, lv.sig[2 * lv.n_owner + owner]);
+        } else {
+            sr->q2 = make_float4(lv.ahat[g], lv.ahat[lv.nseg + g], lv.ahat[2 * lv.nseg + g],
+                                 lv.sig[2 * lv.n_owner + owner]);
+            sr->q3 = make_float4(lv.axes[2 * g], lv.axes[2 * g + 1], (float)lv.n_total[owner], lv.r[owner]);
+        }
+    }
+    float hw;
+    if (lv.kind == 0) {
+        const float zm = (A.z + B.z) * 0.5f;
+        hw = ((0.5f * lv.width[owner]) * cam.fy) / zm;
+    } else {
+        hw = cluster_halfwidth(cam, ax, ay, az, bx, by, bz, A.z, B.z, lv.ahat[g], lv.ahat[lv.nseg + g],
+                               lv.ahat[2 * lv.nseg + g], lv.axes[2 * g], lv.axes[2 * g + 1]);
+    }
+    const float hw16 = 16.0f * hw;
+    SegRec r;
+    r.xa = r.ya = r.xb = r.yb = 0;
+    r.hwfx = 0;
+    r.iza = A.iz;
+    r.izb = B.iz;
+    r.hw = hw;
+    if (A.ok && B.ok && isfinite(hw16) && hw16 >= 0.0f) {
+        r.xa = (int)rintf(A.X16);
+        r.ya = (int)rintf(A.Y16);
+        r.xb = (int)rintf(B.X16);
+        r.yb = (int)rintf(B.Y16);
+        const float c16 = ceilf(hw16);
+        if (abs(r.xb - r.xa) > kMaxAxis || abs(r.yb - r.ya) > kMaxAxis || c16 > (float)kMaxHwFx) {
+            r.hwfx = kFlagCulledLong;
+        } else {
+            r.hwfx = (int)c16 | kFlagVisible;
+            // side of the screen normal (dY, -dX) on which h > 0 (toward y^ = u x x^)
+            const float tx = bx - ax, ty = by - ay, tz = bz - az;
+            const float tl = norm3f(tx, ty, tz);
+            const float ux = tx / tl, uy = ty / tl, uz = tz / tl;
+            const float mx = (ax + bx) * 0.5f, my = (ay + by) * 0.5f, mz = (az + bz) * 0.5f;
+            float wx = cam.pos[0] - mx, wy = cam.pos[1] - my, wz = cam.pos[2] - mz;
+            const float wl = norm3f(wx, wy, wz);
+            wx /= wl; wy /= wl; wz /= wl;
+            const float dwu = (wx * ux + wy * uy) + wz * uz;
+            float px = wx - dwu * ux, py = wy - dwu * uy, pz = wz - dwu * uz;
+            const float pl = fmaxf(norm3f(px, py, pz), 1e-30f);
+            px /= pl; py /= pl; pz /= pl;
+            const float yx = uy * pz - uz * py, yy = uz * px - ux * pz, yz = ux * py - uy * px;
+            const float yvx = (cam.rot[0] * yx + cam.rot[1] * yy) + cam.rot[2] * yz;
+            const float yvy = (cam.rot[3] * yx + cam.rot[4] * yy) + cam.rot[5] * yz;
+            const float yvz = (cam.rot[6] * yx + cam.rot[7] * yy) + cam.rot[8] * yz;
+            const float d0 = mx - cam.pos[0], d1 = my - cam.pos[1], d2 = mz - cam.pos[2];
+            const float mvx = (cam.rot[0] * d0 + cam.rot[1] * d1) + cam.rot[2] * d2;
+            const float mvy = (cam.rot[3] * d0 + cam.rot[4] * d1) + cam.rot[5] * d2;
+            const float mvz = (cam.rot[6] * d0 + cam.rot[7] * d1) + cam.rot[8] * d2;
+            const float Z = -mvz;
+            const float sx = cam.fx * (yvx + (mvx / Z) * yvz);
+            const float sy = -cam.fy * (yvy + (mvy / Z) * yvz);
+            const float side = sx * (float)(r.yb - r.ya) - sy * (float)(r.xb - r.xa);
+            if (side < 0.0f) r.hwfx |= kFlagNegSide;
+        }
+    }
+    return r;
+}
+
 __global__ __launch_bounds__(256) void k_project(LevelDev lv, CamConst cam, SegRec* __restrict__ seg,
                                                  ShadeRec* __restrict__ shade) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    bool vis = false;
-    if (g < lv.nseg) {
-        const int owner = g / lv.S, k = g - owner * lv.S;
-        const int va = owner * (lv.S + 1) + k;
-        const float ax = lv.vx[va], ay = lv.vy[va], az = lv.vz[va];
-        const float bx = lv.vx[va + 1], by = lv.vy[va + 1], bz = lv.vz[va + 1];
-        const PPoint A = project_point(cam, ax, ay, az);
-        const PPoint B = project_point(cam, bx, by, bz);
-        {
-            ShadeRec& sr = shade[g];
-            sr.q0 = make_float4(ax, ay, az, lv.sig[owner]);
-            sr.q1 = make_float4(bx, by, bz, lv.sig[lv.n_owner + owner]);
-            if (lv.kind == 0) {
-                sr.q2 = make_float4(0.f, 0.f, 0.f, lv.sig[2 * lv.n_owner + owner]);
-            } else {
-                sr.q2 = make_float4(lv.ahat[g], lv.ahat[lv.nseg + g], lv.ahat[2 * lv.nseg + g],
-                                    lv.sig[2 * lv.n_owner + owner]);
-                sr.q3 = make_float4(lv.axes[2 * g], lv.axes[2 * g + 1], (float)lv.n_total[owner], lv.r[owner]);
-            }
-        }
-        float hw;
-        if (lv.kind == 0) {
-            const float zm = (A.z + B.z) * 0.5f;
-            hw = ((0.5f * lv.width[owner]) * cam.fy) / zm;
-        } else {
-            hw = cluster_halfwidth(cam, ax, ay, az, bx, by, bz, A.z, B.z, lv.ahat[g], lv.ahat[lv.nseg + g],
-                                   lv.ahat[2 * lv.nseg + g], lv.axes[2 * g], lv.axes[2 * g + 1]);
-        }
-        const float hw16 = 16.0f * hw;
-        SegRec r;
-        r.xa = r.ya = r.xb = r.yb = 0;
-        r.hwfx = 0;
-        r.iza = A.iz;
-        r.izb = B.iz;
-        r.hw = hw;
-        vis = A.ok && B.ok && isfinite(hw16) && hw16 >= 0.0f;
-        if (vis) {
-            r.xa = (int)rintf(A.X16);
-            r.ya = (int)rintf(A.Y16);
-            r.xb = (int)rintf(B.X16);
-            r.yb = (int)rintf(B.Y16);
-            const float c16 = ceilf(hw16);
-            if (abs(r.xb - r.xa) > kMaxAxis || abs(r.yb - r.ya) > kMaxAxis || c16 > (float)kMaxHwFx) {
-                vis = false;
-                r.hwfx = kFlagCulledLong;
-            } else {
-                r.hwfx = (int)c16 | kFlagVisible;
-                // side of the screen normal (dY, -dX) on which h > 0 (toward y^ = u x x^)
-                const float tx = bx - ax, ty = by - ay, tz = bz - az;
-                const float tl = norm3f(tx, ty, tz);
-                const float ux = tx / tl, uy = ty / tl, uz = tz / tl;
-                const float mx = (ax + bx) * 0.5f, my = (ay + by) * 0.5f, mz = (az + bz) * 0.5f;
-                float wx = cam.pos[0] - mx, wy = cam.pos[1] - my, wz = cam.pos[2] - mz;
-                const float wl = norm3f(wx, wy, wz);
-                wx /= wl; wy /= wl; wz /= wl;
-                const float dwu = (wx * ux + wy * uy) + wz * uz;
-                float px = wx - dwu * ux, py = wy - dwu * uy, pz = wz - dwu * uz;
-                const float pl = fmaxf(norm3f(px, py, pz), 1e-30f);
-                px /= pl; py /= pl; pz /= pl;
-                const float yx = uy * pz - uz * py, yy = uz * px - ux * pz, yz = ux * py - uy * px;
-                const float yvx = (cam.rot[0] * yx + cam.rot[1] * yy) + cam.rot[2] * yz;
-                const float yvy = (cam.rot[3] * yx + cam.rot[4] * yy) + cam.rot[5] * yz;
-                const float yvz = (cam.rot[6] * yx + cam.rot[7] * yy) + cam.rot[8] * yz;
-                const float d0 = mx - cam.pos[0], d1 = my - cam.pos[1], d2 = mz - cam.pos[2];
-                const float mvx = (cam.rot[0] * d0 + cam.rot[1] * d1) + cam.rot[2] * d2;
-                const float mvy = (cam.rot[3] * d0 + cam.rot[4] * d1) + cam.rot[5] * d2;
-                const float mvz = (cam.rot[6] * d0 + cam.rot[7] * d1) + cam.rot[8] * d2;
-                const float Z = -mvz;
-                const float sx = cam.fx * (yvx + (mvx / Z) * yvz);
-                const float sy = -cam.fy * (yvy + (mvy / Z) * yvz);
-                const float side = sx * (float)(r.yb - r.ya) - sy * (float)(r.xb - r.xa);
-                if (side < 0.0f) r.hwfx |= kFlagNegSide;
-            }
-        }
-        seg[g] = r;
+    if (g < lv.nseg) seg[g] = project_segment(lv, g, cam, shade + g);
+}
+
+// ---------------------------------------------------------------------------------------
+// Per-group, per-segment LoD (Sec. 5.1 step 5; Sec. 5.2, eq. lod_select).  Groups are the
+// clusters of the coarsest level; every finer level's owners (clusters, or strands at level
+// 0) are listed per group in h.grp_owner[l] (CSR h.grp_start[l]).  The width of (g, k) at
+// level l is the largest 2 hw over the visible k-th segments of level l's owners in g (0 if
+// none is visible).  One wave per (g, k).
+
+// Level of (g, k); levels outside [0, n_levels] are read as 0 (k_sel_count counts them in
+// cnt[G S], which the caller zeroes and checks before rendering).
+__device__ inline int level_at(const HierDev& h, const int32_t* levels, int gk) {
+    const int L = levels[gk];
+    return (L < 0 || L > h.n_levels) ? 0 : L;
+}
+
+// width bits of (g, k) at level l (non-negative float bits order like the floats)
+__device__ inline uint32_t group_width_bits(const HierDev& h, int l, int g, int k, const CamConst& cam) {
+    const LevelDev& lv = h.lv[l];
+    const int b = h.grp_start[l][g], e = h.grp_start[l][g + 1];
+    uint32_t w = 0;
+    for (int i = b + (int)__lane_id(); i < e; i += 64) {
+        const SegRec r = project_segment(lv, h.grp_owner[l][i] * lv.S + k, cam, nullptr);
+        if (r.hwfx & kFlagVisible) w = max(w, __float_as_uint(2.0f * r.hw));
     }
+    for (int off = 32; off >= 1; off >>= 1) w = max(w, (uint32_t)__shfl_xor((int)w, off));
+    return w;
+}
+
+// Initial levels: the coarsest l >= 1 whose width is <= eps_w, else 0 (the strands).
+__global__ __launch_bounds__(256) void k_lod_init(HierDev h, CamConst cam, float eps_w, int32_t* __restrict__ levels) {
+    const int gk = (int)(blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6));
+    if (gk >= h.G * h.S) return;
+    const int g = gk / h.S, k = gk - g * h.S;
+    int pick = 0;
+    for (int l = h.n_levels; l >= 1; --l) {
+        if (__uint_as_float(group_width_bits(h, l, g, k, cam)) <= eps_w) {
+            pick = l;
+            break;
+        }
+    }
+    if (__lane_id() == 0) levels[gk] = pick;
+}
+
+// Deferred update from this frame's level L, with w_cur its width and w_c the width one
+// level coarser: finer if w_cur > eps_w, coarser if w_c <= eps_w, else unchanged.
+__global__ __launch_bounds__(256) void k_lod_update(HierDev h, CamConst cam, float eps_w, int32_t* __restrict__ levels) {
+    const int gk = (int)(blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6));
+    if (gk >= h.G * h.S) return;
+    const int g = gk / h.S, k = gk - g * h.S;
+    const int L = level_at(h, levels, gk);
+    const float w_cur = __uint_as_float(group_width_bits(h, L, g, k, cam));
+    int next = L;
+    if (w_cur > eps_w) {
+        next = max(L - 1, 0);
+    } else if (L < h.n_levels) {
+        const float w_c = __uint_as_float(group_width_bits(h, L + 1, g, k, cam));
+        if (w_c <= eps_w) next = L + 1;
+    }
+    if (__lane_id() == 0) levels[gk] = next;
+}
+
+// Selection of a mixed frame: for every (g, k) the k-th segments of the owners of level
+// L(g, k) in g, in (g, k, owner) order; entry = level << 28 | segment id of that level.
+__global__ __launch_bounds__(256) void k_sel_count(HierDev h, const int32_t* __restrict__ levels,
+                                                   uint32_t* __restrict__ cnt) {
+    const int gk = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gk >= h.G * h.S) return;
+    const int g = gk / h.S, raw = levels[gk], L = level_at(h, levels, gk);
+    if (raw != L) atomicAdd(&cnt[h.G * h.S], 1u);
+    cnt[gk] = (uint32_t)(h.grp_start[L][g + 1] - h.grp_start[L][g]);
+}
+
+__global__ __launch_bounds__(256) void k_sel_fill(HierDev h, const int32_t* __restrict__ levels,
+                                                  const uint32_t* __restrict__ sel_start, uint32_t* __restrict__ sel) {
+    const int gk = (int)(blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6));
+    if (gk >= h.G * h.S) return;
+    const int g = gk / h.S, k = gk - g * h.S, L = level_at(h, levels, gk);
+    const int b = h.grp_start[L][g], e = h.grp_start[L][g + 1];
+    const uint32_t o = sel_start[gk];
+    for (int i = b + (int)__lane_id(); i < e; i += 64)
+        sel[o + (uint32_t)(i - b)] = ((uint32_t)L << 28) | (uint32_t)(h.grp_owner[L][i] * h.S + k);
+}
+
+__global__ __launch_bounds__(256) void k_project_mixed(HierDev h, const uint32_t* __restrict__ sel, int nsel,
+                                                       CamConst cam, SegRec* __restrict__ seg,
+                                                       ShadeRec* __restrict__ shade) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsel) return;
+    const uint32_t e = sel[i];
+    const int L = (int)(e >> 28), g = (int)(e & 0x0FFFFFFFu);
+    SegRec r = project_segment(h.lv[L], g, cam, shade + i);
+    if (h.lv[L].kind == 1) r.hwfx |= kFlagThick;
+    seg[i] = r;
 }
 
 // Exclusive scan of n counts by one 1024-thread block; start[n] = total.
@@ -590,6 +684,7 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
     }
 }
 
+// KIND 0: strands, 1: thick hairs, 2: a mixed frame (the segment's flag decides).
 template <int KIND>
 __device__ inline void shade_fragment(const ShadeArgs& a, uint32_t gseg, int pxg, int pyg, float& alpha, float& hoff,
                                       float L[3]) {
@@ -597,7 +692,7 @@ __device__ inline void shade_fragment(const ShadeArgs& a, uint32_t gseg, int pxg
     const ShadeRec& srec = a.shade[gseg];
     const float4 q0 = srec.q0, q1 = srec.q1, q2 = srec.q2;
     const float sig[3] = {q0.w, q1.w, q2.w};
-    if (KIND == 0) {
+    if (KIND == 0 || (KIND == 2 && !(s.hwfx & kFlagThick))) {
         shade_core<0, float>(a, s, q0, q1, q2, 1.0f, pxg, pyg, s.hw, 0.f, 0.f, 0.f, sig, alpha, hoff, L);
     } else {
         const float4 q3 = srec.q3;
@@ -1717,8 +1812,47 @@ hipError_t launch_batches(const FrameBufs& f, const LevelDev& lv, const CamConst
     DebugDump d = dbg ? *dbg : DebugDump{};
     if (lv.kind == 0)
         hipLaunchKernelGGL(k_batch<0>, dim3(n_batches), dim3(kNT), 0, st, f, a, rgba, d, dbg ? 1 : 0);
-    else
+    else if (lv.kind == 1)
         hipLaunchKernelGGL(k_batch<1>, dim3(n_batches), dim3(kNT), 0, st, f, a, rgba, d, dbg ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_batch<2>, dim3(n_batches), dim3(kNT), 0, st, f, a, rgba, d, dbg ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_lod_init(const HierDev& h, const CamConst& cam, float eps_w, int32_t* levels, hipStream_t st) {
+    const int gk = h.G * h.S;
+    if (gk == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lod_init, dim3((gk + 3) / 4), dim3(256), 0, st, h, cam, eps_w, levels);
+    return hipGetLastError();
+}
+
+hipError_t launch_lod_update(const HierDev& h, const CamConst& cam, float eps_w, int32_t* levels, hipStream_t st) {
+    const int gk = h.G * h.S;
+    if (gk == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lod_update, dim3((gk + 3) / 4), dim3(256), 0, st, h, cam, eps_w, levels);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const HierDev& h, const int32_t* levels, uint32_t* cnt, uint32_t* sel_start,
+                         uint32_t* scan_tmp, hipStream_t st) {
+    const int gk = h.G * h.S;
+    hipLaunchKernelGGL(k_sel_count, dim3(blocks_for(gk, 256)), dim3(256), 0, st, h, levels, cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_exscan(cnt, sel_start, gk, scan_tmp, st);
+}
+
+hipError_t launch_select_fill(const HierDev& h, const int32_t* levels, const uint32_t* sel_start, uint32_t* sel,
+                              hipStream_t st) {
+    const int gk = h.G * h.S;
+    hipLaunchKernelGGL(k_sel_fill, dim3((gk + 3) / 4), dim3(256), 0, st, h, levels, sel_start, sel);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_mixed(const HierDev& h, const uint32_t* sel, int32_t nsel, const CamConst& cam, SegRec* seg,
+                                ShadeRec* shade, hipStream_t st) {
+    if (nsel == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_project_mixed, dim3(blocks_for(nsel, 256)), dim3(256), 0, st, h, sel, nsel, cam, seg, shade);
     return hipGetLastError();
 }
 

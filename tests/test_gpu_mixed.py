@@ -1,0 +1,111 @@
+"""Per-group LoD selection and mixed-level frames on the GPU against the oracle (C-ABI)."""
+import numpy as np
+import pytest
+import torch
+
+import hairsynth as hs
+from oracle import mixed as M
+from oracle import render as R
+
+pytestmark = pytest.mark.gpu
+
+RTOL, ATOL = 1e-4, 1e-7
+
+
+def _lod_dict(L):
+    return {"centers": L.centers, "ahat": L.ahat, "axes": L.axes, "n_total": L.n_total, "sigma_a": L.sigma_a,
+            "r": L.r}
+
+
+@pytest.fixture(scope="module")
+def scene(hip):
+    ctx = hip.Context(0)
+    asset = hs.make_asset(2500, 10, 90.0, seed=23, sigma_spread=True)
+    assigns = hs.kmeans_hierarchy(asset, (400, 80, 12), seed=23)
+    aid = ctx.upload_asset(asset)
+    ctx.build_lod(aid, assigns)
+    lods = [_lod_dict(ctx.get_lod(aid, l)) for l in range(1, 4)]   # the GPU's own level data
+    geoms = M.level_geoms(asset, lods)
+    grps = M.groups(assigns)
+    cam = hs.camera_for(asset, 120, 104)
+    lights = hs.default_lights(asset, with_point=True)
+    G, S = int(assigns[-1].max()) + 1, asset.segs
+    widths = M.level_widths(geoms[1], grps[1], G, S, cam)
+    eps = float(np.median(widths[widths > 0]))
+    yield ctx, asset, aid, assigns, geoms, grps, cam, lights, eps
+    ctx.close()
+
+
+def test_groups_and_initial_levels(hip, scene):
+    print("case: mixed LoD init", flush=True)
+    ctx, asset, aid, assigns, geoms, grps, cam, lights, eps = scene
+    G = ctx.lod_groups(aid)
+    assert G == int(assigns[-1].max()) + 1
+    lev = torch.empty((G, asset.segs), dtype=torch.int32, device="cuda:0")
+    ctx.lod_init(aid, cam, eps, lev)
+    ref = M.init_levels(geoms, grps, cam, eps)
+    got = lev.cpu().numpy()
+    assert len(np.unique(ref)) >= 3
+    assert np.array_equal(got, ref)
+
+
+def test_mixed_frame_matches_oracle_and_updates_levels(hip, scene):
+    print("case: mixed frame", flush=True)
+    ctx, asset, aid, assigns, geoms, grps, cam, lights, eps = scene
+    G, S = ctx.lod_groups(aid), asset.segs
+    rng = np.random.default_rng(7)
+    levels = rng.integers(0, 4, size=(G, S)).astype(np.int32)
+    lev = torch.tensor(levels, device="cuda:0")
+    ws = ctx.workspace()
+    img, st, _ = ctx.render_mixed(aid, cam, lights, lev, eps_w=eps, ws=ws)
+    torch.cuda.synchronize()
+    mixed = M.mixed_geometry(geoms, grps, levels)
+    assert st["segments"] == mixed.pA.shape[1]
+    # projected rows bit-exact, with the thick-hair flag
+    c, XA, YA, XB, YB, izA, izB, hw, hw_fx, vis = R.segment_records(mixed, cam)
+    ri, rf = ctx.debug_segments(ws, mixed.pA.shape[1])
+    assert np.array_equal((ri[:, 5] & 1).astype(bool), vis)
+    for col, ref in enumerate((XA, YA, XB, YB, hw_fx)):
+        assert np.array_equal(ri[vis, col], ref[vis]), col
+    assert np.array_equal(rf[:, 2].view(np.uint32), hw.view(np.uint32))
+    assert np.array_equal((ri[:, 5] & 8) != 0, mixed.thick)
+    ref, ras = R.render(mixed, cam, lights, tuple(float(v) for v in asset.material.as_array()))
+    assert st["fragments"] == len(ras.seg)
+    got = img.cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref) - (RTOL * np.abs(ref) + ATOL)
+    print(f"mixed frame: {len(ras.seg)} fragments, max rel err "
+          f"{float((np.abs(got - ref) / np.maximum(np.abs(ref), 1e-7)).max()):.3e}", flush=True)
+    assert int((err > 0).sum()) == 0
+    # the deferred update that followed the frame
+    assert np.array_equal(lev.cpu().numpy(), M.update_levels(geoms, grps, cam, eps, levels))
+    ws.close()
+
+
+def test_uniform_mixed_equals_level_render(hip, scene):
+    print("case: uniform mixed", flush=True)
+    ctx, asset, aid, assigns, geoms, grps, cam, lights, eps = scene
+    G, S = ctx.lod_groups(aid), asset.segs
+    for l in (0, 3):
+        lev = torch.full((G, S), l, dtype=torch.int32, device="cuda:0")
+        a, _, _ = ctx.render_mixed(aid, cam, lights, lev)
+        b, _, _ = ctx.render(aid, l, cam, lights)
+        torch.cuda.synchronize()
+        assert torch.equal(lev, torch.full_like(lev, l))          # eps_w = 0: levels unchanged
+        x, y = a.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(x - y) <= 2e-4 * np.abs(y) + 1e-7), l
+
+
+def test_mixed_errors(hip, scene):
+    print("case: mixed errors", flush=True)
+    ctx, asset, aid, assigns, geoms, grps, cam, lights, eps = scene
+    G, S = ctx.lod_groups(aid), asset.segs
+    bad = torch.full((G, S), 0, dtype=torch.int32, device="cuda:0")
+    bad[0, 0] = 9
+    with pytest.raises(hip.HairError) as e:
+        ctx.render_mixed(aid, cam, lights, bad)
+    assert e.value.code == hip.HAIR_EINVAL
+    aid2 = ctx.upload_asset(asset)
+    ctx.build_lod(aid2, [hs.kmeans_assign(asset, 40, seed=1), hs.kmeans_assign(asset, 9, seed=2)])
+    with pytest.raises(hip.HairError):
+        ctx.lod_groups(aid2)
+    ctx.release(aid2)
