@@ -100,7 +100,8 @@ def serve_leg(ctx, n_requests: int, warmup: int = 24, rates=(30.0, 60.0, 120.0))
     from paper_2405_10565_amd import serve as S
     assets = S.build_assets(ctx)
     out = {"rates_req_s": list(rates), "requests_per_rate": n_requests, "warmup_per_rate": warmup,
-           "slots": 4, "scratch_budget_gib": 32, "p50_ms": [], "p99_ms": [], "throughput_req_s": [],
+           "slots": 4, "scratch_budget_gib": 32, "lod": "mixed per group and segment, eps_w 2 px",
+           "p50_ms": [], "p99_ms": [], "throughput_req_s": [],
            "mfragments_s": [], "failed": [], "levels": []}
     for rate in rates:
         srv = S.Server(ctx, assets, n_slots=4, scratch_budget=32 << 30)

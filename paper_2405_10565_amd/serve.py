@@ -1,11 +1,14 @@
 """Continuous-batching render server over the HIP library.
 
-Hair assets and their LoD levels stay resident in HBM.  Requests (asset, resolution, view)
-arrive as they come (Poisson arrivals in the benchmark), wait in a FIFO, and are admitted when
-a slot is free and the request's memory footprint fits the scratch budget next to the requests
-already on the GPU.  Each slot owns a HIP stream, a library workspace and an output buffer,
-and runs the per-request LoD choice (Sec. 5.1 step 5: coarsest level whose thick hairs are at
-most eps_w = 2 px wide, Sec. 6) and the frame on its stream; slots overlap on the device.
+Hair assets and their nested LoD hierarchies stay resident in HBM.  Requests (asset,
+resolution, view) arrive as they come (Poisson arrivals in the benchmark), wait in a FIFO, and
+are admitted when a slot is free and the request's memory footprint fits the scratch budget
+next to the requests already on the GPU.  Each slot owns a HIP stream, a library workspace, a
+level buffer and an output buffer, and runs the LoD choice and the frame on its stream; slots
+overlap on the device.  LoD (lod="mixed", the default): per group of the coarsest level and per
+segment index, the coarsest level whose thick hairs are at most eps_w = 2 px wide (Sec. 5.1
+step 5, Sec. 6), rendered as one mixed-level frame (or as that level's own frame when one
+level is chosen everywhere); lod="level": one level for the whole asset.
 A request's latency is its completion time minus its arrival time.
 
     python -m paper_2405_10565_amd.serve [--rates 30 60 120] [--requests 3000] [--warmup 200]
@@ -39,6 +42,7 @@ class Request:
     start: float = 0.0
     done: float = 0.0
     level: int = -1
+    level_hist: list = None     # mixed LoD: (group, segment) entries per level
     fragments: int = 0
     footprint: int = 0
     status: int = 0
@@ -52,6 +56,7 @@ class ServedAsset:
     asset: object              # the host-side description (for framing the camera)
     lights: list
     segments_per_level: list   # segments of level 0..n
+    groups: int = 0            # groups of the nested hierarchy (0: none)
 
 
 class Slot:
@@ -61,15 +66,18 @@ class Slot:
         self.stream = torch.cuda.Stream(device=server.hctx.device)
         self.ws = server.hctx.workspace()
         self.out = torch.empty(max_pixels * 4, dtype=torch.float32, device=f"cuda:{server.hctx.device}")
+        gs = max([a.groups * a.asset.segs for a in server.assets.values()] + [1])
+        self.levels = torch.zeros(gs, dtype=torch.int32, device=f"cuda:{server.hctx.device}")
 
 
 class Server:
     """FIFO admission by footprint; n_slots requests in flight at most."""
 
     def __init__(self, hctx: B.Context, assets: dict, n_slots: int = 4, scratch_budget: int = 32 << 30,
-                 eps_w: float = 2.0, keep_outputs: bool = False):
+                 eps_w: float = 2.0, keep_outputs: bool = False, lod: str = "mixed"):
         self.hctx = hctx
         self.assets = assets
+        self.lod = lod
         self.scratch_budget = int(scratch_budget)
         self.eps_w = eps_w
         self.keep_outputs = keep_outputs
@@ -140,10 +148,23 @@ class Server:
         req.start = self.now()
         req.slot = slot.idx
         try:
-            req.level = self.hctx.select_level(a.aid, cam, self.eps_w, ws=slot.ws, stream=slot.stream)
             out = slot.out[: req.width * req.height * 4].view(req.height, req.width, 4)
-            _, st, rc = self.hctx.render(a.aid, req.level, cam, a.lights, out=out, ws=slot.ws, stream=slot.stream,
-                                         raise_on_error=False)
+            if self.lod == "mixed" and a.groups:
+                lev = slot.levels[: a.groups * a.asset.segs].view(a.groups, a.asset.segs)
+                self.hctx.lod_init(a.aid, cam, self.eps_w, lev, ws=slot.ws, stream=slot.stream)
+                hist = np.bincount(lev.flatten().cpu().numpy(), minlength=len(a.segments_per_level))
+                req.level_hist = hist.tolist()
+                req.level = int(np.argmax(hist))
+                if hist[req.level] == hist.sum():   # one level everywhere: that level's own frame
+                    _, st, rc = self.hctx.render(a.aid, req.level, cam, a.lights, out=out, ws=slot.ws,
+                                                 stream=slot.stream, raise_on_error=False)
+                else:
+                    _, st, rc = self.hctx.render_mixed(a.aid, cam, a.lights, lev, 0.0, out=out, ws=slot.ws,
+                                                       stream=slot.stream, raise_on_error=False)
+            else:
+                req.level = self.hctx.select_level(a.aid, cam, self.eps_w, ws=slot.ws, stream=slot.stream)
+                _, st, rc = self.hctx.render(a.aid, req.level, cam, a.lights, out=out, ws=slot.ws,
+                                             stream=slot.stream, raise_on_error=False)
             req.status = rc
             req.fragments = int(st["fragments"])
             if self.keep_outputs:
@@ -204,7 +225,15 @@ def summarize(reqs, rate: float):
         return {"rate": rate, "completed": 0}
     span = max(r.done for r in ok) - min(r.arrival for r in ok)
     frags = sum(r.fragments for r in ok)
-    levels = np.bincount([r.level for r in ok]).tolist()
+    hists = [r.level_hist for r in ok if r.level_hist is not None]
+    if hists:   # mixed LoD: share of (group, segment) entries per level over all requests
+        n = max(len(h) for h in hists)
+        tot = np.zeros(n)
+        for h in hists:
+            tot[: len(h)] += h
+        levels = [round(float(v), 4) for v in tot / tot.sum()]
+    else:
+        levels = np.bincount([r.level for r in ok]).tolist()
     return {"rate_req_s": rate, "completed": len(ok), "failed": len(reqs) - len(ok),
             "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
             "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
@@ -216,18 +245,17 @@ def summarize(reqs, rate: float):
 
 def build_assets(hctx: B.Context, specs=((10_000, 16), (100_000, 32), (300_000, 48)), seed: int = 1005,
                  level_divisors=(16, 256, 4096)) -> dict:
-    """Upload the serving assets and build their thick-hair levels (resident in HBM)."""
+    """Upload the serving assets and build their nested thick-hair levels (resident in HBM)."""
     import hairsynth as hs
     out = {}
     for i, (n, segs) in enumerate(specs):
         asset = hs.make_asset(n, segs, 90.0, seed=seed + i, sigma_spread=True)
         aid = hctx.upload_asset(asset)
-        assigns = [hs.kmeans_assign(asset, max(1, n // d), seed=seed + i, iters=10, init="random")
-                   for d in level_divisors]
-        hctx.build_lod(aid, assigns)
+        ks = [max(1, n // d) for d in level_divisors]
+        hctx.build_lod(aid, hs.kmeans_hierarchy(asset, ks, seed=seed + i, iters=10, init="random"))
         _, counts, S = hctx.lod_info(aid)
         out[f"{n // 1000}k x {segs}"] = ServedAsset(aid, asset, hs.default_lights(asset, with_point=True),
-                                                     [c * S for c in counts])
+                                                     [c * S for c in counts], hctx.lod_groups(aid))
     return out
 
 
@@ -238,13 +266,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--budget-gib", type=float, default=32.0)
+    ap.add_argument("--lod", choices=["mixed", "level"], default="mixed")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available()
     hctx = B.Context(0)
     assets = build_assets(hctx)
     for rate in args.rates:
-        srv = Server(hctx, assets, n_slots=args.slots, scratch_budget=int(args.budget_gib * (1 << 30)))
+        srv = Server(hctx, assets, n_slots=args.slots, scratch_budget=int(args.budget_gib * (1 << 30)), lod=args.lod)
         reqs = make_requests(sorted(assets), args.requests + args.warmup, seed=int(rate))
         res = summarize(run_poisson(srv, reqs, rate, seed=int(rate), warmup=args.warmup), rate)
         res["peak_in_flight"] = srv.peak_in_flight
