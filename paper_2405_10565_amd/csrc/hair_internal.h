@@ -19,7 +19,7 @@ constexpr int kBinThreads = 512;                 // threads per binning block
 constexpr int kMaxLdsTiles = 36864;              // per-tile LDS counters of one binning pass (144 KiB)
 
 // Projected segment, one per segment of the rendered level (32 bytes, AoS for gathers).
-struct SegRec {
+struct alignas(16) SegRec {
     int32_t xa, ya, xb, yb;   // endpoints, 1/16-pixel units
     int32_t hwfx;             // coverage half-width ceil(16 hw) in bits 0..15; flags above
     float iza, izb;           // inverse view depth at the endpoints

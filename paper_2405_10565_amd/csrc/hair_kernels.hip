@@ -127,16 +127,15 @@ __device__ inline SegRec project_segment(const LevelDev& lv, int g, const CamCon
     const float bx = lv.vx[va + 1], by = lv.vy[va + 1], bz = lv.vz[va + 1];
     const PPoint A = project_point(cam, ax, ay, az);
     const PPoint B = project_point(cam, bx, by, bz);
-    if (sr) {
+    if (sr) {   // whole float4 stores (q3 only for thick hairs)
+        const float sb = lv.sig[2 * lv.n_owner + owner];
+        float4 q2 = make_float4(0.f, 0.f, 0.f, sb);
+        if (lv.kind != 0) q2 = make_float4(lv.ahat[g], lv.ahat[lv.nseg + g], lv.ahat[2 * lv.nseg + g], sb);
         sr->q0 = make_float4(ax, ay, az, lv.sig[owner]);
         sr->q1 = make_float4(bx, by, bz, lv.sig[lv.n_owner + owner]);
-        if (lv.kind == 0) {
-            sr->q2 = make_float4(0.f, 0.f, 0.f, lv.sig[2 * lv.n_owner + owner]);
-        } else {
-            sr->q2 = make_float4(lv.ahat[g], lv.ahat[lv.nseg + g], lv.ahat[2 * lv.nseg + g],
-                                 lv.sig[2 * lv.n_owner + owner]);
+        sr->q2 = q2;
+        if (lv.kind != 0)
             sr->q3 = make_float4(lv.axes[2 * g], lv.axes[2 * g + 1], (float)lv.n_total[owner], lv.r[owner]);
-        }
     }
     float hw;
     if (lv.kind == 0) {
