@@ -35,10 +35,25 @@ __all__ = [
 
 @dataclass
 class Material:
+    """Fibre material.  model 0: near-field R / TT / TRT (eta, alpha, beta_m, beta_n and the
+    strands' absorption); model 1: R / TT / D with constant attenuations, defaults inside the
+    paper's stated ranges (Sec. 6: beta_R 0.08-0.15, beta_TT 0.12-0.3, gamma_TT 0.2-0.4,
+    A_R 0.03-0.25, A_TT (0.25, 0.17, 0.07)-(0.38, 0.25, 0.18), A_D (0.2, 0.11, 0.1)-(0.4, 0.21, 0.08))."""
     eta: float = 1.55
     alpha: float = math.radians(-3.0)   # longitudinal shift (radians)
     beta_m: float = 0.3                  # longitudinal width (radians, std dev)
     beta_n: float = 0.3                  # azimuthal width (radians, std dev)
+    model: int = 0
+    beta_r: float = 0.1
+    beta_tt: float = 0.2
+    gamma_tt: float = 0.3
+    a_r: tuple = (0.1, 0.1, 0.1)
+    a_tt: tuple = (0.3, 0.2, 0.12)
+    a_d: tuple = (0.3, 0.16, 0.09)
+
+    @classmethod
+    def rttd(cls, **kw) -> "Material":
+        return cls(model=1, **kw)
 
     def as_array(self) -> np.ndarray:
         return np.array([self.eta, self.alpha, self.beta_m, self.beta_n], dtype=np.float32)

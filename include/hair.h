@@ -4,7 +4,7 @@
  * Method: "Real-time Level-of-detail Strand-based Hair Rendering" (arxiv 2405.10565).
  *   - strands and their elliptical thick-hair (cluster) levels:        Sec. 5.1
  *   - per-frame hair width and level choice (eps_w = 2 px):            Sec. 5.1 step 5, 5.2, 6
- *   - single-fibre scattering f = sum_p A_p M_p N_p:                   Sec. 3.1 (eq. bcsdf)
+ *   - single-fibre scattering f = sum_p A_p M_p N_p (R/TT/TRT, R/TT/D): Sec. 3.1 (eq. bcsdf)
  *   - aggregated thick-hair scattering f_ours:                         Sec. 4 (eq. our_bcsdf)
  *   - radiance L = sum_lights E f cos(theta_i):                        Sec. 3 (rendering eq.)
  * Segments are binned into 16x16-pixel tiles, covered on a 1/16-pixel integer grid, shaded
@@ -45,12 +45,27 @@ extern "C" {
 typedef struct hair_ctx hair_ctx;
 typedef struct hair_ws hair_ws;
 
-/* Fibre material (Sec. 6 parameter ranges): relative index eta, longitudinal shift alpha
- * (radians, R lobe; TT and TRT use -alpha/2 and -3 alpha/2), longitudinal width beta_m
- * (radians, standard deviation of theta_h for R; TT and TRT use beta_m/2 and 2 beta_m),
- * azimuthal width beta_n (radians, standard deviation). */
+/* Single-fibre scattering model of a material. */
+#define HAIR_MODEL_RTTRT 0 /* near-field R / TT / TRT; attenuation from eta and sigma_a */
+#define HAIR_MODEL_RTTD 1  /* R / TT / D with constant RGB attenuations (Sec. 3.1, eq. bcsdf) */
+
+/* Fibre material.
+ * model HAIR_MODEL_RTTRT reads: relative index eta (> 1), longitudinal shift alpha (radians,
+ *   |alpha| <= 0.5; R lobe, TT and TRT use -alpha/2 and -3 alpha/2), longitudinal width beta_m
+ *   (radians, in (0, 2), standard deviation of theta_h for R; TT and TRT use beta_m/2 and
+ *   2 beta_m), azimuthal width beta_n (radians, in (0, 4), standard deviation); the per-strand
+ *   absorption sigma_a sets the attenuations.
+ * model HAIR_MODEL_RTTD reads (Sec. 3.1 and the lobe shapes of Sec. 4; Sec. 6 gives the
+ *   ranges 0.08-0.15, 0.12-0.3, 0.2-0.4 and the attenuations): beta_r, beta_tt (radians, in
+ *   (0, 2): M_R = 1/2 G(beta_r, theta_h), M_TT = 1/2 G(beta_tt, theta_h)), gamma_tt (radians,
+ *   in (0, 4): N_TT = G(gamma_tt, phi - pi)), a_r, a_tt, a_d (RGB, >= 0, a_r + a_tt + a_d <= 1
+ *   per channel); M_D = 1/pi and N_R = N_D = 1/(2 pi).  sigma_a is not used.
+ * Fields the chosen model does not read are ignored. */
 typedef struct hair_material {
     float eta, alpha, beta_m, beta_n;
+    int32_t model;
+    float beta_r, beta_tt, gamma_tt;
+    float a_r[3], a_tt[3], a_d[3];
 } hair_material;
 
 /* Pinhole camera.  rot: row-major world->view rotation; the view looks along -z with +y up.
@@ -121,7 +136,7 @@ uint64_t hair_ws_estimate(int64_t n_segments, int32_t width, int32_t height, int
  *               vertex k of strand s at column s * verts_per_strand + k.
  *   width       host float[n_strands]: fibre diameter (m), > 0.
  *   sigma_a_soa host float[3][n_strands]: absorption per unit fibre radius (RGB), >= 0.
- *   material    host, see hair_material (eta > 1, beta_m > 0, beta_n > 0).
+ *   material    host, see hair_material (ranges there; out of range -> HAIR_EINVAL).
  * verts_per_strand >= 2.  All values finite.  *asset_out receives the asset id; level 0 is
  * the strands.  Data stays resident in HBM until hair_release or hair_ctx_destroy. */
 int hair_upload(hair_ctx* ctx, int32_t n_strands, int32_t verts_per_strand,

@@ -8,6 +8,7 @@ It is a plain, slow, deliberately unoptimised restatement of what the renderer c
 
   * fiber.py     single-fibre scattering function, near-field R/TT/TRT     (Sec. 3.1, 3.2)
   * aggregate.py the aggregated thick-hair scattering function             (Sec. 4)
+  * rttd.py      the R / TT / D single-fibre model and its aggregated form   (Sec. 3.1, 4)
   * raster.py    projection, tile binning, coverage, alpha, depth key      (Sec. 5.2 strips)
   * lod.py       thick-hair (elliptical cluster) construction              (Sec. 5.1 step 3)
   * render.py    per-fragment radiance and depth-ordered compositing        (Sec. 3 eq. for L_o)

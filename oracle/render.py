@@ -3,7 +3,9 @@
   * Radiance of a fragment: L = sum over lights of E * f(omega_i, omega_o, h) * cos(theta_i)
     (Sec. 3, the fibre rendering equation with a directional or point light: f cos^2 theta_i
     d theta_i d phi_i = f cos theta_i d omega_i).  A directional light has irradiance E; a
-    point light E = I / |x_L - x|^2.  No shadowing between hairs.
+    point light E = I / |x_L - x|^2.  No shadowing between hairs.  f is the near-field
+    R / TT / TRT model (fiber, aggregate) for a (eta, alpha, beta_m, beta_n) material and the
+    R / TT / D model (rttd) for an rttd.RTTD material.
   * Shading frame: u = unit segment tangent, omega_o toward the camera from the fragment's
     world point (perspective-correct parameter t_w = t izB / iz), x^ = normalize(omega_o -
     (omega_o . u) u), y^ = u x x^, sin theta = omega . u, phi = phi_o - phi_i =
@@ -26,6 +28,7 @@ import numpy as np
 import torch
 
 from . import raster as rs
+from . import rttd
 from .aggregate import ellipse_chord, ellipse_support, f_ours, hair_counts
 from .fiber import angles, f_single
 
@@ -223,6 +226,17 @@ def _mixed_radiance(geom: LevelGeom, ras: Raster, cam, lights, mat):
     return alpha, L
 
 
+def material(m):
+    """Oracle material from an object with the library's material fields, at the float32
+    values the library receives: an (eta, alpha, beta_m, beta_n) tuple for model 0, an
+    rttd.RTTD for model 1."""
+    f = lambda v: float(np.float32(v))
+    if getattr(m, "model", 0) == 1:
+        return rttd.RTTD(f(m.beta_r), f(m.beta_tt), f(m.gamma_tt), tuple(f(v) for v in m.a_r),
+                         tuple(f(v) for v in m.a_tt), tuple(f(v) for v in m.a_d))
+    return (f(m.eta), f(m.alpha), f(m.beta_m), f(m.beta_n))
+
+
 def fragment_radiance(geom: LevelGeom, ras: Raster, cam, lights, mat, params=None):
     """(alpha [F], L [F, 3]) in float64.
 
@@ -261,7 +275,7 @@ def fragment_radiance(geom: LevelGeom, ras: Raster, cam, lights, mat, params=Non
         sc = torch.clamp(sin_ti, -1.0, 1.0)
         cos_ti = torch.sqrt((1.0 - sc) * (1.0 + sc))
         if geom.kind == "strand":
-            f = f_single(th, xd, phi, h, sig, mat)
+            f = rttd.f_single(th, phi, mat) if isinstance(mat, rttd.RTTD) else f_single(th, xd, phi, h, sig, mat)
         else:
             Dp = wi - sin_ti[:, None] * u
             dn = torch.linalg.norm(Dp, dim=-1)
@@ -269,7 +283,10 @@ def fragment_radiance(geom: LevelGeom, ras: Raster, cam, lights, mat, params=Non
             s_star = ellipse_chord(h, W, xh, yh, ahat, bhat, a_len, b_len, D)
             s_star = torch.where(dn > 1e-7, s_star, torch.zeros_like(s_star))
             rho, n_F, n_B = hair_counts(phi, s_star, n_total, r, a_len, b_len)
-            f = f_ours(th, xd, phi, h, sig, mat, n_total, rho, n_F, n_B)
+            if isinstance(mat, rttd.RTTD):
+                f = rttd.f_ours(th, phi, mat, n_total, rho, n_F, n_B)
+            else:
+                f = f_ours(th, xd, phi, h, sig, mat, n_total, rho, n_F, n_B)
         L = L + E * f * cos_ti[:, None]
     return alpha, L
 

@@ -36,8 +36,27 @@ class HairError(RuntimeError):
         self.code = code
 
 
+MODEL_RTTRT, MODEL_RTTD = 0, 1
+
+
 class hair_material(C.Structure):
-    _fields_ = [("eta", C.c_float), ("alpha", C.c_float), ("beta_m", C.c_float), ("beta_n", C.c_float)]
+    _fields_ = [("eta", C.c_float), ("alpha", C.c_float), ("beta_m", C.c_float), ("beta_n", C.c_float),
+                ("model", C.c_int32), ("beta_r", C.c_float), ("beta_tt", C.c_float), ("gamma_tt", C.c_float),
+                ("a_r", C.c_float * 3), ("a_tt", C.c_float * 3), ("a_d", C.c_float * 3)]
+
+
+def make_material(material) -> hair_material:
+    """hair_material from an object with the struct's field names (model defaults to
+    R / TT / TRT) or from a sequence (eta, alpha, beta_m, beta_n)."""
+    if not hasattr(material, "eta"):
+        return hair_material(*[float(v) for v in material])
+    m = hair_material(float(material.eta), float(material.alpha), float(material.beta_m), float(material.beta_n),
+                      int(getattr(material, "model", MODEL_RTTRT)))
+    if m.model == MODEL_RTTD:
+        m.beta_r, m.beta_tt, m.gamma_tt = float(material.beta_r), float(material.beta_tt), float(material.gamma_tt)
+        for name in ("a_r", "a_tt", "a_d"):
+            getattr(m, name)[:] = [float(v) for v in getattr(material, name)]
+    return m
 
 
 class hair_camera(C.Structure):
@@ -225,7 +244,7 @@ class Context:
         xyz = np.ascontiguousarray(xyz_soa, dtype=np.float32)
         w = np.ascontiguousarray(width, dtype=np.float32)
         sg = np.ascontiguousarray(sigma_a_soa, dtype=np.float32)
-        m = hair_material(*[float(v) for v in material])
+        m = make_material(material)
         aid = C.c_int32()
         check(lib.hair_upload(self.handle, int(n_strands), int(verts_per_strand), _fptr(xyz), _fptr(w), _fptr(sg),
                               C.byref(m), C.c_void_p(stream), C.byref(aid)))
@@ -233,7 +252,7 @@ class Context:
 
     def upload_asset(self, asset, stream=0) -> int:
         return self.upload(asset.n_strands, asset.verts_per_strand, asset.xyz, asset.width, asset.sigma_a,
-                           asset.material.as_array(), stream)
+                           asset.material, stream)
 
     def release(self, asset: int):
         check(lib.hair_release(self.handle, asset))

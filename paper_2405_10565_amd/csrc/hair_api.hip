@@ -181,6 +181,23 @@ int need_device(hair_ctx* ctx) {
 
 int validate_material(const hair_material* m) {
     if (!m) return fail(HAIR_EINVAL, "null material");
+    if (m->model == HAIR_MODEL_RTTD) {
+        if (!(std::isfinite(m->beta_r) && m->beta_r > 0.0f && m->beta_r < 2.0f))
+            return fail(HAIR_EINVAL, "material beta_r must be in (0, 2)");
+        if (!(std::isfinite(m->beta_tt) && m->beta_tt > 0.0f && m->beta_tt < 2.0f))
+            return fail(HAIR_EINVAL, "material beta_tt must be in (0, 2)");
+        if (!(std::isfinite(m->gamma_tt) && m->gamma_tt > 0.0f && m->gamma_tt < 4.0f))
+            return fail(HAIR_EINVAL, "material gamma_tt must be in (0, 4)");
+        for (int c = 0; c < 3; ++c) {
+            const float v[3] = {m->a_r[c], m->a_tt[c], m->a_d[c]};
+            for (float x : v)
+                if (!(std::isfinite(x) && x >= 0.0f)) return fail(HAIR_EINVAL, "material attenuations must be >= 0");
+            if ((double)v[0] + v[1] + v[2] > 1.0)
+                return fail(HAIR_EINVAL, "material a_r + a_tt + a_d must be <= 1 in every channel");
+        }
+        return HAIR_OK;
+    }
+    if (m->model != HAIR_MODEL_RTTRT) return fail(HAIR_EINVAL, "unknown material model %d", (int)m->model);
     if (!(std::isfinite(m->eta) && m->eta > 1.0f)) return fail(HAIR_EINVAL, "material eta must be finite and > 1");
     if (!std::isfinite(m->alpha) || std::fabs(m->alpha) > 0.5f)
         return fail(HAIR_EINVAL, "material alpha must be finite with |alpha| <= 0.5 rad");
@@ -241,7 +258,7 @@ LightsConst lights_const(const hair_light* l, int n) {
 }
 
 MatConst mat_const(const hair_material& m) {
-    MatConst k;
+    MatConst k{};
     k.eta = m.eta;
     k.inv_eta2 = (float)(1.0 / ((double)m.eta * (double)m.eta));
     k.alpha_p[0] = m.alpha; k.alpha_p[1] = -0.5f * m.alpha; k.alpha_p[2] = -1.5f * m.alpha;
@@ -261,6 +278,37 @@ MatConst mat_const(const hair_material& m) {
     const double lo = 1.0 / (1.0 + std::exp(M_PI / s)), hi = 1.0 / (1.0 + std::exp(-M_PI / s));
     k.cdf_lo = (float)lo;
     k.cdf_scale = (float)(1.0 / (hi - lo));
+    k.model = m.model;
+    if (m.model == HAIR_MODEL_RTTD) {
+        const double bR = m.beta_r, bT = m.beta_tt, g = m.gamma_tt;
+        const double b[2] = {bR, bT};
+        for (int p = 0; p < 2; ++p) {
+            k.d_amp[p] = (float)(0.5 / (b[p] * std::sqrt(2.0 * M_PI)));
+            k.d_k2[p] = (float)(M_LOG2E / (2.0 * b[p] * b[p]));
+            k.d_beta2[p] = (float)(b[p] * b[p]);
+        }
+        k.n_amp = (float)(1.0 / (g * std::sqrt(2.0 * M_PI)));
+        k.n_k2 = (float)(M_LOG2E / (2.0 * g * g));
+        k.gamma2 = (float)(g * g);
+        // hemisphere masses: R and D split evenly; TT (about phi = pi) puts erf(pi / (2 sqrt2 g))
+        // in front (|phi| > pi/2), the rest of its wrapped mass behind
+        const double fT = std::erf(0.5 * M_PI / (std::sqrt(2.0) * g));
+        const double bTm = std::erf(M_PI / (std::sqrt(2.0) * g)) - fT;
+        double mR = 0.0, mT = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            k.A[0][c] = m.a_r[c];
+            k.A[1][c] = m.a_tt[c];
+            k.A[2][c] = m.a_d[c];
+            k.aF[c] = (float)(0.5 * m.a_r[c] + fT * m.a_tt[c] + 0.5 * m.a_d[c]);
+            k.aB[c] = (float)(0.5 * m.a_r[c] + bTm * m.a_tt[c] + 0.5 * m.a_d[c]);
+            mR += m.a_r[c] / 3.0;
+            mT += m.a_tt[c] / 3.0;
+        }
+        // attenuation-weighted longitudinal variances of the R and TT mass in each hemisphere
+        auto mean_var = [&](double wR, double wT) { return wR + wT > 0.0 ? (wR * bR * bR + wT * bT * bT) / (wR + wT) : 0.0; };
+        k.var_f = (float)mean_var(0.5 * mR, fT * mT);
+        k.var_b = (float)mean_var(0.5 * mR, bTm * mT);
+    }
     return k;
 }
 
@@ -462,7 +510,7 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
 // =======================================================================================
 extern "C" {
 
-int hair_version(void) { return 100; }
+int hair_version(void) { return 101; }
 
 const char* hair_last_error(void) { return g_err.c_str(); }
 

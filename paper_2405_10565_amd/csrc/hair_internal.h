@@ -72,6 +72,16 @@ struct MatConst {
     float inv_s_l2;          // log2(e) / s
     float n_norm;            // trimmed-logistic normaliser 1 / (s tanh(pi / 2s))
     float cdf_lo, cdf_scale; // trimmed CDF: (sigmoid(x / s) - cdf_lo) * cdf_scale on [-pi, pi]
+    // R / TT / D model (model == 1); the fields above serve model 0
+    int32_t model;
+    float d_amp[2];          // M_R, M_TT = d_amp exp2(-d_k2 theta_h^2): 1 / (2 beta sqrt(2 pi))
+    float d_k2[2];           //                                     log2(e) / (2 beta^2)
+    float d_beta2[2];        // beta_R^2, beta_TT^2
+    float n_amp, n_k2;       // N_TT = n_amp exp2(-n_k2 psi^2): 1 / (gamma sqrt(2 pi)), log2(e) / (2 gamma^2)
+    float gamma2;            // gamma_TT^2
+    float A[3][3];           // [R, TT, D][channel] attenuations
+    float aF[3], aB[3];      // front / back hemisphere albedos
+    float var_f, var_b;      // attenuation-weighted longitudinal variances (front / back)
 };
 
 // One renderable level, device pointers.

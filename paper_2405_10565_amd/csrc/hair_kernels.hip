@@ -574,7 +574,7 @@ struct ShadeArgs {
 // the scalar type T: float for rendering, Dual<N> for the backward pass.  T carries the
 // fitted parameters (half-width hw, semi-axes |a|, |b|, hair radius r, absorption); the view
 // geometry (frame, angles) does not depend on them and stays float.
-template <int KIND, class T>
+template <int KIND, int MODEL, class T>
 __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const float4& q0, const float4& q1,
                                   const float4& q2, float n_total, int pxg, int pyg, const T& hw, const T& a_len,
                                   const T& b_len, const T& rr, const T sig[3], T& alpha, T& hoff, T L[3]) {
@@ -587,8 +587,24 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
     const int cr = ex * dy - ey * dx;
     const float t = (float)tnum / (float)tden;
     const float iz = s.iza + t * (s.izb - s.iza);
-    const float delta = fabsf((float)cr) / sqrtf((float)tden) * (1.0f / 16.0f);
-    alpha = m_min(m_max(m_min(hw + delta, T(0.5f)) - m_max(delta - hw, T(-0.5f)), T(0.0f)), T(1.0f));
+    float delta;
+    T d_minus, d_plus;   // delta - hw, delta + hw
+    if (KIND == 1) {
+        // a thick hair is many pixels wide, so at its footprint's edge alpha = 1/2 - (delta - hw)
+        // is a small difference of large numbers; delta is carried as a float pair (hi + lo) from
+        // a double evaluation, and hi - hw is exact there (Sterbenz), which keeps alpha's
+        // absolute error at the level of a strand's instead of an ulp of the hair width
+        const double dd = fabs((double)cr) / sqrt((double)tden) * (1.0 / 16.0);
+        delta = (float)dd;
+        const float dlo = (float)(dd - (double)delta);
+        d_minus = (delta - hw) + dlo;
+        d_plus = (hw + delta) + dlo;
+    } else {
+        delta = fabsf((float)cr) / sqrtf((float)tden) * (1.0f / 16.0f);
+        d_minus = delta - hw;
+        d_plus = hw + delta;
+    }
+    alpha = m_min(m_max(m_min(d_plus, T(0.5f)) - m_max(d_minus, T(-0.5f)), T(0.0f)), T(1.0f));
     float sgn = cr > 0 ? 1.0f : (cr < 0 ? -1.0f : 0.0f);
     if (s.hwfx & kFlagNegSide) sgn = -sgn;
     const T h = m_min(m_max((sgn * delta) / (hw + 0.5f), T(-1.0f)), T(1.0f));
@@ -605,6 +621,10 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
     const float dwu = dot(wo, u);
     V3<float> wp = sub(wo, scale(u, dwu));
     float wpn2 = dot(wp, wp);
+    // the longitudinal angle from both of its legs: atan2(sin, |w_perp|) stays accurate where
+    // asin(sin) loses digits (views and lights close to the fibre axis, where the narrow
+    // longitudinal lobes are most sensitive to theta)
+    const float cos_to = m_sqrt(wpn2);
     const bool degen = wpn2 < 1e-14f;
     if (degen) {  // view along the fibre: any normal direction; phi is set to 0
         const float ax = fabsf(u.x), ay = fabsf(u.y), az = fabsf(u.z);
@@ -615,8 +635,7 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
     const V3<float> xh = scale(wp, m_rsqrt(wpn2));
     const V3<float> yh = cross(u, xh);
     const float sin_to = fminf(fmaxf(dwu, -1.0f), 1.0f);
-    const float to = m_asin(sin_to);
-    const float cos_to = m_sqrt((1.0f - sin_to) * (1.0f + sin_to));
+    const float to = m_atan2(sin_to, cos_to);
     const T gamma_o = m_asin(h);
     const T cgo = m_sqrt((1.0f - h) * (1.0f + h));
     const T sigl[3] = {sig[0] * kLog2e, sig[1] * kLog2e, sig[2] * kLog2e};
@@ -653,7 +672,10 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
         const LightView v = light_view(sin_ti, sin_to, to, cos_to, dot(wi, xh), dot(wi, yh), degen, a.mat);
         T f[3];
         if (KIND == 0) {
-            f_single(v, h, gamma_o, cgo, sigl, a.mat, f);
+            if (MODEL == 0)
+                f_single(v, h, gamma_o, cgo, sigl, a.mat, f);
+            else
+                f_single_rttd(v, a.mat, f);
         } else {
             // chord of the view ray's entry point toward the light, in the cross-section
             const V3<float> Dp = sub(wi, scale(u, sin_ti));
@@ -675,7 +697,10 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
             const bool back = fabsf(v.phi) < 0.5f * kPi;
             cf.n_F = (back || n_total < 2.0f) ? T(1.0f) : m_max(cf.rho * kappa * lF, T(1.0f));
             cf.n_B = m_max(cf.rho * kappa * lB, T(1.0f));
-            f_ours(v, h, gamma_o, cgo, sigl, a.mat, cf, f);
+            if (MODEL == 0)
+                f_ours(v, h, gamma_o, cgo, sigl, a.mat, cf, f);
+            else
+                f_ours_rttd(v, a.mat, cf, f);
         }
         L[0] = L[0] + (E[0] * v.cos_ti) * f[0];
         L[1] = L[1] + (E[1] * v.cos_ti) * f[1];
@@ -684,7 +709,8 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
 }
 
 // KIND 0: strands, 1: thick hairs, 2: a mixed frame (the segment's flag decides).
-template <int KIND>
+// MODEL 0: near-field R / TT / TRT, 1: R / TT / D.
+template <int KIND, int MODEL>
 __device__ inline void shade_fragment(const ShadeArgs& a, uint32_t gseg, int pxg, int pyg, float& alpha, float& hoff,
                                       float L[3]) {
     const SegRec s = a.seg[gseg];
@@ -692,10 +718,10 @@ __device__ inline void shade_fragment(const ShadeArgs& a, uint32_t gseg, int pxg
     const float4 q0 = srec.q0, q1 = srec.q1, q2 = srec.q2;
     const float sig[3] = {q0.w, q1.w, q2.w};
     if (KIND == 0 || (KIND == 2 && !(s.hwfx & kFlagThick))) {
-        shade_core<0, float>(a, s, q0, q1, q2, 1.0f, pxg, pyg, s.hw, 0.f, 0.f, 0.f, sig, alpha, hoff, L);
+        shade_core<0, MODEL, float>(a, s, q0, q1, q2, 1.0f, pxg, pyg, s.hw, 0.f, 0.f, 0.f, sig, alpha, hoff, L);
     } else {
         const float4 q3 = srec.q3;
-        shade_core<1, float>(a, s, q0, q1, q2, q3.z, pxg, pyg, s.hw, q3.x, q3.y, q3.w, sig, alpha, hoff, L);
+        shade_core<1, MODEL, float>(a, s, q0, q1, q2, q3.z, pxg, pyg, s.hw, q3.x, q3.y, q3.w, sig, alpha, hoff, L);
     }
 }
 
@@ -1085,7 +1111,7 @@ struct BatchLds {
 // counts, key ranges and offsets are in s_cnt / s_kmin / s_kmax / s_off).  Finished pixels are
 // written to rgba, or (slice_out != nullptr, a single pixel's key slice) their (C, T) goes to
 // slice_out.  rank0 / cnt_total place a slice inside its pixel for the debug dump.
-template <int KIND>
+template <int KIND, int MODEL>
 __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, float* __restrict__ rgba,
                                         const DebugDump& dbg, int has_dbg, const BatchLds& L_, const uint32_t* list,
                                         const uint2* src, int px0, int py0, uint32_t Fb, float* slice_out,
@@ -1113,7 +1139,7 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
         const uint32_t gseg = list[rec.y & 0xFFFFFFu];
         const int gx = px0 + (int)(p % kTile), gy = py0 + (int)(p / kTile);
         float al, hh, L[3];
-        shade_fragment<KIND>(a, gseg, gx, gy, al, hh, L);
+        shade_fragment<KIND, MODEL>(a, gseg, gx, gy, al, hh, L);
         s_pay[3 * i + 0] = al * L[0];
         s_pay[3 * i + 1] = al * L[1];
         s_pay[3 * i + 2] = al * L[2];
@@ -1221,7 +1247,7 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
 // pixel deeper than one batch (its own "oversized" batch) is processed in depth-key slices:
 // a histogram over the pixel's key range picks the longest run of bins that fits LDS, those
 // records are gathered and processed exactly, and the slice composites chain front to back.
-template <int KIND>
+template <int KIND, int MODEL>
 __global__ __launch_bounds__(kNT) void k_batch(FrameBufs f, ShadeArgs a, float* __restrict__ rgba, DebugDump dbg,
                                                int has_dbg) {
     __shared__ uint32_t s_cnt[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix], s_off[kTilePix + 1];
@@ -1259,7 +1285,7 @@ __global__ __launch_bounds__(kNT) void k_batch(FrameBufs f, ShadeArgs a, float* 
         for (uint32_t i = t; i < Fb; i += kNT) L_.s_bk[i] = 0;
         __syncthreads();
         PHASE_END(f.ctr, 5);
-        sort_shade_blend<KIND>(f, a, rgba, dbg, has_dbg, L_, list, src, px0, py0, Fb, nullptr, 0, 0);
+        sort_shade_blend<KIND, MODEL>(f, a, rgba, dbg, has_dbg, L_, list, src, px0, py0, Fb, nullptr, 0, 0);
         return;
     }
     // ---- a pixel deeper than one batch: exact depth-key slices
@@ -1325,7 +1351,7 @@ __global__ __launch_bounds__(kNT) void k_batch(FrameBufs f, ShadeArgs a, float* 
             s_off[p + 1] = Fb;
         }
         __syncthreads();
-        sort_shade_blend<KIND>(f, a, rgba, dbg, has_dbg, L_, list, L_.s_A, px0, py0, Fb, s_slice, done, k);
+        sort_shade_blend<KIND, MODEL>(f, a, rgba, dbg, has_dbg, L_, list, L_.s_A, px0, py0, Fb, s_slice, done, k);
         __syncthreads();
         if (t == 0) {
             C0 += T * s_slice[0];
@@ -1389,6 +1415,7 @@ __device__ inline void halfwidth_partials(const CamConst& c, const SegRec& s, co
     db = W > 0.0f ? k * b_len * cb * cb / W : 0.0f;
 }
 
+template <int MODEL>
 __global__ __launch_bounds__(kNT) void k_batch_bwd(FrameBufs f, ShadeArgs a, GradOut g, int S, int K) {
     __shared__ uint32_t s_cnt[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix], s_off[kTilePix + 1];
     __shared__ uint32_t s_tmp[kNT];
@@ -1441,7 +1468,7 @@ __global__ __launch_bounds__(kNT) void k_batch_bwd(FrameBufs f, ShadeArgs a, Gra
         const uint32_t p = rec.y >> 24;
         const uint32_t gseg = list[rec.y & 0xFFFFFFu];
         float al, hh, L[3];
-        shade_fragment<1>(a, gseg, px0 + (int)(p % kTile), py0 + (int)(p / kTile), al, hh, L);
+        shade_fragment<1, MODEL>(a, gseg, px0 + (int)(p % kTile), py0 + (int)(p / kTile), al, hh, L);
         s_p4[i] = make_float4(al, L[0], L[1], L[2]);
     }
     __syncthreads();
@@ -1554,8 +1581,8 @@ __global__ __launch_bounds__(kNT) void k_batch_bwd(FrameBufs f, ShadeArgs a, Gra
         const Dual6 al = Dual6::seed(q3.x, 0), bl = Dual6::seed(q3.y, 1), rr = Dual6::seed(q3.w, 2);
         const Dual6 sig[3] = {Dual6::seed(q0.w, 3), Dual6::seed(q1.w, 4), Dual6::seed(q2.w, 5)};
         Dual6 alpha, hoff, L[3];
-        shade_core<1, Dual6>(a, s, q0, q1, q2, q3.z, px0 + (int)(p % kTile), py0 + (int)(p / kTile), hw, al, bl, rr,
-                             sig, alpha, hoff, L);
+        shade_core<1, MODEL, Dual6>(a, s, q0, q1, q2, q3.z, px0 + (int)(p % kTile), py0 + (int)(p / kTile), hw, al, bl,
+                                    rr, sig, alpha, hoff, L);
         float gp[6];
 #pragma unroll
         for (int m = 0; m < 6; ++m)
@@ -1809,12 +1836,17 @@ hipError_t launch_batches(const FrameBufs& f, const LevelDev& lv, const CamConst
     a.seg = f.seg;
     a.shade = f.shade;
     DebugDump d = dbg ? *dbg : DebugDump{};
-    if (lv.kind == 0)
-        hipLaunchKernelGGL(k_batch<0>, dim3(n_batches), dim3(kNT), 0, st, f, a, rgba, d, dbg ? 1 : 0);
-    else if (lv.kind == 1)
-        hipLaunchKernelGGL(k_batch<1>, dim3(n_batches), dim3(kNT), 0, st, f, a, rgba, d, dbg ? 1 : 0);
-    else
-        hipLaunchKernelGGL(k_batch<2>, dim3(n_batches), dim3(kNT), 0, st, f, a, rgba, d, dbg ? 1 : 0);
+    const int hd = dbg ? 1 : 0;
+    const dim3 g(n_batches), b(kNT);
+    if (mat.model == 0) {
+        if (lv.kind == 0) hipLaunchKernelGGL((k_batch<0, 0>), g, b, 0, st, f, a, rgba, d, hd);
+        else if (lv.kind == 1) hipLaunchKernelGGL((k_batch<1, 0>), g, b, 0, st, f, a, rgba, d, hd);
+        else hipLaunchKernelGGL((k_batch<2, 0>), g, b, 0, st, f, a, rgba, d, hd);
+    } else {
+        if (lv.kind == 0) hipLaunchKernelGGL((k_batch<0, 1>), g, b, 0, st, f, a, rgba, d, hd);
+        else if (lv.kind == 1) hipLaunchKernelGGL((k_batch<1, 1>), g, b, 0, st, f, a, rgba, d, hd);
+        else hipLaunchKernelGGL((k_batch<2, 1>), g, b, 0, st, f, a, rgba, d, hd);
+    }
     return hipGetLastError();
 }
 
@@ -1864,7 +1896,10 @@ hipError_t launch_batches_bwd(const FrameBufs& f, const LevelDev& lv, const CamC
     a.mat = mat;
     a.seg = f.seg;
     a.shade = f.shade;
-    hipLaunchKernelGGL(k_batch_bwd, dim3(n_batches), dim3(kNT), 0, st, f, a, grad, lv.S, lv.n_owner);
+    if (mat.model == 0)
+        hipLaunchKernelGGL(k_batch_bwd<0>, dim3(n_batches), dim3(kNT), 0, st, f, a, grad, lv.S, lv.n_owner);
+    else
+        hipLaunchKernelGGL(k_batch_bwd<1>, dim3(n_batches), dim3(kNT), 0, st, f, a, grad, lv.S, lv.n_owner);
     return hipGetLastError();
 }
 

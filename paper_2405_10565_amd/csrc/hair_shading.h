@@ -18,6 +18,13 @@
 // S = P_s a_F + max(0, 1 - P_m - P_s) for |phi| < pi/2 with c_m = 0.2, and n = 1 for
 // |phi| < pi/2 or a single-hair cluster.
 //
+// R / TT / D model (Sec. 3.1 eq. bcsdf with constant RGB attenuations A_R, A_TT, A_D; Sec. 4
+// modified lobes): M_R = 1/2 G(beta_R, theta_h), N_R = 1 / (2 pi); M_TT = 1/2 G(beta_TT,
+// theta_h), N_TT = G(gamma_TT, phi - pi); M_D = 1 / pi, N_D = 1 / (2 pi).  For thick hairs the
+// three lobes take a_F^{n-1} and variances widened by (n-1) sigma_f^2; a_F, a_B, sigma_f^2 and
+// sigma_b^2 do not depend on the view and are folded on the host.  The B lobe and S are shared
+// with the Marschner variant.
+//
 // Float arithmetic: the scattering terms use the hardware exp2 / reciprocal / square-root
 // instructions and fitted polynomials for arcsine and arctangent (coefficients and error
 // bounds in hair_fastmath_coef.h); every such step is within a few float32 ulps, far inside the
@@ -38,6 +45,7 @@ constexpr float kPi = 3.14159265358979323846f;
 constexpr float kHalfPi = 1.57079632679489661923f;
 constexpr float kTwoPi = 6.28318530717958647692f;
 constexpr float kInvTwoPi = 0.15915494309189533577f;
+constexpr float kInvTwoPi2 = 0.05066059182116888572f;   // 1 / (2 pi^2) = M_D N_D
 constexpr float kInvSqrt2Pi = 0.39894228040143267794f;
 constexpr float kLog2e = 1.44269504088896340736f;
 constexpr float kSqrt3 = 1.73205080756887729353f;
@@ -153,20 +161,21 @@ struct LightView {
     float inv_ctt;     // 1 / cos theta_t, sin theta_t = sin x_d / eta
 };
 
-// sin_ti / sin_to: sines of the longitudinal angles; x, y: light direction in the normal plane
+// sin_ti / sin_to: sines of the longitudinal angles; wx, wy: light direction in the normal
+// plane, so that cos theta_i = |(wx, wy)| (taken from the components, not from 1 - sin^2)
 __device__ inline LightView light_view(float sin_ti, float sin_to, float theta_o, float cos_to, float wx, float wy,
                                        bool degen, const MatConst& m) {
     LightView v;
     const float si = fminf(fmaxf(sin_ti, -1.0f), 1.0f);
-    const float ci = m_sqrt((1.0f - si) * (1.0f + si));
+    const float r2 = wx * wx + wy * wy;
+    const float ci = m_sqrt(r2);
     v.cos_ti = ci;
-    v.theta_h = 0.5f * (m_asin(si) + theta_o);
+    v.theta_h = 0.5f * (m_atan2(si, ci) + theta_o);
     const float c = fminf(fmaxf(ci * cos_to + si * sin_to, -1.0f), 1.0f);   // cos(theta_i - theta_o)
     v.sxd2 = 0.5f * (1.0f - c);
     v.cxd = m_sqrt(0.5f * (1.0f + c));
     v.inv_eta_p = v.cxd * m_rsqrt(m.eta * m.eta - v.sxd2);
     v.inv_ctt = m_rsqrt(1.0f - v.sxd2 * m.inv_eta2);
-    const float r2 = wx * wx + wy * wy;
     if (degen || !(r2 > 0.0f)) {
         v.phi = 0.0f;
         v.cos_phi = 1.0f;
@@ -276,29 +285,12 @@ template <class T> struct ClusterFrag {
     T n_F, n_B;    // hair counts toward / away from the light
 };
 
-// Aggregated BCSDF, RGB.
+// B lobe (A_1+ + A_1 + A_3 toward the back hemisphere) added to out, then the
+// shadowing-masking factor S applied (Sec. 4; both only for clusters of two or more hairs).
 template <class T>
-__device__ inline void f_ours(const LightView& v, T h, T gamma_o, T cgo, const T sigl[3], const MatConst& m,
-                              const ClusterFrag<T>& cf, T out[3]) {
-    const bool back_hemi = fabsf(v.phi) < 0.5f * kPi;
-    const bool multi = m_val(cf.n_total) >= 2.0f;
-    T aF[3], aB[3], var_f, var_b;
-    hemisphere_stats(v, sigl, m, aF, aB, var_f, var_b);
-    Atten<T> at = attenuation(v, h, cgo, sigl, m);
-    T nm1 = cf.n_F - 1.0f;
-    T extra = nm1 * var_f;
-    T s_bar = kSqrt3 * m_sqrt(T(m.beta_n * m.beta_n) + extra) / kPi;
-    T inv_sb = m_rcp(s_bar);
-    T norm = m_rcp(s_bar * m_tanh(kPi * 0.5f * inv_sb));
-    T fwd[3];
-    for (int c = 0; c < 3; ++c) fwd[c] = m_pow(aF[c], nm1);
-    for (int c = 0; c < 3; ++c) out[c] = T(0.0f);
-    for (int p = 0; p < 3; ++p) {
-        T M = 0.5f * gaussian(m_sqrt(T(m.beta_p[p] * m.beta_p[p]) + extra), T(v.theta_h - m.alpha_p[p]));
-        T N = trimmed_logistic(wrap_pi(v.phi - exit_azimuth(p, gamma_o, at.gamma_t)), inv_sb * kLog2e, norm);
-        T MN = M * N;
-        for (int c = 0; c < 3; ++c) out[c] = out[c] + fwd[c] * at.A[p][c] * MN;
-    }
+__device__ inline void back_lobe_shadow(const LightView& v, const T aF[3], const T aB[3], const T& var_f,
+                                        const T& var_b, const ClusterFrag<T>& cf, bool back_hemi, bool multi,
+                                        T out[3]) {
     if (multi) {
         T A1[3], A3[3], A1p[3];
         T m1 = T(0.0f), m3 = T(0.0f), m1p = T(0.0f);
@@ -325,6 +317,62 @@ __device__ inline void f_ours(const LightView& v, T h, T gamma_o, T cgo, const T
         T Pn = m_max(1.0f - kCm * one_rho - Ps, T(0.0f));
         for (int c = 0; c < 3; ++c) out[c] = (Ps * aF[c] + Pn) * out[c];
     }
+}
+
+// Aggregated BCSDF, RGB.
+template <class T>
+__device__ inline void f_ours(const LightView& v, T h, T gamma_o, T cgo, const T sigl[3], const MatConst& m,
+                              const ClusterFrag<T>& cf, T out[3]) {
+    const bool back_hemi = fabsf(v.phi) < 0.5f * kPi;
+    const bool multi = m_val(cf.n_total) >= 2.0f;
+    T aF[3], aB[3], var_f, var_b;
+    hemisphere_stats(v, sigl, m, aF, aB, var_f, var_b);
+    Atten<T> at = attenuation(v, h, cgo, sigl, m);
+    T nm1 = cf.n_F - 1.0f;
+    T extra = nm1 * var_f;
+    T s_bar = kSqrt3 * m_sqrt(T(m.beta_n * m.beta_n) + extra) / kPi;
+    T inv_sb = m_rcp(s_bar);
+    T norm = m_rcp(s_bar * m_tanh(kPi * 0.5f * inv_sb));
+    T fwd[3];
+    for (int c = 0; c < 3; ++c) fwd[c] = m_pow(aF[c], nm1);
+    for (int c = 0; c < 3; ++c) out[c] = T(0.0f);
+    for (int p = 0; p < 3; ++p) {
+        T M = 0.5f * gaussian(m_sqrt(T(m.beta_p[p] * m.beta_p[p]) + extra), T(v.theta_h - m.alpha_p[p]));
+        T N = trimmed_logistic(wrap_pi(v.phi - exit_azimuth(p, gamma_o, at.gamma_t)), inv_sb * kLog2e, norm);
+        T MN = M * N;
+        for (int c = 0; c < 3; ++c) out[c] = out[c] + fwd[c] * at.A[p][c] * MN;
+    }
+    back_lobe_shadow(v, aF, aB, var_f, var_b, cf, back_hemi, multi, out);
+}
+
+// R / TT / D single fibre, RGB.  |phi - pi| wrapped into [0, pi] is pi - |phi|.
+template <class T>
+__device__ inline void f_single_rttd(const LightView& v, const MatConst& m, T out[3]) {
+    const float th2 = v.theta_h * v.theta_h;
+    const float psi = kPi - fabsf(v.phi);
+    const float MNR = m.d_amp[0] * m_exp2(-m.d_k2[0] * th2) * kInvTwoPi;
+    const float MNT = m.d_amp[1] * m_exp2(-(m.d_k2[1] * th2 + m.n_k2 * (psi * psi))) * m.n_amp;
+    for (int c = 0; c < 3; ++c) out[c] = T(m.A[0][c] * MNR + m.A[1][c] * MNT + m.A[2][c] * kInvTwoPi2);
+}
+
+// Aggregated R^ / TT^ / D^ / B^ model, RGB.
+template <class T>
+__device__ inline void f_ours_rttd(const LightView& v, const MatConst& m, const ClusterFrag<T>& cf, T out[3]) {
+    const bool back_hemi = fabsf(v.phi) < 0.5f * kPi;
+    const bool multi = m_val(cf.n_total) >= 2.0f;
+    const float psi = kPi - fabsf(v.phi);
+    T nm1 = cf.n_F - 1.0f;
+    T extra = nm1 * m.var_f;
+    T MNR = 0.5f * gaussian(m_sqrt(T(m.d_beta2[0]) + extra), T(v.theta_h)) * kInvTwoPi;
+    T MNT = 0.5f * gaussian(m_sqrt(T(m.d_beta2[1]) + extra), T(v.theta_h)) *
+            gaussian(m_sqrt(T(m.gamma2) + extra), T(psi));
+    T aF[3], aB[3];
+    for (int c = 0; c < 3; ++c) {
+        aF[c] = T(m.aF[c]);
+        aB[c] = T(m.aB[c]);
+        out[c] = m_pow(aF[c], nm1) * (m.A[0][c] * MNR + m.A[1][c] * MNT + m.A[2][c] * kInvTwoPi2);
+    }
+    back_lobe_shadow(v, aF, aB, T(m.var_f), T(m.var_b), cf, back_hemi, multi, out);
 }
 
 }  // namespace hair

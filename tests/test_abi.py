@@ -73,6 +73,29 @@ def test_upload_validation_codes(B, hctx):
         assert e.value.code == code, args[:2]
 
 
+def test_rttd_material_validation(B, hctx):
+    """R / TT / D materials: valid ones reach the device check, out-of-range widths,
+    negative or over-unity attenuations and unknown models are rejected on the host."""
+    import dataclasses
+    import hairsynth as hs
+    n, v, xyz, w, s = _asset()
+    good = hs.Material.rttd()
+    with pytest.raises(B.HairError) as e:
+        hctx.upload(n, v, xyz, w, s, good)
+    assert e.value.code == B.HAIR_EDEVICE
+    m = B.make_material(good)
+    assert m.model == 1 and abs(m.gamma_tt - 0.3) < 1e-7 and list(m.a_d) == pytest.approx([0.3, 0.16, 0.09])
+    for change in [dict(beta_r=0.0), dict(beta_tt=2.5), dict(gamma_tt=-0.1), dict(gamma_tt=float("nan")),
+                   dict(a_r=(-0.1, 0.1, 0.1)), dict(a_d=(0.8, 0.1, 0.1)), dict(model=2)]:
+        with pytest.raises(B.HairError) as e:
+            hctx.upload(n, v, xyz, w, s, dataclasses.replace(good, **change))
+        assert e.value.code == B.HAIR_EINVAL, change
+    # model 1 ignores the R / TT / TRT fields
+    with pytest.raises(B.HairError) as e:
+        hctx.upload(n, v, xyz, w, s, dataclasses.replace(good, eta=0.5, beta_m=0.0))
+    assert e.value.code == B.HAIR_EDEVICE
+
+
 def _cam(B, W=64, H=32, **kw):
     c = B.hair_camera()
     c.pos[:] = [0, 0, 1]
