@@ -95,6 +95,22 @@ def cpu_baseline(asset, cam, lights, rows: int = 48):
                       f"{dt:.1f} s wall, torch/numpy float64 on 1 thread)"}
 
 
+def rttd_frame(ctx, asset, cam, lights, ws, frames: int = 20):
+    """The same strand frame with the R / TT / D material (outside the timed region)."""
+    import dataclasses
+    import numpy as np
+    import hairsynth as hs
+    aid = ctx.upload_asset(dataclasses.replace(asset, material=hs.Material.rttd()))
+    ms = []
+    for i in range(frames + 2):
+        _, st, _ = ctx.render(aid, 0, cam, lights, ws=ws)
+        if i >= 2:
+            ms.append(st["ms_total"])
+    ctx.release(aid)
+    return {"gpu_mean": round(float(np.mean(ms)), 4), "gpu_p50": round(float(np.percentile(ms, 50)), 4),
+            "fragments": int(st["fragments"]), "material": "R/TT/D (beta_R 0.1, beta_TT 0.2, gamma_TT 0.3)"}
+
+
 def serve_leg(ctx, n_requests: int, warmup: int = 24, rates=(30.0, 60.0, 120.0)):
     """Served latency: Poisson arrivals at each rate over the three resident serving assets."""
     from paper_2405_10565_amd import serve as S
@@ -204,10 +220,11 @@ def main():
                      "tile": round(float(ms_tile.mean()), 4)},
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_LANE_OPS / 1e12, 2),
                      "unit": "Tops/s", "frac": round(achieved / PEAK_LANE_OPS, 4),
-                     "traffic": traffic, "kernel": "k_batch<0>",
+                     "traffic": traffic, "kernel": "k_batch<0, 0>",
                      "ops_per_launch": int(ops + TRANS_WEIGHT * trans)},
         "cpu_baseline": None,
     }
+    res["frame_ms_rttd"] = rttd_frame(ctx, asset, cam, lights, ws)
     ws.close()
     if not args.no_serve:
         res["serving"] = serve_leg(ctx, args.serve_requests)

@@ -29,6 +29,7 @@ namespace {
 
 constexpr int kNT = 256;                   // threads per tile block (= pixels per tile)
 constexpr int kPerThread = kCap / kNT;     // LDS batch fragments per thread
+static_assert(kCap % kNT == 0, "a batch is kPerThread fragments per thread");
 
 static_assert(kTile == 16, "the shifts below assume 16-pixel tiles in 1/16-pixel units");
 
@@ -585,7 +586,9 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
     const int dx = s.xb - s.xa, dy = s.yb - s.ya;
     const int tnum = ex * dx + ey * dy, tden = dx * dx + dy * dy;
     const int cr = ex * dy - ey * dx;
-    const float t = (float)tnum / (float)tden;
+    // (the coverage decision was taken exactly when the fragment was emitted; what follows is
+    // continuous, so it uses the hardware reciprocal and reciprocal square root)
+    const float t = (float)tnum * m_rcp((float)tden);
     const float iz = s.iza + t * (s.izb - s.iza);
     float delta;
     T d_minus, d_plus;   // delta - hw, delta + hw
@@ -600,16 +603,16 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
         d_minus = (delta - hw) + dlo;
         d_plus = (hw + delta) + dlo;
     } else {
-        delta = fabsf((float)cr) / sqrtf((float)tden) * (1.0f / 16.0f);
+        delta = fabsf((float)cr) * m_rsqrt((float)tden) * (1.0f / 16.0f);
         d_minus = delta - hw;
         d_plus = hw + delta;
     }
     alpha = m_min(m_max(m_min(d_plus, T(0.5f)) - m_max(d_minus, T(-0.5f)), T(0.0f)), T(1.0f));
     float sgn = cr > 0 ? 1.0f : (cr < 0 ? -1.0f : 0.0f);
     if (s.hwfx & kFlagNegSide) sgn = -sgn;
-    const T h = m_min(m_max((sgn * delta) / (hw + 0.5f), T(-1.0f)), T(1.0f));
+    const T h = m_min(m_max((sgn * delta) * m_rcp(hw + 0.5f), T(-1.0f)), T(1.0f));
     hoff = h;
-    const float tw = t * s.izb / iz;
+    const float tw = t * s.izb * m_rcp(iz);
 
     // fibre frame at the fragment's world point
     const V3<float> pA = v3(q0.x, q0.y, q0.z);
@@ -710,19 +713,41 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
 
 // KIND 0: strands, 1: thick hairs, 2: a mixed frame (the segment's flag decides).
 // MODEL 0: near-field R / TT / TRT, 1: R / TT / D.
+// A fragment's segment inputs (integer record and shading record), fetched ahead of use.
+struct SegInputs {
+    SegRec s;
+    float4 q0, q1, q2, q3;
+};
+
+template <int KIND>
+__device__ inline SegInputs fetch_segment(const ShadeArgs& a, uint32_t gseg) {
+    SegInputs r;
+    r.s = a.seg[gseg];
+    const ShadeRec& sr = a.shade[gseg];
+    r.q0 = sr.q0;
+    r.q1 = sr.q1;
+    r.q2 = sr.q2;
+    r.q3 = KIND == 0 ? make_float4(0.f, 0.f, 0.f, 0.f) : sr.q3;
+    return r;
+}
+
+template <int KIND, int MODEL>
+__device__ inline void shade_inputs(const ShadeArgs& a, const SegInputs& in, int pxg, int pyg, float& alpha,
+                                    float& hoff, float L[3]) {
+    const float sig[3] = {in.q0.w, in.q1.w, in.q2.w};
+    if (KIND == 0 || (KIND == 2 && !(in.s.hwfx & kFlagThick))) {
+        shade_core<0, MODEL, float>(a, in.s, in.q0, in.q1, in.q2, 1.0f, pxg, pyg, in.s.hw, 0.f, 0.f, 0.f, sig, alpha,
+                                    hoff, L);
+    } else {
+        shade_core<1, MODEL, float>(a, in.s, in.q0, in.q1, in.q2, in.q3.z, pxg, pyg, in.s.hw, in.q3.x, in.q3.y, in.q3.w,
+                                    sig, alpha, hoff, L);
+    }
+}
+
 template <int KIND, int MODEL>
 __device__ inline void shade_fragment(const ShadeArgs& a, uint32_t gseg, int pxg, int pyg, float& alpha, float& hoff,
                                       float L[3]) {
-    const SegRec s = a.seg[gseg];
-    const ShadeRec& srec = a.shade[gseg];
-    const float4 q0 = srec.q0, q1 = srec.q1, q2 = srec.q2;
-    const float sig[3] = {q0.w, q1.w, q2.w};
-    if (KIND == 0 || (KIND == 2 && !(s.hwfx & kFlagThick))) {
-        shade_core<0, MODEL, float>(a, s, q0, q1, q2, 1.0f, pxg, pyg, s.hw, 0.f, 0.f, 0.f, sig, alpha, hoff, L);
-    } else {
-        const float4 q3 = srec.q3;
-        shade_core<1, MODEL, float>(a, s, q0, q1, q2, q3.z, pxg, pyg, s.hw, q3.x, q3.y, q3.w, sig, alpha, hoff, L);
-    }
+    shade_inputs<KIND, MODEL>(a, fetch_segment<KIND>(a, gseg), pxg, pyg, alpha, hoff, L);
 }
 
 // Block-wide exclusive scan of one uint per thread (256 threads); returns the total.
@@ -1132,14 +1157,36 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
     PHASE_BEGIN();
     order_batch(Fb, src, s_cnt, s_kmin, s_kmax, s_off, s_tmp, s_A, s_B, s_bk, list);
     PHASE_END(f.ctr, 2);
-    // ---- shade: one lane per fragment, payload alpha * L and (1 - alpha)
+    // ---- shade: one lane per fragment, payload alpha * L and (1 - alpha).  A lane's fragments
+    // are i = t, t + kNT, ...: their segment ids are gathered up front (independent loads), and
+    // each fragment's segment inputs are fetched one fragment ahead, so that the gathers
+    // overlap the shading arithmetic instead of stalling it.  (Not for the R / TT / TRT
+    // thick-hair shading: its registers would then exceed the budget of three waves per SIMD.)
+    constexpr bool kAhead = KIND == 0 || MODEL == 1;
+    uint32_t gs[kAhead ? kPerThread : 1];
+    SegInputs nxt{};
+    if (kAhead) {
+#pragma unroll
+        for (int j = 0; j < kPerThread; ++j) {
+            const uint32_t i = t + j * kNT;
+            gs[j] = i < Fb ? list[s_B[i].y & 0xFFFFFFu] : 0u;
+        }
+        if ((uint32_t)t < Fb) nxt = fetch_segment<KIND>(a, gs[0]);
+    }
     for (uint32_t i = t; i < Fb; i += kNT) {
+        if (!kAhead) gs[0] = list[s_B[i].y & 0xFFFFFFu];
+        const SegInputs cur = kAhead ? nxt : fetch_segment<KIND>(a, gs[0]);
+        const uint32_t gseg = gs[0];
+        if (kAhead) {
+#pragma unroll
+            for (int j = 0; j + 1 < (kAhead ? kPerThread : 1); ++j) gs[j] = gs[j + 1];
+            if (i + kNT < Fb) nxt = fetch_segment<KIND>(a, gs[0]);
+        }
         const uint2 rec = s_B[i];
         const uint32_t p = rec.y >> 24;
-        const uint32_t gseg = list[rec.y & 0xFFFFFFu];
         const int gx = px0 + (int)(p % kTile), gy = py0 + (int)(p / kTile);
         float al, hh, L[3];
-        shade_fragment<KIND, MODEL>(a, gseg, gx, gy, al, hh, L);
+        shade_inputs<KIND, MODEL>(a, cur, gx, gy, al, hh, L);
         s_pay[3 * i + 0] = al * L[0];
         s_pay[3 * i + 1] = al * L[1];
         s_pay[3 * i + 2] = al * L[2];
@@ -1247,9 +1294,10 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
 // pixel deeper than one batch (its own "oversized" batch) is processed in depth-key slices:
 // a histogram over the pixel's key range picks the longest run of bins that fits LDS, those
 // records are gathered and processed exactly, and the slice composites chain front to back.
+// (LDS holds three blocks per CU; the register budget is kept at the same three waves per SIMD.)
 template <int KIND, int MODEL>
-__global__ __launch_bounds__(kNT) void k_batch(FrameBufs f, ShadeArgs a, float* __restrict__ rgba, DebugDump dbg,
-                                               int has_dbg) {
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3))) void k_batch(
+    FrameBufs f, ShadeArgs a, float* __restrict__ rgba, DebugDump dbg, int has_dbg) {
     __shared__ uint32_t s_cnt[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix], s_off[kTilePix + 1];
     __shared__ uint32_t s_tmp[kNT];
     __shared__ __align__(16) uint2 s_B[kCap];
