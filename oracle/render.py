@@ -208,7 +208,7 @@ def light_dirs(light, xw):
     return wi, E
 
 
-def _mixed_radiance(geom: LevelGeom, ras: Raster, cam, lights, mat):
+def _mixed_radiance(geom: LevelGeom, ras: Raster, cam, lights, mat, shadow=None):
     """Mixed frames: strand fragments by f_single, thick-hair fragments by f_ours."""
     from dataclasses import replace
     thick_f = geom.thick[ras.seg]
@@ -219,7 +219,8 @@ def _mixed_radiance(geom: LevelGeom, ras: Raster, cam, lights, mat):
             continue
         sub = replace(ras, seg=ras.seg[m], pix=ras.pix[m], key=ras.key[m], t_num=ras.t_num[m], t_den=ras.t_den[m],
                       cross=ras.cross[m])
-        a, l = fragment_radiance(replace(geom, kind=kind), sub, cam, lights, mat)
+        sh = None if shadow is None else [None if n is None else n[torch.as_tensor(np.nonzero(m)[0])] for n in shadow]
+        a, l = fragment_radiance(replace(geom, kind=kind), sub, cam, lights, mat, shadow=sh)
         idx = torch.as_tensor(np.nonzero(m)[0])
         alpha[idx] = a
         L[idx] = l
@@ -237,15 +238,18 @@ def material(m):
     return (f(m.eta), f(m.alpha), f(m.beta_m), f(m.beta_n))
 
 
-def fragment_radiance(geom: LevelGeom, ras: Raster, cam, lights, mat, params=None):
+def fragment_radiance(geom: LevelGeom, ras: Raster, cam, lights, mat, params=None, shadow=None):
     """(alpha [F], L [F, 3]) in float64.
 
     params (cluster levels, for the gradient oracle): dict of torch tensors
     'a_len', 'b_len' [S], 'r' [S], 'sigma_a' [S, 3], and 'hw' [S] (the half-width recomputed
     from them); default: the level's stored values and the float32 half-width.
+    shadow: per light, the number of hairs n_s in front of each fragment toward the light
+    (oracle.shadow) or None: a strand with n_s > 0 is shaded by f_ours with n_total = 1 and
+    n_F = 1 + n_s, a thick hair's n_F grows by n_s.
     """
     if geom.kind == "mixed":
-        return _mixed_radiance(geom, ras, cam, lights, mat)
+        return _mixed_radiance(geom, ras, cam, lights, mat, shadow)
     s = ras.seg
     xw, u, wo = shading_inputs(geom, ras, cam)
     xh, yh, degen, sin_to = frame(u, wo)
@@ -266,7 +270,8 @@ def fragment_radiance(geom: LevelGeom, ras: Raster, cam, lights, mat, params=Non
         n_total = _t(geom.n_total[s])
         W = ellipse_support(a_len, b_len, ahat, bhat, yh)
     L = torch.zeros(len(s), 3, dtype=DT)
-    for light in lights:
+    for li, light in enumerate(lights):
+        ns = None if shadow is None else shadow[li]
         wi, E = light_dirs(light, xw)
         sin_ti = (wi * u).sum(-1)
         phi = -torch.atan2((wi * yh).sum(-1), (wi * xh).sum(-1))
@@ -276,6 +281,13 @@ def fragment_radiance(geom: LevelGeom, ras: Raster, cam, lights, mat, params=Non
         cos_ti = torch.sqrt((1.0 - sc) * (1.0 + sc))
         if geom.kind == "strand":
             f = rttd.f_single(th, phi, mat) if isinstance(mat, rttd.RTTD) else f_single(th, xd, phi, h, sig, mat)
+            if ns is not None:
+                one = torch.ones_like(th)
+                if isinstance(mat, rttd.RTTD):
+                    fo = rttd.f_ours(th, phi, mat, one, one, 1.0 + ns, one)
+                else:
+                    fo = f_ours(th, xd, phi, h, sig, mat, one, one, 1.0 + ns, one)
+                f = torch.where((ns > 0)[:, None], fo, f)
         else:
             Dp = wi - sin_ti[:, None] * u
             dn = torch.linalg.norm(Dp, dim=-1)
@@ -283,6 +295,8 @@ def fragment_radiance(geom: LevelGeom, ras: Raster, cam, lights, mat, params=Non
             s_star = ellipse_chord(h, W, xh, yh, ahat, bhat, a_len, b_len, D)
             s_star = torch.where(dn > 1e-7, s_star, torch.zeros_like(s_star))
             rho, n_F, n_B = hair_counts(phi, s_star, n_total, r, a_len, b_len)
+            if ns is not None:
+                n_F = n_F + ns
             if isinstance(mat, rttd.RTTD):
                 f = rttd.f_ours(th, phi, mat, n_total, rho, n_F, n_B)
             else:
@@ -312,10 +326,15 @@ def composite(ras: Raster, alpha, L):
     return rgba.reshape(ras.H, ras.W, 4)
 
 
-def render(geom: LevelGeom, cam, lights, mat, pix_filter=None, rect=None):
-    """Oracle frame: returns (rgba float64 [H, W, 4] numpy, Raster)."""
+def render(geom: LevelGeom, cam, lights, mat, pix_filter=None, rect=None, shadow=None):
+    """Oracle frame: returns (rgba float64 [H, W, 4] numpy, Raster).  shadow = (R, K, Delta):
+    shade with deep opacity maps of that resolution, layer count and layer depth."""
     ras = rasterize(geom, cam, pix_filter=pix_filter, rect=rect)
-    alpha, L = fragment_radiance(geom, ras, cam, lights, mat)
+    ns = None
+    if shadow is not None:
+        from . import shadow as sh
+        ns = sh.shadow_counts(geom, ras, cam, lights, *shadow)
+    alpha, L = fragment_radiance(geom, ras, cam, lights, mat, shadow=ns)
     return composite(ras, alpha, L).numpy(), ras
 
 
