@@ -182,6 +182,19 @@ int hair_set_cluster_params(hair_ctx* ctx, int32_t asset, int32_t level, const f
 int hair_select_level(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_camera* cam,
                       float eps_w_px, void* stream, int32_t* level_out);
 
+/* Deep opacity map shadows (Sec. 5.2, shadow pass; the count of hairs a light path crosses
+ * scales and widens the forward lobes as in Sec. 4).  Every directional light gets a map of
+ * resolution x resolution texels over the hair seen along it and `layers` depth layers of
+ * layer_depth (world units) from each texel's first hair; a fragment's count of hairs in front
+ * (one layer of bias, linear in depth, bilinear across texels) is added to its forward count:
+ * strands are shaded by the aggregated model with one hair and n_F = 1 + count.  Point lights
+ * are not shadowed.  resolution in [16, 4096], layers in [1, 7], layer_depth > 0. */
+typedef struct hair_shadow {
+    int32_t resolution;
+    int32_t layers;
+    float layer_depth;
+} hair_shadow;
+
 /* Render one frame (the hot path).  rgba_out: device float[height][width][4], premultiplied
  * (C, 1 - T) over transparent black, written in full.  n_lights in 1..HAIR_MAX_LIGHTS.
  * The call synchronises `stream` three times (twice to size the frame's buffers, once at the
@@ -190,6 +203,15 @@ int hair_select_level(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_came
 int hair_render(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,
                 const hair_light* lights, int32_t n_lights, float* rgba_out, void* stream,
                 hair_stats* stats);
+
+/* hair_render with deep opacity map shadows (see hair_shadow) at a strand or thick-hair level
+ * (mixed frames are not shadowed).  One shadow pass per directional light runs on `stream`
+ * before the frame (each synchronises it twice to size its buffers); stats describe the
+ * camera frame, with ms_total including the shadow passes.  The workspace keeps the maps
+ * until its next shadowed render. */
+int hair_render_shadowed(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,
+                         const hair_light* lights, int32_t n_lights, const hair_shadow* shadow, float* rgba_out,
+                         void* stream, hair_stats* stats);
 
 /* Per-group, per-segment LoD (Sec. 5.1 step 5; Sec. 5.2 "Dynamic LoD selection",
  * eq. lod_select).  Available when hair_build_lod built 1..7 levels that nest: every cluster
@@ -239,6 +261,14 @@ int hair_render_backward(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t leve
  *           in no particular order). */
 int hair_debug_segments(hair_ws* ws, int64_t n, int32_t* rec_i, float* rec_f);
 int hair_debug_bins(hair_ws* ws, int64_t n_tiles, uint32_t* tile_start, int64_t n_pairs, uint32_t* tile_segs);
+
+/* Test export of the shadow map of light `light` from the last hair_render_shadowed on `ws`:
+ * texels host float[R * R][8] = (iz0, C_0 .. C_6) per texel, row-major (iz0: z_ref minus the
+ * depth of the texel's first hair along the light, 0 when the texel holds no hair; C_k: hairs
+ * counted through layer k; entries beyond the layer count repeat the last layer's total),
+ * grid host float[16] = (e1, e2, d, omega, u0, v0, texel size, z_ref).
+ * HAIR_EINVAL when that light had no map. */
+int hair_debug_dom(hair_ws* ws, int32_t light, float* texels, float* grid);
 
 /* Test export of composited fragment lists: renders like hair_render and, for pixels in
  * [x0, x0 + w) x [y0, y0 + h), writes per pixel its fragment count (host uint[h][w]) and

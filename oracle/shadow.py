@@ -185,7 +185,9 @@ def build_dom(geom: LevelGeom, omega, R: int, K: int, delta: float) -> Dom:
         W = hw[sg].astype(np.float64) * float(g["s"])
         rho = np.clip(n_total * r * r / (a * b), 0.0, 1.0)
         kappa = np.sqrt(n_total / (math.pi * a * b))
-        cnt[th] = cnt[th] * rho * kappa * (2.0 * a * b / W) * np.sqrt(1.0 - h * h)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            c = cnt[th] * rho * kappa * (2.0 * a * b / W) * np.sqrt(1.0 - h * h)
+        cnt[th] = np.where(W > 0, c, 0.0)     # a zero-width thick hair holds no hairs across the light
     S = np.zeros((R * R, K))
     np.add.at(S, (pix, layer), cnt)
     return Dom(g, K, delta, iz0, np.cumsum(S, axis=1))

@@ -26,7 +26,8 @@ EXPORTS = [
     "hair_ctx_memory", "hair_ws_create", "hair_ws_destroy", "hair_ws_estimate", "hair_upload", "hair_release",
     "hair_build_lod", "hair_lod_info", "hair_get_lod", "hair_set_lod", "hair_set_cluster_params",
     "hair_select_level", "hair_render", "hair_render_backward", "hair_debug_segments", "hair_debug_bins",
-    "hair_debug_fragments", "hair_lod_groups", "hair_lod_init", "hair_render_mixed",
+    "hair_debug_fragments", "hair_lod_groups", "hair_lod_init", "hair_render_mixed", "hair_render_shadowed",
+    "hair_debug_dom",
 ]
 
 
@@ -57,6 +58,10 @@ def make_material(material) -> hair_material:
         for name in ("a_r", "a_tt", "a_d"):
             getattr(m, name)[:] = [float(v) for v in getattr(material, name)]
     return m
+
+
+class hair_shadow(C.Structure):
+    _fields_ = [("resolution", C.c_int32), ("layers", C.c_int32), ("layer_depth", C.c_float)]
 
 
 class hair_camera(C.Structure):
@@ -117,6 +122,9 @@ def _load():
         "hair_lod_init": ([P, P, I32, C.POINTER(hair_camera), F, P, P], C.c_int),
         "hair_render_mixed": ([P, P, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32, P, F, P, P,
                                C.POINTER(hair_stats)], C.c_int),
+        "hair_render_shadowed": ([P, P, I32, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32,
+                                  C.POINTER(hair_shadow), P, P, C.POINTER(hair_stats)], C.c_int),
+        "hair_debug_dom": ([P, I32, fp, fp], C.c_int),
         "hair_debug_segments": ([P, I64, ip, fp], C.c_int),
         "hair_debug_bins": ([P, I64, up, I64, up], C.c_int),
         "hair_debug_fragments": ([P, P, I32, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32, I32, I32, I32,
@@ -318,6 +326,24 @@ class Context:
             check(rc)
         return out, st.as_dict(), rc
 
+    def render_shadowed(self, asset: int, level: int, cam, lights, shadow=(512, 4, 0.02), out=None,
+                        ws: Workspace | None = None, stream=None, raise_on_error: bool = True):
+        """render with deep opacity map shadows; shadow = (resolution, layers, layer_depth)."""
+        import torch
+        c = make_camera(cam)
+        la, nl = make_lights(lights)
+        sh = hair_shadow(int(shadow[0]), int(shadow[1]), float(shadow[2]))
+        if out is None:
+            out = torch.empty((c.height, c.width, 4), dtype=torch.float32, device=f"cuda:{self.device}")
+        assert out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+        assert tuple(out.shape) == (c.height, c.width, 4)
+        st = hair_stats()
+        rc = lib.hair_render_shadowed(self.handle, ws.handle if ws else None, asset, level, C.byref(c), la, nl,
+                                      C.byref(sh), C.c_void_p(out.data_ptr()), _stream_ptr(stream), C.byref(st))
+        if raise_on_error:
+            check(rc)
+        return out, st.as_dict(), rc
+
     def lod_groups(self, asset: int) -> int:
         out = C.c_int32()
         check(lib.hair_lod_groups(self.handle, asset, C.byref(out)))
@@ -368,6 +394,13 @@ class Context:
         rf = np.zeros((n, 3), np.float32)
         check(lib.hair_debug_segments(ws.handle, n, _iptr(ri), _fptr(rf)))
         return ri, rf
+
+    def debug_dom(self, ws: Workspace, light: int, R: int):
+        """(texels float32 [R*R, 8], grid float32 [16]) of the last shadowed render on ws."""
+        tex = np.zeros((R * R, 8), np.float32)
+        grid = np.zeros(16, np.float32)
+        check(lib.hair_debug_dom(ws.handle, light, _fptr(tex), _fptr(grid)))
+        return tex, grid
 
     def debug_bins(self, ws: Workspace, n_tiles: int, n_pairs: int):
         ts = np.zeros(n_tiles + 1, np.uint32)

@@ -83,6 +83,9 @@ struct hair_ws {
     DevBuf seg, shade, scan_tmp, tile_cnt, tile_start, bin_m, bin_blk, list, ctr, sel_cnt, sel_start, sel, sel_tmp;
     DevBuf items, item_start, item_base, pix_cnt, pix_kmin, pix_kmax, pix_off;
     DevBuf tile_tot, frag_base, tile_nb, batch_start, batches, frags;
+    DevBuf dom_tex, dom_grid, dom_part;      // shadow pass: texels, grids, bounds partials
+    int32_t dom_R = 0, dom_K = 0, dom_n = 0;  // last shadowed render: resolution, layers, maps
+    int32_t dom_light[HAIR_MAX_LIGHTS] = {};  // map index of each light, -1 if unshadowed
     hipEvent_t ev[7] = {};
     bool events = false;
     int64_t last_nseg = 0, last_ntiles = 0, last_pairs = 0;
@@ -366,6 +369,15 @@ struct FrameOut {
     float ms[4];
 };
 
+// A shadow-pass raster: the light view's records instead of the camera's, and the per-texel
+// layers instead of shading.
+struct DomPass {
+    const DomGrid* grid;
+    int32_t K;
+    float delta;
+    float4* tex;
+};
+
 // Project + bin + tile for one level; the caller holds ws->mu.
 //   k_project                         per-segment records (projection, half-width, culling)
 //   k_bin_count, k_bin_offsets, k_scan per-block tile counts, their column scan, list offsets
@@ -377,7 +389,7 @@ struct FrameOut {
 int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, const hair_camera* cam,
               const hair_light* lights, int n_lights, float* rgba, const DebugDump* dbg, hipStream_t st,
               FrameOut* out, bool tiles_too = true, const GradOut* grad = nullptr, const HierDev* hier = nullptr,
-              const uint32_t* sel = nullptr) {
+              const uint32_t* sel = nullptr, const DomPass* dom = nullptr, const DomView* views = nullptr) {
     int rc;
     const CamConst cc = cam_const(cam);
     const int ntx = (cam->width + kTile - 1) / kTile, nty = (cam->height + kTile - 1) / kTile;
@@ -402,6 +414,8 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     if (hier)
         HIP_TRY(ctx, launch_project_mixed(*hier, sel, lv.nseg, cc, ws->seg.as<SegRec>(), ws->shade.as<ShadeRec>(), st),
                 "k_project_mixed");
+    else if (dom)
+        HIP_TRY(ctx, launch_project_light(lv, dom->grid, ws->seg.as<SegRec>(), st), "k_project_light");
     else
         HIP_TRY(ctx, launch_project(lv, cc, ws->seg.as<SegRec>(), ws->shade.as<ShadeRec>(), st), "k_project");
     HIP_TRY(ctx, launch_bins(ws->seg.as<SegRec>(), lv.nseg, cc, plan, ws->bin_m.as<uint32_t>(), ws->bin_blk.as<uint4>(),
@@ -472,18 +486,21 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     f.frags = ws->frags.as<uint2>();
     f.batches = ws->batches.as<uint4>();
     HIP_TRY(ctx, hipEventRecord(ws->ev[4], st), "hipEventRecord");
-    HIP_TRY(ctx, launch_batch_records(f, st), "k_batch_records");
+    if (!dom) HIP_TRY(ctx, launch_batch_records(f, st), "k_batch_records");
     HIP_TRY(ctx, launch_emit(f, cc, n_items, st), "k_emit");
     HIP_TRY(ctx, hipEventRecord(ws->ev[5], st), "hipEventRecord");
-    if (grad) {
+    LightsConst lc = lights_const(lights, n_lights);
+    if (views)
+        for (int i = 0; i < n_lights; ++i) lc.dom[i] = views[i];
+    if (dom) {
+        HIP_TRY(ctx, launch_dom_resolve(f, lv, dom->grid, dom->K, dom->delta, dom->tex, st), "k_dom_resolve");
+    } else if (grad) {
         HIP_TRY(ctx, launch_fill_f32(grad->d_axes, 0.0f, 2ull * lv.nseg, st), "fill");
         HIP_TRY(ctx, launch_fill_f32(grad->d_r, 0.0f, (size_t)lv.n_owner, st), "fill");
         HIP_TRY(ctx, launch_fill_f32(grad->d_sig, 0.0f, 3ull * lv.n_owner, st), "fill");
-        HIP_TRY(ctx, launch_batches_bwd(f, lv, cc, lights_const(lights, n_lights), mat_const(a.mat), n_batches, *grad, st),
-                "k_batch_bwd");
+        HIP_TRY(ctx, launch_batches_bwd(f, lv, cc, lc, mat_const(a.mat), n_batches, *grad, st), "k_batch_bwd");
     } else if (rgba) {
-        HIP_TRY(ctx, launch_batches(f, lv, cc, lights_const(lights, n_lights), mat_const(a.mat), n_batches, rgba, dbg, st),
-                "k_batch");
+        HIP_TRY(ctx, launch_batches(f, lv, cc, lc, mat_const(a.mat), n_batches, rgba, dbg, st), "k_batch");
     }
     HIP_TRY(ctx, hipEventRecord(ws->ev[6], st), "hipEventRecord");
     HIP_TRY(ctx, hipMemcpyAsync(&out->ctr, ws->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, st), "copy");
@@ -510,7 +527,7 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
 // =======================================================================================
 extern "C" {
 
-int hair_version(void) { return 101; }
+int hair_version(void) { return 102; }
 
 const char* hair_last_error(void) { return g_err.c_str(); }
 
@@ -580,7 +597,8 @@ int hair_ws_destroy(hair_ws* ws) {
     if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
     for (DevBuf* b : {&ws->seg, &ws->shade, &ws->scan_tmp, &ws->tile_cnt, &ws->tile_start, &ws->bin_m, &ws->bin_blk, &ws->sel_cnt, &ws->sel_start, &ws->sel, &ws->sel_tmp, &ws->list, &ws->ctr, &ws->items,
                       &ws->item_start, &ws->item_base, &ws->pix_cnt, &ws->pix_kmin, &ws->pix_kmax, &ws->pix_off,
-                      &ws->tile_tot, &ws->frag_base, &ws->tile_nb, &ws->batch_start, &ws->batches, &ws->frags})
+                      &ws->tile_tot, &ws->frag_base, &ws->tile_nb, &ws->batch_start, &ws->batches, &ws->frags,
+                      &ws->dom_tex, &ws->dom_grid, &ws->dom_part})
         ctx_free(ctx, *b, ws);
     if (ws->events)
         for (auto& e : ws->ev) (void)hipEventDestroy(e);
@@ -998,6 +1016,121 @@ int hair_render(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const 
     if (fo.ctr.overflow_pixels)
         return fail(HAIR_ERANGE, "%u pixels hold more than %d fragments at one depth key (left transparent)",
                     fo.ctr.overflow_pixels, kCap);
+    return HAIR_OK;
+}
+
+// Light frame of a directional light (float64, stored as float32): e1 = normalize(a x omega)
+// with a = y (x when |omega_y| >= 0.9), e2 = omega x e1, d = -omega.
+static DomBasis dom_basis(const float* vec) {
+    double w[3] = {vec[0], vec[1], vec[2]};
+    const double wn = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    for (double& x : w) x /= wn;
+    const double a[3] = {std::fabs(w[1]) < 0.9 ? 0.0 : 1.0, std::fabs(w[1]) < 0.9 ? 1.0 : 0.0, 0.0};
+    double e1[3] = {a[1] * w[2] - a[2] * w[1], a[2] * w[0] - a[0] * w[2], a[0] * w[1] - a[1] * w[0]};
+    const double en = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    for (double& x : e1) x /= en;
+    const double e2[3] = {w[1] * e1[2] - w[2] * e1[1], w[2] * e1[0] - w[0] * e1[2], w[0] * e1[1] - w[1] * e1[0]};
+    DomBasis b;
+    for (int i = 0; i < 3; ++i) {
+        b.e1[i] = (float)e1[i];
+        b.e2[i] = (float)e2[i];
+        b.d[i] = (float)-w[i];
+        b.omega[i] = (float)w[i];
+    }
+    return b;
+}
+
+int hair_render_shadowed(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,
+                         const hair_light* lights, int32_t n_lights, const hair_shadow* shadow, float* rgba_out,
+                         void* stream, hair_stats* stats) {
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if ((rc = validate_camera(cam))) return rc;
+    if ((rc = validate_lights(lights, n_lights))) return rc;
+    if (!rgba_out) return fail(HAIR_EINVAL, "null output image");
+    if (!shadow) return fail(HAIR_EINVAL, "null shadow descriptor");
+    if (shadow->resolution < 16 || shadow->resolution > 4096)
+        return fail(HAIR_EINVAL, "shadow resolution %d outside [16, 4096]", shadow->resolution);
+    if (shadow->layers < 1 || shadow->layers > kDomMaxLayers)
+        return fail(HAIR_EINVAL, "shadow layers %d outside [1, %d]", shadow->layers, kDomMaxLayers);
+    if (!(std::isfinite(shadow->layer_depth) && shadow->layer_depth > 0.0f))
+        return fail(HAIR_EINVAL, "shadow layer_depth must be finite and > 0");
+    Asset* a;
+    LevelDev lv;
+    if ((rc = find_level(ctx, asset, level, &a, &lv))) return rc;
+    if ((rc = need_device(ctx))) return rc;
+    ws = ws_or_default(ctx, ws);
+    std::lock_guard<std::mutex> g(ws->mu);
+    const int R = shadow->resolution, K = shadow->layers;
+    int n_dom = 0;
+    for (int i = 0; i < n_lights; ++i) n_dom += lights[i].kind == 0;
+    const size_t texels = (size_t)R * R;
+    if ((rc = ws_need(ws, ws->dom_tex, 32 * texels * std::max(n_dom, 1)))) return rc;
+    if ((rc = ws_need(ws, ws->dom_grid, sizeof(DomGrid) * HAIR_MAX_LIGHTS))) return rc;
+    if ((rc = ws_need(ws, ws->dom_part, 20ull * dom_bound_blocks(lv.nseg)))) return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    hair_camera lcam = *cam;   // the light view's raster size; its projection is the light's own
+    lcam.width = lcam.height = R;
+    DomView views[HAIR_MAX_LIGHTS];
+    memset(views, 0, sizeof(views));
+    float ms_dom = 0.0f;
+    int m = 0;
+    for (int i = 0; i < n_lights; ++i) {
+        ws->dom_light[i] = -1;
+        if (lights[i].kind != 0) continue;
+        DomGrid* grid = ws->dom_grid.as<DomGrid>() + m;
+        float4* tex = reinterpret_cast<float4*>(ws->dom_tex.as<float>() + 8 * texels * m);
+        HIP_TRY(ctx, launch_dom_grid(lv, dom_basis(lights[i].vec), R, ws->dom_part.as<float>(), grid, st), "k_dom_grid");
+        const DomPass dp{grid, K, shadow->layer_depth, tex};
+        FrameOut fd;
+        if ((rc = run_frame(ctx, ws, *a, lv, &lcam, lights, n_lights, nullptr, nullptr, st, &fd, true, nullptr,
+                            nullptr, nullptr, &dp)))
+            return rc;
+        if (fd.ctr.list_overflow) return fail(HAIR_ERANGE, "shadow map: %u tiles hold more than 2^24 segments",
+                                              fd.ctr.list_overflow);
+        ms_dom += fd.ms[0];
+        views[i] = DomView{grid, tex, K, shadow->layer_depth};
+        ws->dom_light[i] = m++;
+    }
+    ws->dom_R = R;
+    ws->dom_K = K;
+    ws->dom_n = m;
+    FrameOut fo;
+    if ((rc = run_frame(ctx, ws, *a, lv, cam, lights, n_lights, rgba_out, nullptr, st, &fo, true, nullptr, nullptr,
+                        nullptr, nullptr, views)))
+        return rc;
+    if (stats) {
+        fill_stats(stats, fo, (uint32_t)lv.nseg);
+        stats->ms_total += ms_dom;
+    }
+    if (fo.ctr.list_overflow) return fail(HAIR_ERANGE, "%u tiles hold more than 2^24 segments", fo.ctr.list_overflow);
+    if (fo.ctr.overflow_pixels)
+        return fail(HAIR_ERANGE, "%u pixels hold more than %d fragments at one depth key (left transparent)",
+                    fo.ctr.overflow_pixels, kCap);
+    return HAIR_OK;
+}
+
+int hair_debug_dom(hair_ws* ws, int32_t light, float* texels, float* grid) {
+    if (!ws || !texels || !grid) return fail(HAIR_EINVAL, "null argument");
+    std::lock_guard<std::mutex> g(ws->mu);
+    if (light < 0 || light >= HAIR_MAX_LIGHTS || ws->dom_R == 0 || ws->dom_light[light] < 0)
+        return fail(HAIR_EINVAL, "light %d has no shadow map in the last shadowed render", light);
+    const int m = ws->dom_light[light];
+    const size_t texels_n = (size_t)ws->dom_R * ws->dom_R;
+    hipError_t e = hipMemcpy(texels, ws->dom_tex.as<float>() + 8 * texels_n * m, 32 * texels_n, hipMemcpyDeviceToHost);
+    DomGrid gr;
+    if (e == hipSuccess) e = hipMemcpy(&gr, ws->dom_grid.as<DomGrid>() + m, sizeof(DomGrid), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return dev_fail(ws->ctx, e, "debug_dom");
+    for (int i = 0; i < 3; ++i) {
+        grid[i] = gr.b.e1[i];
+        grid[3 + i] = gr.b.e2[i];
+        grid[6 + i] = gr.b.d[i];
+        grid[9 + i] = gr.b.omega[i];
+    }
+    grid[12] = gr.u0;
+    grid[13] = gr.v0;
+    grid[14] = gr.s;
+    grid[15] = gr.z_ref;
     return HAIR_OK;
 }
 

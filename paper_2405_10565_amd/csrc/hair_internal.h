@@ -52,9 +52,30 @@ struct LightConst {
     float rgb[3];
 };
 
+// Deep opacity map of one directional light.  The frame (e1, e2 across the light, d = -omega
+// along it) is set on the host; the grid origin and texel size are found on the device from
+// the level's bounds (k_dom_grid) and read from device memory by the later kernels.
+struct DomBasis {
+    float e1[3], e2[3], d[3], omega[3];
+};
+struct DomGrid {
+    DomBasis b;
+    float u0, v0, s, k16, z_ref;    // texel (i, j) covers u0 + s [i, i+1) x v0 + s [j, j+1)
+    int32_t R;
+};
+constexpr int kDomMaxLayers = 7;
+// What shading reads per light; grid == nullptr: unshadowed.
+struct DomView {
+    const DomGrid* grid;
+    const float4* tex;              // [R * R][2]: (iz0, C_0, C_1, C_2), (C_3 .. C_6); iz0 = 0: no hair
+    int32_t K;
+    float delta;                    // layer depth (world units)
+};
+
 struct LightsConst {
     int32_t n;
     LightConst l[HAIR_MAX_LIGHTS];
+    DomView dom[HAIR_MAX_LIGHTS];
 };
 
 // Material constants derived on the host from hair_material (Sec. 6 parameters).
@@ -213,6 +234,15 @@ hipError_t launch_build_ellipses(const float* vx, const float* vy, const float* 
                                  const int32_t* members, const int32_t* member_start, int32_t K,
                                  const float* cx, const float* cy, const float* cz, const float* r,
                                  float* ahat, float* axes, hipStream_t st);
+// Deep opacity map: the grid of one light from the level's bounds (part: 5 floats per bounds
+// block, at most dom_bound_blocks(nseg) blocks), the light-view segment records, and the
+// per-texel layers from the light view's fragment lists.
+int dom_bound_blocks(int32_t nseg);
+hipError_t launch_dom_grid(const LevelDev& lv, const DomBasis& b, int32_t R, float* part, DomGrid* grid,
+                           hipStream_t st);
+hipError_t launch_project_light(const LevelDev& lv, const DomGrid* grid, SegRec* seg, hipStream_t st);
+hipError_t launch_dom_resolve(const FrameBufs& f, const LevelDev& lv, const DomGrid* grid, int32_t K, float delta,
+                              float4* tex, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
 hipError_t launch_fill_f32(float* p, float v, size_t n, hipStream_t st);
 

@@ -73,6 +73,7 @@ __device__ inline PPoint project_point(const CamConst& c, float px, float py, fl
 }
 
 __device__ inline float norm3f(float x, float y, float z) { return sqrtf((x * x + y * y) + z * z); }
+__device__ inline float dot_e(const float e[3], float x, float y, float z) { return (x * e[0] + y * e[1]) + z * e[2]; }
 
 // Thick-hair half-width: support of the ellipse across the view at the segment midpoint.
 __device__ inline float cluster_halfwidth(const CamConst& c, float ax, float ay, float az, float bx, float by,
@@ -571,11 +572,74 @@ struct ShadeArgs {
     const ShadeRec* shade;
 };
 
+// Deep opacity map lookup (the shadow pass's count of hairs in front of a point toward a
+// light).  Both helpers round every operation once, in this order, so the lookup position and
+// its texel weights are the ones the integer raster parameter fixes (fragment's point on the
+// centre line: t from the integer parameter, perspective-correct t_w, x = pA + t_w (pB - pA)).
+__device__ inline void dom_point(const SegRec& s, const float4& q0, const float4& q1, int tnum, int tden, float& x,
+                                 float& y, float& z) {
+    const float t = (float)tnum / (float)tden;
+    const float iz = s.iza + t * (s.izb - s.iza);
+    const float tw = (t * s.izb) / iz;
+    x = q0.x + tw * (q1.x - q0.x);
+    y = q0.y + tw * (q1.y - q0.y);
+    z = q0.z + tw * (q1.z - q0.z);
+}
+
+// Entry i of (0, A.y, A.z, A.w, B.x, B.y, B.z, B.w) = (C_{-1}, C_0 .. C_6) of a texel.
+__device__ inline float texel_c(const float4& A, const float4& B, int i) {
+    float v = 0.0f;
+    v = i == 1 ? A.y : v;
+    v = i == 2 ? A.z : v;
+    v = i == 3 ? A.w : v;
+    v = i == 4 ? B.x : v;
+    v = i == 5 ? B.y : v;
+    v = i == 6 ? B.z : v;
+    v = i == 7 ? B.w : v;
+    return v;
+}
+
+// Hairs in front of (x, y, z): per texel, x_l = (iz0 - iz) / delta - 1 layers behind the first
+// hit (one layer of bias), C_{j-1} + (x_l - j)(C_j - C_{j-1}) inside layer j, C_{K-1} beyond;
+// bilinear over the four nearest texel centres; outside the grid or on empty texels 0.
+__device__ inline float dom_count(const DomView& dv, float x, float y, float z) {
+    const DomGrid& g = *dv.grid;
+    const float u = dot_e(g.b.e1, x, y, z), v = dot_e(g.b.e2, x, y, z);
+    const float izp = g.z_ref - dot_e(g.b.d, x, y, z);
+    const float Tx = (u - g.u0) / g.s - 0.5f, Ty = (v - g.v0) / g.s - 0.5f;
+    const float i0f = floorf(Tx), j0f = floorf(Ty);
+    const float fx = Tx - i0f, fy = Ty - j0f;
+    const int i0 = (int)i0f, j0 = (int)j0f;
+    float n = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int i = i0 + (c & 1), j = j0 + (c >> 1);
+        if (i < 0 || j < 0 || i >= g.R || j >= g.R) continue;
+        const size_t o = 2 * ((size_t)j * g.R + i);
+        const float4 A = dv.tex[o];
+        if (!(A.x > 0.0f)) continue;
+        const float xl = (A.x - izp) / dv.delta - 1.0f;
+        if (!(xl >= 0.0f)) continue;
+        const float4 B = dv.tex[o + 1];
+        float val;
+        if (xl >= (float)dv.K) {
+            val = texel_c(A, B, dv.K);
+        } else {
+            const int jl = (int)floorf(xl);
+            const float Cp = texel_c(A, B, jl), Cj = texel_c(A, B, jl + 1);
+            val = Cp + (xl - (float)jl) * (Cj - Cp);
+        }
+        const float w = ((c & 1) ? fx : 1.0f - fx) * ((c >> 1) ? fy : 1.0f - fy);
+        n += w * val;
+    }
+    return n;
+}
+
 // Radiance (RGB), coverage alpha and cross-section offset h of one fragment, written once over
 // the scalar type T: float for rendering, Dual<N> for the backward pass.  T carries the
 // fitted parameters (half-width hw, semi-axes |a|, |b|, hair radius r, absorption); the view
 // geometry (frame, angles) does not depend on them and stays float.
-template <int KIND, int MODEL, class T>
+template <int KIND, int MODEL, class T, bool SHADOW = false>
 __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const float4& q0, const float4& q1,
                                   const float4& q2, float n_total, int pxg, int pyg, const T& hw, const T& a_len,
                                   const T& b_len, const T& rr, const T sig[3], T& alpha, T& hoff, T L[3]) {
@@ -656,6 +720,8 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
         cf.n_total = T(n_total);
         cf.rho = m_min(m_max(n_total * rr * rr * (ia * ib), T(0.0f)), T(1.0f));
     }
+    float dpx = 0.f, dpy = 0.f, dpz = 0.f;
+    if (SHADOW) dom_point(s, q0, q1, tnum, tden, dpx, dpy, dpz);
     L[0] = L[1] = L[2] = T(0.0f);
     for (int li = 0; li < a.lights.n; ++li) {
         const LightConst& lc = a.lights.l[li];
@@ -673,8 +739,20 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
         }
         const float sin_ti = dot(wi, u);
         const LightView v = light_view(sin_ti, sin_to, to, cos_to, dot(wi, xh), dot(wi, yh), degen, a.mat);
+        // hairs between the light and this fragment (shadow pass), added to the forward count
+        const float ns = (SHADOW && a.lights.dom[li].grid) ? dom_count(a.lights.dom[li], dpx, dpy, dpz) : 0.0f;
         T f[3];
-        if (KIND == 0) {
+        if (KIND == 0 && SHADOW && ns > 0.0f) {
+            ClusterFrag<T> c1;
+            c1.n_total = T(1.0f);
+            c1.rho = T(1.0f);
+            c1.n_F = T(1.0f + ns);
+            c1.n_B = T(1.0f);
+            if (MODEL == 0)
+                f_ours(v, h, gamma_o, cgo, sigl, a.mat, c1, f);
+            else
+                f_ours_rttd(v, a.mat, c1, f);
+        } else if (KIND == 0) {
             if (MODEL == 0)
                 f_single(v, h, gamma_o, cgo, sigl, a.mat, f);
             else
@@ -700,6 +778,7 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
             const bool back = fabsf(v.phi) < 0.5f * kPi;
             cf.n_F = (back || n_total < 2.0f) ? T(1.0f) : m_max(cf.rho * kappa * lF, T(1.0f));
             cf.n_B = m_max(cf.rho * kappa * lB, T(1.0f));
+            if (SHADOW) cf.n_F = cf.n_F + ns;
             if (MODEL == 0)
                 f_ours(v, h, gamma_o, cgo, sigl, a.mat, cf, f);
             else
@@ -731,15 +810,15 @@ __device__ inline SegInputs fetch_segment(const ShadeArgs& a, uint32_t gseg) {
     return r;
 }
 
-template <int KIND, int MODEL>
+template <int KIND, int MODEL, bool SHADOW = false>
 __device__ inline void shade_inputs(const ShadeArgs& a, const SegInputs& in, int pxg, int pyg, float& alpha,
                                     float& hoff, float L[3]) {
     const float sig[3] = {in.q0.w, in.q1.w, in.q2.w};
     if (KIND == 0 || (KIND == 2 && !(in.s.hwfx & kFlagThick))) {
-        shade_core<0, MODEL, float>(a, in.s, in.q0, in.q1, in.q2, 1.0f, pxg, pyg, in.s.hw, 0.f, 0.f, 0.f, sig, alpha,
+        shade_core<0, MODEL, float, SHADOW>(a, in.s, in.q0, in.q1, in.q2, 1.0f, pxg, pyg, in.s.hw, 0.f, 0.f, 0.f, sig, alpha,
                                     hoff, L);
     } else {
-        shade_core<1, MODEL, float>(a, in.s, in.q0, in.q1, in.q2, in.q3.z, pxg, pyg, in.s.hw, in.q3.x, in.q3.y, in.q3.w,
+        shade_core<1, MODEL, float, SHADOW>(a, in.s, in.q0, in.q1, in.q2, in.q3.z, pxg, pyg, in.s.hw, in.q3.x, in.q3.y, in.q3.w,
                                     sig, alpha, hoff, L);
     }
 }
@@ -1136,7 +1215,7 @@ struct BatchLds {
 // counts, key ranges and offsets are in s_cnt / s_kmin / s_kmax / s_off).  Finished pixels are
 // written to rgba, or (slice_out != nullptr, a single pixel's key slice) their (C, T) goes to
 // slice_out.  rank0 / cnt_total place a slice inside its pixel for the debug dump.
-template <int KIND, int MODEL>
+template <int KIND, int MODEL, bool SHADOW>
 __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, float* __restrict__ rgba,
                                         const DebugDump& dbg, int has_dbg, const BatchLds& L_, const uint32_t* list,
                                         const uint2* src, int px0, int py0, uint32_t Fb, float* slice_out,
@@ -1162,7 +1241,7 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
     // each fragment's segment inputs are fetched one fragment ahead, so that the gathers
     // overlap the shading arithmetic instead of stalling it.  (Not for the R / TT / TRT
     // thick-hair shading: its registers would then exceed the budget of three waves per SIMD.)
-    constexpr bool kAhead = KIND == 0 || MODEL == 1;
+    constexpr bool kAhead = (KIND == 0 && !(SHADOW && MODEL == 0)) || MODEL == 1;
     uint32_t gs[kAhead ? kPerThread : 1];
     SegInputs nxt{};
     if (kAhead) {
@@ -1186,7 +1265,7 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
         const uint32_t p = rec.y >> 24;
         const int gx = px0 + (int)(p % kTile), gy = py0 + (int)(p / kTile);
         float al, hh, L[3];
-        shade_inputs<KIND, MODEL>(a, cur, gx, gy, al, hh, L);
+        shade_inputs<KIND, MODEL, SHADOW>(a, cur, gx, gy, al, hh, L);
         s_pay[3 * i + 0] = al * L[0];
         s_pay[3 * i + 1] = al * L[1];
         s_pay[3 * i + 2] = al * L[2];
@@ -1295,7 +1374,7 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
 // a histogram over the pixel's key range picks the longest run of bins that fits LDS, those
 // records are gathered and processed exactly, and the slice composites chain front to back.
 // (LDS holds three blocks per CU; the register budget is kept at the same three waves per SIMD.)
-template <int KIND, int MODEL>
+template <int KIND, int MODEL, bool SHADOW>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3))) void k_batch(
     FrameBufs f, ShadeArgs a, float* __restrict__ rgba, DebugDump dbg, int has_dbg) {
     __shared__ uint32_t s_cnt[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix], s_off[kTilePix + 1];
@@ -1333,7 +1412,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3))) void k
         for (uint32_t i = t; i < Fb; i += kNT) L_.s_bk[i] = 0;
         __syncthreads();
         PHASE_END(f.ctr, 5);
-        sort_shade_blend<KIND, MODEL>(f, a, rgba, dbg, has_dbg, L_, list, src, px0, py0, Fb, nullptr, 0, 0);
+        sort_shade_blend<KIND, MODEL, SHADOW>(f, a, rgba, dbg, has_dbg, L_, list, src, px0, py0, Fb, nullptr, 0, 0);
         return;
     }
     // ---- a pixel deeper than one batch: exact depth-key slices
@@ -1399,7 +1478,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3))) void k
             s_off[p + 1] = Fb;
         }
         __syncthreads();
-        sort_shade_blend<KIND, MODEL>(f, a, rgba, dbg, has_dbg, L_, list, L_.s_A, px0, py0, Fb, s_slice, done, k);
+        sort_shade_blend<KIND, MODEL, SHADOW>(f, a, rgba, dbg, has_dbg, L_, list, L_.s_A, px0, py0, Fb, s_slice, done, k);
         __syncthreads();
         if (t == 0) {
             C0 += T * s_slice[0];
@@ -1773,12 +1852,225 @@ __global__ void k_build_ellipses(const float* __restrict__ vx, const float* __re
 
 inline int blocks_for(size_t n, int per) { return (int)((n + per - 1) / per); }
 
+
+// ---------------------------------------------------------------------------------------
+// Shadow pass: deep opacity map toward a directional light (Sec. 5.2 shadow pass; its count
+// feeds the forward lobes of Sec. 4).  The light view is an orthographic raster with the
+// camera pass's integer coverage rule, so binning, counting and emission are the camera
+// kernels; only the projection and the per-texel resolve are the light's own.  Every float
+// step that decides an integer (bounds, grid, snapping, depth) is a single rounding per
+// operation in a fixed order (this file is compiled without contraction).
+
+
+// World half-width padding the grid: a strand's radius, a thick hair's larger semi-axis.
+__device__ inline float pad_halfwidth(const LevelDev& lv, int g) {
+    return lv.kind == 0 ? 0.5f * lv.width[g / lv.S] : fmaxf(lv.axes[2 * g], lv.axes[2 * g + 1]);
+}
+
+constexpr int kDomBoundThreads = 256;
+constexpr int kDomBoundMaxBlocks = 1024;
+
+// Per block: (min u - w, max u + w, min v - w, max v + w, max z) over its segments' endpoints.
+__global__ __launch_bounds__(kDomBoundThreads) void k_dom_bounds(LevelDev lv, DomBasis b, float* __restrict__ part) {
+    __shared__ float s_red[5][kDomBoundThreads];
+    float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY, zmax = -INFINITY;
+    for (int g = blockIdx.x * kDomBoundThreads + threadIdx.x; g < lv.nseg; g += gridDim.x * kDomBoundThreads) {
+        const int owner = g / lv.S, k = g - owner * lv.S;
+        const int va = owner * (lv.S + 1) + k;
+        const float w = pad_halfwidth(lv, g);
+        for (int e = 0; e < 2; ++e) {
+            const float x = lv.vx[va + e], y = lv.vy[va + e], z = lv.vz[va + e];
+            const float u = dot_e(b.e1, x, y, z), v = dot_e(b.e2, x, y, z), d = dot_e(b.d, x, y, z);
+            umin = fminf(umin, u - w);
+            umax = fmaxf(umax, u + w);
+            vmin = fminf(vmin, v - w);
+            vmax = fmaxf(vmax, v + w);
+            zmax = fmaxf(zmax, d);
+        }
+    }
+    const int t = threadIdx.x;
+    s_red[0][t] = umin; s_red[1][t] = -umax; s_red[2][t] = vmin; s_red[3][t] = -vmax; s_red[4][t] = -zmax;
+    __syncthreads();
+    for (int h = kDomBoundThreads / 2; h > 0; h >>= 1) {
+        if (t < h)
+            for (int c = 0; c < 5; ++c) s_red[c][t] = fminf(s_red[c][t], s_red[c][t + h]);
+        __syncthreads();
+    }
+    if (t < 5) part[5 * blockIdx.x + t] = s_red[t][0];
+}
+
+// One block: reduce the partial bounds and set the grid (texel size = extent / (R - 2), one
+// texel of margin; z_ref = z_max + 1 so that iz = z_ref - z >= 1 orders like inverse depth).
+__global__ __launch_bounds__(kDomBoundThreads) void k_dom_grid(const float* __restrict__ part, int nb, DomBasis b,
+                                                             int R, DomGrid* __restrict__ grid) {
+    __shared__ float s_red[5][kDomBoundThreads];
+    const int t = threadIdx.x;
+    float m[5] = {INFINITY, INFINITY, INFINITY, INFINITY, INFINITY};
+    for (int i = t; i < nb; i += kDomBoundThreads)
+        for (int c = 0; c < 5; ++c) m[c] = fminf(m[c], part[5 * i + c]);
+    for (int c = 0; c < 5; ++c) s_red[c][t] = m[c];
+    __syncthreads();
+    for (int h = kDomBoundThreads / 2; h > 0; h >>= 1) {
+        if (t < h)
+            for (int c = 0; c < 5; ++c) s_red[c][t] = fminf(s_red[c][t], s_red[c][t + h]);
+        __syncthreads();
+    }
+    if (t == 0) {
+        const float umin = s_red[0][0], umax = -s_red[1][0], vmin = s_red[2][0], vmax = -s_red[3][0];
+        const float zmax = -s_red[4][0];
+        const float ext = fmaxf(fmaxf(umax - umin, vmax - vmin), 1e-6f);
+        DomGrid gr;
+        gr.b = b;
+        gr.s = ext / (float)(R - 2);
+        gr.u0 = umin - gr.s;
+        gr.v0 = vmin - gr.s;
+        gr.k16 = 16.0f / gr.s;
+        gr.z_ref = zmax + 1.0f;
+        gr.R = R;
+        *grid = gr;
+    }
+}
+
+// Light-view record of segment g: snapped texel coordinates (1/16 texel), iz = z_ref - z, and
+// the half-width in texels (a strand's radius; a thick hair's support across the light).
+__global__ __launch_bounds__(256) void k_project_light(LevelDev lv, const DomGrid* __restrict__ grid,
+                                                       SegRec* __restrict__ seg) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= lv.nseg) return;
+    const DomGrid gr = *grid;
+    const int owner = g / lv.S, k = g - owner * lv.S;
+    const int va = owner * (lv.S + 1) + k;
+    const float ax = lv.vx[va], ay = lv.vy[va], az = lv.vz[va];
+    const float bx = lv.vx[va + 1], by = lv.vy[va + 1], bz = lv.vz[va + 1];
+    float hw;
+    if (lv.kind == 0) {
+        hw = (0.5f * lv.width[owner]) / gr.s;
+    } else {
+        const float tx = bx - ax, ty = by - ay, tz = bz - az;
+        const float tl = norm3f(tx, ty, tz);
+        const float ux = tx / tl, uy = ty / tl, uz = tz / tl;
+        const float wx = gr.b.omega[0], wy = gr.b.omega[1], wz = gr.b.omega[2];
+        const float dwu = (wx * ux + wy * uy) + wz * uz;
+        const float px = wx - dwu * ux, py = wy - dwu * uy, pz = wz - dwu * uz;
+        const float pl = norm3f(px, py, pz);
+        const float xx = px / pl, xy = py / pl, xz = pz / pl;
+        const float yx = uy * xz - uz * xy, yy = uz * xx - ux * xz, yz = ux * xy - uy * xx;
+        const float hx = lv.ahat[g], hy = lv.ahat[lv.nseg + g], hz = lv.ahat[2 * lv.nseg + g];
+        const float bhx = uy * hz - uz * hy, bhy = uz * hx - ux * hz, bhz = ux * hy - uy * hx;
+        const float a_len = lv.axes[2 * g], b_len = lv.axes[2 * g + 1];
+        const float pa = a_len * ((hx * yx + hy * yy) + hz * yz);
+        const float pb = b_len * ((bhx * yx + bhy * yy) + bhz * yz);
+        float W = sqrtf(pa * pa + pb * pb);
+        if (!(pl > 1e-7f)) W = fmaxf(a_len, b_len);
+        hw = W / gr.s;
+    }
+    SegRec r;
+    r.xa = (int)rintf((dot_e(gr.b.e1, ax, ay, az) - gr.u0) * gr.k16);
+    r.ya = (int)rintf((dot_e(gr.b.e2, ax, ay, az) - gr.v0) * gr.k16);
+    r.xb = (int)rintf((dot_e(gr.b.e1, bx, by, bz) - gr.u0) * gr.k16);
+    r.yb = (int)rintf((dot_e(gr.b.e2, bx, by, bz) - gr.v0) * gr.k16);
+    r.iza = gr.z_ref - dot_e(gr.b.d, ax, ay, az);
+    r.izb = gr.z_ref - dot_e(gr.b.d, bx, by, bz);
+    r.hw = hw;
+    const float hw16 = 16.0f * hw;
+    r.hwfx = 0;
+    if (isfinite(hw16) && hw16 >= 0.0f) {
+        const float c16 = ceilf(hw16);
+        if (abs(r.xb - r.xa) > kMaxAxis || abs(r.yb - r.ya) > kMaxAxis || c16 > (float)kMaxHwFx)
+            r.hwfx = kFlagCulledLong;
+        else
+            r.hwfx = (int)c16 | kFlagVisible;
+    }
+    seg[g] = r;
+}
+
+// Per texel (one block per 16 x 16 tile): the first hit iz0 (the pixel's smallest key), then
+// every fragment's expected hair count into its layer floor((iz0 - iz) / delta) (clamped to
+// K - 1): a strand its box coverage alpha, a thick hair alpha rho kappa l_max sqrt(1 - h^2)
+// (Sec. 4, hair number; the chord along the light at the texel's offset h = delta / hw).
+// Output: (iz0, C_0 .. C_{K-1}) with C the cumulative counts; iz0 = 0 marks a texel without hair.
+__global__ __launch_bounds__(kNT) void k_dom_resolve(FrameBufs f, LevelDev lv, const DomGrid* __restrict__ grid, int K,
+                                                     float delta, float4* __restrict__ tex) {
+    const int tile = blockIdx.x, t = threadIdx.x;
+    const int R = grid->R;
+    const int px = (tile % f.ntx) * kTile + (t % kTile), py = (tile / f.ntx) * kTile + (t / kTile);
+    if (px >= R || py >= R) return;
+    const size_t q = (size_t)tile * kTilePix + t;
+    const uint32_t cnt = f.pix_cnt[q];
+    float acc[kDomMaxLayers] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float iz0 = 0.0f;
+    if (cnt) {
+        const float s_tex = grid->s;
+        iz0 = __uint_as_float(0xFFFFFFFFu - f.pix_kmin[q]);
+        const uint2* fr = f.frags + f.frag_base[tile] + f.pix_off[q];
+        const uint32_t* list = f.list + f.tile_start[tile];
+        for (uint32_t i = 0; i < cnt; ++i) {
+            const uint2 rec = fr[i];
+            const float iz = __uint_as_float(0xFFFFFFFFu - rec.x);
+            const int layer = min(K - 1, (int)floorf((iz0 - iz) / delta));
+            const uint32_t g = list[rec.y & 0xFFFFFFu];
+            const SegRec s = f.seg[g];
+            const int ex = 16 * px + 8 - s.xa, ey = 16 * py + 8 - s.ya;
+            const int dx = s.xb - s.xa, dy = s.yb - s.ya;
+            const int tden = dx * dx + dy * dy, cr = ex * dy - ey * dx;
+            const float dl = fabsf((float)cr) / sqrtf((float)tden) * (1.0f / 16.0f);
+            const float hw = s.hw;
+            float c = fminf(fmaxf(fminf(dl + hw, 0.5f) - fmaxf(dl - hw, -0.5f), 0.0f), 1.0f);
+            if (lv.kind != 0 && !(hw > 0.0f)) {
+                c = 0.0f;   // a degenerate (zero-width) thick hair holds no hairs across the light
+            } else if (lv.kind != 0) {
+                const int owner = g / lv.S;
+                const float a = lv.axes[2 * g], b = lv.axes[2 * g + 1];
+                const float n = (float)lv.n_total[owner], r = lv.r[owner];
+                const float h = fminf(dl / hw, 1.0f);
+                const float rho = fminf(fmaxf(n * r * r / (a * b), 0.0f), 1.0f);
+                const float kappa = sqrtf(n / (3.14159265358979f * a * b));
+                c = c * rho * kappa * (2.0f * a * b / (hw * s_tex)) * sqrtf((1.0f - h) * (1.0f + h));
+            }
+#pragma unroll
+            for (int k = 0; k < kDomMaxLayers; ++k) acc[k] += (k == layer) ? c : 0.0f;
+        }
+#pragma unroll
+        for (int k = 1; k < kDomMaxLayers; ++k) acc[k] += acc[k - 1];
+    }
+    const size_t o = 2 * ((size_t)py * R + px);
+    tex[o] = make_float4(iz0, acc[0], acc[1], acc[2]);
+    tex[o + 1] = make_float4(acc[3], acc[4], acc[5], acc[6]);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
 hipError_t launch_project(const LevelDev& lv, const CamConst& cam, SegRec* seg, ShadeRec* shade, hipStream_t st) {
     if (lv.nseg == 0) return hipSuccess;
     hipLaunchKernelGGL(k_project, dim3(blocks_for(lv.nseg, 256)), dim3(256), 0, st, lv, cam, seg, shade);
+    return hipGetLastError();
+}
+
+int dom_bound_blocks(int32_t nseg) {
+    return std::max(1, std::min(kDomBoundMaxBlocks, (int)((nseg + kDomBoundThreads - 1) / kDomBoundThreads)));
+}
+
+hipError_t launch_dom_grid(const LevelDev& lv, const DomBasis& b, int32_t R, float* part, DomGrid* grid,
+                           hipStream_t st) {
+    const int nb = dom_bound_blocks(lv.nseg);
+    hipLaunchKernelGGL(k_dom_bounds, dim3(nb), dim3(kDomBoundThreads), 0, st, lv, b, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dom_grid, dim3(1), dim3(kDomBoundThreads), 0, st, part, nb, b, R, grid);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_light(const LevelDev& lv, const DomGrid* grid, SegRec* seg, hipStream_t st) {
+    if (lv.nseg == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_project_light, dim3(blocks_for(lv.nseg, 256)), dim3(256), 0, st, lv, grid, seg);
+    return hipGetLastError();
+}
+
+hipError_t launch_dom_resolve(const FrameBufs& f, const LevelDev& lv, const DomGrid* grid, int32_t K, float delta,
+                              float4* tex, hipStream_t st) {
+    if (f.T == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dom_resolve, dim3(f.T), dim3(kNT), 0, st, f, lv, grid, K, delta, tex);
     return hipGetLastError();
 }
 
@@ -1886,14 +2178,25 @@ hipError_t launch_batches(const FrameBufs& f, const LevelDev& lv, const CamConst
     DebugDump d = dbg ? *dbg : DebugDump{};
     const int hd = dbg ? 1 : 0;
     const dim3 g(n_batches), b(kNT);
-    if (mat.model == 0) {
-        if (lv.kind == 0) hipLaunchKernelGGL((k_batch<0, 0>), g, b, 0, st, f, a, rgba, d, hd);
-        else if (lv.kind == 1) hipLaunchKernelGGL((k_batch<1, 0>), g, b, 0, st, f, a, rgba, d, hd);
-        else hipLaunchKernelGGL((k_batch<2, 0>), g, b, 0, st, f, a, rgba, d, hd);
+    bool shadow = false;
+    for (int i = 0; i < lights.n; ++i) shadow |= lights.dom[i].grid != nullptr;
+    if (shadow && lv.kind == 2) return hipErrorInvalidValue;   // (callers check this first)
+    if (shadow) {
+        if (mat.model == 0) {
+            if (lv.kind == 0) hipLaunchKernelGGL((k_batch<0, 0, true>), g, b, 0, st, f, a, rgba, d, hd);
+            else hipLaunchKernelGGL((k_batch<1, 0, true>), g, b, 0, st, f, a, rgba, d, hd);
+        } else {
+            if (lv.kind == 0) hipLaunchKernelGGL((k_batch<0, 1, true>), g, b, 0, st, f, a, rgba, d, hd);
+            else hipLaunchKernelGGL((k_batch<1, 1, true>), g, b, 0, st, f, a, rgba, d, hd);
+        }
+    } else if (mat.model == 0) {
+        if (lv.kind == 0) hipLaunchKernelGGL((k_batch<0, 0, false>), g, b, 0, st, f, a, rgba, d, hd);
+        else if (lv.kind == 1) hipLaunchKernelGGL((k_batch<1, 0, false>), g, b, 0, st, f, a, rgba, d, hd);
+        else hipLaunchKernelGGL((k_batch<2, 0, false>), g, b, 0, st, f, a, rgba, d, hd);
     } else {
-        if (lv.kind == 0) hipLaunchKernelGGL((k_batch<0, 1>), g, b, 0, st, f, a, rgba, d, hd);
-        else if (lv.kind == 1) hipLaunchKernelGGL((k_batch<1, 1>), g, b, 0, st, f, a, rgba, d, hd);
-        else hipLaunchKernelGGL((k_batch<2, 1>), g, b, 0, st, f, a, rgba, d, hd);
+        if (lv.kind == 0) hipLaunchKernelGGL((k_batch<0, 1, false>), g, b, 0, st, f, a, rgba, d, hd);
+        else if (lv.kind == 1) hipLaunchKernelGGL((k_batch<1, 1, false>), g, b, 0, st, f, a, rgba, d, hd);
+        else hipLaunchKernelGGL((k_batch<2, 1, false>), g, b, 0, st, f, a, rgba, d, hd);
     }
     return hipGetLastError();
 }
