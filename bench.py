@@ -111,6 +111,19 @@ def rttd_frame(ctx, asset, cam, lights, ws, frames: int = 20):
             "fragments": int(st["fragments"]), "material": "R/TT/D (beta_R 0.1, beta_TT 0.2, gamma_TT 0.3)"}
 
 
+def shadowed_frame(ctx, aid, cam, lights, ws, shadow=(1024, 4, 0.02), frames: int = 20):
+    """The same strand frame with deep opacity map shadows for the directional light
+    (outside the timed region; ms includes the shadow pass)."""
+    import numpy as np
+    ms = []
+    for i in range(frames + 2):
+        _, st, _ = ctx.render_shadowed(aid, 0, cam, lights, shadow, ws=ws)
+        if i >= 2:
+            ms.append(st["ms_total"])
+    return {"gpu_mean": round(float(np.mean(ms)), 4), "gpu_p50": round(float(np.percentile(ms, 50)), 4),
+            "resolution": shadow[0], "layers": shadow[1], "layer_depth": shadow[2]}
+
+
 def serve_leg(ctx, n_requests: int, warmup: int = 24, rates=(30.0, 60.0, 120.0)):
     """Served latency: Poisson arrivals at each rate over the three resident serving assets."""
     from paper_2405_10565_amd import serve as S
@@ -225,6 +238,7 @@ def main():
         "cpu_baseline": None,
     }
     res["frame_ms_rttd"] = rttd_frame(ctx, asset, cam, lights, ws)
+    res["frame_ms_shadowed"] = shadowed_frame(ctx, aid, cam, lights, ws)
     ws.close()
     if not args.no_serve:
         res["serving"] = serve_leg(ctx, args.serve_requests)

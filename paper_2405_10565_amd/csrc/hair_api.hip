@@ -486,14 +486,15 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     f.frags = ws->frags.as<uint2>();
     f.batches = ws->batches.as<uint4>();
     HIP_TRY(ctx, hipEventRecord(ws->ev[4], st), "hipEventRecord");
-    if (!dom) HIP_TRY(ctx, launch_batch_records(f, st), "k_batch_records");
+    HIP_TRY(ctx, launch_batch_records(f, st), "k_batch_records");
     HIP_TRY(ctx, launch_emit(f, cc, n_items, st), "k_emit");
     HIP_TRY(ctx, hipEventRecord(ws->ev[5], st), "hipEventRecord");
     LightsConst lc = lights_const(lights, n_lights);
     if (views)
         for (int i = 0; i < n_lights; ++i) lc.dom[i] = views[i];
     if (dom) {
-        HIP_TRY(ctx, launch_dom_resolve(f, lv, dom->grid, dom->K, dom->delta, dom->tex, st), "k_dom_resolve");
+        HIP_TRY(ctx, launch_dom_resolve(f, lv, dom->grid, dom->K, dom->delta, cam->width, n_batches, dom->tex, st),
+                "k_dom_resolve");
     } else if (grad) {
         HIP_TRY(ctx, launch_fill_f32(grad->d_axes, 0.0f, 2ull * lv.nseg, st), "fill");
         HIP_TRY(ctx, launch_fill_f32(grad->d_r, 0.0f, (size_t)lv.n_owner, st), "fill");

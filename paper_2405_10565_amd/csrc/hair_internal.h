@@ -242,7 +242,7 @@ hipError_t launch_dom_grid(const LevelDev& lv, const DomBasis& b, int32_t R, flo
                            hipStream_t st);
 hipError_t launch_project_light(const LevelDev& lv, const DomGrid* grid, SegRec* seg, hipStream_t st);
 hipError_t launch_dom_resolve(const FrameBufs& f, const LevelDev& lv, const DomGrid* grid, int32_t K, float delta,
-                              float4* tex, hipStream_t st);
+                              int32_t R, uint32_t n_batches, float4* tex, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
 hipError_t launch_fill_f32(float* p, float v, size_t n, hipStream_t st);
 

@@ -1988,56 +1988,78 @@ __global__ __launch_bounds__(256) void k_project_light(LevelDev lv, const DomGri
 // every fragment's expected hair count into its layer floor((iz0 - iz) / delta) (clamped to
 // K - 1): a strand its box coverage alpha, a thick hair alpha rho kappa l_max sqrt(1 - h^2)
 // (Sec. 4, hair number; the chord along the light at the texel's offset h = delta / hw).
+// One block per batch of whole texels (the camera pass's batches), one lane per fragment; the
+// counts are summed per (texel, layer) in LDS.  Texels in no batch hold no hair (cleared).
 // Output: (iz0, C_0 .. C_{K-1}) with C the cumulative counts; iz0 = 0 marks a texel without hair.
-__global__ __launch_bounds__(kNT) void k_dom_resolve(FrameBufs f, LevelDev lv, const DomGrid* __restrict__ grid, int K,
-                                                     float delta, float4* __restrict__ tex) {
-    const int tile = blockIdx.x, t = threadIdx.x;
-    const int R = grid->R;
-    const int px = (tile % f.ntx) * kTile + (t % kTile), py = (tile / f.ntx) * kTile + (t / kTile);
-    if (px >= R || py >= R) return;
-    const size_t q = (size_t)tile * kTilePix + t;
-    const uint32_t cnt = f.pix_cnt[q];
-    float acc[kDomMaxLayers] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    float iz0 = 0.0f;
-    if (cnt) {
-        const float s_tex = grid->s;
-        iz0 = __uint_as_float(0xFFFFFFFFu - f.pix_kmin[q]);
-        const uint2* fr = f.frags + f.frag_base[tile] + f.pix_off[q];
-        const uint32_t* list = f.list + f.tile_start[tile];
-        for (uint32_t i = 0; i < cnt; ++i) {
-            const uint2 rec = fr[i];
-            const float iz = __uint_as_float(0xFFFFFFFFu - rec.x);
-            const int layer = min(K - 1, (int)floorf((iz0 - iz) / delta));
-            const uint32_t g = list[rec.y & 0xFFFFFFu];
-            const SegRec s = f.seg[g];
-            const int ex = 16 * px + 8 - s.xa, ey = 16 * py + 8 - s.ya;
-            const int dx = s.xb - s.xa, dy = s.yb - s.ya;
-            const int tden = dx * dx + dy * dy, cr = ex * dy - ey * dx;
-            const float dl = fabsf((float)cr) / sqrtf((float)tden) * (1.0f / 16.0f);
-            const float hw = s.hw;
-            float c = fminf(fmaxf(fminf(dl + hw, 0.5f) - fmaxf(dl - hw, -0.5f), 0.0f), 1.0f);
-            if (lv.kind != 0 && !(hw > 0.0f)) {
-                c = 0.0f;   // a degenerate (zero-width) thick hair holds no hairs across the light
-            } else if (lv.kind != 0) {
-                const int owner = g / lv.S;
-                const float a = lv.axes[2 * g], b = lv.axes[2 * g + 1];
-                const float n = (float)lv.n_total[owner], r = lv.r[owner];
-                const float h = fminf(dl / hw, 1.0f);
-                const float rho = fminf(fmaxf(n * r * r / (a * b), 0.0f), 1.0f);
-                const float kappa = sqrtf(n / (3.14159265358979f * a * b));
-                c = c * rho * kappa * (2.0f * a * b / (hw * s_tex)) * sqrtf((1.0f - h) * (1.0f + h));
-            }
-#pragma unroll
-            for (int k = 0; k < kDomMaxLayers; ++k) acc[k] += (k == layer) ? c : 0.0f;
-        }
-#pragma unroll
-        for (int k = 1; k < kDomMaxLayers; ++k) acc[k] += acc[k - 1];
+__device__ inline float dom_fragment_count(const FrameBufs& f, const LevelDev& lv, float s_tex, uint32_t g, int px,
+                                           int py) {
+    const SegRec s = f.seg[g];
+    const int ex = 16 * px + 8 - s.xa, ey = 16 * py + 8 - s.ya;
+    const int dx = s.xb - s.xa, dy = s.yb - s.ya;
+    const int tden = dx * dx + dy * dy, cr = ex * dy - ey * dx;
+    const float dl = fabsf((float)cr) / sqrtf((float)tden) * (1.0f / 16.0f);
+    const float hw = s.hw;
+    float c = fminf(fmaxf(fminf(dl + hw, 0.5f) - fmaxf(dl - hw, -0.5f), 0.0f), 1.0f);
+    if (lv.kind != 0 && !(hw > 0.0f)) {
+        c = 0.0f;   // a degenerate (zero-width) thick hair holds no hairs across the light
+    } else if (lv.kind != 0) {
+        const int owner = g / lv.S;
+        const float a = lv.axes[2 * g], b = lv.axes[2 * g + 1];
+        const float n = (float)lv.n_total[owner], r = lv.r[owner];
+        const float h = fminf(dl / hw, 1.0f);
+        const float rho = fminf(fmaxf(n * r * r / (a * b), 0.0f), 1.0f);
+        const float kappa = sqrtf(n / (3.14159265358979f * a * b));
+        c = c * rho * kappa * (2.0f * a * b / (hw * s_tex)) * sqrtf((1.0f - h) * (1.0f + h));
     }
-    const size_t o = 2 * ((size_t)py * R + px);
-    tex[o] = make_float4(iz0, acc[0], acc[1], acc[2]);
-    tex[o + 1] = make_float4(acc[3], acc[4], acc[5], acc[6]);
+    return c;
 }
 
+__global__ __launch_bounds__(kNT) void k_dom_resolve(FrameBufs f, LevelDev lv, const DomGrid* __restrict__ grid, int K,
+                                                     float delta, float4* __restrict__ tex) {
+    // per (texel, layer) sums in 32.32 fixed point: integer adds commute, so the LDS atomics
+    // give the same sums in any order (counts are far below 2^31 hairs; resolution 2^-32)
+    __shared__ unsigned long long s_acc[kDomMaxLayers][kTilePix];
+    __shared__ float s_iz0[kTilePix];
+    const uint4 br = f.batches[xcd_contiguous(blockIdx.x, gridDim.x)];
+    const int tile = (int)br.x, p0 = (int)br.y, p1 = (int)br.z;
+    const int t = threadIdx.x;
+    const int R = grid->R;
+    const float s_tex = grid->s;
+    const int tx0 = (tile % f.ntx) * kTile, ty0 = (tile / f.ntx) * kTile;
+    const size_t q = (size_t)tile * kTilePix + t;
+    const bool mine = t >= p0 && t < p1;
+    s_iz0[t] = (mine && f.pix_cnt[q]) ? __uint_as_float(0xFFFFFFFFu - f.pix_kmin[q]) : 0.0f;
+#pragma unroll
+    for (int k = 0; k < kDomMaxLayers; ++k) s_acc[k][t] = 0ull;
+    __syncthreads();
+    const size_t tq = (size_t)tile * kTilePix;
+    const uint32_t b0 = f.pix_off[tq + p0], b1 = p1 < kTilePix ? f.pix_off[tq + p1] : f.tile_tot[tile];
+    const uint2* fr = f.frags + f.frag_base[tile];
+    const uint32_t* list = f.list + f.tile_start[tile];
+    for (uint32_t i = b0 + t; i < b1; i += kNT) {
+        const uint2 rec = fr[i];
+        const uint32_t p = rec.y >> 24;
+        const float iz = __uint_as_float(0xFFFFFFFFu - rec.x);
+        const int layer = min(K - 1, (int)floorf((s_iz0[p] - iz) / delta));
+        const float c = dom_fragment_count(f, lv, s_tex, list[rec.y & 0xFFFFFFu], tx0 + (int)(p % kTile),
+                                           ty0 + (int)(p / kTile));
+        const unsigned long long fx = (unsigned long long)((double)c * 4294967296.0 + 0.5);
+        if (fx) atomicAdd(&s_acc[layer][p], fx);
+    }
+    __syncthreads();
+    const int px = tx0 + (t % kTile), py = ty0 + (t / kTile);
+    if (!mine || px >= R || py >= R) return;
+    float C[kDomMaxLayers];
+    unsigned long long run = 0;
+#pragma unroll
+    for (int k = 0; k < kDomMaxLayers; ++k) {
+        run += s_acc[k][t];
+        C[k] = (float)((double)run * (1.0 / 4294967296.0));
+    }
+    const size_t o = 2 * ((size_t)py * R + px);
+    tex[o] = make_float4(s_iz0[t], C[0], C[1], C[2]);
+    tex[o + 1] = make_float4(C[3], C[4], C[5], C[6]);
+}
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
@@ -2068,9 +2090,10 @@ hipError_t launch_project_light(const LevelDev& lv, const DomGrid* grid, SegRec*
 }
 
 hipError_t launch_dom_resolve(const FrameBufs& f, const LevelDev& lv, const DomGrid* grid, int32_t K, float delta,
-                              float4* tex, hipStream_t st) {
-    if (f.T == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dom_resolve, dim3(f.T), dim3(kNT), 0, st, f, lv, grid, K, delta, tex);
+                              int32_t R, uint32_t n_batches, float4* tex, hipStream_t st) {
+    hipError_t e = launch_fill_f32(reinterpret_cast<float*>(tex), 0.0f, 8ull * R * R, st);
+    if (e != hipSuccess || n_batches == 0) return e;
+    hipLaunchKernelGGL(k_dom_resolve, dim3(n_batches), dim3(kNT), 0, st, f, lv, grid, K, delta, tex);
     return hipGetLastError();
 }
 
