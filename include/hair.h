@@ -118,6 +118,8 @@ int hair_device_count(void);
  * arguments and then returns HAIR_EDEVICE without touching a device (used to test argument
  * checking on machines without a GPU).  *out receives the context. */
 int hair_ctx_create(int32_t device, uint64_t hbm_budget_bytes, hair_ctx** out);
+/* Frees the context's assets and its default workspace; workspaces made by hair_ws_create
+ * must be destroyed before their context. */
 int hair_ctx_destroy(hair_ctx* ctx);
 /* Bytes the context holds and its budget. */
 int hair_ctx_memory(hair_ctx* ctx, uint64_t* used_bytes, uint64_t* budget_bytes);
@@ -212,6 +214,18 @@ int hair_render(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const 
 int hair_render_shadowed(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,
                          const hair_light* lights, int32_t n_lights, const hair_shadow* shadow, float* rgba_out,
                          void* stream, hair_stats* stats);
+
+/* hair_render at a thick-hair level (level >= 1) with curved centre lines (Sec. 5.2: the
+ * tessellation stage subdivides each thick hair by its distance to the camera; Sec. 6: spline
+ * centre lines).  Each centre line is the uniform Catmull-Rom spline through the level's centre
+ * vertices (ends clamped); segment k is split into m equal parameter steps, m the smallest
+ * integer in [1, max_sub] with 16 * m * max_px >= its snapped screen length in 1/16 pixels
+ * (segments with an endpoint off screen are not split).  A step keeps its segment's
+ * cross-section, hair count, radius and absorption.  max_px in [1, 4096], max_sub in [1, 16];
+ * synchronises `stream` once more than hair_render; stats->segments counts the steps. */
+int hair_render_curved(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,
+                       const hair_light* lights, int32_t n_lights, int32_t max_px, int32_t max_sub, float* rgba_out,
+                       void* stream, hair_stats* stats);
 
 /* Per-group, per-segment LoD (Sec. 5.1 step 5; Sec. 5.2 "Dynamic LoD selection",
  * eq. lod_select).  Available when hair_build_lod built 1..7 levels that nest: every cluster

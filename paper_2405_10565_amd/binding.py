@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -27,7 +28,7 @@ EXPORTS = [
     "hair_build_lod", "hair_lod_info", "hair_get_lod", "hair_set_lod", "hair_set_cluster_params",
     "hair_select_level", "hair_render", "hair_render_backward", "hair_debug_segments", "hair_debug_bins",
     "hair_debug_fragments", "hair_lod_groups", "hair_lod_init", "hair_render_mixed", "hair_render_shadowed",
-    "hair_debug_dom",
+    "hair_debug_dom", "hair_render_curved",
 ]
 
 
@@ -125,6 +126,8 @@ def _load():
         "hair_render_shadowed": ([P, P, I32, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32,
                                   C.POINTER(hair_shadow), P, P, C.POINTER(hair_stats)], C.c_int),
         "hair_debug_dom": ([P, I32, fp, fp], C.c_int),
+        "hair_render_curved": ([P, P, I32, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32, I32, I32, P, P,
+                                C.POINTER(hair_stats)], C.c_int),
         "hair_debug_segments": ([P, I64, ip, fp], C.c_int),
         "hair_debug_bins": ([P, I64, up, I64, up], C.c_int),
         "hair_debug_fragments": ([P, P, I32, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32, I32, I32, I32,
@@ -197,6 +200,7 @@ class Workspace:
         h = C.c_void_p()
         check(lib.hair_ws_create(ctx.handle, max_bytes, C.byref(h)))
         self.handle = h
+        ctx._workspaces.add(self)
 
     def close(self):
         if self.handle:
@@ -228,9 +232,14 @@ class Context:
         check(lib.hair_ctx_create(device, budget_bytes, C.byref(h)))
         self.handle = h
         self.device = device
+        self._workspaces = weakref.WeakSet()
 
     def close(self):
+        """Destroy the context's open workspaces, then the context (the C-ABI requires a
+        workspace to be destroyed before its context)."""
         if self.handle:
+            for ws in list(self._workspaces):
+                ws.close()
             lib.hair_ctx_destroy(self.handle)
             self.handle = None
 
@@ -340,6 +349,25 @@ class Context:
         st = hair_stats()
         rc = lib.hair_render_shadowed(self.handle, ws.handle if ws else None, asset, level, C.byref(c), la, nl,
                                       C.byref(sh), C.c_void_p(out.data_ptr()), _stream_ptr(stream), C.byref(st))
+        if raise_on_error:
+            check(rc)
+        return out, st.as_dict(), rc
+
+    def render_curved(self, asset: int, level: int, cam, lights, max_px: int = 4, max_sub: int = 16, out=None,
+                      ws: Workspace | None = None, stream=None, raise_on_error: bool = True):
+        """render a thick-hair level with curved (Catmull-Rom) centre lines tessellated to at
+        most max_px pixels per step (at most max_sub steps per segment)."""
+        import torch
+        c = make_camera(cam)
+        la, nl = make_lights(lights)
+        if out is None:
+            out = torch.empty((c.height, c.width, 4), dtype=torch.float32, device=f"cuda:{self.device}")
+        assert out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+        assert tuple(out.shape) == (c.height, c.width, 4)
+        st = hair_stats()
+        rc = lib.hair_render_curved(self.handle, ws.handle if ws else None, asset, level, C.byref(c), la, nl,
+                                    int(max_px), int(max_sub), C.c_void_p(out.data_ptr()), _stream_ptr(stream),
+                                    C.byref(st))
         if raise_on_error:
             check(rc)
         return out, st.as_dict(), rc

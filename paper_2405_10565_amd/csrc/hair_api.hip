@@ -371,6 +371,13 @@ struct FrameOut {
 
 // A shadow-pass raster: the light view's records instead of the camera's, and the per-texel
 // layers instead of shading.
+// A curved thick-hair frame: the row list over the level's segments (base) and their steps.
+struct TessPass {
+    LevelDev base;
+    const uint32_t* rows;
+    const uint32_t* cnt;
+};
+
 struct DomPass {
     const DomGrid* grid;
     int32_t K;
@@ -389,7 +396,8 @@ struct DomPass {
 int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, const hair_camera* cam,
               const hair_light* lights, int n_lights, float* rgba, const DebugDump* dbg, hipStream_t st,
               FrameOut* out, bool tiles_too = true, const GradOut* grad = nullptr, const HierDev* hier = nullptr,
-              const uint32_t* sel = nullptr, const DomPass* dom = nullptr, const DomView* views = nullptr) {
+              const uint32_t* sel = nullptr, const DomPass* dom = nullptr, const DomView* views = nullptr,
+              const TessPass* tess = nullptr) {
     int rc;
     const CamConst cc = cam_const(cam);
     const int ntx = (cam->width + kTile - 1) / kTile, nty = (cam->height + kTile - 1) / kTile;
@@ -416,6 +424,10 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
                 "k_project_mixed");
     else if (dom)
         HIP_TRY(ctx, launch_project_light(lv, dom->grid, ws->seg.as<SegRec>(), st), "k_project_light");
+    else if (tess)
+        HIP_TRY(ctx, launch_project_tess(tess->base, tess->rows, lv.nseg, tess->cnt, cc, ws->seg.as<SegRec>(),
+                                         ws->shade.as<ShadeRec>(), st),
+                "k_project_tess");
     else
         HIP_TRY(ctx, launch_project(lv, cc, ws->seg.as<SegRec>(), ws->shade.as<ShadeRec>(), st), "k_project");
     HIP_TRY(ctx, launch_bins(ws->seg.as<SegRec>(), lv.nseg, cc, plan, ws->bin_m.as<uint32_t>(), ws->bin_blk.as<uint4>(),
@@ -1232,6 +1244,53 @@ int hair_render_mixed(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_came
         HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
     }
     if (stats) fill_stats(stats, fo, nsel);
+    if (fo.ctr.list_overflow) return fail(HAIR_ERANGE, "%u tiles hold more than 2^24 segments", fo.ctr.list_overflow);
+    if (fo.ctr.overflow_pixels)
+        return fail(HAIR_ERANGE, "%u pixels hold more than %d fragments at one depth key (left transparent)",
+                    fo.ctr.overflow_pixels, kCap);
+    return HAIR_OK;
+}
+
+int hair_render_curved(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,
+                       const hair_light* lights, int32_t n_lights, int32_t max_px, int32_t max_sub, float* rgba_out,
+                       void* stream, hair_stats* stats) {
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if ((rc = validate_camera(cam))) return rc;
+    if ((rc = validate_lights(lights, n_lights))) return rc;
+    if (!rgba_out) return fail(HAIR_EINVAL, "null output image");
+    if (level < 1) return fail(HAIR_EINVAL, "curved centre lines need a thick-hair level (>= 1)");
+    if (max_px < 1 || max_px > 4096) return fail(HAIR_EINVAL, "max_px %d outside [1, 4096]", max_px);
+    if (max_sub < 1 || max_sub > 16) return fail(HAIR_EINVAL, "max_sub %d outside [1, 16]", max_sub);
+    Asset* a;
+    LevelDev base;
+    if ((rc = find_level(ctx, asset, level, &a, &base))) return rc;
+    if (base.nseg >= (1 << 27)) return fail(HAIR_ERANGE, "level %d has 2^27 segments or more", level);
+    if ((rc = need_device(ctx))) return rc;
+    ws = ws_or_default(ctx, ws);
+    std::lock_guard<std::mutex> g(ws->mu);
+    const hipStream_t st = (hipStream_t)stream;
+    const int n = base.nseg;
+    if ((rc = ws_need(ws, ws->sel_cnt, 4ull * (n + 1))) || (rc = ws_need(ws, ws->sel_start, 4ull * (n + 1))) ||
+        (rc = ws_need(ws, ws->sel_tmp, 4 * exscan_scratch_words(n))))
+        return rc;
+    uint32_t* cnt = ws->sel_cnt.as<uint32_t>();
+    uint32_t* start = ws->sel_start.as<uint32_t>();
+    HIP_TRY(ctx, launch_tess(base, cam_const(cam), max_px, max_sub, cnt, start, ws->sel_tmp.as<uint32_t>(), st),
+            "k_tess_count");
+    uint32_t nrows = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&nrows, start + n, 4, hipMemcpyDeviceToHost, st), "copy");
+    HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
+    if ((rc = ws_need(ws, ws->sel, 4ull * std::max<uint32_t>(nrows, 1)))) return rc;
+    HIP_TRY(ctx, launch_tess_fill(cnt, start, n, ws->sel.as<uint32_t>(), st), "k_tess_fill");
+    LevelDev lv = base;
+    lv.nseg = (int32_t)nrows;
+    const TessPass tp{base, ws->sel.as<uint32_t>(), cnt};
+    FrameOut fo;
+    if ((rc = run_frame(ctx, ws, *a, lv, cam, lights, n_lights, rgba_out, nullptr, st, &fo, true, nullptr, nullptr,
+                        nullptr, nullptr, nullptr, &tp)))
+        return rc;
+    if (stats) fill_stats(stats, fo, nrows);
     if (fo.ctr.list_overflow) return fail(HAIR_ERANGE, "%u tiles hold more than 2^24 segments", fo.ctr.list_overflow);
     if (fo.ctr.overflow_pixels)
         return fail(HAIR_ERANGE, "%u pixels hold more than %d fragments at one depth key (left transparent)",

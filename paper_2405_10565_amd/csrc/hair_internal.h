@@ -234,6 +234,13 @@ hipError_t launch_build_ellipses(const float* vx, const float* vy, const float* 
                                  const int32_t* members, const int32_t* member_start, int32_t K,
                                  const float* cx, const float* cy, const float* cz, const float* r,
                                  float* ahat, float* axes, hipStream_t st);
+// Curved thick hairs: per-segment steps cnt[nseg] and their exclusive scan start[nseg + 1]
+// (scan_tmp: exscan scratch), the row list (g << 4 | j), and the rows' records.
+hipError_t launch_tess(const LevelDev& lv, const CamConst& cam, int32_t max_px, int32_t max_sub, uint32_t* cnt,
+                       uint32_t* start, uint32_t* scan_tmp, hipStream_t st);
+hipError_t launch_tess_fill(const uint32_t* cnt, const uint32_t* start, int32_t nseg, uint32_t* rows, hipStream_t st);
+hipError_t launch_project_tess(const LevelDev& lv, const uint32_t* rows, int32_t nrows, const uint32_t* cnt,
+                               const CamConst& cam, SegRec* seg, ShadeRec* shade, hipStream_t st);
 // Deep opacity map: the grid of one light from the level's bounds (part: 5 floats per bounds
 // block, at most dom_bound_blocks(nseg) blocks), the light-view segment records, and the
 // per-texel layers from the light view's fragment lists.

@@ -120,13 +120,12 @@ __device__ inline TileRect tile_rect(const SegRec& s, int ntx, int nty) {
     return r;
 }
 
-// Segment g of level lv: its screen record (projection, snapping, half-width, culling, side of
-// h > 0) and, when sr is given, its shading record.
-__device__ inline SegRec project_segment(const LevelDev& lv, int g, const CamConst& cam, ShadeRec* sr) {
-    const int owner = g / lv.S, k = g - owner * lv.S;
-    const int va = owner * (lv.S + 1) + k;
-    const float ax = lv.vx[va], ay = lv.vy[va], az = lv.vz[va];
-    const float bx = lv.vx[va + 1], by = lv.vy[va + 1], bz = lv.vz[va + 1];
+// Segment g of level lv, drawn between (ax, ay, az) and (bx, by, bz): its screen record
+// (projection, snapping, half-width, culling, side of h > 0) and, when sr is given, its
+// shading record.  The endpoints are the level's vertices, or points of a curved thick hair.
+__device__ inline SegRec project_segment_at(const LevelDev& lv, int g, float ax, float ay, float az, float bx, float by,
+                                            float bz, const CamConst& cam, ShadeRec* sr) {
+    const int owner = g / lv.S;
     const PPoint A = project_point(cam, ax, ay, az);
     const PPoint B = project_point(cam, bx, by, bz);
     if (sr) {   // whole float4 stores (q3 only for thick hairs)
@@ -192,6 +191,13 @@ __device__ inline SegRec project_segment(const LevelDev& lv, int g, const CamCon
         }
     }
     return r;
+}
+
+__device__ inline SegRec project_segment(const LevelDev& lv, int g, const CamConst& cam, ShadeRec* sr) {
+    const int owner = g / lv.S, k = g - owner * lv.S;
+    const int va = owner * (lv.S + 1) + k;
+    return project_segment_at(lv, g, lv.vx[va], lv.vy[va], lv.vz[va], lv.vx[va + 1], lv.vy[va + 1], lv.vz[va + 1], cam,
+                              sr);
 }
 
 __global__ __launch_bounds__(256) void k_project(LevelDev lv, CamConst cam, SegRec* __restrict__ seg,
@@ -1854,6 +1860,78 @@ inline int blocks_for(size_t n, int per) { return (int)((n + per - 1) / per); }
 
 
 // ---------------------------------------------------------------------------------------
+// Curved thick hairs: the centre line is the uniform Catmull-Rom spline through the level's
+// centre vertices (ends clamped), each segment split into m equal parameter steps by its
+// screen length (Sec. 5.2, tessellation by distance; Sec. 6, spline centre lines).  The
+// points decide integers (snapped endpoints), so the basis is evaluated with one rounding
+// per operation in a fixed order; u = 0 and u = 1 return the vertices themselves.
+
+__device__ inline void spline_point(const LevelDev& lv, int owner, int k, float u, float& x, float& y, float& z) {
+    const int base = owner * (lv.S + 1);
+    if (u == 0.0f || u == 1.0f) {
+        const int i = base + k + (u == 1.0f ? 1 : 0);
+        x = lv.vx[i];
+        y = lv.vy[i];
+        z = lv.vz[i];
+        return;
+    }
+    const int i0 = base + max(k - 1, 0), i1 = base + k, i2 = base + k + 1, i3 = base + min(k + 2, lv.S);
+    const float u2 = u * u, u3 = u2 * u;
+    const float w0 = 0.5f * ((2.0f * u2 - u3) - u);
+    const float w1 = 0.5f * ((3.0f * u3 - 5.0f * u2) + 2.0f);
+    const float w2 = 0.5f * ((4.0f * u2 - 3.0f * u3) + u);
+    const float w3 = 0.5f * (u3 - u2);
+    x = ((w0 * lv.vx[i0] + w1 * lv.vx[i1]) + w2 * lv.vx[i2]) + w3 * lv.vx[i3];
+    y = ((w0 * lv.vy[i0] + w1 * lv.vy[i1]) + w2 * lv.vy[i2]) + w3 * lv.vy[i3];
+    z = ((w0 * lv.vz[i0] + w1 * lv.vz[i1]) + w2 * lv.vz[i2]) + w3 * lv.vz[i3];
+}
+
+// Steps of segment g: the smallest m in [1, max_sub] with (m T16)^2 >= dX^2 + dY^2 (snapped
+// screen extent of the straight segment); 1 when an endpoint is not on screen.
+__global__ __launch_bounds__(256) void k_tess_count(LevelDev lv, CamConst cam, int T16, int max_sub,
+                                                    uint32_t* __restrict__ cnt) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= lv.nseg) return;
+    const int owner = g / lv.S, k = g - owner * lv.S;
+    const int va = owner * (lv.S + 1) + k;
+    const PPoint A = project_point(cam, lv.vx[va], lv.vy[va], lv.vz[va]);
+    const PPoint B = project_point(cam, lv.vx[va + 1], lv.vy[va + 1], lv.vz[va + 1]);
+    int m = 1;
+    if (A.ok && B.ok) {
+        const long long dx = (long long)rintf(B.X16) - (long long)rintf(A.X16);
+        const long long dy = (long long)rintf(B.Y16) - (long long)rintf(A.Y16);
+        const long long d2 = dx * dx + dy * dy;
+        while (m < max_sub && (long long)(m * T16) * (long long)(m * T16) < d2) ++m;
+    }
+    cnt[g] = (uint32_t)m;
+}
+
+// Row list: g << 4 | j for the m steps j of every segment g, at start[g].
+__global__ __launch_bounds__(256) void k_tess_fill(const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ start,
+                                                   int nseg, uint32_t* __restrict__ rows) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nseg) return;
+    const uint32_t m = cnt[g], o = start[g];
+    for (uint32_t j = 0; j < m; ++j) rows[o + j] = ((uint32_t)g << 4) | j;
+}
+
+// Row r: step j of segment g, from P(j / m) to P((j + 1) / m), with segment g's cross-section.
+__global__ __launch_bounds__(256) void k_project_tess(LevelDev lv, const uint32_t* __restrict__ rows, int nrows,
+                                                      const uint32_t* __restrict__ cnt, CamConst cam,
+                                                      SegRec* __restrict__ seg, ShadeRec* __restrict__ shade) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    const uint32_t e = rows[r];
+    const int g = (int)(e >> 4), j = (int)(e & 15u);
+    const int m = (int)cnt[g];
+    const int owner = g / lv.S, k = g - owner * lv.S;
+    float ax, ay, az, bx, by, bz;
+    spline_point(lv, owner, k, (float)j / (float)m, ax, ay, az);
+    spline_point(lv, owner, k, (float)(j + 1) / (float)m, bx, by, bz);
+    seg[r] = project_segment_at(lv, g, ax, ay, az, bx, by, bz, cam, shade + r);
+}
+
+// ---------------------------------------------------------------------------------------
 // Shadow pass: deep opacity map toward a directional light (Sec. 5.2 shadow pass; its count
 // feeds the forward lobes of Sec. 4).  The light view is an orthographic raster with the
 // camera pass's integer coverage rule, so binning, counting and emission are the camera
@@ -2066,6 +2144,30 @@ __global__ __launch_bounds__(kNT) void k_dom_resolve(FrameBufs f, LevelDev lv, c
 hipError_t launch_project(const LevelDev& lv, const CamConst& cam, SegRec* seg, ShadeRec* shade, hipStream_t st) {
     if (lv.nseg == 0) return hipSuccess;
     hipLaunchKernelGGL(k_project, dim3(blocks_for(lv.nseg, 256)), dim3(256), 0, st, lv, cam, seg, shade);
+    return hipGetLastError();
+}
+
+hipError_t launch_tess(const LevelDev& lv, const CamConst& cam, int32_t max_px, int32_t max_sub, uint32_t* cnt,
+                       uint32_t* start, uint32_t* scan_tmp, hipStream_t st) {
+    if (lv.nseg == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tess_count, dim3(blocks_for(lv.nseg, 256)), dim3(256), 0, st, lv, cam, 16 * max_px, max_sub,
+                       cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_exscan(cnt, start, lv.nseg, scan_tmp, st);
+}
+
+hipError_t launch_tess_fill(const uint32_t* cnt, const uint32_t* start, int32_t nseg, uint32_t* rows, hipStream_t st) {
+    if (nseg == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tess_fill, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, cnt, start, nseg, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_tess(const LevelDev& lv, const uint32_t* rows, int32_t nrows, const uint32_t* cnt,
+                               const CamConst& cam, SegRec* seg, ShadeRec* shade, hipStream_t st) {
+    if (nrows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_project_tess, dim3(blocks_for(nrows, 256)), dim3(256), 0, st, lv, rows, nrows, cnt, cam, seg,
+                       shade);
     return hipGetLastError();
 }
 

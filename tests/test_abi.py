@@ -96,6 +96,26 @@ def test_rttd_material_validation(B, hctx):
     assert e.value.code == B.HAIR_EDEVICE
 
 
+def test_curved_and_shadowed_validation(B, hctx):
+    """Argument checks of the curved and shadowed renders happen on the host, before the
+    asset lookup (a host-only context has no assets)."""
+    c = _cam(B)
+    la, nl = B.make_lights([type("L", (), dict(kind=0, vec=[0, 0, 1], rgb=[1, 1, 1]))()])
+    img = C.c_void_p(1)
+    for level, mpx, msub in [(0, 4, 16), (1, 0, 16), (1, 4, 0), (1, 4, 17)]:
+        assert B.lib.hair_render_curved(hctx.handle, None, 0, level, C.byref(c), la, nl, mpx, msub, img, None,
+                                        None) == B.HAIR_EINVAL
+    assert B.lib.hair_render_curved(hctx.handle, None, 0, 1, C.byref(c), la, nl, 4, 16, img, None,
+                                    None) == B.HAIR_ENOENT
+    for r, k, d in [(8, 4, 0.02), (64, 0, 0.02), (64, 8, 0.02), (64, 4, 0.0), (64, 4, float("nan"))]:
+        sh = B.hair_shadow(r, k, d)
+        assert B.lib.hair_render_shadowed(hctx.handle, None, 0, 0, C.byref(c), la, nl, C.byref(sh), img, None,
+                                          None) == B.HAIR_EINVAL
+    sh = B.hair_shadow(64, 4, 0.02)
+    assert B.lib.hair_render_shadowed(hctx.handle, None, 0, 0, C.byref(c), la, nl, C.byref(sh), img, None,
+                                      None) == B.HAIR_ENOENT
+
+
 def _cam(B, W=64, H=32, **kw):
     c = B.hair_camera()
     c.pos[:] = [0, 0, 1]
