@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-latency leg")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the R/TT/D and shadowed frames reported beside the main frame")
     ap.add_argument("--serve-requests", type=int, default=240, help="measured requests per arrival rate")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy 5 times (HBM counter calibration)")
@@ -237,8 +239,9 @@ def main():
                      "ops_per_launch": int(ops + TRANS_WEIGHT * trans)},
         "cpu_baseline": None,
     }
-    res["frame_ms_rttd"] = rttd_frame(ctx, asset, cam, lights, ws)
-    res["frame_ms_shadowed"] = shadowed_frame(ctx, aid, cam, lights, ws)
+    if not args.no_extras:
+        res["frame_ms_rttd"] = rttd_frame(ctx, asset, cam, lights, ws)
+        res["frame_ms_shadowed"] = shadowed_frame(ctx, aid, cam, lights, ws)
     ws.close()
     if not args.no_serve:
         res["serving"] = serve_leg(ctx, args.serve_requests)

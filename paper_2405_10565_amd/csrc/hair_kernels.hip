@@ -2,18 +2,20 @@
 //
 // Frame pipeline, all on the caller's stream:
 //   k_project        one thread per segment: float32 projection and 1/16-pixel snapping, screen
-//                    half-width (Sec. 5.2, hair width calculation), culling, and the count of
-//                    segments per 16x16 tile (integer box of the segment expanded by its radius).
+//                    half-width (Sec. 5.2, hair width calculation), culling.
+//   k_bin_count      per block of consecutive segments: tile counts in LDS (no device atomics);
+//   k_bin_offsets    column scan of the per-block count matrix -> each block's place in every list;
 //   k_scan           exclusive prefix sums (tile list offsets, work items, fragment and batch bases).
-//   k_scatter        one thread per segment: append its id to every overlapped tile's list.
+//   k_scatter        per block: append its segments' ids to the overlapped tiles' lists.
 //   k_count          per (tile, list chunk): exact integer coverage -> per-pixel fragment counts
-//                    and depth-key ranges (LDS-aggregated, then one global atomic per pixel).
+//                    (LDS-aggregated, then one global atomic per pixel).
 //   k_tile_prep      per tile: pixel offsets, and whole pixels packed into batches of <= kCap.
-//   k_emit           per (tile, list chunk): (key, local index) records into the fragment buffer.
-//   k_batch          one workgroup per batch, all in LDS: exact per-pixel order by a bucket sort
-//                    (buckets = linear key ranges of each pixel) + insertion inside buckets,
-//                    one lane per fragment for shading, front-to-back blending by a two-level
-//                    segmented scan, coalesced RGBA stores.
+//   k_emit           per (tile, list chunk): (key, local index) records into the fragment buffer
+//                    and each pixel's depth-key range.
+//   k_batch          one workgroup per batch, all in LDS: exact per-pixel order (bucket map over
+//                    each pixel's key range, then each record's rank in its bucket), one lane per
+//                    fragment for shading, front-to-back blending by a two-level segmented scan,
+//                    coalesced RGBA stores.
 // The integer-deciding steps (projection, snapping, half-width, depth key) are float32 with
 // one rounding per operation and no contraction, so they match a float32 reference bit for bit.
 #include <algorithm>
@@ -528,29 +530,36 @@ __device__ inline void for_each_fragment(const SegRec& s, int px0, int py0, int 
     const int j0 = max(py0 + row_lo, ((loy - 8) >> 4) + 1);
     const int j1 = min(min(py0 + row_hi, H - 1), ((hiy - 8 + 15) >> 4) - 1);
     if (i0 > i1 || j0 > j1) return;
-    const double inv_dx = dx != 0 ? 1.0 / (double)dx : 0.0;
-    const double inv_dy = dy != 0 ? 1.0 / (double)dy : 0.0;
-    const double half = dy != 0 ? (double)R * sqrt((double)tden) * fabs(inv_dy) : 0.0;
+    // Candidate columns per row from the two constraints (0 <= t < 1 and the radius), in float32:
+    // only an enumeration (the integer tests below decide), so it just has to contain every
+    // covered column.  Each bound is a product or difference of values below 2^31 computed with
+    // relative error under 1e-6 (float conversions, the hardware reciprocal and square root,
+    // roundings); the range is widened by 2e-6 of the magnitudes involved plus one sub-pixel.
+    const float inv_dx = dx != 0 ? __builtin_amdgcn_rcpf((float)dx) : 0.0f;
+    const float inv_dy = dy != 0 ? __builtin_amdgcn_rcpf((float)dy) : 0.0f;
+    const float half = dy != 0 ? (float)R * __builtin_amdgcn_sqrtf((float)tden) * fabsf(inv_dy) : 0.0f;
     for (int j = j0; j <= j1; ++j) {
         const int ey = 16 * j + 8 - ay;
-        double lo = -1e300, hi = 1e300;
+        float lo = -1e30f, hi = 1e30f, mag = fabsf((float)ax);
         if (dx != 0) {
-            const double a = (double)(-ey * dy) * inv_dx;
-            const double b = (double)(tden - ey * dy) * inv_dx;
-            lo = fmin(a, b);
-            hi = fmax(a, b);
+            const float a = (float)(-ey * dy) * inv_dx;
+            const float b = (float)(tden - ey * dy) * inv_dx;
+            lo = fminf(a, b);
+            hi = fmaxf(a, b);
+            mag += fmaxf(fabsf(a), fabsf(b));
         }
         if (dy != 0) {
-            const double c = (double)(ey * dx) * inv_dy;
-            lo = fmax(lo, c - half);
-            hi = fmin(hi, c + half);
+            const float c = (float)(ey * dx) * inv_dy;
+            lo = fmaxf(lo, c - half);
+            hi = fminf(hi, c + half);
+            mag += fabsf(c) + half;
         }
-        // columns whose centre offset 16 i + 8 - ax lies in [lo, hi]; the float64 bounds carry
-        // relative errors near 1e-16 of values below 2^21, far inside the 1e-6 pixel widening
-        const double flo = ceil(((double)ax + lo - 8.0) * (1.0 / 16.0) - 1e-6);
-        const double fhi = floor(((double)ax + hi - 8.0) * (1.0 / 16.0) + 1e-6);
-        const int c0 = (int)fmax((double)i0, flo);
-        const int c1 = (int)fmin((double)i1, fhi);
+        const float w = 2e-6f * mag + 1.0f;
+        // columns whose centre offset 16 i + 8 - ax lies in [lo - w, hi + w]
+        const float flo = ceilf(((float)ax + (lo - w) - 8.0f) * (1.0f / 16.0f));
+        const float fhi = floorf(((float)ax + (hi + w) - 8.0f) * (1.0f / 16.0f));
+        const int c0 = (int)fmaxf((float)i0, flo);
+        const int c1 = (int)fminf((float)i1, fhi);
         const int ey_dy = ey * dy, ey_dx = ey * dx;
         for (int i = c0; i <= c1; ++i) {
             const int ex = 16 * i + 8 - ax;
@@ -891,11 +900,10 @@ __global__ __launch_bounds__(256) void k_tile_items(const uint32_t* __restrict__
     items[t] = (n + kNT - 1) / kNT;
 }
 
-// Count pass: per-pixel fragment counts and depth-key range of each tile.  Each item adds
-// its LDS-aggregated counts to the tile's pixels and keeps the returned base (its slice of
-// every pixel's range).
+// Count pass: per-pixel fragment counts of each tile.  Each item adds its LDS-aggregated
+// counts to the tile's pixels and keeps the returned base (its slice of every pixel's range).
 __global__ __launch_bounds__(kNT) void k_count(FrameBufs f, CamConst cam, uint32_t n_items) {
-    __shared__ uint32_t s_cnt[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix];
+    __shared__ uint32_t s_cnt[kTilePix];
     __shared__ int s_tile;
     __shared__ uint32_t s_chunk;
     PHASE_BEGIN();
@@ -910,8 +918,6 @@ __global__ __launch_bounds__(kNT) void k_count(FrameBufs f, CamConst cam, uint32
         s_chunk = chunk;
     }
     s_cnt[t] = 0;
-    s_kmin[t] = 0xFFFFFFFFu;
-    s_kmax[t] = 0;
     __syncthreads();
     const int tile = s_tile;
     const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
@@ -920,22 +926,13 @@ __global__ __launch_bounds__(kNT) void k_count(FrameBufs f, CamConst cam, uint32
     const uint32_t j = s_chunk * kNT + t;
     if (j < n) {
         const SegRec s = f.seg[f.list[lstart + j]];
-        for_each_fragment(s, px0, py0, 0, kTile - 1, cam.W, cam.H, [&](int li, int lj, int tnum, int tden, int) {
-            const int p = lj * kTile + li;
-            const uint32_t key = depth_key(s, tnum, tden);
-            atomicAdd(&s_cnt[p], 1u);
-            atomicMin(&s_kmin[p], key);
-            atomicMax(&s_kmax[p], key);
-        });
+        for_each_fragment(s, px0, py0, 0, kTile - 1, cam.W, cam.H,
+                          [&](int li, int lj, int, int, int) { atomicAdd(&s_cnt[lj * kTile + li], 1u); });
     }
     __syncthreads();
     const size_t q = (size_t)tile * kTilePix + t;
     uint32_t base = 0;
-    if (s_cnt[t]) {
-        base = atomicAdd(&f.pix_cnt[q], s_cnt[t]);
-        atomicMin(&f.pix_kmin[q], s_kmin[t]);
-        atomicMax(&f.pix_kmax[q], s_kmax[t]);
-    }
+    if (s_cnt[t]) base = atomicAdd(&f.pix_cnt[q], s_cnt[t]);
     f.item_base[(size_t)item * kTilePix + t] = base;
     PHASE_END(f.ctr, 0);
 }
@@ -1017,9 +1014,10 @@ __global__ __launch_bounds__(kNT) void k_batch_records(FrameBufs f) {
 }
 
 // Emit pass: every fragment into the frame's fragment buffer at
-// frag_base[tile] + pix_off[pixel] + (the item's slice of the pixel) + local slot.
+// frag_base[tile] + pix_off[pixel] + (the item's slice of the pixel) + local slot, and each
+// pixel's depth-key range (LDS-aggregated per item).
 __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam, uint32_t n_items) {
-    __shared__ uint32_t s_cur[kTilePix], s_pos[kTilePix];
+    __shared__ uint32_t s_cur[kTilePix], s_pos[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix];
     __shared__ int s_tile;
     __shared__ uint32_t s_chunk;
     PHASE_BEGIN();
@@ -1035,8 +1033,11 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam, uint32_
     }
     __syncthreads();
     const int tile = s_tile;
+    const size_t q = (size_t)tile * kTilePix + t;
     s_cur[t] = 0;
-    s_pos[t] = f.frag_base[tile] + f.pix_off[(size_t)tile * kTilePix + t] + f.item_base[(size_t)item * kTilePix + t];
+    s_kmin[t] = 0xFFFFFFFFu;
+    s_kmax[t] = 0;
+    s_pos[t] = f.frag_base[tile] + f.pix_off[q] + f.item_base[(size_t)item * kTilePix + t];
     __syncthreads();
     const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
     const uint32_t lstart = f.tile_start[tile];
@@ -1048,8 +1049,15 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam, uint32_
             const int p = lj * kTile + li;
             const uint32_t key = depth_key(s, tnum, tden);
             const uint32_t slot = atomicAdd(&s_cur[p], 1u);
+            atomicMin(&s_kmin[p], key);
+            atomicMax(&s_kmax[p], key);
             f.frags[s_pos[p] + slot] = make_uint2(key, j | ((uint32_t)p << 24));
         });
+    }
+    __syncthreads();
+    if (s_cur[t]) {
+        atomicMin(&f.pix_kmin[q], s_kmin[t]);
+        atomicMax(&f.pix_kmax[q], s_kmax[t]);
     }
     PHASE_END(f.ctr, 1);
 }
