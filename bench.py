@@ -230,8 +230,7 @@ def main():
                    "fragments_per_frame": f1, "pairs_per_frame": frames[0]["pairs"]},
         "frame_ms": {"gpu_mean": round(float(ms_frame.mean()), 4), "gpu_p50": round(float(np.percentile(ms_frame, 50)), 4),
                      "gpu_p99": round(float(np.percentile(ms_frame, 99)), 4),
-                     "project": round(float(np.mean([f["ms_project"] for f in frames])), 4),
-                     "bin": round(float(np.mean([f["ms_bin"] for f in frames])), 4),
+                     "front": round(float(np.mean([f["ms_project"] for f in frames])), 4),
                      "tile": round(float(ms_tile.mean()), 4)},
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_LANE_OPS / 1e12, 2),
                      "unit": "Tops/s", "frac": round(achieved / PEAK_LANE_OPS, 4),

@@ -96,7 +96,9 @@ typedef struct hair_stats {
     uint32_t segments_culled_long; /* culled for exceeding 1024 px per axis or 256 px half-width */
     uint32_t overflow_pixels;    /* pixels with more than HAIR_PIXEL_CAPACITY fragments at one depth key (left 0) */
     float ms_total;              /* GPU time of the call's kernels (hipEvent) */
-    float ms_project, ms_bin, ms_tile;
+    float ms_project;            /* of which before shading: projection, binning, coverage, emission */
+    float ms_bin;                /* 0: binning is timed within ms_project */
+    float ms_tile;               /* of which the shading pass (sort, shade, blend) */
     uint32_t deep_pixels;        /* pixels deeper than one LDS batch, rendered in depth-key slices */
     uint32_t batches;            /* LDS batches of the frame */
 } hair_stats;
@@ -199,8 +201,10 @@ typedef struct hair_shadow {
 
 /* Render one frame (the hot path).  rgba_out: device float[height][width][4], premultiplied
  * (C, 1 - T) over transparent black, written in full.  n_lights in 1..HAIR_MAX_LIGHTS.
- * The call synchronises `stream` three times (twice to size the frame's buffers, once at the
- * end).  Pixels of any depth are rendered exactly; HAIR_ERANGE only when more than
+ * The call synchronises `stream` once, at the end.  The first frame on a workspace (and a
+ * frame that outgrows the workspace's buffers, which is then rendered again) also
+ * synchronises twice in between to size them, with a quarter of headroom kept for the
+ * frames that follow.  Pixels of any depth are rendered exactly; HAIR_ERANGE only when more than
  * HAIR_PIXEL_CAPACITY fragments of one pixel share one depth key (stats->overflow_pixels). */
 int hair_render(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,
                 const hair_light* lights, int32_t n_lights, float* rgba_out, void* stream,
@@ -208,7 +212,7 @@ int hair_render(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const 
 
 /* hair_render with deep opacity map shadows (see hair_shadow) at a strand or thick-hair level
  * (mixed frames are not shadowed).  One shadow pass per directional light runs on `stream`
- * before the frame (each synchronises it twice to size its buffers); stats describe the
+ * before the frame (sized like a frame, see hair_render); stats describe the
  * camera frame, with ms_total including the shadow passes.  The workspace keeps the maps
  * until its next shadowed render. */
 int hair_render_shadowed(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,

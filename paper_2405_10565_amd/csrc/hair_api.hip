@@ -86,6 +86,7 @@ struct hair_ws {
     DevBuf dom_tex, dom_grid, dom_part;      // shadow pass: texels, grids, bounds partials
     int32_t dom_R = 0, dom_K = 0, dom_n = 0;  // last shadowed render: resolution, layers, maps
     int32_t dom_light[HAIR_MAX_LIGHTS] = {};  // map index of each light, -1 if unshadowed
+    FrameCaps caps = {};                      // buffer capacities of warm frames (0: none yet)
     hipEvent_t ev[7] = {};
     bool events = false;
     int64_t last_nseg = 0, last_ntiles = 0, last_pairs = 0;
@@ -388,22 +389,31 @@ struct DomPass {
 // Project + bin + tile for one level; the caller holds ws->mu.
 //   k_project                         per-segment records (projection, half-width, culling)
 //   k_bin_count, k_bin_offsets, k_scan per-block tile counts, their column scan, list offsets
-//   k_tile_items, k_scan              work items (list chunks) per tile      -> sync 1 (sizes)
+//   k_tile_items, k_scan              work items (list chunks) per tile
 //   k_scatter                         tile lists (per-block LDS cursors)
-//   k_count, k_tile_prep, k_scan x2   per-pixel counts / key ranges, offsets, batches -> sync 2
-//   k_batch_records, k_emit           batch table, fragment buffer
+//   k_count, k_tile_prep, k_scan x2   per-pixel counts, offsets, batches
+//   k_batch_records, k_emit           batch table, fragment buffer and per-pixel key ranges
 //   k_batch                           sort, shade, blend (one workgroup per batch)
+// A cold frame reads the frame's sizes back twice (after the work items and after the
+// batches) to size its buffers, with a quarter of headroom that the workspace keeps as its
+// capacities.  A warm frame launches on those capacities without reading anything back: the
+// kernels take the real sizes from device memory, k_check_caps flags a size beyond its
+// capacity (after which the passes that fill sized buffers do nothing), and a flagged frame
+// is rendered again cold.  The frame ends with one synchronisation for the counters.
+static uint32_t with_headroom(uint32_t n) { return n + n / 4 + 256; }
+
 int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, const hair_camera* cam,
               const hair_light* lights, int n_lights, float* rgba, const DebugDump* dbg, hipStream_t st,
               FrameOut* out, bool tiles_too = true, const GradOut* grad = nullptr, const HierDev* hier = nullptr,
               const uint32_t* sel = nullptr, const DomPass* dom = nullptr, const DomView* views = nullptr,
-              const TessPass* tess = nullptr) {
+              const TessPass* tess = nullptr, bool cold = false) {
     int rc;
     const CamConst cc = cam_const(cam);
     const int ntx = (cam->width + kTile - 1) / kTile, nty = (cam->height + kTile - 1) / kTile;
     const int T = ntx * nty;
     const size_t TP = (size_t)T * kTilePix;
     const BinPlan plan = bin_plan(lv.nseg, T);
+    const bool warm = tiles_too && !cold && ws->caps.items > 0 && ws->caps.batches > 0;
     if ((rc = ws_events(ws))) return rc;
     if ((rc = ws_need(ws, ws->seg, sizeof(SegRec) * (size_t)std::max(lv.nseg, 1)))) return rc;
     if ((rc = ws_need(ws, ws->shade, sizeof(ShadeRec) * (size_t)std::max(lv.nseg, 1)))) return rc;
@@ -435,22 +445,29 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
             "k_bin_count");
     HIP_TRY(ctx, launch_tile_items(tile_start, T, ws->items.as<uint32_t>(), st), "k_tile_items");
     HIP_TRY(ctx, launch_exscan(ws->items.as<uint32_t>(), ws->item_start.as<uint32_t>(), T, scan_tmp, st), "k_scan");
-    HIP_TRY(ctx, hipEventRecord(ws->ev[1], st), "hipEventRecord");
-    uint32_t sizes1[2] = {0, 0};
-    HIP_TRY(ctx, hipMemcpyAsync(&sizes1[0], tile_start + T, 4, hipMemcpyDeviceToHost, st), "copy");
-    HIP_TRY(ctx, hipMemcpyAsync(&sizes1[1], ws->item_start.as<uint32_t>() + T, 4, hipMemcpyDeviceToHost, st), "copy");
-    HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
-    const uint32_t pairs = sizes1[0], n_items = sizes1[1];
-    ws->last_nseg = lv.nseg;
-    ws->last_ntiles = T;
-    ws->last_pairs = pairs;
-    out->pairs = pairs;
-    if (!tiles_too) {
-        HIP_TRY(ctx, hipMemcpy(&out->ctr, ws->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost), "copy");
-        return HAIR_OK;
+    FrameCaps caps = ws->caps;
+    uint32_t pairs = 0, n_items = 0;
+    if (!warm) {
+        uint32_t sizes1[2] = {0, 0};
+        HIP_TRY(ctx, hipMemcpyAsync(&sizes1[0], tile_start + T, 4, hipMemcpyDeviceToHost, st), "copy");
+        HIP_TRY(ctx, hipMemcpyAsync(&sizes1[1], ws->item_start.as<uint32_t>() + T, 4, hipMemcpyDeviceToHost, st),
+                "copy");
+        HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
+        pairs = sizes1[0];
+        n_items = sizes1[1];
+        ws->last_nseg = lv.nseg;
+        ws->last_ntiles = T;
+        ws->last_pairs = pairs;
+        out->pairs = pairs;
+        if (!tiles_too) {
+            HIP_TRY(ctx, hipMemcpy(&out->ctr, ws->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost), "copy");
+            return HAIR_OK;
+        }
+        caps.pairs = std::max(caps.pairs, with_headroom(pairs));
+        caps.items = std::max(caps.items, with_headroom(n_items));
     }
-    if ((rc = ws_need(ws, ws->list, 4ull * std::max<uint32_t>(pairs, 1)))) return rc;
-    if ((rc = ws_need(ws, ws->item_base, 4ull * kTilePix * std::max<uint32_t>(n_items, 1)))) return rc;
+    if ((rc = ws_need(ws, ws->list, 4ull * caps.pairs))) return rc;
+    if ((rc = ws_need(ws, ws->item_base, 4ull * kTilePix * caps.items))) return rc;
     for (DevBuf* b : {&ws->pix_cnt, &ws->pix_kmin, &ws->pix_kmax, &ws->pix_off})
         if ((rc = ws_need(ws, *b, 4 * TP))) return rc;
     for (DevBuf* b : {&ws->tile_tot, &ws->tile_nb})
@@ -476,61 +493,81 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     f.frag_base = ws->frag_base.as<uint32_t>();
     f.batch_start = ws->batch_start.as<uint32_t>();
     f.ctr = ws->ctr.as<Counters>();
-    HIP_TRY(ctx, hipEventRecord(ws->ev[2], st), "hipEventRecord");
-    HIP_TRY(ctx, launch_scatter(f.seg, lv.nseg, cc, plan, tile_start, ws->bin_m.as<uint32_t>(), ws->list.as<uint32_t>(), st),
+    HIP_TRY(ctx, launch_check_caps(f, caps, 1, st), "k_check_caps");
+    HIP_TRY(ctx, launch_scatter(f.seg, lv.nseg, cc, plan, tile_start, ws->bin_m.as<uint32_t>(), ws->list.as<uint32_t>(),
+                                f.ctr, st),
             "k_scatter");
-    HIP_TRY(ctx, launch_fill_u32(f.pix_cnt, 0u, TP, st), "fill");
-    HIP_TRY(ctx, launch_fill_u32(f.pix_kmin, 0xFFFFFFFFu, TP, st), "fill");
-    HIP_TRY(ctx, launch_fill_u32(f.pix_kmax, 0u, TP, st), "fill");
+    HIP_TRY(ctx, launch_fill_pix(f.pix_cnt, f.pix_kmin, f.pix_kmax, TP, st), "fill");
     if (rgba) HIP_TRY(ctx, launch_fill_f32(rgba, 0.0f, 4ull * cam->width * cam->height, st), "fill");
-    HIP_TRY(ctx, launch_count(f, cc, n_items, st), "k_count");
+    const uint32_t item_grid = warm ? caps.items : n_items;
+    HIP_TRY(ctx, launch_count(f, cc, item_grid, st), "k_count");
     HIP_TRY(ctx, launch_tile_prep(f, st), "k_tile_prep");
     HIP_TRY(ctx, launch_exscan(f.tile_tot, ws->frag_base.as<uint32_t>(), T, scan_tmp, st), "k_scan");
     HIP_TRY(ctx, launch_exscan(f.tile_nb, ws->batch_start.as<uint32_t>(), T, scan_tmp, st), "k_scan");
-    HIP_TRY(ctx, hipEventRecord(ws->ev[3], st), "hipEventRecord");
-    uint32_t sizes2[2] = {0, 0};
-    HIP_TRY(ctx, hipMemcpyAsync(&sizes2[0], ws->frag_base.as<uint32_t>() + T, 4, hipMemcpyDeviceToHost, st), "copy");
-    HIP_TRY(ctx, hipMemcpyAsync(&sizes2[1], ws->batch_start.as<uint32_t>() + T, 4, hipMemcpyDeviceToHost, st), "copy");
-    HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
-    const uint32_t n_frags = sizes2[0], n_batches = sizes2[1];
-    if ((rc = ws_need(ws, ws->frags, 8ull * std::max<uint32_t>(n_frags, 1)))) return rc;
-    if ((rc = ws_need(ws, ws->batches, 16ull * std::max<uint32_t>(n_batches, 1)))) return rc;
+    uint32_t n_frags = 0, n_batches = 0;
+    if (!warm) {
+        uint32_t sizes2[2] = {0, 0};
+        HIP_TRY(ctx, hipMemcpyAsync(&sizes2[0], ws->frag_base.as<uint32_t>() + T, 4, hipMemcpyDeviceToHost, st),
+                "copy");
+        HIP_TRY(ctx, hipMemcpyAsync(&sizes2[1], ws->batch_start.as<uint32_t>() + T, 4, hipMemcpyDeviceToHost, st),
+                "copy");
+        HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
+        n_frags = sizes2[0];
+        n_batches = sizes2[1];
+        caps.frags = std::max(caps.frags, with_headroom(n_frags));
+        caps.batches = std::max(caps.batches, with_headroom(n_batches));
+    }
+    if ((rc = ws_need(ws, ws->frags, 8ull * caps.frags))) return rc;
+    if ((rc = ws_need(ws, ws->batches, 16ull * caps.batches))) return rc;
     f.frags = ws->frags.as<uint2>();
     f.batches = ws->batches.as<uint4>();
-    HIP_TRY(ctx, hipEventRecord(ws->ev[4], st), "hipEventRecord");
+    HIP_TRY(ctx, launch_check_caps(f, caps, 2, st), "k_check_caps");
+    const uint32_t batch_grid = warm ? caps.batches : n_batches;
     HIP_TRY(ctx, launch_batch_records(f, st), "k_batch_records");
-    HIP_TRY(ctx, launch_emit(f, cc, n_items, st), "k_emit");
+    HIP_TRY(ctx, launch_emit(f, cc, item_grid, st), "k_emit");
     HIP_TRY(ctx, hipEventRecord(ws->ev[5], st), "hipEventRecord");
     LightsConst lc = lights_const(lights, n_lights);
     if (views)
         for (int i = 0; i < n_lights; ++i) lc.dom[i] = views[i];
     if (dom) {
-        HIP_TRY(ctx, launch_dom_resolve(f, lv, dom->grid, dom->K, dom->delta, cam->width, n_batches, dom->tex, st),
+        HIP_TRY(ctx, launch_dom_resolve(f, lv, dom->grid, dom->K, dom->delta, cam->width, batch_grid, dom->tex, st),
                 "k_dom_resolve");
     } else if (grad) {
         HIP_TRY(ctx, launch_fill_f32(grad->d_axes, 0.0f, 2ull * lv.nseg, st), "fill");
         HIP_TRY(ctx, launch_fill_f32(grad->d_r, 0.0f, (size_t)lv.n_owner, st), "fill");
         HIP_TRY(ctx, launch_fill_f32(grad->d_sig, 0.0f, 3ull * lv.n_owner, st), "fill");
-        HIP_TRY(ctx, launch_batches_bwd(f, lv, cc, lc, mat_const(a.mat), n_batches, *grad, st), "k_batch_bwd");
+        HIP_TRY(ctx, launch_batches_bwd(f, lv, cc, lc, mat_const(a.mat), batch_grid, *grad, st), "k_batch_bwd");
     } else if (rgba) {
-        HIP_TRY(ctx, launch_batches(f, lv, cc, lc, mat_const(a.mat), n_batches, rgba, dbg, st), "k_batch");
+        HIP_TRY(ctx, launch_batches(f, lv, cc, lc, mat_const(a.mat), batch_grid, rgba, dbg, st), "k_batch");
     }
     HIP_TRY(ctx, hipEventRecord(ws->ev[6], st), "hipEventRecord");
     HIP_TRY(ctx, hipMemcpyAsync(&out->ctr, ws->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, st), "copy");
     HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
+    if (out->ctr.cap_overflow) {
+        if (!warm) return fail(HAIR_EDEVICE, "frame sizes exceeded the capacities read for them");
+        return run_frame(ctx, ws, a, lv, cam, lights, n_lights, rgba, dbg, st, out, tiles_too, grad, hier, sel, dom, views,
+                         tess, true);
+    }
+    ws->caps = caps;
+    pairs = out->ctr.sizes[0];
+    n_frags = out->ctr.sizes[2];
+    n_batches = out->ctr.sizes[3];
+    ws->last_nseg = lv.nseg;
+    ws->last_ntiles = T;
+    ws->last_pairs = pairs;
+    out->pairs = pairs;
     out->ctr.fragments = n_frags;
-    float t01 = 0, t23 = 0, t45 = 0, t56 = 0, t06 = 0;
-    HIP_TRY(ctx, hipEventElapsedTime(&t01, ws->ev[0], ws->ev[1]), "elapsed");
-    HIP_TRY(ctx, hipEventElapsedTime(&t23, ws->ev[2], ws->ev[3]), "elapsed");
-    HIP_TRY(ctx, hipEventElapsedTime(&t45, ws->ev[4], ws->ev[5]), "elapsed");
+    // three timing markers only: each costs the stream a few microseconds of idle time
+    float t05 = 0, t56 = 0, t06 = 0;
+    HIP_TRY(ctx, hipEventElapsedTime(&t05, ws->ev[0], ws->ev[5]), "elapsed");
     HIP_TRY(ctx, hipEventElapsedTime(&t56, ws->ev[5], ws->ev[6]), "elapsed");
     HIP_TRY(ctx, hipEventElapsedTime(&t06, ws->ev[0], ws->ev[6]), "elapsed");
-    out->ms[0] = t06; out->ms[1] = t01; out->ms[2] = t23 + t45; out->ms[3] = t56;
+    out->ms[0] = t06; out->ms[1] = t05; out->ms[2] = 0.0f; out->ms[3] = t56;
     out->n_batches = n_batches;
 #ifdef HAIR_PHASE_STATS
     fprintf(stderr, "phase cycles: count %llu emit %llu sort %llu shade %llu blend %llu load %llu | batches %u items %u\n",
             out->ctr.phase[0], out->ctr.phase[1], out->ctr.phase[2], out->ctr.phase[3], out->ctr.phase[4], out->ctr.phase[5], n_batches,
-            n_items);
+            out->ctr.sizes[1]);
 #endif
     return HAIR_OK;
 }

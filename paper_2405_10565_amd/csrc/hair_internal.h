@@ -142,7 +142,14 @@ struct Counters {
     uint32_t max_hw_bits;    // float bits of the largest visible half-width (non-negative)
     uint32_t list_overflow;  // tiles whose list exceeded the 24-bit local index
     uint32_t deep_pixels;    // pixels deeper than one LDS batch (rendered in depth-key slices)
+    uint32_t cap_overflow;   // a frame size exceeded its buffer: the later passes did nothing
+    uint32_t sizes[4];       // list entries, work items, fragments, batches of the frame
     unsigned long long phase[8];  // per-phase cycle sums (instrumented builds only)
+};
+
+// Buffer capacities a frame may fill without the host reading its sizes first.
+struct FrameCaps {
+    uint32_t pairs, items, frags, batches;
 };
 
 // Optional per-pixel fragment dump of a pixel rectangle (tests).
@@ -206,7 +213,12 @@ hipError_t launch_bins(const SegRec* seg, int32_t nseg, const CamConst& cam, con
                        uint4* blk, uint32_t* tot, uint32_t* tile_start, Counters* ctr, uint32_t* scan_tmp,
                        hipStream_t st);
 hipError_t launch_scatter(const SegRec* seg, int32_t nseg, const CamConst& cam, const BinPlan& p,
-                          const uint32_t* tile_start, const uint32_t* M, uint32_t* list, hipStream_t st);
+                          const uint32_t* tile_start, const uint32_t* M, uint32_t* list, const Counters* ctr,
+                          hipStream_t st);
+// Record the frame's sizes in ctr->sizes and flag ctr->cap_overflow when one exceeds its
+// capacity (stage 1: list entries and work items; stage 2: fragments and batches).  Every
+// later pass that would fill a sized buffer does nothing once the flag is set.
+hipError_t launch_check_caps(const FrameBufs& f, const FrameCaps& caps, int stage, hipStream_t st);
 hipError_t launch_tile_items(const uint32_t* tile_start, int T, uint32_t* items, hipStream_t st);
 // Per-group LoD: initial levels, deferred update in place, and a mixed frame's selection
 // (cnt and sel_start: G*S and G*S + 1 words; sel: one entry per selected segment).
@@ -218,14 +230,15 @@ hipError_t launch_select_fill(const HierDev& h, const int32_t* levels, const uin
                               hipStream_t st);
 hipError_t launch_project_mixed(const HierDev& h, const uint32_t* sel, int32_t nsel, const CamConst& cam, SegRec* seg,
                                 ShadeRec* shade, hipStream_t st);
-hipError_t launch_count(const FrameBufs& f, const CamConst& cam, uint32_t n_items, hipStream_t st);
+// grid: blocks to launch (>= the frame's work items / batches, read on the device)
+hipError_t launch_count(const FrameBufs& f, const CamConst& cam, uint32_t grid, hipStream_t st);
 hipError_t launch_tile_prep(const FrameBufs& f, hipStream_t st);
 hipError_t launch_batch_records(const FrameBufs& f, hipStream_t st);
-hipError_t launch_emit(const FrameBufs& f, const CamConst& cam, uint32_t n_items, hipStream_t st);
+hipError_t launch_emit(const FrameBufs& f, const CamConst& cam, uint32_t grid, hipStream_t st);
 hipError_t launch_batches(const FrameBufs& f, const LevelDev& lv, const CamConst& cam, const LightsConst& lights,
-                          const MatConst& mat, uint32_t n_batches, float* rgba, const DebugDump* dbg, hipStream_t st);
+                          const MatConst& mat, uint32_t grid, float* rgba, const DebugDump* dbg, hipStream_t st);
 hipError_t launch_batches_bwd(const FrameBufs& f, const LevelDev& lv, const CamConst& cam, const LightsConst& lights,
-                              const MatConst& mat, uint32_t n_batches, const GradOut& grad, hipStream_t st);
+                              const MatConst& mat, uint32_t grid, const GradOut& grad, hipStream_t st);
 hipError_t launch_build_centers(const float* vx, const float* vy, const float* vz, const float* width,
                                 const float* sig, int32_t n_strands, int32_t V, const int32_t* members,
                                 const int32_t* member_start, int32_t K, float* cx, float* cy, float* cz,
@@ -249,8 +262,10 @@ hipError_t launch_dom_grid(const LevelDev& lv, const DomBasis& b, int32_t R, flo
                            hipStream_t st);
 hipError_t launch_project_light(const LevelDev& lv, const DomGrid* grid, SegRec* seg, hipStream_t st);
 hipError_t launch_dom_resolve(const FrameBufs& f, const LevelDev& lv, const DomGrid* grid, int32_t K, float delta,
-                              int32_t R, uint32_t n_batches, float4* tex, hipStream_t st);
+                              int32_t R, uint32_t n_blocks, float4* tex, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
+// The frame's per-pixel counters: n counts set to 0, key minima to ~0, key maxima to 0.
+hipError_t launch_fill_pix(uint32_t* cnt, uint32_t* kmin, uint32_t* kmax, size_t n, hipStream_t st);
 hipError_t launch_fill_f32(float* p, float v, size_t n, hipStream_t st);
 
 }  // namespace hair

@@ -5,7 +5,7 @@
 //                    half-width (Sec. 5.2, hair width calculation), culling.
 //   k_bin_count      per block of consecutive segments: tile counts in LDS (no device atomics);
 //   k_bin_offsets    column scan of the per-block count matrix -> each block's place in every list;
-//   k_scan           exclusive prefix sums (tile list offsets, work items, fragment and batch bases).
+//   k_scan1          exclusive prefix sums (tile list offsets, work items, fragment and batch bases).
 //   k_scatter        per block: append its segments' ids to the overlapped tiles' lists.
 //   k_count          per (tile, list chunk): exact integer coverage -> per-pixel fragment counts
 //                    (LDS-aggregated, then one global atomic per pixel).
@@ -302,32 +302,61 @@ __global__ __launch_bounds__(256) void k_project_mixed(HierDev h, const uint32_t
     seg[i] = r;
 }
 
-// Exclusive scan of n counts by one 1024-thread block; start[n] = total.
-__global__ __launch_bounds__(1024) void k_scan(const uint32_t* __restrict__ cnt, uint32_t* __restrict__ start, int n) {
-    __shared__ uint32_t s_part[1024];
-    const int t = threadIdx.x;
-    const int per = (n + 1023) / 1024;
-    const int b = t * per, e = min(n, b + per);
-    uint32_t sum = 0;
-    for (int i = b; i < e; ++i) sum += cnt[i];
-    s_part[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t v = t >= off ? s_part[t - off] : 0u;
+// Exclusive scan of n counts by one 1024-thread block in coalesced chunks of 4096 (four
+// consecutive counts per lane, wave shuffles, one LDS step across the 16 waves); start[n] =
+// total.  For n up to kScanOneBlock.
+constexpr int kScanOneBlock = 1 << 16;
+__global__ __launch_bounds__(1024) void k_scan1(const uint32_t* __restrict__ cnt, uint32_t* __restrict__ start, int n) {
+    __shared__ uint32_t s_w[16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    uint32_t carry = 0;
+    for (int base = 0; base < n; base += 4096) {
+        const int i0 = base + 4 * t;
+        uint32_t v[4], sum = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = i0 + k < n ? cnt[i0 + k] : 0u;
+            sum += v[k];
+        }
+        uint32_t x = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) s_w[w] = x;
         __syncthreads();
-        s_part[t] += v;
+        uint32_t wbase = 0, total = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const uint32_t a = s_w[k];
+            if (k < w) wbase += a;
+            total += a;
+        }
+        uint32_t run = carry + wbase + (x - sum);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (i0 + k < n) start[i0 + k] = run;
+            run += v[k];
+        }
+        carry += total;
         __syncthreads();
     }
-    uint32_t run = s_part[t] - sum;
-    for (int i = b; i < e; ++i) {
-        start[i] = run;
-        run += cnt[i];
+    if (t == 0) start[n] = carry;
+}
+
+// The per-pixel counters of a frame: counts 0, key minima ~0, key maxima 0.
+__global__ void k_fill_pix(uint32_t* __restrict__ cnt, uint32_t* __restrict__ kmin, uint32_t* __restrict__ kmax,
+                           size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        cnt[i] = 0u;
+        kmin[i] = 0xFFFFFFFFu;
+        kmax[i] = 0u;
     }
-    if (t == 1023) start[n] = s_part[1023];
 }
 
 // Multi-block exclusive scan: each 1024-thread block scans kScanChunk counts and leaves its
-// total; the totals are scanned by k_scan; k_scan_add adds each block's base.
+// total; the totals are scanned by k_scan1; k_scan_add adds each block's base.
 __global__ __launch_bounds__(1024) void k_scan_local(const uint32_t* __restrict__ cnt, uint32_t* __restrict__ out,
                                                       uint32_t* __restrict__ part, int n) {
     __shared__ uint32_t s_part[1024];
@@ -488,8 +517,10 @@ __global__ __launch_bounds__(1024) void k_bin_offsets(uint32_t* __restrict__ M, 
 __global__ __launch_bounds__(kBinThreads) void k_scatter(const SegRec* __restrict__ seg, int nseg, int per_block,
                                                          int ntx, int nty, int t0, int nt,
                                                          const uint32_t* __restrict__ tile_start,
-                                                         const uint32_t* __restrict__ M, uint32_t* __restrict__ list) {
+                                                         const uint32_t* __restrict__ M, uint32_t* __restrict__ list,
+                                                         const Counters* __restrict__ ctr) {
     extern __shared__ uint32_t s_tc[];
+    if (ctr->cap_overflow) return;
     const int T = ntx * nty;
     const uint32_t* row = M + (size_t)blockIdx.x * T + t0;
     for (int i = threadIdx.x; i < nt; i += kBinThreads) s_tc[i] = tile_start[t0 + i] + row[i];
@@ -497,6 +528,24 @@ __global__ __launch_bounds__(kBinThreads) void k_scatter(const SegRec* __restric
     const int g0 = blockIdx.x * per_block, g1 = min(nseg, g0 + per_block);
     for (int g = g0 + (int)threadIdx.x; g < g1; g += kBinThreads)
         for_each_tile_in_range(seg[g], ntx, nty, t0, nt, [&](int l) { list[atomicAdd(&s_tc[l], 1u)] = (uint32_t)g; });
+}
+
+// The frame's sizes against the buffers' capacities (one thread).
+__global__ void k_check_caps(FrameBufs f, FrameCaps caps, int stage) {
+    if (threadIdx.x != 0) return;
+    uint32_t over = 0;
+    if (stage == 1) {
+        const uint32_t pairs = f.tile_start[f.T], items = f.item_start[f.T];
+        f.ctr->sizes[0] = pairs;
+        f.ctr->sizes[1] = items;
+        over = (pairs > caps.pairs) || (items > caps.items);
+    } else {
+        const uint32_t frags = f.frag_base[f.T], batches = f.batch_start[f.T];
+        f.ctr->sizes[2] = frags;
+        f.ctr->sizes[3] = batches;
+        over = (frags > caps.frags) || (batches > caps.batches);
+    }
+    if (over) f.ctr->cap_overflow = 1u;
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
@@ -902,13 +951,14 @@ __global__ __launch_bounds__(256) void k_tile_items(const uint32_t* __restrict__
 
 // Count pass: per-pixel fragment counts of each tile.  Each item adds its LDS-aggregated
 // counts to the tile's pixels and keeps the returned base (its slice of every pixel's range).
-__global__ __launch_bounds__(kNT) void k_count(FrameBufs f, CamConst cam, uint32_t n_items) {
+__global__ __launch_bounds__(kNT) void k_count(FrameBufs f, CamConst cam) {
     __shared__ uint32_t s_cnt[kTilePix];
     __shared__ int s_tile;
     __shared__ uint32_t s_chunk;
     PHASE_BEGIN();
-    const uint32_t item = xcd_contiguous(blockIdx.x, gridDim.x);
-    if (item >= n_items) return;
+    const uint32_t n_items = f.item_start[f.T];
+    if (blockIdx.x >= n_items || f.ctr->cap_overflow) return;
+    const uint32_t item = xcd_contiguous(blockIdx.x, n_items);
     const int t = threadIdx.x;
     if (t == 0) {
         int tile;
@@ -996,6 +1046,7 @@ __global__ __launch_bounds__(kNT) void k_tile_prep(FrameBufs f) {
 
 __global__ __launch_bounds__(kNT) void k_batch_records(FrameBufs f) {
     __shared__ uint32_t s_cnt[kTilePix], s_off[kTilePix + 1];
+    if (f.ctr->cap_overflow) return;
     const int tile = blockIdx.x, t = threadIdx.x;
     const size_t q = (size_t)tile * kTilePix + t;
     s_cnt[t] = f.pix_cnt[q];
@@ -1016,13 +1067,14 @@ __global__ __launch_bounds__(kNT) void k_batch_records(FrameBufs f) {
 // Emit pass: every fragment into the frame's fragment buffer at
 // frag_base[tile] + pix_off[pixel] + (the item's slice of the pixel) + local slot, and each
 // pixel's depth-key range (LDS-aggregated per item).
-__global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam, uint32_t n_items) {
+__global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam) {
     __shared__ uint32_t s_cur[kTilePix], s_pos[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix];
     __shared__ int s_tile;
     __shared__ uint32_t s_chunk;
     PHASE_BEGIN();
-    const uint32_t item = xcd_contiguous(blockIdx.x, gridDim.x);
-    if (item >= n_items) return;
+    const uint32_t n_items = f.item_start[f.T];
+    if (blockIdx.x >= n_items || f.ctr->cap_overflow) return;
+    const uint32_t item = xcd_contiguous(blockIdx.x, n_items);
     const int t = threadIdx.x;
     if (t == 0) {
         int tile;
@@ -1404,7 +1456,9 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3))) void k
                 reinterpret_cast<float*>(s_work), s_agg, s_aggh};
     PHASE_BEGIN();
 
-    const uint4 br = f.batches[xcd_contiguous(blockIdx.x, gridDim.x)];
+    const uint32_t n_batches = f.batch_start[f.T];
+    if (blockIdx.x >= n_batches || f.ctr->cap_overflow) return;
+    const uint4 br = f.batches[xcd_contiguous(blockIdx.x, n_batches)];
     const int tile = (int)br.x, p0 = (int)br.y, p1 = (int)br.z;
     const int t = threadIdx.x;
     const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
@@ -1571,7 +1625,9 @@ __global__ __launch_bounds__(kNT) void k_batch_bwd(FrameBufs f, ShadeArgs a, Gra
     uint32_t* s_bk = reinterpret_cast<uint32_t*>(s_work) + 2 * kCap;
     float4* s_p4 = reinterpret_cast<float4*>(s_work);
 
-    const uint4 br = f.batches[xcd_contiguous(blockIdx.x, gridDim.x)];
+    const uint32_t n_batches = f.batch_start[f.T];
+    if (blockIdx.x >= n_batches || f.ctr->cap_overflow) return;
+    const uint4 br = f.batches[xcd_contiguous(blockIdx.x, n_batches)];
     const int tile = (int)br.x, p0 = (int)br.y, p1 = (int)br.z;
     const int t = threadIdx.x;
     if (br.w) return;
@@ -2106,7 +2162,9 @@ __global__ __launch_bounds__(kNT) void k_dom_resolve(FrameBufs f, LevelDev lv, c
     // give the same sums in any order (counts are far below 2^31 hairs; resolution 2^-32)
     __shared__ unsigned long long s_acc[kDomMaxLayers][kTilePix];
     __shared__ float s_iz0[kTilePix];
-    const uint4 br = f.batches[xcd_contiguous(blockIdx.x, gridDim.x)];
+    const uint32_t n_batches = f.batch_start[f.T];
+    if (blockIdx.x >= n_batches || f.ctr->cap_overflow) return;
+    const uint4 br = f.batches[xcd_contiguous(blockIdx.x, n_batches)];
     const int tile = (int)br.x, p0 = (int)br.y, p1 = (int)br.z;
     const int t = threadIdx.x;
     const int R = grid->R;
@@ -2201,6 +2259,7 @@ hipError_t launch_project_light(const LevelDev& lv, const DomGrid* grid, SegRec*
 
 hipError_t launch_dom_resolve(const FrameBufs& f, const LevelDev& lv, const DomGrid* grid, int32_t K, float delta,
                               int32_t R, uint32_t n_batches, float4* tex, hipStream_t st) {
+    // n_batches: the grid (at least the frame's batch count, which the kernel reads)
     hipError_t e = launch_fill_f32(reinterpret_cast<float*>(tex), 0.0f, 8ull * R * R, st);
     if (e != hipSuccess || n_batches == 0) return e;
     hipLaunchKernelGGL(k_dom_resolve, dim3(n_batches), dim3(kNT), 0, st, f, lv, grid, K, delta, tex);
@@ -2245,21 +2304,22 @@ hipError_t launch_bins(const SegRec* seg, int32_t nseg, const CamConst& cam, con
 }
 
 hipError_t launch_exscan(const uint32_t* cnt, uint32_t* start, int32_t n, uint32_t* scratch, hipStream_t st) {
-    if (n <= kScanChunk) {
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cnt, start, n);
+    if (n <= kScanOneBlock) {
+        hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, st, cnt, start, n);
         return hipGetLastError();
     }
     const int nb = (n + kScanChunk - 1) / kScanChunk;
     uint32_t* part = scratch;            // [nb]
     uint32_t* base = scratch + nb + 1;   // [nb + 1]
     hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(1024), 0, st, cnt, start, part, n);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, part, base, nb);
+    hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, st, part, base, nb);
     hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(1024), 0, st, start, base, n, nb);
     return hipGetLastError();
 }
 
 hipError_t launch_scatter(const SegRec* seg, int32_t nseg, const CamConst& cam, const BinPlan& p,
-                          const uint32_t* tile_start, const uint32_t* M, uint32_t* list, hipStream_t st) {
+                          const uint32_t* tile_start, const uint32_t* M, uint32_t* list, const Counters* ctr,
+                          hipStream_t st) {
     if (nseg == 0) return hipSuccess;
     const int ntx = (cam.W + kTile - 1) / kTile, nty = (cam.H + kTile - 1) / kTile, T = ntx * nty;
     hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_scatter), 4 * p.range);
@@ -2267,7 +2327,7 @@ hipError_t launch_scatter(const SegRec* seg, int32_t nseg, const CamConst& cam, 
     for (int t0 = 0; t0 < T; t0 += p.range) {
         const int nt = std::min(p.range, T - t0);
         hipLaunchKernelGGL(k_scatter, dim3(p.nb), dim3(kBinThreads), 4 * nt, st, seg, nseg, p.per_block, ntx, nty, t0,
-                           nt, tile_start, M, list);
+                           nt, tile_start, M, list, ctr);
     }
     return hipGetLastError();
 }
@@ -2277,9 +2337,9 @@ hipError_t launch_tile_items(const uint32_t* tile_start, int T, uint32_t* items,
     return hipGetLastError();
 }
 
-hipError_t launch_count(const FrameBufs& f, const CamConst& cam, uint32_t n_items, hipStream_t st) {
-    if (n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_count, dim3(n_items), dim3(kNT), 0, st, f, cam, n_items);
+hipError_t launch_count(const FrameBufs& f, const CamConst& cam, uint32_t grid, hipStream_t st) {
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count, dim3(grid), dim3(kNT), 0, st, f, cam);
     return hipGetLastError();
 }
 
@@ -2293,14 +2353,15 @@ hipError_t launch_batch_records(const FrameBufs& f, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_emit(const FrameBufs& f, const CamConst& cam, uint32_t n_items, hipStream_t st) {
-    if (n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_emit, dim3(n_items), dim3(kNT), 0, st, f, cam, n_items);
+hipError_t launch_emit(const FrameBufs& f, const CamConst& cam, uint32_t grid, hipStream_t st) {
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_emit, dim3(grid), dim3(kNT), 0, st, f, cam);
     return hipGetLastError();
 }
 
 hipError_t launch_batches(const FrameBufs& f, const LevelDev& lv, const CamConst& cam, const LightsConst& lights,
                           const MatConst& mat, uint32_t n_batches, float* rgba, const DebugDump* dbg, hipStream_t st) {
+    // n_batches: the grid (at least the frame's batch count, which the kernels read)
     if (n_batches == 0) return hipSuccess;
     ShadeArgs a;
     a.cam = cam;
@@ -2401,6 +2462,18 @@ hipError_t launch_build_ellipses(const float* vx, const float* vy, const float* 
                                  const float* cz, const float* r, float* ahat, float* axes, hipStream_t st) {
     hipLaunchKernelGGL(k_build_ellipses, dim3(blocks_for((size_t)K * (V - 1), 128)), dim3(128), 0, st, vx, vy, vz, V,
                        members, member_start, K, cx, cy, cz, r, ahat, axes);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_caps(const FrameBufs& f, const FrameCaps& caps, int stage, hipStream_t st) {
+    hipLaunchKernelGGL(k_check_caps, dim3(1), dim3(64), 0, st, f, caps, stage);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_pix(uint32_t* cnt, uint32_t* kmin, uint32_t* kmax, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const int nb = (int)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_pix, dim3(nb), dim3(256), 0, st, cnt, kmin, kmax, n);
     return hipGetLastError();
 }
 
