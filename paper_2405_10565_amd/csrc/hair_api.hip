@@ -82,7 +82,7 @@ struct hair_ws {
     uint64_t held = 0;
     DevBuf seg, shade, scan_tmp, tile_cnt, tile_start, bin_m, bin_blk, list, ctr, sel_cnt, sel_start, sel, sel_tmp;
     DevBuf items, item_start, item_base, pix_cnt, pix_kmin, pix_kmax, pix_off;
-    DevBuf tile_tot, frag_base, tile_nb, batch_start, batches, frags;
+    DevBuf tile_tot, frag_base, tile_nb, batch_mask, batch_start, batches, frags;
     DevBuf dom_tex, dom_grid, dom_part;      // shadow pass: texels, grids, bounds partials
     int32_t dom_R = 0, dom_K = 0, dom_n = 0;  // last shadowed render: resolution, layers, maps
     int32_t dom_light[HAIR_MAX_LIGHTS] = {};  // map index of each light, -1 if unshadowed
@@ -472,6 +472,7 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
         if ((rc = ws_need(ws, *b, 4 * TP))) return rc;
     for (DevBuf* b : {&ws->tile_tot, &ws->tile_nb})
         if ((rc = ws_need(ws, *b, 4ull * T))) return rc;
+    if ((rc = ws_need(ws, ws->batch_mask, 4ull * T * (kTilePix / 32)))) return rc;
     for (DevBuf* b : {&ws->frag_base, &ws->batch_start})
         if ((rc = ws_need(ws, *b, 4ull * (T + 1)))) return rc;
     FrameBufs f;
@@ -490,6 +491,7 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     f.pix_off = ws->pix_off.as<uint32_t>();
     f.tile_tot = ws->tile_tot.as<uint32_t>();
     f.tile_nb = ws->tile_nb.as<uint32_t>();
+    f.batch_mask = ws->batch_mask.as<uint32_t>();
     f.frag_base = ws->frag_base.as<uint32_t>();
     f.batch_start = ws->batch_start.as<uint32_t>();
     f.ctr = ws->ctr.as<Counters>();
@@ -647,7 +649,8 @@ int hair_ws_destroy(hair_ws* ws) {
     if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
     for (DevBuf* b : {&ws->seg, &ws->shade, &ws->scan_tmp, &ws->tile_cnt, &ws->tile_start, &ws->bin_m, &ws->bin_blk, &ws->sel_cnt, &ws->sel_start, &ws->sel, &ws->sel_tmp, &ws->list, &ws->ctr, &ws->items,
                       &ws->item_start, &ws->item_base, &ws->pix_cnt, &ws->pix_kmin, &ws->pix_kmax, &ws->pix_off,
-                      &ws->tile_tot, &ws->frag_base, &ws->tile_nb, &ws->batch_start, &ws->batches, &ws->frags,
+                      &ws->tile_tot, &ws->frag_base, &ws->tile_nb, &ws->batch_mask, &ws->batch_start, &ws->batches,
+                      &ws->frags,
                       &ws->dom_tex, &ws->dom_grid, &ws->dom_part})
         ctx_free(ctx, *b, ws);
     if (ws->events)
@@ -671,7 +674,7 @@ uint64_t hair_ws_estimate(int64_t n_segments, int32_t width, int32_t height, int
     const uint64_t raw = (sizeof(SegRec) + sizeof(ShadeRec)) * (uint64_t)std::max<int64_t>(n_segments, 1) +
                          4ull * (2 * T + 1) + 20ull * bin_nb * T +
                          4ull * (2 * T + 2) + 4 * P + 4ull * kTilePix * items +
-                         4ull * 4 * T * kTilePix + 4ull * 4 * (T + 1) + 8 * frags + 16 * (T + frags / 512) +
+                         4ull * 4 * T * kTilePix + 4ull * 4 * (T + 1) + 32 * T + 8 * frags + 16 * (T + frags / 512) +
                          sizeof(Counters) + 4 * exscan_scratch_words(T);
     return raw + raw / 4 + 24 * 256;
 }

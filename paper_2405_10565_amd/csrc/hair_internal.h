@@ -186,6 +186,7 @@ struct FrameBufs {
     uint32_t* pix_off;            // [T][kTilePix] exclusive prefix of pix_cnt within the tile
     uint32_t* tile_tot;           // [T] fragments per tile
     uint32_t* tile_nb;            // [T] batches per tile
+    uint32_t* batch_mask;         // [T][kTilePix / 32] pixels that start a batch
     const uint32_t* frag_base;    // [T + 1] exclusive scan of tile_tot
     const uint32_t* batch_start;  // [T + 1] exclusive scan of tile_nb
     uint4* batches;               // [batches]: (tile, p0, p1, oversized)

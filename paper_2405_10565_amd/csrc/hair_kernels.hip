@@ -988,37 +988,16 @@ __global__ __launch_bounds__(kNT) void k_count(FrameBufs f, CamConst cam) {
 }
 
 // Greedy batch packing of whole pixels: from p0 skip empty pixels, then take the longest run
-// [p0, p1) whose fragments fit one LDS batch.  A pixel deeper than a batch is "oversized".
-__device__ inline bool next_batch(const uint32_t* s_cnt, const uint32_t* s_off, int& p0, int& p1, bool& oversized) {
-    if (p0 >= kTilePix) return false;
-    if (s_cnt[p0] == 0) {   // next non-empty pixel: the last q with s_off[q] == s_off[p0]
-        const uint32_t o = s_off[p0];
-        if (s_off[kTilePix] == o) return false;
-        int lo = p0, hi = kTilePix - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] == o) lo = mid; else hi = mid - 1;
-        }
-        p0 = lo;
-    }
-    oversized = s_cnt[p0] > (uint32_t)kCap;
-    if (oversized) {
-        p1 = p0 + 1;
-        return true;
-    }
-    int lo = p0 + 1, hi = kTilePix;
-    const uint32_t o0 = s_off[p0];
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_off[mid] - o0 <= (uint32_t)kCap) lo = mid; else hi = mid - 1;
-    }
-    p1 = lo;
-    return true;
-}
-
-// Per tile: pixel offsets, fragment total and number of batches.
+// [p0, p1) whose fragments fit one LDS batch; a pixel deeper than a batch is "oversized" and
+// forms a batch of its own.  Every lane finds, in parallel, the next non-empty pixel at or
+// after it and the end of a batch that would start at it; one lane then follows the chain of
+// batch starts and marks them in a 256-bit mask of the tile.  k_batch_records turns the mask
+// into the batch table in parallel (a batch runs to the next start, or to the tile's end: the
+// pixels in between are empty).
 __global__ __launch_bounds__(kNT) void k_tile_prep(FrameBufs f) {
     __shared__ uint32_t s_cnt[kTilePix], s_off[kTilePix + 1], s_tmp[kNT];
+    __shared__ uint16_t s_nxt[kTilePix + 1], s_end[kTilePix];
+    __shared__ uint32_t s_mask[kTilePix / 32];
     const int tile = blockIdx.x, t = threadIdx.x;
     const size_t q = (size_t)tile * kTilePix + t;
     const uint32_t c = f.pix_cnt[q];
@@ -1028,40 +1007,70 @@ __global__ __launch_bounds__(kNT) void k_tile_prep(FrameBufs f) {
     s_off[t] = ex;
     f.pix_off[q] = ex;
     if (t == 0) s_off[kTilePix] = total;
+    if (t < kTilePix / 32) s_mask[t] = 0u;
+    __syncthreads();
+    {   // next non-empty pixel q >= t: the smallest q with s_off[q + 1] > s_off[t]
+        int lo = t, hi = kTilePix;
+        const uint32_t o = s_off[t];
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (s_off[mid + 1] > o) hi = mid; else lo = mid + 1;
+        }
+        s_nxt[t] = (uint16_t)lo;
+    }
+    if (c > (uint32_t)kCap) {
+        s_end[t] = (uint16_t)(t + 1);
+    } else {   // the largest p1 with s_off[p1] - s_off[t] <= kCap
+        int lo = t + 1, hi = kTilePix;
+        const uint32_t o0 = s_off[t];
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] - o0 <= (uint32_t)kCap) lo = mid; else hi = mid - 1;
+        }
+        s_end[t] = (uint16_t)lo;
+    }
+    if (t == 0) s_nxt[kTilePix] = (uint16_t)kTilePix;
     __syncthreads();
     if (t == 0) {
-        f.tile_tot[tile] = total;
         uint32_t nb = 0, over = 0;
-        int p0 = 0, p1;
-        bool oversized;
-        while (next_batch(s_cnt, s_off, p0, p1, oversized)) {
+        for (int p = s_nxt[0]; p < kTilePix; p = s_nxt[s_end[p]]) {
+            s_mask[p >> 5] |= 1u << (p & 31);
             ++nb;
-            over += oversized;
-            p0 = p1;
+            over += s_cnt[p] > (uint32_t)kCap;
         }
+        f.tile_tot[tile] = total;
         f.tile_nb[tile] = nb;
         if (over) atomicAdd(&f.ctr->deep_pixels, over);
     }
+    __syncthreads();
+    if (t < kTilePix / 32) f.batch_mask[(size_t)tile * (kTilePix / 32) + t] = s_mask[t];
 }
 
+// The batch table: one record (tile, first pixel, end pixel, oversized) per marked start, in
+// pixel order, at the tile's batch offset.
 __global__ __launch_bounds__(kNT) void k_batch_records(FrameBufs f) {
-    __shared__ uint32_t s_cnt[kTilePix], s_off[kTilePix + 1];
+    __shared__ uint32_t s_mask[kTilePix / 32];
     if (f.ctr->cap_overflow) return;
     const int tile = blockIdx.x, t = threadIdx.x;
-    const size_t q = (size_t)tile * kTilePix + t;
-    s_cnt[t] = f.pix_cnt[q];
-    s_off[t] = f.pix_off[q];
-    if (t == 0) s_off[kTilePix] = f.tile_tot[tile];
+    if (t < kTilePix / 32) s_mask[t] = f.batch_mask[(size_t)tile * (kTilePix / 32) + t];
     __syncthreads();
-    if (t == 0) {
-        uint32_t b = f.batch_start[tile];
-        int p0 = 0, p1;
-        bool oversized;
-        while (next_batch(s_cnt, s_off, p0, p1, oversized)) {
-            f.batches[b++] = make_uint4((uint32_t)tile, (uint32_t)p0, (uint32_t)p1, oversized ? 1u : 0u);
-            p0 = p1;
-        }
+    const int w = t >> 5, b = t & 31;
+    if (!((s_mask[w] >> b) & 1u)) return;
+    uint32_t idx = __popc(s_mask[w] & ((1u << b) - 1u));
+    for (int k = 0; k < w; ++k) idx += __popc(s_mask[k]);
+    int end = kTilePix;
+    const uint32_t above = b == 31 ? 0u : (s_mask[w] >> (b + 1));
+    if (above) {
+        end = t + 1 + __ffs(above) - 1;
+    } else {
+        for (int k = w + 1; k < kTilePix / 32; ++k)
+            if (s_mask[k]) {
+                end = 32 * k + __ffs(s_mask[k]) - 1;
+                break;
+            }
     }
+    const bool oversized = f.pix_cnt[(size_t)tile * kTilePix + t] > (uint32_t)kCap;
+    f.batches[f.batch_start[tile] + idx] = make_uint4((uint32_t)tile, (uint32_t)t, (uint32_t)end, oversized ? 1u : 0u);
 }
 
 // Emit pass: every fragment into the frame's fragment buffer at
