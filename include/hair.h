@@ -103,7 +103,7 @@ typedef struct hair_stats {
     uint32_t batches;            /* LDS batches of the frame */
 } hair_stats;
 
-#define HAIR_PIXEL_CAPACITY 2048   /* fragments per LDS batch */
+#define HAIR_PIXEL_CAPACITY 1536   /* fragments per LDS batch */
 #define HAIR_TILE 16               /* tile edge (pixels) */
 
 /* Library version (major * 10000 + minor * 100 + patch). */

@@ -19,7 +19,7 @@ LIB_PATH = os.environ.get("HAIR_LIBRARY", os.path.join(HERE, "libhair.so"))
 
 HAIR_OK, HAIR_EINVAL, HAIR_ENOMEM, HAIR_ENOENT, HAIR_EDEVICE, HAIR_ERANGE = 0, -1, -2, -3, -4, -5
 HAIR_MAX_LIGHTS = 8
-HAIR_PIXEL_CAPACITY = 2048
+HAIR_PIXEL_CAPACITY = 1536
 HAIR_TILE = 16
 
 EXPORTS = [

@@ -1448,9 +1448,10 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
 // pixel deeper than one batch (its own "oversized" batch) is processed in depth-key slices:
 // a histogram over the pixel's key range picks the longest run of bins that fits LDS, those
 // records are gathered and processed exactly, and the slice composites chain front to back.
-// (LDS holds three blocks per CU; the register budget is kept at the same three waves per SIMD.)
+// (LDS holds four blocks per CU; unshadowed strand instances keep their registers within four waves
+// per SIMD, the heavier shading (thick hairs, shadowed strands) within three.)
 template <int KIND, int MODEL, bool SHADOW>
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(3))) void k_batch(
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 && !SHADOW ? 4 : 3))) void k_batch(
     FrameBufs f, ShadeArgs a, float* __restrict__ rgba, DebugDump dbg, int has_dbg) {
     __shared__ uint32_t s_cnt[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix], s_off[kTilePix + 1];
     __shared__ uint32_t s_tmp[kNT];

@@ -273,7 +273,7 @@ def test_config2_full_size_sampled(hip, ctx):
 
 
 def test_pixels_deeper_than_one_batch(hip, ctx):
-    """A dense asset seen small: pixels hold more fragments than one LDS batch (2048) and are
+    """A dense asset seen small: pixels hold more fragments than one LDS batch (1536) and are
     rendered in exact depth-key slices; radiance and count still match the oracle."""
     print("case: deep pixels", flush=True)
     asset = hs.make_asset(12000, 16, 60.0, seed=31)
@@ -281,10 +281,11 @@ def test_pixels_deeper_than_one_batch(hip, ctx):
     lights = hs.default_lights(asset, with_point=True)
     ref, ras = R.render(R.strand_level(asset), cam, lights, mat_of(asset))
     depth = np.bincount(ras.pix, minlength=cam.width * cam.height)
-    assert depth.max() > 2048, depth.max()          # at least two key slices
+    cap = hip.HAIR_PIXEL_CAPACITY
+    assert depth.max() > cap, depth.max()           # at least two key slices
     aid, ws, img, stats = _render(hip, ctx, asset, cam, lights)
     assert stats["fragments"] == len(ras.seg)
-    assert stats["deep_pixels"] == int((depth > 2048).sum()) and stats["overflow_pixels"] == 0
+    assert stats["deep_pixels"] == int((depth > cap).sum()) and stats["overflow_pixels"] == 0
     assert_radiance(img, ref, what="deep pixels")
     ws.close()
 
