@@ -234,7 +234,7 @@ def main():
                      "tile": round(float(ms_tile.mean()), 4)},
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_LANE_OPS / 1e12, 2),
                      "unit": "Tops/s", "frac": round(achieved / PEAK_LANE_OPS, 4),
-                     "traffic": traffic, "kernel": "k_batch<0, 0>",
+                     "traffic": traffic, "kernel": "k_batch<0, 0, false>",
                      "ops_per_launch": int(ops + TRANS_WEIGHT * trans)},
         "cpu_baseline": None,
     }
