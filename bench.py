@@ -134,6 +134,7 @@ def serve_leg(ctx, n_requests: int, warmup: int = 24, rates=(30.0, 60.0, 120.0))
            "mfragments_s": [], "failed": [], "levels": []}
     for rate in rates:
         srv = S.Server(ctx, assets, n_slots=4, scratch_budget=32 << 30)
+        srv.prewarm()
         reqs = S.make_requests(sorted(assets), n_requests + warmup, seed=int(rate))
         r = S.summarize(S.run_poisson(srv, reqs, rate, seed=int(rate), warmup=warmup), rate)
         srv.close()

@@ -93,7 +93,13 @@ class Asset:
         return d / np.linalg.norm(d, axis=1, keepdims=True)
 
     def aabb(self):
-        return self.xyz.min(axis=1).astype(np.float64), self.xyz.max(axis=1).astype(np.float64)
+        """(min, max) corners of the vertices, float64; cached per vertex array (assets are not
+        modified in place)."""
+        c = self.__dict__.get("_aabb_cache")
+        if c is None or c[0] is not self.xyz:
+            c = (self.xyz, self.xyz.min(axis=1).astype(np.float64), self.xyz.max(axis=1).astype(np.float64))
+            self.__dict__["_aabb_cache"] = c
+        return c[1], c[2]
 
 
 @dataclass

@@ -99,6 +99,21 @@ class Server:
     def now(self) -> float:
         return time.perf_counter() - self.t0
 
+    def prewarm(self):
+        """Render the largest request class (largest asset, largest resolution, nearest view)
+        once on every slot, so that each slot's workspace keeps buffer capacities for the
+        request mix and served frames are not rendered a second time to grow them."""
+        import torch
+        import hairsynth as hs
+        name = max(self.assets, key=lambda n: self.assets[n].segments_per_level[0])
+        a = self.assets[name]
+        w, h = max(RESOLUTIONS, key=lambda r: r[0] * r[1])
+        cam = hs.camera_occupancy(a.asset, w, h, 0.6, 0.0)
+        for slot in self.slots:
+            out = slot.out[: w * h * 4].view(h, w, 4)
+            self.hctx.render(a.aid, 0, cam, a.lights, out=out, ws=slot.ws, stream=slot.stream)
+        torch.cuda.synchronize()
+
     def footprint(self, req: Request) -> int:
         """Scratch bytes a request may need: workspace upper estimate at the finest level plus
         its output image."""
@@ -274,6 +289,7 @@ def main():
     assets = build_assets(hctx)
     for rate in args.rates:
         srv = Server(hctx, assets, n_slots=args.slots, scratch_budget=int(args.budget_gib * (1 << 30)), lod=args.lod)
+        srv.prewarm()
         reqs = make_requests(sorted(assets), args.requests + args.warmup, seed=int(rate))
         res = summarize(run_poisson(srv, reqs, rate, seed=int(rate), warmup=args.warmup), rate)
         res["peak_in_flight"] = srv.peak_in_flight
