@@ -291,7 +291,10 @@ int hair_debug_dom(hair_ws* ws, int32_t light, float* texels, float* grid);
 /* Test export of composited fragment lists: renders like hair_render and, for pixels in
  * [x0, x0 + w) x [y0, y0 + h), writes per pixel its fragment count (host uint[h][w]) and
  * its fragments in compositing order (host arrays of cap entries, pixels row-major):
- * key uint, segment id uint, alpha float, offset h float.  HAIR_ERANGE if cap is short. */
+ * key uint, segment id uint, alpha float, offset h float.  A pixel's dump holds at most
+ * max(HAIR_PIXEL_CAPACITY, cap / (w h)) fragments (device scratch of that many entries per
+ * pixel).  HAIR_ERANGE if cap or a pixel's room is short, or if a pixel of the frame exceeded
+ * the capacity at one depth key. */
 int hair_debug_fragments(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level,
                          const hair_camera* cam, const hair_light* lights, int32_t n_lights,
                          int32_t x0, int32_t y0, int32_t w, int32_t h, uint32_t* counts,

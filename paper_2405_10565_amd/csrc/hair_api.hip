@@ -567,9 +567,10 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     out->ms[0] = t06; out->ms[1] = t05; out->ms[2] = 0.0f; out->ms[3] = t56;
     out->n_batches = n_batches;
 #ifdef HAIR_PHASE_STATS
-    fprintf(stderr, "phase cycles: count %llu emit %llu sort %llu shade %llu blend %llu load %llu | batches %u items %u\n",
-            out->ctr.phase[0], out->ctr.phase[1], out->ctr.phase[2], out->ctr.phase[3], out->ctr.phase[4], out->ctr.phase[5], n_batches,
-            out->ctr.sizes[1]);
+    fprintf(stderr, "phase cycles: count %llu emit %llu sort %llu shade %llu blend %llu load %llu deep-slicing %llu | "
+            "deep fragments %llu batches %u items %u\n",
+            out->ctr.phase[0], out->ctr.phase[1], out->ctr.phase[2], out->ctr.phase[3], out->ctr.phase[4], out->ctr.phase[5],
+            out->ctr.phase[6], out->ctr.phase[7], n_batches, out->ctr.sizes[1]);
 #endif
     return HAIR_OK;
 }
@@ -1411,7 +1412,8 @@ int hair_debug_fragments(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t leve
     ws = ws_or_default(ctx, ws);
     std::lock_guard<std::mutex> g(ws->mu);
     const int npx = w * h;
-    const int stride = (int)std::min<int64_t>(cap, (int64_t)kCap);
+    // per-pixel room in the dump: a batch's worth, or an even share of cap when that is larger
+    const int stride = (int)std::min<int64_t>(cap, std::max<int64_t>((int64_t)kCap, std::min<int64_t>(cap / (w * h), 1 << 24)));
     DevBuf img, dc, dk, ds, da, dh;
     const size_t ent = (size_t)npx * stride;
     auto cleanup = [&]() { for (DevBuf* b : {&img, &dc, &dk, &ds, &da, &dh}) ctx_free(ctx, *b); };

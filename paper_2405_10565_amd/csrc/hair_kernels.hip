@@ -925,9 +925,13 @@ __device__ inline uint32_t block_exscan_u32(uint32_t v, uint32_t* s_tmp, uint32_
         if (threadIdx.x == 0) atomicAdd(&(ctr)->phase[i], wall_clock64() - ph_t0); \
         ph_t0 = wall_clock64();                                                \
     } while (0)
+#define PHASE_RESET() ph_t0 = wall_clock64()
+#define PHASE_ADD(ctr, i, v) do { if (threadIdx.x == 0) atomicAdd(&(ctr)->phase[i], (unsigned long long)(v)); } while (0)
 #else
 #define PHASE_BEGIN() do {} while (0)
 #define PHASE_END(ctr, i) do {} while (0)
+#define PHASE_RESET() do {} while (0)
+#define PHASE_ADD(ctr, i, v) do {} while (0)
 #endif
 
 // Work items of the count and emit kernels: chunks of kNT consecutive entries of a tile list.
@@ -1502,29 +1506,63 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 &
     float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;   // carried composite (thread 0)
     uint32_t done = 0;
     constexpr uint32_t kBins = kCap;            // histogram in s_bk
+    PHASE_ADD(f.ctr, 7, k);
+    PHASE_END(f.ctr, 5);
     while (lo < key_end) {
         unsigned long long range_hi = key_end;
-        // refine until a run of whole bins starting at lo fits one batch
+        // refine until a run of whole bins starting at lo fits one batch.  Keys are 32-bit, so
+        // lo < 2^32, the bin width stays below 2^22 and bins are exact 32-bit quotients.
         while (true) {
             const unsigned long long width = (range_hi - lo + kBins - 1) / kBins;
+            const uint32_t lo32 = (uint32_t)lo, w32 = (uint32_t)width;
             for (uint32_t i = t; i < kBins; i += kNT) L_.s_bk[i] = 0;
             __syncthreads();
-            for (uint32_t i = t; i < k; i += kNT) {
-                const unsigned long long key = src[i].x;
-                if (key >= lo && key < range_hi) atomicAdd(&L_.s_bk[(uint32_t)((key - lo) / width)], 1u);
+            // histogram of the keys in [lo, range_hi); each lane's loads are issued together
+            for (uint32_t i0 = 0; i0 < k; i0 += kNT * kPerThread) {
+                uint32_t kk[kPerThread];
+#pragma unroll
+                for (int qq = 0; qq < kPerThread; ++qq) {
+                    const uint32_t i = i0 + t + qq * kNT;
+                    kk[qq] = i < k ? src[i].x : 0u;
+                }
+#pragma unroll
+                for (int qq = 0; qq < kPerThread; ++qq) {
+                    const uint32_t i = i0 + t + qq * kNT;
+                    if (i < k && kk[qq] >= lo32 && (unsigned long long)kk[qq] < range_hi)
+                        atomicAdd(&L_.s_bk[(kk[qq] - lo32) / w32], 1u);
+                }
             }
             __syncthreads();
-            if (t == 0) {
-                uint32_t acc = 0, nb = 0;
+            // the longest run of leading bins holding at most kCap keys, from a block scan of
+            // the bin counts (lane t owns bins t * kPerThread ...): the one lane that owns the
+            // run's last bin writes the slice; lane 0 flags a first bin that alone exceeds kCap
+            {
                 const uint32_t used = (uint32_t)((range_hi - lo + width - 1) / width);
-                while (nb < used && acc + L_.s_bk[nb] <= (uint32_t)kCap) acc += L_.s_bk[nb++];
-                if (nb == 0) {
+                uint32_t loc[kPerThread], sum = 0;
+#pragma unroll
+                for (int qq = 0; qq < kPerThread; ++qq) {
+                    const uint32_t i = t * kPerThread + qq;
+                    loc[qq] = i < used ? L_.s_bk[i] : 0u;
+                    sum += loc[qq];
+                }
+                uint32_t incl;
+                block_exscan_u32(sum, s_tmp, incl);
+#pragma unroll
+                for (int qq = 0; qq < kPerThread; ++qq) {
+                    const uint32_t i = t * kPerThread + qq;
+                    incl += loc[qq];
+                    if (i < used && incl <= (uint32_t)kCap) {
+                        const uint32_t nxt = i + 1 >= used ? 0u : (qq + 1 < kPerThread ? loc[qq + 1] : L_.s_bk[i + 1]);
+                        if (i + 1 >= used || incl + nxt > (uint32_t)kCap) {
+                            s_flag = 0;
+                            s_range[1] = min(range_hi, lo + (unsigned long long)(i + 1) * width);
+                            s_slot = incl;
+                        }
+                    }
+                }
+                if (t == 0 && loc[0] > (uint32_t)kCap) {
                     s_flag = width == 1 ? 2u : 1u;     // 1: refine inside the first bin; 2: equal keys overflow
                     s_range[1] = lo + width;
-                } else {
-                    s_flag = 0;
-                    s_range[1] = min(range_hi, lo + (unsigned long long)nb * width);
-                    s_slot = acc;
                 }
             }
             __syncthreads();
@@ -1541,10 +1579,19 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 &
         __syncthreads();
         if (t == 0) s_slot = 0;
         __syncthreads();
-        for (uint32_t i = t; i < k; i += kNT) {
-            const uint2 rec = src[i];
-            if ((unsigned long long)rec.x >= lo && (unsigned long long)rec.x < range_hi)
-                L_.s_A[atomicAdd(&s_slot, 1u)] = rec;
+        for (uint32_t i0 = 0; i0 < k; i0 += kNT * kPerThread) {
+            uint2 rr[kPerThread];
+#pragma unroll
+            for (int qq = 0; qq < kPerThread; ++qq) {
+                const uint32_t i = i0 + t + qq * kNT;
+                rr[qq] = i < k ? src[i] : make_uint2(0u, 0u);
+            }
+#pragma unroll
+            for (int qq = 0; qq < kPerThread; ++qq) {
+                const uint32_t i = i0 + t + qq * kNT;
+                if (i < k && (unsigned long long)rr[qq].x >= lo && (unsigned long long)rr[qq].x < range_hi)
+                    L_.s_A[atomicAdd(&s_slot, 1u)] = rr[qq];
+            }
         }
         __syncthreads();
         for (uint32_t i = t; i < Fb; i += kNT) L_.s_bk[i] = 0;
@@ -1556,7 +1603,9 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 &
             s_off[p + 1] = Fb;
         }
         __syncthreads();
+        PHASE_END(f.ctr, 6);
         sort_shade_blend<KIND, MODEL, SHADOW>(f, a, rgba, dbg, has_dbg, L_, list, L_.s_A, px0, py0, Fb, s_slice, done, k);
+        PHASE_RESET();
         __syncthreads();
         if (t == 0) {
             C0 += T * s_slice[0];

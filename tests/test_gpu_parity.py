@@ -319,3 +319,98 @@ def test_large_images_binning(hip, ctx, W, H):
     ref, ras = R.render(geom, cam, lights, mat_of(asset), rect=(x0, y0, 24, 24))
     assert_radiance(img[y0:y0 + 24, x0:x0 + 24], ref[y0:y0 + 24, x0:x0 + 24], what=f"{W}x{H} rect")
     ws.close()
+
+
+def _layered_asset(depths, width_px=40, half_extent=0.2):
+    """One horizontal single-segment strand per depth, all crossing pixel row 20 of a 40 x 40
+    camera at the origin looking down -z (fy = fx = 74.6): every covered pixel holds one
+    fragment per strand, with the depth key of that strand's 1 / z."""
+    fy = float(np.float32(74.6))
+    d = np.asarray(depths, dtype=np.float64)
+    n = len(d)
+    y = -0.5 * d / fy                                   # pixel row centre 20.5
+    xyz = np.empty((3, 2 * n), dtype=np.float32)
+    xyz[0, 0::2], xyz[0, 1::2] = -half_extent * d, half_extent * d
+    xyz[1, 0::2] = xyz[1, 1::2] = y
+    xyz[2, 0::2] = xyz[2, 1::2] = -d
+    sig = np.repeat(np.array([0.3, 0.6, 1.2], dtype=np.float32)[:, None], n, axis=1)
+    asset = hs.Asset(n, 1, xyz, np.full(n, 80e-6, dtype=np.float32), np.ascontiguousarray(sig))
+    cam = hs.Camera(np.zeros(3, np.float32), np.eye(3, dtype=np.float32), fy, fy, 20.0, 20.0, width_px, 40, 0.01)
+    return asset, cam
+
+
+def _key_runs(ras, n_pix):
+    """Per pixel: fragment count, and the largest number of fragments sharing one depth key."""
+    depth = np.bincount(ras.pix, minlength=n_pix)
+    same = np.zeros(n_pix, dtype=np.int64)
+    if len(ras.pix):
+        run_start = np.r_[True, (np.diff(ras.pix) != 0) | (np.diff(ras.key.astype(np.int64)) != 0)]
+        ids = np.cumsum(run_start) - 1
+        run_len = np.bincount(ids)
+        np.maximum.at(same, ras.pix[run_start], run_len)
+    return depth, same
+
+
+def test_deep_pixels_with_clustered_keys(hip, ctx):
+    """Pixels of about 5,000 fragments whose keys crowd into a tiny part of their key range:
+    the first histogram over the pixel's range puts more than one batch into one bin, so the
+    slicing refines inside it; several slices chain front to back.  Count and radiance match
+    the oracle."""
+    print("case: deep pixels, clustered keys", flush=True)
+    cap = hip.HAIR_PIXEL_CAPACITY
+    cluster = 1.0 + 3e-7 * np.arange(5000)
+    depths = np.concatenate([np.linspace(0.5, 0.9, 17), cluster, np.linspace(3.0, 10.0, 41)])
+    asset, cam = _layered_asset(depths)
+    lights = hs.default_lights(asset, with_point=False)
+    ref, ras = R.render(R.strand_level(asset), cam, lights, mat_of(asset))
+    depth, same = _key_runs(ras, cam.width * cam.height)
+    deep = np.nonzero(depth > cap)[0]
+    assert len(deep) >= 20 and depth.max() >= 3 * cap and same.max() <= cap
+    # the refinement is exercised: some bin of the first histogram holds more than a batch
+    st = np.r_[0, np.cumsum(depth)]
+    p = deep[0]
+    k = ras.key[st[p]:st[p + 1]].astype(np.int64)
+    width = -(-(int(k.max()) - int(k.min()) + 1) // cap)
+    assert np.bincount((k - k.min()) // width).max() > cap
+    aid, ws, img, stats = _render(hip, ctx, asset, cam, lights)
+    assert stats["fragments"] == len(ras.seg)
+    assert stats["deep_pixels"] == len(deep) and stats["overflow_pixels"] == 0
+    assert_radiance(img, ref, what="deep clustered")
+    # the whole order of the deep row, slice after slice, is the oracle's
+    counts, keys, segs, alpha, hoff = ctx.debug_fragments(aid, 0, cam, lights, 0, 20, 40, 1, cap=40 * 5200)
+    rc, rk, rsg, idx = _oracle_lists(ras, 0, 20, 40, 1, cam.width)
+    assert np.array_equal(counts, rc) and counts.max() == depth.max()
+    assert np.array_equal(keys, rk)
+    assert np.array_equal(segs, rsg)
+    ws.close()
+
+
+def test_pixels_with_one_key_beyond_a_batch_are_flagged(hip, ctx):
+    """More fragments than one batch at a single depth key cannot be ordered in LDS: such
+    pixels are counted in overflow_pixels and left 0; every other pixel matches the oracle."""
+    print("case: equal-key overflow", flush=True)
+    cap = hip.HAIR_PIXEL_CAPACITY
+    asset, cam = _layered_asset(np.concatenate([np.full(cap + 64, 1.0), np.linspace(2.0, 3.0, 5)]),
+                                half_extent=0.1)
+    # a second layer of strands on another row that stays within one batch
+    extra, _ = _layered_asset(np.linspace(1.5, 2.5, 300), half_extent=0.2)
+    extra.xyz[1] += (6.0 * np.linspace(1.5, 2.5, 300) / 74.6).repeat(2).astype(np.float32)
+    n = asset.n_strands + extra.n_strands
+    asset = hs.Asset(n, 1, np.concatenate([asset.xyz, extra.xyz], axis=1),
+                     np.concatenate([asset.width, extra.width]), np.concatenate([asset.sigma_a, extra.sigma_a], axis=1))
+    lights = hs.default_lights(asset, with_point=False)
+    ref, ras = R.render(R.strand_level(asset), cam, lights, mat_of(asset))
+    depth, same = _key_runs(ras, cam.width * cam.height)
+    over = same > cap
+    assert over.sum() >= 10 and ((depth > 0) & ~over).sum() >= 10
+    aid = ctx.upload_asset(asset)
+    ws = ctx.workspace()
+    out, stats, rc = ctx.render(aid, 0, cam, lights, ws=ws, raise_on_error=False)
+    torch.cuda.synchronize()
+    assert rc == hip.HAIR_ERANGE, rc                  # the frame is complete but reports them
+    assert stats["fragments"] == len(ras.seg)
+    assert stats["overflow_pixels"] == int(over.sum())
+    flat = out.cpu().numpy().reshape(-1, 4)
+    assert np.all(flat[over] == 0.0)
+    assert_radiance(flat[~over], ref.reshape(-1, 4)[~over], what="beside overflow pixels")
+    ws.close()
