@@ -189,7 +189,7 @@ struct FrameBufs {
     uint32_t* batch_mask;         // [T][kTilePix / 32] pixels that start a batch
     const uint32_t* frag_base;    // [T + 1] exclusive scan of tile_tot
     const uint32_t* batch_start;  // [T + 1] exclusive scan of tile_nb
-    uint4* batches;               // [batches]: (tile, p0, p1, oversized)
+    uint4* batches;               // [batches]: packed (tile, p0, p1, oversized, first fragment, count), in launch order
     uint2* frags;                 // [fragments]: (depth key, local list index | pixel << 24)
     Counters* ctr;
 };

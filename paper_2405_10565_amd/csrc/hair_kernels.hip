@@ -48,6 +48,36 @@ __device__ inline uint32_t xcd_contiguous(uint32_t b, uint32_t nb) {
     return x * q + min(x, rem) + slot;
 }
 
+// Its inverse on [0, nb): the block that xcd_contiguous sends to index r.
+__device__ inline uint32_t xcd_block_of(uint32_t r, uint32_t nb) {
+    const uint32_t q = nb / 8, rem = nb % 8, big = rem * (q + 1);
+    uint32_t x, slot;
+    if (r < big) {
+        x = r / (q + 1);
+        slot = r - x * (q + 1);
+    } else {   // here q >= 1
+        x = rem + (r - big) / q;
+        slot = (r - big) - (x - rem) * q;
+    }
+    return slot * 8 + x;
+}
+
+// One LDS batch of the shading pass: tile, pixels [p0, p1), oversized (one pixel deeper than
+// a batch), the frame-wide index of its first fragment and its fragment count.  The table is
+// stored in launch order (record b is processed by block b, which keeps the tiles of an XCD
+// contiguous), so a block reads its record without first reading the batch count.
+struct BatchRec {
+    int tile, p0, p1;
+    bool over;
+    uint32_t frag0, nfrag;
+};
+__device__ inline uint4 pack_batch(int tile, int p0, int p1, bool over, uint32_t frag0, uint32_t nfrag) {
+    return make_uint4((uint32_t)tile, (uint32_t)p0 | ((uint32_t)p1 << 9) | (over ? 1u << 18 : 0u), frag0, nfrag);
+}
+__device__ inline BatchRec unpack_batch(const uint4 r) {
+    return BatchRec{(int)r.x, (int)(r.y & 511u), (int)((r.y >> 9) & 511u), ((r.y >> 18) & 1u) != 0, r.z, r.w};
+}
+
 // ---------------------------------------------------------------------------------------
 // Projection (float32, fixed operation order).
 struct PPoint {
@@ -622,9 +652,120 @@ __device__ inline void for_each_fragment(const SegRec& s, int px0, int py0, int 
     }
 }
 
-__device__ inline uint32_t depth_key(const SegRec& s, int tnum, int tden) {
+// Coverage with the work balanced across a wave.  for_each_fragment gives each lane one
+// segment, so a wave runs as long as its longest segment; here a segment's candidate pixels
+// are enumerated one line at a time along its major axis (rows when |dy| >= |dx|, else
+// columns), and the wave's lanes share out all (segment, line) pairs, 64 per round.  A line's
+// span (the minor-axis candidates) comes from the same slab and strip bounds as above, with
+// the axes named u (major) and v (minor): for steep segments the computation is the one above
+// term for term, for shallow ones it is the same with x and y exchanged (|cross| and t_num are
+// symmetric under the exchange), so the integer predicate meets the same candidates.
+struct CovSetup {
+    int4 g0;     // (au, av, du, dv): start and extent along the major and minor axes, 1/16 px
+    int4 g1;     // (R, tden, first line - lines before this lane in the wave, steep)
+    float4 g2;   // (1 / du, 1 / dv or 0, R sqrt(tden) / |du|, bits: first | last minor index << 16)
+};
+constexpr int kCovLinesPerWave = 64 * kTile;   // a segment has at most kTile lines in a tile
+
+// Stages lane t's segment (valid: the lane holds one) in s_cov[t], numbers the wave's lines
+// and records each line's lane in s_own (kCovLinesPerWave bytes per wave); returns the wave's
+// line count.  Ends with a block barrier (all threads must call it).
+__device__ inline uint32_t cov_setup(const SegRec& s, bool valid, int px0, int py0, int W, int H, CovSetup* s_cov,
+                                     uint8_t* s_own) {
+    const int t = threadIdx.x, lane = t & 63;
+    uint32_t nl = 0;
+    CovSetup c{};
+    if (valid) {
+        const int dx = s.xb - s.xa, dy = s.yb - s.ya;
+        const int tden = dx * dx + dy * dy;
+        const int R = (s.hwfx & kHwMask) + 8;
+        const int i0 = max(px0, ((min(s.xa, s.xb) - R - 8) >> 4) + 1);
+        const int i1 = min(min(px0 + kTile, W) - 1, ((max(s.xa, s.xb) + R - 8 + 15) >> 4) - 1);
+        const int j0 = max(py0, ((min(s.ya, s.yb) - R - 8) >> 4) + 1);
+        const int j1 = min(min(py0 + kTile, H) - 1, ((max(s.ya, s.yb) + R - 8 + 15) >> 4) - 1);
+        if (tden > 0 && i0 <= i1 && j0 <= j1) {
+            const bool steep = abs(dy) >= abs(dx);
+            const int au = steep ? s.ya : s.xa, av = steep ? s.xa : s.ya;
+            const int du = steep ? dy : dx, dv = steep ? dx : dy;
+            nl = (uint32_t)(steep ? j1 - j0 + 1 : i1 - i0 + 1);
+            const float inv_du = __builtin_amdgcn_rcpf((float)du);
+            const float inv_dv = dv != 0 ? __builtin_amdgcn_rcpf((float)dv) : 0.0f;
+            const int vmin = steep ? i0 : j0, vmax = steep ? i1 : j1;   // 0 <= vmin <= vmax < 2^16
+            c.g0 = make_int4(au, av, du, dv);
+            c.g1 = make_int4(R, tden, steep ? j0 : i0, steep ? 1 : 0);
+            c.g2 = make_float4(inv_du, inv_dv, (float)R * __builtin_amdgcn_sqrtf((float)tden) * fabsf(inv_du),
+                               __int_as_float(vmin | (vmax << 16)));
+        }
+    }
+    uint32_t x = nl;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    const uint32_t excl = x - nl;
+    c.g1.z -= (int)excl;     // line index = g1.z + the wave-wide line number
+    s_cov[t] = c;
+    uint8_t* own = s_own + (t >> 6) * kCovLinesPerWave;
+    for (uint32_t r = 0; r < nl; ++r) own[excl + r] = (uint8_t)lane;
+    const uint32_t total = __shfl(x, 63);
+    __syncthreads();
+    return total;
+}
+
+// Calls f(li, lj, tnum, tden, owner) for every fragment of the wave's segments in this tile
+// (owner: the block thread whose segment it is).  total and the staging from cov_setup.
+template <class F>
+__device__ inline void wave_coverage(const CovSetup* s_cov, const uint8_t* s_own, uint32_t total, int px0, int py0,
+                                     F&& f) {
+    const int t = threadIdx.x, lane = t & 63, wbase = t & ~63;
+    const uint8_t* own = s_own + (t >> 6) * kCovLinesPerWave;
+    for (uint32_t g = (uint32_t)lane; g < total; g += 64) {
+        const int o = wbase + own[g];
+        const CovSetup c = s_cov[o];
+        const int au = c.g0.x, av = c.g0.y, du = c.g0.z, dv = c.g0.w;
+        const int R = c.g1.x, tden = c.g1.y, u = c.g1.z + (int)g;
+        const bool steep = c.g1.w != 0;
+        const int vb = __float_as_int(c.g2.w);
+        const int vmin = vb & 0xFFFF, vmax = vb >> 16;
+        const unsigned long long RR = (unsigned long long)(unsigned)(R * R) * (unsigned)tden;
+        const int eu = 16 * u + 8 - au;
+        float lo_f = -1e30f, hi_f = 1e30f, mag = fabsf((float)av);
+        if (dv != 0) {
+            const float a = (float)(-eu * du) * c.g2.y;
+            const float b = (float)(tden - eu * du) * c.g2.y;
+            lo_f = fminf(a, b);
+            hi_f = fmaxf(a, b);
+            mag += fmaxf(fabsf(a), fabsf(b));
+        }
+        {
+            const float cc = (float)(eu * dv) * c.g2.x;
+            lo_f = fmaxf(lo_f, cc - c.g2.z);
+            hi_f = fminf(hi_f, cc + c.g2.z);
+            mag += fabsf(cc) + c.g2.z;
+        }
+        const float w = 2e-6f * mag + 1.0f;
+        const float flo = ceilf(((float)av + (lo_f - w) - 8.0f) * (1.0f / 16.0f));
+        const float fhi = floorf(((float)av + (hi_f + w) - 8.0f) * (1.0f / 16.0f));
+        const int k0 = (int)fmaxf((float)vmin, flo);
+        const int k1 = (int)fminf((float)vmax, fhi);
+        const int eu_du = eu * du, eu_dv = eu * dv;
+        for (int k = k0; k <= k1; ++k) {
+            const int ev = 16 * k + 8 - av;
+            const int tnum = ev * dv + eu_du;
+            if (tnum < 0 || tnum >= tden) continue;
+            const int cr = ev * du - eu_dv;
+            const unsigned acr = (unsigned)abs(cr);
+            if ((unsigned long long)acr * acr >= RR) continue;
+            if (steep) f(k - px0, u - py0, tnum, tden, o);
+            else f(u - px0, k - py0, tnum, tden, o);
+        }
+    }
+}
+
+__device__ inline uint32_t depth_key_iz(float iza, float izb, int tnum, int tden) {
     const float t = (float)tnum / (float)tden;
-    const float iz = s.iza + t * (s.izb - s.iza);
+    const float iz = iza + t * (izb - iza);
     return 0xFFFFFFFFu - __float_as_uint(iz);
 }
 
@@ -957,6 +1098,8 @@ __global__ __launch_bounds__(256) void k_tile_items(const uint32_t* __restrict__
 // counts to the tile's pixels and keeps the returned base (its slice of every pixel's range).
 __global__ __launch_bounds__(kNT) void k_count(FrameBufs f, CamConst cam) {
     __shared__ uint32_t s_cnt[kTilePix];
+    __shared__ CovSetup s_cov[kNT];
+    __shared__ uint8_t s_own[kNT / 64 * kCovLinesPerWave];
     __shared__ int s_tile;
     __shared__ uint32_t s_chunk;
     PHASE_BEGIN();
@@ -978,11 +1121,11 @@ __global__ __launch_bounds__(kNT) void k_count(FrameBufs f, CamConst cam) {
     const uint32_t lstart = f.tile_start[tile];
     const uint32_t n = f.tile_start[tile + 1] - lstart;
     const uint32_t j = s_chunk * kNT + t;
-    if (j < n) {
-        const SegRec s = f.seg[f.list[lstart + j]];
-        for_each_fragment(s, px0, py0, 0, kTile - 1, cam.W, cam.H,
-                          [&](int li, int lj, int, int, int) { atomicAdd(&s_cnt[lj * kTile + li], 1u); });
-    }
+    SegRec s{};
+    if (j < n) s = f.seg[f.list[lstart + j]];
+    const uint32_t total = cov_setup(s, j < n, px0, py0, cam.W, cam.H, s_cov, s_own);
+    wave_coverage(s_cov, s_own, total, px0, py0,
+                  [&](int li, int lj, int, int, int) { atomicAdd(&s_cnt[lj * kTile + li], 1u); });
     __syncthreads();
     const size_t q = (size_t)tile * kTilePix + t;
     uint32_t base = 0;
@@ -1073,8 +1216,12 @@ __global__ __launch_bounds__(kNT) void k_batch_records(FrameBufs f) {
                 break;
             }
     }
-    const bool oversized = f.pix_cnt[(size_t)tile * kTilePix + t] > (uint32_t)kCap;
-    f.batches[f.batch_start[tile] + idx] = make_uint4((uint32_t)tile, (uint32_t)t, (uint32_t)end, oversized ? 1u : 0u);
+    const size_t tq = (size_t)tile * kTilePix;
+    const bool oversized = f.pix_cnt[tq + t] > (uint32_t)kCap;
+    const uint32_t off0 = f.pix_off[tq + t];
+    const uint32_t off1 = end < kTilePix ? f.pix_off[tq + end] : f.tile_tot[tile];
+    f.batches[xcd_block_of(f.batch_start[tile] + idx, f.batch_start[f.T])] =
+        pack_batch(tile, t, end, oversized, f.frag_base[tile] + off0, off1 - off0);
 }
 
 // Emit pass: every fragment into the frame's fragment buffer at
@@ -1082,6 +1229,9 @@ __global__ __launch_bounds__(kNT) void k_batch_records(FrameBufs f) {
 // pixel's depth-key range (LDS-aggregated per item).
 __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam) {
     __shared__ uint32_t s_cur[kTilePix], s_pos[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix];
+    __shared__ CovSetup s_cov[kNT];
+    __shared__ uint8_t s_own[kNT / 64 * kCovLinesPerWave];
+    __shared__ float2 s_iz[kNT];
     __shared__ int s_tile;
     __shared__ uint32_t s_chunk;
     PHASE_BEGIN();
@@ -1108,17 +1258,20 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam) {
     const uint32_t lstart = f.tile_start[tile];
     const uint32_t n = f.tile_start[tile + 1] - lstart;
     const uint32_t j = s_chunk * kNT + t;
-    if (j < n) {
-        const SegRec s = f.seg[f.list[lstart + j]];
-        for_each_fragment(s, px0, py0, 0, kTile - 1, cam.W, cam.H, [&](int li, int lj, int tnum, int tden, int) {
-            const int p = lj * kTile + li;
-            const uint32_t key = depth_key(s, tnum, tden);
-            const uint32_t slot = atomicAdd(&s_cur[p], 1u);
-            atomicMin(&s_kmin[p], key);
-            atomicMax(&s_kmax[p], key);
-            f.frags[s_pos[p] + slot] = make_uint2(key, j | ((uint32_t)p << 24));
-        });
-    }
+    SegRec s{};
+    if (j < n) s = f.seg[f.list[lstart + j]];
+    s_iz[t] = make_float2(s.iza, s.izb);
+    const uint32_t total = cov_setup(s, j < n, px0, py0, cam.W, cam.H, s_cov, s_own);
+    const uint32_t j0 = s_chunk * kNT;
+    wave_coverage(s_cov, s_own, total, px0, py0, [&](int li, int lj, int tnum, int tden, int o) {
+        const int p = lj * kTile + li;
+        const float2 iz = s_iz[o];
+        const uint32_t key = depth_key_iz(iz.x, iz.y, tnum, tden);
+        const uint32_t slot = atomicAdd(&s_cur[p], 1u);
+        atomicMin(&s_kmin[p], key);
+        atomicMax(&s_kmax[p], key);
+        f.frags[s_pos[p] + slot] = make_uint2(key, (j0 + (uint32_t)o) | ((uint32_t)p << 24));
+    });
     __syncthreads();
     if (s_cur[t]) {
         atomicMin(&f.pix_kmin[q], s_kmin[t]);
@@ -1134,17 +1287,11 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam) {
 // bucket order in s_A, and each record's place inside its bucket is its rank there by
 // (key, segment id), which is unique within a pixel.  s_bk must hold Fb zeros on entry.
 // Ends with a barrier.
-__device__ inline void order_batch(uint32_t Fb, const uint2* src, const uint32_t* s_cnt, const uint32_t* s_kmin,
-                                   const uint32_t* s_kmax, const uint32_t* s_off, uint32_t* s_tmp, uint2* s_A,
-                                   uint2* s_B, uint32_t* s_bk, const uint32_t* list) {
+__device__ inline void order_batch(uint32_t Fb, const uint2 (&rec)[kPerThread], const uint32_t* s_cnt,
+                                   const uint32_t* s_kmin, const uint32_t* s_kmax, const uint32_t* s_off,
+                                   uint32_t* s_tmp, uint2* s_A, uint2* s_B, uint32_t* s_bk, const uint32_t* list) {
     const int t = threadIdx.x;
-    uint2 rec[kPerThread];
     uint32_t my_b[kPerThread], my_r[kPerThread];
-#pragma unroll
-    for (int qq = 0; qq < kPerThread; ++qq) {
-        const uint32_t i = t + qq * kNT;
-        if (i < Fb) rec[qq] = src[i];
-    }
 #pragma unroll
     for (int qq = 0; qq < kPerThread; ++qq) {
         const uint32_t i = t + qq * kNT;
@@ -1297,7 +1444,7 @@ struct BatchLds {
 template <int KIND, int MODEL, bool SHADOW>
 __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, float* __restrict__ rgba,
                                         const DebugDump& dbg, int has_dbg, const BatchLds& L_, const uint32_t* list,
-                                        const uint2* src, int px0, int py0, uint32_t Fb, float* slice_out,
+                                        const uint2 (&rec)[kPerThread], int px0, int py0, uint32_t Fb, float* slice_out,
                                         uint32_t rank0, uint32_t cnt_total) {
     uint32_t* s_cnt = L_.s_cnt;
     uint32_t* s_kmin = L_.s_kmin;
@@ -1313,7 +1460,7 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
     const int t = threadIdx.x;
     const int W = a.cam.W, H = a.cam.H;
     PHASE_BEGIN();
-    order_batch(Fb, src, s_cnt, s_kmin, s_kmax, s_off, s_tmp, s_A, s_B, s_bk, list);
+    order_batch(Fb, rec, s_cnt, s_kmin, s_kmax, s_off, s_tmp, s_A, s_B, s_bk, list);
     PHASE_END(f.ctr, 2);
     // ---- shade: one lane per fragment, payload alpha * L and (1 - alpha).  A lane's fragments
     // are i = t, t + kNT, ...: their segment ids are gathered up front (independent loads), and
@@ -1471,36 +1618,44 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 &
     PHASE_BEGIN();
 
     const uint32_t n_batches = f.batch_start[f.T];
+    const uint4 br = f.batches[blockIdx.x];   // in the table's capacity; used only below n_batches
     if (blockIdx.x >= n_batches || f.ctr->cap_overflow) return;
-    const uint4 br = f.batches[xcd_contiguous(blockIdx.x, n_batches)];
-    const int tile = (int)br.x, p0 = (int)br.y, p1 = (int)br.z;
+    const BatchRec b = unpack_batch(br);
+    const int tile = b.tile, p0 = b.p0, p1 = b.p1;
     const int t = threadIdx.x;
     const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
     const int W = a.cam.W, H = a.cam.H;
     const uint32_t* list = f.list + f.tile_start[tile];
     const size_t q = (size_t)tile * kTilePix + t;
-    const uint32_t tile_off0 = f.pix_off[(size_t)tile * kTilePix + p0];
-    const uint2* src = f.frags + f.frag_base[tile] + tile_off0;
-    if (!br.w) {
+    const uint2* src = f.frags + b.frag0;
+    if (!b.over) {
+        // the batch's records, its pixels' counts, key ranges and offsets: all loads in flight
+        // together before the first barrier
+        const uint32_t Fb = b.nfrag;
+        uint2 rec[kPerThread];
+#pragma unroll
+        for (int qq = 0; qq < kPerThread; ++qq) {
+            const uint32_t i = t + qq * kNT;
+            if (i < Fb) rec[qq] = src[i];
+        }
+        const uint32_t tile_off0 = f.pix_off[(size_t)tile * kTilePix + p0];
         if (t >= p0 && t < p1) {
             s_cnt[t] = f.pix_cnt[q];
             s_kmin[t] = f.pix_kmin[q];
             s_kmax[t] = f.pix_kmax[q];
             s_off[t] = f.pix_off[q] - tile_off0;
         }
-        if (t == 0) s_off[p1] = (p1 < kTilePix ? f.pix_off[(size_t)tile * kTilePix + p1] : f.tile_tot[tile]) - tile_off0;
-        __syncthreads();
-        const uint32_t Fb = s_off[p1];
+        if (t == 0) s_off[p1] = Fb;
         for (uint32_t i = t; i < Fb; i += kNT) L_.s_bk[i] = 0;
         __syncthreads();
         PHASE_END(f.ctr, 5);
-        sort_shade_blend<KIND, MODEL, SHADOW>(f, a, rgba, dbg, has_dbg, L_, list, src, px0, py0, Fb, nullptr, 0, 0);
+        sort_shade_blend<KIND, MODEL, SHADOW>(f, a, rgba, dbg, has_dbg, L_, list, rec, px0, py0, Fb, nullptr, 0, 0);
         return;
     }
     // ---- a pixel deeper than one batch: exact depth-key slices
     const int p = p0;
     const size_t qp = (size_t)tile * kTilePix + p;
-    const uint32_t k = f.pix_cnt[qp];
+    const uint32_t k = b.nfrag;
     const unsigned long long key_end = (unsigned long long)f.pix_kmax[qp] + 1ull;
     unsigned long long lo = f.pix_kmin[qp];
     float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;   // carried composite (thread 0)
@@ -1604,7 +1759,13 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 &
         }
         __syncthreads();
         PHASE_END(f.ctr, 6);
-        sort_shade_blend<KIND, MODEL, SHADOW>(f, a, rgba, dbg, has_dbg, L_, list, L_.s_A, px0, py0, Fb, s_slice, done, k);
+        uint2 rec[kPerThread];
+#pragma unroll
+        for (int qq = 0; qq < kPerThread; ++qq) {
+            const uint32_t i = t + qq * kNT;
+            if (i < Fb) rec[qq] = L_.s_A[i];
+        }
+        sort_shade_blend<KIND, MODEL, SHADOW>(f, a, rgba, dbg, has_dbg, L_, list, rec, px0, py0, Fb, s_slice, done, k);
         PHASE_RESET();
         __syncthreads();
         if (t == 0) {
@@ -1685,11 +1846,12 @@ __global__ __launch_bounds__(kNT) void k_batch_bwd(FrameBufs f, ShadeArgs a, Gra
     float4* s_p4 = reinterpret_cast<float4*>(s_work);
 
     const uint32_t n_batches = f.batch_start[f.T];
+    const uint4 br = f.batches[blockIdx.x];
     if (blockIdx.x >= n_batches || f.ctr->cap_overflow) return;
-    const uint4 br = f.batches[xcd_contiguous(blockIdx.x, n_batches)];
-    const int tile = (int)br.x, p0 = (int)br.y, p1 = (int)br.z;
+    const BatchRec b = unpack_batch(br);
+    const int tile = b.tile, p0 = b.p0, p1 = b.p1;
     const int t = threadIdx.x;
-    if (br.w) return;
+    if (b.over) return;
     const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
     const int W = a.cam.W, H = a.cam.H;
     const uint32_t lstart = f.tile_start[tile];
@@ -1707,11 +1869,11 @@ __global__ __launch_bounds__(kNT) void k_batch_bwd(FrameBufs f, ShadeArgs a, Gra
         const float4 dp = in ? reinterpret_cast<const float4*>(g.d_rgba)[(size_t)gy * W + gx] : make_float4(0, 0, 0, 0);
         s_dpix[4 * t + 0] = dp.x; s_dpix[4 * t + 1] = dp.y; s_dpix[4 * t + 2] = dp.z; s_dpix[4 * t + 3] = dp.w;
     }
-    if (t == 0) s_off[p1] = (p1 < kTilePix ? f.pix_off[(size_t)tile * kTilePix + p1] : f.tile_tot[tile]) - tile_off0;
+    if (t == 0) s_off[p1] = b.nfrag;
     for (int i = t; i < 6 * kNAcc; i += kNT) s_acc[i] = 0.0f;
     __syncthreads();
-    const uint32_t Fb = s_off[p1];
-    const uint2* src = f.frags + f.frag_base[tile] + tile_off0;
+    const uint32_t Fb = b.nfrag;
+    const uint2* src = f.frags + b.frag0;
     for (uint32_t i = t; i < Fb; i += kNT) {
         s_A[i] = src[i];
         s_bk[i] = 0;
@@ -2222,9 +2384,10 @@ __global__ __launch_bounds__(kNT) void k_dom_resolve(FrameBufs f, LevelDev lv, c
     __shared__ unsigned long long s_acc[kDomMaxLayers][kTilePix];
     __shared__ float s_iz0[kTilePix];
     const uint32_t n_batches = f.batch_start[f.T];
+    const uint4 br = f.batches[blockIdx.x];
     if (blockIdx.x >= n_batches || f.ctr->cap_overflow) return;
-    const uint4 br = f.batches[xcd_contiguous(blockIdx.x, n_batches)];
-    const int tile = (int)br.x, p0 = (int)br.y, p1 = (int)br.z;
+    const BatchRec b = unpack_batch(br);
+    const int tile = b.tile, p0 = b.p0, p1 = b.p1;
     const int t = threadIdx.x;
     const int R = grid->R;
     const float s_tex = grid->s;
@@ -2235,11 +2398,9 @@ __global__ __launch_bounds__(kNT) void k_dom_resolve(FrameBufs f, LevelDev lv, c
 #pragma unroll
     for (int k = 0; k < kDomMaxLayers; ++k) s_acc[k][t] = 0ull;
     __syncthreads();
-    const size_t tq = (size_t)tile * kTilePix;
-    const uint32_t b0 = f.pix_off[tq + p0], b1 = p1 < kTilePix ? f.pix_off[tq + p1] : f.tile_tot[tile];
-    const uint2* fr = f.frags + f.frag_base[tile];
+    const uint2* fr = f.frags + b.frag0;
     const uint32_t* list = f.list + f.tile_start[tile];
-    for (uint32_t i = b0 + t; i < b1; i += kNT) {
+    for (uint32_t i = t; i < b.nfrag; i += kNT) {
         const uint2 rec = fr[i];
         const uint32_t p = rec.y >> 24;
         const float iz = __uint_as_float(0xFFFFFFFFu - rec.x);
