@@ -586,80 +586,23 @@ __global__ void k_fill_f32(float* p, float v, size_t n) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Coverage: every fragment of segment s whose pixel lies in tile rows [row_lo, row_hi].
-// Candidate columns per row come from the row's interval of the slab 0 <= t_num <= t_den and
-// the strip |cross| <= R sqrt(t_den), widened by 1e-6 pixel; the exact integer predicate decides.
-template <class F>
-__device__ inline void for_each_fragment(const SegRec& s, int px0, int py0, int row_lo, int row_hi, int W, int H,
-                                         F&& f) {
-    // 32-bit integers are exact here: endpoints lie inside the guard band, |dx|, |dy| <= kMaxAxis
-    // (longer segments are culled), the radius is <= kMaxHwFx + 8 and every candidate pixel centre
-    // lies in the segment's box widened by the radius, so |ex|, |ey| < 2^15 and each product
-    // below stays under 2^31; cr^2 and R^2 t_den are compared in 64 bits.  x >> 4 is floor(x / 16).
-    const int ax = s.xa, ay = s.ya;
-    const int dx = s.xb - ax, dy = s.yb - ay;
-    const int tden = dx * dx + dy * dy;
-    if (tden <= 0) return;
-    const int R = (s.hwfx & kHwMask) + 8;
-    const unsigned long long RR = (unsigned long long)(unsigned)(R * R) * (unsigned)tden;
-    const int lox = min(ax, s.xb) - R, hix = max(ax, s.xb) + R;
-    const int loy = min(ay, s.yb) - R, hiy = max(ay, s.yb) + R;
-    const int i0 = max(px0, ((lox - 8) >> 4) + 1);
-    const int i1 = min(min(px0 + kTile, W) - 1, ((hix - 8 + 15) >> 4) - 1);
-    const int j0 = max(py0 + row_lo, ((loy - 8) >> 4) + 1);
-    const int j1 = min(min(py0 + row_hi, H - 1), ((hiy - 8 + 15) >> 4) - 1);
-    if (i0 > i1 || j0 > j1) return;
-    // Candidate columns per row from the two constraints (0 <= t < 1 and the radius), in float32:
-    // only an enumeration (the integer tests below decide), so it just has to contain every
-    // covered column.  Each bound is a product or difference of values below 2^31 computed with
-    // relative error under 1e-6 (float conversions, the hardware reciprocal and square root,
-    // roundings); the range is widened by 2e-6 of the magnitudes involved plus one sub-pixel.
-    const float inv_dx = dx != 0 ? __builtin_amdgcn_rcpf((float)dx) : 0.0f;
-    const float inv_dy = dy != 0 ? __builtin_amdgcn_rcpf((float)dy) : 0.0f;
-    const float half = dy != 0 ? (float)R * __builtin_amdgcn_sqrtf((float)tden) * fabsf(inv_dy) : 0.0f;
-    for (int j = j0; j <= j1; ++j) {
-        const int ey = 16 * j + 8 - ay;
-        float lo = -1e30f, hi = 1e30f, mag = fabsf((float)ax);
-        if (dx != 0) {
-            const float a = (float)(-ey * dy) * inv_dx;
-            const float b = (float)(tden - ey * dy) * inv_dx;
-            lo = fminf(a, b);
-            hi = fmaxf(a, b);
-            mag += fmaxf(fabsf(a), fabsf(b));
-        }
-        if (dy != 0) {
-            const float c = (float)(ey * dx) * inv_dy;
-            lo = fmaxf(lo, c - half);
-            hi = fminf(hi, c + half);
-            mag += fabsf(c) + half;
-        }
-        const float w = 2e-6f * mag + 1.0f;
-        // columns whose centre offset 16 i + 8 - ax lies in [lo - w, hi + w]
-        const float flo = ceilf(((float)ax + (lo - w) - 8.0f) * (1.0f / 16.0f));
-        const float fhi = floorf(((float)ax + (hi + w) - 8.0f) * (1.0f / 16.0f));
-        const int c0 = (int)fmaxf((float)i0, flo);
-        const int c1 = (int)fminf((float)i1, fhi);
-        const int ey_dy = ey * dy, ey_dx = ey * dx;
-        for (int i = c0; i <= c1; ++i) {
-            const int ex = 16 * i + 8 - ax;
-            const int tnum = ex * dx + ey_dy;
-            if (tnum < 0 || tnum >= tden) continue;
-            const int cr = ex * dy - ey_dx;
-            const unsigned acr = (unsigned)abs(cr);
-            if ((unsigned long long)acr * acr >= RR) continue;
-            f(i - px0, j - py0, tnum, tden, cr);
-        }
-    }
-}
-
-// Coverage with the work balanced across a wave.  for_each_fragment gives each lane one
-// segment, so a wave runs as long as its longest segment; here a segment's candidate pixels
-// are enumerated one line at a time along its major axis (rows when |dy| >= |dx|, else
-// columns), and the wave's lanes share out all (segment, line) pairs, 64 per round.  A line's
-// span (the minor-axis candidates) comes from the same slab and strip bounds as above, with
-// the axes named u (major) and v (minor): for steep segments the computation is the one above
-// term for term, for shallow ones it is the same with x and y exchanged (|cross| and t_num are
-// symmetric under the exchange), so the integer predicate meets the same candidates.
+// Coverage: every fragment of a tile's segments, with the work shared across a wave.  A
+// segment's candidate pixels are enumerated one line at a time along its major axis (rows when
+// |dy| >= |dx|, else columns; u names the major axis, v the minor one), and the lanes of a wave
+// share out all its (segment, line) pairs, 64 per round, so that a wave does not run as long
+// as its longest segment.  On a line, the candidates are the v whose pixel centre lies in the
+// interval of the slab 0 <= t_num <= t_den and of the strip |cross| <= R sqrt(t_den), widened
+// by 1e-6 pixel; the exact integer predicate decides (t_num and |cross| are symmetric under the
+// exchange of x and y, so the same predicate serves both orientations).
+//
+// 32-bit integers are exact here: endpoints lie inside the guard band, |dx|, |dy| <= kMaxAxis
+// (longer segments are culled), the radius is <= kMaxHwFx + 8 and every candidate pixel centre
+// lies in the segment's box widened by the radius, so |e_u|, |e_v| < 2^15 and each product
+// stays under 2^31; cross^2 and R^2 t_den are compared in 64 bits.  x >> 4 is floor(x / 16).
+// The candidate interval is computed in float32: only an enumeration, so it just has to contain
+// every covered pixel.  Each bound is a product or difference of values below 2^31 computed with
+// relative error under 1e-6 (float conversions, the hardware reciprocal and square root,
+// roundings); the interval is widened by 2e-6 of the magnitudes involved plus one sub-pixel.
 struct CovSetup {
     int4 g0;     // (au, av, du, dv): start and extent along the major and minor axes, 1/16 px
     int4 g1;     // (R, tden, first line - lines before this lane in the wave, steep)
