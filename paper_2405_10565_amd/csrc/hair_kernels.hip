@@ -2297,9 +2297,8 @@ __global__ __launch_bounds__(256) void k_project_light(LevelDev lv, const DomGri
 // One block per batch of whole texels (the camera pass's batches), one lane per fragment; the
 // counts are summed per (texel, layer) in LDS.  Texels in no batch hold no hair (cleared).
 // Output: (iz0, C_0 .. C_{K-1}) with C the cumulative counts; iz0 = 0 marks a texel without hair.
-__device__ inline float dom_fragment_count(const FrameBufs& f, const LevelDev& lv, float s_tex, uint32_t g, int px,
+__device__ inline float dom_fragment_count(const SegRec& s, const LevelDev& lv, float s_tex, uint32_t g, int px,
                                            int py) {
-    const SegRec s = f.seg[g];
     const int ex = 16 * px + 8 - s.xa, ey = 16 * py + 8 - s.ya;
     const int dx = s.xb - s.xa, dy = s.yb - s.ya;
     const int tden = dx * dx + dy * dy, cr = ex * dy - ey * dx;
@@ -2343,15 +2342,39 @@ __global__ __launch_bounds__(kNT) void k_dom_resolve(FrameBufs f, LevelDev lv, c
     __syncthreads();
     const uint2* fr = f.frags + b.frag0;
     const uint32_t* list = f.list + f.tile_start[tile];
-    for (uint32_t i = t; i < b.nfrag; i += kNT) {
-        const uint2 rec = fr[i];
-        const uint32_t p = rec.y >> 24;
-        const float iz = __uint_as_float(0xFFFFFFFFu - rec.x);
-        const int layer = min(K - 1, (int)floorf((s_iz0[p] - iz) / delta));
-        const float c = dom_fragment_count(f, lv, s_tex, list[rec.y & 0xFFFFFFu], tx0 + (int)(p % kTile),
-                                           ty0 + (int)(p / kTile));
-        const unsigned long long fx = (unsigned long long)((double)c * 4294967296.0 + 0.5);
-        if (fx) atomicAdd(&s_acc[layer][p], fx);
+    // kU records per lane in flight: the record, list and segment gathers of one round are
+    // issued together instead of one dependent chain per record
+    constexpr int kU = 4;
+    for (uint32_t i0 = 0; i0 < b.nfrag; i0 += kU * kNT) {
+        uint2 rec[kU];
+        uint32_t g[kU];
+        SegRec sg[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const uint32_t i = i0 + t + u * kNT;
+            rec[u] = i < b.nfrag ? fr[i] : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const uint32_t i = i0 + t + u * kNT;
+            g[u] = i < b.nfrag ? list[rec[u].y & 0xFFFFFFu] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const uint32_t i = i0 + t + u * kNT;
+            if (i < b.nfrag) sg[u] = f.seg[g[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const uint32_t i = i0 + t + u * kNT;
+            if (i >= b.nfrag) continue;
+            const uint32_t p = rec[u].y >> 24;
+            const float iz = __uint_as_float(0xFFFFFFFFu - rec[u].x);
+            const int layer = min(K - 1, (int)floorf((s_iz0[p] - iz) / delta));
+            const float c = dom_fragment_count(sg[u], lv, s_tex, g[u], tx0 + (int)(p % kTile), ty0 + (int)(p / kTile));
+            const unsigned long long fx = (unsigned long long)((double)c * 4294967296.0 + 0.5);
+            if (fx) atomicAdd(&s_acc[layer][p], fx);
+        }
     }
     __syncthreads();
     const int px = tx0 + (t % kTile), py = ty0 + (t / kTile);
