@@ -28,10 +28,13 @@ struct alignas(16) SegRec {
 // Per-segment shading inputs gathered once per frame by k_project (64 bytes, one aligned
 // half cache line per fragment instead of five scattered reads):
 //   q0 = (pA, sigma_r)  q1 = (pB, sigma_g)  q2 = (a^, sigma_b)  q3 = (|a|, |b|, n_total, r)
-// (strands leave a^ and q3 unused).
+// (strands in mixed frames leave a^ and q3 unused).  In a strand-level frame the same 64 bytes
+// hold the packed strand layout of pack_strand_shade instead, which also carries the screen
+// record's fields the shading needs, so that a fragment's gather is one line.
 struct ShadeRec {
     float4 q0, q1, q2, q3;
 };
+static_assert(sizeof(SegRec) == 32 && sizeof(ShadeRec) == 64, "records are stored as 16-byte words");
 
 constexpr int32_t kFlagVisible = 1 << 16;
 constexpr int32_t kFlagNegSide = 1 << 17;        // h > 0 lies on the e x d < 0 side

@@ -152,15 +152,31 @@ __device__ inline TileRect tile_rect(const SegRec& s, int ntx, int nty) {
     return r;
 }
 
+// The shading record of a strand segment in a strand-level frame: everything the shading pass
+// reads for one fragment in one aligned 64-byte line (the screen record's coverage geometry,
+// inverse depths and half-width, whose sign bit carries the side flag, then the world
+// endpoints and the strand's absorption):
+//   q0 = (xa, ya, xb, yb as int bits)  q1 = (iza, izb, +-hw, pA.x)  q2 = (pA.y, pA.z, pB.x, pB.y)
+//   q3 = (pB.z, sigma_r, sigma_g, sigma_b)
+__device__ inline void pack_strand_shade(const SegRec& r, float ax, float ay, float az, float bx, float by, float bz,
+                                         float sr_, float sg_, float sb_, ShadeRec* sr) {
+    const float shw = __uint_as_float(__float_as_uint(r.hw) | ((r.hwfx & kFlagNegSide) ? 0x80000000u : 0u));
+    sr->q0 = make_float4(__int_as_float(r.xa), __int_as_float(r.ya), __int_as_float(r.xb), __int_as_float(r.yb));
+    sr->q1 = make_float4(r.iza, r.izb, shw, ax);
+    sr->q2 = make_float4(ay, az, bx, by);
+    sr->q3 = make_float4(bz, sr_, sg_, sb_);
+}
+
 // Segment g of level lv, drawn between (ax, ay, az) and (bx, by, bz): its screen record
 // (projection, snapping, half-width, culling, side of h > 0) and, when sr is given, its
-// shading record.  The endpoints are the level's vertices, or points of a curved thick hair.
+// shading record (packed: the strand-level layout above; otherwise q0..q3 as ShadeRec states).
+// The endpoints are the level's vertices, or points of a curved thick hair.
 __device__ inline SegRec project_segment_at(const LevelDev& lv, int g, float ax, float ay, float az, float bx, float by,
-                                            float bz, const CamConst& cam, ShadeRec* sr) {
+                                            float bz, const CamConst& cam, ShadeRec* sr, bool packed = false) {
     const int owner = g / lv.S;
     const PPoint A = project_point(cam, ax, ay, az);
     const PPoint B = project_point(cam, bx, by, bz);
-    if (sr) {   // whole float4 stores (q3 only for thick hairs)
+    if (sr && !packed) {   // whole float4 stores (q3 only for thick hairs)
         const float sb = lv.sig[2 * lv.n_owner + owner];
         float4 q2 = make_float4(0.f, 0.f, 0.f, sb);
         if (lv.kind != 0) q2 = make_float4(lv.ahat[g], lv.ahat[lv.nseg + g], lv.ahat[2 * lv.nseg + g], sb);
@@ -222,20 +238,45 @@ __device__ inline SegRec project_segment_at(const LevelDev& lv, int g, float ax,
             if (side < 0.0f) r.hwfx |= kFlagNegSide;
         }
     }
+    if (sr && packed)
+        pack_strand_shade(r, ax, ay, az, bx, by, bz, lv.sig[owner], lv.sig[lv.n_owner + owner],
+                          lv.sig[2 * lv.n_owner + owner], sr);
     return r;
 }
 
-__device__ inline SegRec project_segment(const LevelDev& lv, int g, const CamConst& cam, ShadeRec* sr) {
+__device__ inline SegRec project_segment(const LevelDev& lv, int g, const CamConst& cam, ShadeRec* sr,
+                                         bool packed = false) {
     const int owner = g / lv.S, k = g - owner * lv.S;
     const int va = owner * (lv.S + 1) + k;
     return project_segment_at(lv, g, lv.vx[va], lv.vy[va], lv.vz[va], lv.vx[va + 1], lv.vy[va + 1], lv.vz[va + 1], cam,
-                              sr);
+                              sr, packed);
 }
 
+// A frame of one level: strand levels write the packed strand shading record.  The block's
+// records are staged in LDS and stored as consecutive 16-byte words, so that every store
+// instruction writes whole contiguous lines.
 __global__ __launch_bounds__(256) void k_project(LevelDev lv, CamConst cam, SegRec* __restrict__ seg,
                                                  ShadeRec* __restrict__ shade) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < lv.nseg) seg[g] = project_segment(lv, g, cam, shade + g);
+    __shared__ float4 s_seg[2 * 256];
+    __shared__ float4 s_sh[4 * 256];
+    const int t = threadIdx.x, g0 = blockIdx.x * 256, g = g0 + t;
+    if (g < lv.nseg) {
+        ShadeRec sr;
+        sr.q3 = make_float4(0.f, 0.f, 0.f, 0.f);
+        const SegRec r = project_segment(lv, g, cam, &sr, lv.kind == 0);
+        s_seg[2 * t] = make_float4(__int_as_float(r.xa), __int_as_float(r.ya), __int_as_float(r.xb), __int_as_float(r.yb));
+        s_seg[2 * t + 1] = make_float4(__int_as_float(r.hwfx), r.iza, r.izb, r.hw);
+        s_sh[4 * t] = sr.q0;
+        s_sh[4 * t + 1] = sr.q1;
+        s_sh[4 * t + 2] = sr.q2;
+        s_sh[4 * t + 3] = sr.q3;
+    }
+    __syncthreads();
+    const int n = min(256, lv.nseg - g0);
+    float4* dseg = reinterpret_cast<float4*>(seg + g0);
+    for (int i = t; i < 2 * n; i += 256) dseg[i] = s_seg[i];
+    float4* dsh = reinterpret_cast<float4*>(shade + g0);
+    for (int i = t; i < 4 * n; i += 256) dsh[i] = s_sh[i];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -946,15 +987,33 @@ struct SegInputs {
     float4 q0, q1, q2, q3;
 };
 
+// KIND 0 (a strand-level frame) reads the packed strand record alone; the others read the
+// screen record and the ShadeRec.
 template <int KIND>
 __device__ inline SegInputs fetch_segment(const ShadeArgs& a, uint32_t gseg) {
     SegInputs r;
-    r.s = a.seg[gseg];
     const ShadeRec& sr = a.shade[gseg];
+    if (KIND == 0) {
+        const float4 p0 = sr.q0, p1 = sr.q1, p2 = sr.q2, p3 = sr.q3;
+        r.s.xa = __float_as_int(p0.x);
+        r.s.ya = __float_as_int(p0.y);
+        r.s.xb = __float_as_int(p0.z);
+        r.s.yb = __float_as_int(p0.w);
+        r.s.iza = p1.x;
+        r.s.izb = p1.y;
+        r.s.hw = fabsf(p1.z);
+        r.s.hwfx = (__float_as_uint(p1.z) >> 31) ? kFlagNegSide : 0;
+        r.q0 = make_float4(p1.w, p2.x, p2.y, p3.y);
+        r.q1 = make_float4(p2.z, p2.w, p3.x, p3.z);
+        r.q2 = make_float4(0.f, 0.f, 0.f, p3.w);
+        r.q3 = make_float4(0.f, 0.f, 0.f, 0.f);
+        return r;
+    }
+    r.s = a.seg[gseg];
     r.q0 = sr.q0;
     r.q1 = sr.q1;
     r.q2 = sr.q2;
-    r.q3 = KIND == 0 ? make_float4(0.f, 0.f, 0.f, 0.f) : sr.q3;
+    r.q3 = sr.q3;
     return r;
 }
 
