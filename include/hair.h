@@ -210,6 +210,23 @@ int hair_render(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const 
                 const hair_light* lights, int32_t n_lights, float* rgba_out, void* stream,
                 hair_stats* stats);
 
+/* The same frame as hair_render (same operation, same output) without waiting for it: on a
+ * workspace that has rendered before (its buffer capacities are known) the frame is enqueued
+ * on `stream` and the call returns at once, so that a caller can keep frames in flight (one
+ * per workspace) with no host round trip between them.  On a workspace without capacities
+ * the frame runs synchronously, as hair_render.  ws is required; the workspace then holds
+ * the frame until hair_ws_finish, and every other call on it fails with HAIR_EINVAL until
+ * then.  cam and lights are copied; rgba_out must stay valid until the frame is finished.
+ * Argument errors are reported here, frame errors by hair_ws_finish. */
+int hair_render_async(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,
+                      const hair_light* lights, int32_t n_lights, float* rgba_out, void* stream);
+
+/* Waits for the workspace's frame of hair_render_async and checks it as hair_render does: a
+ * frame that outgrew the workspace's buffers is rendered again, synchronously, on its stream.
+ * Fills stats (may be NULL) and returns the frame's status (HAIR_ERANGE as for hair_render).
+ * With no frame held: HAIR_OK and zeroed stats. */
+int hair_ws_finish(hair_ws* ws, hair_stats* stats);
+
 /* hair_render with deep opacity map shadows (see hair_shadow) at a strand or thick-hair level
  * (mixed frames are not shadowed).  One shadow pass per directional light runs on `stream`
  * before the frame (sized like a frame, see hair_render); stats describe the

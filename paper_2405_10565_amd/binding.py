@@ -28,7 +28,7 @@ EXPORTS = [
     "hair_build_lod", "hair_lod_info", "hair_get_lod", "hair_set_lod", "hair_set_cluster_params",
     "hair_select_level", "hair_render", "hair_render_backward", "hair_debug_segments", "hair_debug_bins",
     "hair_debug_fragments", "hair_lod_groups", "hair_lod_init", "hair_render_mixed", "hair_render_shadowed",
-    "hair_debug_dom", "hair_render_curved",
+    "hair_debug_dom", "hair_render_curved", "hair_render_async", "hair_ws_finish",
 ]
 
 
@@ -117,6 +117,8 @@ def _load():
         "hair_select_level": ([P, P, I32, C.POINTER(hair_camera), F, P, ip], C.c_int),
         "hair_render": ([P, P, I32, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32, P, P,
                          C.POINTER(hair_stats)], C.c_int),
+        "hair_render_async": ([P, P, I32, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32, P, P], C.c_int),
+        "hair_ws_finish": ([P, C.POINTER(hair_stats)], C.c_int),
         "hair_render_backward": ([P, P, I32, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32, P, P, P, P, P],
                                  C.c_int),
         "hair_lod_groups": ([P, I32, ip], C.c_int),
@@ -200,7 +202,17 @@ class Workspace:
         h = C.c_void_p()
         check(lib.hair_ws_create(ctx.handle, max_bytes, C.byref(h)))
         self.handle = h
+        self._pending_out = None
         ctx._workspaces.add(self)
+
+    def finish(self, raise_on_error: bool = True):
+        """Wait for the frame of Context.render_async (hair_ws_finish): (stats dict, status)."""
+        st = hair_stats()
+        rc = lib.hair_ws_finish(self.handle, C.byref(st))
+        self._pending_out = None
+        if raise_on_error:
+            check(rc)
+        return st.as_dict(), rc
 
     def close(self):
         if self.handle:
@@ -334,6 +346,18 @@ class Context:
         if raise_on_error:
             check(rc)
         return out, st.as_dict(), rc
+
+    def render_async(self, asset: int, level: int, cam, lights, out, ws: Workspace, stream=None):
+        """Enqueue a frame into `out` on `ws` without waiting (hair_render_async); ws.finish()
+        returns its (stats dict, status code)."""
+        import torch
+        c = make_camera(cam)
+        la, nl = make_lights(lights)
+        assert out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+        assert tuple(out.shape) == (c.height, c.width, 4)
+        check(lib.hair_render_async(self.handle, ws.handle, asset, level, C.byref(c), la, nl,
+                                    C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        ws._pending_out = out      # keeps the output alive until the frame is finished
 
     def render_shadowed(self, asset: int, level: int, cam, lights, shadow=(512, 4, 0.02), out=None,
                         ws: Workspace | None = None, stream=None, raise_on_error: bool = True):

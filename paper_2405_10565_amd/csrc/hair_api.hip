@@ -90,6 +90,20 @@ struct hair_ws {
     hipEvent_t ev[7] = {};
     bool events = false;
     int64_t last_nseg = 0, last_ntiles = 0, last_pairs = 0;
+    // a frame enqueued by hair_render_async and not yet finished: what a rerun needs, and
+    // (done) the result of a frame that already ran to completion
+    struct Pending {
+        bool active = false, done = false;
+        int32_t asset = -1, level = 0;
+        hair_camera cam{};
+        std::vector<hair_light> lights;
+        float* rgba = nullptr;
+        hipStream_t st = nullptr;
+        Counters ctr{};            // result of a frame that ran to completion (done)
+        uint32_t pairs = 0, n_batches = 0;
+        float ms[4] = {};
+    } pending;
+    Counters* ctr_host = nullptr;   // pinned copy of a deferred frame's counters
     std::mutex mu;
 };
 
@@ -368,7 +382,26 @@ struct FrameOut {
     uint32_t pairs;
     uint32_t n_batches;
     float ms[4];
+    bool deferred = false;   // counters and timings are read when the workspace is finished
 };
+
+// A frame's sizes and timings from its counters (after its stream has passed ev[6]).
+int frame_result(hair_ctx* ctx, hair_ws* ws, int64_t nseg, int T, FrameOut* out) {
+    const uint32_t pairs = out->ctr.sizes[0];
+    ws->last_nseg = nseg;
+    ws->last_ntiles = T;
+    ws->last_pairs = pairs;
+    out->pairs = pairs;
+    out->ctr.fragments = out->ctr.sizes[2];
+    out->n_batches = out->ctr.sizes[3];
+    // three timing markers only: each costs the stream a few microseconds of idle time
+    float t05 = 0, t56 = 0, t06 = 0;
+    HIP_TRY(ctx, hipEventElapsedTime(&t05, ws->ev[0], ws->ev[5]), "elapsed");
+    HIP_TRY(ctx, hipEventElapsedTime(&t56, ws->ev[5], ws->ev[6]), "elapsed");
+    HIP_TRY(ctx, hipEventElapsedTime(&t06, ws->ev[0], ws->ev[6]), "elapsed");
+    out->ms[0] = t06; out->ms[1] = t05; out->ms[2] = 0.0f; out->ms[3] = t56;
+    return HAIR_OK;
+}
 
 // A shadow-pass raster: the light view's records instead of the camera's, and the per-texel
 // layers instead of shading.
@@ -406,8 +439,10 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
               const hair_light* lights, int n_lights, float* rgba, const DebugDump* dbg, hipStream_t st,
               FrameOut* out, bool tiles_too = true, const GradOut* grad = nullptr, const HierDev* hier = nullptr,
               const uint32_t* sel = nullptr, const DomPass* dom = nullptr, const DomView* views = nullptr,
-              const TessPass* tess = nullptr, bool cold = false) {
+              const TessPass* tess = nullptr, bool cold = false, bool defer = false) {
     int rc;
+    if (ws->pending.active)
+        return fail(HAIR_EINVAL, "the workspace holds a frame of hair_render_async: call hair_ws_finish first");
     const CamConst cc = cam_const(cam);
     const int ntx = (cam->width + kTile - 1) / kTile, nty = (cam->height + kTile - 1) / kTile;
     const int T = ntx * nty;
@@ -543,6 +578,14 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
         HIP_TRY(ctx, launch_batches(f, lv, cc, lc, mat_const(a.mat), batch_grid, rgba, dbg, st), "k_batch");
     }
     HIP_TRY(ctx, hipEventRecord(ws->ev[6], st), "hipEventRecord");
+    if (defer && warm) {   // no host synchronisation: the counters land in pinned memory
+        if (!ws->ctr_host)
+            HIP_TRY(ctx, hipHostMalloc((void**)&ws->ctr_host, sizeof(Counters), hipHostMallocDefault), "hipHostMalloc");
+        HIP_TRY(ctx, hipMemcpyAsync(ws->ctr_host, ws->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, st), "copy");
+        HIP_TRY(ctx, hipEventRecord(ws->ev[1], st), "hipEventRecord");
+        out->deferred = true;
+        return HAIR_OK;
+    }
     HIP_TRY(ctx, hipMemcpyAsync(&out->ctr, ws->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, st), "copy");
     HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
     if (out->ctr.cap_overflow) {
@@ -551,21 +594,8 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
                          tess, true);
     }
     ws->caps = caps;
-    pairs = out->ctr.sizes[0];
-    n_frags = out->ctr.sizes[2];
-    n_batches = out->ctr.sizes[3];
-    ws->last_nseg = lv.nseg;
-    ws->last_ntiles = T;
-    ws->last_pairs = pairs;
-    out->pairs = pairs;
-    out->ctr.fragments = n_frags;
-    // three timing markers only: each costs the stream a few microseconds of idle time
-    float t05 = 0, t56 = 0, t06 = 0;
-    HIP_TRY(ctx, hipEventElapsedTime(&t05, ws->ev[0], ws->ev[5]), "elapsed");
-    HIP_TRY(ctx, hipEventElapsedTime(&t56, ws->ev[5], ws->ev[6]), "elapsed");
-    HIP_TRY(ctx, hipEventElapsedTime(&t06, ws->ev[0], ws->ev[6]), "elapsed");
-    out->ms[0] = t06; out->ms[1] = t05; out->ms[2] = 0.0f; out->ms[3] = t56;
-    out->n_batches = n_batches;
+    if ((rc = frame_result(ctx, ws, lv.nseg, T, out))) return rc;
+    n_batches = out->n_batches;
 #ifdef HAIR_PHASE_STATS
     fprintf(stderr, "phase cycles: count %llu emit %llu sort %llu shade %llu blend %llu load %llu deep-slicing %llu | "
             "deep fragments %llu batches %u items %u\n",
@@ -654,6 +684,8 @@ int hair_ws_destroy(hair_ws* ws) {
                       &ws->frags,
                       &ws->dom_tex, &ws->dom_grid, &ws->dom_part})
         ctx_free(ctx, *b, ws);
+    if (ws->pending.active && !ws->pending.done && ws->events) (void)hipEventSynchronize(ws->ev[1]);
+    if (ws->ctr_host) (void)hipHostFree(ws->ctr_host);
     if (ws->events)
         for (auto& e : ws->ev) (void)hipEventDestroy(e);
     if (ctx->default_ws == ws) ctx->default_ws = nullptr;
@@ -1065,6 +1097,89 @@ int hair_render(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const 
     std::lock_guard<std::mutex> g(ws->mu);
     FrameOut fo;
     if ((rc = run_frame(ctx, ws, *a, lv, cam, lights, n_lights, rgba_out, nullptr, (hipStream_t)stream, &fo))) return rc;
+    if (stats) fill_stats(stats, fo, (uint32_t)lv.nseg);
+    if (fo.ctr.list_overflow) return fail(HAIR_ERANGE, "%u tiles hold more than 2^24 segments", fo.ctr.list_overflow);
+    if (fo.ctr.overflow_pixels)
+        return fail(HAIR_ERANGE, "%u pixels hold more than %d fragments at one depth key (left transparent)",
+                    fo.ctr.overflow_pixels, kCap);
+    return HAIR_OK;
+}
+
+int hair_render_async(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,
+                      const hair_light* lights, int32_t n_lights, float* rgba_out, void* stream) {
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if (!ws) return fail(HAIR_EINVAL, "hair_render_async needs a workspace of its own");
+    if (ws->ctx != ctx) return fail(HAIR_EINVAL, "the workspace belongs to another context");
+    if ((rc = validate_camera(cam))) return rc;
+    if ((rc = validate_lights(lights, n_lights))) return rc;
+    if (!rgba_out) return fail(HAIR_EINVAL, "null output image");
+    Asset* a;
+    LevelDev lv;
+    if ((rc = find_level(ctx, asset, level, &a, &lv))) return rc;
+    if ((rc = need_device(ctx))) return rc;
+    std::lock_guard<std::mutex> g(ws->mu);
+    FrameOut fo;
+    if ((rc = run_frame(ctx, ws, *a, lv, cam, lights, n_lights, rgba_out, nullptr, (hipStream_t)stream, &fo, true,
+                        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, false, true)))
+        return rc;
+    hair_ws::Pending& pd = ws->pending;
+    pd.active = true;
+    pd.done = !fo.deferred;
+    pd.asset = asset;
+    pd.level = level;
+    pd.cam = *cam;
+    pd.lights.assign(lights, lights + n_lights);
+    pd.rgba = rgba_out;
+    pd.st = (hipStream_t)stream;
+    if (pd.done) {
+        pd.ctr = fo.ctr;
+        pd.pairs = fo.pairs;
+        pd.n_batches = fo.n_batches;
+        for (int i = 0; i < 4; ++i) pd.ms[i] = fo.ms[i];
+    }
+    return HAIR_OK;
+}
+
+int hair_ws_finish(hair_ws* ws, hair_stats* stats) {
+    if (!ws) return fail(HAIR_EINVAL, "null workspace");
+    hair_ctx* ctx = ws->ctx;
+    std::lock_guard<std::mutex> g(ws->mu);
+    hair_ws::Pending& pd = ws->pending;
+    if (!pd.active) {
+        if (stats) *stats = hair_stats{};
+        return HAIR_OK;
+    }
+    int rc;
+    FrameOut fo;
+    Asset* a;
+    LevelDev lv;
+    const int T = ((pd.cam.width + kTile - 1) / kTile) * ((pd.cam.height + kTile - 1) / kTile);
+    if ((rc = find_level(ctx, pd.asset, pd.level, &a, &lv))) {
+        pd.active = false;
+        return rc;
+    }
+    if (pd.done) {
+        fo.ctr = pd.ctr;
+        fo.pairs = pd.pairs;
+        fo.n_batches = pd.n_batches;
+        for (int i = 0; i < 4; ++i) fo.ms[i] = pd.ms[i];
+    } else {
+        if (ctx->device >= 0) HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+        HIP_TRY(ctx, hipEventSynchronize(ws->ev[1]), "hipEventSynchronize");
+        fo.ctr = *ws->ctr_host;
+        if (fo.ctr.cap_overflow) {   // the frame outgrew the capacities: render it again, cold
+            const hair_ws::Pending p = pd;
+            pd.active = false;
+            if ((rc = run_frame(ctx, ws, *a, lv, &p.cam, p.lights.data(), (int)p.lights.size(), p.rgba, nullptr, p.st,
+                                &fo, true, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true)))
+                return rc;
+        } else if ((rc = frame_result(ctx, ws, lv.nseg, T, &fo))) {
+            pd.active = false;
+            return rc;
+        }
+    }
+    pd.active = false;
     if (stats) fill_stats(stats, fo, (uint32_t)lv.nseg);
     if (fo.ctr.list_overflow) return fail(HAIR_ERANGE, "%u tiles hold more than 2^24 segments", fo.ctr.list_overflow);
     if (fo.ctr.overflow_pixels)

@@ -163,3 +163,27 @@ def test_null_and_unknown_handles(B, hctx):
     assert B.lib.hair_ws_destroy(None) == B.HAIR_EINVAL
     nl = C.c_int32()
     assert B.lib.hair_lod_info(hctx.handle, 5, C.byref(nl), None, 0, None) == B.HAIR_ENOENT
+
+
+def test_async_render_validation(B, hctx):
+    """hair_render_async needs a workspace of its own context and checks its arguments on the
+    host; hair_ws_finish on a workspace that holds no frame returns OK with zeroed stats."""
+    la, nl = B.make_lights([type("L", (), dict(kind=0, vec=[0, 0, 1], rgb=[1, 1, 1]))()])
+    c = _cam(B)
+    img = C.c_void_p(1)
+    assert B.lib.hair_render_async(hctx.handle, None, 0, 0, C.byref(c), la, nl, img, None) == B.HAIR_EINVAL
+    ws = hctx.workspace()
+    assert B.lib.hair_render_async(hctx.handle, ws.handle, 0, 0, C.byref(_cam(B, width=0)), la, nl, img,
+                                   None) == B.HAIR_EINVAL
+    assert B.lib.hair_render_async(hctx.handle, ws.handle, 0, 0, C.byref(c), la, 0, img, None) == B.HAIR_EINVAL
+    assert B.lib.hair_render_async(hctx.handle, ws.handle, 0, 0, C.byref(c), la, nl, None, None) == B.HAIR_EINVAL
+    assert B.lib.hair_render_async(hctx.handle, ws.handle, 0, 0, C.byref(c), la, nl, img, None) == B.HAIR_ENOENT
+    other = B.Context(device=-1)
+    ows = other.workspace()
+    assert B.lib.hair_render_async(hctx.handle, ows.handle, 0, 0, C.byref(c), la, nl, img, None) == B.HAIR_EINVAL
+    st = B.hair_stats()
+    st.fragments = 7
+    assert B.lib.hair_ws_finish(ws.handle, C.byref(st)) == B.HAIR_OK and st.fragments == 0
+    assert B.lib.hair_ws_finish(None, C.byref(st)) == B.HAIR_EINVAL
+    ws.close()
+    other.close()
