@@ -153,8 +153,8 @@ def serve_leg(ctx, n_requests: int, warmup: int = 24, rates=(30.0, 60.0, 120.0))
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-latency leg")
     ap.add_argument("--no-extras", action="store_true",

@@ -372,7 +372,10 @@ hair_ws* ws_or_default(hair_ctx* ctx, hair_ws* ws) {
 
 int ws_events(hair_ws* ws) {
     if (ws->events) return HAIR_OK;
-    for (auto& e : ws->ev) HIP_TRY(ws->ctx, hipEventCreate(&e), "hipEventCreate");
+    // ev[0], ev[5], ev[6] time the frame; ev[1] only marks a deferred frame's end (no timestamp)
+    for (int i = 0; i < 7; ++i)
+        HIP_TRY(ws->ctx, i == 1 ? hipEventCreateWithFlags(&ws->ev[i], hipEventDisableTiming) : hipEventCreate(&ws->ev[i]),
+                "hipEventCreate");
     ws->events = true;
     return HAIR_OK;
 }
