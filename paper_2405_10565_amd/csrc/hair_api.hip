@@ -613,7 +613,7 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
 // =======================================================================================
 extern "C" {
 
-int hair_version(void) { return 102; }
+int hair_version(void) { return 103; }
 
 const char* hair_last_error(void) { return g_err.c_str(); }
 
