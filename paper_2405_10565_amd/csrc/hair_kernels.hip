@@ -1973,8 +1973,28 @@ __global__ __launch_bounds__(kNT) void k_batch_bwd(FrameBufs f, ShadeArgs a, Gra
         }
     }
     __syncthreads();
-    // ---- 4. partials: alpha and L as Dual6, contracted with the adjoints
-    for (uint32_t i = t; i < Fb; i += kNT) {
+    // ---- 4. partials: alpha and L as Dual6, contracted with the adjoints.  A fragment whose
+    // four adjoints are all zero (behind an opaque fragment of its pixel, T_k = 0, or in a
+    // pixel without output adjoint) contributes exactly nothing; the others are listed first
+    // (in s_T, free after step 3) so that every lane's Dual6 work is a fragment that counts.
+    uint32_t* s_idx = reinterpret_cast<uint32_t*>(s_T);
+    uint32_t n_live;
+    {
+        uint32_t mine = 0;
+        for (uint32_t i = t; i < Fb; i += kNT) {
+            const float4 v = s_p4[i];
+            mine += (v.x != 0.0f || v.y != 0.0f || v.z != 0.0f || v.w != 0.0f) ? 1u : 0u;
+        }
+        uint32_t pos;
+        n_live = block_exscan_u32(mine, s_tmp, pos);
+        for (uint32_t i = t; i < Fb; i += kNT) {
+            const float4 v = s_p4[i];
+            if (v.x != 0.0f || v.y != 0.0f || v.z != 0.0f || v.w != 0.0f) s_idx[pos++] = i;
+        }
+        __syncthreads();
+    }
+    for (uint32_t k = t; k < n_live; k += kNT) {
+        const uint32_t i = s_idx[k];
         const uint2 rec = s_B[i];
         const uint32_t p = rec.y >> 24;
         const uint32_t j = rec.y & 0xFFFFFFu;
