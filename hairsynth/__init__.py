@@ -299,21 +299,27 @@ def default_lights(asset: Asset, with_point: bool) -> list[Light]:
     return lights
 
 
-# The five workloads.  Sizes follow the paper's scales (Sec. 6); the generator recipe is above.
+# The five workloads, numbered (the number also offsets the generator seed: 1000 + n).  Sizes
+# follow the paper's scales (Sec. 6); the generator recipe is above.
 CONFIGS = {
+    # 1: small frame, 1k strands x 16 segments at 256x256, one directional light
     1: dict(strands=1_000, segs=16, cap=60.0, res=(256, 256), point=False, spread=False),
+    # 2: full frame, 100k strands x 32 segments at 1920x1080, directional + point light
     2: dict(strands=100_000, segs=32, cap=90.0, res=(1920, 1080), point=True, spread=True),
+    # 3: LoD sweep, 150k strands x 64 segments at 1080p with 10k / 1k / 100 thick hairs
     3: dict(strands=150_000, segs=64, cap=90.0, res=(1920, 1080), point=True, spread=True,
             levels=(10_000, 1_000, 100)),
+    # 4: fitting, 50k strands x 32 segments -> 500 thick hairs, 8 views at 512x512
     4: dict(strands=50_000, segs=32, cap=90.0, res=(512, 512), point=False, spread=False,
             levels=(500,), views=8),
+    # 5: serving, three resident assets at 720p / 1080p / 2160p
     5: dict(assets=((10_000, 16), (100_000, 32), (300_000, 48)), cap=90.0, point=True, spread=True,
             resolutions=((1280, 720), (1920, 1080), (3840, 2160))),
 }
 
 
 def config(cfg: int, scale: float = 1.0):
-    """(asset, camera, lights) for configs 1-4; `scale` shrinks the strand count for tests."""
+    """(asset, camera, lights) for workloads 1-4; `scale` shrinks the strand count for tests."""
     c = CONFIGS[cfg]
     n = max(1, int(round(c["strands"] * scale)))
     asset = make_asset(n, c["segs"], c["cap"], seed=1000 + cfg, sigma_spread=c["spread"])

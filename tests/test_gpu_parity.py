@@ -54,7 +54,7 @@ def _render(hip, ctx, asset, cam, lights, level=0, aid=None, lod=None):
 
 
 def test_segments_bins_bit_exact_config1(hip, ctx):
-    print("case: config 1 segments/bins", flush=True)
+    print("case: 1k strands at 256x256, segments/bins", flush=True)
     asset, cam, lights = hs.config(1)
     aid, ws, img, stats = _render(hip, ctx, asset, cam, lights)
     geom = R.strand_level(asset)
@@ -82,13 +82,13 @@ def test_segments_bins_bit_exact_config1(hip, ctx):
 
 
 def test_radiance_and_count_config1(hip, ctx):
-    print("case: config 1 radiance", flush=True)
+    print("case: 1k strands at 256x256, radiance", flush=True)
     asset, cam, lights = hs.config(1)
     aid, ws, img, stats = _render(hip, ctx, asset, cam, lights)
     ref, ras = R.render(R.strand_level(asset), cam, lights, mat_of(asset))
     assert stats["fragments"] == len(ras.seg)
     assert stats["overflow_pixels"] == 0
-    assert_radiance(img, ref, what="config 1")
+    assert_radiance(img, ref, what="1k strands at 256x256")
     ws.close()
 
 
@@ -103,7 +103,7 @@ def _oracle_lists(ras, x0, y0, w, h, W):
 
 
 def test_fragment_order_bit_exact(hip, ctx):
-    print("case: fragment lists config 1 rect", flush=True)
+    print("case: fragment lists, 1k strands at 256x256, rect", flush=True)
     asset, cam, lights = hs.config(1)
     aid = ctx.upload_asset(asset)
     geom = R.strand_level(asset)
@@ -248,7 +248,7 @@ def test_select_level_matches_oracle(hip, ctx):
 def test_config2_full_size_sampled(hip, ctx):
     """100k strands x 32 segments at 1920x1080: the GPU frame against the oracle on three
     sampled pixel rectangles (dense, medium, sparse), plus determinism at full size."""
-    print("case: config 2 full size", flush=True)
+    print("case: 100k strands at 1920x1080", flush=True)
     asset, cam, lights = hs.config(2)
     aid = ctx.upload_asset(asset)
     ws = ctx.workspace()
@@ -257,7 +257,7 @@ def test_config2_full_size_sampled(hip, ctx):
     torch.cuda.synchronize()
     assert torch.equal(img.view(torch.int32), img2.view(torch.int32))
     got = img.cpu().numpy()
-    print(f"config 2: {stats['fragments']} fragments, {stats['ms_total']:.3f} ms", flush=True)
+    print(f"100k strands at 1080p: {stats['fragments']} fragments, {stats['ms_total']:.3f} ms", flush=True)
     alpha = got[..., 3]
     ys, xs = np.nonzero(alpha > 0)
     order = np.argsort(alpha[ys, xs])
@@ -268,7 +268,7 @@ def test_config2_full_size_sampled(hip, ctx):
         x0 = int(min(max(xs[pk] - 8, 0), cam.width - 24))
         y0 = int(min(max(ys[pk] - 8, 0), cam.height - 24))
         ref, ras = R.render(geom, cam, lights, mat, rect=(x0, y0, 24, 24))
-        assert_radiance(got[y0:y0 + 24, x0:x0 + 24], ref[y0:y0 + 24, x0:x0 + 24], what=f"config 2 rect {x0},{y0}")
+        assert_radiance(got[y0:y0 + 24, x0:x0 + 24], ref[y0:y0 + 24, x0:x0 + 24], what=f"100k-strand 1080p rect {x0},{y0}")
     ws.close()
 
 

@@ -40,7 +40,7 @@ def ctx(hip):
 
 
 def test_rttd_strand_level(hip, ctx):
-    print("case: R/TT/D strands, config 1", flush=True)
+    print("case: R/TT/D strands, 1k strands at 256x256", flush=True)
     asset, cam, lights = hs.config(1)
     asset = _rttd(asset)
     aid = ctx.upload_asset(asset)
@@ -103,7 +103,7 @@ def test_rttd_mixed_frame(hip, ctx):
 def test_rttd_config2_full_size_sampled(hip, ctx):
     """100k strands x 32 segments at 1920x1080 (the benchmark's frame) with the R / TT / D
     material: the densest 24x24 rectangle against the oracle."""
-    print("case: R/TT/D config 2 full size", flush=True)
+    print("case: R/TT/D 100k strands at 1920x1080", flush=True)
     asset, cam, lights = hs.config(2)
     asset = _rttd(asset)
     aid = ctx.upload_asset(asset)
@@ -114,7 +114,7 @@ def test_rttd_config2_full_size_sampled(hip, ctx):
     y, x = np.unravel_index(np.argmax(a * (a < 1.0) + (a >= 1.0) * 0.5), a.shape)
     x0, y0 = int(min(max(x - 12, 0), cam.width - 24)), int(min(max(y - 12, 0), cam.height - 24))
     ref, ras = R.render(R.strand_level(asset), cam, lights, R.material(asset.material), rect=(x0, y0, 24, 24))
-    _check(got[y0:y0 + 24, x0:x0 + 24], ref[y0:y0 + 24, x0:x0 + 24], f"rttd config 2 rect {x0},{y0}")
+    _check(got[y0:y0 + 24, x0:x0 + 24], ref[y0:y0 + 24, x0:x0 + 24], f"rttd 100k-strand 1080p rect {x0},{y0}")
     ws.close()
     ctx.release(aid)
 
