@@ -2,6 +2,7 @@
 
     python -m paper_2405_10565_amd.experiments lod-sweep [--scale S]
     python -m paper_2405_10565_amd.experiments fit [--iters N] [--scale S]
+    python -m paper_2405_10565_amd.experiments shadow [--iters N]
 
 lod-sweep: 150k strands x 64 segments at 1920 x 1080, clustered by k-means on root position
 and first tangent into 10k, 1k and 100 thick hairs (Sec. 5.1); every level is rendered and
@@ -12,6 +13,9 @@ fit: 50k strands x 32 segments reduced to 500 thick hairs, 8 views on a ring at 
 one directional light; the thick hairs' semi-axes, radius and absorption are fitted by Adam
 (log parameters, lr 1e-2) so the coarse render matches the strand render; the adjoint is
 checked against central differences (h = 1e-3 in log space) on 20 random parameters.
+
+shadow: the 100k-strand 1080p frame with deep opacity map shadows (1024 x 1024 texels, 4
+layers of 2 cm, Sec. 5.2) rendered N times after two warm-up frames; GPU ms per frame.
 """
 from __future__ import annotations
 
@@ -141,9 +145,29 @@ def fit_report(hctx: B.Context, iters: int = 200, scale: float = 1.0, n_fd: int 
     return out
 
 
+def shadow_frames(hctx: B.Context, iters: int = 20, shadow=(1024, 4, 0.02)):
+    import torch
+    import hairsynth as hs
+    asset, cam, lights = hs.config(2)
+    aid = hctx.upload_asset(asset)
+    ws = hctx.workspace()
+    ms = []
+    for i in range(iters + 2):
+        _, st, _ = hctx.render_shadowed(aid, 0, cam, lights, shadow, ws=ws)
+        if i >= 2:
+            ms.append(st["ms_total"])
+    torch.cuda.synchronize()
+    ws.close()
+    hctx.release(aid)
+    return {"experiment": "shadow", "strands": asset.n_strands, "width": cam.width, "height": cam.height,
+            "resolution": shadow[0], "layers": shadow[1], "layer_depth": shadow[2], "frames": iters,
+            "fragments": int(st["fragments"]), "frame_ms_p50": round(float(np.percentile(ms, 50)), 4),
+            "frame_ms_mean": round(float(np.mean(ms)), 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["lod-sweep", "fit"])
+    ap.add_argument("what", choices=["lod-sweep", "fit", "shadow"])
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--iters", type=int, default=200)
     args = ap.parse_args()
@@ -152,6 +176,8 @@ def main():
     hctx = B.Context(0)
     if args.what == "lod-sweep":
         print(json.dumps(lod_sweep(hctx, args.scale)), flush=True)
+    elif args.what == "shadow":
+        print(json.dumps(shadow_frames(hctx, args.iters if args.iters != 200 else 20)), flush=True)
     else:
         print(json.dumps(fit_report(hctx, args.iters, args.scale)), flush=True)
     hctx.close()
