@@ -20,7 +20,8 @@
  *   - memory the library allocates (assets, LoD levels, workspaces) counts against the
  *     context's HBM budget; exceeding it returns HAIR_ENOMEM and allocates nothing.
  *   - a context may be used from several threads; renders on distinct workspaces may run
- *     concurrently.  One workspace serves one call at a time.
+ *     concurrently.  One workspace serves one call at a time, and a workspace holding a frame
+ *     of hair_render_async serves no other call until hair_ws_finish.
  *   - a HIP runtime error makes the call return HAIR_EDEVICE and poisons the context: every
  *     later call on it fails with HAIR_EDEVICE.
  */
