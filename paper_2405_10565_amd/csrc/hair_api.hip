@@ -1158,7 +1158,11 @@ int hair_ws_finish(hair_ws* ws, hair_stats* stats) {
     Asset* a;
     LevelDev lv;
     const int T = ((pd.cam.width + kTile - 1) / kTile) * ((pd.cam.height + kTile - 1) / kTile);
-    if ((rc = find_level(ctx, pd.asset, pd.level, &a, &lv))) {
+    if (!pd.done) {   // the frame's work ends before anything else happens to the workspace
+        if (ctx->device >= 0) HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+        HIP_TRY(ctx, hipEventSynchronize(ws->ev[1]), "hipEventSynchronize");
+    }
+    if ((rc = find_level(ctx, pd.asset, pd.level, &a, &lv))) {   // (released since: no rerun possible)
         pd.active = false;
         return rc;
     }
@@ -1168,8 +1172,6 @@ int hair_ws_finish(hair_ws* ws, hair_stats* stats) {
         fo.n_batches = pd.n_batches;
         for (int i = 0; i < 4; ++i) fo.ms[i] = pd.ms[i];
     } else {
-        if (ctx->device >= 0) HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
-        HIP_TRY(ctx, hipEventSynchronize(ws->ev[1]), "hipEventSynchronize");
         fo.ctr = *ws->ctr_host;
         if (fo.ctr.cap_overflow) {   // the frame outgrew the capacities: render it again, cold
             const hair_ws::Pending p = pd;

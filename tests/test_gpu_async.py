@@ -123,3 +123,22 @@ def test_held_workspace_refuses_other_calls(hip, ctx, scene):
     torch.cuda.synchronize()
     ref, _ = _sync(ctx, aid, cam, lights)
     assert _same(out, ref)
+
+
+def test_asset_released_before_finish(hip, ctx, scene):
+    print("case: asset released while its frame is held", flush=True)
+    asset, aid, lights = scene
+    cam = hs.camera_for(asset, 128, 96)
+    tmp = ctx.upload_asset(asset)
+    ws = ctx.workspace()
+    ctx.render(tmp, 0, cam, lights, ws=ws)
+    out = torch.empty((96, 128, 4), dtype=torch.float32, device="cuda:0")
+    ctx.render_async(tmp, 0, cam, lights, out, ws)
+    ctx.release(tmp)                                 # waits for the device before freeing
+    _, rc = ws.finish(raise_on_error=False)
+    assert rc == hip.HAIR_ENOENT
+    img, st, rc2 = ctx.render(aid, 0, cam, lights, ws=ws)   # the workspace is free again
+    torch.cuda.synchronize()
+    ref, _ = _sync(ctx, aid, cam, lights)
+    assert rc2 == hip.HAIR_OK and _same(img, ref)
+    ws.close()
