@@ -1459,7 +1459,7 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
     // each fragment's segment inputs are fetched one fragment ahead, so that the gathers
     // overlap the shading arithmetic instead of stalling it.  (Not for the R / TT / TRT
     // thick-hair shading: its registers would then exceed the budget of three waves per SIMD.)
-    constexpr bool kAhead = (KIND == 0 && !(SHADOW && MODEL == 0)) || MODEL == 1;
+    constexpr bool kAhead = KIND == 0 || MODEL == 1;
     uint32_t gs[kAhead ? kPerThread : 1];
     SegInputs nxt{};
     if (kAhead) {
