@@ -481,8 +481,17 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     HIP_TRY(ctx, launch_bins(ws->seg.as<SegRec>(), lv.nseg, cc, plan, ws->bin_m.as<uint32_t>(), ws->bin_blk.as<uint4>(),
                              ws->tile_cnt.as<uint32_t>(), tile_start, ws->ctr.as<Counters>(), scan_tmp, st),
             "k_bin_count");
-    HIP_TRY(ctx, launch_tile_items(tile_start, T, ws->items.as<uint32_t>(), st), "k_tile_items");
-    HIP_TRY(ctx, launch_exscan(ws->items.as<uint32_t>(), ws->item_start.as<uint32_t>(), T, scan_tmp, st), "k_scan");
+    // frames of up to 2^16 tiles scan and check their sizes in single-block kernels
+    const bool fused = T <= kScanOneBlockTiles;
+    const uint32_t kNoCap = 0xFFFFFFFFu;   // cold frames size their buffers from the sizes read back
+    if (fused) {
+        HIP_TRY(ctx, launch_items_scan(tile_start, T, ws->item_start.as<uint32_t>(), ws->ctr.as<Counters>(),
+                                       warm ? ws->caps.pairs : kNoCap, warm ? ws->caps.items : kNoCap, st),
+                "k_items_scan");
+    } else {
+        HIP_TRY(ctx, launch_tile_items(tile_start, T, ws->items.as<uint32_t>(), st), "k_tile_items");
+        HIP_TRY(ctx, launch_exscan(ws->items.as<uint32_t>(), ws->item_start.as<uint32_t>(), T, scan_tmp, st), "k_scan");
+    }
     FrameCaps caps = ws->caps;
     uint32_t pairs = 0, n_items = 0;
     if (!warm) {
@@ -533,7 +542,7 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     f.frag_base = ws->frag_base.as<uint32_t>();
     f.batch_start = ws->batch_start.as<uint32_t>();
     f.ctr = ws->ctr.as<Counters>();
-    HIP_TRY(ctx, launch_check_caps(f, caps, 1, st), "k_check_caps");
+    if (!fused) HIP_TRY(ctx, launch_check_caps(f, caps, 1, st), "k_check_caps");
     HIP_TRY(ctx, launch_scatter(f.seg, lv.nseg, cc, plan, tile_start, ws->bin_m.as<uint32_t>(), ws->list.as<uint32_t>(),
                                 f.ctr, st),
             "k_scatter");
@@ -542,8 +551,14 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     const uint32_t item_grid = warm ? caps.items : n_items;
     HIP_TRY(ctx, launch_count(f, cc, item_grid, st), "k_count");
     HIP_TRY(ctx, launch_tile_prep(f, st), "k_tile_prep");
-    HIP_TRY(ctx, launch_exscan(f.tile_tot, ws->frag_base.as<uint32_t>(), T, scan_tmp, st), "k_scan");
-    HIP_TRY(ctx, launch_exscan(f.tile_nb, ws->batch_start.as<uint32_t>(), T, scan_tmp, st), "k_scan");
+    if (fused) {
+        HIP_TRY(ctx, launch_tile_scans(f, ws->frag_base.as<uint32_t>(), ws->batch_start.as<uint32_t>(),
+                                       warm ? caps.frags : kNoCap, warm ? caps.batches : kNoCap, st),
+                "k_tile_scans");
+    } else {
+        HIP_TRY(ctx, launch_exscan(f.tile_tot, ws->frag_base.as<uint32_t>(), T, scan_tmp, st), "k_scan");
+        HIP_TRY(ctx, launch_exscan(f.tile_nb, ws->batch_start.as<uint32_t>(), T, scan_tmp, st), "k_scan");
+    }
     uint32_t n_frags = 0, n_batches = 0;
     if (!warm) {
         uint32_t sizes2[2] = {0, 0};
@@ -561,7 +576,7 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     if ((rc = ws_need(ws, ws->batches, 16ull * caps.batches))) return rc;
     f.frags = ws->frags.as<uint2>();
     f.batches = ws->batches.as<uint4>();
-    HIP_TRY(ctx, launch_check_caps(f, caps, 2, st), "k_check_caps");
+    if (!fused) HIP_TRY(ctx, launch_check_caps(f, caps, 2, st), "k_check_caps");
     const uint32_t batch_grid = warm ? caps.batches : n_batches;
     HIP_TRY(ctx, launch_batch_records(f, st), "k_batch_records");
     HIP_TRY(ctx, launch_emit(f, cc, item_grid, st), "k_emit");

@@ -224,6 +224,13 @@ hipError_t launch_scatter(const SegRec* seg, int32_t nseg, const CamConst& cam, 
 // later pass that would fill a sized buffer does nothing once the flag is set.
 hipError_t launch_check_caps(const FrameBufs& f, const FrameCaps& caps, int stage, hipStream_t st);
 hipError_t launch_tile_items(const uint32_t* tile_start, int T, uint32_t* items, hipStream_t st);
+// Fused single-block forms for frames of at most kScanOneBlockTiles tiles: the items and their
+// scan with the first capacity check; the fragment and batch offsets with the second.
+constexpr int kScanOneBlockTiles = 1 << 16;
+hipError_t launch_items_scan(const uint32_t* tile_start, int T, uint32_t* item_start, Counters* ctr,
+                             uint32_t cap_pairs, uint32_t cap_items, hipStream_t st);
+hipError_t launch_tile_scans(const FrameBufs& f, uint32_t* frag_base, uint32_t* batch_start, uint32_t cap_frags,
+                             uint32_t cap_batches, hipStream_t st);
 // Per-group LoD: initial levels, deferred update in place, and a mixed frame's selection
 // (cnt and sel_start: G*S and G*S + 1 words; sel: one entry per selected segment).
 hipError_t launch_lod_init(const HierDev& h, const CamConst& cam, float eps_w, int32_t* levels, hipStream_t st);

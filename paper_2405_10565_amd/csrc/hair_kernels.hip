@@ -416,6 +416,86 @@ __global__ __launch_bounds__(1024) void k_scan1(const uint32_t* __restrict__ cnt
     if (t == 0) start[n] = carry;
 }
 
+// Single-block exclusive scan of n values get(i) into put(i, prefix); returns the total.  The
+// caller's block has 1024 threads; n up to kScanOneBlock.
+template <class G, class P>
+__device__ inline uint32_t block_scan_1024(int n, G get, P put, uint32_t* s_w) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    uint32_t carry = 0;
+    for (int base = 0; base < n; base += 4096) {
+        const int i0 = base + 4 * t;
+        uint32_t v[4], sum = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = i0 + k < n ? get(i0 + k) : 0u;
+            sum += v[k];
+        }
+        uint32_t x = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) s_w[w] = x;
+        __syncthreads();
+        uint32_t wbase = 0, total = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const uint32_t a = s_w[k];
+            if (k < w) wbase += a;
+            total += a;
+        }
+        uint32_t run = carry + wbase + (x - sum);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (i0 + k < n) put(i0 + k, run);
+            run += v[k];
+        }
+        carry += total;
+        __syncthreads();
+    }
+    return carry;
+}
+
+// Work items of the count and emit passes (kNT list entries of a tile each), their exclusive
+// scan, and the first capacity check (list entries and items against their buffers), in one
+// block: the work of k_tile_items, k_scan1 and k_check_caps stage 1 for up to kScanOneBlock tiles.
+__global__ __launch_bounds__(1024) void k_items_scan(const uint32_t* __restrict__ tile_start, int T,
+                                                     uint32_t* __restrict__ item_start, Counters* ctr, uint32_t cap_pairs,
+                                                     uint32_t cap_items) {
+    __shared__ uint32_t s_w[16];
+    const uint32_t items = block_scan_1024(
+        T, [&](int i) { return (tile_start[i + 1] - tile_start[i] + kNT - 1) / kNT; },
+        [&](int i, uint32_t v) { item_start[i] = v; }, s_w);
+    if (threadIdx.x == 0) {
+        const uint32_t pairs = tile_start[T];
+        item_start[T] = items;
+        ctr->sizes[0] = pairs;
+        ctr->sizes[1] = items;
+        if (pairs > cap_pairs || items > cap_items) ctr->cap_overflow = 1u;
+    }
+}
+
+// The tiles' fragment and batch offsets (exclusive scans of tile_tot and tile_nb) and the
+// second capacity check, in one block (k_scan1 twice and k_check_caps stage 2).
+__global__ __launch_bounds__(1024) void k_tile_scans(const uint32_t* __restrict__ tile_tot,
+                                                     uint32_t* __restrict__ frag_base, const uint32_t* __restrict__ tile_nb,
+                                                     uint32_t* __restrict__ batch_start, int T, Counters* ctr,
+                                                     uint32_t cap_frags, uint32_t cap_batches) {
+    __shared__ uint32_t s_w[16];
+    const uint32_t frags = block_scan_1024(
+        T, [&](int i) { return tile_tot[i]; }, [&](int i, uint32_t v) { frag_base[i] = v; }, s_w);
+    const uint32_t batches = block_scan_1024(
+        T, [&](int i) { return tile_nb[i]; }, [&](int i, uint32_t v) { batch_start[i] = v; }, s_w);
+    if (threadIdx.x == 0) {
+        frag_base[T] = frags;
+        batch_start[T] = batches;
+        ctr->sizes[2] = frags;
+        ctr->sizes[3] = batches;
+        if (frags > cap_frags || batches > cap_batches) ctr->cap_overflow = 1u;
+    }
+}
+
 // The per-pixel counters of a frame: counts 0, key minima ~0, key maxima 0.
 __global__ void k_fill_pix(uint32_t* __restrict__ cnt, uint32_t* __restrict__ kmin, uint32_t* __restrict__ kmax,
                            size_t n) {
@@ -2584,6 +2664,19 @@ hipError_t launch_scatter(const SegRec* seg, int32_t nseg, const CamConst& cam, 
         hipLaunchKernelGGL(k_scatter, dim3(p.nb), dim3(kBinThreads), 4 * nt, st, seg, nseg, p.per_block, ntx, nty, t0,
                            nt, tile_start, M, list, ctr);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_items_scan(const uint32_t* tile_start, int T, uint32_t* item_start, Counters* ctr,
+                             uint32_t cap_pairs, uint32_t cap_items, hipStream_t st) {
+    hipLaunchKernelGGL(k_items_scan, dim3(1), dim3(1024), 0, st, tile_start, T, item_start, ctr, cap_pairs, cap_items);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_scans(const FrameBufs& f, uint32_t* frag_base, uint32_t* batch_start, uint32_t cap_frags,
+                             uint32_t cap_batches, hipStream_t st) {
+    hipLaunchKernelGGL(k_tile_scans, dim3(1), dim3(1024), 0, st, f.tile_tot, frag_base, f.tile_nb, batch_start, f.T,
+                       f.ctr, cap_frags, cap_batches);
     return hipGetLastError();
 }
 
