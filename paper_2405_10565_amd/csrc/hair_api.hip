@@ -546,8 +546,8 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     HIP_TRY(ctx, launch_scatter(f.seg, lv.nseg, cc, plan, tile_start, ws->bin_m.as<uint32_t>(), ws->list.as<uint32_t>(),
                                 f.ctr, st),
             "k_scatter");
-    HIP_TRY(ctx, launch_fill_pix(f.pix_cnt, f.pix_kmin, f.pix_kmax, TP, st), "fill");
-    if (rgba) HIP_TRY(ctx, launch_fill_f32(rgba, 0.0f, 4ull * cam->width * cam->height, st), "fill");
+    HIP_TRY(ctx, launch_fill_pix(f.pix_cnt, f.pix_kmin, f.pix_kmax, TP, rgba, (size_t)cam->width * cam->height, st),
+            "fill");
     const uint32_t item_grid = warm ? caps.items : n_items;
     HIP_TRY(ctx, launch_count(f, cc, item_grid, st), "k_count");
     HIP_TRY(ctx, launch_tile_prep(f, st), "k_tile_prep");

@@ -276,7 +276,8 @@ hipError_t launch_dom_resolve(const FrameBufs& f, const LevelDev& lv, const DomG
                               int32_t R, uint32_t n_blocks, float4* tex, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
 // The frame's per-pixel counters: n counts set to 0, key minima to ~0, key maxima to 0.
-hipError_t launch_fill_pix(uint32_t* cnt, uint32_t* kmin, uint32_t* kmax, size_t n, hipStream_t st);
+hipError_t launch_fill_pix(uint32_t* cnt, uint32_t* kmin, uint32_t* kmax, size_t n, float* rgba, size_t n_rgba4,
+                           hipStream_t st);   // also clears rgba (n_rgba4 pixels) when given
 hipError_t launch_fill_f32(float* p, float v, size_t n, hipStream_t st);
 
 }  // namespace hair

@@ -498,12 +498,15 @@ __global__ __launch_bounds__(1024) void k_tile_scans(const uint32_t* __restrict_
 
 // The per-pixel counters of a frame: counts 0, key minima ~0, key maxima 0.
 __global__ void k_fill_pix(uint32_t* __restrict__ cnt, uint32_t* __restrict__ kmin, uint32_t* __restrict__ kmax,
-                           size_t n) {
+                           size_t n, float4* __restrict__ rgba, size_t n_rgba) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         cnt[i] = 0u;
         kmin[i] = 0xFFFFFFFFu;
         kmax[i] = 0u;
     }
+    // (and the frame's image, transparent black, when one is given)
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_rgba; i += (size_t)gridDim.x * blockDim.x)
+        rgba[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 // Multi-block exclusive scan: each 1024-thread block scans kScanChunk counts and leaves its
@@ -2818,10 +2821,13 @@ hipError_t launch_check_caps(const FrameBufs& f, const FrameCaps& caps, int stag
     return hipGetLastError();
 }
 
-hipError_t launch_fill_pix(uint32_t* cnt, uint32_t* kmin, uint32_t* kmax, size_t n, hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    const int nb = (int)std::min<size_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_fill_pix, dim3(nb), dim3(256), 0, st, cnt, kmin, kmax, n);
+hipError_t launch_fill_pix(uint32_t* cnt, uint32_t* kmin, uint32_t* kmax, size_t n, float* rgba, size_t n_rgba4,
+                           hipStream_t st) {
+    const size_t m = std::max(n, n_rgba4);
+    if (m == 0) return hipSuccess;
+    const int nb = (int)std::min<size_t>((m + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_pix, dim3(nb), dim3(256), 0, st, cnt, kmin, kmax, n, reinterpret_cast<float4*>(rgba),
+                       rgba ? n_rgba4 : 0);
     return hipGetLastError();
 }
 
