@@ -61,7 +61,8 @@ def kernel_hash() -> str:
 
 
 def read_traffic():
-    """Bytes per k_tile launch from the committed counter summary, if it matches this source."""
+    """HBM bytes per k_batch launch from the committed counter summary, if it was measured on
+    the current kernel sources (else None)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
