@@ -290,12 +290,14 @@ def test_pixels_deeper_than_one_batch(hip, ctx):
     ws.close()
 
 
-@pytest.mark.parametrize("W,H", [(3840, 2160), (4112, 2320)])
+@pytest.mark.parametrize("W,H", [(3840, 2160), (4112, 2320), (4200, 4100)])
 def test_large_images_binning(hip, ctx, W, H):
-    """Tile binning at 4K (per-block tile counters above 64 KiB of LDS) and on an image with
-    more tiles than one binning pass holds (37,265 > 36,864: two passes).  The hair is framed
-    low so that it crosses the pass boundary; bins, fragment count and a rectangle of radiance
-    across the boundary match the oracle."""
+    """Tile binning at 4K (per-block tile counters above 64 KiB of LDS), on an image with more
+    tiles than one binning pass holds (37,265 > 36,864: two passes), and on one with more than
+    2^16 tiles (67,591: the multi-block scans and the separate capacity checks instead of the
+    single-block ones).  The hair is framed low so that it crosses the pass boundary; bins,
+    fragment count and a rectangle of radiance across the boundary match the oracle, and a
+    second (warm) frame on the same workspace equals the first bit for bit."""
     import dataclasses
     print(f"case: large image {W}x{H}", flush=True)
     asset = hs.make_asset(3000, 16, 90.0, seed=41)
@@ -318,6 +320,10 @@ def test_large_images_binning(hip, ctx, W, H):
     y0 = min(y0, H - 24)
     ref, ras = R.render(geom, cam, lights, mat_of(asset), rect=(x0, y0, 24, 24))
     assert_radiance(img[y0:y0 + 24, x0:x0 + 24], ref[y0:y0 + 24, x0:x0 + 24], what=f"{W}x{H} rect")
+    img2, st2, _ = ctx.render(aid, 0, cam, lights, ws=ws)
+    torch.cuda.synchronize()
+    assert st2["fragments"] == stats["fragments"]
+    assert np.array_equal(img2.cpu().numpy().view(np.uint32), np.asarray(img, dtype=np.float32).view(np.uint32))
     ws.close()
 
 
