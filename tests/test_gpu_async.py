@@ -142,3 +142,37 @@ def test_asset_released_before_finish(hip, ctx, scene):
     ref, _ = _sync(ctx, aid, cam, lights)
     assert rc2 == hip.HAIR_OK and _same(img, ref)
     ws.close()
+
+
+@pytest.mark.parametrize("material", ["rtt", "rttd"])
+def test_thick_hair_levels_async(hip, ctx, material):
+    """Thick-hair levels (and the R/TT/D material) through the deferred-check path: every level
+    of a small hierarchy, frames in flight on two workspaces, equal to synchronous frames."""
+    print(f"case: async thick-hair levels, {material}", flush=True)
+    import dataclasses
+    asset = hs.make_asset(1500, 10, 90.0, seed=27, sigma_spread=True)
+    if material == "rttd":
+        asset = dataclasses.replace(asset, material=hs.Material.rttd())
+    aid = ctx.upload_asset(asset)
+    ctx.build_lod(aid, hs.kmeans_hierarchy(asset, (300, 60, 10), seed=27))
+    cam = hs.camera_for(asset, 160, 120)
+    lights = hs.default_lights(asset, with_point=True)
+    wss = [ctx.workspace(), ctx.workspace()]
+    for ws in wss:
+        ctx.render(aid, 0, cam, lights, ws=ws)
+    outs = [torch.empty((120, 160, 4), dtype=torch.float32, device="cuda:0") for _ in range(4)]
+    for level in range(4):
+        ctx.render_async(aid, level, cam, lights, outs[level], wss[level % 2])
+        if level >= 1:
+            wss[(level - 1) % 2].finish()
+    wss[1].finish()
+    torch.cuda.synchronize()
+    for level in range(4):
+        ws = ctx.workspace()
+        ref, _, _ = ctx.render(aid, level, cam, lights, ws=ws)
+        torch.cuda.synchronize()
+        assert _same(outs[level], ref), level
+        ws.close()
+    for ws in wss:
+        ws.close()
+    ctx.release(aid)
