@@ -3,6 +3,7 @@
     python -m paper_2405_10565_amd.experiments lod-sweep [--scale S]
     python -m paper_2405_10565_amd.experiments fit [--iters N] [--scale S]
     python -m paper_2405_10565_amd.experiments shadow [--iters N]
+    python -m paper_2405_10565_amd.experiments curved [--scale S]
 
 lod-sweep: 150k strands x 64 segments at 1920 x 1080, clustered by k-means on root position
 and first tangent into 10k, 1k and 100 thick hairs (Sec. 5.1); every level is rendered and
@@ -13,6 +14,10 @@ fit: 50k strands x 32 segments reduced to 500 thick hairs, 8 views on a ring at 
 one directional light; the thick hairs' semi-axes, radius and absorption are fitted by Adam
 (log parameters, lr 1e-2) so the coarse render matches the strand render; the adjoint is
 checked against central differences (h = 1e-3 in log space) on 20 random parameters.
+
+curved: the LoD sweep's groom reduced to 1k thick hairs at 1080p, rendered with polyline
+centre lines and with curved ones tessellated to at most 4, 2 and 1 px per step (Sec. 5.2,
+Sec. 6); steps, fragments, frame ms and the RGB difference to the polyline frame.
 
 shadow: the 100k-strand 1080p frame with deep opacity map shadows (1024 x 1024 texels, 4
 layers of 2 cm, Sec. 5.2) rendered N times after two warm-up frames; GPU ms per frame.
@@ -145,6 +150,39 @@ def fit_report(hctx: B.Context, iters: int = 200, scale: float = 1.0, n_fd: int 
     return out
 
 
+def curved_frames(hctx: B.Context, scale: float = 1.0, repeats: int = 20, clusters: int = 1000):
+    import torch
+    import hairsynth as hs
+    asset, cam, lights = hs.config(3, scale)
+    aid = hctx.upload_asset(asset)
+    hctx.build_lod(aid, [hs.kmeans_assign(asset, max(1, int(round(clusters * scale))), seed=1003)])
+    ws = hctx.workspace()
+
+    def timed(fn):
+        img, st, _ = fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(repeats):
+            _, s2, _ = fn()
+            ms.append(s2["ms_total"])
+        return img.clone(), st, float(np.percentile(ms, 50))
+
+    out = {"experiment": "curved", "strands": asset.n_strands, "clusters": clusters, "width": cam.width,
+           "height": cam.height, "frames": []}
+    poly, st, ms = timed(lambda: hctx.render(aid, 1, cam, lights, ws=ws))
+    out["frames"].append({"centre_lines": "polyline", "steps": int(st["segments"]), "fragments": int(st["fragments"]),
+                          "frame_ms_p50": round(ms, 4), "rmse_vs_polyline": 0.0})
+    for max_px in (4, 2, 1):
+        img, st, ms = timed(lambda: hctx.render_curved(aid, 1, cam, lights, max_px, 16, ws=ws))
+        rmse, _ = _rgb_error(img, poly)
+        out["frames"].append({"centre_lines": f"curved, <= {max_px} px per step", "steps": int(st["segments"]),
+                              "fragments": int(st["fragments"]), "frame_ms_p50": round(ms, 4),
+                              "rmse_vs_polyline": round(rmse, 6)})
+    ws.close()
+    hctx.release(aid)
+    return out
+
+
 def shadow_frames(hctx: B.Context, iters: int = 20, shadow=(1024, 4, 0.02)):
     import torch
     import hairsynth as hs
@@ -167,7 +205,7 @@ def shadow_frames(hctx: B.Context, iters: int = 20, shadow=(1024, 4, 0.02)):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["lod-sweep", "fit", "shadow"])
+    ap.add_argument("what", choices=["lod-sweep", "fit", "shadow", "curved"])
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--iters", type=int, default=200)
     args = ap.parse_args()
@@ -176,6 +214,8 @@ def main():
     hctx = B.Context(0)
     if args.what == "lod-sweep":
         print(json.dumps(lod_sweep(hctx, args.scale)), flush=True)
+    elif args.what == "curved":
+        print(json.dumps(curved_frames(hctx, args.scale)), flush=True)
     elif args.what == "shadow":
         print(json.dumps(shadow_frames(hctx, args.iters if args.iters != 200 else 20)), flush=True)
     else:
