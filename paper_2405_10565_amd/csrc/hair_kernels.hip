@@ -715,9 +715,10 @@ __global__ void k_fill_f32(float* p, float v, size_t n) {
 // |dy| >= |dx|, else columns; u names the major axis, v the minor one), and the lanes of a wave
 // share out all its (segment, line) pairs, 64 per round, so that a wave does not run as long
 // as its longest segment.  On a line, the candidates are the v whose pixel centre lies in the
-// strip |cross| <= R sqrt(t_den), widened by 1e-6 pixel, and in the segment's box widened by R;
-// the exact integer predicate decides, the slab 0 <= t_num < t_den included (t_num and |cross|
-// are symmetric under the exchange of x and y, so the same predicate serves both orientations).
+// strip |cross| <= R sqrt(t_den) (and, for wide segments, the slab 0 <= t_num <= t_den),
+// widened by 1e-6 pixel, and in the segment's box widened by R; the exact integer predicate
+// decides, the slab 0 <= t_num < t_den included (t_num and |cross| are symmetric under the
+// exchange of x and y, so the same predicate serves both orientations).
 //
 // 32-bit integers are exact here: endpoints lie inside the guard band, |dx|, |dy| <= kMaxAxis
 // (longer segments are culled), the radius is <= kMaxHwFx + 8 and every candidate pixel centre
@@ -730,7 +731,7 @@ __global__ void k_fill_f32(float* p, float v, size_t n) {
 struct CovSetup {
     int4 g0;     // (au, av, du, dv): start and extent along the major and minor axes, 1/16 px
     int4 g1;     // (R, tden, first line - lines before this lane in the wave, steep)
-    float4 g2;   // (1 / du, unused, R sqrt(tden) / |du|, bits: first | last minor index << 16)
+    float4 g2;   // (1 / du, 1 / dv or 0, R sqrt(tden) / |du|, bits: first | last minor index << 16)
 };
 constexpr int kCovLinesPerWave = 64 * kTile;   // a segment has at most kTile lines in a tile
 
@@ -756,10 +757,11 @@ __device__ inline uint32_t cov_setup(const SegRec& s, bool valid, int px0, int p
             const int du = steep ? dy : dx, dv = steep ? dx : dy;
             nl = (uint32_t)(steep ? j1 - j0 + 1 : i1 - i0 + 1);
             const float inv_du = __builtin_amdgcn_rcpf((float)du);
+            const float inv_dv = dv != 0 ? __builtin_amdgcn_rcpf((float)dv) : 0.0f;
             const int vmin = steep ? i0 : j0, vmax = steep ? i1 : j1;   // 0 <= vmin <= vmax < 2^16
             c.g0 = make_int4(au, av, du, dv);
             c.g1 = make_int4(R, tden, steep ? j0 : i0, steep ? 1 : 0);
-            c.g2 = make_float4(inv_du, 0.0f, (float)R * __builtin_amdgcn_sqrtf((float)tden) * fabsf(inv_du),
+            c.g2 = make_float4(inv_du, inv_dv, (float)R * __builtin_amdgcn_sqrtf((float)tden) * fabsf(inv_du),
                                __int_as_float(vmin | (vmax << 16)));
         }
     }
@@ -796,11 +798,20 @@ __device__ inline void wave_coverage(const CovSetup* s_cov, const uint8_t* s_own
         const int vmin = vb & 0xFFFF, vmax = vb >> 16;
         const unsigned long long RR = (unsigned long long)(unsigned)(R * R) * (unsigned)tden;
         const int eu = 16 * u + 8 - au;
-        // the strip alone bounds the span (the slab would only trim the end lines, whose extra
-        // candidates the integer test rejects; lines already stop at the box widened by R)
+        // the strip bounds the span; the slab trims it too for wide segments (radius above
+        // 2 px: thick hairs, whose short steps would otherwise test most of their box), while
+        // for strands it would only trim the end lines, whose extra candidates the integer
+        // test rejects
         const float cc = (float)(eu * dv) * c.g2.x;
-        const float lo_f = cc - c.g2.z, hi_f = cc + c.g2.z;
-        const float mag = (fabsf((float)av) + fabsf(cc)) + c.g2.z;
+        float lo_f = cc - c.g2.z, hi_f = cc + c.g2.z;
+        float mag = (fabsf((float)av) + fabsf(cc)) + c.g2.z;
+        if (R > 32 && dv != 0) {
+            const float a = (float)(-eu * du) * c.g2.y;
+            const float b = (float)(tden - eu * du) * c.g2.y;
+            lo_f = fmaxf(lo_f, fminf(a, b));
+            hi_f = fminf(hi_f, fmaxf(a, b));
+            mag += fmaxf(fabsf(a), fabsf(b));
+        }
         const float w = 2e-6f * mag + 1.0f;
         const float flo = ceilf(((float)av + (lo_f - w) - 8.0f) * (1.0f / 16.0f));
         const float fhi = floorf(((float)av + (hi_f + w) - 8.0f) * (1.0f / 16.0f));
