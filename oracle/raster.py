@@ -177,8 +177,30 @@ def tile_ranges(XA, YA, XB, YB, hw_fx, vis, W, H, tile):
     return tx0, tx1, ty0, ty1
 
 
+def tile_meets_footprint(XA, YA, XB, YB, hw_fx, seg, tx, ty, tile):
+    """Whether the rectangle of tile (tx, ty)'s pixel centres meets segment seg's footprint
+    (slab 0 <= t_num <= t_den, strip |cross| <= R sqrt(t_den)), by projecting its four corner
+    centres on the segment's direction and normal (exact integers).  Applied to wide segments
+    (R above 32 sub-pixels, 2 px); thin and zero-length segments keep every tile of their box."""
+    xa, ya = XA[seg].astype(np.int64), YA[seg].astype(np.int64)
+    dx, dy = XB[seg].astype(np.int64) - xa, YB[seg].astype(np.int64) - ya
+    tden = dx * dx + dy * dy
+    R = hw_fx[seg].astype(np.int64) + 8
+    RR = R * R * tden
+    ex0 = 16 * tile * tx.astype(np.int64) + 8 - xa
+    ey0 = 16 * tile * ty.astype(np.int64) + 8 - ya
+    span = 16 * (tile - 1)
+    tn = [ex * dx + ey * dy for ex in (ex0, ex0 + span) for ey in (ey0, ey0 + span)]
+    cr = [ex * dy - ey * dx for ex in (ex0, ex0 + span) for ey in (ey0, ey0 + span)]
+    tmin, tmax = np.minimum.reduce(tn), np.maximum.reduce(tn)
+    cmin, cmax = np.minimum.reduce(cr), np.maximum.reduce(cr)
+    apart = (tmax < 0) | (tmin > tden) | ((cmin > 0) & (cmin * cmin >= RR)) | ((cmax < 0) & (cmax * cmax >= RR))
+    return (tden <= 0) | (R <= 32) | ~apart
+
+
 def bins(XA, YA, XB, YB, hw_fx, vis, W, H, tile):
-    """(tile_id, seg_id) pairs, sorted by tile then segment id."""
+    """(tile_id, seg_id) pairs, sorted by tile then segment id: the tiles of each segment's box
+    widened by its radius whose pixel centres can meet its footprint."""
     tx0, tx1, ty0, ty1 = tile_ranges(XA, YA, XB, YB, hw_fx, vis, W, H, tile)
     ntx = (W + tile - 1) // tile
     nx = np.maximum(tx1 - tx0 + 1, 0)
@@ -190,6 +212,9 @@ def bins(XA, YA, XB, YB, hw_fx, vis, W, H, tile):
     nxs = nx[seg]
     tx = tx0[seg] + local % np.maximum(nxs, 1)
     ty = ty0[seg] + local // np.maximum(nxs, 1)
+    keep = tile_meets_footprint(XA, YA, XB, YB, hw_fx, seg, tx, ty, tile)
+    seg, tx, ty = seg[keep], tx[keep], ty[keep]
+    cnt = np.bincount(seg, minlength=XA.size)
     tid = ty * ntx + tx
     order = np.lexsort((seg, tid))
     return tid[order], seg[order], cnt

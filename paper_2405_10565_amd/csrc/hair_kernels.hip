@@ -554,6 +554,37 @@ __global__ __launch_bounds__(1024) void k_scan_add(uint32_t* __restrict__ out, c
 // [t0, t0 + nt) (the whole image unless it has more than kMaxLdsTiles tiles); the counts form
 // row b of M [nb][T].  A column-wise exclusive scan of M gives each block its place inside
 // every tile list, and the scatter pass appends each segment at its block's LDS cursors.
+// A tile of the box of a wide segment (radius above 2 px) is kept only if the rectangle of its
+// pixel centres meets the segment's footprint (the slab 0 <= t_num <= t_den and the strip
+// |cross| <= R sqrt(t_den)): projected on the segment's direction and normal, the four corner
+// centres must overlap both.  Exact in integers (corner offsets below 2^15, products below
+// 2^30, cross^2 and R^2 t_den in 64 bits); for short, wide segments (thick hairs) this drops
+// the many box tiles beyond the segment's ends.  Thin segments keep their box's tiles.
+__device__ inline bool tile_meets_footprint(const SegRec& r, int tx, int ty) {
+    const int R = (r.hwfx & kHwMask) + 8;
+    if (R <= 32) return true;
+    const int dx = r.xb - r.xa, dy = r.yb - r.ya;
+    const int tden = dx * dx + dy * dy;
+    if (tden <= 0) return true;
+    const unsigned long long RR = (unsigned long long)(unsigned)(R * R) * (unsigned)tden;
+    const int ex0 = 16 * kTile * tx + 8 - r.xa, ex1 = ex0 + 16 * (kTile - 1);
+    const int ey0 = 16 * kTile * ty + 8 - r.ya, ey1 = ey0 + 16 * (kTile - 1);
+    int tmin = 0x7FFFFFFF, tmax = -0x7FFFFFFF - 1, cmin = 0x7FFFFFFF, cmax = -0x7FFFFFFF - 1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int ex = (k & 1) ? ex1 : ex0, ey = (k & 2) ? ey1 : ey0;
+        const int tn = ex * dx + ey * dy, cr = ex * dy - ey * dx;
+        tmin = min(tmin, tn);
+        tmax = max(tmax, tn);
+        cmin = min(cmin, cr);
+        cmax = max(cmax, cr);
+    }
+    if (tmax < 0 || tmin > tden) return false;
+    if (cmin > 0 && (unsigned long long)((long long)cmin * cmin) >= RR) return false;
+    if (cmax < 0 && (unsigned long long)((long long)cmax * cmax) >= RR) return false;
+    return true;
+}
+
 template <class F>
 __device__ inline void for_each_tile_in_range(const SegRec& r, int ntx, int nty, int t0, int nt, F&& f) {
     if (!(r.hwfx & kFlagVisible)) return;
@@ -561,7 +592,7 @@ __device__ inline void for_each_tile_in_range(const SegRec& r, int ntx, int nty,
     for (int ty = rc.ty0; ty <= rc.ty1; ++ty)
         for (int tx = rc.tx0; tx <= rc.tx1; ++tx) {
             const int l = ty * ntx + tx - t0;
-            if ((unsigned)l < (unsigned)nt) f(l);
+            if ((unsigned)l < (unsigned)nt && tile_meets_footprint(r, tx, ty)) f(l);
         }
 }
 

@@ -102,6 +102,11 @@ def test_shared_vertex_counted_once():
 
 @pytest.mark.parametrize("tile", [8, 16])
 def test_binning_equals_brute_force_rectangles(tile):
+    """Bins = the tiles of each segment's box widened by R that hold a pixel centre of the
+    footprint's bounding region, checked against brute force over the tiles' pixel centres:
+    a box tile is dropped only if no pixel-centre grid point of the tile (extended over the
+    whole tile, image edge or not) satisfies 0 <= t_num <= t_den and cross^2 <= R^2 t_den in
+    real terms at the rectangle's corners; every kept tile passes the corner projections."""
     rng = np.random.default_rng(4)
     W, H = 70, 45
     XA, YA, XB, YB, hw_fx, vis = _random_segments(rng, 80, W, H)
@@ -115,11 +120,28 @@ def test_binning_equals_brute_force_rectangles(tile):
         Rr = int(hw_fx[s]) + 8
         lox, hix = min(XA[s], XB[s]) - Rr, max(XA[s], XB[s]) + Rr
         loy, hiy = min(YA[s], YB[s]) - Rr, max(YA[s], YB[s]) + Rr
+        dx, dy = int(XB[s] - XA[s]), int(YB[s] - YA[s])
+        tden = dx * dx + dy * dy
         for ty in range(nty):
             for tx in range(ntx):
                 x0, x1 = 16 * tile * tx, 16 * tile * (tx + 1) - 1
                 y0, y1 = 16 * tile * ty, 16 * tile * (ty + 1) - 1
-                if lox <= x1 and hix >= x0 and loy <= y1 and hiy >= y0:
+                if not (lox <= x1 and hix >= x0 and loy <= y1 and hiy >= y0):
+                    continue
+                if tden == 0 or Rr <= 32:   # thin or zero-length: the whole box
+                    brute.append((ty * ntx + tx, s))
+                    continue
+                # any point of the rectangle of this tile's pixel centres inside the footprint?
+                # (the footprint is convex and the conditions linear / quadratic in the point, so
+                # test the corners' projections: overlap on both axes of the segment's frame)
+                cs = [(16 * tile * tx + 8 + i * 16 * (tile - 1) - int(XA[s]),
+                       16 * tile * ty + 8 + j * 16 * (tile - 1) - int(YA[s])) for i in (0, 1) for j in (0, 1)]
+                tn = [ex * dx + ey * dy for ex, ey in cs]
+                cr = [ex * dy - ey * dx for ex, ey in cs]
+                slab = max(tn) >= 0 and min(tn) <= tden
+                strip = not ((min(cr) > 0 and min(cr) ** 2 >= Rr * Rr * tden) or
+                             (max(cr) < 0 and max(cr) ** 2 >= Rr * Rr * tden))
+                if slab and strip:
                     brute.append((ty * ntx + tx, s))
     assert list(zip(tid.tolist(), seg.tolist())) == sorted(brute)
     # every fragment's tile holds its segment (the binning is conservative)
@@ -181,3 +203,21 @@ def test_compositing_closed_forms():
     swapped = R.composite(ras2, a.flip(0), L.flip(0)).numpy()[0, 0]
     assert not np.allclose(swapped[:3], out[:3])        # the order matters
     assert np.isclose(swapped[3], out[3])               # coverage does not depend on it
+
+
+def test_binning_drops_the_box_tiles_beyond_a_wide_segments_ends():
+    """A short, wide segment (a thick hair's step): its footprint is a 2R-wide band of the
+    segment's length, so the box widened by R holds many tiles the footprint never reaches;
+    the bins keep every tile a fragment lands in and far fewer than the box."""
+    XA, YA, XB, YB = np.array([800]), np.array([800]), np.array([960]), np.array([800])
+    hw_fx = np.array([600]); vis = np.ones(1, bool)
+    W, H = 128, 128
+    tid, seg, _ = rs.bins(XA, YA, XB, YB, hw_fx, vis, W, H, 16)
+    tx0, tx1, ty0, ty1 = rs.tile_ranges(XA, YA, XB, YB, hw_fx, vis, W, H, 16)
+    box = int((tx1[0] - tx0[0] + 1) * (ty1[0] - ty0[0] + 1))
+    assert len(tid) < box
+    sg, pi, pj = rs.candidate_pixels(XA, YA, XB, YB, hw_fx, vis, W, H)
+    ok, *_ = rs.coverage(XA, YA, XB, YB, hw_fx, sg, pi, pj)
+    kept = set(tid.tolist())
+    hit = {(j // 16) * (-(-W // 16)) + i // 16 for i, j in zip(pi[ok], pj[ok])}
+    assert hit and hit <= kept
