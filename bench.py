@@ -174,7 +174,7 @@ def main():
         print(json.dumps({"copy_probe_bytes": src.numel() * 4, "launches": 5}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the renderer runs on one GPU; --gpus {args.gpus} is not supported "
               "(the renderer's multi-GPU split is a design note only)", file=sys.stderr)
         sys.exit(2)
 
