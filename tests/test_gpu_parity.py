@@ -272,6 +272,35 @@ def test_config2_full_size_sampled(hip, ctx):
     ws.close()
 
 
+def test_wide_thick_hairs_full_size_sampled(hip, ctx):
+    """Thick hairs tens of pixels wide at 1920x1080 (20k strands x 16 segments in 60
+    clusters): tile binning keeps only the tiles a wide segment's footprint can reach, and the
+    oracle enumerates pixels without any binning, so rectangles on the footprints' borders and
+    at the deepest pixel show a tile dropped by mistake as missing coverage."""
+    print("case: wide thick hairs at 1920x1080", flush=True)
+    asset, cam, lights, assign = _cluster_case(n=20000, segs=16, k=60, W=1920, H=1080, seed=33)
+    lod = OL.build_level(asset, assign)
+    aid, ws, img, stats = _render(hip, ctx, asset, cam, lights, level=1, lod=lod)
+    alpha = img[..., 3]
+    inside = alpha > 0
+    edge = inside & ~(np.roll(inside, 1, 0) & np.roll(inside, -1, 0) & np.roll(inside, 1, 1) & np.roll(inside, -1, 1))
+    ys, xs = np.nonzero(edge)
+    assert ys.size > 0
+    rng = np.random.default_rng(33)
+    picks = [(int(ys[i]), int(xs[i])) for i in rng.choice(ys.size, size=3, replace=False)]
+    picks.append(tuple(int(v) for v in np.unravel_index(np.argmax(alpha * (alpha < 1.0)), alpha.shape)))
+    geom = R.cluster_level(lod)
+    mat = mat_of(asset)
+    print(f"wide thick hairs: {stats['fragments']} fragments", flush=True)
+    for y, x in picks:
+        x0 = int(min(max(x - 12, 0), cam.width - 24))
+        y0 = int(min(max(y - 12, 0), cam.height - 24))
+        ref, ras = R.render(geom, cam, lights, mat, rect=(x0, y0, 24, 24))
+        assert_radiance(img[y0:y0 + 24, x0:x0 + 24], ref[y0:y0 + 24, x0:x0 + 24],
+                        what=f"wide thick hairs 1080p rect {x0},{y0}")
+    ws.close()
+    ctx.release(aid)
+
 def test_pixels_deeper_than_one_batch(hip, ctx):
     """A dense asset seen small: pixels hold more fragments than one LDS batch (1536) and are
     rendered in exact depth-key slices; radiance and count still match the oracle."""
