@@ -81,3 +81,46 @@ def test_unsplit_curve_is_the_plain_level(hip, ctx):
     assert torch.equal(a.view(torch.int32), b.view(torch.int32))
     ws.close()
     ctx.release(aid)
+
+
+def test_curved_wide_hairs_full_size_sampled(hip, ctx):
+    """Curved thick hairs up to ~150 px in radius at 1920x1080 (20k strands x 16 segments in 60
+    clusters, at most 2 px per step): every tessellated record bit-exact, and the radiance on
+    rectangles at the footprints' borders and at the deepest pixel against the oracle, which
+    enumerates pixels without tile binning."""
+    print("case: curved wide thick hairs at 1920x1080", flush=True)
+    asset = hs.make_asset(20000, 16, 90.0, seed=34, sigma_spread=True)
+    cam = hs.camera_for(asset, 1920, 1080)
+    lights = hs.default_lights(asset, with_point=True)
+    lod = OL.build_level(asset, hs.kmeans_assign(asset, 60, seed=34))
+    aid = ctx.upload_asset(asset)
+    ctx.set_lod(aid, 1, lod)
+    ws = ctx.workspace()
+    img, st, _ = ctx.render_curved(aid, 1, cam, lights, 2, 16, ws=ws)
+    geom = CV.curved_geometry(lod, cam, 2, 16)
+    n = geom.pA.shape[1]
+    assert st["segments"] == n
+    c, XA, YA, XB, YB, izA, izB, hw, hw_fx, vis = R.segment_records(geom, cam)
+    ri, rf = ctx.debug_segments(ws, n)
+    v = (ri[:, 5] & 1).astype(bool)
+    assert np.array_equal(v, vis)
+    for col, ref in enumerate((XA, YA, XB, YB, hw_fx)):
+        assert np.array_equal(ri[v, col], ref[vis]), col
+    got = img.cpu().numpy()
+    alpha = got[..., 3]
+    inside = alpha > 0
+    edge = inside & ~(np.roll(inside, 1, 0) & np.roll(inside, -1, 0) & np.roll(inside, 1, 1) & np.roll(inside, -1, 1))
+    ys, xs = np.nonzero(edge)
+    assert ys.size > 0
+    rng = np.random.default_rng(34)
+    picks = [(int(ys[i]), int(xs[i])) for i in rng.choice(ys.size, size=3, replace=False)]
+    picks.append(tuple(int(q) for q in np.unravel_index(np.argmax(alpha * (alpha < 1.0)), alpha.shape)))
+    mat = R.material(asset.material)
+    print(f"curved wide thick hairs: {n} segments, {st['fragments']} fragments", flush=True)
+    for y, x in picks:
+        x0 = int(min(max(x - 12, 0), cam.width - 24))
+        y0 = int(min(max(y - 12, 0), cam.height - 24))
+        ref, _ = R.render(geom, cam, lights, mat, rect=(x0, y0, 24, 24))
+        _check(got[y0:y0 + 24, x0:x0 + 24], ref[y0:y0 + 24, x0:x0 + 24], f"curved wide 1080p rect {x0},{y0}")
+    ws.close()
+    ctx.release(aid)
