@@ -109,3 +109,56 @@ def test_mixed_errors(hip, scene):
     with pytest.raises(hip.HairError):
         ctx.lod_groups(aid2)
     ctx.release(aid2)
+
+
+def test_mixed_frame_full_size_sampled(hip):
+    """A mixed-level frame at 1920x1080 (20k strands x 16 segments; 2000 / 300 / 40 thick
+    hairs; a random level per group and segment): every projected row bit-exact, the deferred
+    level update equal, and the radiance on rectangles at coverage borders and at the deepest
+    pixel against the oracle."""
+    print("case: mixed frame at 1920x1080", flush=True)
+    ctx = hip.Context(0)
+    asset = hs.make_asset(20000, 16, 90.0, seed=35, sigma_spread=True)
+    assigns = hs.kmeans_hierarchy(asset, (2000, 300, 40), seed=35)
+    aid = ctx.upload_asset(asset)
+    ctx.build_lod(aid, assigns)
+    lods = [_lod_dict(ctx.get_lod(aid, l)) for l in range(1, 4)]
+    geoms = M.level_geoms(asset, lods)
+    grps = M.groups(assigns)
+    cam = hs.camera_for(asset, 1920, 1080)
+    lights = hs.default_lights(asset, with_point=True)
+    G, S = ctx.lod_groups(aid), asset.segs
+    levels = np.random.default_rng(35).integers(0, 4, size=(G, S)).astype(np.int32)
+    lev = torch.tensor(levels, device="cuda:0")
+    ws = ctx.workspace()
+    img, st, _ = ctx.render_mixed(aid, cam, lights, lev, eps_w=2.0, ws=ws)
+    torch.cuda.synchronize()
+    mixed = M.mixed_geometry(geoms, grps, levels)
+    n = mixed.pA.shape[1]
+    assert st["segments"] == n
+    c, XA, YA, XB, YB, izA, izB, hw, hw_fx, vis = R.segment_records(mixed, cam)
+    ri, rf = ctx.debug_segments(ws, n)
+    assert np.array_equal((ri[:, 5] & 1).astype(bool), vis)
+    for col, ref in enumerate((XA, YA, XB, YB, hw_fx)):
+        assert np.array_equal(ri[vis, col], ref[vis]), col
+    assert np.array_equal(lev.cpu().numpy(), M.update_levels(geoms, grps, cam, 2.0, levels))
+    got = img.cpu().numpy().astype(np.float64)
+    alpha = got[..., 3]
+    inside = alpha > 0
+    edge = inside & ~(np.roll(inside, 1, 0) & np.roll(inside, -1, 0) & np.roll(inside, 1, 1) & np.roll(inside, -1, 1))
+    ys, xs = np.nonzero(edge)
+    rng = np.random.default_rng(36)
+    picks = [(int(ys[i]), int(xs[i])) for i in rng.choice(ys.size, size=2, replace=False)]
+    picks.append(tuple(int(q) for q in np.unravel_index(np.argmax(alpha * (alpha < 1.0)), alpha.shape)))
+    mat = tuple(float(v) for v in asset.material.as_array())
+    print(f"mixed 1080p: {n} segments, {st['fragments']} fragments", flush=True)
+    for y, x in picks:
+        x0 = int(min(max(x - 12, 0), cam.width - 24))
+        y0 = int(min(max(y - 12, 0), cam.height - 24))
+        ref, _ = R.render(mixed, cam, lights, mat, rect=(x0, y0, 24, 24))
+        err = np.abs(got - ref)[y0:y0 + 24, x0:x0 + 24] - (RTOL * np.abs(ref) + ATOL)[y0:y0 + 24, x0:x0 + 24]
+        print(f"[mixed 1080p rect {x0},{y0}] violations {int((err > 0).sum())}", flush=True)
+        assert int((err > 0).sum()) == 0
+    ws.close()
+    ctx.release(aid)
+    ctx.close()
