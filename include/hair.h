@@ -211,6 +211,26 @@ int hair_render(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const 
                 const hair_light* lights, int32_t n_lights, float* rgba_out, void* stream,
                 hair_stats* stats);
 
+/* The frame of hair_render (same operation, same output, same errors) for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  The call allocates nothing (no hipMalloc, hipFree, pinned host memory or
+ * event creation): its scratch buffers are carved, per frame and at their exact sizes, from a
+ * static device array of hair_noalloc_scratch_bytes() bytes (64 MiB) that every device the
+ * library runs on holds until the process ends; the context set it up when it was created.
+ * A frame needing more returns HAIR_ENOMEM before the image is written (e.g. 1,000 strands x
+ * 16 segments at 256 x 256 needs about 4 MB; a 1920 x 1080 frame of 100k x 32 strands does not
+ * fit).  Inputs (the resident asset) and the output (device float[height][width][4],
+ * caller-owned) are as for hair_render.  The frame is sized on the device, read back twice
+ * and synchronised at its end, as a first hair_render on a workspace.  Every call on one
+ * device shares that device's scratch, which keeps the last call's contents: calls on one
+ * context are serialised, but calls that overlap on one device from different contexts race
+ * and must not be made. */
+int hair_render_noalloc(hair_ctx* ctx, int32_t asset, int32_t level, const hair_camera* cam,
+                        const hair_light* lights, int32_t n_lights, float* rgba_out, void* stream,
+                        hair_stats* stats);
+/* Size in bytes of the static scratch of hair_render_noalloc. */
+uint64_t hair_noalloc_scratch_bytes(void);
+
 /* The same frame as hair_render (same operation, same output) without waiting for it: on a
  * workspace that has rendered before (its buffer capacities are known) the frame is enqueued
  * on `stream` and the call returns at once, so that a caller can keep frames in flight (one

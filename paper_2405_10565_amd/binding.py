@@ -28,7 +28,8 @@ EXPORTS = [
     "hair_build_lod", "hair_lod_info", "hair_get_lod", "hair_set_lod", "hair_set_cluster_params",
     "hair_select_level", "hair_render", "hair_render_backward", "hair_debug_segments", "hair_debug_bins",
     "hair_debug_fragments", "hair_lod_groups", "hair_lod_init", "hair_render_mixed", "hair_render_shadowed",
-    "hair_debug_dom", "hair_render_curved", "hair_render_async", "hair_ws_finish",
+    "hair_debug_dom", "hair_render_curved", "hair_render_async", "hair_ws_finish", "hair_render_noalloc",
+    "hair_noalloc_scratch_bytes",
 ]
 
 
@@ -119,6 +120,9 @@ def _load():
                          C.POINTER(hair_stats)], C.c_int),
         "hair_render_async": ([P, P, I32, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32, P, P], C.c_int),
         "hair_ws_finish": ([P, C.POINTER(hair_stats)], C.c_int),
+        "hair_render_noalloc": ([P, I32, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32, P, P,
+                                 C.POINTER(hair_stats)], C.c_int),
+        "hair_noalloc_scratch_bytes": ([], U64),
         "hair_render_backward": ([P, P, I32, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32, P, P, P, P, P],
                                  C.c_int),
         "hair_lod_groups": ([P, I32, ip], C.c_int),
@@ -343,6 +347,21 @@ class Context:
         st = hair_stats()
         rc = lib.hair_render(self.handle, ws.handle if ws else None, asset, level, C.byref(c), la, nl,
                              C.c_void_p(out.data_ptr()), _stream_ptr(stream), C.byref(st))
+        if raise_on_error:
+            check(rc)
+        return out, st.as_dict(), rc
+
+    def render_noalloc(self, asset: int, level: int, cam, lights, out, stream=None, raise_on_error: bool = True):
+        """hair_render_noalloc into `out` (torch float32 [H, W, 4] on the context's device, given
+        by the caller: the call allocates nothing).  Returns (out, stats dict, status code)."""
+        import torch
+        c = make_camera(cam)
+        la, nl = make_lights(lights)
+        assert out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+        assert tuple(out.shape) == (c.height, c.width, 4)
+        st = hair_stats()
+        rc = lib.hair_render_noalloc(self.handle, asset, level, C.byref(c), la, nl, C.c_void_p(out.data_ptr()),
+                                     _stream_ptr(stream), C.byref(st))
         if raise_on_error:
             check(rc)
         return out, st.as_dict(), rc

@@ -2,6 +2,7 @@
 // workspaces, host-side argument validation (always before any launch), and the frame
 // orchestration around the kernels of hair_kernels.hip.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -57,6 +58,32 @@ struct Asset {
     Hierarchy hier;
 };
 
+// Static scratch of hair_render_noalloc: every device the library runs on holds one copy of
+// it until the process ends.  In host code the name stands for a host-side shadow, not a
+// device address; host code uses only the per-device address that hipGetSymbolAddress
+// returned for it (scratch_ptr below).
+constexpr size_t kScratchBytes = 64ull << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char*> g_scratch_ptr;   // device -> its copy of scratch
+
+// The device's copy of scratch; the device must be current.  Looked up once per device.
+hipError_t scratch_ptr(int device, unsigned char** out) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<unsigned char*>(ptr);
+    *out = static_cast<unsigned char*>(ptr);
+    return hipSuccess;
+}
+
 bool finite_all(const float* p, size_t n) {
     for (size_t i = 0; i < n; ++i)
         if (!std::isfinite(p[i])) return false;
@@ -74,6 +101,7 @@ struct hair_ctx {
     std::map<int, Asset> assets;
     int next_id = 1;
     hair_ws* default_ws = nullptr;
+    hair_ws* fixed_ws = nullptr;   // frames of hair_render_noalloc (buffers in the static scratch)
 };
 
 struct hair_ws {
@@ -104,6 +132,10 @@ struct hair_ws {
         float ms[4] = {};
     } pending;
     Counters* ctr_host = nullptr;   // pinned copy of a deferred frame's counters
+    // A workspace over the device's static scratch (hair_render_noalloc): its buffers are
+    // carved from [arena, arena + arena_bytes) afresh for every frame and never allocated.
+    unsigned char* arena = nullptr;
+    size_t arena_bytes = 0, arena_off = 0;
     std::mutex mu;
 };
 
@@ -157,8 +189,32 @@ void ctx_free(hair_ctx* ctx, DevBuf& b, hair_ws* ws = nullptr) {
     b.bytes = 0;
 }
 
+// Every device buffer a workspace can hold.
+std::array<DevBuf*, 30> ws_buffers(hair_ws* ws) {
+    return {{&ws->seg, &ws->shade, &ws->scan_tmp, &ws->tile_cnt, &ws->tile_start, &ws->bin_m, &ws->bin_blk,
+            &ws->sel_cnt, &ws->sel_start, &ws->sel, &ws->sel_tmp, &ws->list, &ws->ctr, &ws->items,
+            &ws->item_start, &ws->item_base, &ws->pix_cnt, &ws->pix_kmin, &ws->pix_kmax, &ws->pix_off,
+            &ws->tile_tot, &ws->frag_base, &ws->tile_nb, &ws->batch_mask, &ws->batch_start, &ws->batches,
+            &ws->frags, &ws->dom_tex, &ws->dom_grid, &ws->dom_part}};
+}
+
+// A buffer carved from a static-scratch workspace (256-byte aligned, no headroom).
+int arena_take(hair_ws* ws, DevBuf& b, size_t bytes) {
+    if (b.p && b.bytes >= bytes) return HAIR_OK;
+    if (bytes == 0) bytes = 4;
+    const size_t off = (ws->arena_off + 255) & ~size_t(255);
+    if (bytes > ws->arena_bytes || off > ws->arena_bytes - bytes)
+        return fail(HAIR_ENOMEM, "the frame needs more than the %zu bytes of static scratch of hair_render_noalloc",
+                    ws->arena_bytes);
+    b.p = ws->arena + off;
+    b.bytes = bytes;
+    ws->arena_off = off + bytes;
+    return HAIR_OK;
+}
+
 // Grow-only workspace buffer (25% headroom).
 int ws_need(hair_ws* ws, DevBuf& b, size_t bytes) {
+    if (ws->arena) return arena_take(ws, b, bytes);
     if (b.bytes >= bytes && b.p) return HAIR_OK;
     ctx_free(ws->ctx, b, ws);
     return ctx_alloc(ws->ctx, b, bytes + bytes / 4 + 256, ws);
@@ -451,7 +507,14 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     const int T = ntx * nty;
     const size_t TP = (size_t)T * kTilePix;
     const BinPlan plan = bin_plan(lv.nseg, T);
-    const bool warm = tiles_too && !cold && ws->caps.items > 0 && ws->caps.batches > 0;
+    if (ws->arena) {   // static scratch: every frame is sized afresh from its own counts
+        for (DevBuf* b : ws_buffers(ws)) *b = DevBuf{};
+        ws->arena_off = 0;
+        ws->caps = FrameCaps{};
+    }
+    const bool warm = tiles_too && !cold && !ws->arena && ws->caps.items > 0 && ws->caps.batches > 0;
+    // with_headroom for buffers a workspace keeps; exact sizes in the static scratch
+    auto cap_of = [&](uint32_t n) { return ws->arena ? n : with_headroom(n); };
     if ((rc = ws_events(ws))) return rc;
     if ((rc = ws_need(ws, ws->seg, sizeof(SegRec) * (size_t)std::max(lv.nseg, 1)))) return rc;
     if ((rc = ws_need(ws, ws->shade, sizeof(ShadeRec) * (size_t)std::max(lv.nseg, 1)))) return rc;
@@ -510,8 +573,8 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
             HIP_TRY(ctx, hipMemcpy(&out->ctr, ws->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost), "copy");
             return HAIR_OK;
         }
-        caps.pairs = std::max(caps.pairs, with_headroom(pairs));
-        caps.items = std::max(caps.items, with_headroom(n_items));
+        caps.pairs = std::max(caps.pairs, cap_of(pairs));
+        caps.items = std::max(caps.items, cap_of(n_items));
     }
     if ((rc = ws_need(ws, ws->list, 4ull * caps.pairs))) return rc;
     if ((rc = ws_need(ws, ws->item_base, 4ull * kTilePix * caps.items))) return rc;
@@ -546,7 +609,10 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     HIP_TRY(ctx, launch_scatter(f.seg, lv.nseg, cc, plan, tile_start, ws->bin_m.as<uint32_t>(), ws->list.as<uint32_t>(),
                                 f.ctr, st),
             "k_scatter");
-    HIP_TRY(ctx, launch_fill_pix(f.pix_cnt, f.pix_kmin, f.pix_kmax, TP, rgba, (size_t)cam->width * cam->height, st),
+    // (a static-scratch frame clears the image only once every buffer has been carved, so that
+    // a frame too large for the scratch fails with the caller's image untouched)
+    HIP_TRY(ctx, launch_fill_pix(f.pix_cnt, f.pix_kmin, f.pix_kmax, TP, ws->arena ? nullptr : rgba,
+                                 (size_t)cam->width * cam->height, st),
             "fill");
     const uint32_t item_grid = warm ? caps.items : n_items;
     HIP_TRY(ctx, launch_count(f, cc, item_grid, st), "k_count");
@@ -569,13 +635,15 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
         HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
         n_frags = sizes2[0];
         n_batches = sizes2[1];
-        caps.frags = std::max(caps.frags, with_headroom(n_frags));
-        caps.batches = std::max(caps.batches, with_headroom(n_batches));
+        caps.frags = std::max(caps.frags, cap_of(n_frags));
+        caps.batches = std::max(caps.batches, cap_of(n_batches));
     }
     if ((rc = ws_need(ws, ws->frags, 8ull * caps.frags))) return rc;
     if ((rc = ws_need(ws, ws->batches, 16ull * caps.batches))) return rc;
     f.frags = ws->frags.as<uint2>();
     f.batches = ws->batches.as<uint4>();
+    if (ws->arena && rgba)
+        HIP_TRY(ctx, launch_fill_f32(rgba, 0.0f, 4ull * cam->width * cam->height, st), "fill");
     if (!fused) HIP_TRY(ctx, launch_check_caps(f, caps, 2, st), "k_check_caps");
     const uint32_t batch_grid = warm ? caps.batches : n_batches;
     HIP_TRY(ctx, launch_batch_records(f, st), "k_batch_records");
@@ -656,6 +724,22 @@ int hair_ctx_create(int32_t device, uint64_t hbm_budget_bytes, hair_ctx** out) {
         e = hipMemGetInfo(&free_b, &total_b);
         if (e != hipSuccess) return fail(HAIR_EDEVICE, "hipMemGetInfo: %s", hipGetErrorString(e));
         ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)total_b);
+        // set-up of hair_render_noalloc: the device's scratch address and a workspace over it
+        // whose timing events exist before any frame, so that its frames create nothing
+        unsigned char* sp = nullptr;
+        e = scratch_ptr(device, &sp);
+        if (e != hipSuccess) return fail(HAIR_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        hair_ws* fw = new hair_ws();
+        fw->ctx = ctx.get();
+        fw->arena = sp;
+        fw->arena_bytes = kScratchBytes;
+        ctx->fixed_ws = fw;
+        int rc = ws_events(fw);
+        if (rc) {
+            hair_ws_destroy(fw);
+            ctx->fixed_ws = nullptr;
+            return rc;
+        }
     } else {
         ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (1ull << 40);
     }
@@ -668,6 +752,7 @@ int hair_ctx_destroy(hair_ctx* ctx) {
     if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
     for (auto& kv : ctx->assets) free_asset(ctx, kv.second);
     if (ctx->default_ws) hair_ws_destroy(ctx->default_ws);
+    if (ctx->fixed_ws) hair_ws_destroy(ctx->fixed_ws);
     delete ctx;
     return HAIR_OK;
 }
@@ -696,13 +781,11 @@ int hair_ws_destroy(hair_ws* ws) {
     if (!ws) return fail(HAIR_EINVAL, "null workspace");
     hair_ctx* ctx = ws->ctx;
     if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
-    for (DevBuf* b : {&ws->seg, &ws->shade, &ws->scan_tmp, &ws->tile_cnt, &ws->tile_start, &ws->bin_m, &ws->bin_blk, &ws->sel_cnt, &ws->sel_start, &ws->sel, &ws->sel_tmp, &ws->list, &ws->ctr, &ws->items,
-                      &ws->item_start, &ws->item_base, &ws->pix_cnt, &ws->pix_kmin, &ws->pix_kmax, &ws->pix_off,
-                      &ws->tile_tot, &ws->frag_base, &ws->tile_nb, &ws->batch_mask, &ws->batch_start, &ws->batches,
-                      &ws->frags,
-                      &ws->dom_tex, &ws->dom_grid, &ws->dom_part})
-        ctx_free(ctx, *b, ws);
+    // a frame of hair_render_async still reads and writes the buffers: let it end first
     if (ws->pending.active && !ws->pending.done && ws->events) (void)hipEventSynchronize(ws->ev[1]);
+    ws->pending.active = false;
+    if (!ws->arena)
+        for (DevBuf* b : ws_buffers(ws)) ctx_free(ctx, *b, ws);
     if (ws->ctr_host) (void)hipHostFree(ws->ctr_host);
     if (ws->events)
         for (auto& e : ws->ev) (void)hipEventDestroy(e);
@@ -1122,6 +1205,38 @@ int hair_render(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const 
                     fo.ctr.overflow_pixels, kCap);
     return HAIR_OK;
 }
+
+int hair_render_noalloc(hair_ctx* ctx, int32_t asset, int32_t level, const hair_camera* cam, const hair_light* lights,
+                        int32_t n_lights, float* rgba_out, void* stream, hair_stats* stats) {
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if ((rc = validate_camera(cam))) return rc;
+    if ((rc = validate_lights(lights, n_lights))) return rc;
+    if (!rgba_out) return fail(HAIR_EINVAL, "null output image");
+    Asset* a;
+    LevelDev lv;
+    if ((rc = find_level(ctx, asset, level, &a, &lv))) return rc;
+    if ((rc = need_device(ctx))) return rc;
+    hair_ws* ws = ctx->fixed_ws;
+    if (!ws) return fail(HAIR_EDEVICE, "the context has no static scratch");
+    std::lock_guard<std::mutex> g(ws->mu);
+    FrameOut fo;
+    if ((rc = run_frame(ctx, ws, *a, lv, cam, lights, n_lights, rgba_out, nullptr, (hipStream_t)stream, &fo, true,
+                        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true))) {
+        // a frame rejected after its first kernels were enqueued: they end before the scratch
+        // serves another call (which may come on another stream)
+        if (rc == HAIR_ENOMEM) (void)hipStreamSynchronize((hipStream_t)stream);
+        return rc;
+    }
+    if (stats) fill_stats(stats, fo, (uint32_t)lv.nseg);
+    if (fo.ctr.list_overflow) return fail(HAIR_ERANGE, "%u tiles hold more than 2^24 segments", fo.ctr.list_overflow);
+    if (fo.ctr.overflow_pixels)
+        return fail(HAIR_ERANGE, "%u pixels hold more than %d fragments at one depth key (left transparent)",
+                    fo.ctr.overflow_pixels, kCap);
+    return HAIR_OK;
+}
+
+uint64_t hair_noalloc_scratch_bytes(void) { return kScratchBytes; }
 
 int hair_render_async(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,
                       const hair_light* lights, int32_t n_lights, float* rgba_out, void* stream) {
