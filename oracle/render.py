@@ -161,16 +161,28 @@ def fragment_alpha_h(ras: Raster, hw):
     return alpha, h
 
 
+def perspective_t(t, izA, izB):
+    """World parameter t_w of the point at screen parameter t on a segment whose endpoints
+    have inverse depths izA, izB: inverse depth is affine in screen space, so with
+    iz = izA + t (izB - izA) the world parameter is t_w = t izB / iz."""
+    iz = izA + t * (izB - izA)
+    return t * izB / iz
+
+
+def azimuth(wi, xh, yh, degen):
+    """phi = phi_o - phi_i with phi_o = 0 (Sec. 3.1): minus the angle of omega_i about u from
+    x^ toward y^ = u x x^; 0 where the view runs along the fibre."""
+    phi = -torch.atan2((wi * yh).sum(-1), (wi * xh).sum(-1))
+    return torch.where(degen, torch.zeros_like(phi), phi)
+
+
 def shading_inputs(geom: LevelGeom, ras: Raster, cam):
     """World point, tangent u and view direction per fragment (float64)."""
     s = ras.seg
     pA = _t(geom.pA[:, s].T)
     pB = _t(geom.pB[:, s].T)
     t = _t(ras.t_num) / _t(ras.t_den)
-    izA = _t(ras.izA[s])
-    izB = _t(ras.izB[s])
-    iz = izA + t * (izB - izA)
-    tw = t * izB / iz
+    tw = perspective_t(t, _t(ras.izA[s]), _t(ras.izB[s]))
     xw = pA + tw[:, None] * (pB - pA)
     u = _normalize(pB - pA)
     wo = _normalize(_t(np.asarray(cam.pos, dtype=np.float32))[None, :] - xw)
@@ -274,8 +286,7 @@ def fragment_radiance(geom: LevelGeom, ras: Raster, cam, lights, mat, params=Non
         ns = None if shadow is None else shadow[li]
         wi, E = light_dirs(light, xw)
         sin_ti = (wi * u).sum(-1)
-        phi = -torch.atan2((wi * yh).sum(-1), (wi * xh).sum(-1))
-        phi = torch.where(degen, torch.zeros_like(phi), phi)
+        phi = azimuth(wi, xh, yh, degen)
         _, _, th, xd = angles(sin_ti, sin_to)
         sc = torch.clamp(sin_ti, -1.0, 1.0)
         cos_ti = torch.sqrt((1.0 - sc) * (1.0 + sc))

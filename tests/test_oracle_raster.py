@@ -100,27 +100,26 @@ def test_shared_vertex_counted_once():
     assert got == [(0, 0, 0), (0, 1, 0), (1, 2, 0), (1, 3, 0)]
 
 
-@pytest.mark.parametrize("tile", [8, 16])
-def test_binning_equals_brute_force_rectangles(tile):
-    """Bins = the tiles of each segment's box widened by R that hold a pixel centre of the
-    footprint's bounding region, checked against brute force over the tiles' pixel centres:
-    a box tile is dropped only if no pixel-centre grid point of the tile (extended over the
-    whole tile, image edge or not) satisfies 0 <= t_num <= t_den and cross^2 <= R^2 t_den in
-    real terms at the rectangle's corners; every kept tile passes the corner projections."""
-    rng = np.random.default_rng(4)
-    W, H = 70, 45
-    XA, YA, XB, YB, hw_fx, vis = _random_segments(rng, 80, W, H)
-    vis[3] = False
-    tid, seg, _ = rs.bins(XA, YA, XB, YB, hw_fx, vis, W, H, tile)
+def _brute_tiles(XA, YA, XB, YB, hw_fx, vis, W, H, tile):
+    """Tile sets by enumerating every tile's pixel centres (Python integers).
+
+    kept: the box tiles (box = the segment's bounding box widened by R = hw_fx + 8) except
+    those whose pixel centres, every one of them (the tile's whole grid, on the image or
+    not), lie beyond the same one of the four lines that bound the footprint's region:
+    t_num < 0, t_num > t_den, or cross^2 >= R^2 t_den on one side (cross > 0, or cross < 0).
+    Thin (R <= 2 px) and zero-length segments keep the whole box.
+    real: the tiles holding a pixel centre of the closed real footprint
+    0 <= t_num <= t_den, cross^2 <= R^2 t_den."""
     ntx, nty = -(-W // tile), -(-H // tile)
-    brute = []
+    kept, real = [], set()
     for s in range(len(XA)):
         if not vis[s]:
             continue
         Rr = int(hw_fx[s]) + 8
-        lox, hix = min(XA[s], XB[s]) - Rr, max(XA[s], XB[s]) + Rr
-        loy, hiy = min(YA[s], YB[s]) - Rr, max(YA[s], YB[s]) + Rr
-        dx, dy = int(XB[s] - XA[s]), int(YB[s] - YA[s])
+        xa, ya = int(XA[s]), int(YA[s])
+        lox, hix = min(xa, int(XB[s])) - Rr, max(xa, int(XB[s])) + Rr
+        loy, hiy = min(ya, int(YB[s])) - Rr, max(ya, int(YB[s])) + Rr
+        dx, dy = int(XB[s]) - xa, int(YB[s]) - ya
         tden = dx * dx + dy * dy
         for ty in range(nty):
             for tx in range(ntx):
@@ -128,28 +127,76 @@ def test_binning_equals_brute_force_rectangles(tile):
                 y0, y1 = 16 * tile * ty, 16 * tile * (ty + 1) - 1
                 if not (lox <= x1 and hix >= x0 and loy <= y1 and hiy >= y0):
                     continue
-                if tden == 0 or Rr <= 32:   # thin or zero-length: the whole box
-                    brute.append((ty * ntx + tx, s))
-                    continue
-                # any point of the rectangle of this tile's pixel centres inside the footprint?
-                # (the footprint is convex and the conditions linear / quadratic in the point, so
-                # test the corners' projections: overlap on both axes of the segment's frame)
-                cs = [(16 * tile * tx + 8 + i * 16 * (tile - 1) - int(XA[s]),
-                       16 * tile * ty + 8 + j * 16 * (tile - 1) - int(YA[s])) for i in (0, 1) for j in (0, 1)]
-                tn = [ex * dx + ey * dy for ex, ey in cs]
-                cr = [ex * dy - ey * dx for ex, ey in cs]
-                slab = max(tn) >= 0 and min(tn) <= tden
-                strip = not ((min(cr) > 0 and min(cr) ** 2 >= Rr * Rr * tden) or
-                             (max(cr) < 0 and max(cr) ** 2 >= Rr * Rr * tden))
-                if slab and strip:
-                    brute.append((ty * ntx + tx, s))
-    assert list(zip(tid.tolist(), seg.tolist())) == sorted(brute)
-    # every fragment's tile holds its segment (the binning is conservative)
+                beyond = [True, True, True, True]
+                for j in range(tile):
+                    for i in range(tile):
+                        ex = 16 * (tile * tx + i) + 8 - xa
+                        ey = 16 * (tile * ty + j) + 8 - ya
+                        tn, cr = ex * dx + ey * dy, ex * dy - ey * dx
+                        out = cr * cr >= Rr * Rr * tden
+                        side = [tn < 0, tn > tden, cr > 0 and out, cr < 0 and out]
+                        beyond = [b and c for b, c in zip(beyond, side)]
+                        if tden > 0 and 0 <= tn <= tden and cr * cr <= Rr * Rr * tden:
+                            real.add((ty * ntx + tx, s))
+                if tden == 0 or Rr <= 32 or not any(beyond):
+                    kept.append((ty * ntx + tx, s))
+    return sorted(kept), real
+
+
+def _wide_segments(rng, W, H):
+    """Random segments, half of them wide (radius 2.5 to 25 px) and longer, so that the
+    footprint rule drops tiles of their boxes."""
+    XA, YA, XB, YB, hw_fx, vis = _random_segments(rng, 80, W, H)
+    ang = rng.uniform(0, 2 * math.pi, 40)
+    L = rng.integers(16 * 4, 16 * 40, 40)
+    XB[40:] = XA[40:] + np.round(L * np.cos(ang)).astype(np.int64)
+    YB[40:] = YA[40:] + np.round(L * np.sin(ang)).astype(np.int64)
+    hw_fx[40:] = rng.integers(40, 400, 40)
+    return XA, YA, XB, YB, hw_fx, vis
+
+
+@pytest.mark.parametrize("tile", [8, 16])
+def test_binning_equals_brute_force_over_pixel_centres(tile):
+    """The tile rule (corner projections) against the enumeration of every tile's pixel
+    centres; the kept set holds every tile with a pixel centre in the real footprint, and
+    every fragment's tile holds its segment."""
+    rng = np.random.default_rng(4)
+    W, H = 70, 45
+    XA, YA, XB, YB, hw_fx, vis = _wide_segments(rng, W, H)
+    vis[3] = False
+    tid, seg, _ = rs.bins(XA, YA, XB, YB, hw_fx, vis, W, H, tile)
+    kept, real = _brute_tiles(XA, YA, XB, YB, hw_fx, vis, W, H, tile)
+    got = list(zip(tid.tolist(), seg.tolist()))
+    assert got == kept
+    pairs = set(got)
+    assert real <= pairs
+    wide = [(t, s) for t, s in got if int(hw_fx[s]) + 8 > 32]
+    assert len(wide) > 50 and len(real) < len(pairs)     # the rule is exercised and conservative
+    # every fragment's tile holds its segment
+    ntx = -(-W // tile)
     sg, pi, pj = rs.candidate_pixels(XA, YA, XB, YB, hw_fx, vis, W, H)
     ok, *_ = rs.coverage(XA, YA, XB, YB, hw_fx, sg, pi, pj)
-    pairs = set(zip(tid.tolist(), seg.tolist()))
     for s, i, j in zip(sg[ok], pi[ok], pj[ok]):
         assert ((j // tile) * ntx + i // tile, s) in pairs
+
+
+def test_planted_binning_mistakes_are_caught(monkeypatch):
+    """Plausible mistakes in the tile rule (tile origin, the strip test left out, the
+    half-pixel offset of pixel centres) differ from the enumeration."""
+    rng = np.random.default_rng(4)
+    W, H, tile = 70, 45, 16
+    XA, YA, XB, YB, hw_fx, vis = _wide_segments(rng, W, H)
+    kept, _ = _brute_tiles(XA, YA, XB, YB, hw_fx, vis, W, H, tile)
+    orig = rs.tile_meets_footprint
+    for plant in (lambda XA, YA, XB, YB, hw_fx, seg, tx, ty, tile:          # tile origin off by one tile
+                  orig(XA, YA, XB, YB, hw_fx, seg, tx + 1, ty, tile),
+                  lambda XA, YA, XB, YB, hw_fx, seg, tx, ty, tile:          # the slab alone
+                  orig(XA, YA, XB, YB, hw_fx * 1000 + 1000, seg, tx, ty, tile),
+                  lambda XA, YA, XB, YB, hw_fx, seg, tx, ty, tile:          # the pixel-centre offset dropped
+                  orig(XA + 8, YA + 8, XB + 8, YB + 8, hw_fx, seg, tx, ty, tile)):
+        monkeypatch.setattr(rs, "tile_meets_footprint", plant)
+        tid, seg, _ = rs.bins(XA, YA, XB, YB, hw_fx, vis, W, H, tile)
+        assert list(zip(tid.tolist(), seg.tolist())) != kept
 
 
 def test_depth_key_orders_nearer_first():
