@@ -132,6 +132,15 @@ int hair_ctx_memory(hair_ctx* ctx, uint64_t* used_bytes, uint64_t* budget_bytes)
  * render stream. */
 int hair_ws_create(hair_ctx* ctx, uint64_t max_bytes, hair_ws** out);
 int hair_ws_destroy(hair_ws* ws);
+/* Bytes the workspace holds on the device now and its limit (0 = none). */
+int hair_ws_memory(hair_ws* ws, uint64_t* held_bytes, uint64_t* max_bytes);
+/* Change the workspace's limit (0 = none) for its later calls; buffers it already holds are
+ * kept, so held bytes may exceed a lowered limit until hair_ws_trim.  A call that would grow
+ * the workspace beyond the limit fails with HAIR_ENOMEM. */
+int hair_ws_set_limit(hair_ws* ws, uint64_t max_bytes);
+/* Free every buffer the workspace holds (its next frame sizes them afresh, as a first frame
+ * does).  HAIR_EINVAL while it holds a frame of hair_render_async. */
+int hair_ws_trim(hair_ws* ws);
 /* Bytes a render of n_segments at width x height needs in a workspace (upper bound used
  * for admission control); pairs_estimate = expected (tile, segment) pairs (0 = 4 per segment). */
 uint64_t hair_ws_estimate(int64_t n_segments, int32_t width, int32_t height, int64_t pairs_estimate);
@@ -166,9 +175,12 @@ int hair_lod_info(hair_ctx* ctx, int32_t asset, int32_t* n_levels, int32_t* coun
 
 /* Export (get) or import (set) a thick-hair level as host arrays (the stored configuration
  * of Sec. 6, "Memory cost and initialization time").  K clusters, S segments per centre line:
- *   centers float[K][S+1][3], ahat float[K][S][3], axes float[K][S][2] (|a|, |b|, m),
+ *   centers float[K][S+1][3], ahat float[K][S][3], axes float[K][S][2] (|a|, |b|),
  *   n_total int[K], sigma_a float[3][K], r float[K].
- * set: level in 1..n_levels+1 (n_levels+1 appends); get: level in 1..n_levels. */
+ * set: level in 1..n_levels+1 (n_levels+1 appends); get: level in 1..n_levels.  Replacing a
+ * level by one with the same cluster count keeps the clusters' memberships from
+ * hair_build_lod (cluster c stays cluster c, so per-group LoD stays available); appending a
+ * level or changing its cluster count drops the nested hierarchy. */
 int hair_get_lod(hair_ctx* ctx, int32_t asset, int32_t level, int32_t n_clusters,
                  float* centers, float* ahat, float* axes, int32_t* n_total, float* sigma_a, float* r);
 int hair_set_lod(hair_ctx* ctx, int32_t asset, int32_t level, int32_t n_clusters,

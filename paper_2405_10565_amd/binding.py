@@ -24,7 +24,7 @@ HAIR_TILE = 16
 
 EXPORTS = [
     "hair_version", "hair_last_error", "hair_device_count", "hair_ctx_create", "hair_ctx_destroy",
-    "hair_ctx_memory", "hair_ws_create", "hair_ws_destroy", "hair_ws_estimate", "hair_upload", "hair_release",
+    "hair_ctx_memory", "hair_ws_create", "hair_ws_destroy", "hair_ws_estimate", "hair_ws_memory", "hair_ws_set_limit", "hair_ws_trim", "hair_upload", "hair_release",
     "hair_build_lod", "hair_lod_info", "hair_get_lod", "hair_set_lod", "hair_set_cluster_params",
     "hair_select_level", "hair_render", "hair_render_backward", "hair_debug_segments", "hair_debug_bins",
     "hair_debug_fragments", "hair_lod_groups", "hair_lod_init", "hair_render_mixed", "hair_render_shadowed",
@@ -108,6 +108,9 @@ def _load():
         "hair_ws_create": ([P, U64, C.POINTER(P)], C.c_int),
         "hair_ws_destroy": ([P], C.c_int),
         "hair_ws_estimate": ([I64, I32, I32, I64], U64),
+        "hair_ws_memory": ([P, C.POINTER(U64), C.POINTER(U64)], C.c_int),
+        "hair_ws_set_limit": ([P, U64], C.c_int),
+        "hair_ws_trim": ([P], C.c_int),
         "hair_upload": ([P, I32, I32, fp, fp, fp, C.POINTER(hair_material), P, ip], C.c_int),
         "hair_release": ([P, I32], C.c_int),
         "hair_build_lod": ([P, I32, I32, ip, ip, P], C.c_int),
@@ -217,6 +220,18 @@ class Workspace:
         if raise_on_error:
             check(rc)
         return st.as_dict(), rc
+
+    def memory(self):
+        """(bytes held on the device, limit) of the workspace (hair_ws_memory)."""
+        h, m = C.c_uint64(), C.c_uint64()
+        check(lib.hair_ws_memory(self.handle, C.byref(h), C.byref(m)))
+        return h.value, m.value
+
+    def set_limit(self, max_bytes: int):
+        check(lib.hair_ws_set_limit(self.handle, int(max_bytes)))
+
+    def trim(self):
+        check(lib.hair_ws_trim(self.handle))
 
     def close(self):
         if self.handle:

@@ -794,6 +794,35 @@ int hair_ws_destroy(hair_ws* ws) {
     return HAIR_OK;
 }
 
+int hair_ws_memory(hair_ws* ws, uint64_t* held_bytes, uint64_t* max_bytes) {
+    if (!ws) return fail(HAIR_EINVAL, "null workspace");
+    std::lock_guard<std::mutex> g(ws->mu);
+    if (held_bytes) *held_bytes = ws->arena ? 0 : ws->held;
+    if (max_bytes) *max_bytes = ws->max_bytes;
+    return HAIR_OK;
+}
+
+int hair_ws_set_limit(hair_ws* ws, uint64_t max_bytes) {
+    if (!ws) return fail(HAIR_EINVAL, "null workspace");
+    std::lock_guard<std::mutex> g(ws->mu);
+    ws->max_bytes = max_bytes;
+    return HAIR_OK;
+}
+
+int hair_ws_trim(hair_ws* ws) {
+    if (!ws) return fail(HAIR_EINVAL, "null workspace");
+    hair_ctx* ctx = ws->ctx;
+    std::lock_guard<std::mutex> g(ws->mu);
+    if (ws->pending.active)
+        return fail(HAIR_EINVAL, "the workspace holds a frame of hair_render_async: call hair_ws_finish first");
+    if (ws->arena) return HAIR_OK;
+    if (ctx->device >= 0) HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    for (DevBuf* b : ws_buffers(ws)) ctx_free(ctx, *b, ws);
+    ws->caps = FrameCaps{};
+    ws->dom_n = 0;
+    return HAIR_OK;
+}
+
 uint64_t hair_ws_estimate(int64_t n_segments, int32_t width, int32_t height, int64_t pairs_estimate) {
     if (n_segments < 0) n_segments = 0;
     if (width < 1) width = 1;
@@ -1108,13 +1137,16 @@ int hair_set_lod(hair_ctx* ctx, int32_t asset, int32_t level, int32_t n_clusters
         free_level(ctx, L);
         return dev_fail(ctx, e, "set_lod");
     }
+    // the same clusters with new data keep their memberships (the nesting of per-group LoD);
+    // a new level or another cluster count makes them unknown
+    const bool same_clusters = level <= (int)a.levels.size() && a.levels[level - 1].K == (int)K;
     if (level == (int)a.levels.size() + 1) {
         a.levels.push_back(std::move(L));
     } else {
         free_level(ctx, a.levels[level - 1]);
         a.levels[level - 1] = std::move(L);
     }
-    free_hierarchy(ctx, a.hier);   // memberships of a level set from arrays are unknown
+    if (!same_clusters) free_hierarchy(ctx, a.hier);
     return HAIR_OK;
 }
 

@@ -3,13 +3,22 @@
 Hair assets and their nested LoD hierarchies stay resident in HBM.  Requests (asset,
 resolution, view) arrive as they come (Poisson arrivals in the benchmark), wait in a FIFO, and
 are admitted when a slot is free and the request's memory footprint fits the scratch budget
-next to the requests already on the GPU.  Each slot owns a HIP stream, a library workspace, a
+next to the memory the other slots really hold.  Each slot owns a HIP stream, a library workspace, a
 level buffer and an output buffer, and runs the LoD choice and the frame on its stream; slots
 overlap on the device.  LoD (lod="mixed", the default): per group of the coarsest level and per
 segment index, the coarsest level whose thick hairs are at most eps_w = 2 px wide (Sec. 5.1
 step 5, Sec. 6), rendered as one mixed-level frame (or as that level's own frame when one
 level is chosen everywhere); lod="level": one level for the whole asset.
 A request's latency is its completion time minus its arrival time.
+
+Memory: the budget is charged with what the workspaces really hold on the device.  A request
+is admitted to a free slot when the slot's reservation, max(its workspace's bytes, the
+request's estimated footprint), fits beside the busy slots' reservations and the idle slots'
+held bytes; the slot's workspace is then limited to that reservation, so no frame can grow
+past the budget.  A frame that needs more than its estimate fails in the library with
+HAIR_ENOMEM (nothing allocated) and goes back to the head of the queue with twice the
+estimate (at most the budget), to wait for memory.  When the head request fits nowhere, idle
+slots give their workspace memory back (hair_ws_trim).
 
     python -m paper_2405_10565_amd.serve [--rates 30 60 120] [--requests 3000] [--warmup 200]
 """
@@ -48,6 +57,8 @@ class Request:
     status: int = 0
     slot: int = -1
     output: object = None
+    levels_used: object = None  # with keep_outputs, mixed LoD: the (group, segment) level map
+    retries: int = 0            # re-queued after outgrowing its estimate
 
 
 @dataclass
@@ -57,6 +68,7 @@ class ServedAsset:
     lights: list
     segments_per_level: list   # segments of level 0..n
     groups: int = 0            # groups of the nested hierarchy (0: none)
+    assigns: list = None       # cluster assignments of levels 1..n (finer -> coarser)
 
 
 class Slot:
@@ -68,6 +80,9 @@ class Slot:
         self.out = torch.empty(max_pixels * 4, dtype=torch.float32, device=f"cuda:{server.hctx.device}")
         gs = max([a.groups * a.asset.segs for a in server.assets.values()] + [1])
         self.levels = torch.zeros(gs, dtype=torch.int32, device=f"cuda:{server.hctx.device}")
+        self.busy = False
+        self.held = 0          # bytes the workspace holds (read after each frame)
+        self.reserve = 0       # while busy: the workspace's limit for the running request
 
 
 class Server:
@@ -85,7 +100,8 @@ class Server:
         self.slots = [Slot(self, i, max_pixels) for i in range(n_slots)]
         self.free_slots = deque(self.slots)
         self.queue: deque[Request] = deque()
-        self.in_flight_bytes = 0
+        self.in_flight_bytes = 0          # charged bytes: busy reservations + idle workspaces
+        self.peak_bytes = 0
         self.cv = threading.Condition()
         self.done: list[Request] = []
         self.rejected: list[Request] = []
@@ -109,9 +125,16 @@ class Server:
         a = self.assets[name]
         w, h = max(RESOLUTIONS, key=lambda r: r[0] * r[1])
         cam = hs.camera_occupancy(a.asset, w, h, 0.6, 0.0)
-        for slot in self.slots:
-            out = slot.out[: w * h * 4].view(h, w, 4)
-            self.hctx.render(a.aid, 0, cam, a.lights, out=out, ws=slot.ws, stream=slot.stream)
+        with self.cv:
+            for slot in self.slots:
+                out = slot.out[: w * h * 4].view(h, w, 4)
+                slot.ws.set_limit(max(1, self.scratch_budget - self._charged(slot)))
+                _, _, rc = self.hctx.render(a.aid, 0, cam, a.lights, out=out, ws=slot.ws, stream=slot.stream,
+                                            raise_on_error=False)
+                if rc != B.HAIR_OK:        # the budget holds fewer warm slots: keep the rest cold
+                    slot.ws.trim()
+                slot.held = slot.ws.memory()[0]
+            self.in_flight_bytes = self._charged(None)
         torch.cuda.synchronize()
 
     def footprint(self, req: Request) -> int:
@@ -131,29 +154,60 @@ class Server:
             self.queue.append(req)
             self.cv.notify_all()
 
+    def _charged(self, skip) -> int:
+        """Bytes charged to the budget by every slot but `skip`: a busy slot its reservation,
+        an idle one what its workspace holds."""
+        return sum(s.reserve if s.busy else s.held for s in self.slots if s is not skip)
+
     def _take(self):
-        """First queued request (FIFO order) whose footprint fits next to the in-flight ones."""
-        for i, r in enumerate(self.queue):
-            if self.in_flight_bytes + r.footprint <= self.scratch_budget:
-                del self.queue[i]
-                return r
+        """(request, slot): the first queued request (FIFO order) that fits on a free slot
+        beside the memory the other slots hold; idle slots give their memory back when the
+        head request fits nowhere."""
+        for attempt in range(2):
+            for i, r in enumerate(self.queue):
+                for slot in sorted(self.free_slots, key=lambda s: -s.held):
+                    if self._charged(slot) + max(slot.held, r.footprint) <= self.scratch_budget:
+                        del self.queue[i]
+                        self.free_slots.remove(slot)
+                        return r, slot
+            idle = [s for s in self.free_slots if s.held]
+            busy = sum(s.reserve for s in self.slots if s.busy)
+            if attempt or not self.queue or not idle or busy + self.queue[0].footprint > self.scratch_budget:
+                break
+            for s in idle:     # the head request fits once the idle workspaces are emptied
+                s.ws.trim()
+                s.held = s.ws.memory()[0]
         return None
 
     def _worker(self):
         while True:
             with self.cv:
-                while self.running and (not self.free_slots or not self.queue or (req := self._take()) is None):
+                while self.running and (not self.free_slots or not self.queue or (got := self._take()) is None):
                     self.cv.wait()
                 if not self.running:
                     return
-                slot = self.free_slots.popleft()
-                self.in_flight_bytes += req.footprint
-                self.peak_in_flight = max(self.peak_in_flight, len(self.slots) - len(self.free_slots))
+                req, slot = got
+                slot.busy = True
+                slot.reserve = max(slot.held, req.footprint)
+                slot.ws.set_limit(slot.reserve)
+                self.in_flight_bytes = self._charged(None)
+                self.peak_bytes = max(self.peak_bytes, self.in_flight_bytes)
+                self.peak_in_flight = max(self.peak_in_flight, sum(s.busy for s in self.slots))
             self._run(slot, req)
             with self.cv:
-                self.in_flight_bytes -= req.footprint
+                slot.held = slot.ws.memory()[0]
+                slot.busy = False
+                slot.reserve = 0
                 self.free_slots.append(slot)
-                self.done.append(req)
+                if req.status == B.HAIR_ENOMEM and req.footprint < self.scratch_budget:
+                    # outgrew its estimate: wait at the head of the queue with a larger one
+                    req.retries += 1
+                    req.footprint = min(self.scratch_budget, 2 * max(req.footprint, slot.held))
+                    req.status = 0
+                    self.queue.appendleft(req)
+                else:
+                    self.done.append(req)
+                self.in_flight_bytes = self._charged(None)
                 self.cv.notify_all()
 
     def _run(self, slot: Slot, req: Request):
@@ -167,7 +221,10 @@ class Server:
             if self.lod == "mixed" and a.groups:
                 lev = slot.levels[: a.groups * a.asset.segs].view(a.groups, a.asset.segs)
                 self.hctx.lod_init(a.aid, cam, self.eps_w, lev, ws=slot.ws, stream=slot.stream)
-                hist = np.bincount(lev.flatten().cpu().numpy(), minlength=len(a.segments_per_level))
+                lev_host = lev.cpu().numpy()
+                if self.keep_outputs:
+                    req.levels_used = lev_host.copy()
+                hist = np.bincount(lev_host.reshape(-1), minlength=len(a.segments_per_level))
                 req.level_hist = hist.tolist()
                 req.level = int(np.argmax(hist))
                 if hist[req.level] == hist.sum():   # one level everywhere: that level's own frame
@@ -183,7 +240,9 @@ class Server:
             req.status = rc
             req.fragments = int(st["fragments"])
             if self.keep_outputs:
-                req.output = out.clone()
+                import torch
+                with torch.cuda.stream(slot.stream):   # ordered after the frame on the slot's stream
+                    req.output = out.clone()
                 slot.stream.synchronize()
         except B.HairError as e:
             req.status = e.code
@@ -267,10 +326,11 @@ def build_assets(hctx: B.Context, specs=((10_000, 16), (100_000, 32), (300_000, 
         asset = hs.make_asset(n, segs, 90.0, seed=seed + i, sigma_spread=True)
         aid = hctx.upload_asset(asset)
         ks = [max(1, n // d) for d in level_divisors]
-        hctx.build_lod(aid, hs.kmeans_hierarchy(asset, ks, seed=seed + i, iters=10, init="random"))
+        assigns = hs.kmeans_hierarchy(asset, ks, seed=seed + i, iters=10, init="random")
+        hctx.build_lod(aid, assigns)
         _, counts, S = hctx.lod_info(aid)
-        out[f"{n // 1000}k x {segs}"] = ServedAsset(aid, asset, hs.default_lights(asset, with_point=True),
-                                                     [c * S for c in counts], hctx.lod_groups(aid))
+        out[f"{n / 1000:g}k x {segs}"] = ServedAsset(aid, asset, hs.default_lights(asset, with_point=True),
+                                                      [c * S for c in counts], hctx.lod_groups(aid), assigns)
     return out
 
 

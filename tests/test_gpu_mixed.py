@@ -4,6 +4,7 @@ import pytest
 import torch
 
 import hairsynth as hs
+from oracle import lod as OL
 from oracle import mixed as M
 from oracle import render as R
 
@@ -12,9 +13,15 @@ pytestmark = pytest.mark.gpu
 RTOL, ATOL = 1e-4, 1e-7
 
 
-def _lod_dict(L):
-    return {"centers": L.centers, "ahat": L.ahat, "axes": L.axes, "n_total": L.n_total, "sigma_a": L.sigma_a,
-            "r": L.r}
+def oracle_levels(ctx, aid, asset, assigns):
+    """The hierarchy's memberships from hair_build_lod, every level's data from the oracle's
+    construction (uploaded with hair_set_lod, which keeps the memberships): both sides then
+    render the same level data, none of it computed by the HIP path."""
+    ctx.build_lod(aid, assigns)
+    lods = [OL.build_level(asset, a) for a in assigns]
+    for l, lod in enumerate(lods, 1):
+        ctx.set_lod(aid, l, lod)
+    return lods
 
 
 @pytest.fixture(scope="module")
@@ -23,8 +30,7 @@ def scene(hip):
     asset = hs.make_asset(2500, 10, 90.0, seed=23, sigma_spread=True)
     assigns = hs.kmeans_hierarchy(asset, (400, 80, 12), seed=23)
     aid = ctx.upload_asset(asset)
-    ctx.build_lod(aid, assigns)
-    lods = [_lod_dict(ctx.get_lod(aid, l)) for l in range(1, 4)]   # the GPU's own level data
+    lods = oracle_levels(ctx, aid, asset, assigns)
     geoms = M.level_geoms(asset, lods)
     grps = M.groups(assigns)
     cam = hs.camera_for(asset, 120, 104)
@@ -114,15 +120,15 @@ def test_mixed_errors(hip, scene):
 def test_mixed_frame_full_size_sampled(hip):
     """A mixed-level frame at 1920x1080 (20k strands x 16 segments; 2000 / 300 / 40 thick
     hairs; a random level per group and segment): every projected row bit-exact, the deferred
-    level update equal, and the radiance on rectangles at coverage borders and at the deepest
-    pixel against the oracle."""
+    level update equal, the fragment count equal to the oracle's stored census, and the
+    radiance on rectangles at coverage borders and at the deepest pixel (most fragments, from
+    the census) against the oracle."""
     print("case: mixed frame at 1920x1080", flush=True)
     ctx = hip.Context(0)
     asset = hs.make_asset(20000, 16, 90.0, seed=35, sigma_spread=True)
     assigns = hs.kmeans_hierarchy(asset, (2000, 300, 40), seed=35)
     aid = ctx.upload_asset(asset)
-    ctx.build_lod(aid, assigns)
-    lods = [_lod_dict(ctx.get_lod(aid, l)) for l in range(1, 4)]
+    lods = oracle_levels(ctx, aid, asset, assigns)
     geoms = M.level_geoms(asset, lods)
     grps = M.groups(assigns)
     cam = hs.camera_for(asset, 1920, 1080)
@@ -143,15 +149,22 @@ def test_mixed_frame_full_size_sampled(hip):
         assert np.array_equal(ri[vis, col], ref[vis]), col
     assert np.array_equal(lev.cpu().numpy(), M.update_levels(geoms, grps, cam, 2.0, levels))
     got = img.cpu().numpy().astype(np.float64)
+    # the fragment count and the deepest pixel (most fragments) from the oracle's stored census
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "mixed_20k_1080p.json")) as f:
+        gold = json.load(f)
+    assert st["fragments"] == gold["fragments"]
+    deep = gold["deepest"][0]
     alpha = got[..., 3]
     inside = alpha > 0
     edge = inside & ~(np.roll(inside, 1, 0) & np.roll(inside, -1, 0) & np.roll(inside, 1, 1) & np.roll(inside, -1, 1))
     ys, xs = np.nonzero(edge)
     rng = np.random.default_rng(36)
     picks = [(int(ys[i]), int(xs[i])) for i in rng.choice(ys.size, size=2, replace=False)]
-    picks.append(tuple(int(q) for q in np.unravel_index(np.argmax(alpha * (alpha < 1.0)), alpha.shape)))
+    picks.append((deep["y"], deep["x"]))
     mat = tuple(float(v) for v in asset.material.as_array())
-    print(f"mixed 1080p: {n} segments, {st['fragments']} fragments", flush=True)
+    print(f"mixed 1080p: {n} segments, {st['fragments']} fragments, deepest pixel {deep['count']}", flush=True)
     for y, x in picks:
         x0 = int(min(max(x - 12, 0), cam.width - 24))
         y0 = int(min(max(y - 12, 0), cam.height - 24))

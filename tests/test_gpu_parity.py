@@ -237,17 +237,43 @@ def test_select_level_matches_oracle(hip, ctx):
     asset, cam, lights, assign = _cluster_case(k=200)
     assigns = [assign, hs.kmeans_assign(asset, 30, seed=1), hs.kmeans_assign(asset, 4, seed=1)]
     aid = ctx.upload_asset(asset)
-    ctx.build_lod(aid, assigns)
-    geoms = [R.strand_level(asset)] + [R.cluster_level(ctx.get_lod(aid, l).__dict__) for l in (1, 2, 3)]
+    lods = [OL.build_level(asset, a) for a in assigns]
+    for l, lod in enumerate(lods, 1):
+        ctx.set_lod(aid, l, lod)
+    geoms = [R.strand_level(asset)] + [R.cluster_level(lod) for lod in lods]
     for eps in (0.5, 2.0, 6.0, 1e6):
         assert ctx.select_level(aid, cam, eps) == R.select_level(geoms, cam, eps), eps
 
 
 # ---- full-size configuration (the benchmark's launch) ----------------------------------------
 
+def golden(name):
+    """Stored oracle values of a full-size frame (written by tests/golden/make_golden.py)."""
+    import json
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"{name}.json")) as f:
+        return json.load(f)
+
+
+def check_census(hip, ctx, aid, level, cam, lights, stats, gold, what):
+    """The frame's fragment count, the counts of its densest, a middle and a sparse row and of
+    its deepest pixels, against the oracle's stored census."""
+    assert stats["fragments"] == gold["fragments"], (what, stats["fragments"], gold["fragments"])
+    rows = np.asarray(gold["rows"])
+    nz = np.nonzero(rows)[0]
+    for y in (int(np.argmax(rows)), int(nz[len(nz) // 2]), int(nz[len(nz) // 20])):
+        cnt, *_ = ctx.debug_fragments(aid, level, cam, lights, 0, y, cam.width, 1, int(rows[y]) + 64)
+        assert int(cnt.sum()) == int(rows[y]), (what, y)
+    for d in gold["deepest"][:2]:
+        cnt, *_ = ctx.debug_fragments(aid, level, cam, lights, d["x"], d["y"], 1, 1, max(d["count"], 1536))
+        assert int(cnt[0, 0]) == d["count"], (what, d)
+    print(f"[{what}] {gold['fragments']} fragments; rows and deepest pixels ({gold['deepest'][0]['count']}) "
+          "equal the oracle's census", flush=True)
+
+
 def test_config2_full_size_sampled(hip, ctx):
-    """100k strands x 32 segments at 1920x1080: the GPU frame against the oracle on three
-    sampled pixel rectangles (dense, medium, sparse), plus determinism at full size."""
+    """100k strands x 32 segments at 1920x1080 (the benchmark's launch): the fragment count,
+    row counts and deepest-pixel counts against the oracle's stored census, the frame against
+    the oracle on pixel rectangles (densest pixel, dense, medium, sparse), and determinism."""
     print("case: 100k strands at 1920x1080", flush=True)
     asset, cam, lights = hs.config(2)
     aid = ctx.upload_asset(asset)
@@ -258,15 +284,18 @@ def test_config2_full_size_sampled(hip, ctx):
     assert torch.equal(img.view(torch.int32), img2.view(torch.int32))
     got = img.cpu().numpy()
     print(f"100k strands at 1080p: {stats['fragments']} fragments, {stats['ms_total']:.3f} ms", flush=True)
+    gold = golden("strands_100k_1080p")
+    check_census(hip, ctx, aid, 0, cam, lights, stats, gold, "100k strands 1080p")
     alpha = got[..., 3]
     ys, xs = np.nonzero(alpha > 0)
     order = np.argsort(alpha[ys, xs])
-    picks = [order[-1], order[len(order) // 2], order[len(order) // 20]]
+    picks = [(gold["deepest"][0]["x"], gold["deepest"][0]["y"])]
+    picks += [(int(xs[k]), int(ys[k])) for k in (order[-1], order[len(order) // 2], order[len(order) // 20])]
     geom = R.strand_level(asset)
     mat = mat_of(asset)
-    for pk in picks:
-        x0 = int(min(max(xs[pk] - 8, 0), cam.width - 24))
-        y0 = int(min(max(ys[pk] - 8, 0), cam.height - 24))
+    for x, y in picks:
+        x0 = int(min(max(x - 8, 0), cam.width - 24))
+        y0 = int(min(max(y - 8, 0), cam.height - 24))
         ref, ras = R.render(geom, cam, lights, mat, rect=(x0, y0, 24, 24))
         assert_radiance(got[y0:y0 + 24, x0:x0 + 24], ref[y0:y0 + 24, x0:x0 + 24], what=f"100k-strand 1080p rect {x0},{y0}")
     ws.close()

@@ -80,9 +80,10 @@ def test_rttd_mixed_frame(hip, ctx):
     asset = _rttd(hs.make_asset(1500, 10, 90.0, seed=24, sigma_spread=True))
     assigns = hs.kmeans_hierarchy(asset, (300, 60, 10), seed=24)
     aid = ctx.upload_asset(asset)
-    ctx.build_lod(aid, assigns)
-    lods = [{k: getattr(ctx.get_lod(aid, l), k) for k in ("centers", "ahat", "axes", "n_total", "sigma_a", "r")}
-            for l in range(1, 4)]
+    ctx.build_lod(aid, assigns)            # memberships; the level data below is the oracle's
+    lods = [OL.build_level(asset, a) for a in assigns]
+    for l, lod in enumerate(lods, 1):
+        ctx.set_lod(aid, l, lod)
     geoms = M.level_geoms(asset, lods)
     grps = M.groups(assigns)
     cam = hs.camera_for(asset, 112, 96)
