@@ -36,15 +36,16 @@ sys.path.insert(0, ROOT)
 WORKLOAD = "hair-100k-strands-32seg-1920x1080-2lights"
 METRIC = "Mfragments/s + frame ms (100k strands, 1080p); served p50/p99 latency"
 
-# Algorithmic operations per fragment of the shading kernel k_batch, counted from the
-# definition step by step (each add / mul / div / sqrt / compare / min / max / int op = 1;
-# exp, asin, atan2, sin, cos = one transcendental each).  Strand level.  Coverage (18) and the
-# depth key (7) belong to k_count / k_emit and are not counted here.
-OPS_BASE = 18 + 35 + 32 + 11 + 8                # alpha+h, point+tangent, frame, blend, sort
-TRANS_BASE = 1                                  # asin(theta_o)
-OPS_DIR_LIGHT = 171                             # angles 25 + f_single 137 + accumulate 9
-OPS_POINT_LIGHT = 186                           # + 15: direction, distance, 1/d^2
-TRANS_PER_LIGHT = 15                            # atan2, asin(theta_i), sin, cos, 2 asin, 3 exp, 3 x (2 exp)
+# Algorithmic operations per fragment of the shading kernel k_batch, counted by running the
+# oracle's per-fragment definition under an operation counter (tests/golden/count_ops.py ->
+# tests/golden/ops_per_fragment.json): alpha and h, world point, frame, each light, blend, and
+# ceil(log2 k) compares of the per-pixel sort.  Convention: an add, multiply, compare, select
+# or divide is one op, so a fused multiply-add counts as two ops; exp, log, sqrt, sin, cos,
+# asin, atan2 are one transcendental each, weighted 4 (the transcendental unit issues at a
+# quarter of the VALU rate).  The peak is one VALU instruction per lane per cycle (no packed
+# FP32): a kernel that fuses multiply-adds issues fewer instructions than the count, so the
+# fraction credits fusion; against the fused peak (two ops per lane per cycle) it is half.
+OPS_FILE = os.path.join(ROOT, "tests", "golden", "ops_per_fragment.json")
 TRANS_WEIGHT = 4                                # transcendental unit issues at 1/4 rate
 PEAK_LANE_OPS = 256 * 64 * 2.4e9                # 256 CUs x 64 lanes x 2.4 GHz (one op per lane per cycle)
 PEAK_HBM = 8.0e12
@@ -80,10 +81,30 @@ def read_traffic():
         return None
 
 
-def alg_ops(fragments: int, n_dir: int, n_point: int):
-    ops = fragments * (OPS_BASE + n_dir * OPS_DIR_LIGHT + n_point * OPS_POINT_LIGHT)
-    trans = fragments * (TRANS_BASE + (n_dir + n_point) * TRANS_PER_LIGHT)
+def ops_per_fragment(kind: str, lights):
+    """(ops, transcendentals) per fragment of k_batch for `kind` ("strand_100k_1080p" or
+    "thick_1080p") and the lights' kinds, from the oracle's counted definition."""
+    with open(OPS_FILE) as f:
+        c = json.load(f)[kind]
+    per = {0: next(v for k, v in c.items() if k.endswith("kind0")), 1: next(v for k, v in c.items() if k.endswith("kind1"))}
+    ops = c["base"][0] + c["blend"][0] + c["sort_compares"] + sum(per[l.kind][0] for l in lights)
+    trans = c["base"][1] + c["blend"][1] + sum(per[l.kind][1] for l in lights)
     return ops, trans
+
+
+def alg_ops(fragments: int, lights, kind: str = "strand_100k_1080p"):
+    ops, trans = ops_per_fragment(kind, lights)
+    return fragments * ops, fragments * trans
+
+
+def roofline(fragments: int, lights, t_kernel_s: float, kind: str, kernel: str, traffic=None):
+    ops, trans = alg_ops(fragments, lights, kind)
+    w = ops + TRANS_WEIGHT * trans
+    achieved = w / t_kernel_s
+    return {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_LANE_OPS / 1e12, 2),
+            "unit": "Tops/s", "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": traffic, "kernel": kernel,
+            "ops_per_launch": int(w), "ops_per_fragment": round(ops, 2), "trans_per_fragment": round(trans, 2),
+            "frac_of_fused_peak": round(achieved / (2 * PEAK_LANE_OPS), 4)}
 
 
 def cpu_baseline(asset, cam, lights, rows: int = 48):
@@ -115,6 +136,31 @@ def rttd_frame(ctx, asset, cam, lights, ws, frames: int = 20):
     ctx.release(aid)
     return {"gpu_mean": round(float(np.mean(ms)), 4), "gpu_p50": round(float(np.percentile(ms, 50)), 4),
             "fragments": int(st["fragments"]), "material": "R/TT/D (beta_R 0.1, beta_TT 0.2, gamma_TT 0.3)"}
+
+
+def thick_frame(ctx, ws, clusters: int = 1000, frames: int = 20):
+    """A thick-hair frame of the level sweep (150k strands x 64 segments, seeded k-means to 1k
+    thick hairs, 1920 x 1080, directional + point light) with the roofline of its shading
+    kernel k_batch<1, 0, false> (outside the timed region)."""
+    import numpy as np
+    import hairsynth as hs
+    t0 = time.perf_counter()
+    asset, cam, lights = hs.config(3)
+    aid = ctx.upload_asset(asset)
+    ctx.build_lod(aid, [hs.kmeans_assign(asset, clusters, seed=1003)])
+    ms, tile = [], []
+    for i in range(frames + 2):
+        _, st, _ = ctx.render(aid, 1, cam, lights, ws=ws)
+        if i >= 2:
+            ms.append(st["ms_total"])
+            tile.append(st["ms_tile"])
+    ctx.release(aid)
+    t = float(np.mean(tile)) * 1e-3
+    print(f"bench: thick-hair frame measured ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    return {"workload": f"hair-150k-strands-64seg-{clusters}-thick-hairs-1920x1080-2lights",
+            "gpu_mean": round(float(np.mean(ms)), 4), "gpu_p50": round(float(np.percentile(ms, 50)), 4),
+            "fragments": int(st["fragments"]), "k_batch_ms": round(t * 1e3, 4),
+            "roofline": roofline(int(st["fragments"]), lights, t, "thick_1080p", "k_batch<1, 0, false>")}
 
 
 def shadowed_frame(ctx, aid, cam, lights, ws, shadow=(1024, 4, 0.02), frames: int = 20):
@@ -227,12 +273,8 @@ def main():
     frags = sum(f["fragments"] for f in frames)
     ms_frame = np.array([f["ms_total"] for f in frames])
     ms_tile = np.array([f["ms_tile"] for f in frames])
-    n_dir = sum(1 for l in lights if l.kind == 0)
-    n_pt = len(lights) - n_dir
     f1 = frames[0]["fragments"]
-    ops, trans = alg_ops(f1, n_dir, n_pt)
     t_tile = float(ms_tile.mean()) * 1e-3
-    achieved = (ops + TRANS_WEIGHT * trans) / t_tile
     traffic = read_traffic()
     res = {
         "metric": METRIC,
@@ -254,15 +296,13 @@ def main():
                      "gpu_p99": round(float(np.percentile(ms_frame, 99)), 4),
                      "front": round(float(np.mean([f["ms_project"] for f in frames])), 4),
                      "tile": round(float(ms_tile.mean()), 4)},
-        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_LANE_OPS / 1e12, 2),
-                     "unit": "Tops/s", "frac": round(achieved / PEAK_LANE_OPS, 4),
-                     "traffic": traffic, "kernel": "k_batch<0, 0, false>",
-                     "ops_per_launch": int(ops + TRANS_WEIGHT * trans)},
+        "roofline": roofline(f1, lights, t_tile, "strand_100k_1080p", "k_batch<0, 0, false>", traffic),
         "cpu_baseline": None,
     }
     if not args.no_extras:
         res["frame_ms_rttd"] = rttd_frame(ctx, asset, cam, lights, ws)
         res["frame_ms_shadowed"] = shadowed_frame(ctx, aid, cam, lights, ws)
+        res["frame_ms_thick"] = thick_frame(ctx, ws)
     for w in wss:
         w.close()
     if not args.no_serve:

@@ -1,6 +1,6 @@
 """The benchmark's contract on the CPU: one GPU only (other counts exit with a message), the
-algorithmic operation count of the shading kernel, and the traffic summary taken only when it
-was measured on the current kernel sources."""
+algorithmic operation count of the shading kernel (the oracle's counted definition), and the
+traffic summary taken only when it was measured on the current kernel sources."""
 import os
 import subprocess
 import sys
@@ -17,15 +17,60 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
-def test_algorithmic_ops_per_fragment():
-    # per fragment: base 104 ops + 1 transcendental; each light adds its lobes and 15 transcendentals
-    ops, trans = bench.alg_ops(1, 0, 0)
-    assert (ops, trans) == (104, 1)
-    ops, trans = bench.alg_ops(10, 1, 1)
-    assert ops == 10 * (104 + 171 + 186) and trans == 10 * (1 + 2 * 15)
-    # the figure the bench reports for the 1080p frame (25,244,783 fragments, one light of each kind)
-    ops, trans = bench.alg_ops(25_244_783, 1, 1)
-    assert int(ops + bench.TRANS_WEIGHT * trans) == 14_768_198_055
+def _count_ops_module():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("count_ops", os.path.join(ROOT, "tests", "golden", "count_ops.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_ops_per_fragment_are_the_oracles_counted_definition():
+    """The counts the bench prices its roofline with equal a fresh count of the oracle's
+    per-fragment path on another (small) scene: per fragment they do not depend on the scene."""
+    import json
+
+    import numpy as np
+
+    import hairsynth as hs
+    from oracle import lod as OL
+    from oracle import render as R
+    co = _count_ops_module()
+    with open(bench.OPS_FILE) as f:
+        stored = json.load(f)
+    asset = hs.make_asset(400, 8, 90.0, seed=77, sigma_spread=True)
+    cam = hs.camera_for(asset, 96, 80)
+    lights = hs.default_lights(asset, with_point=True)
+    mat = tuple(float(v) for v in asset.material.as_array())
+    for kind, geom in (("strand_100k_1080p", R.strand_level(asset)),
+                       ("thick_1080p", R.cluster_level(OL.build_level(asset, hs.kmeans_assign(asset, 20, seed=77))))):
+        got = co.count(geom, cam, lights, mat, (0, 0, 96, 80))
+        assert got["unknown"] == {}
+        for key in ("base", "light0_kind0", "light1_kind1", "blend"):
+            assert np.allclose(got[key], stored[kind][key], rtol=2e-3, atol=0.02), (kind, key, got[key], stored[kind][key])
+    # the bench's per-fragment figures for the 1080p frame (one light of each kind)
+    ops, trans = bench.ops_per_fragment("strand_100k_1080p", lights)
+    st = stored["strand_100k_1080p"]
+    assert abs(ops - (st["base"][0] + st["light0_kind0"][0] + st["light1_kind1"][0] + st["blend"][0]
+                      + st["sort_compares"])) < 1e-9
+    assert abs(trans - (st["base"][1] + st["light0_kind0"][1] + st["light1_kind1"][1])) < 1e-9
+
+
+def test_planted_op_count_mistake_is_caught(monkeypatch):
+    """A dropped term in the counted definition changes the count."""
+    co = _count_ops_module()
+    import hairsynth as hs
+    from oracle import fiber as FB
+    from oracle import render as R
+    asset = hs.make_asset(100, 6, 90.0, seed=78)
+    cam = hs.camera_for(asset, 64, 48)
+    lights = hs.default_lights(asset, with_point=False)
+    mat = tuple(float(v) for v in asset.material.as_array())
+    ref = co.count(R.strand_level(asset), cam, lights, mat, (0, 0, 64, 48))["light0_kind0"]
+    orig = FB.gaussian
+    monkeypatch.setattr(FB, "gaussian", lambda beta, x: orig(beta, x) * 1.0)
+    got = co.count(R.strand_level(asset), cam, lights, mat, (0, 0, 64, 48))["light0_kind0"]
+    assert got[0] != ref[0]
 
 
 def test_traffic_only_for_the_measured_sources(tmp_path, monkeypatch):

@@ -40,12 +40,17 @@ def _gpu_vjp(ctx, aid, cam, lights, d_rgba, K, S):
     return da.cpu().numpy(), dr.cpu().numpy(), ds.cpu().numpy()
 
 
-def _close(got, ref, what):
+def _close(got, ref, what, rel=2e-3, floor=2e-3):
+    """|got - ref| <= rel |ref| + floor max|ref| per entry (float32 sums of many per-fragment
+    terms, accumulated by atomics in no fixed order, against a float64 gradient)."""
     scale = float(np.abs(ref).max())
     err = np.abs(got - ref)
-    tol = 2e-3 * scale + 2e-3 * np.abs(ref)
+    tol = floor * scale + rel * np.abs(ref)
     bad = int((err > tol).sum())
-    print(f"[{what}] max |err| {float(err.max()):.3e} (scale {scale:.3e}), violations {bad}/{ref.size}", flush=True)
+    big = np.abs(ref) > 1e-3 * scale
+    worst = float((err[big] / np.abs(ref[big])).max()) if big.any() else 0.0
+    print(f"[{what}] max |err| {float(err.max()):.3e} (scale {scale:.3e}), worst rel err of entries above "
+          f"1e-3 of the scale {worst:.2e}, violations {bad}/{ref.size}", flush=True)
     assert bad == 0, what
 
 
@@ -65,6 +70,35 @@ def test_backward_matches_oracle_gradient(hip, ctx, seed):
     _close(da, g_axes, "d_axes")
     _close(dr, g_r, "d_r")
     _close(ds, g_sig, "d_sigma_a")
+    ctx.release(aid)
+
+
+def test_backward_long_tile_lists_matches_oracle_gradient(hip, ctx):
+    """1,500 thick hairs x 8 segments at 64x64: tile lists of up to ~4,600 segments, so list
+    entries beyond the 1,024 that the kernel sums in LDS go straight to global atomics; every
+    gradient entry within 1e-3 relative of the oracle's, above a floor of 1e-5 of the largest."""
+    print("case: backward vs oracle with tile lists beyond 1024 entries", flush=True)
+    asset = hs.make_asset(6000, 8, 90.0, seed=17, sigma_spread=True)
+    cam = hs.camera_for(asset, 64, 64)
+    lights = hs.default_lights(asset, with_point=True)
+    lod = OL.build_level(asset, hs.kmeans_assign(asset, 1500, seed=17))
+    K, S = lod["n_total"].size, asset.segs
+    aid = ctx.upload_asset(asset)
+    ctx.set_lod(aid, 1, lod)
+    ws = ctx.workspace()
+    _, st, _ = ctx.render(aid, 1, cam, lights, ws=ws)
+    ts, _ = ctx.debug_bins(ws, 16, int(st["pairs"]))
+    assert int(np.diff(ts.astype(np.int64)).max()) > 2 * 1024     # tile lists beyond the LDS accumulators
+    rng = np.random.default_rng(17)
+    d_rgba = rng.normal(size=(cam.height, cam.width, 4))
+    mat = tuple(float(v) for v in asset.material.as_array())
+    geom = R.cluster_level(lod)
+    g_axes, g_r, g_sig, _ = OG.cluster_vjp(geom, cam, lights, mat, d_rgba, K, S)
+    da, dr, ds = _gpu_vjp(ctx, aid, cam, lights, d_rgba, K, S)
+    _close(da, g_axes, "d_axes (long lists)", rel=1e-3, floor=1e-5)
+    _close(dr, g_r, "d_r (long lists)", rel=1e-3, floor=1e-5)
+    _close(ds, g_sig, "d_sigma_a (long lists)", rel=1e-3, floor=1e-5)
+    ws.close()
     ctx.release(aid)
 
 
