@@ -39,15 +39,17 @@ METRIC = "Mfragments/s + frame ms (100k strands, 1080p); served p50/p99 latency"
 # Algorithmic operations per fragment of the shading kernel k_batch, counted by running the
 # oracle's per-fragment definition under an operation counter (tests/golden/count_ops.py ->
 # tests/golden/ops_per_fragment.json): alpha and h, world point, frame, each light, blend, and
-# ceil(log2 k) compares of the per-pixel sort.  Convention: an add, multiply, compare, select
-# or divide is one op, so a fused multiply-add counts as two ops; exp, log, sqrt, sin, cos,
-# asin, atan2 are one transcendental each, weighted 4 (the transcendental unit issues at a
-# quarter of the VALU rate).  The peak is one VALU instruction per lane per cycle (no packed
-# FP32): a kernel that fuses multiply-adds issues fewer instructions than the count, so the
-# fraction credits fusion; against the fused peak (two ops per lane per cycle) it is half.
+# ceil(log2 k) compares of the per-pixel sort; operations on values every fragment shares are
+# not counted.  Unit: an FP32 lane-operation.  An add, multiply, compare, select or divide is
+# one (the definition does not fuse, so a multiply-add counts two); exp, log, sqrt, sin, cos,
+# asin, atan2 are one transcendental each, weighted 4 (quarter-rate issue).  Peak: MI355X's
+# published FP32 vector rate, 157.3 TFLOP/s = 256 CUs x 128 FP32 lanes x 2.4 GHz x 2 (FMA), i.e.
+# 78.6 T lane-operations per second.  (Measured on the device with --rate-probe: unpacked
+# v_fma_f32 issues at ~56 T/s, v_exp/v_rcp/v_sqrt at ~18 T/s.)  A kernel that fuses
+# multiply-adds issues fewer lane-operations than counted, so the fraction credits fusion.
 OPS_FILE = os.path.join(ROOT, "tests", "golden", "ops_per_fragment.json")
 TRANS_WEIGHT = 4                                # transcendental unit issues at 1/4 rate
-PEAK_LANE_OPS = 256 * 64 * 2.4e9                # 256 CUs x 64 lanes x 2.4 GHz (one op per lane per cycle)
+PEAK_LANE_OPS = 256 * 128 * 2.4e9               # 256 CUs x 128 FP32 lanes x 2.4 GHz = 157.3 TFLOP/s / 2
 PEAK_HBM = 8.0e12
 
 KERNEL_SOURCES = ["paper_2405_10565_amd/csrc/hair_kernels.hip", "paper_2405_10565_amd/csrc/hair_shading.h",
@@ -98,13 +100,13 @@ def alg_ops(fragments: int, lights, kind: str = "strand_100k_1080p"):
 
 
 def roofline(fragments: int, lights, t_kernel_s: float, kind: str, kernel: str, traffic=None):
-    ops, trans = alg_ops(fragments, lights, kind)
-    w = ops + TRANS_WEIGHT * trans
+    opf, trf = ops_per_fragment(kind, lights)
+    w = fragments * (opf + TRANS_WEIGHT * trf)
     achieved = w / t_kernel_s
     return {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_LANE_OPS / 1e12, 2),
             "unit": "Tops/s", "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": traffic, "kernel": kernel,
-            "ops_per_launch": int(w), "ops_per_fragment": round(ops, 2), "trans_per_fragment": round(trans, 2),
-            "frac_of_fused_peak": round(achieved / (2 * PEAK_LANE_OPS), 4)}
+            "ops_per_launch": int(w), "ops_per_fragment": round(opf, 2), "trans_per_fragment": round(trf, 2),
+            "trans_weight": TRANS_WEIGHT}
 
 
 def cpu_baseline(asset, cam, lights, rows: int = 48):
@@ -217,6 +219,8 @@ def main():
                     help="skip the R/TT/D and shadowed frames reported beside the main frame")
     ap.add_argument("--serve-requests", type=int, default=3000, help="measured requests per arrival rate")
     ap.add_argument("--serve-warmup", type=int, default=200, help="unmeasured requests before them, per rate")
+    ap.add_argument("--rate-probe", action="store_true",
+                    help="only measure the device's issue rates of fma, exp, rcp, sqrt and integer multiplies")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -228,6 +232,14 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": src.numel() * 4, "launches": 5}))
+        return
+    if args.rate_probe:
+        from paper_2405_10565_amd import binding as B
+        ctx = B.Context(0)
+        names = ["v_fma_f32", "v_exp_f32", "v_rcp_f32", "v_sqrt_f32", "v_mul_lo_u32", "v_mul_u32_u24"]
+        rates = {n: round(ctx.issue_rate(k, 8192) / 1e12, 3) for k, n in enumerate(names)}
+        ctx.close()
+        print(json.dumps({"issue_rate_tops": rates, "peak_lane_ops_tops": round(PEAK_LANE_OPS / 1e12, 2)}))
         return
     if args.gpus != 1:
         print(f"bench.py: the renderer runs on one GPU; --gpus {args.gpus} is not supported "

@@ -321,6 +321,13 @@ int hair_render_backward(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t leve
                          const float* d_rgba, float* d_axes, float* d_r, float* d_sigma_a,
                          void* stream);
 
+/* Measurement export: the device's issue rate of one instruction kind, in lane-operations per
+ * second, from a kernel of independent chains at full occupancy (256 x 32 blocks of 256
+ * threads, iters rounds of 8 operations per thread) timed with hipEvents on the legacy default
+ * stream.  kind 0: v_fma_f32, 1: v_exp_f32, 2: v_rcp_f32, 3: v_sqrt_f32, 4: v_mul_lo_u32,
+ * 5: v_mul_u32_u24.  Uses the context's static scratch (see hair_render_noalloc). */
+int hair_debug_issue_rate(hair_ctx* ctx, int32_t kind, int32_t iters, double* ops_per_s);
+
 /* Test exports of the last hair_render on `ws` (synchronise and copy to host):
  * segments: int[n][6] (XA, YA, XB, YB, hw_fx, flags: bit0 visible, bit1 negative h side,
  *           bit2 culled for size, bit3 thick hair of a mixed frame) and float[n][3]

@@ -29,7 +29,7 @@ EXPORTS = [
     "hair_select_level", "hair_render", "hair_render_backward", "hair_debug_segments", "hair_debug_bins",
     "hair_debug_fragments", "hair_lod_groups", "hair_lod_init", "hair_render_mixed", "hair_render_shadowed",
     "hair_debug_dom", "hair_render_curved", "hair_render_async", "hair_ws_finish", "hair_render_noalloc",
-    "hair_noalloc_scratch_bytes",
+    "hair_noalloc_scratch_bytes", "hair_debug_issue_rate",
 ]
 
 
@@ -126,6 +126,7 @@ def _load():
         "hair_render_noalloc": ([P, I32, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32, P, P,
                                  C.POINTER(hair_stats)], C.c_int),
         "hair_noalloc_scratch_bytes": ([], U64),
+        "hair_debug_issue_rate": ([P, I32, I32, C.POINTER(C.c_double)], C.c_int),
         "hair_render_backward": ([P, P, I32, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32, P, P, P, P, P],
                                  C.c_int),
         "hair_lod_groups": ([P, I32, ip], C.c_int),
@@ -474,6 +475,12 @@ class Context:
                                        C.c_void_p(d_rgba.data_ptr()), C.c_void_p(d_axes.data_ptr()),
                                        C.c_void_p(d_r.data_ptr()), C.c_void_p(d_sigma_a.data_ptr()),
                                        _stream_ptr(stream)))
+
+    def issue_rate(self, kind: int, iters: int = 4096) -> float:
+        """Lane-operations per second of one instruction kind (hair_debug_issue_rate)."""
+        v = C.c_double()
+        check(lib.hair_debug_issue_rate(self.handle, int(kind), int(iters), C.byref(v)))
+        return v.value
 
     def debug_segments(self, ws: Workspace, n: int):
         ri = np.zeros((n, 6), np.int32)

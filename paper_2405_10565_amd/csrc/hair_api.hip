@@ -1646,6 +1646,29 @@ int hair_render_backward(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t leve
     return HAIR_OK;
 }
 
+int hair_debug_issue_rate(hair_ctx* ctx, int32_t kind, int32_t iters, double* ops_per_s) {
+    int rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if (kind < 0 || kind > 5) return fail(HAIR_EINVAL, "probe kind %d outside [0, 5]", kind);
+    if (iters < 1 || iters > (1 << 20)) return fail(HAIR_EINVAL, "iters %d outside [1, 2^20]", iters);
+    if (!ops_per_s) return fail(HAIR_EINVAL, "null output pointer");
+    if ((rc = need_device(ctx))) return rc;
+    hair_ws* ws = ctx->fixed_ws;
+    if (!ws) return fail(HAIR_EDEVICE, "the context has no static scratch");
+    std::lock_guard<std::mutex> g(ws->mu);
+    const int blocks = 256 * 32;                     // 32 blocks of 4 waves per CU: full occupancy
+    float* out = reinterpret_cast<float*>(ws->arena);
+    HIP_TRY(ctx, launch_probe_rate(kind, blocks, 1, out, nullptr), "k_probe_rate");   // warm-up
+    HIP_TRY(ctx, hipEventRecord(ws->ev[0], nullptr), "hipEventRecord");
+    HIP_TRY(ctx, launch_probe_rate(kind, blocks, iters, out, nullptr), "k_probe_rate");
+    HIP_TRY(ctx, hipEventRecord(ws->ev[6], nullptr), "hipEventRecord");
+    HIP_TRY(ctx, hipEventSynchronize(ws->ev[6]), "hipEventSynchronize");
+    float ms = 0.0f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, ws->ev[0], ws->ev[6]), "elapsed");
+    *ops_per_s = (double)blocks * 256.0 * 8.0 * (double)iters / (ms * 1e-3);
+    return HAIR_OK;
+}
+
 int hair_debug_segments(hair_ws* ws, int64_t n, int32_t* rec_i, float* rec_f) {
     if (!ws || !rec_i || !rec_f) return fail(HAIR_EINVAL, "null argument");
     if (n != ws->last_nseg) return fail(HAIR_EINVAL, "last render had %lld segments", (long long)ws->last_nseg);

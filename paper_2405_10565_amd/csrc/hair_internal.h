@@ -279,5 +279,6 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
 hipError_t launch_fill_pix(uint32_t* cnt, uint32_t* kmin, uint32_t* kmax, size_t n, float* rgba, size_t n_rgba4,
                            hipStream_t st);   // also clears rgba (n_rgba4 pixels) when given
 hipError_t launch_fill_f32(float* p, float v, size_t n, hipStream_t st);
+hipError_t launch_probe_rate(int kind, int blocks, int iters, float* out, hipStream_t st);
 
 }  // namespace hair

@@ -754,16 +754,29 @@ __global__ void k_fill_f32(float* p, float v, size_t n) {
 // 32-bit integers are exact here: endpoints lie inside the guard band, |dx|, |dy| <= kMaxAxis
 // (longer segments are culled), the radius is <= kMaxHwFx + 8 and every candidate pixel centre
 // lies in the segment's box widened by the radius, so |e_u|, |e_v| < 2^15 and each product
-// stays under 2^31; cross^2 and R^2 t_den are compared in 64 bits.  x >> 4 is floor(x / 16).
+// stays under 2^31: the products take the 24-bit multiplier (operands below 2^23), and along a
+// line t_num and cross advance by 16 dv and 16 du per pixel.  cross^2 < R^2 t_den is decided as
+// |cross| <= s_max = floor(sqrt(R^2 t_den - 1)), found per segment in 64-bit integers.
+// x >> 4 is floor(x / 16).
 // The candidate interval is computed in float32: only an enumeration, so it just has to contain
 // every covered pixel.  Each bound is a product or difference of values below 2^31 computed with
 // relative error under 1e-6 (float conversions, the hardware reciprocal and square root,
 // roundings); the interval is widened by 2e-6 of the magnitudes involved plus one sub-pixel.
 struct CovSetup {
     int4 g0;     // (au, av, du, dv): start and extent along the major and minor axes, 1/16 px
-    int4 g1;     // (R, tden, first line - lines before this lane in the wave, steep)
+    int4 g1;     // (s_max, tden, first line - lines before this lane in the wave, steep | wide << 1)
     float4 g2;   // (1 / du, 1 / dv or 0, R sqrt(tden) / |du|, bits: first | last minor index << 16)
 };
+
+// The largest s with s^2 < R^2 t_den (R^2 t_den >= 64): a double square root, corrected in
+// 64-bit integers, so that |cross| <= s_max is exactly cross^2 < R^2 t_den.
+__device__ inline int strip_smax(int R, int tden) {
+    const unsigned long long lim = (unsigned long long)(unsigned)(R * R) * (unsigned)tden - 1ull;
+    unsigned long long s = (unsigned long long)sqrt((double)lim);
+    while (s * s > lim) --s;
+    while ((s + 1) * (s + 1) <= lim) ++s;
+    return (int)min(s, 0x7FFFFFFFull);
+}
 constexpr int kCovLinesPerWave = 64 * kTile;   // a segment has at most kTile lines in a tile
 
 // Stages lane t's segment (valid: the lane holds one) in s_cov[t], numbers the wave's lines
@@ -791,7 +804,7 @@ __device__ inline uint32_t cov_setup(const SegRec& s, bool valid, int px0, int p
             const float inv_dv = dv != 0 ? __builtin_amdgcn_rcpf((float)dv) : 0.0f;
             const int vmin = steep ? i0 : j0, vmax = steep ? i1 : j1;   // 0 <= vmin <= vmax < 2^16
             c.g0 = make_int4(au, av, du, dv);
-            c.g1 = make_int4(R, tden, steep ? j0 : i0, steep ? 1 : 0);
+            c.g1 = make_int4(strip_smax(R, tden), tden, steep ? j0 : i0, (steep ? 1 : 0) | (R > 32 ? 2 : 0));
             c.g2 = make_float4(inv_du, inv_dv, (float)R * __builtin_amdgcn_sqrtf((float)tden) * fabsf(inv_du),
                                __int_as_float(vmin | (vmax << 16)));
         }
@@ -823,22 +836,22 @@ __device__ inline void wave_coverage(const CovSetup* s_cov, const uint8_t* s_own
         const int o = wbase + own[g];
         const CovSetup c = s_cov[o];
         const int au = c.g0.x, av = c.g0.y, du = c.g0.z, dv = c.g0.w;
-        const int R = c.g1.x, tden = c.g1.y, u = c.g1.z + (int)g;
-        const bool steep = c.g1.w != 0;
+        const int smax = c.g1.x, tden = c.g1.y, u = c.g1.z + (int)g;
+        const bool steep = (c.g1.w & 1) != 0, wide = (c.g1.w & 2) != 0;
         const int vb = __float_as_int(c.g2.w);
         const int vmin = vb & 0xFFFF, vmax = vb >> 16;
-        const unsigned long long RR = (unsigned long long)(unsigned)(R * R) * (unsigned)tden;
         const int eu = 16 * u + 8 - au;
+        const int eu_du = __mul24(eu, du), eu_dv = __mul24(eu, dv);
         // the strip bounds the span; the slab trims it too for wide segments (radius above
         // 2 px: thick hairs, whose short steps would otherwise test most of their box), while
         // for strands it would only trim the end lines, whose extra candidates the integer
         // test rejects
-        const float cc = (float)(eu * dv) * c.g2.x;
+        const float cc = (float)eu_dv * c.g2.x;
         float lo_f = cc - c.g2.z, hi_f = cc + c.g2.z;
         float mag = (fabsf((float)av) + fabsf(cc)) + c.g2.z;
-        if (R > 32 && dv != 0) {
-            const float a = (float)(-eu * du) * c.g2.y;
-            const float b = (float)(tden - eu * du) * c.g2.y;
+        if (wide && dv != 0) {
+            const float a = (float)(-eu_du) * c.g2.y;
+            const float b = (float)(tden - eu_du) * c.g2.y;
             lo_f = fmaxf(lo_f, fminf(a, b));
             hi_f = fminf(hi_f, fmaxf(a, b));
             mag += fmaxf(fabsf(a), fabsf(b));
@@ -848,14 +861,13 @@ __device__ inline void wave_coverage(const CovSetup* s_cov, const uint8_t* s_own
         const float fhi = floorf(((float)av + (hi_f + w) - 8.0f) * (1.0f / 16.0f));
         const int k0 = (int)fmaxf((float)vmin, flo);
         const int k1 = (int)fminf((float)vmax, fhi);
-        const int eu_du = eu * du, eu_dv = eu * dv;
-        for (int k = k0; k <= k1; ++k) {
-            const int ev = 16 * k + 8 - av;
-            const int tnum = ev * dv + eu_du;
+        const int ev0 = 16 * k0 + 8 - av;
+        int tnum = __mul24(ev0, dv) + eu_du;
+        int cr = __mul24(ev0, du) - eu_dv;
+        const int dv16 = dv * 16, du16 = du * 16;
+        for (int k = k0; k <= k1; ++k, tnum += dv16, cr += du16) {
             if (tnum < 0 || tnum >= tden) continue;
-            const int cr = ev * du - eu_dv;
-            const unsigned acr = (unsigned)abs(cr);
-            if ((unsigned long long)acr * acr >= RR) continue;
+            if ((unsigned)abs(cr) > (unsigned)smax) continue;
             if (steep) f(k - px0, u - py0, tnum, tden, o);
             else f(u - px0, k - py0, tnum, tden, o);
         }
@@ -2876,6 +2888,49 @@ hipError_t launch_fill_pix(uint32_t* cnt, uint32_t* kmin, uint32_t* kmax, size_t
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3(min(blocks_for(n, 256), 4096)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+// Issue-rate probe: every lane runs `iters` rounds of 8 independent chains of one instruction
+// (0: v_fma_f32, 1: v_exp_f32, 2: v_rcp_f32, 3: v_sqrt_f32, 4: v_mul_lo_u32, 5: v_mul_u32_u24),
+// so that the rate, not the latency, bounds the kernel.  The chains stay finite and bounded
+// (exp2 of a value in [-1, 0], rcp alternating, sqrt toward 1, integer products wrapping);
+// their sum is stored only if it equals an impossible value, which keeps them live.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_probe_rate(float* __restrict__ out, int iters) {
+    float a[8];
+    uint32_t u[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        a[i] = 0.5f + 1e-3f * (float)(threadIdx.x & 63) + 0.01f * (float)i;
+        u[i] = threadIdx.x * 8u + (uint32_t)i + 1u;
+    }
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (KIND == 0) a[i] = __builtin_fmaf(a[i], 0.999f, 1e-4f);
+            if (KIND == 1) a[i] = __builtin_amdgcn_exp2f(-a[i]);
+            if (KIND == 2) a[i] = __builtin_amdgcn_rcpf(a[i]);
+            if (KIND == 3) a[i] = __builtin_amdgcn_sqrtf(a[i]);
+            if (KIND == 4) u[i] = u[i] * 0x9E3779B1u;
+            if (KIND == 5) u[i] = __umul24(u[i], 0x3779B1u);
+        }
+    }
+    float sum = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) sum += a[i] + (float)u[i];
+    if (sum == -1.0f) out[0] = sum;
+}
+
+hipError_t launch_probe_rate(int kind, int blocks, int iters, float* out, hipStream_t st) {
+    switch (kind) {
+        case 0: hipLaunchKernelGGL(k_probe_rate<0>, dim3(blocks), dim3(256), 0, st, out, iters); break;
+        case 1: hipLaunchKernelGGL(k_probe_rate<1>, dim3(blocks), dim3(256), 0, st, out, iters); break;
+        case 2: hipLaunchKernelGGL(k_probe_rate<2>, dim3(blocks), dim3(256), 0, st, out, iters); break;
+        case 3: hipLaunchKernelGGL(k_probe_rate<3>, dim3(blocks), dim3(256), 0, st, out, iters); break;
+        case 4: hipLaunchKernelGGL(k_probe_rate<4>, dim3(blocks), dim3(256), 0, st, out, iters); break;
+        default: hipLaunchKernelGGL(k_probe_rate<5>, dim3(blocks), dim3(256), 0, st, out, iters); break;
+    }
     return hipGetLastError();
 }
 

@@ -4,8 +4,10 @@ definition under an operation counter, and writes tests/golden/ops_per_fragment.
     python tests/golden/count_ops.py
 
 What is counted: every elementwise arithmetic operation the oracle's per-fragment path
-performs on its float64 tensors (torch), weighted by the number of elements it produces
-(reductions by inputs minus outputs), divided by the number of fragments.  The path is the
+performs on its float64 tensors (torch) with an input that differs between fragments,
+weighted by the number of elements it produces (reductions by inputs minus outputs), divided
+by the number of fragments.  Operations on values every fragment shares (material, light and
+quadrature-node constants) are computed once per frame and not counted.  The path is the
 one the shading kernel executes per fragment: alpha and h (oracle.render.fragment_alpha_h),
 the world point and tangent (shading_inputs), the frame (frame), then per light its
 direction and irradiance (light_dirs) and the scattering function (f_single for strands,
@@ -67,11 +69,24 @@ def _numel(x):
     return x.numel() if isinstance(x, torch.Tensor) else 1
 
 
+def _varying(x, F):
+    """Whether tensor x holds different values for different fragments (dimension 0 of
+    length F); values shared by every fragment (material, light and quadrature constants,
+    expanded or not) are computed once per frame, not per fragment."""
+    if not isinstance(x, torch.Tensor) or x.dim() == 0 or x.shape[0] != F or F <= 1:
+        return False
+    if x.stride(0) == 0:
+        return False
+    return not bool((x == x[:1]).all())
+
+
 class OpCounter(TorchFunctionMode):
     """Counts arithmetic on tensors (elements produced per operation)."""
 
-    def __init__(self):
+    def __init__(self, F, shared_filter=True):
         super().__init__()
+        self.F = F
+        self.shared_filter = shared_filter
         self.ops = 0
         self.trans = 0
         self.unknown = Counter()
@@ -82,6 +97,12 @@ class OpCounter(TorchFunctionMode):
         name = getattr(func, "__name__", "") or str(func)
         name = name.split(".")[-1]
         n = _numel(out[0] if isinstance(out, tuple) else out)
+        ins = [a for a in list(args) + list(kwargs.values()) if isinstance(a, torch.Tensor)]
+        for a in args:
+            if isinstance(a, (list, tuple)):
+                ins += [b for b in a if isinstance(b, torch.Tensor)]
+        if self.shared_filter and name not in NO_ARITH and not any(_varying(a, self.F) for a in ins):
+            return out                                                # the same for every fragment
         if name in ELEM_OPS:
             self.ops += n
         elif name in ("__pow__", "pow") and len(args) > 1 and isinstance(args[1], (int, float)) and args[1] == 2:
@@ -129,7 +150,7 @@ class _HalfWeight:
 
 
 def _counted(geom, ras, cam, lights, mat):
-    with OpCounter() as c:
+    with OpCounter(len(ras.seg)) as c:
         AG.hemisphere_stats = _HalfWeight(c, AG.hemisphere_stats)
         try:
             R.fragment_radiance(geom, ras, cam, lights, mat)
@@ -151,7 +172,7 @@ def count(geom, cam, lights, mat, band):
         res[f"light{li}_kind{light.kind}"] = (c.ops / F - res["base"][0], c.trans / F - res["base"][1])
         unknown.update(c.unknown)
     alpha, L = R.fragment_radiance(geom, ras, cam, lights, mat)
-    with OpCounter() as c:
+    with OpCounter(F, shared_filter=False) as c:       # (its tensors are per pixel rank, all varying)
         R.composite(ras, alpha, L)
     # (less the image's 1 - T for every pixel, which is per pixel, not per fragment)
     res["blend"] = ((c.ops - ras.W * ras.H) / F, c.trans / F)
