@@ -95,7 +95,7 @@ typedef struct hair_stats {
     uint32_t segments;           /* segments of the level */
     uint32_t segments_visible;   /* after near-plane, guard-band and size culling */
     uint32_t segments_culled_long; /* culled for exceeding 1024 px per axis or 256 px half-width */
-    uint32_t overflow_pixels;    /* pixels with more than HAIR_PIXEL_CAPACITY fragments at one depth key (left 0) */
+    uint32_t overflow_pixels;    /* pixels that could not be ordered (none in a forward frame; backward: > 64 slices) */
     float ms_total;              /* GPU time of the call's kernels (hipEvent) */
     float ms_project;            /* of which before shading: projection, binning, coverage, emission */
     float ms_bin;                /* 0: binning is timed within ms_project */
@@ -212,13 +212,17 @@ typedef struct hair_shadow {
     float layer_depth;
 } hair_shadow;
 
-/* Render one frame (the hot path).  rgba_out: device float[height][width][4], premultiplied
+/* Render one frame (the hot path: projection and half-width, Sec. 5.2; binning and coverage
+ * of the strips; per fragment f_single (Sec. 3.1, eq. bcsdf) or f_ours (Sec. 4, eq. our_bcsdf)
+ * times E cos(theta_i) (Sec. 3); front-to-back compositing in (depth key, segment id) order).
+ * rgba_out: device float[height][width][4], premultiplied
  * (C, 1 - T) over transparent black, written in full.  n_lights in 1..HAIR_MAX_LIGHTS.
  * The call synchronises `stream` once, at the end.  The first frame on a workspace (and a
  * frame that outgrows the workspace's buffers, which is then rendered again) also
  * synchronises twice in between to size them, with a quarter of headroom kept for the
- * frames that follow.  Pixels of any depth are rendered exactly; HAIR_ERANGE only when more than
- * HAIR_PIXEL_CAPACITY fragments of one pixel share one depth key (stats->overflow_pixels). */
+ * frames that follow.  Pixels of any depth are rendered exactly, in slices of at most
+ * HAIR_PIXEL_CAPACITY fragments cut by depth key and, inside a key shared by more fragments,
+ * by segment id. */
 int hair_render(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,
                 const hair_light* lights, int32_t n_lights, float* rgba_out, void* stream,
                 hair_stats* stats);
@@ -309,8 +313,11 @@ int hair_render_mixed(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_came
                       float* rgba_out, void* stream, hair_stats* stats);
 
 /* Vector-Jacobian product of hair_render at a thick-hair level (level >= 1) with respect to
- * the level's fitted parameters (HAIR_ERANGE when a pixel is deeper than one LDS batch of
- * HAIR_PIXEL_CAPACITY fragments): given d_rgba (device float[height][width][4]) writes
+ * the level's fitted parameters (Sec. 4: the aggregated model's |a|, |b| per cluster segment,
+ * r and sigma_a per cluster; the half-width of Sec. 5.2 follows |a|, |b|).  Pixels deeper
+ * than one LDS batch are differentiated slice by slice in (key, segment id) order (HAIR_ERANGE
+ * only for a pixel needing more than 64 slices of HAIR_PIXEL_CAPACITY fragments): given
+ * d_rgba (device float[height][width][4]) writes
  *   d_axes    device float[K][S][2]  d/d|a|, d/d|b|
  *   d_r       device float[K]        d/dr
  *   d_sigma_a device float[3][K]     d/dsigma_a

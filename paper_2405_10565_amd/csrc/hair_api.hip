@@ -1640,9 +1640,9 @@ int hair_render_backward(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t leve
     FrameOut fo;
     if ((rc = run_frame(ctx, ws, *a, lv, cam, lights, n_lights, nullptr, nullptr, (hipStream_t)stream, &fo, true, &grad)))
         return rc;
-    if (fo.ctr.deep_pixels || fo.ctr.overflow_pixels)
-        return fail(HAIR_ERANGE, "%u pixels are deeper than one batch of %d fragments (their gradient is missing)",
-                    fo.ctr.deep_pixels + fo.ctr.overflow_pixels, kCap);
+    if (fo.ctr.overflow_pixels)
+        return fail(HAIR_ERANGE, "%u pixels need more than 64 slices of %d fragments (their gradient is missing)",
+                    fo.ctr.overflow_pixels, kCap);
     return HAIR_OK;
 }
 

@@ -1569,12 +1569,14 @@ struct BatchLds {
 // Exact order, shading and blending of the Fb records staged in s_A (whole pixels whose
 // counts, key ranges and offsets are in s_cnt / s_kmin / s_kmax / s_off).  Finished pixels are
 // written to rgba, or (slice_out != nullptr, a single pixel's key slice) their (C, T) goes to
-// slice_out.  rank0 / cnt_total place a slice inside its pixel for the debug dump.
+// slice_out.  rank0 / cnt_total place a slice inside its pixel for the debug dump; by_seg: the
+// records carry segment ids in place of keys (a slice inside one key, key_of_slice).
 template <int KIND, int MODEL, bool SHADOW>
 __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, float* __restrict__ rgba,
                                         const DebugDump& dbg, int has_dbg, const BatchLds& L_, const uint32_t* list,
                                         const uint2 (&rec)[kPerThread], int px0, int py0, uint32_t Fb, float* slice_out,
-                                        uint32_t rank0, uint32_t cnt_total) {
+                                        uint32_t rank0, uint32_t cnt_total, bool by_seg = false,
+                                        uint32_t key_of_slice = 0u) {
     uint32_t* s_cnt = L_.s_cnt;
     uint32_t* s_kmin = L_.s_kmin;
     uint32_t* s_kmax = L_.s_kmax;
@@ -1633,7 +1635,7 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
                 if (rank == 0) dbg.counts[q2] = cnt_total ? cnt_total : s_cnt[p];
                 if ((int)rank < dbg.stride) {
                     const size_t o = (size_t)q2 * dbg.stride + rank;
-                    dbg.keys[o] = rec.x;
+                    dbg.keys[o] = by_seg ? key_of_slice : rec.x;
                     dbg.segs[o] = gseg;
                     dbg.alpha[o] = al;
                     dbg.hoff[o] = hh;
@@ -1724,6 +1726,86 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
     PHASE_END(f.ctr, 4);
 }
 
+// Slice of a deep pixel's k records at src: among the records that val(r, v) admits, with
+// value v in [lo, end), the longest run of leading histogram bins holding at most kCap of them
+// (bins refined until one fits).  Returns 0 with [lo, *hi) and its record count *Fb, or 2 when
+// more than kCap admitted records share the single value lo.  Values are 32-bit, so lo < 2^32,
+// the bin width stays below 2^22 and bins are exact 32-bit quotients.  s_bk holds the
+// histogram (kCap bins); all threads call it; ends with a barrier.
+template <class Val>
+__device__ inline uint32_t refine_slice(uint32_t k, const uint2* __restrict__ src, unsigned long long lo,
+                                        unsigned long long end, Val&& val, uint32_t* s_bk, uint32_t* s_tmp,
+                                        unsigned long long* s_range, uint32_t& s_slot, uint32_t& s_flag,
+                                        unsigned long long& hi_out, uint32_t& Fb) {
+    constexpr uint32_t kBins = kCap;
+    const int t = threadIdx.x;
+    unsigned long long range_hi = end;
+    while (true) {
+        const unsigned long long width = (range_hi - lo + kBins - 1) / kBins;
+        const uint32_t lo32 = (uint32_t)lo, w32 = (uint32_t)width;
+        for (uint32_t i = t; i < kBins; i += kNT) s_bk[i] = 0;
+        __syncthreads();
+        // histogram of the admitted values in [lo, range_hi); each lane's loads issued together
+        for (uint32_t i0 = 0; i0 < k; i0 += kNT * kPerThread) {
+            uint2 rr[kPerThread];
+#pragma unroll
+            for (int qq = 0; qq < kPerThread; ++qq) {
+                const uint32_t i = i0 + t + qq * kNT;
+                rr[qq] = i < k ? src[i] : make_uint2(0u, 0u);
+            }
+#pragma unroll
+            for (int qq = 0; qq < kPerThread; ++qq) {
+                const uint32_t i = i0 + t + qq * kNT;
+                uint32_t v;
+                if (i < k && val(rr[qq], v) && v >= lo32 && (unsigned long long)v < range_hi)
+                    atomicAdd(&s_bk[(v - lo32) / w32], 1u);
+            }
+        }
+        __syncthreads();
+        // the longest run of leading bins holding at most kCap records, from a block scan of the
+        // bin counts (lane t owns bins t * kPerThread ...): the one lane that owns the run's last
+        // bin writes the slice; lane 0 flags a first bin that alone exceeds kCap
+        {
+            const uint32_t used = (uint32_t)((range_hi - lo + width - 1) / width);
+            uint32_t loc[kPerThread], sum = 0;
+#pragma unroll
+            for (int qq = 0; qq < kPerThread; ++qq) {
+                const uint32_t i = t * kPerThread + qq;
+                loc[qq] = i < used ? s_bk[i] : 0u;
+                sum += loc[qq];
+            }
+            uint32_t incl;
+            block_exscan_u32(sum, s_tmp, incl);
+#pragma unroll
+            for (int qq = 0; qq < kPerThread; ++qq) {
+                const uint32_t i = t * kPerThread + qq;
+                incl += loc[qq];
+                if (i < used && incl <= (uint32_t)kCap) {
+                    const uint32_t nxt = i + 1 >= used ? 0u : (qq + 1 < kPerThread ? loc[qq + 1] : s_bk[i + 1]);
+                    if (i + 1 >= used || incl + nxt > (uint32_t)kCap) {
+                        s_flag = 0;
+                        s_range[1] = min(range_hi, lo + (unsigned long long)(i + 1) * width);
+                        s_slot = incl;
+                    }
+                }
+            }
+            if (t == 0 && loc[0] > (uint32_t)kCap) {
+                s_flag = width == 1 ? 2u : 1u;     // 1: refine inside the first bin; 2: one value overflows
+                s_range[1] = lo + width;
+            }
+        }
+        __syncthreads();
+        const uint32_t flag = s_flag;
+        range_hi = s_range[1];
+        Fb = s_slot;
+        __syncthreads();
+        if (flag != 1) {
+            hi_out = range_hi;
+            return flag;
+        }
+    }
+}
+
 // One LDS batch of whole pixels: exact per-pixel order, shading, front-to-back blending.  A
 // pixel deeper than one batch (its own "oversized" batch) is processed in depth-key slices:
 // a histogram over the pixel's key range picks the longest run of bins that fits LDS, those
@@ -1781,7 +1863,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 &
         sort_shade_blend<KIND, MODEL, SHADOW>(f, a, rgba, dbg, has_dbg, L_, list, rec, px0, py0, Fb, nullptr, 0, 0);
         return;
     }
-    // ---- a pixel deeper than one batch: exact depth-key slices
+    // ---- a pixel deeper than one batch: exact slices in (key, segment id) order
     const int p = p0;
     const size_t qp = (size_t)tile * kTilePix + p;
     const uint32_t k = b.nfrag;
@@ -1789,78 +1871,12 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 &
     unsigned long long lo = f.pix_kmin[qp];
     float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;   // carried composite (thread 0)
     uint32_t done = 0;
-    constexpr uint32_t kBins = kCap;            // histogram in s_bk
     PHASE_ADD(f.ctr, 7, k);
     PHASE_END(f.ctr, 5);
-    while (lo < key_end) {
-        unsigned long long range_hi = key_end;
-        // refine until a run of whole bins starting at lo fits one batch.  Keys are 32-bit, so
-        // lo < 2^32, the bin width stays below 2^22 and bins are exact 32-bit quotients.
-        while (true) {
-            const unsigned long long width = (range_hi - lo + kBins - 1) / kBins;
-            const uint32_t lo32 = (uint32_t)lo, w32 = (uint32_t)width;
-            for (uint32_t i = t; i < kBins; i += kNT) L_.s_bk[i] = 0;
-            __syncthreads();
-            // histogram of the keys in [lo, range_hi); each lane's loads are issued together
-            for (uint32_t i0 = 0; i0 < k; i0 += kNT * kPerThread) {
-                uint32_t kk[kPerThread];
-#pragma unroll
-                for (int qq = 0; qq < kPerThread; ++qq) {
-                    const uint32_t i = i0 + t + qq * kNT;
-                    kk[qq] = i < k ? src[i].x : 0u;
-                }
-#pragma unroll
-                for (int qq = 0; qq < kPerThread; ++qq) {
-                    const uint32_t i = i0 + t + qq * kNT;
-                    if (i < k && kk[qq] >= lo32 && (unsigned long long)kk[qq] < range_hi)
-                        atomicAdd(&L_.s_bk[(kk[qq] - lo32) / w32], 1u);
-                }
-            }
-            __syncthreads();
-            // the longest run of leading bins holding at most kCap keys, from a block scan of
-            // the bin counts (lane t owns bins t * kPerThread ...): the one lane that owns the
-            // run's last bin writes the slice; lane 0 flags a first bin that alone exceeds kCap
-            {
-                const uint32_t used = (uint32_t)((range_hi - lo + width - 1) / width);
-                uint32_t loc[kPerThread], sum = 0;
-#pragma unroll
-                for (int qq = 0; qq < kPerThread; ++qq) {
-                    const uint32_t i = t * kPerThread + qq;
-                    loc[qq] = i < used ? L_.s_bk[i] : 0u;
-                    sum += loc[qq];
-                }
-                uint32_t incl;
-                block_exscan_u32(sum, s_tmp, incl);
-#pragma unroll
-                for (int qq = 0; qq < kPerThread; ++qq) {
-                    const uint32_t i = t * kPerThread + qq;
-                    incl += loc[qq];
-                    if (i < used && incl <= (uint32_t)kCap) {
-                        const uint32_t nxt = i + 1 >= used ? 0u : (qq + 1 < kPerThread ? loc[qq + 1] : L_.s_bk[i + 1]);
-                        if (i + 1 >= used || incl + nxt > (uint32_t)kCap) {
-                            s_flag = 0;
-                            s_range[1] = min(range_hi, lo + (unsigned long long)(i + 1) * width);
-                            s_slot = incl;
-                        }
-                    }
-                }
-                if (t == 0 && loc[0] > (uint32_t)kCap) {
-                    s_flag = width == 1 ? 2u : 1u;     // 1: refine inside the first bin; 2: equal keys overflow
-                    s_range[1] = lo + width;
-                }
-            }
-            __syncthreads();
-            const uint32_t flag = s_flag;
-            range_hi = s_range[1];
-            __syncthreads();
-            if (flag == 0) break;
-            if (flag == 2) {   // more than kCap fragments share one depth key: unsupported
-                if (t == 0) atomicAdd(&f.ctr->overflow_pixels, 1u);
-                return;
-            }
-        }
-        const uint32_t Fb = s_slot;
-        __syncthreads();
+    // one slice: the records whose value (their key, or inside one key their segment id) lies
+    // in [v_lo, v_hi), staged as (value, local index | pixel), ordered, shaded and blended
+    auto run_slice = [&](uint32_t Fb, unsigned long long v_lo, unsigned long long v_hi, auto&& val, bool by_seg,
+                         uint32_t key) {
         if (t == 0) s_slot = 0;
         __syncthreads();
         for (uint32_t i0 = 0; i0 < k; i0 += kNT * kPerThread) {
@@ -1873,16 +1889,17 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 &
 #pragma unroll
             for (int qq = 0; qq < kPerThread; ++qq) {
                 const uint32_t i = i0 + t + qq * kNT;
-                if (i < k && (unsigned long long)rr[qq].x >= lo && (unsigned long long)rr[qq].x < range_hi)
-                    L_.s_A[atomicAdd(&s_slot, 1u)] = rr[qq];
+                uint32_t v;
+                if (i < k && val(rr[qq], v) && (unsigned long long)v >= v_lo && (unsigned long long)v < v_hi)
+                    L_.s_A[atomicAdd(&s_slot, 1u)] = make_uint2(v, rr[qq].y);
             }
         }
         __syncthreads();
         for (uint32_t i = t; i < Fb; i += kNT) L_.s_bk[i] = 0;
         if (t == 0) {
             s_cnt[p] = Fb;
-            s_kmin[p] = (uint32_t)lo;
-            s_kmax[p] = (uint32_t)(range_hi - 1);
+            s_kmin[p] = (uint32_t)v_lo;
+            s_kmax[p] = (uint32_t)(v_hi - 1);
             s_off[p] = 0;
             s_off[p + 1] = Fb;
         }
@@ -1894,7 +1911,8 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 &
             const uint32_t i = t + qq * kNT;
             if (i < Fb) rec[qq] = L_.s_A[i];
         }
-        sort_shade_blend<KIND, MODEL, SHADOW>(f, a, rgba, dbg, has_dbg, L_, list, rec, px0, py0, Fb, s_slice, done, k);
+        sort_shade_blend<KIND, MODEL, SHADOW>(f, a, rgba, dbg, has_dbg, L_, list, rec, px0, py0, Fb, s_slice, done, k,
+                                              by_seg, key);
         PHASE_RESET();
         __syncthreads();
         if (t == 0) {
@@ -1904,8 +1922,39 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 &
             T *= s_slice[3];
         }
         done += Fb;
-        lo = range_hi;
         __syncthreads();
+    };
+    auto by_key = [&](const uint2& r, uint32_t& v) { v = r.x; return true; };
+    while (lo < key_end) {
+        unsigned long long hi;
+        uint32_t Fb;
+        const uint32_t flag = refine_slice(k, src, lo, key_end, by_key, L_.s_bk, s_tmp, s_range, s_slot, s_flag, hi, Fb);
+        if (flag == 0) {
+            // (a slice of leading empty bins holds no record and changes nothing)
+            if (Fb) run_slice(Fb, lo, hi, by_key, false, 0u);
+            lo = hi;
+            continue;
+        }
+        // more than one batch of fragments at one key K0: slices by segment id inside it (a
+        // segment meets a pixel once, so every id range refines down to a slice that fits)
+        const uint32_t K0 = (uint32_t)lo;
+        auto by_seg = [&](const uint2& r, uint32_t& v) {
+            if (r.x != K0) return false;
+            v = list[r.y & 0xFFFFFFu];
+            return true;
+        };
+        unsigned long long slo = 0;
+        const unsigned long long send = 1ull << 32;
+        while (slo < send) {
+            unsigned long long shi;
+            if (refine_slice(k, src, slo, send, by_seg, L_.s_bk, s_tmp, s_range, s_slot, s_flag, shi, Fb) != 0) {
+                if (t == 0) atomicAdd(&f.ctr->overflow_pixels, 1u);   // (not reachable: ids are unique)
+                return;
+            }
+            if (Fb) run_slice(Fb, slo, shi, by_seg, true, K0);
+            slo = shi;
+        }
+        lo = (unsigned long long)K0 + 1ull;
     }
     if (t == 0) {
         const int gx = px0 + (p % kTile), gy = py0 + (p / kTile);
@@ -1959,6 +2008,8 @@ __device__ inline void halfwidth_partials(const CamConst& c, const SegRec& s, co
     db = W > 0.0f ? k * b_len * cb * cb / W : 0.0f;
 }
 
+constexpr int kMaxBwdSlices = 64;    // slices of one pixel deeper than a batch (more: HAIR_ERANGE)
+
 template <int MODEL>
 __global__ __launch_bounds__(kNT) void k_batch_bwd(FrameBufs f, ShadeArgs a, GradOut g, int S, int K) {
     __shared__ uint32_t s_cnt[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix], s_off[kTilePix + 1];
@@ -1970,6 +2021,16 @@ __global__ __launch_bounds__(kNT) void k_batch_bwd(FrameBufs f, ShadeArgs a, Gra
     __shared__ float s_dpix[4 * kTilePix];               // output adjoint of the batch's pixels
     __shared__ float s_agg[kNT * 4];
     __shared__ uint32_t s_aggh[kNT];
+    // a pixel deeper than one batch: its slices (value range, by segment id inside key), their
+    // composites (C rgb, T) and the boundary values each slice's adjoints need
+    __shared__ unsigned long long s_range[2];
+    __shared__ uint32_t s_slot, s_flag;
+    __shared__ unsigned long long s_sl_lo[kMaxBwdSlices], s_sl_hi[kMaxBwdSlices];
+    __shared__ uint32_t s_sl_key[kMaxBwdSlices], s_sl_n[kMaxBwdSlices];
+    __shared__ float4 s_sl_agg[kMaxBwdSlices];
+    __shared__ float4 s_sl_after[kMaxBwdSlices];        // (C rgb, S) of the slices behind
+    __shared__ float s_sl_before[kMaxBwdSlices];         // T of the slices in front
+    __shared__ uint32_t s_nsl;
     uint2* s_A = reinterpret_cast<uint2*>(s_work);
     uint32_t* s_bk = reinterpret_cast<uint32_t*>(s_work) + 2 * kCap;
     float4* s_p4 = reinterpret_cast<float4*>(s_work);
@@ -1980,7 +2041,6 @@ __global__ __launch_bounds__(kNT) void k_batch_bwd(FrameBufs f, ShadeArgs a, Gra
     const BatchRec b = unpack_batch(br);
     const int tile = b.tile, p0 = b.p0, p1 = b.p1;
     const int t = threadIdx.x;
-    if (b.over) return;
     const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
     const int W = a.cam.W, H = a.cam.H;
     const uint32_t lstart = f.tile_start[tile];
@@ -2001,173 +2061,312 @@ __global__ __launch_bounds__(kNT) void k_batch_bwd(FrameBufs f, ShadeArgs a, Gra
     if (t == 0) s_off[p1] = b.nfrag;
     for (int i = t; i < 6 * kNAcc; i += kNT) s_acc[i] = 0.0f;
     __syncthreads();
-    const uint32_t Fb = b.nfrag;
     const uint2* src = f.frags + b.frag0;
-    for (uint32_t i = t; i < Fb; i += kNT) {
-        s_A[i] = src[i];
-        s_bk[i] = 0;
-    }
-    __syncthreads();
-    order_batch_insertion(Fb, s_cnt, s_kmin, s_kmax, s_off, s_tmp, s_A, s_B, s_bk, list);
-    // ---- 2. alpha and L per fragment (float)
-    for (uint32_t i = t; i < Fb; i += kNT) {
-        const uint2 rec = s_B[i];
-        const uint32_t p = rec.y >> 24;
-        const uint32_t gseg = list[rec.y & 0xFFFFFFu];
-        float al, hh, L[3];
-        shade_fragment<1, MODEL>(a, gseg, px0 + (int)(p % kTile), py0 + (int)(p / kTile), al, hh, L);
-        s_p4[i] = make_float4(al, L[0], L[1], L[2]);
-    }
-    __syncthreads();
-    // ---- 3a. forward: T before each fragment (segmented exclusive product over runs)
-    const uint32_t run = (Fb + kNT - 1) / kNT;
-    const uint32_t rb = min(Fb, t * run), re = min(Fb, rb + run);
-    {
-        float T = 1.f;
-        uint32_t head = 0;
-        for (uint32_t i = rb; i < re; ++i) {
-            const uint32_t p = s_B[i].y >> 24;
-            if (i == s_off[p]) { T = 1.f; head = 1; }
-            T *= 1.0f - s_p4[i].x;
-        }
-        s_agg[4 * t + 3] = T;
-        s_aggh[t] = head;
-        __syncthreads();
-        for (int off = 1; off < kNT; off <<= 1) {
-            float tt = 1;
-            uint32_t hh2 = 0;
-            const bool has = t >= off;
-            if (has) { tt = s_agg[4 * (t - off) + 3]; hh2 = s_aggh[t - off]; }
-            __syncthreads();
-            if (has && !s_aggh[t]) { s_agg[4 * t + 3] = tt * s_agg[4 * t + 3]; s_aggh[t] = hh2; }
-            __syncthreads();
-        }
-        T = t > 0 ? s_agg[4 * (t - 1) + 3] : 1.f;
-        for (uint32_t i = rb; i < re; ++i) {
-            const uint32_t p = s_B[i].y >> 24;
-            if (i == s_off[p]) T = 1.f;
-            s_T[i] = T;
-            T *= 1.0f - s_p4[i].x;
+
+    // Steps 2-4 on the Fb records ordered in s_B (whole pixels, or one slice of one pixel).  A
+    // slice's pixel starts with transmittance T_in (the slices in front) and ends over the
+    // composite (C_out rgb, S_out) of the slices behind it; whole pixels start at 1 and end over
+    // (0, 1).  grads = false: only the slice's own composite, into agg (C rgb, T).
+    auto slice_core = [&](uint32_t Fb, float T_in, float4 out_c, bool grads, float4* agg) __attribute__((always_inline)) {
+        // ---- 2. alpha and L per fragment (float)
+        for (uint32_t i = t; i < Fb; i += kNT) {
+            const uint2 rec = s_B[i];
+            const uint32_t p = rec.y >> 24;
+            const uint32_t gseg = list[rec.y & 0xFFFFFFu];
+            float al, hh, L[3];
+            shade_fragment<1, MODEL>(a, gseg, px0 + (int)(p % kTile), py0 + (int)(p / kTile), al, hh, L);
+            s_p4[i] = make_float4(al, L[0], L[1], L[2]);
         }
         __syncthreads();
-    }
-    // ---- 3b. backward: suffix composite (C+, S+) after each fragment, then the adjoints
-    {
-        // run aggregate from the run start through its first pixel end (or the whole run)
-        float C0 = 0.f, C1 = 0.f, C2 = 0.f, Sx = 1.f;
-        uint32_t tail = 0;
-        for (uint32_t i = re; i > rb; --i) {
-            const uint32_t k = i - 1;
-            const uint32_t p = s_B[k].y >> 24;
-            if (k + 1 == s_off[p] + s_cnt[p]) { C0 = C1 = C2 = 0.f; Sx = 1.f; tail = 1; }
-            const float4 v = s_p4[k];
-            C0 = v.x * v.y + (1.0f - v.x) * C0;
-            C1 = v.x * v.z + (1.0f - v.x) * C1;
-            C2 = v.x * v.w + (1.0f - v.x) * C2;
-            Sx = (1.0f - v.x) * Sx;
-        }
-        s_agg[4 * t + 0] = C0; s_agg[4 * t + 1] = C1; s_agg[4 * t + 2] = C2; s_agg[4 * t + 3] = Sx;
-        s_aggh[t] = tail;
-        __syncthreads();
-        // right-to-left inclusive scan: R_t = agg_t.tail ? agg_t : agg_t over R_{t+1}
-        for (int off = 1; off < kNT; off <<= 1) {
-            float c0 = 0, c1 = 0, c2 = 0, ss = 1;
-            const bool has = t + off < kNT;
-            if (has) {
-                c0 = s_agg[4 * (t + off) + 0]; c1 = s_agg[4 * (t + off) + 1];
-                c2 = s_agg[4 * (t + off) + 2]; ss = s_agg[4 * (t + off) + 3];
+        // ---- 3a. forward: T before each fragment (segmented exclusive product over runs)
+        const uint32_t run = (Fb + kNT - 1) / kNT;
+        const uint32_t rb = min(Fb, t * run), re = min(Fb, rb + run);
+        {
+            float T = 1.f;
+            uint32_t head = 0;
+            for (uint32_t i = rb; i < re; ++i) {
+                const uint32_t p = s_B[i].y >> 24;
+                if (i == s_off[p]) { T = 1.f; head = 1; }
+                T *= 1.0f - s_p4[i].x;
             }
-            const uint32_t my_tail = s_aggh[t];
-            const uint32_t r_tail = has ? s_aggh[t + off] : 0u;
+            s_agg[4 * t + 3] = T;
+            s_aggh[t] = head;
             __syncthreads();
-            if (has && !my_tail) {
-                const float mS = s_agg[4 * t + 3];
-                s_agg[4 * t + 0] = s_agg[4 * t + 0] + mS * c0;
-                s_agg[4 * t + 1] = s_agg[4 * t + 1] + mS * c1;
-                s_agg[4 * t + 2] = s_agg[4 * t + 2] + mS * c2;
-                s_agg[4 * t + 3] = mS * ss;
-                s_aggh[t] = r_tail;
+            for (int off = 1; off < kNT; off <<= 1) {
+                float tt = 1;
+                uint32_t hh2 = 0;
+                const bool has = t >= off;
+                if (has) { tt = s_agg[4 * (t - off) + 3]; hh2 = s_aggh[t - off]; }
+                __syncthreads();
+                if (has && !s_aggh[t]) { s_agg[4 * t + 3] = tt * s_agg[4 * t + 3]; s_aggh[t] = hh2; }
+                __syncthreads();
+            }
+            T = t > 0 ? s_agg[4 * (t - 1) + 3] : 1.f;
+            for (uint32_t i = rb; i < re; ++i) {
+                const uint32_t p = s_B[i].y >> 24;
+                if (i == s_off[p]) T = 1.f;
+                s_T[i] = T_in * T;
+                T *= 1.0f - s_p4[i].x;
             }
             __syncthreads();
         }
-        if (t + 1 < kNT) { C0 = s_agg[4 * (t + 1) + 0]; C1 = s_agg[4 * (t + 1) + 1]; C2 = s_agg[4 * (t + 1) + 2]; Sx = s_agg[4 * (t + 1) + 3]; }
-        else { C0 = C1 = C2 = 0.f; Sx = 1.f; }
+        if (!grads) {   // the slice's own composite: C = sum T_k alpha_k L_k, T = prod (1 - alpha_k)
+            float c0 = 0.f, c1 = 0.f, c2 = 0.f;
+            for (uint32_t i = t; i < Fb; i += kNT) {
+                const float4 v = s_p4[i];
+                const float w = s_T[i] * v.x;
+                c0 += w * v.y;
+                c1 += w * v.z;
+                c2 += w * v.w;
+            }
+            s_agg[4 * t + 0] = c0; s_agg[4 * t + 1] = c1; s_agg[4 * t + 2] = c2;
+            __syncthreads();
+            if (t == 0) {
+                float4 r = make_float4(0.f, 0.f, 0.f, 1.f);
+                for (int i = 0; i < kNT; ++i) { r.x += s_agg[4 * i]; r.y += s_agg[4 * i + 1]; r.z += s_agg[4 * i + 2]; }
+                if (Fb) r.w = s_T[Fb - 1] * (1.0f - s_p4[Fb - 1].x);
+                *agg = r;
+            }
+            __syncthreads();
+            return;
+        }
+        // ---- 3b. backward: suffix composite (C+, S+) after each fragment, then the adjoints
+        {
+            // run aggregate from the run start through its first pixel end (or the whole run)
+            float C0 = 0.f, C1 = 0.f, C2 = 0.f, Sx = 1.f;
+            uint32_t tail = 0;
+            for (uint32_t i = re; i > rb; --i) {
+                const uint32_t k = i - 1;
+                const uint32_t p = s_B[k].y >> 24;
+                if (k + 1 == s_off[p] + s_cnt[p]) { C0 = C1 = C2 = 0.f; Sx = 1.f; tail = 1; }
+                const float4 v = s_p4[k];
+                C0 = v.x * v.y + (1.0f - v.x) * C0;
+                C1 = v.x * v.z + (1.0f - v.x) * C1;
+                C2 = v.x * v.w + (1.0f - v.x) * C2;
+                Sx = (1.0f - v.x) * Sx;
+            }
+            s_agg[4 * t + 0] = C0; s_agg[4 * t + 1] = C1; s_agg[4 * t + 2] = C2; s_agg[4 * t + 3] = Sx;
+            s_aggh[t] = tail;
+            __syncthreads();
+            // right-to-left inclusive scan: R_t = agg_t.tail ? agg_t : agg_t over R_{t+1}
+            for (int off = 1; off < kNT; off <<= 1) {
+                float c0 = 0, c1 = 0, c2 = 0, ss = 1;
+                const bool has = t + off < kNT;
+                if (has) {
+                    c0 = s_agg[4 * (t + off) + 0]; c1 = s_agg[4 * (t + off) + 1];
+                    c2 = s_agg[4 * (t + off) + 2]; ss = s_agg[4 * (t + off) + 3];
+                }
+                const uint32_t my_tail = s_aggh[t];
+                const uint32_t r_tail = has ? s_aggh[t + off] : 0u;
+                __syncthreads();
+                if (has && !my_tail) {
+                    const float mS = s_agg[4 * t + 3];
+                    s_agg[4 * t + 0] = s_agg[4 * t + 0] + mS * c0;
+                    s_agg[4 * t + 1] = s_agg[4 * t + 1] + mS * c1;
+                    s_agg[4 * t + 2] = s_agg[4 * t + 2] + mS * c2;
+                    s_agg[4 * t + 3] = mS * ss;
+                    s_aggh[t] = r_tail;
+                }
+                __syncthreads();
+            }
+            if (t + 1 < kNT) { C0 = s_agg[4 * (t + 1) + 0]; C1 = s_agg[4 * (t + 1) + 1]; C2 = s_agg[4 * (t + 1) + 2]; Sx = s_agg[4 * (t + 1) + 3]; }
+            else { C0 = C1 = C2 = 0.f; Sx = 1.f; }
+            __syncthreads();
+            for (uint32_t i = re; i > rb; --i) {
+                const uint32_t k = i - 1;
+                const uint32_t p = s_B[k].y >> 24;
+                if (k + 1 == s_off[p] + s_cnt[p]) { C0 = C1 = C2 = 0.f; Sx = 1.f; }
+                const float4 v = s_p4[k];
+                const float Tk = s_T[k];
+                const float dR = s_dpix[4 * p + 0], dG = s_dpix[4 * p + 1], dB = s_dpix[4 * p + 2], dA = s_dpix[4 * p + 3];
+                // behind fragment k: the rest of its pixel's records here, then what lies behind
+                const float Ca0 = C0 + Sx * out_c.x, Ca1 = C1 + Sx * out_c.y, Ca2 = C2 + Sx * out_c.z;
+                const float Sa = Sx * out_c.w;
+                const float g_alpha = Tk * (dR * (v.y - Ca0) + dG * (v.z - Ca1) + dB * (v.w - Ca2) + dA * Sa);
+                const float ta = Tk * v.x;
+                C0 = v.x * v.y + (1.0f - v.x) * C0;
+                C1 = v.x * v.z + (1.0f - v.x) * C1;
+                C2 = v.x * v.w + (1.0f - v.x) * C2;
+                Sx = (1.0f - v.x) * Sx;
+                s_p4[k] = make_float4(g_alpha, dR * ta, dG * ta, dB * ta);
+            }
+        }
         __syncthreads();
-        for (uint32_t i = re; i > rb; --i) {
-            const uint32_t k = i - 1;
-            const uint32_t p = s_B[k].y >> 24;
-            if (k + 1 == s_off[p] + s_cnt[p]) { C0 = C1 = C2 = 0.f; Sx = 1.f; }
-            const float4 v = s_p4[k];
-            const float Tk = s_T[k];
-            const float dR = s_dpix[4 * p + 0], dG = s_dpix[4 * p + 1], dB = s_dpix[4 * p + 2], dA = s_dpix[4 * p + 3];
-            const float g_alpha = Tk * (dR * (v.y - C0) + dG * (v.z - C1) + dB * (v.w - C2) + dA * Sx);
-            const float ta = Tk * v.x;
-            C0 = v.x * v.y + (1.0f - v.x) * C0;
-            C1 = v.x * v.z + (1.0f - v.x) * C1;
-            C2 = v.x * v.w + (1.0f - v.x) * C2;
-            Sx = (1.0f - v.x) * Sx;
-            s_p4[k] = make_float4(g_alpha, dR * ta, dG * ta, dB * ta);
+        // ---- 4. partials: alpha and L as Dual6, contracted with the adjoints.  A fragment whose
+        // four adjoints are all zero (behind an opaque fragment of its pixel, T_k = 0, or in a
+        // pixel without output adjoint) contributes exactly nothing; the others are listed first
+        // (in s_T, free after step 3) so that every lane's Dual6 work is a fragment that counts.
+        uint32_t* s_idx = reinterpret_cast<uint32_t*>(s_T);
+        uint32_t n_live;
+        {
+            uint32_t mine = 0;
+            for (uint32_t i = t; i < Fb; i += kNT) {
+                const float4 v = s_p4[i];
+                mine += (v.x != 0.0f || v.y != 0.0f || v.z != 0.0f || v.w != 0.0f) ? 1u : 0u;
+            }
+            uint32_t pos;
+            n_live = block_exscan_u32(mine, s_tmp, pos);
+            for (uint32_t i = t; i < Fb; i += kNT) {
+                const float4 v = s_p4[i];
+                if (v.x != 0.0f || v.y != 0.0f || v.z != 0.0f || v.w != 0.0f) s_idx[pos++] = i;
+            }
+            __syncthreads();
         }
-    }
-    __syncthreads();
-    // ---- 4. partials: alpha and L as Dual6, contracted with the adjoints.  A fragment whose
-    // four adjoints are all zero (behind an opaque fragment of its pixel, T_k = 0, or in a
-    // pixel without output adjoint) contributes exactly nothing; the others are listed first
-    // (in s_T, free after step 3) so that every lane's Dual6 work is a fragment that counts.
-    uint32_t* s_idx = reinterpret_cast<uint32_t*>(s_T);
-    uint32_t n_live;
-    {
-        uint32_t mine = 0;
-        for (uint32_t i = t; i < Fb; i += kNT) {
-            const float4 v = s_p4[i];
-            mine += (v.x != 0.0f || v.y != 0.0f || v.z != 0.0f || v.w != 0.0f) ? 1u : 0u;
-        }
-        uint32_t pos;
-        n_live = block_exscan_u32(mine, s_tmp, pos);
-        for (uint32_t i = t; i < Fb; i += kNT) {
-            const float4 v = s_p4[i];
-            if (v.x != 0.0f || v.y != 0.0f || v.z != 0.0f || v.w != 0.0f) s_idx[pos++] = i;
+        for (uint32_t kk = t; kk < n_live; kk += kNT) {
+            const uint32_t i = s_idx[kk];
+            const uint2 rec = s_B[i];
+            const uint32_t p = rec.y >> 24;
+            const uint32_t j = rec.y & 0xFFFFFFu;
+            const uint32_t gseg = list[j];
+            const float4 adj = s_p4[i];
+            const SegRec s = a.seg[gseg];
+            const ShadeRec& srec = a.shade[gseg];
+            const float4 q0 = srec.q0, q1 = srec.q1, q2 = srec.q2, q3 = srec.q3;
+            float dha, dhb;
+            halfwidth_partials(a.cam, s, q0, q1, q2, q3.x, q3.y, dha, dhb);
+            Dual6 hw(s.hw);
+            hw.d[0] = dha;
+            hw.d[1] = dhb;
+            const Dual6 al = Dual6::seed(q3.x, 0), bl = Dual6::seed(q3.y, 1), rr = Dual6::seed(q3.w, 2);
+            const Dual6 sig[3] = {Dual6::seed(q0.w, 3), Dual6::seed(q1.w, 4), Dual6::seed(q2.w, 5)};
+            Dual6 alpha, hoff, L[3];
+            shade_core<1, MODEL, Dual6>(a, s, q0, q1, q2, q3.z, px0 + (int)(p % kTile), py0 + (int)(p / kTile), hw, al,
+                                        bl, rr, sig, alpha, hoff, L);
+            float gp[6];
+#pragma unroll
+            for (int m = 0; m < 6; ++m)
+                gp[m] = adj.x * alpha.d[m] + adj.y * L[0].d[m] + adj.z * L[1].d[m] + adj.w * L[2].d[m];
+            if (j < (uint32_t)kNAcc) {
+#pragma unroll
+                for (int m = 0; m < 6; ++m) atomicAdd(&s_acc[m * kNAcc + j], gp[m]);
+            } else {
+                const int owner = (int)gseg / S;
+                atomicAdd(&g.d_axes[2 * gseg], gp[0]);
+                atomicAdd(&g.d_axes[2 * gseg + 1], gp[1]);
+                atomicAdd(&g.d_r[owner], gp[2]);
+                atomicAdd(&g.d_sig[owner], gp[3]);
+                atomicAdd(&g.d_sig[K + owner], gp[4]);
+                atomicAdd(&g.d_sig[2 * K + owner], gp[5]);
+            }
         }
         __syncthreads();
-    }
-    for (uint32_t k = t; k < n_live; k += kNT) {
-        const uint32_t i = s_idx[k];
-        const uint2 rec = s_B[i];
-        const uint32_t p = rec.y >> 24;
-        const uint32_t j = rec.y & 0xFFFFFFu;
-        const uint32_t gseg = list[j];
-        const float4 adj = s_p4[i];
-        const SegRec s = a.seg[gseg];
-        const ShadeRec& srec = a.shade[gseg];
-        const float4 q0 = srec.q0, q1 = srec.q1, q2 = srec.q2, q3 = srec.q3;
-        float dha, dhb;
-        halfwidth_partials(a.cam, s, q0, q1, q2, q3.x, q3.y, dha, dhb);
-        Dual6 hw(s.hw);
-        hw.d[0] = dha;
-        hw.d[1] = dhb;
-        const Dual6 al = Dual6::seed(q3.x, 0), bl = Dual6::seed(q3.y, 1), rr = Dual6::seed(q3.w, 2);
-        const Dual6 sig[3] = {Dual6::seed(q0.w, 3), Dual6::seed(q1.w, 4), Dual6::seed(q2.w, 5)};
-        Dual6 alpha, hoff, L[3];
-        shade_core<1, MODEL, Dual6>(a, s, q0, q1, q2, q3.z, px0 + (int)(p % kTile), py0 + (int)(p / kTile), hw, al, bl,
-                                    rr, sig, alpha, hoff, L);
-        float gp[6];
-#pragma unroll
-        for (int m = 0; m < 6; ++m)
-            gp[m] = adj.x * alpha.d[m] + adj.y * L[0].d[m] + adj.z * L[1].d[m] + adj.w * L[2].d[m];
-        if (j < (uint32_t)kNAcc) {
-#pragma unroll
-            for (int m = 0; m < 6; ++m) atomicAdd(&s_acc[m * kNAcc + j], gp[m]);
-        } else {
-            const int owner = (int)gseg / S;
-            atomicAdd(&g.d_axes[2 * gseg], gp[0]);
-            atomicAdd(&g.d_axes[2 * gseg + 1], gp[1]);
-            atomicAdd(&g.d_r[owner], gp[2]);
-            atomicAdd(&g.d_sig[owner], gp[3]);
-            atomicAdd(&g.d_sig[K + owner], gp[4]);
-            atomicAdd(&g.d_sig[2 * K + owner], gp[5]);
+    };
+
+    if (!b.over) {
+        const uint32_t Fb = b.nfrag;
+        for (uint32_t i = t; i < Fb; i += kNT) {
+            s_A[i] = src[i];
+            s_bk[i] = 0;
+        }
+        __syncthreads();
+        order_batch_insertion(Fb, s_cnt, s_kmin, s_kmax, s_off, s_tmp, s_A, s_B, s_bk, list);
+        slice_core(Fb, 1.0f, make_float4(0.f, 0.f, 0.f, 1.f), true, nullptr);
+    } else {
+        // ---- a pixel deeper than one batch: the forward's slices in (key, segment id) order,
+        // each differentiated with the transmittance of the slices in front of it and the
+        // composite of the slices behind it (two sweeps: composites, then adjoints)
+        const int p = p0;
+        const uint32_t k = b.nfrag;
+        const unsigned long long key_end = (unsigned long long)s_kmax[p] + 1ull;
+        auto by_key = [&](const uint2& r, uint32_t& v) { v = r.x; return true; };
+        // stage the records of slice [v_lo, v_hi) (by key, or inside key K0 by segment id) in
+        // s_B, ordered, as a one-pixel batch
+        auto stage = [&](uint32_t Fb, unsigned long long v_lo, unsigned long long v_hi, bool by_seg, uint32_t K0)
+            __attribute__((always_inline)) {
+            if (t == 0) s_slot = 0;
+            __syncthreads();
+            for (uint32_t i = t; i < k; i += kNT) {
+                const uint2 r = src[i];
+                uint32_t v = r.x;
+                bool in = true;
+                if (by_seg) {
+                    in = r.x == K0;
+                    if (in) v = list[r.y & 0xFFFFFFu];
+                }
+                if (in && (unsigned long long)v >= v_lo && (unsigned long long)v < v_hi)
+                    s_A[atomicAdd(&s_slot, 1u)] = make_uint2(v, r.y);
+            }
+            __syncthreads();
+            for (uint32_t i = t; i < Fb; i += kNT) s_bk[i] = 0;
+            if (t == 0) {
+                s_cnt[p] = Fb;
+                s_kmin[p] = (uint32_t)v_lo;
+                s_kmax[p] = (uint32_t)(v_hi - 1);
+                s_off[p] = 0;
+                s_off[p + 1] = Fb;
+            }
+            __syncthreads();
+            order_batch_insertion(Fb, s_cnt, s_kmin, s_kmax, s_off, s_tmp, s_A, s_B, s_bk, list);
+        };
+        uint32_t nsl = 0;
+        bool ok = true;
+        auto add_slice = [&](uint32_t Fb, unsigned long long v_lo, unsigned long long v_hi, bool by_seg, uint32_t K0)
+            __attribute__((always_inline)) {
+            if (nsl >= (uint32_t)kMaxBwdSlices) { ok = false; return; }
+            stage(Fb, v_lo, v_hi, by_seg, K0);
+            slice_core(Fb, 1.0f, make_float4(0.f, 0.f, 0.f, 1.f), false, &s_sl_agg[nsl]);
+            if (t == 0) {
+                s_sl_lo[nsl] = v_lo;
+                s_sl_hi[nsl] = v_hi;
+                s_sl_key[nsl] = by_seg ? K0 : 0xFFFFFFFFu;
+                s_sl_n[nsl] = Fb | (by_seg ? 0x80000000u : 0u);
+            }
+            ++nsl;
+        };
+        unsigned long long lo = s_kmin[p];
+        while (ok && lo < key_end) {
+            unsigned long long hi;
+            uint32_t Fb;
+            const uint32_t flag = refine_slice(k, src, lo, key_end, by_key, s_bk, s_tmp, s_range, s_slot, s_flag, hi, Fb);
+            if (flag == 0) {
+                if (Fb) add_slice(Fb, lo, hi, false, 0u);
+                lo = hi;
+                continue;
+            }
+            const uint32_t K0 = (uint32_t)lo;
+            auto by_seg = [&](const uint2& r, uint32_t& v) {
+                if (r.x != K0) return false;
+                v = list[r.y & 0xFFFFFFu];
+                return true;
+            };
+            unsigned long long slo = 0;
+            const unsigned long long send = 1ull << 32;
+            while (ok && slo < send) {
+                unsigned long long shi;
+                if (refine_slice(k, src, slo, send, by_seg, s_bk, s_tmp, s_range, s_slot, s_flag, shi, Fb) != 0) {
+                    ok = false;
+                    break;
+                }
+                if (Fb) add_slice(Fb, slo, shi, true, K0);
+                slo = shi;
+            }
+            lo = (unsigned long long)K0 + 1ull;
+        }
+        if (!ok) {   // more slices than the kernel keeps: reported, not differentiated
+            if (t == 0) atomicAdd(&f.ctr->overflow_pixels, 1u);
+            return;
+        }
+        if (t == 0) {   // transmittance in front of each slice and the composite behind it
+            float T = 1.f;
+            for (uint32_t i = 0; i < nsl; ++i) {
+                s_sl_before[i] = T;
+                T *= s_sl_agg[i].w;
+            }
+            float4 behind = make_float4(0.f, 0.f, 0.f, 1.f);
+            for (uint32_t i = nsl; i > 0; --i) {
+                s_sl_after[i - 1] = behind;
+                const float4 c = s_sl_agg[i - 1];
+                behind = make_float4(c.x + c.w * behind.x, c.y + c.w * behind.y, c.z + c.w * behind.z, c.w * behind.w);
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = 0; i < nsl; ++i) {
+            const uint32_t Fb = s_sl_n[i] & 0x7FFFFFFFu;
+            const bool by_seg = (s_sl_n[i] >> 31) != 0;
+            stage(Fb, s_sl_lo[i], s_sl_hi[i], by_seg, s_sl_key[i]);
+            slice_core(Fb, s_sl_before[i], s_sl_after[i], true, nullptr);
         }
     }
-    __syncthreads();
     const uint32_t nacc = min(n, (uint32_t)kNAcc);
     for (uint32_t j = t; j < nacc; j += kNT) {
         float v[6];

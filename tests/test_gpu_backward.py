@@ -102,6 +102,65 @@ def test_backward_long_tile_lists_matches_oracle_gradient(hip, ctx):
     ctx.release(aid)
 
 
+def _stacked_thick_hairs(depths, W=24, H=40):
+    """One horizontal one-segment thick hair per depth, all on pixel row 20 of a W x H camera
+    at the origin looking down -z (fy = 74.6): every covered pixel holds one fragment per hair.
+    Semi-axes 1e-5 m (alpha ~ 1e-3 per fragment, so light still reaches the back of a deep
+    pixel), six hairs of radius 4 um per cluster."""
+    fy = float(np.float32(74.6))
+    d = np.asarray(depths, dtype=np.float64)
+    K = len(d)
+    y = -0.5 * d / fy
+    xyz = np.empty((3, 2 * K), dtype=np.float32)
+    xyz[0, 0::2], xyz[0, 1::2] = -0.1 * d, 0.1 * d
+    xyz[1, 0::2] = xyz[1, 1::2] = y
+    xyz[2, 0::2] = xyz[2, 1::2] = -d
+    rng = np.random.default_rng(5)
+    sig = (np.array([0.3, 0.6, 1.2])[:, None] * np.exp(0.2 * rng.normal(size=(1, K)))).astype(np.float32)
+    asset = hs.Asset(K, 1, xyz, np.full(K, 8e-6, dtype=np.float32), np.ascontiguousarray(sig))
+    lod = {"centers": xyz.T.reshape(K, 2, 3).copy(),
+           "ahat": np.tile(np.array([0.0, 1.0, 0.0], np.float32), (K, 1, 1)),
+           "axes": np.stack([np.full((K, 1), 1.2e-5), np.full((K, 1), 0.8e-5)], -1).astype(np.float32),
+           "n_total": np.full(K, 6, np.int32), "sigma_a": sig.copy(), "r": np.full(K, 4e-6, np.float32)}
+    cam = hs.Camera(np.zeros(3, np.float32), np.eye(3, dtype=np.float32), fy, fy, W / 2.0, H / 2.0, W, H, 0.01)
+    return asset, lod, cam
+
+
+def test_backward_pixels_deeper_than_a_batch_match_oracle_gradient(hip, ctx):
+    """Pixels of ~4,900 thick-hair fragments: more than a batch of them at one depth key (sliced
+    by segment id) in front of a range of distinct keys (sliced by key).  The backward
+    differentiates each slice with the transmittance of the slices in front and the composite
+    of the slices behind; forward radiance and every gradient entry against the oracle."""
+    print("case: backward through pixels deeper than one batch", flush=True)
+    cap = hip.HAIR_PIXEL_CAPACITY
+    depths = np.concatenate([np.full(cap + 250, 1.0), np.linspace(1.2, 3.0, 2 * cap)])
+    asset, lod, cam = _stacked_thick_hairs(depths)
+    lights = hs.default_lights(asset, with_point=True)
+    K, S = len(depths), 1
+    aid = ctx.upload_asset(asset)
+    ctx.set_lod(aid, 1, lod)
+    ws = ctx.workspace()
+    img, st, rc = ctx.render(aid, 1, cam, lights, ws=ws)
+    torch.cuda.synchronize()
+    mat = tuple(float(v) for v in asset.material.as_array())
+    geom = R.cluster_level(lod)
+    ras = R.rasterize(geom, cam)
+    depth = np.bincount(ras.pix)
+    assert depth.max() > 3 * cap and st["deep_pixels"] == int((depth > cap).sum()) > 5
+    rng = np.random.default_rng(19)
+    d_rgba = rng.normal(size=(cam.height, cam.width, 4))
+    g_axes, g_r, g_sig, ref = OG.cluster_vjp(geom, cam, lights, mat, d_rgba, K, S, ras=ras)
+    got = img.cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref) - (1e-4 * np.abs(ref) + 1e-7)
+    assert int((err > 0).sum()) == 0
+    da, dr, ds = _gpu_vjp(ctx, aid, cam, lights, d_rgba, K, S)
+    _close(da, g_axes, "d_axes (deep pixels)", rel=1e-3, floor=1e-5)
+    _close(dr, g_r, "d_r (deep pixels)", rel=1e-3, floor=1e-5)
+    _close(ds, g_sig, "d_sigma_a (deep pixels)", rel=1e-3, floor=1e-5)
+    ws.close()
+    ctx.release(aid)
+
+
 def test_backward_matches_gpu_central_differences(hip, ctx):
     """20 parameters, central differences of the GPU forward at h = 1e-3 in log space (one
     Richardson step); parameters whose perturbation changes a coverage radius are skipped

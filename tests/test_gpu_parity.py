@@ -449,13 +449,15 @@ def test_deep_pixels_with_clustered_keys(hip, ctx):
     ws.close()
 
 
-def test_pixels_with_one_key_beyond_a_batch_are_flagged(hip, ctx):
-    """More fragments than one batch at a single depth key cannot be ordered in LDS: such
-    pixels are counted in overflow_pixels and left 0; every other pixel matches the oracle."""
-    print("case: equal-key overflow", flush=True)
+def test_pixels_with_one_key_beyond_a_batch(hip, ctx):
+    """More fragments than one LDS batch at a single depth key (two such runs in a pixel, one
+    of more than two batches): the pixel is sliced by segment id inside the key, so its order
+    is the exact (key, segment id) order; the frame reports no overflow, every pixel matches
+    the oracle and a deep pixel's whole fragment list equals the oracle's."""
+    print("case: equal keys beyond a batch", flush=True)
     cap = hip.HAIR_PIXEL_CAPACITY
-    asset, cam = _layered_asset(np.concatenate([np.full(cap + 64, 1.0), np.linspace(2.0, 3.0, 5)]),
-                                half_extent=0.1)
+    depths = np.concatenate([np.full(2 * cap + 100, 1.0), np.full(cap + 10, 1.5), np.linspace(2.0, 3.0, 5)])
+    asset, cam = _layered_asset(depths, half_extent=0.1)
     # a second layer of strands on another row that stays within one batch
     extra, _ = _layered_asset(np.linspace(1.5, 2.5, 300), half_extent=0.2)
     extra.xyz[1] += (6.0 * np.linspace(1.5, 2.5, 300) / 74.6).repeat(2).astype(np.float32)
@@ -466,15 +468,20 @@ def test_pixels_with_one_key_beyond_a_batch_are_flagged(hip, ctx):
     ref, ras = R.render(R.strand_level(asset), cam, lights, mat_of(asset))
     depth, same = _key_runs(ras, cam.width * cam.height)
     over = same > cap
-    assert over.sum() >= 10 and ((depth > 0) & ~over).sum() >= 10
+    assert over.sum() >= 10 and ((depth > 0) & ~over).sum() >= 10 and same.max() > 2 * cap
     aid = ctx.upload_asset(asset)
     ws = ctx.workspace()
     out, stats, rc = ctx.render(aid, 0, cam, lights, ws=ws, raise_on_error=False)
     torch.cuda.synchronize()
-    assert rc == hip.HAIR_ERANGE, rc                  # the frame is complete but reports them
+    assert rc == hip.HAIR_OK, (rc, hip.last_error())
     assert stats["fragments"] == len(ras.seg)
-    assert stats["overflow_pixels"] == int(over.sum())
-    flat = out.cpu().numpy().reshape(-1, 4)
-    assert np.all(flat[over] == 0.0)
-    assert_radiance(flat[~over], ref.reshape(-1, 4)[~over], what="beside overflow pixels")
+    assert stats["overflow_pixels"] == 0 and stats["deep_pixels"] == int((depth > cap).sum())
+    assert_radiance(out.cpu().numpy(), ref, what="equal keys beyond a batch")
+    # the whole order of one such pixel
+    p = int(np.nonzero(over)[0][len(np.nonzero(over)[0]) // 2])
+    x, y = p % cam.width, p // cam.width
+    cnt, keys, segs, alpha, hoff = ctx.debug_fragments(aid, 0, cam, lights, x, y, 1, 1, int(depth[p]) + 16, ws=ws)
+    sel = ras.pix == p
+    assert int(cnt[0, 0]) == int(depth[p])
+    assert np.array_equal(keys, ras.key[sel]) and np.array_equal(segs, ras.seg[sel].astype(np.uint32))
     ws.close()
