@@ -265,13 +265,23 @@ int hair_render_async(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, 
 int hair_ws_finish(hair_ws* ws, hair_stats* stats);
 
 /* hair_render with deep opacity map shadows (see hair_shadow) at a strand or thick-hair level
- * (mixed frames are not shadowed).  One shadow pass per directional light runs on `stream`
+ * (mixed frames: hair_render_mixed_shadowed).  One shadow pass per directional light runs on `stream`
  * before the frame (sized like a frame, see hair_render); stats describe the
  * camera frame, with ms_total including the shadow passes.  The workspace keeps the maps
  * until its next shadowed render. */
 int hair_render_shadowed(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,
                          const hair_light* lights, int32_t n_lights, const hair_shadow* shadow, float* rgba_out,
                          void* stream, hair_stats* stats);
+
+/* hair_render_mixed with deep opacity map shadows (see hair_shadow): the shadow pass of every
+ * directional light rasterises the frame's own rows (each (g, k) at its level: strands with
+ * their radius, thick hairs with their cross-section and hair count), and each strand or
+ * thick-hair fragment adds the hairs in front of it to its forward count as in
+ * hair_render_shadowed.  Same levels, deferred update, output and errors as hair_render_mixed;
+ * stats->ms_total includes the shadow passes. */
+int hair_render_mixed_shadowed(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_camera* cam,
+                               const hair_light* lights, int32_t n_lights, int32_t* levels, float eps_w_px,
+                               const hair_shadow* shadow, float* rgba_out, void* stream, hair_stats* stats);
 
 /* hair_render at a thick-hair level (level >= 1) with curved centre lines (Sec. 5.2: the
  * tessellation stage subdivides each thick hair by its distance to the camera; Sec. 6: spline

@@ -30,6 +30,7 @@ EXPORTS = [
     "hair_debug_fragments", "hair_lod_groups", "hair_lod_init", "hair_render_mixed", "hair_render_shadowed",
     "hair_debug_dom", "hair_render_curved", "hair_render_async", "hair_ws_finish", "hair_render_noalloc",
     "hair_noalloc_scratch_bytes", "hair_debug_issue_rate",
+    "hair_render_mixed_shadowed",
 ]
 
 
@@ -133,6 +134,8 @@ def _load():
         "hair_lod_init": ([P, P, I32, C.POINTER(hair_camera), F, P, P], C.c_int),
         "hair_render_mixed": ([P, P, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32, P, F, P, P,
                                C.POINTER(hair_stats)], C.c_int),
+        "hair_render_mixed_shadowed": ([P, P, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32, P, F,
+                                        C.POINTER(hair_shadow), P, P, C.POINTER(hair_stats)], C.c_int),
         "hair_render_shadowed": ([P, P, I32, I32, C.POINTER(hair_camera), C.POINTER(hair_light), I32,
                                   C.POINTER(hair_shadow), P, P, C.POINTER(hair_stats)], C.c_int),
         "hair_debug_dom": ([P, I32, fp, fp], C.c_int),
@@ -461,6 +464,27 @@ class Context:
         rc = lib.hair_render_mixed(self.handle, ws.handle if ws else None, asset, C.byref(c), la, nl,
                                    C.c_void_p(levels.data_ptr()), float(eps_w), C.c_void_p(out.data_ptr()),
                                    _stream_ptr(stream), C.byref(st))
+        if raise_on_error:
+            check(rc)
+        return out, st.as_dict(), rc
+
+    def render_mixed_shadowed(self, asset: int, cam, lights, levels, shadow=(512, 4, 0.02), eps_w: float = 0.0,
+                              out=None, ws: Workspace | None = None, stream=None, raise_on_error: bool = True):
+        """Mixed-level frame with deep opacity map shadows; shadow = (resolution, layers,
+        layer_depth).  Returns (out, stats dict, status code)."""
+        import torch
+        assert levels.is_cuda and levels.dtype == torch.int32 and levels.is_contiguous()
+        c = make_camera(cam)
+        la, nl = make_lights(lights)
+        sh = hair_shadow(int(shadow[0]), int(shadow[1]), float(shadow[2]))
+        if out is None:
+            out = torch.empty((c.height, c.width, 4), dtype=torch.float32, device=f"cuda:{self.device}")
+        assert out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+        assert tuple(out.shape) == (c.height, c.width, 4)
+        st = hair_stats()
+        rc = lib.hair_render_mixed_shadowed(self.handle, ws.handle if ws else None, asset, C.byref(c), la, nl,
+                                            C.c_void_p(levels.data_ptr()), float(eps_w), C.byref(sh),
+                                            C.c_void_p(out.data_ptr()), _stream_ptr(stream), C.byref(st))
         if raise_on_error:
             check(rc)
         return out, st.as_dict(), rc

@@ -476,6 +476,7 @@ struct DomPass {
     int32_t K;
     float delta;
     float4* tex;
+    const ShadeRec* rows;   // a mixed frame's rows (their camera shading records), or nullptr
 };
 
 // Project + bin + tile for one level; the caller holds ws->mu.
@@ -534,7 +535,7 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
         HIP_TRY(ctx, launch_project_mixed(*hier, sel, lv.nseg, cc, ws->seg.as<SegRec>(), ws->shade.as<ShadeRec>(), st),
                 "k_project_mixed");
     else if (dom)
-        HIP_TRY(ctx, launch_project_light(lv, dom->grid, ws->seg.as<SegRec>(), st), "k_project_light");
+        HIP_TRY(ctx, launch_project_light(lv, dom->rows, dom->grid, ws->seg.as<SegRec>(), st), "k_project_light");
     else if (tess)
         HIP_TRY(ctx, launch_project_tess(tess->base, tess->rows, lv.nseg, tess->cnt, cc, ws->seg.as<SegRec>(),
                                          ws->shade.as<ShadeRec>(), st),
@@ -653,7 +654,7 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     if (views)
         for (int i = 0; i < n_lights; ++i) lc.dom[i] = views[i];
     if (dom) {
-        HIP_TRY(ctx, launch_dom_resolve(f, lv, dom->grid, dom->K, dom->delta, cam->width, batch_grid, dom->tex, st),
+        HIP_TRY(ctx, launch_dom_resolve(f, lv, dom->rows, dom->grid, dom->K, dom->delta, cam->width, batch_grid, dom->tex, st),
                 "k_dom_resolve");
     } else if (grad) {
         HIP_TRY(ctx, launch_fill_f32(grad->d_axes, 0.0f, 2ull * lv.nseg, st), "fill");
@@ -1376,6 +1377,59 @@ static DomBasis dom_basis(const float* vec) {
     return b;
 }
 
+static int validate_shadow(const hair_shadow* shadow) {
+    if (!shadow) return fail(HAIR_EINVAL, "null shadow descriptor");
+    if (shadow->resolution < 16 || shadow->resolution > 4096)
+        return fail(HAIR_EINVAL, "shadow resolution %d outside [16, 4096]", shadow->resolution);
+    if (shadow->layers < 1 || shadow->layers > kDomMaxLayers)
+        return fail(HAIR_EINVAL, "shadow layers %d outside [1, %d]", shadow->layers, kDomMaxLayers);
+    if (!(std::isfinite(shadow->layer_depth) && shadow->layer_depth > 0.0f))
+        return fail(HAIR_EINVAL, "shadow layer_depth must be finite and > 0");
+    return HAIR_OK;
+}
+
+// One shadow pass per directional light over the level lv (or, with rows, over a mixed
+// frame's rows): grid, light-view raster, per-texel resolve; fills views[] for the camera
+// pass and adds the passes' GPU time to *ms.  The caller holds ws->mu.
+static int shadow_passes(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, const ShadeRec* rows,
+                         const hair_camera* cam, const hair_light* lights, int n_lights, const hair_shadow* shadow,
+                         hipStream_t st, DomView* views, float* ms) {
+    int rc;
+    const int R = shadow->resolution, K = shadow->layers;
+    int n_dom = 0;
+    for (int i = 0; i < n_lights; ++i) n_dom += lights[i].kind == 0;
+    const size_t texels = (size_t)R * R;
+    if ((rc = ws_need(ws, ws->dom_tex, 32 * texels * std::max(n_dom, 1)))) return rc;
+    if ((rc = ws_need(ws, ws->dom_grid, sizeof(DomGrid) * HAIR_MAX_LIGHTS))) return rc;
+    if ((rc = ws_need(ws, ws->dom_part, 20ull * dom_bound_blocks(lv.nseg)))) return rc;
+    hair_camera lcam = *cam;   // the light view's raster size; its projection is the light's own
+    lcam.width = lcam.height = R;
+    memset(views, 0, sizeof(DomView) * HAIR_MAX_LIGHTS);
+    int m = 0;
+    for (int i = 0; i < n_lights; ++i) {
+        ws->dom_light[i] = -1;
+        if (lights[i].kind != 0) continue;
+        DomGrid* grid = ws->dom_grid.as<DomGrid>() + m;
+        float4* tex = reinterpret_cast<float4*>(ws->dom_tex.as<float>() + 8 * texels * m);
+        HIP_TRY(ctx, launch_dom_grid(lv, rows, dom_basis(lights[i].vec), R, ws->dom_part.as<float>(), grid, st),
+                "k_dom_grid");
+        const DomPass dp{grid, K, shadow->layer_depth, tex, rows};
+        FrameOut fd;
+        if ((rc = run_frame(ctx, ws, a, lv, &lcam, lights, n_lights, nullptr, nullptr, st, &fd, true, nullptr,
+                            nullptr, nullptr, &dp)))
+            return rc;
+        if (fd.ctr.list_overflow) return fail(HAIR_ERANGE, "shadow map: %u tiles hold more than 2^24 segments",
+                                              fd.ctr.list_overflow);
+        *ms += fd.ms[0];
+        views[i] = DomView{grid, tex, K, shadow->layer_depth};
+        ws->dom_light[i] = m++;
+    }
+    ws->dom_R = R;
+    ws->dom_K = K;
+    ws->dom_n = m;
+    return HAIR_OK;
+}
+
 int hair_render_shadowed(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,
                          const hair_light* lights, int32_t n_lights, const hair_shadow* shadow, float* rgba_out,
                          void* stream, hair_stats* stats) {
@@ -1384,53 +1438,17 @@ int hair_render_shadowed(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t leve
     if ((rc = validate_camera(cam))) return rc;
     if ((rc = validate_lights(lights, n_lights))) return rc;
     if (!rgba_out) return fail(HAIR_EINVAL, "null output image");
-    if (!shadow) return fail(HAIR_EINVAL, "null shadow descriptor");
-    if (shadow->resolution < 16 || shadow->resolution > 4096)
-        return fail(HAIR_EINVAL, "shadow resolution %d outside [16, 4096]", shadow->resolution);
-    if (shadow->layers < 1 || shadow->layers > kDomMaxLayers)
-        return fail(HAIR_EINVAL, "shadow layers %d outside [1, %d]", shadow->layers, kDomMaxLayers);
-    if (!(std::isfinite(shadow->layer_depth) && shadow->layer_depth > 0.0f))
-        return fail(HAIR_EINVAL, "shadow layer_depth must be finite and > 0");
+    if ((rc = validate_shadow(shadow))) return rc;
     Asset* a;
     LevelDev lv;
     if ((rc = find_level(ctx, asset, level, &a, &lv))) return rc;
     if ((rc = need_device(ctx))) return rc;
     ws = ws_or_default(ctx, ws);
     std::lock_guard<std::mutex> g(ws->mu);
-    const int R = shadow->resolution, K = shadow->layers;
-    int n_dom = 0;
-    for (int i = 0; i < n_lights; ++i) n_dom += lights[i].kind == 0;
-    const size_t texels = (size_t)R * R;
-    if ((rc = ws_need(ws, ws->dom_tex, 32 * texels * std::max(n_dom, 1)))) return rc;
-    if ((rc = ws_need(ws, ws->dom_grid, sizeof(DomGrid) * HAIR_MAX_LIGHTS))) return rc;
-    if ((rc = ws_need(ws, ws->dom_part, 20ull * dom_bound_blocks(lv.nseg)))) return rc;
     const hipStream_t st = (hipStream_t)stream;
-    hair_camera lcam = *cam;   // the light view's raster size; its projection is the light's own
-    lcam.width = lcam.height = R;
     DomView views[HAIR_MAX_LIGHTS];
-    memset(views, 0, sizeof(views));
     float ms_dom = 0.0f;
-    int m = 0;
-    for (int i = 0; i < n_lights; ++i) {
-        ws->dom_light[i] = -1;
-        if (lights[i].kind != 0) continue;
-        DomGrid* grid = ws->dom_grid.as<DomGrid>() + m;
-        float4* tex = reinterpret_cast<float4*>(ws->dom_tex.as<float>() + 8 * texels * m);
-        HIP_TRY(ctx, launch_dom_grid(lv, dom_basis(lights[i].vec), R, ws->dom_part.as<float>(), grid, st), "k_dom_grid");
-        const DomPass dp{grid, K, shadow->layer_depth, tex};
-        FrameOut fd;
-        if ((rc = run_frame(ctx, ws, *a, lv, &lcam, lights, n_lights, nullptr, nullptr, st, &fd, true, nullptr,
-                            nullptr, nullptr, &dp)))
-            return rc;
-        if (fd.ctr.list_overflow) return fail(HAIR_ERANGE, "shadow map: %u tiles hold more than 2^24 segments",
-                                              fd.ctr.list_overflow);
-        ms_dom += fd.ms[0];
-        views[i] = DomView{grid, tex, K, shadow->layer_depth};
-        ws->dom_light[i] = m++;
-    }
-    ws->dom_R = R;
-    ws->dom_K = K;
-    ws->dom_n = m;
+    if ((rc = shadow_passes(ctx, ws, *a, lv, nullptr, cam, lights, n_lights, shadow, st, views, &ms_dom))) return rc;
     FrameOut fo;
     if ((rc = run_frame(ctx, ws, *a, lv, cam, lights, n_lights, rgba_out, nullptr, st, &fo, true, nullptr, nullptr,
                         nullptr, nullptr, views)))
@@ -1522,15 +1540,19 @@ int hair_lod_init(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_camera* 
     return HAIR_OK;
 }
 
-int hair_render_mixed(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_camera* cam, const hair_light* lights,
-                      int32_t n_lights, int32_t* levels, float eps_w_px, float* rgba_out, void* stream,
-                      hair_stats* stats) {
+// A mixed frame (optionally shadowed): rows of every (group, segment) at its level, then the
+// shadow passes over those rows (their world data from the camera projection of the rows),
+// the camera frame, and the deferred level update.
+static int render_mixed(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_camera* cam, const hair_light* lights,
+                        int32_t n_lights, int32_t* levels, float eps_w_px, const hair_shadow* shadow, float* rgba_out,
+                        void* stream, hair_stats* stats) {
     int rc;
     if ((rc = check_ctx(ctx))) return rc;
     if ((rc = validate_camera(cam))) return rc;
     if ((rc = validate_lights(lights, n_lights))) return rc;
     if (!rgba_out || !levels) return fail(HAIR_EINVAL, "null output image or levels");
     if (!std::isfinite(eps_w_px)) return fail(HAIR_EINVAL, "eps_w must be finite");
+    if (shadow && (rc = validate_shadow(shadow))) return rc;
     Asset* a;
     HierDev h;
     if ((rc = mixed_hierarchy(ctx, asset, &a, &h))) return rc;
@@ -1558,20 +1580,51 @@ int hair_render_mixed(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_came
     lv.kind = 2;
     lv.nseg = (int32_t)nsel;
     lv.S = a->S;
+    DomView views[HAIR_MAX_LIGHTS];
+    float ms_dom = 0.0f;
+    if (shadow) {
+        // the rows' shading records (world endpoints and cross-sections) feed the shadow passes;
+        // the camera frame projects them again into the same buffers
+        if ((rc = ws_need(ws, ws->seg, sizeof(SegRec) * (size_t)std::max<uint32_t>(nsel, 1))) ||
+            (rc = ws_need(ws, ws->shade, sizeof(ShadeRec) * (size_t)std::max<uint32_t>(nsel, 1))))
+            return rc;
+        HIP_TRY(ctx, launch_project_mixed(h, ws->sel.as<uint32_t>(), (int32_t)nsel, cam_const(cam),
+                                          ws->seg.as<SegRec>(), ws->shade.as<ShadeRec>(), st),
+                "k_project_mixed");
+        if ((rc = shadow_passes(ctx, ws, *a, lv, ws->shade.as<ShadeRec>(), cam, lights, n_lights, shadow, st, views,
+                                &ms_dom)))
+            return rc;
+    }
     FrameOut fo;
     if ((rc = run_frame(ctx, ws, *a, lv, cam, lights, n_lights, rgba_out, nullptr, st, &fo, true, nullptr, &h,
-                        ws->sel.as<uint32_t>())))
+                        ws->sel.as<uint32_t>(), nullptr, shadow ? views : nullptr)))
         return rc;
     if (eps_w_px > 0) {
         HIP_TRY(ctx, launch_lod_update(h, cam_const(cam), eps_w_px, levels, st), "k_lod_update");
         HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
     }
-    if (stats) fill_stats(stats, fo, nsel);
+    if (stats) {
+        fill_stats(stats, fo, nsel);
+        stats->ms_total += ms_dom;
+    }
     if (fo.ctr.list_overflow) return fail(HAIR_ERANGE, "%u tiles hold more than 2^24 segments", fo.ctr.list_overflow);
     if (fo.ctr.overflow_pixels)
         return fail(HAIR_ERANGE, "%u pixels hold more than %d fragments at one depth key (left transparent)",
                     fo.ctr.overflow_pixels, kCap);
     return HAIR_OK;
+}
+
+int hair_render_mixed(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_camera* cam, const hair_light* lights,
+                      int32_t n_lights, int32_t* levels, float eps_w_px, float* rgba_out, void* stream,
+                      hair_stats* stats) {
+    return render_mixed(ctx, ws, asset, cam, lights, n_lights, levels, eps_w_px, nullptr, rgba_out, stream, stats);
+}
+
+int hair_render_mixed_shadowed(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_camera* cam,
+                               const hair_light* lights, int32_t n_lights, int32_t* levels, float eps_w_px,
+                               const hair_shadow* shadow, float* rgba_out, void* stream, hair_stats* stats) {
+    if (!shadow) return fail(HAIR_EINVAL, "null shadow descriptor");
+    return render_mixed(ctx, ws, asset, cam, lights, n_lights, levels, eps_w_px, shadow, rgba_out, stream, stats);
 }
 
 int hair_render_curved(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const hair_camera* cam,

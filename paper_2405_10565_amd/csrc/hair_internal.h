@@ -269,10 +269,11 @@ hipError_t launch_project_tess(const LevelDev& lv, const uint32_t* rows, int32_t
 // block, at most dom_bound_blocks(nseg) blocks), the light-view segment records, and the
 // per-texel layers from the light view's fragment lists.
 int dom_bound_blocks(int32_t nseg);
-hipError_t launch_dom_grid(const LevelDev& lv, const DomBasis& b, int32_t R, float* part, DomGrid* grid,
+hipError_t launch_dom_grid(const LevelDev& lv, const ShadeRec* rows, const DomBasis& b, int32_t R, float* part, DomGrid* grid,
                            hipStream_t st);
-hipError_t launch_project_light(const LevelDev& lv, const DomGrid* grid, SegRec* seg, hipStream_t st);
-hipError_t launch_dom_resolve(const FrameBufs& f, const LevelDev& lv, const DomGrid* grid, int32_t K, float delta,
+hipError_t launch_project_light(const LevelDev& lv, const ShadeRec* rows, const DomGrid* grid, SegRec* seg,
+                                hipStream_t st);
+hipError_t launch_dom_resolve(const FrameBufs& f, const LevelDev& lv, const ShadeRec* rows, const DomGrid* grid, int32_t K, float delta,
                               int32_t R, uint32_t n_blocks, float4* tex, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
 // The frame's per-pixel counters: n counts set to 0, key minima to ~0, key maxima to 0.

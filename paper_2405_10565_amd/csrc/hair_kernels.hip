@@ -370,6 +370,9 @@ __global__ __launch_bounds__(256) void k_project_mixed(HierDev h, const uint32_t
     const int L = (int)(e >> 28), g = (int)(e & 0x0FFFFFFFu);
     SegRec r = project_segment(h.lv[L], g, cam, shade + i);
     if (h.lv[L].kind == 1) r.hwfx |= kFlagThick;
+    // (a strand row's q3 is otherwise unused: its world radius, and -1 marking a strand, for
+    // the shadow pass, which reads the rows' world data from these records)
+    else shade[i].q3 = make_float4(0.5f * h.lv[L].width[g / h.lv[L].S], 0.0f, 0.0f, -1.0f);
     seg[i] = r;
 }
 
@@ -2578,19 +2581,41 @@ __device__ inline float pad_halfwidth(const LevelDev& lv, int g) {
     return lv.kind == 0 ? 0.5f * lv.width[g / lv.S] : fmaxf(lv.axes[2 * g], lv.axes[2 * g + 1]);
 }
 
+// A mixed frame's shadow pass reads its rows from the camera pass's shading records instead
+// of a level: q0.xyz, q1.xyz the world endpoints, q2.xyz a^, and q3 = (|a|, |b|, n_total, r)
+// for a thick hair or (radius, 0, 0, -1) for a strand.
+__device__ inline bool row_is_strand(const ShadeRec& r) { return r.q3.w < 0.0f; }
+
+// Endpoints of segment (or row) g.
+__device__ inline void dom_endpoints(const LevelDev& lv, const ShadeRec* rows, int g, float& ax, float& ay, float& az,
+                                     float& bx, float& by, float& bz) {
+    if (rows) {
+        const float4 q0 = rows[g].q0, q1 = rows[g].q1;
+        ax = q0.x; ay = q0.y; az = q0.z;
+        bx = q1.x; by = q1.y; bz = q1.z;
+        return;
+    }
+    const int owner = g / lv.S, k = g - owner * lv.S;
+    const int va = owner * (lv.S + 1) + k;
+    ax = lv.vx[va]; ay = lv.vy[va]; az = lv.vz[va];
+    bx = lv.vx[va + 1]; by = lv.vy[va + 1]; bz = lv.vz[va + 1];
+}
+
 constexpr int kDomBoundThreads = 256;
 constexpr int kDomBoundMaxBlocks = 1024;
 
 // Per block: (min u - w, max u + w, min v - w, max v + w, max z) over its segments' endpoints.
-__global__ __launch_bounds__(kDomBoundThreads) void k_dom_bounds(LevelDev lv, DomBasis b, float* __restrict__ part) {
+__global__ __launch_bounds__(kDomBoundThreads) void k_dom_bounds(LevelDev lv, const ShadeRec* __restrict__ rows,
+                                                                DomBasis b, float* __restrict__ part) {
     __shared__ float s_red[5][kDomBoundThreads];
     float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY, zmax = -INFINITY;
     for (int g = blockIdx.x * kDomBoundThreads + threadIdx.x; g < lv.nseg; g += gridDim.x * kDomBoundThreads) {
-        const int owner = g / lv.S, k = g - owner * lv.S;
-        const int va = owner * (lv.S + 1) + k;
-        const float w = pad_halfwidth(lv, g);
+        float pe[2][3];
+        dom_endpoints(lv, rows, g, pe[0][0], pe[0][1], pe[0][2], pe[1][0], pe[1][1], pe[1][2]);
+        const float w = !rows ? pad_halfwidth(lv, g)
+                              : (row_is_strand(rows[g]) ? rows[g].q3.x : fmaxf(rows[g].q3.x, rows[g].q3.y));
         for (int e = 0; e < 2; ++e) {
-            const float x = lv.vx[va + e], y = lv.vy[va + e], z = lv.vz[va + e];
+            const float x = pe[e][0], y = pe[e][1], z = pe[e][2];
             const float u = dot_e(b.e1, x, y, z), v = dot_e(b.e2, x, y, z), d = dot_e(b.d, x, y, z);
             umin = fminf(umin, u - w);
             umax = fmaxf(umax, u + w);
@@ -2644,18 +2669,18 @@ __global__ __launch_bounds__(kDomBoundThreads) void k_dom_grid(const float* __re
 
 // Light-view record of segment g: snapped texel coordinates (1/16 texel), iz = z_ref - z, and
 // the half-width in texels (a strand's radius; a thick hair's support across the light).
-__global__ __launch_bounds__(256) void k_project_light(LevelDev lv, const DomGrid* __restrict__ grid,
-                                                       SegRec* __restrict__ seg) {
+__global__ __launch_bounds__(256) void k_project_light(LevelDev lv, const ShadeRec* __restrict__ rows,
+                                                       const DomGrid* __restrict__ grid, SegRec* __restrict__ seg) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= lv.nseg) return;
     const DomGrid gr = *grid;
-    const int owner = g / lv.S, k = g - owner * lv.S;
-    const int va = owner * (lv.S + 1) + k;
-    const float ax = lv.vx[va], ay = lv.vy[va], az = lv.vz[va];
-    const float bx = lv.vx[va + 1], by = lv.vy[va + 1], bz = lv.vz[va + 1];
+    const int owner = g / lv.S;
+    float ax, ay, az, bx, by, bz;
+    dom_endpoints(lv, rows, g, ax, ay, az, bx, by, bz);
+    const bool strand = rows ? row_is_strand(rows[g]) : lv.kind == 0;
     float hw;
-    if (lv.kind == 0) {
-        hw = (0.5f * lv.width[owner]) / gr.s;
+    if (strand) {
+        hw = (rows ? rows[g].q3.x : 0.5f * lv.width[owner]) / gr.s;
     } else {
         const float tx = bx - ax, ty = by - ay, tz = bz - az;
         const float tl = norm3f(tx, ty, tz);
@@ -2666,9 +2691,11 @@ __global__ __launch_bounds__(256) void k_project_light(LevelDev lv, const DomGri
         const float pl = norm3f(px, py, pz);
         const float xx = px / pl, xy = py / pl, xz = pz / pl;
         const float yx = uy * xz - uz * xy, yy = uz * xx - ux * xz, yz = ux * xy - uy * xx;
-        const float hx = lv.ahat[g], hy = lv.ahat[lv.nseg + g], hz = lv.ahat[2 * lv.nseg + g];
+        const float hx = rows ? rows[g].q2.x : lv.ahat[g];
+        const float hy = rows ? rows[g].q2.y : lv.ahat[lv.nseg + g];
+        const float hz = rows ? rows[g].q2.z : lv.ahat[2 * lv.nseg + g];
         const float bhx = uy * hz - uz * hy, bhy = uz * hx - ux * hz, bhz = ux * hy - uy * hx;
-        const float a_len = lv.axes[2 * g], b_len = lv.axes[2 * g + 1];
+        const float a_len = rows ? rows[g].q3.x : lv.axes[2 * g], b_len = rows ? rows[g].q3.y : lv.axes[2 * g + 1];
         const float pa = a_len * ((hx * yx + hy * yy) + hz * yz);
         const float pb = b_len * ((bhx * yx + bhy * yy) + bhz * yz);
         float W = sqrtf(pa * pa + pb * pb);
@@ -2695,6 +2722,9 @@ __global__ __launch_bounds__(256) void k_project_light(LevelDev lv, const DomGri
     seg[g] = r;
 }
 
+__device__ inline float dom_fragment_count(const SegRec& s, const LevelDev& lv, const ShadeRec* rows, float s_tex,
+                                           uint32_t g, int px, int py);
+
 // Per texel (one block per 16 x 16 tile): the first hit iz0 (the pixel's smallest key), then
 // every fragment's expected hair count into its layer floor((iz0 - iz) / delta) (clamped to
 // K - 1): a strand its box coverage alpha, a thick hair alpha rho kappa l_max sqrt(1 - h^2)
@@ -2702,20 +2732,21 @@ __global__ __launch_bounds__(256) void k_project_light(LevelDev lv, const DomGri
 // One block per batch of whole texels (the camera pass's batches), one lane per fragment; the
 // counts are summed per (texel, layer) in LDS.  Texels in no batch hold no hair (cleared).
 // Output: (iz0, C_0 .. C_{K-1}) with C the cumulative counts; iz0 = 0 marks a texel without hair.
-__device__ inline float dom_fragment_count(const SegRec& s, const LevelDev& lv, float s_tex, uint32_t g, int px,
-                                           int py) {
+__device__ inline float dom_fragment_count(const SegRec& s, const LevelDev& lv, const ShadeRec* rows, float s_tex,
+                                           uint32_t g, int px, int py) {
     const int ex = 16 * px + 8 - s.xa, ey = 16 * py + 8 - s.ya;
     const int dx = s.xb - s.xa, dy = s.yb - s.ya;
     const int tden = dx * dx + dy * dy, cr = ex * dy - ey * dx;
     const float dl = fabsf((float)cr) / sqrtf((float)tden) * (1.0f / 16.0f);
     const float hw = s.hw;
     float c = fminf(fmaxf(fminf(dl + hw, 0.5f) - fmaxf(dl - hw, -0.5f), 0.0f), 1.0f);
-    if (lv.kind != 0 && !(hw > 0.0f)) {
+    const bool thick = rows ? !row_is_strand(rows[g]) : lv.kind != 0;
+    if (thick && !(hw > 0.0f)) {
         c = 0.0f;   // a degenerate (zero-width) thick hair holds no hairs across the light
-    } else if (lv.kind != 0) {
+    } else if (thick) {
         const int owner = g / lv.S;
-        const float a = lv.axes[2 * g], b = lv.axes[2 * g + 1];
-        const float n = (float)lv.n_total[owner], r = lv.r[owner];
+        const float a = rows ? rows[g].q3.x : lv.axes[2 * g], b = rows ? rows[g].q3.y : lv.axes[2 * g + 1];
+        const float n = rows ? rows[g].q3.z : (float)lv.n_total[owner], r = rows ? rows[g].q3.w : lv.r[owner];
         const float h = fminf(dl / hw, 1.0f);
         const float rho = fminf(fmaxf(n * r * r / (a * b), 0.0f), 1.0f);
         const float kappa = sqrtf(n / (3.14159265358979f * a * b));
@@ -2724,8 +2755,9 @@ __device__ inline float dom_fragment_count(const SegRec& s, const LevelDev& lv, 
     return c;
 }
 
-__global__ __launch_bounds__(kNT) void k_dom_resolve(FrameBufs f, LevelDev lv, const DomGrid* __restrict__ grid, int K,
-                                                     float delta, float4* __restrict__ tex) {
+__global__ __launch_bounds__(kNT) void k_dom_resolve(FrameBufs f, LevelDev lv, const ShadeRec* __restrict__ rows,
+                                                     const DomGrid* __restrict__ grid, int K, float delta,
+                                                     float4* __restrict__ tex) {
     // per (texel, layer) sums in 32.32 fixed point: integer adds commute, so the LDS atomics
     // give the same sums in any order (counts are far below 2^31 hairs; resolution 2^-32)
     __shared__ unsigned long long s_acc[kDomMaxLayers][kTilePix];
@@ -2776,7 +2808,7 @@ __global__ __launch_bounds__(kNT) void k_dom_resolve(FrameBufs f, LevelDev lv, c
             const uint32_t p = rec[u].y >> 24;
             const float iz = __uint_as_float(0xFFFFFFFFu - rec[u].x);
             const int layer = min(K - 1, (int)floorf((s_iz0[p] - iz) / delta));
-            const float c = dom_fragment_count(sg[u], lv, s_tex, g[u], tx0 + (int)(p % kTile), ty0 + (int)(p / kTile));
+            const float c = dom_fragment_count(sg[u], lv, rows, s_tex, g[u], tx0 + (int)(p % kTile), ty0 + (int)(p / kTile));
             const unsigned long long fx = (unsigned long long)((double)c * 4294967296.0 + 0.5);
             if (fx) atomicAdd(&s_acc[layer][p], fx);
         }
@@ -2832,28 +2864,29 @@ int dom_bound_blocks(int32_t nseg) {
     return std::max(1, std::min(kDomBoundMaxBlocks, (int)((nseg + kDomBoundThreads - 1) / kDomBoundThreads)));
 }
 
-hipError_t launch_dom_grid(const LevelDev& lv, const DomBasis& b, int32_t R, float* part, DomGrid* grid,
-                           hipStream_t st) {
+hipError_t launch_dom_grid(const LevelDev& lv, const ShadeRec* rows, const DomBasis& b, int32_t R, float* part,
+                           DomGrid* grid, hipStream_t st) {
     const int nb = dom_bound_blocks(lv.nseg);
-    hipLaunchKernelGGL(k_dom_bounds, dim3(nb), dim3(kDomBoundThreads), 0, st, lv, b, part);
+    hipLaunchKernelGGL(k_dom_bounds, dim3(nb), dim3(kDomBoundThreads), 0, st, lv, rows, b, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_dom_grid, dim3(1), dim3(kDomBoundThreads), 0, st, part, nb, b, R, grid);
     return hipGetLastError();
 }
 
-hipError_t launch_project_light(const LevelDev& lv, const DomGrid* grid, SegRec* seg, hipStream_t st) {
+hipError_t launch_project_light(const LevelDev& lv, const ShadeRec* rows, const DomGrid* grid, SegRec* seg,
+                                hipStream_t st) {
     if (lv.nseg == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_project_light, dim3(blocks_for(lv.nseg, 256)), dim3(256), 0, st, lv, grid, seg);
+    hipLaunchKernelGGL(k_project_light, dim3(blocks_for(lv.nseg, 256)), dim3(256), 0, st, lv, rows, grid, seg);
     return hipGetLastError();
 }
 
-hipError_t launch_dom_resolve(const FrameBufs& f, const LevelDev& lv, const DomGrid* grid, int32_t K, float delta,
-                              int32_t R, uint32_t n_batches, float4* tex, hipStream_t st) {
+hipError_t launch_dom_resolve(const FrameBufs& f, const LevelDev& lv, const ShadeRec* rows, const DomGrid* grid,
+                              int32_t K, float delta, int32_t R, uint32_t n_batches, float4* tex, hipStream_t st) {
     // n_batches: the grid (at least the frame's batch count, which the kernel reads)
     hipError_t e = launch_fill_f32(reinterpret_cast<float*>(tex), 0.0f, 8ull * R * R, st);
     if (e != hipSuccess || n_batches == 0) return e;
-    hipLaunchKernelGGL(k_dom_resolve, dim3(n_batches), dim3(kNT), 0, st, f, lv, grid, K, delta, tex);
+    hipLaunchKernelGGL(k_dom_resolve, dim3(n_batches), dim3(kNT), 0, st, f, lv, rows, grid, K, delta, tex);
     return hipGetLastError();
 }
 
@@ -2978,14 +3011,15 @@ hipError_t launch_batches(const FrameBufs& f, const LevelDev& lv, const CamConst
     const dim3 g(n_batches), b(kNT);
     bool shadow = false;
     for (int i = 0; i < lights.n; ++i) shadow |= lights.dom[i].grid != nullptr;
-    if (shadow && lv.kind == 2) return hipErrorInvalidValue;   // (callers check this first)
     if (shadow) {
         if (mat.model == 0) {
             if (lv.kind == 0) hipLaunchKernelGGL((k_batch<0, 0, true>), g, b, 0, st, f, a, rgba, d, hd);
-            else hipLaunchKernelGGL((k_batch<1, 0, true>), g, b, 0, st, f, a, rgba, d, hd);
+            else if (lv.kind == 1) hipLaunchKernelGGL((k_batch<1, 0, true>), g, b, 0, st, f, a, rgba, d, hd);
+            else hipLaunchKernelGGL((k_batch<2, 0, true>), g, b, 0, st, f, a, rgba, d, hd);
         } else {
             if (lv.kind == 0) hipLaunchKernelGGL((k_batch<0, 1, true>), g, b, 0, st, f, a, rgba, d, hd);
-            else hipLaunchKernelGGL((k_batch<1, 1, true>), g, b, 0, st, f, a, rgba, d, hd);
+            else if (lv.kind == 1) hipLaunchKernelGGL((k_batch<1, 1, true>), g, b, 0, st, f, a, rgba, d, hd);
+            else hipLaunchKernelGGL((k_batch<2, 1, true>), g, b, 0, st, f, a, rgba, d, hd);
         }
     } else if (mat.model == 0) {
         if (lv.kind == 0) hipLaunchKernelGGL((k_batch<0, 0, false>), g, b, 0, st, f, a, rgba, d, hd);

@@ -195,12 +195,42 @@ def shadow_frames(hctx: B.Context, iters: int = 20, shadow=(1024, 4, 0.02)):
         if i >= 2:
             ms.append(st["ms_total"])
     torch.cuda.synchronize()
-    ws.close()
+    plain = []
+    for i in range(iters + 2):
+        _, st0, _ = hctx.render(aid, 0, cam, lights, ws=ws)
+        if i >= 2:
+            plain.append(st0["ms_total"])
+    out = {"experiment": "shadow", "strands": asset.n_strands, "width": cam.width, "height": cam.height,
+           "resolution": shadow[0], "layers": shadow[1], "layer_depth": shadow[2], "frames": iters,
+           "fragments": int(st["fragments"]), "frame_ms_p50": round(float(np.percentile(ms, 50)), 4),
+           "frame_ms_mean": round(float(np.mean(ms)), 4),
+           "plain_frame_ms_p50": round(float(np.percentile(plain, 50)), 4)}
     hctx.release(aid)
-    return {"experiment": "shadow", "strands": asset.n_strands, "width": cam.width, "height": cam.height,
-            "resolution": shadow[0], "layers": shadow[1], "layer_depth": shadow[2], "frames": iters,
-            "fragments": int(st["fragments"]), "frame_ms_p50": round(float(np.percentile(ms, 50)), 4),
-            "frame_ms_mean": round(float(np.mean(ms)), 4)}
+    # a mixed-level frame (per-group LoD of the serving asset of the same size: 100k strands
+    # x 32 segments with 6250 / 390 / 24 thick hairs, initial levels at eps_w = 8 px so that
+    # a share of the (group, segment) cells goes coarse), plain and shadowed
+    from . import serve as S
+    assets = S.build_assets(hctx, specs=((100_000, 32),), seed=1002)
+    a = next(iter(assets.values()))
+    lev = torch.empty((a.groups, a.asset.segs), dtype=torch.int32, device=f"cuda:{hctx.device}")
+    hctx.lod_init(a.aid, cam, 8.0, lev, ws=ws)
+    hist = np.bincount(lev.cpu().numpy().reshape(-1), minlength=len(a.segments_per_level))
+    mixed_plain, mixed_sh = [], []
+    for i in range(iters + 2):
+        _, s1, _ = hctx.render_mixed(a.aid, cam, a.lights, lev, ws=ws)
+        _, s2, _ = hctx.render_mixed_shadowed(a.aid, cam, a.lights, lev, shadow, ws=ws)
+        if i >= 2:
+            mixed_plain.append(s1["ms_total"])
+            mixed_sh.append(s2["ms_total"])
+    torch.cuda.synchronize()
+    out["mixed"] = {"asset": "100k x 32 strands, 6250 / 390 / 24 thick hairs", "eps_w": 8.0,
+                    "cells_per_level": [round(float(v), 4) for v in hist / hist.sum()],
+                    "segments": int(s1["segments"]), "fragments": int(s1["fragments"]),
+                    "plain_ms_p50": round(float(np.percentile(mixed_plain, 50)), 4),
+                    "shadowed_ms_p50": round(float(np.percentile(mixed_sh, 50)), 4)}
+    hctx.release(a.aid)
+    ws.close()
+    return out
 
 
 def main():

@@ -8,7 +8,9 @@ level buffer and an output buffer, and runs the LoD choice and the frame on its 
 overlap on the device.  LoD (lod="mixed", the default): per group of the coarsest level and per
 segment index, the coarsest level whose thick hairs are at most eps_w = 2 px wide (Sec. 5.1
 step 5, Sec. 6), rendered as one mixed-level frame (or as that level's own frame when one
-level is chosen everywhere); lod="level": one level for the whole asset.
+level is chosen everywhere); lod="level": one level for the whole asset.  With shadow =
+(resolution, layers, layer_depth) every frame gets deep opacity map shadows (mixed frames
+over their own rows).
 A request's latency is its completion time minus its arrival time.
 
 Memory: the budget is charged with what the workspaces really hold on the device.  A request
@@ -89,10 +91,11 @@ class Server:
     """FIFO admission by footprint; n_slots requests in flight at most."""
 
     def __init__(self, hctx: B.Context, assets: dict, n_slots: int = 4, scratch_budget: int = 32 << 30,
-                 eps_w: float = 2.0, keep_outputs: bool = False, lod: str = "mixed"):
+                 eps_w: float = 2.0, keep_outputs: bool = False, lod: str = "mixed", shadow=None):
         self.hctx = hctx
         self.assets = assets
         self.lod = lod
+        self.shadow = shadow          # (resolution, layers, layer_depth): deep opacity map shadows
         self.scratch_budget = int(scratch_budget)
         self.eps_w = eps_w
         self.keep_outputs = keep_outputs
@@ -228,15 +231,16 @@ class Server:
                 req.level_hist = hist.tolist()
                 req.level = int(np.argmax(hist))
                 if hist[req.level] == hist.sum():   # one level everywhere: that level's own frame
-                    _, st, rc = self.hctx.render(a.aid, req.level, cam, a.lights, out=out, ws=slot.ws,
-                                                 stream=slot.stream, raise_on_error=False)
+                    _, st, rc = self._level_frame(a, req.level, cam, out, slot)
+                elif self.shadow is not None:
+                    _, st, rc = self.hctx.render_mixed_shadowed(a.aid, cam, a.lights, lev, self.shadow, 0.0, out=out,
+                                                                ws=slot.ws, stream=slot.stream, raise_on_error=False)
                 else:
                     _, st, rc = self.hctx.render_mixed(a.aid, cam, a.lights, lev, 0.0, out=out, ws=slot.ws,
                                                        stream=slot.stream, raise_on_error=False)
             else:
                 req.level = self.hctx.select_level(a.aid, cam, self.eps_w, ws=slot.ws, stream=slot.stream)
-                _, st, rc = self.hctx.render(a.aid, req.level, cam, a.lights, out=out, ws=slot.ws,
-                                             stream=slot.stream, raise_on_error=False)
+                _, st, rc = self._level_frame(a, req.level, cam, out, slot)
             req.status = rc
             req.fragments = int(st["fragments"])
             if self.keep_outputs:
@@ -247,6 +251,13 @@ class Server:
         except B.HairError as e:
             req.status = e.code
         req.done = self.now()
+
+    def _level_frame(self, a, level, cam, out, slot):
+        if self.shadow is not None:
+            return self.hctx.render_shadowed(a.aid, level, cam, a.lights, self.shadow, out=out, ws=slot.ws,
+                                             stream=slot.stream, raise_on_error=False)
+        return self.hctx.render(a.aid, level, cam, a.lights, out=out, ws=slot.ws, stream=slot.stream,
+                                raise_on_error=False)
 
     def drain(self, timeout: float = 600.0):
         end = time.perf_counter() + timeout

@@ -119,6 +119,39 @@ def test_mix_equals_alone(hip, served, lod):
     assert "mixed" in kinds
 
 
+def test_shadowed_serving_equals_alone_and_oracle(hip, served):
+    """Served frames with deep opacity map shadows (mixed frames over their own rows): the same
+    alone and in the mix, and a mixed-level one against the oracle."""
+    print("case: shadowed serving", flush=True)
+    from paper_2405_10565_amd import serve as S
+    ctx, assets, lods = served
+    names = sorted(assets)
+    sh = (128, 4, 0.02)
+    mix = S.make_requests(names, 16, seed=8, resolutions=SMALL_RES[:2])
+    srv = S.Server(ctx, assets, n_slots=4, keep_outputs=True, eps_w=6.0, shadow=sh)
+    S.run_poisson(srv, mix, rate=2000.0, seed=8)
+    srv.close()
+    alone = S.make_requests(names, 16, seed=8, resolutions=SMALL_RES[:2])
+    srv1 = S.Server(ctx, assets, n_slots=1, keep_outputs=True, eps_w=6.0, shadow=sh)
+    for r in alone:
+        srv1.submit(r)
+        srv1.drain()
+    srv1.close()
+    assert all(r.status == 0 for r in mix + alone)
+    for a, b in zip(mix, alone):
+        assert torch.equal(a.output.view(torch.int32), b.output.view(torch.int32)), a.rid
+    mixed = [r for r in mix if r.levels_used is not None and len(np.unique(r.levels_used)) > 1]
+    assert mixed
+    r = mixed[0]
+    a = assets[r.asset]
+    geom, _ = _oracle_geom(a, lods[r.asset], r)
+    ref, ras = R.render(geom, _camera(a, r), a.lights, tuple(float(v) for v in a.asset.material.as_array()), shadow=sh)
+    got = r.output.cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref) - (RTOL * np.abs(ref) + ATOL)
+    print(f"shadowed served request {r.rid}: {int((err > 0).sum())} violations", flush=True)
+    assert int((err > 0).sum()) == 0 and r.fragments == len(ras.seg)
+
+
 def test_admission_by_footprint(hip, served):
     print("case: admission", flush=True)
     from paper_2405_10565_amd import serve as S

@@ -112,3 +112,52 @@ def test_without_directional_lights_the_plain_frame(hip, ctx):
     assert torch.equal(a.view(torch.int32), b.view(torch.int32))
     ws.close()
     ctx.release(aid)
+
+
+@pytest.mark.parametrize("material", ["rttrt", "rttd"])
+def test_shadowed_mixed_frame(hip, ctx, material):
+    """A mixed-level frame (a random level per group and segment) with deep opacity maps: the
+    map of the frame's own rows (grid and first hits bit-exact, counts within float32 summation
+    error) and the frame within 1e-4 of the oracle; with one level everywhere it is that
+    level's shadowed frame."""
+    print(f"case: shadowed mixed frame ({material})", flush=True)
+    from oracle import mixed as M
+    asset = hs.make_asset(2500, 10, 90.0, seed=23, sigma_spread=True)
+    if material == "rttd":
+        asset = dataclasses.replace(asset, material=hs.Material.rttd())
+    assigns = hs.kmeans_hierarchy(asset, (400, 80, 12), seed=23)
+    aid = ctx.upload_asset(asset)
+    ctx.build_lod(aid, assigns)
+    lods = [OL.build_level(asset, a) for a in assigns]
+    for l, lod in enumerate(lods, 1):
+        ctx.set_lod(aid, l, lod)
+    geoms = M.level_geoms(asset, lods)
+    grps = M.groups(assigns)
+    cam = hs.camera_for(asset, 120, 104)
+    lights = hs.default_lights(asset, with_point=True)
+    G, S = ctx.lod_groups(aid), asset.segs
+    levels = np.random.default_rng(41).integers(0, 4, size=(G, S)).astype(np.int32)
+    R_, K, delta = 96, 4, 0.02
+    ws = ctx.workspace()
+    lev = torch.tensor(levels, device="cuda:0")
+    img, st, _ = ctx.render_mixed_shadowed(aid, cam, lights, lev, (R_, K, delta), ws=ws)
+    torch.cuda.synchronize()
+    mixed = M.mixed_geometry(geoms, grps, levels)
+    assert st["segments"] == mixed.pA.shape[1]
+    _dom_parity(ctx, ws, mixed, lights[0], 0, R_, K, delta, "mixed frame")
+    ref, ras = R.render(mixed, cam, lights, R.material(asset.material), shadow=(R_, K, delta))
+    assert st["fragments"] == len(ras.seg)
+    _check(img.cpu().numpy(), ref, f"shadowed mixed frame ({material})")
+    plain, _, _ = ctx.render_mixed(aid, cam, lights, lev, ws=ws)
+    torch.cuda.synchronize()
+    assert not torch.equal(plain, img)
+    # one level everywhere: the level's own shadowed frame (rows in another order)
+    for l in (0, 2):
+        uni = torch.full((G, S), l, dtype=torch.int32, device="cuda:0")
+        a, _, _ = ctx.render_mixed_shadowed(aid, cam, lights, uni, (R_, K, delta), ws=ws)
+        b, _, _ = ctx.render_shadowed(aid, l, cam, lights, (R_, K, delta), ws=ws)
+        torch.cuda.synchronize()
+        x, y = a.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(x - y) <= 2e-4 * np.abs(y) + 1e-7), l
+    ws.close()
+    ctx.release(aid)

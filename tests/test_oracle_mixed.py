@@ -116,3 +116,20 @@ def test_selection_rules(scene):
     vis_w = widths[1] > 0
     up = M.update_levels(geoms, grps, cam, 0.0, start)
     assert np.all(up[vis_w] == 0) and np.all(up[~vis_w] == 2)
+
+
+def test_uniform_levels_reproduce_single_level_shadowed_frames(scene):
+    """A mixed frame's deep opacity map holds the frame's own rows: with one level everywhere
+    the shadowed mixed frame is that level's shadowed frame (the rows in another order)."""
+    asset, assigns, lods, cam, lights, geoms, grps = scene
+    G, S = int(assigns[-1].max()) + 1, asset.segs
+    mat = mat_of(asset)
+    sh = (48, 3, 0.02)
+    for l in (0, 2):
+        mixed = M.mixed_geometry(geoms, grps, np.full((G, S), l, np.int32))
+        a, _ = R.render(mixed, cam, lights, mat, shadow=sh)
+        b, _ = R.render(geoms[l], cam, lights, mat, shadow=sh)
+        assert np.allclose(a, b, rtol=1e-9, atol=1e-13), l
+        plain, _ = R.render(geoms[l], cam, lights, mat)
+        assert np.abs(a - plain).max() > 1e-6                # the map does shadow
+
