@@ -92,9 +92,11 @@ typedef struct hair_light {
 typedef struct hair_stats {
     uint64_t fragments;          /* accepted (segment, pixel) fragments */
     uint64_t pairs;              /* (tile, segment) binning pairs */
-    uint32_t segments;           /* segments of the level */
+    uint32_t segments;           /* rows drawn: the level's segments, or with long segments as pieces */
     uint32_t segments_visible;   /* after near-plane, guard-band and size culling */
-    uint32_t segments_culled_long; /* culled for exceeding 1024 px per axis or 256 px half-width */
+    uint32_t segments_culled_long; /* culled as too long (more than 64 pieces of 1000 px, or any
+                                      segment beyond 1024 px in hair_render_noalloc) or wider
+                                      than 2048 px in half-width */
     uint32_t overflow_pixels;    /* pixels that could not be ordered (none in a forward frame; backward: > 64 slices) */
     float ms_total;              /* GPU time of the call's kernels (hipEvent) */
     float ms_project;            /* of which before shading: projection, binning, coverage, emission */

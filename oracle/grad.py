@@ -18,7 +18,7 @@ import numpy as np
 import torch
 
 from . import raster as rs
-from .render import DT, LevelGeom, composite, fragment_radiance, rasterize
+from .render import DT, LevelGeom, composite, fragment_radiance, rasterize, split_long
 
 
 def _midpoint_yhat(geom: LevelGeom, cam):
@@ -53,17 +53,22 @@ def halfwidth_torch(geom: LevelGeom, ras, cam, a_len, b_len):
 
 
 def cluster_vjp(geom: LevelGeom, cam, lights, mat, d_rgba, K: int, S: int, ras=None):
-    """(d_axes [K, S, 2], d_r [K], d_sigma_a [3, K], rgba) for the loss sum(d_rgba * rgba)."""
+    """(d_axes [K, S, 2], d_r [K], d_sigma_a [3, K], rgba) for the loss sum(d_rgba * rgba).
+    The camera raster draws long segments as pieces (render.split_long); a piece's parameters
+    are its segment's.  A given ras must come from split_long(geom, cam)."""
+    base = geom
+    geom = split_long(geom, cam)
     if ras is None:
         ras = rasterize(geom, cam)
-    axes = torch.tensor(np.stack([geom.a_len.reshape(K, S), geom.b_len.reshape(K, S)], -1),
+    axes = torch.tensor(np.stack([base.a_len.reshape(K, S), base.b_len.reshape(K, S)], -1),
                         dtype=DT, requires_grad=True)
-    r = torch.tensor(geom.r.reshape(K, S)[:, 0], dtype=DT, requires_grad=True)
-    sig = torch.tensor(geom.sigma_a.reshape(K, S, 3)[:, 0, :].T.copy(), dtype=DT, requires_grad=True)
-    a_len = axes[..., 0].reshape(-1)
-    b_len = axes[..., 1].reshape(-1)
+    r = torch.tensor(base.r.reshape(K, S)[:, 0], dtype=DT, requires_grad=True)
+    sig = torch.tensor(base.sigma_a.reshape(K, S, 3)[:, 0, :].T.copy(), dtype=DT, requires_grad=True)
+    rows = torch.as_tensor(geom.parent if geom.parent is not None else np.arange(K * S), dtype=torch.int64)
+    a_len = axes[..., 0].reshape(-1)[rows]
+    b_len = axes[..., 1].reshape(-1)[rows]
     params = dict(a_len=a_len, b_len=b_len,
-                  r=r.repeat_interleave(S), sigma_a=sig.T.repeat_interleave(S, dim=0),
+                  r=r.repeat_interleave(S)[rows], sigma_a=sig.T.repeat_interleave(S, dim=0)[rows],
                   hw=halfwidth_torch(geom, ras, cam, a_len, b_len))
     alpha, L = fragment_radiance(geom, ras, cam, lights, mat, params=params)
     rgba = composite(ras, alpha, L)

@@ -9,8 +9,9 @@ restates that as an exact integer predicate on a 1/16-pixel grid so the result i
     depth iz = 1 / -vz.  Float32, one rounding per operation, no fused multiply-add: these
     values decide integers, so they are taken in the kernel's precision.
   * cull: an endpoint nearer than z_near, a snapped coordinate outside the guard band
-    [-2^14, 16 W + 2^14] (and likewise for H), a segment longer than 2^14 sub-pixels on an
-    axis or with hw_fx > 4096.  The last two keep every int64 product below 2^62.
+    [-2^14, 16 W + 2^14] (and likewise for H), or hw_fx > 32768 (2048 px).  A segment longer
+    than 2^14 sub-pixels (1024 px) on an axis is drawn as pieces (render.split_long), each
+    within that extent; the two limits keep every coverage product below 2^31.
   * half-width hw (pixels): a strand uses (w / 2) fy / z_mid; a thick hair uses the
     ellipse's support half-width across the view, at the segment midpoint, times fy / z_mid.
     The coverage radius is hw_fx = ceil(16 hw) sub-pixels, plus 8 (half a pixel) for the
@@ -30,8 +31,10 @@ import numpy as np
 
 F32 = np.float32
 GUARD = 16384          # 2^14 sub-pixels = 1024 px
-MAX_AXIS = 16384       # longest allowed segment extent per axis (sub-pixels)
-MAX_HW_FX = 4096       # largest allowed coverage half-width (sub-pixels)
+MAX_AXIS = 16384       # longest segment (or piece) extent per axis (sub-pixels)
+MAX_HW_FX = 32768      # largest allowed coverage half-width (sub-pixels)
+SPLIT_LEN = 16000      # a longer segment is cut into pieces of at most this extent (sub-pixels)
+MAX_PIECES = 64
 
 
 def cam_arrays(cam):

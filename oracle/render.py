@@ -51,6 +51,7 @@ class LevelGeom:
     cluster: np.ndarray = None  # i64 [S] cluster of each segment
     seg_in_cluster: np.ndarray = None
     thick: np.ndarray = None   # bool [S]: mixed frames, rows that are thick hairs
+    parent: np.ndarray = None  # i64 [rows]: after split_long, the segment each piece comes from
 
 
 def strand_level(asset) -> LevelGeom:
@@ -114,6 +115,52 @@ def segment_records(geom: LevelGeom, cam):
                                      geom.b_len[t], c)
     hw_fx, vis = rs.finalize_segments(XA, YA, XB, YB, okA, okB, hw)
     return c, XA, YA, XB, YB, izA, izB, hw.astype(np.float32), hw_fx, vis
+
+
+def split_long(geom: LevelGeom, cam) -> LevelGeom:
+    """Segments longer than 1024 px on a screen axis, as pieces (projection step, Sec. 5.2).
+
+    A segment whose snapped endpoints are both on the guard band and whose extent
+    max(|dX|, |dY|) exceeds 2^14 sub-pixels is drawn as m = min(ceil(extent / 16000), 64)
+    pieces of equal screen parameter: piece j runs between the world points of screen
+    parameters j / m and (j + 1) / m, found with the perspective-correct parameter (inverse
+    depth is affine on screen: t_w = s izB / (izA + s (izB - izA))), float32 with one rounding
+    per operation: s = j / m, iz = izA + s (izB - izA), t_w = (s izB) / iz, P = A + t_w (B - A),
+    and P = A, B exactly at s = 0, 1.  A piece keeps its segment's attributes; rows are in
+    (segment, piece) order and `parent` maps each row to its segment.  Frames without such a
+    segment are returned unchanged."""
+    c = rs.cam_arrays(cam)
+    XA, YA, _, izA, okA = rs.project_points(geom.pA, c)
+    XB, YB, _, izB, okB = rs.project_points(geom.pB, c)
+    ext = np.maximum(np.abs(XB - XA), np.abs(YB - YA))
+    long = okA & okB & (ext > rs.MAX_AXIS)
+    if not long.any():
+        return geom
+    m = np.where(long, np.minimum((ext + rs.SPLIT_LEN - 1) // rs.SPLIT_LEN, rs.MAX_PIECES), 1).astype(np.int64)
+    parent = np.repeat(np.arange(m.size), m)
+    j = np.arange(parent.size) - np.repeat(np.cumsum(m) - m, m)
+    F = np.float32
+
+    def point(jj):
+        mm = m[parent].astype(F)
+        sp = jj.astype(F) / mm
+        a, b = izA[parent], izB[parent]
+        iz = a + sp * (b - a)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            tw = (sp * b) / iz
+        A, B = geom.pA[:, parent], geom.pB[:, parent]
+        P = np.stack([A[i] + tw * (B[i] - A[i]) for i in range(3)]).astype(F)
+        P = np.where((jj == 0)[None, :], A, P)
+        return np.where((jj == m[parent])[None, :], B, P)
+
+    pick = lambda x: None if x is None else x[parent].copy()      # per-row attributes [S]
+    out = LevelGeom(geom.kind, point(j), point(j + 1), geom.sigma_a[parent].copy(),
+                    width=None if geom.width is None else geom.width[parent].copy(),
+                    ahat=None if geom.ahat is None else geom.ahat[:, parent].copy(),
+                    a_len=pick(geom.a_len), b_len=pick(geom.b_len), n_total=pick(geom.n_total), r=pick(geom.r),
+                    cluster=pick(geom.cluster), seg_in_cluster=pick(geom.seg_in_cluster), thick=pick(geom.thick),
+                    parent=parent if geom.parent is None else geom.parent[parent])
+    return out
 
 
 def rasterize(geom: LevelGeom, cam, pix_filter=None, rect=None) -> Raster:
@@ -339,13 +386,16 @@ def composite(ras: Raster, alpha, L):
 
 def render(geom: LevelGeom, cam, lights, mat, pix_filter=None, rect=None, shadow=None):
     """Oracle frame: returns (rgba float64 [H, W, 4] numpy, Raster).  shadow = (R, K, Delta):
-    shade with deep opacity maps of that resolution, layer count and layer depth."""
-    ras = rasterize(geom, cam, pix_filter=pix_filter, rect=rect)
+    shade with deep opacity maps of that resolution, layer count and layer depth (the maps
+    rasterise the segments themselves; the camera raster draws long segments as pieces).
+    The Raster's segment ids index split_long(geom, cam)."""
+    cgeom = split_long(geom, cam)
+    ras = rasterize(cgeom, cam, pix_filter=pix_filter, rect=rect)
     ns = None
     if shadow is not None:
         from . import shadow as sh
-        ns = sh.shadow_counts(geom, ras, cam, lights, *shadow)
-    alpha, L = fragment_radiance(geom, ras, cam, lights, mat, shadow=ns)
+        ns = sh.shadow_counts(cgeom, ras, cam, lights, *shadow, dom_geom=geom)
+    alpha, L = fragment_radiance(cgeom, ras, cam, lights, mat, shadow=ns)
     return composite(ras, alpha, L).numpy(), ras
 
 

@@ -234,15 +234,16 @@ def dom_count(dom: Dom, x):
     return out
 
 
-def shadow_counts(geom: LevelGeom, ras, cam, lights, R: int, K: int, delta: float):
+def shadow_counts(geom: LevelGeom, ras, cam, lights, R: int, K: int, delta: float, dom_geom: LevelGeom = None):
     """Per light, n_s of every camera fragment (float64 tensor) or None (point lights); the
-    DOM of each directional light is built from the same geometry."""
+    DOM of each directional light is built from dom_geom (default: the same geometry; the
+    camera raster's rows may be pieces of dom_geom's long segments)."""
     x = lookup_point(geom, ras, cam)
     out = []
     for light in lights:
         if light.kind != 0:
             out.append(None)
             continue
-        dom = build_dom(geom, light.vec, R, K, delta)
+        dom = build_dom(geom if dom_geom is None else dom_geom, light.vec, R, K, delta)
         out.append(torch.as_tensor(dom_count(dom, x), dtype=DT))
     return out

@@ -465,10 +465,12 @@ int frame_result(hair_ctx* ctx, hair_ws* ws, int64_t nseg, int T, FrameOut* out)
 // A shadow-pass raster: the light view's records instead of the camera's, and the per-texel
 // layers instead of shading.
 // A curved thick-hair frame: the row list over the level's segments (base) and their steps.
+// A frame of pieces of the level's long segments (split): the same, with rows of pieces.
 struct TessPass {
     LevelDev base;
     const uint32_t* rows;
     const uint32_t* cnt;
+    bool split = false;
 };
 
 struct DomPass {
@@ -536,6 +538,10 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
                 "k_project_mixed");
     else if (dom)
         HIP_TRY(ctx, launch_project_light(lv, dom->rows, dom->grid, ws->seg.as<SegRec>(), st), "k_project_light");
+    else if (tess && tess->split)
+        HIP_TRY(ctx, launch_project_split(tess->base, tess->rows, lv.nseg, tess->cnt, cc, ws->seg.as<SegRec>(),
+                                          ws->shade.as<ShadeRec>(), st),
+                "k_project_split");
     else if (tess)
         HIP_TRY(ctx, launch_project_tess(tess->base, tess->rows, lv.nseg, tess->cnt, cc, ws->seg.as<SegRec>(),
                                          ws->shade.as<ShadeRec>(), st),
@@ -657,7 +663,7 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
         HIP_TRY(ctx, launch_dom_resolve(f, lv, dom->rows, dom->grid, dom->K, dom->delta, cam->width, batch_grid, dom->tex, st),
                 "k_dom_resolve");
     } else if (grad) {
-        HIP_TRY(ctx, launch_fill_f32(grad->d_axes, 0.0f, 2ull * lv.nseg, st), "fill");
+        HIP_TRY(ctx, launch_fill_f32(grad->d_axes, 0.0f, 2ull * (tess ? tess->base.nseg : lv.nseg), st), "fill");
         HIP_TRY(ctx, launch_fill_f32(grad->d_r, 0.0f, (size_t)lv.n_owner, st), "fill");
         HIP_TRY(ctx, launch_fill_f32(grad->d_sig, 0.0f, 3ull * lv.n_owner, st), "fill");
         HIP_TRY(ctx, launch_batches_bwd(f, lv, cc, lc, mat_const(a.mat), batch_grid, *grad, st), "k_batch_bwd");
@@ -689,6 +695,59 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
             out->ctr.phase[0], out->ctr.phase[1], out->ctr.phase[2], out->ctr.phase[3], out->ctr.phase[4], out->ctr.phase[5],
             out->ctr.phase[6], out->ctr.phase[7], n_batches, out->ctr.sizes[1]);
 #endif
+    return HAIR_OK;
+}
+
+// Rows of a frame that draws the level's long segments as pieces (into ws->sel_*), and the
+// pass and level that render them.  Synchronises st once (the row count).
+int split_rows(hair_ctx* ctx, hair_ws* ws, const LevelDev& lv, const hair_camera* cam, hipStream_t st, TessPass* tp,
+               LevelDev* lv_out) {
+    int rc;
+    const int n = lv.nseg;
+    if ((rc = ws_need(ws, ws->sel_cnt, 4ull * (n + 1))) || (rc = ws_need(ws, ws->sel_start, 4ull * (n + 1))) ||
+        (rc = ws_need(ws, ws->sel_tmp, 4 * exscan_scratch_words(n))))
+        return rc;
+    uint32_t* cnt = ws->sel_cnt.as<uint32_t>();
+    uint32_t* start = ws->sel_start.as<uint32_t>();
+    HIP_TRY(ctx, launch_split(lv, cam_const(cam), cnt, start, ws->sel_tmp.as<uint32_t>(), st), "k_split_count");
+    uint32_t nrows = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&nrows, start + n, 4, hipMemcpyDeviceToHost, st), "copy");
+    HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
+    if (nrows >= (1u << 26)) return fail(HAIR_ERANGE, "%u pieces: the frame has 2^26 rows or more", nrows);
+    if ((rc = ws_need(ws, ws->sel, 4ull * std::max<uint32_t>(nrows, 1)))) return rc;
+    HIP_TRY(ctx, launch_split_fill(cnt, start, n, ws->sel.as<uint32_t>(), st), "k_split_fill");
+    tp->base = lv;
+    tp->rows = ws->sel.as<uint32_t>();
+    tp->cnt = cnt;
+    tp->split = true;
+    *lv_out = lv;
+    lv_out->nseg = (int32_t)nrows;
+    return HAIR_OK;
+}
+
+// A frame of a level (rendered, shadowed with views, differentiated with grad, or dumped with
+// dbg), drawn again with its long segments as pieces when the first pass found any (those are
+// culled there).  *nseg_out: the rows of the frame that counts.
+int level_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, const hair_camera* cam,
+                const hair_light* lights, int n_lights, float* rgba, const DebugDump* dbg, hipStream_t st,
+                FrameOut* fo, GradOut* grad = nullptr, const DomView* views = nullptr, uint32_t* nseg_out = nullptr) {
+    int rc;
+    if ((rc = run_frame(ctx, ws, a, lv, cam, lights, n_lights, rgba, dbg, st, fo, true, grad, nullptr, nullptr, nullptr,
+                        views)))
+        return rc;
+    if (nseg_out) *nseg_out = (uint32_t)lv.nseg;
+    if (!fo->ctr.split_needed || ws->arena) return HAIR_OK;
+    TessPass tp;
+    LevelDev lv2;
+    if ((rc = split_rows(ctx, ws, lv, cam, st, &tp, &lv2))) return rc;
+    if (grad) grad->rows = tp.rows;
+    if (nseg_out) *nseg_out = (uint32_t)lv2.nseg;
+    float first[4];
+    std::copy(fo->ms, fo->ms + 4, first);
+    if ((rc = run_frame(ctx, ws, a, lv2, cam, lights, n_lights, rgba, dbg, st, fo, true, grad, nullptr, nullptr, nullptr,
+                        views, &tp)))
+        return rc;
+    for (int i = 0; i < 4; ++i) fo->ms[i] += first[i];   // both passes count
     return HAIR_OK;
 }
 
@@ -1230,8 +1289,11 @@ int hair_render(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t level, const 
     ws = ws_or_default(ctx, ws);
     std::lock_guard<std::mutex> g(ws->mu);
     FrameOut fo;
-    if ((rc = run_frame(ctx, ws, *a, lv, cam, lights, n_lights, rgba_out, nullptr, (hipStream_t)stream, &fo))) return rc;
-    if (stats) fill_stats(stats, fo, (uint32_t)lv.nseg);
+    uint32_t nrows = 0;
+    if ((rc = level_frame(ctx, ws, *a, lv, cam, lights, n_lights, rgba_out, nullptr, (hipStream_t)stream, &fo, nullptr,
+                          nullptr, &nrows)))
+        return rc;
+    if (stats) fill_stats(stats, fo, nrows);
     if (fo.ctr.list_overflow) return fail(HAIR_ERANGE, "%u tiles hold more than 2^24 segments", fo.ctr.list_overflow);
     if (fo.ctr.overflow_pixels)
         return fail(HAIR_ERANGE, "%u pixels hold more than %d fragments at one depth key (left transparent)",
@@ -1348,7 +1410,17 @@ int hair_ws_finish(hair_ws* ws, hair_stats* stats) {
         }
     }
     pd.active = false;
-    if (stats) fill_stats(stats, fo, (uint32_t)lv.nseg);
+    uint32_t nrows = (uint32_t)lv.nseg;
+    if (fo.ctr.split_needed && !ws->arena) {   // long segments: the frame again, with pieces
+        TessPass tp;
+        LevelDev lv2;
+        if ((rc = split_rows(ctx, ws, lv, &pd.cam, pd.st, &tp, &lv2))) return rc;
+        if ((rc = run_frame(ctx, ws, *a, lv2, &pd.cam, pd.lights.data(), (int)pd.lights.size(), pd.rgba, nullptr,
+                            pd.st, &fo, true, nullptr, nullptr, nullptr, nullptr, nullptr, &tp)))
+            return rc;
+        nrows = (uint32_t)lv2.nseg;
+    }
+    if (stats) fill_stats(stats, fo, nrows);
     if (fo.ctr.list_overflow) return fail(HAIR_ERANGE, "%u tiles hold more than 2^24 segments", fo.ctr.list_overflow);
     if (fo.ctr.overflow_pixels)
         return fail(HAIR_ERANGE, "%u pixels hold more than %d fragments at one depth key (left transparent)",
@@ -1450,11 +1522,11 @@ int hair_render_shadowed(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t leve
     float ms_dom = 0.0f;
     if ((rc = shadow_passes(ctx, ws, *a, lv, nullptr, cam, lights, n_lights, shadow, st, views, &ms_dom))) return rc;
     FrameOut fo;
-    if ((rc = run_frame(ctx, ws, *a, lv, cam, lights, n_lights, rgba_out, nullptr, st, &fo, true, nullptr, nullptr,
-                        nullptr, nullptr, views)))
+    uint32_t nrows = 0;
+    if ((rc = level_frame(ctx, ws, *a, lv, cam, lights, n_lights, rgba_out, nullptr, st, &fo, nullptr, views, &nrows)))
         return rc;
     if (stats) {
-        fill_stats(stats, fo, (uint32_t)lv.nseg);
+        fill_stats(stats, fo, nrows);
         stats->ms_total += ms_dom;
     }
     if (fo.ctr.list_overflow) return fail(HAIR_ERANGE, "%u tiles hold more than 2^24 segments", fo.ctr.list_overflow);
@@ -1689,9 +1761,9 @@ int hair_render_backward(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t leve
     if ((rc = need_device(ctx))) return rc;
     ws = ws_or_default(ctx, ws);
     std::lock_guard<std::mutex> g(ws->mu);
-    GradOut grad{d_rgba, d_axes, d_r, d_sigma_a};
+    GradOut grad{d_rgba, d_axes, d_r, d_sigma_a, nullptr};
     FrameOut fo;
-    if ((rc = run_frame(ctx, ws, *a, lv, cam, lights, n_lights, nullptr, nullptr, (hipStream_t)stream, &fo, true, &grad)))
+    if ((rc = level_frame(ctx, ws, *a, lv, cam, lights, n_lights, nullptr, nullptr, (hipStream_t)stream, &fo, &grad)))
         return rc;
     if (fo.ctr.overflow_pixels)
         return fail(HAIR_ERANGE, "%u pixels need more than 64 slices of %d fragments (their gradient is missing)",
@@ -1791,7 +1863,7 @@ int hair_debug_fragments(hair_ctx* ctx, hair_ws* ws, int32_t asset, int32_t leve
     DebugDump dbg{x0, y0, w, h, stride, dc.as<uint32_t>(), dk.as<uint32_t>(), ds.as<uint32_t>(), da.as<float>(),
                   dh.as<float>()};
     FrameOut fo;
-    rc = run_frame(ctx, ws, *a, lv, cam, lights, n_lights, img.as<float>(), &dbg, (hipStream_t)stream, &fo);
+    rc = level_frame(ctx, ws, *a, lv, cam, lights, n_lights, img.as<float>(), &dbg, (hipStream_t)stream, &fo);
     if (rc) {
         cleanup();
         return rc;

@@ -12,8 +12,10 @@ constexpr int kTile = HAIR_TILE;                 // tile edge in pixels
 constexpr int kTilePix = kTile * kTile;          // pixels per tile = threads per tile block
 constexpr int kCap = HAIR_PIXEL_CAPACITY;        // fragments per LDS batch
 constexpr int kGuard = 16384;                    // guard band, 1/16-px units (1024 px)
-constexpr int kMaxAxis = 16384;                  // longest segment extent per axis (1/16 px)
-constexpr int kMaxHwFx = 4096;                   // widest coverage half-width (1/16 px)
+constexpr int kMaxAxis = 16384;                  // longest segment (or piece) extent per axis (1/16 px)
+constexpr int kMaxHwFx = 32768;                  // widest coverage half-width (1/16 px)
+constexpr int kSplitLen = 16000;                 // a longer segment is drawn as pieces of at most this extent
+constexpr int kMaxPieces = 64;                   // pieces per segment (row = segment << 6 | piece)
 constexpr int kMaxListLen = (1 << 24) - 1;       // per-tile list limit (24-bit local index)
 constexpr int kBinThreads = 512;                 // threads per binning block
 constexpr int kMaxLdsTiles = 36864;              // per-tile LDS counters of one binning pass (144 KiB)
@@ -40,6 +42,7 @@ constexpr int32_t kFlagVisible = 1 << 16;
 constexpr int32_t kFlagNegSide = 1 << 17;        // h > 0 lies on the e x d < 0 side
 constexpr int32_t kFlagCulledLong = 1 << 18;
 constexpr int32_t kFlagThick = 1 << 19;          // mixed frames: a thick-hair segment
+constexpr int32_t kFlagSplit = 1 << 20;          // culled as longer than kMaxAxis, both endpoints on the guard band
 constexpr int32_t kHwMask = 0xFFFF;
 
 struct CamConst {
@@ -146,6 +149,7 @@ struct Counters {
     uint32_t list_overflow;  // tiles whose list exceeded the 24-bit local index
     uint32_t deep_pixels;    // pixels deeper than one LDS batch (rendered in depth-key slices)
     uint32_t cap_overflow;   // a frame size exceeded its buffer: the later passes did nothing
+    uint32_t split_needed;   // segments culled as too long that pieces can draw (the frame is drawn again)
     uint32_t sizes[4];       // list entries, work items, fragments, batches of the frame
     unsigned long long phase[8];  // per-phase cycle sums (instrumented builds only)
 };
@@ -172,6 +176,7 @@ struct GradOut {
     float* d_axes;           // [nseg][2]
     float* d_r;              // [K]
     float* d_sig;            // [3][K]
+    const uint32_t* rows;    // a frame of pieces: row -> segment << 6 | piece (nullptr: rows are segments)
 };
 
 // Device buffers of one frame's tile pipeline (T tiles of kTilePix pixels).
@@ -263,6 +268,11 @@ hipError_t launch_build_ellipses(const float* vx, const float* vy, const float* 
 hipError_t launch_tess(const LevelDev& lv, const CamConst& cam, int32_t max_px, int32_t max_sub, uint32_t* cnt,
                        uint32_t* start, uint32_t* scan_tmp, hipStream_t st);
 hipError_t launch_tess_fill(const uint32_t* cnt, const uint32_t* start, int32_t nseg, uint32_t* rows, hipStream_t st);
+hipError_t launch_split(const LevelDev& lv, const CamConst& cam, uint32_t* cnt, uint32_t* start, uint32_t* scan_tmp,
+                        hipStream_t st);
+hipError_t launch_split_fill(const uint32_t* cnt, const uint32_t* start, int32_t nseg, uint32_t* rows, hipStream_t st);
+hipError_t launch_project_split(const LevelDev& lv, const uint32_t* rows, int32_t nrows, const uint32_t* cnt,
+                                const CamConst& cam, SegRec* seg, ShadeRec* shade, hipStream_t st);
 hipError_t launch_project_tess(const LevelDev& lv, const uint32_t* rows, int32_t nrows, const uint32_t* cnt,
                                const CamConst& cam, SegRec* seg, ShadeRec* shade, hipStream_t st);
 // Deep opacity map: the grid of one light from the level's bounds (part: 5 floats per bounds

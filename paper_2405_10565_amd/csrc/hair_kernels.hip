@@ -207,8 +207,10 @@ __device__ inline SegRec project_segment_at(const LevelDev& lv, int g, float ax,
         r.xb = (int)rintf(B.X16);
         r.yb = (int)rintf(B.Y16);
         const float c16 = ceilf(hw16);
-        if (abs(r.xb - r.xa) > kMaxAxis || abs(r.yb - r.ya) > kMaxAxis || c16 > (float)kMaxHwFx) {
-            r.hwfx = kFlagCulledLong;
+        const bool too_long = abs(r.xb - r.xa) > kMaxAxis || abs(r.yb - r.ya) > kMaxAxis;
+        if (too_long || c16 > (float)kMaxHwFx) {
+            // (a segment too long but not too wide is drawn again as pieces)
+            r.hwfx = kFlagCulledLong | (too_long && c16 <= (float)kMaxHwFx ? kFlagSplit : 0);
         } else {
             r.hwfx = (int)c16 | kFlagVisible;
             // side of the screen normal (dY, -dX) on which h > 0 (toward y^ = u x x^)
@@ -611,7 +613,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const SegRec* __restr
     if (threadIdx.x == 0) s_maxhw = 0;
     __syncthreads();
     const int g0 = blockIdx.x * per_block, g1 = min(nseg, g0 + per_block);
-    uint32_t nvis = 0, nlong = 0, maxhw = 0;
+    uint32_t nvis = 0, nlong = 0, nsplit = 0, maxhw = 0;
     for (int g = g0 + (int)threadIdx.x; g < g1; g += kBinThreads) {
         const SegRec r = seg[g];
         if (r.hwfx & kFlagVisible) {
@@ -619,28 +621,32 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(const SegRec* __restr
             maxhw = max(maxhw, __float_as_uint(r.hw));
         }
         nlong += (r.hwfx & kFlagCulledLong) ? 1u : 0u;
+        nsplit += (r.hwfx & kFlagSplit) ? 1u : 0u;
         for_each_tile_in_range(r, ntx, nty, t0, nt, [&](int l) { atomicAdd(&s_tc[l], 1u); });
     }
     if (t0 == 0) {
         if (maxhw) atomicMax(&s_maxhw, maxhw);
-        uint32_t v = nvis, c = nlong;
+        uint32_t v = nvis, c = nlong, sp = nsplit;
         for (int off = 32; off >= 1; off >>= 1) {
             v += __shfl_xor(v, off);
             c += __shfl_xor(c, off);
+            sp += __shfl_xor(sp, off);
         }
-        __shared__ uint32_t s_v[kBinThreads / 64], s_c[kBinThreads / 64];
+        __shared__ uint32_t s_v[kBinThreads / 64], s_c[kBinThreads / 64], s_sp[kBinThreads / 64];
         if ((threadIdx.x & 63) == 0) {
             s_v[threadIdx.x >> 6] = v;
             s_c[threadIdx.x >> 6] = c;
+            s_sp[threadIdx.x >> 6] = sp;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            uint32_t tv = 0, tc = 0;
+            uint32_t tv = 0, tc = 0, ts = 0;
             for (int w = 0; w < kBinThreads / 64; ++w) {
                 tv += s_v[w];
                 tc += s_c[w];
+                ts += s_sp[w];
             }
-            blk[blockIdx.x] = make_uint4(tv, tc, s_maxhw, 0u);
+            blk[blockIdx.x] = make_uint4(tv, tc, s_maxhw, ts);
         }
     }
     __syncthreads();
@@ -682,22 +688,25 @@ __global__ __launch_bounds__(1024) void k_bin_offsets(uint32_t* __restrict__ M, 
         if (w == 0) tot[t] = total;
     }
     if (blockIdx.x == 0 && w == 0) {
-        uint32_t v = 0, c = 0, m = 0;
+        uint32_t v = 0, c = 0, m = 0, sp = 0;
         for (int b = lane; b < nb; b += 64) {
             const uint4 x = blk[b];
             v += x.x;
             c += x.y;
             m = max(m, x.z);
+            sp += x.w;
         }
         for (int off = 32; off >= 1; off >>= 1) {
             v += __shfl_xor(v, off);
             c += __shfl_xor(c, off);
             m = max(m, (uint32_t)__shfl_xor((int)m, off));
+            sp += __shfl_xor(sp, off);
         }
         if (lane == 0) {
             ctr->visible = v;
             ctr->culled_long = c;
             ctr->max_hw_bits = m;
+            ctr->split_needed = sp;
         }
     }
 }
@@ -2243,9 +2252,10 @@ __global__ __launch_bounds__(kNT) void k_batch_bwd(FrameBufs f, ShadeArgs a, Gra
 #pragma unroll
                 for (int m = 0; m < 6; ++m) atomicAdd(&s_acc[m * kNAcc + j], gp[m]);
             } else {
-                const int owner = (int)gseg / S;
-                atomicAdd(&g.d_axes[2 * gseg], gp[0]);
-                atomicAdd(&g.d_axes[2 * gseg + 1], gp[1]);
+                const uint32_t par = g.rows ? g.rows[gseg] >> 6 : gseg;   // a piece's segment
+                const int owner = (int)par / S;
+                atomicAdd(&g.d_axes[2 * par], gp[0]);
+                atomicAdd(&g.d_axes[2 * par + 1], gp[1]);
                 atomicAdd(&g.d_r[owner], gp[2]);
                 atomicAdd(&g.d_sig[owner], gp[3]);
                 atomicAdd(&g.d_sig[K + owner], gp[4]);
@@ -2381,9 +2391,10 @@ __global__ __launch_bounds__(kNT) void k_batch_bwd(FrameBufs f, ShadeArgs a, Gra
         }
         if (!any) continue;
         const uint32_t gseg = list[j];
-        const int owner = (int)gseg / S;
-        atomicAdd(&g.d_axes[2 * gseg], v[0]);
-        atomicAdd(&g.d_axes[2 * gseg + 1], v[1]);
+        const uint32_t par = g.rows ? g.rows[gseg] >> 6 : gseg;
+        const int owner = (int)par / S;
+        atomicAdd(&g.d_axes[2 * par], v[0]);
+        atomicAdd(&g.d_axes[2 * par + 1], v[1]);
         atomicAdd(&g.d_r[owner], v[2]);
         atomicAdd(&g.d_sig[owner], v[3]);
         atomicAdd(&g.d_sig[K + owner], v[4]);
@@ -2565,6 +2576,79 @@ __global__ __launch_bounds__(256) void k_project_tess(LevelDev lv, const uint32_
     spline_point(lv, owner, k, (float)j / (float)m, ax, ay, az);
     spline_point(lv, owner, k, (float)(j + 1) / (float)m, bx, by, bz);
     seg[r] = project_segment_at(lv, g, ax, ay, az, bx, by, bz, cam, shade + r);
+}
+
+// ---------------------------------------------------------------------------------------
+// Long segments (an axis extent above kMaxAxis sub-pixels, both endpoints on the guard band)
+// are drawn as m = min(ceil(extent / kSplitLen), kMaxPieces) pieces of equal screen parameter:
+// piece j runs between the world points of screen parameters j / m and (j + 1) / m, found
+// with the perspective-correct parameter t_w = s izB / (izA + s (izB - izA)) in float32 (one
+// rounding per operation) and exact at s = 0 and 1.  A piece keeps its segment's attributes.
+__global__ __launch_bounds__(256) void k_split_count(LevelDev lv, CamConst cam, uint32_t* __restrict__ cnt) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= lv.nseg) return;
+    const int owner = g / lv.S, k = g - owner * lv.S;
+    const int va = owner * (lv.S + 1) + k;
+    const PPoint A = project_point(cam, lv.vx[va], lv.vy[va], lv.vz[va]);
+    const PPoint B = project_point(cam, lv.vx[va + 1], lv.vy[va + 1], lv.vz[va + 1]);
+    int m = 1;
+    if (A.ok && B.ok) {
+        const int dx = abs((int)rintf(B.X16) - (int)rintf(A.X16)), dy = abs((int)rintf(B.Y16) - (int)rintf(A.Y16));
+        const int ext = max(dx, dy);
+        if (ext > kMaxAxis) m = min((ext + kSplitLen - 1) / kSplitLen, kMaxPieces);
+    }
+    cnt[g] = (uint32_t)m;
+}
+
+// Row list: g << 6 | j for the m pieces j of every segment g, at start[g].
+__global__ __launch_bounds__(256) void k_split_fill(const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ start,
+                                                    int nseg, uint32_t* __restrict__ rows) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nseg) return;
+    const uint32_t m = cnt[g], o = start[g];
+    for (uint32_t j = 0; j < m; ++j) rows[o + j] = ((uint32_t)g << 6) | j;
+}
+
+__device__ inline void split_point(float ax, float ay, float az, float bx, float by, float bz, float izA, float izB,
+                                   int j, int m, float& x, float& y, float& z) {
+    if (j == 0) { x = ax; y = ay; z = az; return; }
+    if (j == m) { x = bx; y = by; z = bz; return; }
+    const float s = (float)j / (float)m;
+    const float iz = izA + s * (izB - izA);
+    const float tw = (s * izB) / iz;
+    x = ax + tw * (bx - ax);
+    y = ay + tw * (by - ay);
+    z = az + tw * (bz - az);
+}
+
+// Row r: piece j of segment g (a whole segment when it has one piece), with segment g's
+// attributes; strand levels write the packed strand shading record.
+__global__ __launch_bounds__(256) void k_project_split(LevelDev lv, const uint32_t* __restrict__ rows, int nrows,
+                                                       const uint32_t* __restrict__ cnt, CamConst cam,
+                                                       SegRec* __restrict__ seg, ShadeRec* __restrict__ shade) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    const uint32_t e = rows[r];
+    const int g = (int)(e >> 6), j = (int)(e & 63u);
+    const int m = (int)cnt[g];
+    ShadeRec sr;
+    sr.q3 = make_float4(0.f, 0.f, 0.f, 0.f);
+    SegRec rec;
+    if (m == 1) {
+        rec = project_segment(lv, g, cam, &sr, lv.kind == 0);
+    } else {
+        const int owner = g / lv.S, k = g - owner * lv.S;
+        const int va = owner * (lv.S + 1) + k;
+        const float ax = lv.vx[va], ay = lv.vy[va], az = lv.vz[va];
+        const float bx = lv.vx[va + 1], by = lv.vy[va + 1], bz = lv.vz[va + 1];
+        const PPoint A = project_point(cam, ax, ay, az), B = project_point(cam, bx, by, bz);
+        float p0x, p0y, p0z, p1x, p1y, p1z;
+        split_point(ax, ay, az, bx, by, bz, A.iz, B.iz, j, m, p0x, p0y, p0z);
+        split_point(ax, ay, az, bx, by, bz, A.iz, B.iz, j + 1, m, p1x, p1y, p1z);
+        rec = project_segment_at(lv, g, p0x, p0y, p0z, p1x, p1y, p1z, cam, &sr, lv.kind == 0);
+    }
+    seg[r] = rec;
+    shade[r] = sr;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -2849,6 +2933,29 @@ hipError_t launch_tess(const LevelDev& lv, const CamConst& cam, int32_t max_px, 
 hipError_t launch_tess_fill(const uint32_t* cnt, const uint32_t* start, int32_t nseg, uint32_t* rows, hipStream_t st) {
     if (nseg == 0) return hipSuccess;
     hipLaunchKernelGGL(k_tess_fill, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, cnt, start, nseg, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_split(const LevelDev& lv, const CamConst& cam, uint32_t* cnt, uint32_t* start, uint32_t* scan_tmp,
+                        hipStream_t st) {
+    if (lv.nseg == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_split_count, dim3(blocks_for(lv.nseg, 256)), dim3(256), 0, st, lv, cam, cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_exscan(cnt, start, lv.nseg, scan_tmp, st);
+}
+
+hipError_t launch_split_fill(const uint32_t* cnt, const uint32_t* start, int32_t nseg, uint32_t* rows, hipStream_t st) {
+    if (nseg == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_split_fill, dim3(blocks_for(nseg, 256)), dim3(256), 0, st, cnt, start, nseg, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_split(const LevelDev& lv, const uint32_t* rows, int32_t nrows, const uint32_t* cnt,
+                                const CamConst& cam, SegRec* seg, ShadeRec* shade, hipStream_t st) {
+    if (nrows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_project_split, dim3(blocks_for(nrows, 256)), dim3(256), 0, st, lv, rows, nrows, cnt, cam, seg,
+                       shade);
     return hipGetLastError();
 }
 
