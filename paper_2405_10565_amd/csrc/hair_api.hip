@@ -109,6 +109,7 @@ struct hair_ws {
     uint64_t max_bytes = 0;
     uint64_t held = 0;
     DevBuf seg, shade, scan_tmp, tile_cnt, tile_start, bin_m, bin_blk, list, ctr, sel_cnt, sel_start, sel, sel_tmp;
+    DevBuf pieces;                            // rows of a frame drawn with long segments as pieces
     DevBuf items, item_start, item_base, pix_cnt, pix_kmin, pix_kmax, pix_off;
     DevBuf tile_tot, frag_base, tile_nb, batch_mask, batch_start, batches, frags;
     DevBuf dom_tex, dom_grid, dom_part;      // shadow pass: texels, grids, bounds partials
@@ -190,12 +191,12 @@ void ctx_free(hair_ctx* ctx, DevBuf& b, hair_ws* ws = nullptr) {
 }
 
 // Every device buffer a workspace can hold.
-std::array<DevBuf*, 30> ws_buffers(hair_ws* ws) {
+std::array<DevBuf*, 31> ws_buffers(hair_ws* ws) {
     return {{&ws->seg, &ws->shade, &ws->scan_tmp, &ws->tile_cnt, &ws->tile_start, &ws->bin_m, &ws->bin_blk,
             &ws->sel_cnt, &ws->sel_start, &ws->sel, &ws->sel_tmp, &ws->list, &ws->ctr, &ws->items,
             &ws->item_start, &ws->item_base, &ws->pix_cnt, &ws->pix_kmin, &ws->pix_kmax, &ws->pix_off,
             &ws->tile_tot, &ws->frag_base, &ws->tile_nb, &ws->batch_mask, &ws->batch_start, &ws->batches,
-            &ws->frags, &ws->dom_tex, &ws->dom_grid, &ws->dom_part}};
+            &ws->frags, &ws->dom_tex, &ws->dom_grid, &ws->dom_part, &ws->pieces}};
 }
 
 // A buffer carved from a static-scratch workspace (256-byte aligned, no headroom).
@@ -533,7 +534,11 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     uint32_t* scan_tmp = ws->scan_tmp.as<uint32_t>();
     HIP_TRY(ctx, hipEventRecord(ws->ev[0], st), "hipEventRecord");
     HIP_TRY(ctx, launch_fill_u32(ws->ctr.as<uint32_t>(), 0u, sizeof(Counters) / 4, st), "fill");
-    if (hier)
+    if (hier && tess && tess->split)
+        HIP_TRY(ctx, launch_project_split_mixed(*hier, sel, tess->rows, lv.nseg, tess->cnt, cc, ws->seg.as<SegRec>(),
+                                                ws->shade.as<ShadeRec>(), st),
+                "k_project_split_mixed");
+    else if (hier)
         HIP_TRY(ctx, launch_project_mixed(*hier, sel, lv.nseg, cc, ws->seg.as<SegRec>(), ws->shade.as<ShadeRec>(), st),
                 "k_project_mixed");
     else if (dom)
@@ -698,10 +703,11 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     return HAIR_OK;
 }
 
-// Rows of a frame that draws the level's long segments as pieces (into ws->sel_*), and the
-// pass and level that render them.  Synchronises st once (the row count).
+// Rows of a frame that draws the long segments of a level (or of a mixed frame's rows, hier
+// and sel given) as pieces, in ws->pieces with counts in ws->sel_cnt, and the pass and level
+// that render them.  Synchronises st once (the row count).
 int split_rows(hair_ctx* ctx, hair_ws* ws, const LevelDev& lv, const hair_camera* cam, hipStream_t st, TessPass* tp,
-               LevelDev* lv_out) {
+               LevelDev* lv_out, const HierDev* hier = nullptr, const uint32_t* sel = nullptr) {
     int rc;
     const int n = lv.nseg;
     if ((rc = ws_need(ws, ws->sel_cnt, 4ull * (n + 1))) || (rc = ws_need(ws, ws->sel_start, 4ull * (n + 1))) ||
@@ -709,15 +715,19 @@ int split_rows(hair_ctx* ctx, hair_ws* ws, const LevelDev& lv, const hair_camera
         return rc;
     uint32_t* cnt = ws->sel_cnt.as<uint32_t>();
     uint32_t* start = ws->sel_start.as<uint32_t>();
-    HIP_TRY(ctx, launch_split(lv, cam_const(cam), cnt, start, ws->sel_tmp.as<uint32_t>(), st), "k_split_count");
+    if (hier)
+        HIP_TRY(ctx, launch_split_mixed(*hier, sel, n, cam_const(cam), cnt, start, ws->sel_tmp.as<uint32_t>(), st),
+                "k_split_count_mixed");
+    else
+        HIP_TRY(ctx, launch_split(lv, cam_const(cam), cnt, start, ws->sel_tmp.as<uint32_t>(), st), "k_split_count");
     uint32_t nrows = 0;
     HIP_TRY(ctx, hipMemcpyAsync(&nrows, start + n, 4, hipMemcpyDeviceToHost, st), "copy");
     HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
     if (nrows >= (1u << 26)) return fail(HAIR_ERANGE, "%u pieces: the frame has 2^26 rows or more", nrows);
-    if ((rc = ws_need(ws, ws->sel, 4ull * std::max<uint32_t>(nrows, 1)))) return rc;
-    HIP_TRY(ctx, launch_split_fill(cnt, start, n, ws->sel.as<uint32_t>(), st), "k_split_fill");
+    if ((rc = ws_need(ws, ws->pieces, 4ull * std::max<uint32_t>(nrows, 1)))) return rc;
+    HIP_TRY(ctx, launch_split_fill(cnt, start, n, ws->pieces.as<uint32_t>(), st), "k_split_fill");
     tp->base = lv;
-    tp->rows = ws->sel.as<uint32_t>();
+    tp->rows = ws->pieces.as<uint32_t>();
     tp->cnt = cnt;
     tp->split = true;
     *lv_out = lv;
@@ -725,26 +735,28 @@ int split_rows(hair_ctx* ctx, hair_ws* ws, const LevelDev& lv, const hair_camera
     return HAIR_OK;
 }
 
-// A frame of a level (rendered, shadowed with views, differentiated with grad, or dumped with
-// dbg), drawn again with its long segments as pieces when the first pass found any (those are
-// culled there).  *nseg_out: the rows of the frame that counts.
+// A frame of a level or of a mixed frame's rows (hier and sel) — rendered, shadowed with
+// views, differentiated with grad, or dumped with dbg — drawn again with its long segments
+// as pieces when the first pass found any (those are culled there).  *nseg_out: the rows of
+// the frame that counts.
 int level_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, const hair_camera* cam,
                 const hair_light* lights, int n_lights, float* rgba, const DebugDump* dbg, hipStream_t st,
-                FrameOut* fo, GradOut* grad = nullptr, const DomView* views = nullptr, uint32_t* nseg_out = nullptr) {
+                FrameOut* fo, GradOut* grad = nullptr, const DomView* views = nullptr, uint32_t* nseg_out = nullptr,
+                const HierDev* hier = nullptr, const uint32_t* sel = nullptr) {
     int rc;
-    if ((rc = run_frame(ctx, ws, a, lv, cam, lights, n_lights, rgba, dbg, st, fo, true, grad, nullptr, nullptr, nullptr,
+    if ((rc = run_frame(ctx, ws, a, lv, cam, lights, n_lights, rgba, dbg, st, fo, true, grad, hier, sel, nullptr,
                         views)))
         return rc;
     if (nseg_out) *nseg_out = (uint32_t)lv.nseg;
     if (!fo->ctr.split_needed || ws->arena) return HAIR_OK;
     TessPass tp;
     LevelDev lv2;
-    if ((rc = split_rows(ctx, ws, lv, cam, st, &tp, &lv2))) return rc;
+    if ((rc = split_rows(ctx, ws, lv, cam, st, &tp, &lv2, hier, sel))) return rc;
     if (grad) grad->rows = tp.rows;
     if (nseg_out) *nseg_out = (uint32_t)lv2.nseg;
     float first[4];
     std::copy(fo->ms, fo->ms + 4, first);
-    if ((rc = run_frame(ctx, ws, a, lv2, cam, lights, n_lights, rgba, dbg, st, fo, true, grad, nullptr, nullptr, nullptr,
+    if ((rc = run_frame(ctx, ws, a, lv2, cam, lights, n_lights, rgba, dbg, st, fo, true, grad, hier, sel, nullptr,
                         views, &tp)))
         return rc;
     for (int i = 0; i < 4; ++i) fo->ms[i] += first[i];   // both passes count
@@ -1668,15 +1680,16 @@ static int render_mixed(hair_ctx* ctx, hair_ws* ws, int32_t asset, const hair_ca
             return rc;
     }
     FrameOut fo;
-    if ((rc = run_frame(ctx, ws, *a, lv, cam, lights, n_lights, rgba_out, nullptr, st, &fo, true, nullptr, &h,
-                        ws->sel.as<uint32_t>(), nullptr, shadow ? views : nullptr)))
+    uint32_t nrows = 0;
+    if ((rc = level_frame(ctx, ws, *a, lv, cam, lights, n_lights, rgba_out, nullptr, st, &fo, nullptr,
+                          shadow ? views : nullptr, &nrows, &h, ws->sel.as<uint32_t>())))
         return rc;
     if (eps_w_px > 0) {
         HIP_TRY(ctx, launch_lod_update(h, cam_const(cam), eps_w_px, levels, st), "k_lod_update");
         HIP_TRY(ctx, hipStreamSynchronize(st), "sync");
     }
     if (stats) {
-        fill_stats(stats, fo, nsel);
+        fill_stats(stats, fo, nrows);
         stats->ms_total += ms_dom;
     }
     if (fo.ctr.list_overflow) return fail(HAIR_ERANGE, "%u tiles hold more than 2^24 segments", fo.ctr.list_overflow);

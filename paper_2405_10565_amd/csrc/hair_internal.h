@@ -270,6 +270,11 @@ hipError_t launch_tess(const LevelDev& lv, const CamConst& cam, int32_t max_px, 
 hipError_t launch_tess_fill(const uint32_t* cnt, const uint32_t* start, int32_t nseg, uint32_t* rows, hipStream_t st);
 hipError_t launch_split(const LevelDev& lv, const CamConst& cam, uint32_t* cnt, uint32_t* start, uint32_t* scan_tmp,
                         hipStream_t st);
+hipError_t launch_split_mixed(const HierDev& h, const uint32_t* sel, int32_t nsel, const CamConst& cam, uint32_t* cnt,
+                              uint32_t* start, uint32_t* scan_tmp, hipStream_t st);
+hipError_t launch_project_split_mixed(const HierDev& h, const uint32_t* sel, const uint32_t* rows, int32_t nrows,
+                                      const uint32_t* cnt, const CamConst& cam, SegRec* seg, ShadeRec* shade,
+                                      hipStream_t st);
 hipError_t launch_split_fill(const uint32_t* cnt, const uint32_t* start, int32_t nseg, uint32_t* rows, hipStream_t st);
 hipError_t launch_project_split(const LevelDev& lv, const uint32_t* rows, int32_t nrows, const uint32_t* cnt,
                                 const CamConst& cam, SegRec* seg, ShadeRec* shade, hipStream_t st);

@@ -2042,7 +2042,6 @@ __global__ __launch_bounds__(kNT) void k_batch_bwd(FrameBufs f, ShadeArgs a, Gra
     __shared__ float4 s_sl_agg[kMaxBwdSlices];
     __shared__ float4 s_sl_after[kMaxBwdSlices];        // (C rgb, S) of the slices behind
     __shared__ float s_sl_before[kMaxBwdSlices];         // T of the slices in front
-    __shared__ uint32_t s_nsl;
     uint2* s_A = reinterpret_cast<uint2*>(s_work);
     uint32_t* s_bk = reinterpret_cast<uint32_t*>(s_work) + 2 * kCap;
     float4* s_p4 = reinterpret_cast<float4*>(s_work);
@@ -2584,9 +2583,7 @@ __global__ __launch_bounds__(256) void k_project_tess(LevelDev lv, const uint32_
 // piece j runs between the world points of screen parameters j / m and (j + 1) / m, found
 // with the perspective-correct parameter t_w = s izB / (izA + s (izB - izA)) in float32 (one
 // rounding per operation) and exact at s = 0 and 1.  A piece keeps its segment's attributes.
-__global__ __launch_bounds__(256) void k_split_count(LevelDev lv, CamConst cam, uint32_t* __restrict__ cnt) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= lv.nseg) return;
+__device__ inline uint32_t split_pieces(const LevelDev& lv, int g, const CamConst& cam) {
     const int owner = g / lv.S, k = g - owner * lv.S;
     const int va = owner * (lv.S + 1) + k;
     const PPoint A = project_point(cam, lv.vx[va], lv.vy[va], lv.vz[va]);
@@ -2597,7 +2594,22 @@ __global__ __launch_bounds__(256) void k_split_count(LevelDev lv, CamConst cam, 
         const int ext = max(dx, dy);
         if (ext > kMaxAxis) m = min((ext + kSplitLen - 1) / kSplitLen, kMaxPieces);
     }
-    cnt[g] = (uint32_t)m;
+    return (uint32_t)m;
+}
+
+__global__ __launch_bounds__(256) void k_split_count(LevelDev lv, CamConst cam, uint32_t* __restrict__ cnt) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= lv.nseg) return;
+    cnt[g] = split_pieces(lv, g, cam);
+}
+
+// The same over the rows of a mixed frame (sel[i] = level << 28 | segment of that level).
+__global__ __launch_bounds__(256) void k_split_count_mixed(HierDev h, const uint32_t* __restrict__ sel, int nsel,
+                                                           CamConst cam, uint32_t* __restrict__ cnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsel) return;
+    const uint32_t e = sel[i];
+    cnt[i] = split_pieces(h.lv[e >> 28], (int)(e & 0x0FFFFFFFu), cam);
 }
 
 // Row list: g << 6 | j for the m pieces j of every segment g, at start[g].
@@ -2621,6 +2633,21 @@ __device__ inline void split_point(float ax, float ay, float az, float bx, float
     z = az + tw * (bz - az);
 }
 
+// Piece j of m of segment g of lv (the whole segment when m = 1).
+__device__ inline SegRec project_piece(const LevelDev& lv, int g, int j, int m, const CamConst& cam, ShadeRec* sr,
+                                       bool packed) {
+    if (m == 1) return project_segment(lv, g, cam, sr, packed);
+    const int owner = g / lv.S, k = g - owner * lv.S;
+    const int va = owner * (lv.S + 1) + k;
+    const float ax = lv.vx[va], ay = lv.vy[va], az = lv.vz[va];
+    const float bx = lv.vx[va + 1], by = lv.vy[va + 1], bz = lv.vz[va + 1];
+    const PPoint A = project_point(cam, ax, ay, az), B = project_point(cam, bx, by, bz);
+    float p0x, p0y, p0z, p1x, p1y, p1z;
+    split_point(ax, ay, az, bx, by, bz, A.iz, B.iz, j, m, p0x, p0y, p0z);
+    split_point(ax, ay, az, bx, by, bz, A.iz, B.iz, j + 1, m, p1x, p1y, p1z);
+    return project_segment_at(lv, g, p0x, p0y, p0z, p1x, p1y, p1z, cam, sr, packed);
+}
+
 // Row r: piece j of segment g (a whole segment when it has one piece), with segment g's
 // attributes; strand levels write the packed strand shading record.
 __global__ __launch_bounds__(256) void k_project_split(LevelDev lv, const uint32_t* __restrict__ rows, int nrows,
@@ -2630,25 +2657,28 @@ __global__ __launch_bounds__(256) void k_project_split(LevelDev lv, const uint32
     if (r >= nrows) return;
     const uint32_t e = rows[r];
     const int g = (int)(e >> 6), j = (int)(e & 63u);
-    const int m = (int)cnt[g];
     ShadeRec sr;
     sr.q3 = make_float4(0.f, 0.f, 0.f, 0.f);
-    SegRec rec;
-    if (m == 1) {
-        rec = project_segment(lv, g, cam, &sr, lv.kind == 0);
-    } else {
-        const int owner = g / lv.S, k = g - owner * lv.S;
-        const int va = owner * (lv.S + 1) + k;
-        const float ax = lv.vx[va], ay = lv.vy[va], az = lv.vz[va];
-        const float bx = lv.vx[va + 1], by = lv.vy[va + 1], bz = lv.vz[va + 1];
-        const PPoint A = project_point(cam, ax, ay, az), B = project_point(cam, bx, by, bz);
-        float p0x, p0y, p0z, p1x, p1y, p1z;
-        split_point(ax, ay, az, bx, by, bz, A.iz, B.iz, j, m, p0x, p0y, p0z);
-        split_point(ax, ay, az, bx, by, bz, A.iz, B.iz, j + 1, m, p1x, p1y, p1z);
-        rec = project_segment_at(lv, g, p0x, p0y, p0z, p1x, p1y, p1z, cam, &sr, lv.kind == 0);
-    }
-    seg[r] = rec;
+    seg[r] = project_piece(lv, g, j, (int)cnt[g], cam, &sr, lv.kind == 0);
     shade[r] = sr;
+}
+
+// Row r of a mixed frame drawn in pieces: piece j of selection row i (rows[r] = i << 6 | j),
+// with the record layout of k_project_mixed.
+__global__ __launch_bounds__(256) void k_project_split_mixed(HierDev h, const uint32_t* __restrict__ sel,
+                                                             const uint32_t* __restrict__ rows, int nrows,
+                                                             const uint32_t* __restrict__ cnt, CamConst cam,
+                                                             SegRec* __restrict__ seg, ShadeRec* __restrict__ shade) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    const uint32_t e = rows[r];
+    const int i = (int)(e >> 6), j = (int)(e & 63u);
+    const uint32_t s = sel[i];
+    const int L = (int)(s >> 28), g = (int)(s & 0x0FFFFFFFu);
+    SegRec rec = project_piece(h.lv[L], g, j, (int)cnt[i], cam, shade + r, false);
+    if (h.lv[L].kind == 1) rec.hwfx |= kFlagThick;
+    else shade[r].q3 = make_float4(0.5f * h.lv[L].width[g / h.lv[L].S], 0.0f, 0.0f, -1.0f);
+    seg[r] = rec;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -2943,6 +2973,24 @@ hipError_t launch_split(const LevelDev& lv, const CamConst& cam, uint32_t* cnt, 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_exscan(cnt, start, lv.nseg, scan_tmp, st);
+}
+
+hipError_t launch_split_mixed(const HierDev& h, const uint32_t* sel, int32_t nsel, const CamConst& cam, uint32_t* cnt,
+                              uint32_t* start, uint32_t* scan_tmp, hipStream_t st) {
+    if (nsel == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_split_count_mixed, dim3(blocks_for(nsel, 256)), dim3(256), 0, st, h, sel, nsel, cam, cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_exscan(cnt, start, nsel, scan_tmp, st);
+}
+
+hipError_t launch_project_split_mixed(const HierDev& h, const uint32_t* sel, const uint32_t* rows, int32_t nrows,
+                                      const uint32_t* cnt, const CamConst& cam, SegRec* seg, ShadeRec* shade,
+                                      hipStream_t st) {
+    if (nrows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_project_split_mixed, dim3(blocks_for(nrows, 256)), dim3(256), 0, st, h, sel, rows, nrows, cnt,
+                       cam, seg, shade);
+    return hipGetLastError();
 }
 
 hipError_t launch_split_fill(const uint32_t* cnt, const uint32_t* start, int32_t nseg, uint32_t* rows, hipStream_t st) {

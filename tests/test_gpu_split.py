@@ -3,13 +3,16 @@ of equal screen parameter (projection step, Sec. 5.2) instead of being culled.  
 strands up to ~2700 px long and thick hairs longer than 1024 px and wider than 256 px in
 half-width: the piece records are bit-exact against the oracle's split geometry, the fragment
 count is the oracle's, the radiance matches it within 1e-4, no segment is culled for its
-size, and the backward pass of the wide thick hairs matches the oracle's autograd gradient."""
+size, and the backward pass of the wide thick hairs matches the oracle's autograd gradient;
+mixed-level frames (plain and shadowed) whose every row is drawn in pieces match the oracle."""
 import numpy as np
 import pytest
 import torch
 
 import hairsynth as hs
 from oracle import grad as OG
+from oracle import lod as OL
+from oracle import mixed as M
 from oracle import render as R
 
 pytestmark = pytest.mark.gpu
@@ -96,7 +99,10 @@ def _radiance(got, ref, what, hw_max):
     up to 2 hw + 1 px and each a few float32 roundings in the kernel, so a fragment's alpha
     carries up to about 8 ulp(1) (2 hw_max + 1) of absolute error, scaled by the radiance."""
     got = np.asarray(got, np.float64)
-    atol = ATOL + 8 * 2.0 ** -24 * (2 * float(hw_max) + 1) * max(1.0, float(np.abs(ref).max()))
+    hw_max = np.asarray(hw_max, np.float64)
+    if hw_max.ndim == 2:                     # per pixel: the widest fragment there
+        hw_max = hw_max[..., None]
+    atol = ATOL + 8 * 2.0 ** -24 * (2 * hw_max + 1) * max(1.0, float(np.abs(ref).max()))
     err = np.abs(got - ref) - (RTOL * np.abs(ref) + atol)
     bad = int((err > 0).sum())
     print(f"[{what}] violations {bad} of {ref.size}", flush=True)
@@ -225,3 +231,66 @@ def test_long_wide_thick_hairs_backward(hip, ctx):
     _close(dr.cpu().numpy(), g_r, "d_r")
     _close(ds.cpu().numpy(), g_sig, "d_sigma_a")
     ctx.release(aid)
+
+
+def _curtain(n=240, seed=81):
+    """Straight two-segment strands spanning the image left to right, every segment 1000-1600
+    px long at 3840x2160, receding in depth; widths 60 um to 1 mm."""
+    rng = np.random.default_rng(seed)
+    y = rng.uniform(-0.4, 0.4, n)
+    z = rng.uniform(-0.05, 0.05, n)
+    v0 = np.stack([rng.uniform(-0.85, -0.75, n), y, -1.0 + z], 1)
+    v1 = np.stack([rng.uniform(-0.02, 0.02, n), y + 0.03 * np.sin(7 * y), -1.1 + z], 1)
+    v2 = np.stack([rng.uniform(0.75, 0.85, n), y - 0.02, -1.25 + z], 1)
+    pts = np.stack([v0, v1, v2], 1).astype(F32)
+    xyz = np.ascontiguousarray(pts.reshape(3 * n, 3).T)
+    sig = np.ascontiguousarray(rng.uniform(0.2, 1.5, size=(3, n)).astype(F32))
+    return hs.Asset(n, 2, xyz, rng.uniform(60e-6, 1e-3, n).astype(F32), sig)
+
+
+@pytest.fixture(scope="module")
+def curtain(hip, ctx):
+    asset = _curtain()
+    assigns = hs.kmeans_hierarchy(asset, (40, 10, 3), seed=81)
+    aid = ctx.upload_asset(asset)
+    ctx.build_lod(aid, assigns)
+    lods = [OL.build_level(asset, a) for a in assigns]
+    for l, lod in enumerate(lods, 1):
+        ctx.set_lod(aid, l, lod)
+    geoms = M.level_geoms(asset, lods)
+    yield asset, aid, geoms, M.groups(assigns)
+    ctx.release(aid)
+
+
+def _hw_per_pixel(ras):
+    out = np.zeros(W * H)
+    np.maximum.at(out, ras.pix, ras.hw[ras.seg].astype(np.float64))
+    return out.reshape(H, W)
+
+
+@pytest.mark.parametrize("shadow", [None, (128, 4, 0.02)])
+def test_mixed_frame_drawn_as_pieces(hip, ctx, curtain, shadow):
+    print(f"case: mixed frame of long rows at 3840x2160, shadow {shadow}", flush=True)
+    asset, aid, geoms, grps = curtain
+    cam = _camera()
+    lights = _lights_for(asset)
+    G, S = ctx.lod_groups(aid), asset.segs
+    levels = np.random.default_rng(82).integers(0, 4, size=(G, S)).astype(np.int32)
+    lev = torch.tensor(levels, device="cuda:0")
+    ws = ctx.workspace()
+    if shadow is None:
+        img, stats, _ = ctx.render_mixed(aid, cam, lights, lev, ws=ws)
+    else:
+        img, stats, _ = ctx.render_mixed_shadowed(aid, cam, lights, lev, shadow=shadow, ws=ws)
+    torch.cuda.synchronize()
+    mixed = M.mixed_geometry(geoms, grps, levels)
+    assert len(np.unique(levels)) >= 3 and mixed.thick.any() and not mixed.thick.all()
+    sp, _ = _check_rows(ctx, ws, mixed, cam, stats, "mixed rows")
+    ri, _ = ctx.debug_segments(ws, sp.pA.shape[1])
+    assert np.array_equal((ri[:, 5] & 8) != 0, sp.thick)
+    assert stats["segments_culled_long"] == 0
+    ref, ras = R.render(mixed, cam, lights, tuple(float(v) for v in asset.material.as_array()), shadow=shadow)
+    print(f"mixed pieces: {stats['fragments']} fragments, oracle {len(ras.seg)}", flush=True)
+    assert stats["fragments"] == len(ras.seg)
+    _radiance(img.cpu().numpy(), ref, f"mixed frame in pieces, shadow {shadow}", _hw_per_pixel(ras))
+    ws.close()
