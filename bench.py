@@ -124,6 +124,50 @@ def cpu_baseline(asset, cam, lights, rows: int = 48):
                       f"{dt:.1f} s wall, torch/numpy float64 on 1 thread)"}
 
 
+def _oracle_band(y0: int, rows: int, t_start: float):
+    """Worker of cpu_baseline_multicore: the oracle on rows [y0, y0 + rows) of the headline
+    frame, single-threaded, starting at wall time t_start (after imports and set-up)."""
+    import torch
+    torch.set_num_threads(1)
+    import hairsynth as hs
+    from oracle import render as R
+    asset, cam, lights = hs.config(2)
+    geom = R.strand_level(asset)
+    mat = tuple(float(v) for v in asset.material.as_array())
+    while time.time() < t_start:
+        time.sleep(0.01)
+    t0 = time.time()
+    _, ras = R.render(geom, cam, lights, mat, rect=(0, y0, cam.width, rows))
+    print(json.dumps({"y0": y0, "fragments": int(len(ras.seg)), "t0": t0, "t1": time.time()}), flush=True)
+
+
+def cpu_baseline_multicore(rows: int = 48, max_workers: int = 16):
+    """The oracle on host cores in parallel: one single-threaded process per band of `rows`
+    rows around the frame's centre (as many bands as workers), all starting together; the
+    rate is their fragments over the wall time from the common start to the last finish."""
+    import subprocess
+    n = max(1, min(max_workers, len(os.sched_getaffinity(0))))
+    H = 1080
+    y_first = H // 2 - (n * rows) // 2
+    t_start = time.time() + 30.0 + 2.0 * n        # room for every worker's imports and set-up
+    procs = [subprocess.Popen([sys.executable, "-c",
+                               f"import sys; sys.path.insert(0, {ROOT!r}); import bench; "
+                               f"bench._oracle_band({y_first + i * rows}, {rows}, {t_start})"],
+                              stdout=subprocess.PIPE, text=True, cwd=ROOT) for i in range(n)]
+    outs = []
+    for p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError(f"oracle worker failed with status {p.returncode}")
+        outs.append(json.loads(out.strip().splitlines()[-1]))
+    frags = sum(o["fragments"] for o in outs)
+    wall = max(o["t1"] for o in outs) - min(o["t0"] for o in outs)
+    return {"value": round(frags / wall / 1e6, 5), "unit": "Mfragments/s", "cores": n, "kind": "oracle",
+            "sample": f"rows {y_first}-{y_first + n * rows - 1} of the 1920x1080 frame in {n} bands of {rows} rows, one "
+                      f"single-threaded oracle process per band ({frags} fragments, {wall:.1f} s wall from the "
+                      f"common start to the last finish)"}
+
+
 def rttd_frame(ctx, asset, cam, lights, ws, frames: int = 20):
     """The same strand frame with the R / TT / D material (outside the timed region)."""
     import dataclasses
@@ -322,6 +366,9 @@ def main():
     ctx.close()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(asset, cam, lights)
+        print("bench: single-core oracle timed", file=sys.stderr, flush=True)
+        res["cpu_baseline_multicore"] = cpu_baseline_multicore()
+        print("bench: multi-core oracle timed", file=sys.stderr, flush=True)
     print(json.dumps(res), flush=True)
 
 
