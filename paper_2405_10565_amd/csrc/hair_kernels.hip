@@ -980,8 +980,6 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
     const int cr = ex * dy - ey * dx;
     // (the coverage decision was taken exactly when the fragment was emitted; what follows is
     // continuous, so it uses the hardware reciprocal and reciprocal square root)
-    const float t = (float)tnum * m_rcp((float)tden);
-    const float iz = s.iza + t * (s.izb - s.iza);
     float delta;
     T d_minus, d_plus;   // delta - hw, delta + hw
     if (KIND == 1) {
@@ -1004,7 +1002,10 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
     if (s.hwfx & kFlagNegSide) sgn = -sgn;
     const T h = m_min(m_max((sgn * delta) * m_rcp(hw + 0.5f), T(-1.0f)), T(1.0f));
     hoff = h;
-    const float tw = t * s.izb * m_rcp(iz);
+    // the world parameter of the fragment's screen parameter t = t_num / t_den: inverse depth is
+    // affine on screen, so t_w = t izB / (izA + t (izB - izA)), here with t_den cleared
+    const float ftn = (float)tnum;
+    const float tw = ftn * s.izb * m_rcp((float)tden * s.iza + ftn * (s.izb - s.iza));
 
     // fibre frame at the fragment's world point
     const V3<float> pA = v3(q0.x, q0.y, q0.z);
@@ -1019,18 +1020,19 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
     // the longitudinal angle from both of its legs: atan2(sin, |w_perp|) stays accurate where
     // asin(sin) loses digits (views and lights close to the fibre axis, where the narrow
     // longitudinal lobes are most sensitive to theta)
-    const float cos_to = m_sqrt(wpn2);
+    float r_wp = m_rsqrt(wpn2);
+    const float cos_to = wpn2 > 0.0f ? wpn2 * r_wp : 0.0f;   // |w_perp|
     const bool degen = wpn2 < 1e-14f;
     if (degen) {  // view along the fibre: any normal direction; phi is set to 0
         const float ax = fabsf(u.x), ay = fabsf(u.y), az = fabsf(u.z);
         V3<float> e = (ax <= ay && ax <= az) ? v3(1.f, 0.f, 0.f) : (ay <= az ? v3(0.f, 1.f, 0.f) : v3(0.f, 0.f, 1.f));
         wp = sub(e, scale(u, dot(e, u)));
         wpn2 = dot(wp, wp);
+        r_wp = m_rsqrt(wpn2);
     }
-    const V3<float> xh = scale(wp, m_rsqrt(wpn2));
+    const V3<float> xh = scale(wp, r_wp);
     const V3<float> yh = cross(u, xh);
     const float sin_to = fminf(fmaxf(dwu, -1.0f), 1.0f);
-    const float to = m_atan2(sin_to, cos_to);
     const T gamma_o = m_asin(h);
     const T cgo = m_sqrt((1.0f - h) * (1.0f + h));
     const T sigl[3] = {sig[0] * kLog2e, sig[1] * kLog2e, sig[2] * kLog2e};
@@ -1066,7 +1068,7 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
             E[0] = lc.rgb[0] * i2; E[1] = lc.rgb[1] * i2; E[2] = lc.rgb[2] * i2;
         }
         const float sin_ti = dot(wi, u);
-        const LightView v = light_view(sin_ti, sin_to, to, cos_to, dot(wi, xh), dot(wi, yh), degen, a.mat);
+        const LightView v = light_view(sin_ti, sin_to, cos_to, dot(wi, xh), dot(wi, yh), degen, a.mat);
         // hairs between the light and this fragment (shadow pass), added to the forward count
         const float ns = (SHADOW && a.lights.dom[li].grid) ? dom_count(a.lights.dom[li], dpx, dpy, dpz) : 0.0f;
         T f[3];
@@ -1573,7 +1575,6 @@ struct BatchLds {
     uint2* s_B;
     uint2* s_A;
     uint32_t* s_bk;
-    float* s_pay;
     float* s_agg;
     uint32_t* s_aggh;
 };
@@ -1597,7 +1598,6 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
     uint2* s_B = L_.s_B;
     uint2* s_A = L_.s_A;
     uint32_t* s_bk = L_.s_bk;
-    float* s_pay = L_.s_pay;
     float* s_agg = L_.s_agg;
     uint32_t* s_aggh = L_.s_aggh;
     const int t = threadIdx.x;
@@ -1605,44 +1605,68 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
     PHASE_BEGIN();
     order_batch(Fb, rec, s_cnt, s_kmin, s_kmax, s_off, s_tmp, s_A, s_B, s_bk, list);
     PHASE_END(f.ctr, 2);
-    // ---- shade: one lane per fragment, payload alpha * L and (1 - alpha).  A lane's fragments
-    // are i = t, t + kNT, ...: their segment ids are gathered up front (independent loads), and
+    // ---- shade and blend: thread t takes the run [rb, re) of consecutive fragments of the
+    // ordered batch, shades them in order and composites them front to back ("over") as it
+    // goes, restarting at each pixel's first fragment.  A pixel that begins and ends inside
+    // the run is finished there; the run's first pixel, when it began in an earlier run, is
+    // finished after a segmented scan of the runs' open composites gives what lies in front.
+    // The segment ids of a thread's fragments are gathered up front (independent loads) and
     // each fragment's segment inputs are fetched one fragment ahead, so that the gathers
-    // overlap the shading arithmetic instead of stalling it.  (Not for the R / TT / TRT
-    // thick-hair shading: its registers would then exceed the budget of three waves per SIMD.)
+    // overlap the shading arithmetic.  (Not for the R / TT / TRT thick-hair shading: its
+    // registers would then exceed the budget of three waves per SIMD.)
     constexpr bool kAhead = KIND == 0 || MODEL == 1;
+    const uint32_t run = (Fb + kNT - 1) / kNT;   // at most kPerThread
+    const uint32_t rb = min(Fb, t * run), re = min(Fb, rb + run);
     uint32_t gs[kAhead ? kPerThread : 1];
     SegInputs nxt{};
     if (kAhead) {
 #pragma unroll
         for (int j = 0; j < kPerThread; ++j) {
-            const uint32_t i = t + j * kNT;
-            gs[j] = i < Fb ? list[s_B[i].y & 0xFFFFFFu] : 0u;
+            const uint32_t i = rb + j;
+            gs[j] = i < re ? list[s_B[i].y & 0xFFFFFFu] : 0u;
         }
-        if ((uint32_t)t < Fb) nxt = fetch_segment<KIND>(a, gs[0]);
+        if (rb < re) nxt = fetch_segment<KIND>(a, gs[0]);
     }
-    for (uint32_t i = t; i < Fb; i += kNT) {
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;   // the open pixel's composite so far
+    uint32_t head = 0;                             // the open pixel began in this run
+    float H0 = 0.f, H1 = 0.f, H2 = 0.f, HT = 1.f;  // the run's first pixel, begun earlier, ended here
+    int hp = -1;
+    auto finish = [&](int p, float c0, float c1, float c2, float tt) {
+        if (slice_out) {
+            slice_out[0] = c0; slice_out[1] = c1; slice_out[2] = c2; slice_out[3] = tt;
+        } else {
+            const int gx = px0 + (p % kTile), gy = py0 + (p / kTile);
+            if (gx < W && gy < H) reinterpret_cast<float4*>(rgba)[(size_t)gy * W + gx] = make_float4(c0, c1, c2, 1.0f - tt);
+        }
+    };
+    for (uint32_t i = rb; i < re; ++i) {
         if (!kAhead) gs[0] = list[s_B[i].y & 0xFFFFFFu];
         const SegInputs cur = kAhead ? nxt : fetch_segment<KIND>(a, gs[0]);
         const uint32_t gseg = gs[0];
         if (kAhead) {
 #pragma unroll
             for (int j = 0; j + 1 < (kAhead ? kPerThread : 1); ++j) gs[j] = gs[j + 1];
-            if (i + kNT < Fb) nxt = fetch_segment<KIND>(a, gs[0]);
+            if (i + 1 < re) nxt = fetch_segment<KIND>(a, gs[0]);
         }
         const uint2 rec = s_B[i];
         const uint32_t p = rec.y >> 24;
+        const uint32_t p_beg = s_off[p], p_end = s_off[p + 1];
+        if (i == p_beg) { C0 = C1 = C2 = 0.f; T = 1.f; head = 1; }
         const int gx = px0 + (int)(p % kTile), gy = py0 + (int)(p / kTile);
         float al, hh, L[3];
         shade_inputs<KIND, MODEL, SHADOW>(a, cur, gx, gy, al, hh, L);
-        s_pay[3 * i + 0] = al * L[0];
-        s_pay[3 * i + 1] = al * L[1];
-        s_pay[3 * i + 2] = al * L[2];
-        s_B[i].x = __float_as_uint(1.0f - al);
+        C0 += T * (al * L[0]);
+        C1 += T * (al * L[1]);
+        C2 += T * (al * L[2]);
+        T *= 1.0f - al;
+        if (i + 1 == p_end) {
+            if (head) finish((int)p, C0, C1, C2, T);
+            else { H0 = C0; H1 = C1; H2 = C2; HT = T; hp = (int)p; }
+        }
         if (has_dbg) {
             const int dx = gx - dbg.x0, dy = gy - dbg.y0;
             if (dx >= 0 && dy >= 0 && dx < dbg.w && dy < dbg.h) {
-                const uint32_t rank = i - s_off[p] + rank0;
+                const uint32_t rank = i - p_beg + rank0;
                 const int q2 = dy * dbg.w + dx;
                 if (rank == 0) dbg.counts[q2] = cnt_total ? cnt_total : s_cnt[p];
                 if ((int)rank < dbg.stride) {
@@ -1655,24 +1679,10 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
             }
         }
     }
-    __syncthreads();
     PHASE_END(f.ctr, 3);
-    // ---- blend: segmented scan of (C, T) over runs of consecutive fragments.  Runs have odd
-    // length so that the lanes' strided LDS reads fall in distinct banks.
-    const uint32_t run = ((Fb + kNT - 1) / kNT) | 1u;
-    const uint32_t rb = min(Fb, t * run), re = min(Fb, rb + run);
-    float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
-    uint32_t head = 0;
-    for (uint32_t i = rb; i < re; ++i) {
-        const uint32_t p = s_B[i].y >> 24;
-        if (i == s_off[p]) { C0 = C1 = C2 = 0.f; T = 1.f; head = 1; }
-        C0 += T * s_pay[3 * i + 0];
-        C1 += T * s_pay[3 * i + 1];
-        C2 += T * s_pay[3 * i + 2];
-        T *= __uint_as_float(s_B[i].x);
-    }
-    // inclusive scan of the run aggregates, (l) then (r) = r.head ? r : (l.C + l.T r.C, l.T r.T):
-    // within the wave by shuffles, then across the block's waves through LDS
+    // inclusive scan of the runs' open composites, (l) then (r) = r.head ? r : (l.C + l.T r.C,
+    // l.T r.T): within the wave by shuffles, then across the block's waves through LDS; a thread
+    // with no fragments passes its left neighbour's composite through
     const int lane = t & 63, wv = t >> 6;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -1687,12 +1697,14 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
             head = hh2;
         }
     }
+    const float l0 = __shfl_up(C0, 1), l1 = __shfl_up(C1, 1), l2 = __shfl_up(C2, 1), lT = __shfl_up(T, 1);
+    const uint32_t lh = __shfl_up(head, 1);
     if (lane == 63) {
         s_agg[4 * wv + 0] = C0; s_agg[4 * wv + 1] = C1; s_agg[4 * wv + 2] = C2; s_agg[4 * wv + 3] = T;
         s_aggh[wv] = head;
     }
     __syncthreads();
-    {   // exclusive prefix of this thread's run: earlier waves, then earlier lanes of this wave
+    if (hp >= 0) {   // what lies in front of this run: earlier waves, then earlier lanes of this wave
         float e0 = 0.f, e1 = 0.f, e2 = 0.f, eT = 1.f;
         for (int w2 = 0; w2 < wv; ++w2) {
             if (s_aggh[w2]) { e0 = s_agg[4 * w2 + 0]; e1 = s_agg[4 * w2 + 1]; e2 = s_agg[4 * w2 + 2]; eT = s_agg[4 * w2 + 3]; }
@@ -1703,8 +1715,6 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
                 eT = eT * s_agg[4 * w2 + 3];
             }
         }
-        const float l0 = __shfl_up(C0, 1), l1 = __shfl_up(C1, 1), l2 = __shfl_up(C2, 1), lT = __shfl_up(T, 1);
-        const uint32_t lh = __shfl_up(head, 1);
         if (lane > 0) {
             if (lh) { e0 = l0; e1 = l1; e2 = l2; eT = lT; }
             else {
@@ -1714,26 +1724,7 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
                 eT = eT * lT;
             }
         }
-        C0 = e0; C1 = e1; C2 = e2; T = eT;
-    }
-    for (uint32_t i = rb; i < re; ++i) {
-        const uint32_t p = s_B[i].y >> 24;
-        if (i == s_off[p]) { C0 = C1 = C2 = 0.f; T = 1.f; }
-        C0 += T * s_pay[3 * i + 0];
-        C1 += T * s_pay[3 * i + 1];
-        C2 += T * s_pay[3 * i + 2];
-        T *= __uint_as_float(s_B[i].x);
-        if (i + 1 == s_off[p] + s_cnt[p]) {
-            if (slice_out) {
-                slice_out[0] = C0; slice_out[1] = C1; slice_out[2] = C2; slice_out[3] = T;
-            } else {
-                const int gx = px0 + (int)(p % kTile), gy = py0 + (int)(p / kTile);
-                if (gx < W && gy < H) {
-                    float4* o = reinterpret_cast<float4*>(rgba) + ((size_t)gy * W + gx);
-                    *o = make_float4(C0, C1, C2, 1.0f - T);
-                }
-            }
-        }
+        finish(hp, e0 + eT * H0, e1 + eT * H1, e2 + eT * H2, eT * HT);
     }
     PHASE_END(f.ctr, 4);
 }
@@ -1830,14 +1821,14 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 &
     __shared__ uint32_t s_cnt[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix], s_off[kTilePix + 1];
     __shared__ uint32_t s_tmp[kNT];
     __shared__ __align__(16) uint2 s_B[kCap];
-    __shared__ __align__(16) uint32_t s_work[3 * kCap];   // staged records (2 words) + bucket counters, later payload
+    __shared__ __align__(16) uint32_t s_work[3 * kCap];   // staged records (2 words) + bucket counters
     __shared__ float s_agg[kNT / 64 * 4];     // wave aggregates of the blend scan (C rgb, T)
     __shared__ uint32_t s_aggh[kNT / 64];
     __shared__ float s_slice[4];
     __shared__ unsigned long long s_range[2];
     __shared__ uint32_t s_slot, s_flag;
-    BatchLds L_{s_cnt, s_kmin, s_kmax, s_off, s_tmp, s_B, reinterpret_cast<uint2*>(s_work), s_work + 2 * kCap,
-                reinterpret_cast<float*>(s_work), s_agg, s_aggh};
+    BatchLds L_{s_cnt, s_kmin, s_kmax, s_off, s_tmp, s_B, reinterpret_cast<uint2*>(s_work), s_work + 2 * kCap, s_agg,
+                s_aggh};
     PHASE_BEGIN();
 
     const uint32_t n_batches = f.batch_start[f.T];

@@ -141,12 +141,15 @@ template <class T> __device__ inline T periodic_cdf(T x, const MatConst& m) {
     return T(k) + (m_rcp(1.0f + m_exp2(-y * m.inv_s_l2)) - m.cdf_lo) * m.cdf_scale;
 }
 
+// (one reciprocal of the product of the two denominators, both at least cos theta_t > 0)
 template <class T> __device__ inline T fresnel(T cos_i, const MatConst& m) {
     T sin2_t = (1.0f - cos_i * cos_i) * m.inv_eta2;
     T cos_t = m_sqrt(1.0f - sin2_t);
     T ec = m.eta * cos_t, ei = m.eta * cos_i;
-    T rs = (cos_i - ec) * m_rcp(cos_i + ec);
-    T rp = (ei - cos_t) * m_rcp(ei + cos_t);
+    T ds = cos_i + ec, dp = ei + cos_t;
+    T inv = m_rcp(ds * dp);
+    T rs = (cos_i - ec) * dp * inv;
+    T rp = (ei - cos_t) * ds * inv;
     return 0.5f * (rs * rs + rp * rp);
 }
 
@@ -161,27 +164,33 @@ struct LightView {
     float inv_ctt;     // 1 / cos theta_t, sin theta_t = sin x_d / eta
 };
 
-// sin_ti / sin_to: sines of the longitudinal angles; wx, wy: light direction in the normal
-// plane, so that cos theta_i = |(wx, wy)| (taken from the components, not from 1 - sin^2)
-__device__ inline LightView light_view(float sin_ti, float sin_to, float theta_o, float cos_to, float wx, float wy,
-                                       bool degen, const MatConst& m) {
+// sin_ti / sin_to: sines of the longitudinal angles (cos_to = cos theta_o >= 0); wx, wy: light
+// direction in the normal plane, so that cos theta_i = |(wx, wy)| (taken from the components,
+// not from 1 - sin^2).  theta_h = (theta_i + theta_o) / 2 is half the angle whose sine and
+// cosine the sum formulas give (one arctangent per light; theta_o itself is not needed).
+// 1 / eta' = cos x_d / sqrt(eta^2 - sin^2 x_d) and 1 / cos theta_t = eta / sqrt(eta^2 - sin^2 x_d)
+// share their square root.
+__device__ inline LightView light_view(float sin_ti, float sin_to, float cos_to, float wx, float wy, bool degen,
+                                       const MatConst& m) {
     LightView v;
     const float si = fminf(fmaxf(sin_ti, -1.0f), 1.0f);
     const float r2 = wx * wx + wy * wy;
-    const float ci = m_sqrt(r2);
+    const float r_w = m_rsqrt(r2);
+    const float ci = r2 > 0.0f ? r2 * r_w : 0.0f;
     v.cos_ti = ci;
-    v.theta_h = 0.5f * (m_atan2(si, ci) + theta_o);
+    v.theta_h = 0.5f * m_atan2(si * cos_to + ci * sin_to, ci * cos_to - si * sin_to);
     const float c = fminf(fmaxf(ci * cos_to + si * sin_to, -1.0f), 1.0f);   // cos(theta_i - theta_o)
     v.sxd2 = 0.5f * (1.0f - c);
     v.cxd = m_sqrt(0.5f * (1.0f + c));
-    v.inv_eta_p = v.cxd * m_rsqrt(m.eta * m.eta - v.sxd2);
-    v.inv_ctt = m_rsqrt(1.0f - v.sxd2 * m.inv_eta2);
+    const float r_e = m_rsqrt(m.eta * m.eta - v.sxd2);
+    v.inv_eta_p = v.cxd * r_e;
+    v.inv_ctt = m.eta * r_e;
     if (degen || !(r2 > 0.0f)) {
         v.phi = 0.0f;
         v.cos_phi = 1.0f;
     } else {
         v.phi = -m_atan2(wy, wx);
-        v.cos_phi = wx * m_rsqrt(r2);
+        v.cos_phi = wx * r_w;
     }
     return v;
 }
