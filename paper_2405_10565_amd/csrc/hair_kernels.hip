@@ -1423,29 +1423,42 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam) {
     PHASE_END(f.ctr, 1);
 }
 
-// Exact per-pixel order of the Fb records at src (global memory, or LDS that may be s_A) of
-// whole pixels with counts, key ranges and offsets in s_cnt / s_kmin / s_kmax / s_off, into s_B.
-// Bucket sort with one bucket per record, bucket = the record's place in its pixel's linear key
-// range (a monotone map, so sorted buckets give a sorted pixel); the records are scattered to
-// bucket order in s_A, and each record's place inside its bucket is its rank there by
-// (key, segment id), which is unique within a pixel.  s_bk must hold Fb zeros on entry.
-// Ends with a barrier.
+// The bucket map's scale of a pixel of cnt records with keys in [kmin, kmax].
+__device__ inline float bucket_scale(uint32_t cnt, uint32_t kmin, uint32_t kmax) {
+    return (float)cnt * __builtin_amdgcn_rcpf((float)(kmax - kmin) + 1.0f);
+}
+
+// Exact per-pixel order of the Fb records rec (records i = t + qq kNT; entries beyond Fb are
+// ignored) of whole pixels with counts, key minima, bucket scales and offsets in s_cnt /
+// s_kmin / s_scale / s_off, into s_B.  Bucket sort with one bucket per record, bucket = the
+// record's place in its pixel's linear key range (s_scale[p] = count / (key range + 1): a
+// monotone map, so sorted buckets give a sorted pixel); the records are scattered to bucket
+// order in s_A, and each record's place inside its bucket is its rank there by (key, segment
+// id), which is unique within a pixel.  A thread's LDS reads of one step are issued together,
+// and a bucket of up to four records is ranked from one set of reads (larger ones loop).
+// s_bk must hold Fb zeros on entry.  Ends with a barrier.
 __device__ inline void order_batch(uint32_t Fb, const uint2 (&rec)[kPerThread], const uint32_t* s_cnt,
-                                   const uint32_t* s_kmin, const uint32_t* s_kmax, const uint32_t* s_off,
+                                   const uint32_t* s_kmin, const float* s_scale, const uint32_t* s_off,
                                    uint32_t* s_tmp, uint2* s_A, uint2* s_B, uint32_t* s_bk, const uint32_t* list) {
     const int t = threadIdx.x;
     uint32_t my_b[kPerThread], my_r[kPerThread];
+    {
+        uint32_t kmn[kPerThread], cnt[kPerThread], off[kPerThread];
+        float sc[kPerThread];
 #pragma unroll
-    for (int qq = 0; qq < kPerThread; ++qq) {
-        const uint32_t i = t + qq * kNT;
-        if (i < Fb) {
-            const uint32_t p = rec[qq].y >> 24;
-            const uint32_t kmn = s_kmin[p], cnt = s_cnt[p];
-            const float scale = (float)cnt * __builtin_amdgcn_rcpf((float)(s_kmax[p] - kmn) + 1.0f);
-            const uint32_t bucket = min(cnt - 1u, (uint32_t)((float)(rec[qq].x - kmn) * scale));
-            my_b[qq] = s_off[p] + bucket;
-            my_r[qq] = atomicAdd(&s_bk[my_b[qq]], 1u);
+        for (int qq = 0; qq < kPerThread; ++qq) {
+            const uint32_t p = rec[qq].y >> 24;   // (< 256 for any record)
+            kmn[qq] = s_kmin[p];
+            sc[qq] = s_scale[p];
+            off[qq] = s_off[p];
+            cnt[qq] = s_cnt[p];
         }
+#pragma unroll
+        for (int qq = 0; qq < kPerThread; ++qq)
+            my_b[qq] = off[qq] + min(cnt[qq] - 1u, (uint32_t)((float)(rec[qq].x - kmn[qq]) * sc[qq]));
+#pragma unroll
+        for (int qq = 0; qq < kPerThread; ++qq)
+            if (t + qq * kNT < Fb) my_r[qq] = atomicAdd(&s_bk[my_b[qq]], 1u);
     }
     __syncthreads();
     {   // exclusive scan of the bucket counters, kOwn consecutive per thread (odd, so the
@@ -1469,28 +1482,48 @@ __device__ inline void order_batch(uint32_t Fb, const uint2 (&rec)[kPerThread], 
         }
     }
     __syncthreads();
+    uint32_t b0[kPerThread], b1[kPerThread];
 #pragma unroll
     for (int qq = 0; qq < kPerThread; ++qq) {
-        const uint32_t i = t + qq * kNT;
-        if (i < Fb) s_A[s_bk[my_b[qq]] + my_r[qq]] = rec[qq];
+        const bool ok = t + qq * kNT < Fb;
+        b0[qq] = ok ? s_bk[my_b[qq]] : 0u;
+        b1[qq] = ok && my_b[qq] + 1 < Fb ? s_bk[my_b[qq] + 1] : Fb;
     }
-    __syncthreads();
 #pragma unroll
-    for (int qq = 0; qq < kPerThread; ++qq) {
-        const uint32_t i = t + qq * kNT;
-        if (i < Fb) {
-            const uint32_t b0 = s_bk[my_b[qq]];
-            const uint32_t b1 = my_b[qq] + 1 < Fb ? s_bk[my_b[qq] + 1] : Fb;
-            const uint32_t self = b0 + my_r[qq];
-            const uint2 me = s_A[self];
+    for (int qq = 0; qq < kPerThread; ++qq)
+        if (t + qq * kNT < Fb) s_A[b0[qq] + my_r[qq]] = rec[qq];
+    __syncthreads();
+    // ranks, two records at a time (each one's bucket read with independent loads)
+    constexpr uint32_t kSmall = 4;
+    static_assert(kPerThread % 2 == 0, "records are ranked in pairs");
+#pragma unroll
+    for (int q0 = 0; q0 < kPerThread; q0 += 2) {
+        uint2 u[2][kSmall];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int qq = q0 + h;
+            const uint32_t n = t + qq * kNT < Fb ? b1[qq] - b0[qq] : 1u;
+#pragma unroll
+            for (uint32_t k = 0; k < kSmall; ++k) u[h][k] = n > 1 ? s_A[b0[qq] + min(k, n - 1)] : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int qq = q0 + h;
+            if (t + qq * kNT >= Fb) continue;
+            const uint2 me = rec[qq];
+            const uint32_t n = b1[qq] - b0[qq];
             uint32_t rank = 0;
-            for (uint32_t j = b0; j < b1; ++j) {
-                const uint2 u2 = s_A[j];
-                bool less = u2.x < me.x;
-                if (u2.x == me.x && j != self) less = list[u2.y & 0xFFFFFFu] < list[me.y & 0xFFFFFFu];
-                rank += less;
-            }
-            s_B[b0 + rank] = me;
+            auto before = [&](const uint2& v) {   // (key, segment id) of v below me's
+                bool less = v.x < me.x;
+                if (v.x == me.x) less = list[v.y & 0xFFFFFFu] < list[me.y & 0xFFFFFFu];
+                return less;
+            };
+#pragma unroll
+            for (uint32_t k = 0; k < kSmall; ++k)
+                if (k < n && k != my_r[qq]) rank += before(u[h][k]);
+            for (uint32_t k = kSmall; k < n; ++k)
+                if (k != my_r[qq]) rank += before(s_A[b0[qq] + k]);
+            s_B[b0[qq] + rank] = me;
         }
     }
     __syncthreads();
@@ -1569,7 +1602,7 @@ __device__ inline void order_batch_insertion(uint32_t Fb, const uint32_t* s_cnt,
 struct BatchLds {
     uint32_t* s_cnt;
     uint32_t* s_kmin;
-    uint32_t* s_kmax;
+    float* s_scale;
     uint32_t* s_off;
     uint32_t* s_tmp;
     uint2* s_B;
@@ -1580,7 +1613,7 @@ struct BatchLds {
 };
 
 // Exact order, shading and blending of the Fb records staged in s_A (whole pixels whose
-// counts, key ranges and offsets are in s_cnt / s_kmin / s_kmax / s_off).  Finished pixels are
+// counts, key minima, bucket scales and offsets are in s_cnt / s_kmin / s_scale / s_off).  Finished pixels are
 // written to rgba, or (slice_out != nullptr, a single pixel's key slice) their (C, T) goes to
 // slice_out.  rank0 / cnt_total place a slice inside its pixel for the debug dump; by_seg: the
 // records carry segment ids in place of keys (a slice inside one key, key_of_slice).
@@ -1592,7 +1625,7 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
                                         uint32_t key_of_slice = 0u) {
     uint32_t* s_cnt = L_.s_cnt;
     uint32_t* s_kmin = L_.s_kmin;
-    uint32_t* s_kmax = L_.s_kmax;
+    const float* s_scale = L_.s_scale;
     uint32_t* s_off = L_.s_off;
     uint32_t* s_tmp = L_.s_tmp;
     uint2* s_B = L_.s_B;
@@ -1603,7 +1636,7 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
     const int t = threadIdx.x;
     const int W = a.cam.W, H = a.cam.H;
     PHASE_BEGIN();
-    order_batch(Fb, rec, s_cnt, s_kmin, s_kmax, s_off, s_tmp, s_A, s_B, s_bk, list);
+    order_batch(Fb, rec, s_cnt, s_kmin, s_scale, s_off, s_tmp, s_A, s_B, s_bk, list);
     PHASE_END(f.ctr, 2);
     // ---- shade and blend: thread t takes the run [rb, re) of consecutive fragments of the
     // ordered batch, shades them in order and composites them front to back ("over") as it
@@ -1818,7 +1851,8 @@ __device__ inline uint32_t refine_slice(uint32_t k, const uint2* __restrict__ sr
 template <int KIND, int MODEL, bool SHADOW>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 && !SHADOW ? 4 : 3))) void k_batch(
     FrameBufs f, ShadeArgs a, float* __restrict__ rgba, DebugDump dbg, int has_dbg) {
-    __shared__ uint32_t s_cnt[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix], s_off[kTilePix + 1];
+    __shared__ uint32_t s_cnt[kTilePix], s_kmin[kTilePix], s_off[kTilePix + 1];
+    __shared__ float s_scale[kTilePix];   // count / (key range + 1): the bucket map of the ordering
     __shared__ uint32_t s_tmp[kNT];
     __shared__ __align__(16) uint2 s_B[kCap];
     __shared__ __align__(16) uint32_t s_work[3 * kCap];   // staged records (2 words) + bucket counters
@@ -1827,7 +1861,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 &
     __shared__ float s_slice[4];
     __shared__ unsigned long long s_range[2];
     __shared__ uint32_t s_slot, s_flag;
-    BatchLds L_{s_cnt, s_kmin, s_kmax, s_off, s_tmp, s_B, reinterpret_cast<uint2*>(s_work), s_work + 2 * kCap, s_agg,
+    BatchLds L_{s_cnt, s_kmin, s_scale, s_off, s_tmp, s_B, reinterpret_cast<uint2*>(s_work), s_work + 2 * kCap, s_agg,
                 s_aggh};
     PHASE_BEGIN();
 
@@ -1850,13 +1884,14 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 &
 #pragma unroll
         for (int qq = 0; qq < kPerThread; ++qq) {
             const uint32_t i = t + qq * kNT;
-            if (i < Fb) rec[qq] = src[i];
+            rec[qq] = i < Fb ? src[i] : make_uint2(0u, 0u);
         }
         const uint32_t tile_off0 = f.pix_off[(size_t)tile * kTilePix + p0];
         if (t >= p0 && t < p1) {
-            s_cnt[t] = f.pix_cnt[q];
-            s_kmin[t] = f.pix_kmin[q];
-            s_kmax[t] = f.pix_kmax[q];
+            const uint32_t cnt = f.pix_cnt[q], kmn = f.pix_kmin[q];
+            s_cnt[t] = cnt;
+            s_kmin[t] = kmn;
+            s_scale[t] = bucket_scale(cnt, kmn, f.pix_kmax[q]);
             s_off[t] = f.pix_off[q] - tile_off0;
         }
         if (t == 0) s_off[p1] = Fb;
@@ -1902,7 +1937,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 &
         if (t == 0) {
             s_cnt[p] = Fb;
             s_kmin[p] = (uint32_t)v_lo;
-            s_kmax[p] = (uint32_t)(v_hi - 1);
+            s_scale[p] = bucket_scale(Fb, (uint32_t)v_lo, (uint32_t)(v_hi - 1));
             s_off[p] = 0;
             s_off[p + 1] = Fb;
         }
@@ -1912,7 +1947,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 &
 #pragma unroll
         for (int qq = 0; qq < kPerThread; ++qq) {
             const uint32_t i = t + qq * kNT;
-            if (i < Fb) rec[qq] = L_.s_A[i];
+            rec[qq] = i < Fb ? L_.s_A[i] : make_uint2(0u, 0u);
         }
         sort_shade_blend<KIND, MODEL, SHADOW>(f, a, rgba, dbg, has_dbg, L_, list, rec, px0, py0, Fb, s_slice, done, k,
                                               by_seg, key);
