@@ -617,6 +617,8 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     f.frag_base = ws->frag_base.as<uint32_t>();
     f.batch_start = ws->batch_start.as<uint32_t>();
     f.ctr = ws->ctr.as<Counters>();
+    // (the backward pass accumulates per list entry, so its records keep list indices)
+    f.gid = grad == nullptr && lv.nseg < (1 << 24);
     if (!fused) HIP_TRY(ctx, launch_check_caps(f, caps, 1, st), "k_check_caps");
     HIP_TRY(ctx, launch_scatter(f.seg, lv.nseg, cc, plan, tile_start, ws->bin_m.as<uint32_t>(), ws->list.as<uint32_t>(),
                                 f.ctr, st),

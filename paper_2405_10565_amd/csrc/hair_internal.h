@@ -198,8 +198,10 @@ struct FrameBufs {
     const uint32_t* frag_base;    // [T + 1] exclusive scan of tile_tot
     const uint32_t* batch_start;  // [T + 1] exclusive scan of tile_nb
     uint4* batches;               // [batches]: packed (tile, p0, p1, oversized, first fragment, count), in launch order
-    uint2* frags;                 // [fragments]: (depth key, local list index | pixel << 24)
+    uint2* frags;                 // [fragments]: (depth key, segment | pixel << 24), see gid
     Counters* ctr;
+    int32_t gid;                  // fragment records hold the global segment id (frames of fewer than
+                                  // 2^24 rows, forward passes) instead of the index in the tile's list
 };
 
 // Kernel launchers (hair_kernels.hip).

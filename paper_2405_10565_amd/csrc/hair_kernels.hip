@@ -892,6 +892,12 @@ __device__ inline uint32_t depth_key_iz(float iza, float izb, int tnum, int tden
     return 0xFFFFFFFFu - __float_as_uint(iz);
 }
 
+// The global segment id of a fragment record's second word (see FrameBufs::gid): the record
+// holds it, or the index of the segment in the tile's list.
+__device__ inline uint32_t seg_of(uint32_t y, const uint32_t* list, bool gid) {
+    return gid ? (y & 0xFFFFFFu) : list[y & 0xFFFFFFu];
+}
+
 struct ShadeArgs {
     CamConst cam;
     LightsConst lights;
@@ -1372,6 +1378,7 @@ __global__ __launch_bounds__(kNT) void k_batch_records(FrameBufs f) {
 // pixel's depth-key range (LDS-aggregated per item).
 __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam) {
     __shared__ uint32_t s_cur[kTilePix], s_pos[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix];
+    __shared__ uint32_t s_id[kNT];   // each owner's record word: global segment id or list index
     __shared__ CovSetup s_cov[kNT];
     __shared__ uint8_t s_own[kNT / 64 * kCovLinesPerWave];
     __shared__ float2 s_iz[kNT];
@@ -1402,10 +1409,14 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam) {
     const uint32_t n = f.tile_start[tile + 1] - lstart;
     const uint32_t j = s_chunk * kNT + t;
     SegRec s{};
-    if (j < n) s = f.seg[f.list[lstart + j]];
+    uint32_t gseg = 0;
+    if (j < n) {
+        gseg = f.list[lstart + j];
+        s = f.seg[gseg];
+    }
     s_iz[t] = make_float2(s.iza, s.izb);
+    s_id[t] = f.gid ? gseg : j;
     const uint32_t total = cov_setup(s, j < n, px0, py0, cam.W, cam.H, s_cov, s_own);
-    const uint32_t j0 = s_chunk * kNT;
     wave_coverage(s_cov, s_own, total, px0, py0, [&](int li, int lj, int tnum, int tden, int o) {
         const int p = lj * kTile + li;
         const float2 iz = s_iz[o];
@@ -1413,7 +1424,7 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam) {
         const uint32_t slot = atomicAdd(&s_cur[p], 1u);
         atomicMin(&s_kmin[p], key);
         atomicMax(&s_kmax[p], key);
-        f.frags[s_pos[p] + slot] = make_uint2(key, (j0 + (uint32_t)o) | ((uint32_t)p << 24));
+        f.frags[s_pos[p] + slot] = make_uint2(key, s_id[o] | ((uint32_t)p << 24));
     });
     __syncthreads();
     if (s_cur[t]) {
@@ -1439,7 +1450,8 @@ __device__ inline float bucket_scale(uint32_t cnt, uint32_t kmin, uint32_t kmax)
 // s_bk must hold Fb zeros on entry.  Ends with a barrier.
 __device__ inline void order_batch(uint32_t Fb, const uint2 (&rec)[kPerThread], const uint32_t* s_cnt,
                                    const uint32_t* s_kmin, const float* s_scale, const uint32_t* s_off,
-                                   uint32_t* s_tmp, uint2* s_A, uint2* s_B, uint32_t* s_bk, const uint32_t* list) {
+                                   uint32_t* s_tmp, uint2* s_A, uint2* s_B, uint32_t* s_bk, const uint32_t* list,
+                                   bool gid) {
     const int t = threadIdx.x;
     uint32_t my_b[kPerThread], my_r[kPerThread];
     {
@@ -1515,7 +1527,7 @@ __device__ inline void order_batch(uint32_t Fb, const uint2 (&rec)[kPerThread], 
             uint32_t rank = 0;
             auto before = [&](const uint2& v) {   // (key, segment id) of v below me's
                 bool less = v.x < me.x;
-                if (v.x == me.x) less = list[v.y & 0xFFFFFFu] < list[me.y & 0xFFFFFFu];
+                if (v.x == me.x) less = seg_of(v.y, list, gid) < seg_of(me.y, list, gid);
                 return less;
             };
 #pragma unroll
@@ -1636,7 +1648,8 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
     const int t = threadIdx.x;
     const int W = a.cam.W, H = a.cam.H;
     PHASE_BEGIN();
-    order_batch(Fb, rec, s_cnt, s_kmin, s_scale, s_off, s_tmp, s_A, s_B, s_bk, list);
+    const bool gid = f.gid != 0;
+    order_batch(Fb, rec, s_cnt, s_kmin, s_scale, s_off, s_tmp, s_A, s_B, s_bk, list, gid);
     PHASE_END(f.ctr, 2);
     // ---- shade and blend: thread t takes the run [rb, re) of consecutive fragments of the
     // ordered batch, shades them in order and composites them front to back ("over") as it
@@ -1656,7 +1669,7 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
 #pragma unroll
         for (int j = 0; j < kPerThread; ++j) {
             const uint32_t i = rb + j;
-            gs[j] = i < re ? list[s_B[i].y & 0xFFFFFFu] : 0u;
+            gs[j] = i < re ? seg_of(s_B[i].y, list, gid) : 0u;
         }
         if (rb < re) nxt = fetch_segment<KIND>(a, gs[0]);
     }
@@ -1673,7 +1686,7 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
         }
     };
     for (uint32_t i = rb; i < re; ++i) {
-        if (!kAhead) gs[0] = list[s_B[i].y & 0xFFFFFFu];
+        if (!kAhead) gs[0] = seg_of(s_B[i].y, list, gid);
         const SegInputs cur = kAhead ? nxt : fetch_segment<KIND>(a, gs[0]);
         const uint32_t gseg = gs[0];
         if (kAhead) {
@@ -1978,7 +1991,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 &
         const uint32_t K0 = (uint32_t)lo;
         auto by_seg = [&](const uint2& r, uint32_t& v) {
             if (r.x != K0) return false;
-            v = list[r.y & 0xFFFFFFu];
+            v = seg_of(r.y, list, f.gid != 0);
             return true;
         };
         unsigned long long slo = 0;
@@ -2934,7 +2947,7 @@ __global__ __launch_bounds__(kNT) void k_dom_resolve(FrameBufs f, LevelDev lv, c
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             const uint32_t i = i0 + t + u * kNT;
-            g[u] = i < b.nfrag ? list[rec[u].y & 0xFFFFFFu] : 0u;
+            g[u] = i < b.nfrag ? seg_of(rec[u].y, list, f.gid != 0) : 0u;
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
