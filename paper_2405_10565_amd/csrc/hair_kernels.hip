@@ -771,13 +771,18 @@ __global__ void k_fill_f32(float* p, float v, size_t n) {
 // |cross| <= s_max = floor(sqrt(R^2 t_den - 1)), found per segment in 64-bit integers.
 // x >> 4 is floor(x / 16).
 // The candidate interval is computed in float32: only an enumeration, so it just has to contain
-// every covered pixel.  Each bound is a product or difference of values below 2^31 computed with
-// relative error under 1e-6 (float conversions, the hardware reciprocal and square root,
-// roundings); the interval is widened by 2e-6 of the magnitudes involved plus one sub-pixel.
+// every covered pixel.  The strip's centre on line u is linear in u (slope u + base, minor
+// pixel indices, per segment), so a line's interval is one multiply-add and two roundings;
+// each term is a product or difference of values below 2^31 computed with relative error under
+// 1e-6 (float conversions, the hardware reciprocal and square root, roundings), and the
+// half-width is widened by 4e-6 of the magnitudes of all terms plus one sub-pixel (the slab
+// bounds of wide segments by 2e-6 of theirs plus one sub-pixel).
 struct CovSetup {
     int4 g0;     // (au, av, du, dv): start and extent along the major and minor axes, 1/16 px
-    int4 g1;     // (s_max, tden, first line - lines before this lane in the wave, steep | wide << 1)
-    float4 g2;   // (1 / du, 1 / dv or 0, R sqrt(tden) / |du|, bits: first | last minor index << 16)
+    int4 g1;     // (s_max, tden, first line - lines before this lane in the wave, bits of 1 / dv (wide only))
+    float4 g2;   // (slope, base, half, bits: first | steep << 15 | last minor index << 16 | wide << 31):
+                 // on line u the strip's centre is at minor pixel index slope u + base and its
+                 // half-width, with the enumeration's margin, is half (pixels)
 };
 
 // The largest s with s^2 < R^2 t_den (R^2 t_den >= 64): a double square root, corrected in
@@ -814,11 +819,22 @@ __device__ inline uint32_t cov_setup(const SegRec& s, bool valid, int px0, int p
             nl = (uint32_t)(steep ? j1 - j0 + 1 : i1 - i0 + 1);
             const float inv_du = __builtin_amdgcn_rcpf((float)du);
             const float inv_dv = dv != 0 ? __builtin_amdgcn_rcpf((float)dv) : 0.0f;
-            const int vmin = steep ? i0 : j0, vmax = steep ? i1 : j1;   // 0 <= vmin <= vmax < 2^16
+            const int vmin = steep ? i0 : j0, vmax = steep ? i1 : j1;   // 0 <= vmin <= vmax < 2^14
+            const int u0 = steep ? j0 : i0, u1 = steep ? j1 : i1;
+            const bool wide = R > 32;
+            // the strip's centre line in minor pixel indices: (av + (16 u + 8 - au) dv / du - 8) / 16
+            const float slope = (float)dv * inv_du;
+            const float base = ((float)av - 8.0f) * (1.0f / 16.0f) + (8.0f - (float)au) * slope * (1.0f / 16.0f);
+            const float half = (float)R * __builtin_amdgcn_sqrtf((float)tden) * fabsf(inv_du) * (1.0f / 16.0f);
+            // margin: one sub-pixel plus 4e-6 of the magnitudes of every term (each float step's
+            // relative error is below 1e-6; slope u + base is evaluated with 0 <= u <= u1, and
+            // base's two terms may cancel)
+            const float mag = (fabsf((float)av) + fabsf((float)au * slope)) * (1.0f / 16.0f) +
+                              fabsf(slope) * (float)u1 + half + 1.0f;
             c.g0 = make_int4(au, av, du, dv);
-            c.g1 = make_int4(strip_smax(R, tden), tden, steep ? j0 : i0, (steep ? 1 : 0) | (R > 32 ? 2 : 0));
-            c.g2 = make_float4(inv_du, inv_dv, (float)R * __builtin_amdgcn_sqrtf((float)tden) * fabsf(inv_du),
-                               __int_as_float(vmin | (vmax << 16)));
+            c.g1 = make_int4(strip_smax(R, tden), tden, u0, __float_as_int(inv_dv));
+            c.g2 = make_float4(slope, base, half + (1.0f / 16.0f) + 4e-6f * mag,
+                               __int_as_float(vmin | (steep ? 1 << 15 : 0) | (vmax << 16) | (wide ? (int)0x80000000u : 0)));
         }
     }
     uint32_t x = nl;
@@ -849,30 +865,26 @@ __device__ inline void wave_coverage(const CovSetup* s_cov, const uint8_t* s_own
         const CovSetup c = s_cov[o];
         const int au = c.g0.x, av = c.g0.y, du = c.g0.z, dv = c.g0.w;
         const int smax = c.g1.x, tden = c.g1.y, u = c.g1.z + (int)g;
-        const bool steep = (c.g1.w & 1) != 0, wide = (c.g1.w & 2) != 0;
         const int vb = __float_as_int(c.g2.w);
-        const int vmin = vb & 0xFFFF, vmax = vb >> 16;
+        const bool steep = (vb & (1 << 15)) != 0;
+        const int vmin = vb & 0x7FFF, vmax = (vb >> 16) & 0x7FFF;
         const int eu = 16 * u + 8 - au;
         const int eu_du = __mul24(eu, du), eu_dv = __mul24(eu, dv);
         // the strip bounds the span; the slab trims it too for wide segments (radius above
         // 2 px: thick hairs, whose short steps would otherwise test most of their box), while
         // for strands it would only trim the end lines, whose extra candidates the integer
         // test rejects
-        const float cc = (float)eu_dv * c.g2.x;
-        float lo_f = cc - c.g2.z, hi_f = cc + c.g2.z;
-        float mag = (fabsf((float)av) + fabsf(cc)) + c.g2.z;
-        if (wide && dv != 0) {
-            const float a = (float)(-eu_du) * c.g2.y;
-            const float b = (float)(tden - eu_du) * c.g2.y;
-            lo_f = fmaxf(lo_f, fminf(a, b));
-            hi_f = fminf(hi_f, fmaxf(a, b));
-            mag += fmaxf(fabsf(a), fabsf(b));
+        const float m = fmaf((float)u, c.g2.x, c.g2.y);
+        float flo = m - c.g2.z, fhi = m + c.g2.z;
+        if (vb < 0 && dv != 0) {   // wide
+            const float inv_dv = __int_as_float(c.g1.w);
+            const float a = (float)(-eu_du) * inv_dv, b = (float)(tden - eu_du) * inv_dv;
+            const float w = 1.0f + 2e-6f * (fabsf((float)av) + fmaxf(fabsf(a), fabsf(b)));
+            flo = fmaxf(flo, ((float)av + (fminf(a, b) - w) - 8.0f) * (1.0f / 16.0f));
+            fhi = fminf(fhi, ((float)av + (fmaxf(a, b) + w) - 8.0f) * (1.0f / 16.0f));
         }
-        const float w = 2e-6f * mag + 1.0f;
-        const float flo = ceilf(((float)av + (lo_f - w) - 8.0f) * (1.0f / 16.0f));
-        const float fhi = floorf(((float)av + (hi_f + w) - 8.0f) * (1.0f / 16.0f));
-        const int k0 = (int)fmaxf((float)vmin, flo);
-        const int k1 = (int)fminf((float)vmax, fhi);
+        const int k0 = (int)fmaxf((float)vmin, ceilf(flo));
+        const int k1 = (int)fminf((float)vmax, floorf(fhi));
         const int ev0 = 16 * k0 + 8 - av;
         int tnum = __mul24(ev0, dv) + eu_du;
         int cr = __mul24(ev0, du) - eu_dv;
