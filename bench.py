@@ -84,13 +84,15 @@ def read_traffic():
 
 
 def ops_per_fragment(kind: str, lights):
-    """(ops, transcendentals) per fragment of k_batch for `kind` ("strand_100k_1080p" or
-    "thick_1080p") and the lights' kinds, from the oracle's counted definition."""
+    """(ops, transcendentals) per fragment of k_batch for `kind` ("strand_100k_1080p",
+    "thick_1080p" or "strand_shadowed_100k_1080p") and the lights' kinds, from the oracle's
+    counted definition (a shadowed frame adds its deep opacity map lookup)."""
     with open(OPS_FILE) as f:
         c = json.load(f)[kind]
     per = {0: next(v for k, v in c.items() if k.endswith("kind0")), 1: next(v for k, v in c.items() if k.endswith("kind1"))}
-    ops = c["base"][0] + c["blend"][0] + c["sort_compares"] + sum(per[l.kind][0] for l in lights)
-    trans = c["base"][1] + c["blend"][1] + sum(per[l.kind][1] for l in lights)
+    look = c.get("lookup", (0.0, 0.0))
+    ops = c["base"][0] + c["blend"][0] + c["sort_compares"] + look[0] + sum(per[l.kind][0] for l in lights)
+    trans = c["base"][1] + c["blend"][1] + look[1] + sum(per[l.kind][1] for l in lights)
     return ops, trans
 
 
@@ -211,15 +213,19 @@ def thick_frame(ctx, ws, clusters: int = 1000, frames: int = 20):
 
 def shadowed_frame(ctx, aid, cam, lights, ws, shadow=(1024, 4, 0.02), frames: int = 20):
     """The same strand frame with deep opacity map shadows for the directional light
-    (outside the timed region; ms includes the shadow pass)."""
+    (outside the timed region; ms includes the shadow pass), with the roofline of its camera
+    shading kernel k_batch<0, 0, true>."""
     import numpy as np
-    ms = []
+    ms, tile = [], []
     for i in range(frames + 2):
         _, st, _ = ctx.render_shadowed(aid, 0, cam, lights, shadow, ws=ws)
         if i >= 2:
             ms.append(st["ms_total"])
+            tile.append(st["ms_tile"])
+    t = float(np.mean(tile)) * 1e-3
     return {"gpu_mean": round(float(np.mean(ms)), 4), "gpu_p50": round(float(np.percentile(ms, 50)), 4),
-            "resolution": shadow[0], "layers": shadow[1], "layer_depth": shadow[2]}
+            "resolution": shadow[0], "layers": shadow[1], "layer_depth": shadow[2], "k_batch_ms": round(t * 1e3, 4),
+            "roofline": roofline(int(st["fragments"]), lights, t, "strand_shadowed_100k_1080p", "k_batch<0, 0, true>")}
 
 
 def serve_leg(ctx, n_requests: int, warmup: int, rates=(30.0, 60.0, 120.0)):

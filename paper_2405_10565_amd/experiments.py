@@ -61,10 +61,11 @@ def lod_sweep(hctx: B.Context, scale: float = 1.0, repeats: int = 20):
     for level in range(n_levels + 1):
         img, st, _ = hctx.render(aid, level, cam, lights, ws=ws)
         torch.cuda.synchronize()
-        ms = []
+        ms, tile = [], []
         for _ in range(repeats):
             _, s2, _ = hctx.render(aid, level, cam, lights, out=img, ws=ws)
             ms.append(s2["ms_total"])
+            tile.append(s2["ms_tile"])
         img = img.clone()
         if level == 0:
             ref = img
@@ -72,6 +73,7 @@ def lod_sweep(hctx: B.Context, scale: float = 1.0, repeats: int = 20):
         out["levels"].append({"level": level, "clusters": None if level == 0 else int(counts[level]),
                               "segments": int(st["segments"]), "fragments": int(st["fragments"]),
                               "frame_ms_p50": round(float(np.percentile(ms, 50)), 4),
+                              "shading_ms_p50": round(float(np.percentile(tile, 50)), 4),
                               "rmse": round(rmse, 6), "psnr_db": round(psnr, 2)})
     ws.close()
     hctx.release(aid)

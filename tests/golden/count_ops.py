@@ -183,6 +183,111 @@ def count(geom, cam, lights, mat, band):
     return res
 
 
+NP_TRANS = {"sqrt", "exp", "exp2", "log", "log2", "sin", "cos", "arcsin", "arctan2", "arctan", "tanh"}
+NP_FREE = {"astype", "stack", "zeros", "zeros_like", "concatenate", "copy", "reshape", "asarray", "array"}
+
+
+class _NpCounted(np.ndarray):
+    """An array whose elementwise arithmetic (numpy ufuncs, where, clip) is counted by the
+    elements it produces, with the same classes as OpCounter; gathers (indexing) and
+    conversions are free, as they are there."""
+    counter = None
+
+    def __array_ufunc__(self, ufunc, method, *inputs, **kwargs):
+        args = [np.asarray(x) if isinstance(x, _NpCounted) else x for x in inputs]
+        if "out" in kwargs:
+            kwargs["out"] = tuple(np.asarray(x) if isinstance(x, _NpCounted) else x for x in kwargs["out"])
+        out = getattr(ufunc, method)(*args, **kwargs)
+        c = _NpCounted.counter
+        n = int(np.size(out[0] if isinstance(out, tuple) else out))
+        if ufunc.__name__ in NP_TRANS:
+            c.trans += n
+        else:
+            c.ops += n
+        return np.asarray(out).view(_NpCounted) if isinstance(out, np.ndarray) else out
+
+    def __array_function__(self, func, types, args, kwargs):
+        plain = lambda a: np.asarray(a) if isinstance(a, _NpCounted) else a
+        args2 = [plain(a) if not isinstance(a, (list, tuple)) else type(a)(plain(b) for b in a) for a in args]
+        kwargs2 = {k: plain(v) for k, v in kwargs.items()}
+        out = func(*args2, **kwargs2)
+        c = _NpCounted.counter
+        n = int(np.size(out)) if isinstance(out, np.ndarray) else 0
+        if func.__name__ == "where":
+            c.ops += n
+        elif func.__name__ == "clip":
+            c.ops += 2 * n
+        elif func.__name__ not in NP_FREE:
+            c.unknown[func.__name__] += n
+        return out.view(_NpCounted) if isinstance(out, np.ndarray) else out
+
+
+def _counted_lookup(geom, ras, cam, doms):
+    """Operations of the deep opacity map lookup of every fragment: its world point on the
+    centre line (oracle.shadow.lookup_point) and, per map, the bilinear, layer-interpolated
+    count (dom_count); the maps themselves are the shadow pass's, built outside."""
+    from oracle import shadow as SH
+    c = OpCounter(len(ras.seg))
+    _NpCounted.counter = c
+    counted = lambda a: np.asarray(a).view(_NpCounted)
+    rv = R.Raster(**{k: (counted(v) if k in ("t_num", "t_den", "izA", "izB") else v)
+                     for k, v in vars(ras).items()})
+    gv = R.LevelGeom(**{k: (counted(v) if k in ("pA", "pB") else v) for k, v in vars(geom).items()})
+    x = SH.lookup_point(gv, rv, cam)
+    for dom in doms:
+        SH.dom_count(dom, np.asarray(x).view(_NpCounted))
+    _NpCounted.counter = None
+    return c
+
+
+def count_shadowed(geom, cam, lights, mat, band, shadow):
+    """(ops, trans) per fragment of the shadowed shading pass: base, the map lookup (point and
+    per directional light), each light with the hairs in front as the frame has them (a
+    strand with n_s > 0 takes the aggregated model, the others the single-fibre one: the
+    average over the band's fragments), blend and sort."""
+    from oracle import shadow as SH
+    res = count(geom, cam, [], mat, band)
+    ras = R.rasterize(geom, cam, rect=band)
+    F = len(ras.seg)
+    Rm, K, delta = shadow
+    doms = [SH.build_dom(geom, l.vec, Rm, K, delta) for l in lights if l.kind == 0]
+    x = SH.lookup_point(geom, ras, cam)
+    ns, it = [], iter(doms)
+    for l in lights:
+        ns.append(None if l.kind != 0 else torch.as_tensor(SH.dom_count(next(it), x), dtype=torch.float64))
+    c = _counted_lookup(geom, ras, cam, doms)
+    res["lookup"] = (c.ops / F, c.trans / F)
+    res["shadowed_fraction"] = [None if n is None else float((n > 0).double().mean()) for n in ns]
+    unknown = Counter(res["unknown"])
+    unknown.update(c.unknown)
+    base = res["base"]
+    for li, light in enumerate(lights):
+        single = _counted(geom, ras, cam, [light], mat)
+        one = (single.ops / F - base[0], single.trans / F - base[1])
+        key = f"light{li}_kind{light.kind}"
+        if ns[li] is None:
+            res[key] = one
+            continue
+        # the oracle evaluates both models for every fragment and selects; a fragment takes
+        # one of them, so a fragment with hairs in front costs (both - f_single) and one
+        # without costs f_single
+        with OpCounter(F) as c:
+            AG.hemisphere_stats = _HalfWeight(c, AG.hemisphere_stats)
+            try:
+                R.fragment_radiance(geom, ras, cam, [light], mat, shadow=[ns[li]])
+            finally:
+                AG.hemisphere_stats = AG.hemisphere_stats.orig
+        both = (c.ops / F - base[0], c.trans / F - base[1])
+        ours = (both[0] - one[0], both[1] - one[1])
+        fr = res["shadowed_fraction"][li]
+        res[key] = (fr * ours[0] + (1 - fr) * one[0], fr * ours[1] + (1 - fr) * one[1])
+        res[key + "_models"] = {"f_single": one, "f_ours_with_selection": ours}
+        unknown.update(c.unknown)
+        unknown.update(single.unknown)
+    res["unknown"] = dict(unknown)
+    return res
+
+
 def coverage_ops():
     """Integer operations per candidate (pixel, segment) of the coverage predicate, and float32
     operations of the depth key per fragment, from oracle.raster (numpy) by reading: the
@@ -205,6 +310,8 @@ def main():
     cam3 = hs.camera_for(small, 1920, 1080)
     lights3 = hs.default_lights(small, with_point=True)
     out["thick_1080p"] = count(R.cluster_level(lod), cam3, lights3, mat, (0, 536, cam3.width, 4))
+    # the shadowed headline frame (deep opacity map 1024^2, 4 layers of 2 cm)
+    out["strand_shadowed_100k_1080p"] = count_shadowed(R.strand_level(asset), cam, lights, mat, band, (1024, 4, 0.02))
     out["coverage"] = coverage_ops()
     path = os.path.join(HERE, "ops_per_fragment.json")
     with open(path, "w") as f:

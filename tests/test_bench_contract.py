@@ -59,6 +59,37 @@ def test_ops_per_fragment_are_the_oracles_counted_definition():
     assert abs(trans - (st["base"][1] + st["light0_kind0"][1] + st["light1_kind1"][1])) < 1e-9
 
 
+def test_shadowed_op_counts_are_the_oracles_counted_definition():
+    """The shadowed frame's stored counts: the map lookup and the two scattering models per
+    fragment do not depend on the scene (a fresh count on a small one agrees), and the light
+    with a map is their mixture by the fraction of fragments with hairs in front."""
+    import json
+
+    import numpy as np
+
+    import hairsynth as hs
+    from oracle import render as R
+    co = _count_ops_module()
+    with open(bench.OPS_FILE) as f:
+        stored = json.load(f)["strand_shadowed_100k_1080p"]
+    asset = hs.make_asset(400, 8, 90.0, seed=77, sigma_spread=True)
+    cam = hs.camera_for(asset, 96, 80)
+    lights = hs.default_lights(asset, with_point=True)
+    mat = tuple(float(v) for v in asset.material.as_array())
+    got = co.count_shadowed(R.strand_level(asset), cam, lights, mat, (0, 0, 96, 80), (64, 4, 0.02))
+    assert got["unknown"] == {}
+    assert np.allclose(got["lookup"], stored["lookup"], rtol=1e-9)
+    for m in ("f_single", "f_ours_with_selection"):
+        assert np.allclose(got["light0_kind0_models"][m], stored["light0_kind0_models"][m], rtol=2e-2), m
+    fr = stored["shadowed_fraction"][0]
+    mods = stored["light0_kind0_models"]
+    mix = [fr * mods["f_ours_with_selection"][i] + (1 - fr) * mods["f_single"][i] for i in range(2)]
+    assert np.allclose(stored["light0_kind0"], mix, rtol=1e-12)
+    ops, trans = bench.ops_per_fragment("strand_shadowed_100k_1080p", lights)
+    assert abs(ops - (stored["base"][0] + stored["lookup"][0] + stored["light0_kind0"][0] + stored["light1_kind1"][0]
+                      + stored["blend"][0] + stored["sort_compares"])) < 1e-9
+
+
 def test_planted_op_count_mistake_is_caught(monkeypatch):
     """A dropped term in the counted definition changes the count."""
     co = _count_ops_module()
