@@ -350,6 +350,8 @@ MatConst mat_const(const hair_material& m) {
     k.inv_s = (float)(1.0 / s);
     k.inv_s_l2 = (float)(M_LOG2E / s);
     k.n_norm = (float)(1.0 / (s * std::tanh(M_PI / (2.0 * s))));
+    for (int p = 0; p < 3; ++p)
+        k.mn_amp[p] = (float)(0.5 / ((double)k.beta_p[p] * std::sqrt(2.0 * M_PI)) / (s * std::tanh(M_PI / (2.0 * s))));
     const double lo = 1.0 / (1.0 + std::exp(M_PI / s)), hi = 1.0 / (1.0 + std::exp(-M_PI / s));
     k.cdf_lo = (float)lo;
     k.cdf_scale = (float)(1.0 / (hi - lo));

@@ -98,6 +98,7 @@ struct MatConst {
     float inv_s;             // 1 / s
     float inv_s_l2;          // log2(e) / s
     float n_norm;            // trimmed-logistic normaliser 1 / (s tanh(pi / 2s))
+    float mn_amp[3];         // g_amp[p] n_norm: the amplitude of M_p N_p
     float cdf_lo, cdf_scale; // trimmed CDF: (sigmoid(x / s) - cdf_lo) * cdf_scale on [-pi, pi]
     // R / TT / D model (model == 1); the fields above serve model 0
     int32_t model;

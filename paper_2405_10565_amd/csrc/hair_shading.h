@@ -227,19 +227,33 @@ template <class T> __device__ inline T exit_azimuth(int p, T gamma_o, T gamma_t)
     return p == 0 ? g2 : (p == 1 ? (g2 + 2.0f * gamma_t) + kPi : (g2 + 4.0f * gamma_t) + kTwoPi);
 }
 
-// Single-fibre BCSDF, RGB (gamma_o = asin h, cgo = cos gamma_o).
+// Single-fibre BCSDF, RGB (gamma_o = asin h, cgo = cos gamma_o).  With the absorption
+// transmittance T_c of channel c, A_R = F, A_TT = (1 - F)^2 T_c and A_TRT = (1 - F)^2 F T_c^2,
+// so the three lobes sum per channel as q_R + T_c (q_TT + T_c q_TRT) with q_p the lobe's M_p N_p
+// times its channel-independent factor; M_p N_p's two amplitudes are one host constant.
 template <class T>
 __device__ inline void f_single(const LightView& v, T h, T gamma_o, T cgo, const T sigl[3], const MatConst& m,
                                 T out[3]) {
-    Atten<T> at = attenuation(v, h, cgo, sigl, m);
-    const T ks = T(m.inv_s_l2), norm = T(m.n_norm);
-    out[0] = out[1] = out[2] = T(0.0f);
+    const T sgt = h * v.inv_eta_p;
+    const T gamma_t = m_asin(sgt);
+    const T cgt = m_sqrt(1.0f - sgt * sgt);
+    const T F = fresnel(v.cxd * cgo, m);
+    const T path = 2.0f * cgt * v.inv_ctt;
+    const T one_f = 1.0f - F;
+    const T one_f2 = one_f * one_f;
+    const T ks = T(m.inv_s_l2);
+    T mn[3];
     for (int p = 0; p < 3; ++p) {
         const float x = v.theta_h - m.alpha_p[p];
-        const float M = m.g_amp[p] * m_exp2(-m.g_k2[p] * (x * x));
-        T N = trimmed_logistic(wrap_pi(v.phi - exit_azimuth(p, gamma_o, at.gamma_t)), ks, norm);
-        T MN = M * N;
-        for (int c = 0; c < 3; ++c) out[c] = out[c] + at.A[p][c] * MN;
+        const float M = m_exp2(-m.g_k2[p] * (x * x));
+        const T e = m_exp2(-m_abs(wrap_pi(v.phi - exit_azimuth(p, gamma_o, gamma_t))) * ks);
+        const T one_e = 1.0f + e;
+        mn[p] = (m.mn_amp[p] * M) * (e * m_rcp(one_e * one_e));
+    }
+    const T q0 = F * mn[0], q1 = one_f2 * mn[1], q2 = (one_f2 * F) * mn[2];
+    for (int c = 0; c < 3; ++c) {
+        const T Tc = m_exp2(-sigl[c] * path);
+        out[c] = q0 + Tc * (q1 + Tc * q2);
     }
 }
 
