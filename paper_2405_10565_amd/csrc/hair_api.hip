@@ -110,7 +110,7 @@ struct hair_ws {
     uint64_t held = 0;
     DevBuf seg, shade, scan_tmp, tile_cnt, tile_start, bin_m, bin_blk, list, ctr, sel_cnt, sel_start, sel, sel_tmp;
     DevBuf pieces;                            // rows of a frame drawn with long segments as pieces
-    DevBuf items, item_start, item_base, pix_cnt, pix_kmin, pix_kmax, pix_off;
+    DevBuf items, item_start, item_tab, item_base, pix_cnt, pix_kmin, pix_kmax, pix_off;
     DevBuf tile_tot, frag_base, tile_nb, batch_mask, batch_start, batches, frags;
     DevBuf dom_tex, dom_grid, dom_part;      // shadow pass: texels, grids, bounds partials
     int32_t dom_R = 0, dom_K = 0, dom_n = 0;  // last shadowed render: resolution, layers, maps
@@ -191,10 +191,10 @@ void ctx_free(hair_ctx* ctx, DevBuf& b, hair_ws* ws = nullptr) {
 }
 
 // Every device buffer a workspace can hold.
-std::array<DevBuf*, 31> ws_buffers(hair_ws* ws) {
+std::array<DevBuf*, 32> ws_buffers(hair_ws* ws) {
     return {{&ws->seg, &ws->shade, &ws->scan_tmp, &ws->tile_cnt, &ws->tile_start, &ws->bin_m, &ws->bin_blk,
             &ws->sel_cnt, &ws->sel_start, &ws->sel, &ws->sel_tmp, &ws->list, &ws->ctr, &ws->items,
-            &ws->item_start, &ws->item_base, &ws->pix_cnt, &ws->pix_kmin, &ws->pix_kmax, &ws->pix_off,
+            &ws->item_start, &ws->item_tab, &ws->item_base, &ws->pix_cnt, &ws->pix_kmin, &ws->pix_kmax, &ws->pix_off,
             &ws->tile_tot, &ws->frag_base, &ws->tile_nb, &ws->batch_mask, &ws->batch_start, &ws->batches,
             &ws->frags, &ws->dom_tex, &ws->dom_grid, &ws->dom_part, &ws->pieces}};
 }
@@ -592,6 +592,7 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     }
     if ((rc = ws_need(ws, ws->list, 4ull * caps.pairs))) return rc;
     if ((rc = ws_need(ws, ws->item_base, 4ull * kTilePix * caps.items))) return rc;
+    if ((rc = ws_need(ws, ws->item_tab, 8ull * caps.items))) return rc;
     for (DevBuf* b : {&ws->pix_cnt, &ws->pix_kmin, &ws->pix_kmax, &ws->pix_off})
         if ((rc = ws_need(ws, *b, 4 * TP))) return rc;
     for (DevBuf* b : {&ws->tile_tot, &ws->tile_nb})
@@ -608,6 +609,7 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     f.tile_start = tile_start;
     f.list = ws->list.as<uint32_t>();
     f.item_start = ws->item_start.as<uint32_t>();
+    f.item_tab = ws->item_tab.as<uint2>();
     f.item_base = ws->item_base.as<uint32_t>();
     f.pix_cnt = ws->pix_cnt.as<uint32_t>();
     f.pix_kmin = ws->pix_kmin.as<uint32_t>();
@@ -628,7 +630,8 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     // (a static-scratch frame clears the image only once every buffer has been carved, so that
     // a frame too large for the scratch fails with the caller's image untouched)
     HIP_TRY(ctx, launch_fill_pix(f.pix_cnt, f.pix_kmin, f.pix_kmax, TP, ws->arena ? nullptr : rgba,
-                                 (size_t)cam->width * cam->height, st),
+                                 (size_t)cam->width * cam->height, f.item_start, T, ws->item_tab.as<uint2>(),
+                                 caps.items, st),
             "fill");
     const uint32_t item_grid = warm ? caps.items : n_items;
     HIP_TRY(ctx, launch_count(f, cc, item_grid, st), "k_count");
@@ -912,10 +915,10 @@ uint64_t hair_ws_estimate(int64_t n_segments, int32_t width, int32_t height, int
     const uint64_t bin_nb = (uint64_t)bin_plan((int32_t)std::min<int64_t>(n_segments, INT32_MAX), (int32_t)T).nb;
     const uint64_t raw = (sizeof(SegRec) + sizeof(ShadeRec)) * (uint64_t)std::max<int64_t>(n_segments, 1) +
                          4ull * (2 * T + 1) + 20ull * bin_nb * T +
-                         4ull * (2 * T + 2) + 4 * P + 4ull * kTilePix * items +
+                         4ull * (2 * T + 2) + 4 * P + (4ull * kTilePix + 8) * items +
                          4ull * 4 * T * kTilePix + 4ull * 4 * (T + 1) + 32 * T + 8 * frags + 16 * (T + frags / 512) +
                          sizeof(Counters) + 4 * exscan_scratch_words(T);
-    return raw + raw / 4 + 24 * 256;
+    return raw + raw / 4 + 25 * 256;
 }
 
 int hair_upload(hair_ctx* ctx, int32_t n_strands, int32_t verts_per_strand, const float* xyz_soa,

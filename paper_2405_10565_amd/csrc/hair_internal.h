@@ -188,6 +188,7 @@ struct FrameBufs {
     const uint32_t* tile_start;   // [T + 1]: tile t's list is [tile_start[t], tile_start[t + 1])
     const uint32_t* list;         // segment ids
     const uint32_t* item_start;   // [T + 1] exclusive scan of per-tile work items
+    const uint2* item_tab;        // [items] each work item's (tile, chunk of the tile's list)
     uint32_t* item_base;          // [items][kTilePix] each item's slice of each pixel's range
     uint32_t* pix_cnt;            // [T][kTilePix] fragments per pixel
     uint32_t* pix_kmin;           // [T][kTilePix] smallest depth key per pixel
@@ -296,7 +297,7 @@ hipError_t launch_dom_resolve(const FrameBufs& f, const LevelDev& lv, const Shad
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
 // The frame's per-pixel counters: n counts set to 0, key minima to ~0, key maxima to 0.
 hipError_t launch_fill_pix(uint32_t* cnt, uint32_t* kmin, uint32_t* kmax, size_t n, float* rgba, size_t n_rgba4,
-                           hipStream_t st);   // also clears rgba (n_rgba4 pixels) when given
+                           const uint32_t* item_start, int T, uint2* item_tab, uint32_t cap_items, hipStream_t st);   // also clears rgba (n_rgba4 pixels) when given
 hipError_t launch_fill_f32(float* p, float v, size_t n, hipStream_t st);
 hipError_t launch_probe_rate(int kind, int blocks, int iters, float* out, hipStream_t st);
 

@@ -502,8 +502,11 @@ __global__ __launch_bounds__(1024) void k_tile_scans(const uint32_t* __restrict_
 }
 
 // The per-pixel counters of a frame: counts 0, key minima ~0, key maxima 0.
+// ... and the work-item table of the count and emit passes: item i of tile t (its list chunk
+// i - item_start[t]), for the items within the table's capacity.
 __global__ void k_fill_pix(uint32_t* __restrict__ cnt, uint32_t* __restrict__ kmin, uint32_t* __restrict__ kmax,
-                           size_t n, float4* __restrict__ rgba, size_t n_rgba) {
+                           size_t n, float4* __restrict__ rgba, size_t n_rgba, const uint32_t* __restrict__ item_start,
+                           int T, uint2* __restrict__ item_tab, uint32_t cap_items) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         cnt[i] = 0u;
         kmin[i] = 0xFFFFFFFFu;
@@ -512,6 +515,10 @@ __global__ void k_fill_pix(uint32_t* __restrict__ cnt, uint32_t* __restrict__ km
     // (and the frame's image, transparent black, when one is given)
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_rgba; i += (size_t)gridDim.x * blockDim.x)
         rgba[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < T; t += gridDim.x * blockDim.x) {
+        const uint32_t i0 = item_start[t], i1 = min(item_start[t + 1], cap_items);
+        for (uint32_t i = i0; i < i1; ++i) item_tab[i] = make_uint2((uint32_t)t, i - i0);
+    }
 }
 
 // Multi-block exclusive scan: each 1024-thread block scans kScanChunk counts and leaves its
@@ -754,35 +761,40 @@ __global__ void k_fill_f32(float* p, float v, size_t n) {
 
 // ---------------------------------------------------------------------------------------
 // Coverage: every fragment of a tile's segments, with the work shared across a wave.  A
-// segment's candidate pixels are enumerated one line at a time along its major axis (rows when
-// |dy| >= |dx|, else columns; u names the major axis, v the minor one), and the lanes of a wave
-// share out all its (segment, line) pairs, 64 per round, so that a wave does not run as long
-// as its longest segment.  On a line, the candidates are the v whose pixel centre lies in the
-// strip |cross| <= R sqrt(t_den) (and, for wide segments, the slab 0 <= t_num <= t_den),
-// widened by 1e-6 pixel, and in the segment's box widened by R; the exact integer predicate
-// decides, the slab 0 <= t_num < t_den included (t_num and |cross| are symmetric under the
-// exchange of x and y, so the same predicate serves both orientations).
+// segment's pixels are taken one line at a time along its major axis (rows when |dy| >= |dx|,
+// else columns; u names the major axis, v the minor one), and the lanes of a wave share out all
+// its (segment, line) pairs, 64 per round, so that a wave does not run as long as its longest
+// segment.  On a line the covered pixels are exactly those of the segment's box (widened by the
+// radius, clipped to the tile and the image) whose centre passes the integer predicate
+// 0 <= t_num < t_den and cross^2 < R^2 t_den.  Along a line both t_num and cross are linear in
+// the minor index (steps 16 dv and 16 du per pixel; t_num and |cross| are symmetric under the
+// exchange of x and y, so one predicate serves both orientations), so each condition holds on
+// an interval of the minor index, and the line's fragments are the intersection of three
+// intervals: no candidate is tested one by one.
 //
 // 32-bit integers are exact here: endpoints lie inside the guard band, |dx|, |dy| <= kMaxAxis
-// (longer segments are culled), the radius is <= kMaxHwFx + 8 and every candidate pixel centre
-// lies in the segment's box widened by the radius, so |e_u|, |e_v| < 2^15 and each product
-// stays under 2^31: the products take the 24-bit multiplier (operands below 2^23), and along a
-// line t_num and cross advance by 16 dv and 16 du per pixel.  cross^2 < R^2 t_den is decided as
-// |cross| <= s_max = floor(sqrt(R^2 t_den - 1)), found per segment in 64-bit integers.
-// x >> 4 is floor(x / 16).
-// The candidate interval is computed in float32: only an enumeration, so it just has to contain
-// every covered pixel.  The strip's centre on line u is linear in u (slope u + base, minor
-// pixel indices, per segment), so a line's interval is one multiply-add and two roundings;
-// each term is a product or difference of values below 2^31 computed with relative error under
-// 1e-6 (float conversions, the hardware reciprocal and square root, roundings), and the
-// half-width is widened by 4e-6 of the magnitudes of all terms plus one sub-pixel (the slab
-// bounds of wide segments by 2e-6 of theirs plus one sub-pixel).
+// (longer segments are drawn as pieces), the radius is <= kMaxHwFx + 8 and every pixel centre
+// of the widened box lies within kMaxAxis + kMaxHwFx + 24 < 2^16 sub-pixels of the first
+// endpoint on each axis, so each product e dv, e du is below 2^30 and t_num, cross are below
+// 2^31 (the products take the 24-bit multiplier: operands below 2^23); s_max < 2^30 and
+// t_den < 2^30.  cross^2 < R^2 t_den is decided as |cross| <= s_max =
+// floor(sqrt(R^2 t_den - 1)), found per segment in 64-bit integers.  x >> 4 is floor(x / 16).
+//
+// The interval ends are floor divisions n / d with d = 16 |du| or 16 |dv| (<= 2^18), exact:
+// only quotients in [-17, 17] matter (a line has at most 16 pixels in a tile), and there n is
+// below 2^23 in magnitude, so float(n) is exact; q = floor(n / d - 2^-16) from the hardware
+// reciprocal is then floor(n / d) or one less (the reciprocal and the fused multiply-add err by
+// under 3e-6 on quotients of that size, less than the 2^-16 bias), and one exact integer test,
+// (q + 1) d <= n, settles it.  Quotients beyond [-17, 17] are clamped to +-17 before the test
+// and stay on their side.
 struct CovSetup {
-    int4 g0;     // (au, av, du, dv): start and extent along the major and minor axes, 1/16 px
-    int4 g1;     // (s_max, tden, first line - lines before this lane in the wave, bits of 1 / dv (wide only))
-    float4 g2;   // (slope, base, half, bits: first | steep << 15 | last minor index << 16 | wide << 31):
-                 // on line u the strip's centre is at minor pixel index slope u + base and its
-                 // half-width, with the enumeration's margin, is half (pixels)
+    int4 g0;     // (c0, t0, dc, dt): cross and t_num at the box's first minor pixel of line l = 0
+                 // and their steps per line, each sign-normalised (c by the sign of du, t by
+                 // that of dv) so that both grow with the minor index at 16 |du| and 16 |dv|
+    int4 g1;     // (s_max, lo, hi, first line - lines before this lane in the wave): the slab
+                 // lo <= t <= hi is 0 <= t_num <= t_den - 1 after the sign normalisation
+    float4 g2;   // (1 / (16 |du|), 1 / max(16 |dv|, 1), bits of 16 |du|,
+                 //  bits of 16 |dv| | first pixel (8 bits) << 19 | last minor offset (4 bits) << 27 | steep << 31)
 };
 
 // The largest s with s^2 < R^2 t_den (R^2 t_den >= 64): a double square root, corrected in
@@ -795,6 +807,15 @@ __device__ inline int strip_smax(int R, int tden) {
     return (int)min(s, 0x7FFFFFFFull);
 }
 constexpr int kCovLinesPerWave = 64 * kTile;   // a segment has at most kTile lines in a tile
+
+// floor(n / d) for 1 <= d <= 2^18 where it lies in [-17, 17]; a quotient beyond that range
+// comes back beyond [-17, 16] on its own side.  rd: the hardware reciprocal of d.
+__device__ inline int floordiv_small(int n, int d, float rd) {
+    float qf = floorf(fmaf((float)n, rd, -0x1p-16f));
+    qf = fminf(fmaxf(qf, -17.0f), 17.0f);
+    const int q = (int)qf;
+    return q + ((__mul24(q, d) + d <= n) ? 1 : 0);
+}
 
 // Stages lane t's segment (valid: the lane holds one) in s_cov[t], numbers the wave's lines
 // and records each line's lane in s_own (kCovLinesPerWave bytes per wave); returns the wave's
@@ -817,24 +838,21 @@ __device__ inline uint32_t cov_setup(const SegRec& s, bool valid, int px0, int p
             const int au = steep ? s.ya : s.xa, av = steep ? s.xa : s.ya;
             const int du = steep ? dy : dx, dv = steep ? dx : dy;
             nl = (uint32_t)(steep ? j1 - j0 + 1 : i1 - i0 + 1);
-            const float inv_du = __builtin_amdgcn_rcpf((float)du);
-            const float inv_dv = dv != 0 ? __builtin_amdgcn_rcpf((float)dv) : 0.0f;
-            const int vmin = steep ? i0 : j0, vmax = steep ? i1 : j1;   // 0 <= vmin <= vmax < 2^14
-            const int u0 = steep ? j0 : i0, u1 = steep ? j1 : i1;
-            const bool wide = R > 32;
-            // the strip's centre line in minor pixel indices: (av + (16 u + 8 - au) dv / du - 8) / 16
-            const float slope = (float)dv * inv_du;
-            const float base = ((float)av - 8.0f) * (1.0f / 16.0f) + (8.0f - (float)au) * slope * (1.0f / 16.0f);
-            const float half = (float)R * __builtin_amdgcn_sqrtf((float)tden) * fabsf(inv_du) * (1.0f / 16.0f);
-            // margin: one sub-pixel plus 4e-6 of the magnitudes of every term (each float step's
-            // relative error is below 1e-6; slope u + base is evaluated with 0 <= u <= u1, and
-            // base's two terms may cancel)
-            const float mag = (fabsf((float)av) + fabsf((float)au * slope)) * (1.0f / 16.0f) +
-                              fabsf(slope) * (float)u1 + half + 1.0f;
-            c.g0 = make_int4(au, av, du, dv);
-            c.g1 = make_int4(strip_smax(R, tden), tden, u0, __float_as_int(inv_dv));
-            c.g2 = make_float4(slope, base, half + (1.0f / 16.0f) + 4e-6f * mag,
-                               __int_as_float(vmin | (steep ? 1 << 15 : 0) | (vmax << 16) | (wide ? (int)0x80000000u : 0)));
+            const int vmin = steep ? i0 : j0, vmax = steep ? i1 : j1;
+            const int u0 = steep ? j0 : i0;
+            const int eu = 16 * u0 + 8 - au, ev = 16 * vmin + 8 - av;
+            const int tn = __mul24(ev, dv) + __mul24(eu, du);   // t_num at (u0, vmin)
+            const int cr = __mul24(ev, du) - __mul24(eu, dv);   // cross at (u0, vmin)
+            // per line eu grows by 16: t_num by 16 du, cross by -16 dv
+            const int sgu = du < 0 ? -1 : 1, sgv = dv < 0 ? -1 : 1;
+            const int B = 16 * abs(du), A = 16 * abs(dv);
+            const int lu = u0 - (steep ? py0 : px0), lv = vmin - (steep ? px0 : py0);   // 0..15
+            const int pix0 = steep ? lu * kTile + lv : lv * kTile + lu;
+            c.g0 = make_int4(sgu * cr, sgv * tn, -16 * sgu * dv, 16 * sgv * du);
+            c.g1 = make_int4(strip_smax(R, tden), dv < 0 ? 1 - tden : 0, dv < 0 ? 0 : tden - 1, 0);
+            c.g2 = make_float4(__builtin_amdgcn_rcpf((float)B), __builtin_amdgcn_rcpf((float)max(A, 1)),
+                               __int_as_float(B),
+                               __int_as_float(A | pix0 << 19 | (vmax - vmin) << 27 | (steep ? (int)0x80000000u : 0)));
         }
     }
     uint32_t x = nl;
@@ -844,7 +862,7 @@ __device__ inline uint32_t cov_setup(const SegRec& s, bool valid, int px0, int p
         if (lane >= off) x += y;
     }
     const uint32_t excl = x - nl;
-    c.g1.z -= (int)excl;     // line index = g1.z + the wave-wide line number
+    c.g1.w = -(int)excl;     // line index = g1.w + the wave-wide line number
     s_cov[t] = c;
     uint8_t* own = s_own + (t >> 6) * kCovLinesPerWave;
     for (uint32_t r = 0; r < nl; ++r) own[excl + r] = (uint8_t)lane;
@@ -853,48 +871,47 @@ __device__ inline uint32_t cov_setup(const SegRec& s, bool valid, int px0, int p
     return total;
 }
 
-// Calls f(li, lj, tnum, tden, owner) for every fragment of the wave's segments in this tile
-// (owner: the block thread whose segment it is).  total and the staging from cov_setup.
+// Calls f(p, tnum, tden, owner) for every fragment of the wave's segments in this tile (p: the
+// pixel's index in the tile; owner: the block thread whose segment it is).  total and the
+// staging from cov_setup.
 template <class F>
-__device__ inline void wave_coverage(const CovSetup* s_cov, const uint8_t* s_own, uint32_t total, int px0, int py0,
-                                     F&& f) {
+__device__ inline void wave_coverage(const CovSetup* s_cov, const uint8_t* s_own, uint32_t total, F&& f) {
     const int t = threadIdx.x, lane = t & 63, wbase = t & ~63;
     const uint8_t* own = s_own + (t >> 6) * kCovLinesPerWave;
     for (uint32_t g = (uint32_t)lane; g < total; g += 64) {
         const int o = wbase + own[g];
         const CovSetup c = s_cov[o];
-        const int au = c.g0.x, av = c.g0.y, du = c.g0.z, dv = c.g0.w;
-        const int smax = c.g1.x, tden = c.g1.y, u = c.g1.z + (int)g;
-        const int vb = __float_as_int(c.g2.w);
-        const bool steep = (vb & (1 << 15)) != 0;
-        const int vmin = vb & 0x7FFF, vmax = (vb >> 16) & 0x7FFF;
-        const int eu = 16 * u + 8 - au;
-        const int eu_du = __mul24(eu, du), eu_dv = __mul24(eu, dv);
-        // the strip bounds the span; the slab trims it too for wide segments (radius above
-        // 2 px: thick hairs, whose short steps would otherwise test most of their box), while
-        // for strands it would only trim the end lines, whose extra candidates the integer
-        // test rejects
-        const float m = fmaf((float)u, c.g2.x, c.g2.y);
-        float flo = m - c.g2.z, fhi = m + c.g2.z;
-        if (vb < 0 && dv != 0) {   // wide
-            const float inv_dv = __int_as_float(c.g1.w);
-            const float a = (float)(-eu_du) * inv_dv, b = (float)(tden - eu_du) * inv_dv;
-            const float w = 1.0f + 2e-6f * (fabsf((float)av) + fmaxf(fabsf(a), fabsf(b)));
-            flo = fmaxf(flo, ((float)av + (fminf(a, b) - w) - 8.0f) * (1.0f / 16.0f));
-            fhi = fminf(fhi, ((float)av + (fmaxf(a, b) + w) - 8.0f) * (1.0f / 16.0f));
+        const int l = c.g1.w + (int)g;                       // line within the box, 0..15
+        const int cl = c.g0.x + __mul24(l, c.g0.z);          // at the box's first minor pixel
+        const int tl = c.g0.y + __mul24(l, c.g0.w);
+        const int smax = c.g1.x, lo = c.g1.y, hi = c.g1.z;
+        const int B = __float_as_int(c.g2.z);
+        const int bits = __float_as_int(c.g2.w);
+        const int A = bits & 0x7FFFF;
+        // strip: -s_max <= cl + x B <= s_max; slab: lo <= tl + x A <= hi.  Values that leave
+        // a condition false on all of x = 0..15 are clamped to just beyond that range first, so
+        // that the numerators stay below 2^31.
+        const int m = smax + 16 * B;
+        const int cc = min(max(cl, -m), m);
+        int x0 = max(0, -floordiv_small(smax + cc, B, c.g2.x));
+        int x1 = min((bits >> 27) & 15, floordiv_small(smax - cc, B, c.g2.x));
+        if (A > 0) {
+            const int tc = min(max(tl, lo - 16 * A), hi + 1);
+            x0 = max(x0, -floordiv_small(tc - lo, A, c.g2.y));
+            x1 = min(x1, floordiv_small(hi - tc, A, c.g2.y));
+        } else if (tl < lo || tl > hi) {
+            x1 = -1;
         }
-        const int k0 = (int)fmaxf((float)vmin, ceilf(flo));
-        const int k1 = (int)fminf((float)vmax, floorf(fhi));
-        const int ev0 = 16 * k0 + 8 - av;
-        int tnum = __mul24(ev0, dv) + eu_du;
-        int cr = __mul24(ev0, du) - eu_dv;
-        const int dv16 = dv * 16, du16 = du * 16;
-        for (int k = k0; k <= k1; ++k, tnum += dv16, cr += du16) {
-            if (tnum < 0 || tnum >= tden) continue;
-            if ((unsigned)abs(cr) > (unsigned)smax) continue;
-            if (steep) f(k - px0, u - py0, tnum, tden, o);
-            else f(u - px0, k - py0, tnum, tden, o);
-        }
+        if (x0 > x1) continue;
+        const int tden = hi - lo + 1;
+        const int sv = bits < 0 ? 1 : kTile;                  // pixel step along the minor axis
+        int p = ((bits >> 19) & 0xFF) + __mul24(l, bits < 0 ? kTile : 1) + __mul24(x0, sv);
+        // t_num itself: the normalised t times the sign of dv (lo < 0 exactly when dv < 0, as
+        // then t_den >= 2)
+        const int sgn = lo < 0 ? -1 : 1;
+        int tnum = sgn * (tl + __mul24(x0, A));
+        const int tstep = sgn * A;
+        for (int xx = x0; xx <= x1; ++xx, p += sv, tnum += tstep) f(p, tnum, tden, o);
     }
 }
 
@@ -1237,16 +1254,6 @@ __device__ inline uint32_t block_exscan_u32(uint32_t v, uint32_t* s_tmp, uint32_
 #endif
 
 // Work items of the count and emit kernels: chunks of kNT consecutive entries of a tile list.
-__device__ inline void item_of(const uint32_t* item_start, int T, uint32_t item, int& tile, uint32_t& chunk) {
-    int lo = 0, hi = T - 1;   // last tile with item_start[tile] <= item
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (item_start[mid] <= item) lo = mid; else hi = mid - 1;
-    }
-    tile = lo;
-    chunk = item - item_start[lo];
-}
-
 __global__ __launch_bounds__(256) void k_tile_items(const uint32_t* __restrict__ tile_start, int T,
                                                     uint32_t* __restrict__ items) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1261,32 +1268,22 @@ __global__ __launch_bounds__(kNT) void k_count(FrameBufs f, CamConst cam) {
     __shared__ uint32_t s_cnt[kTilePix];
     __shared__ CovSetup s_cov[kNT];
     __shared__ uint8_t s_own[kNT / 64 * kCovLinesPerWave];
-    __shared__ int s_tile;
-    __shared__ uint32_t s_chunk;
     PHASE_BEGIN();
     const uint32_t n_items = f.item_start[f.T];
     if (blockIdx.x >= n_items || f.ctr->cap_overflow) return;
     const uint32_t item = xcd_contiguous(blockIdx.x, n_items);
     const int t = threadIdx.x;
-    if (t == 0) {
-        int tile;
-        uint32_t chunk;
-        item_of(f.item_start, f.T, item, tile, chunk);
-        s_tile = tile;
-        s_chunk = chunk;
-    }
+    const uint2 it = f.item_tab[item];
+    const int tile = (int)it.x;
     s_cnt[t] = 0;
-    __syncthreads();
-    const int tile = s_tile;
     const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
     const uint32_t lstart = f.tile_start[tile];
     const uint32_t n = f.tile_start[tile + 1] - lstart;
-    const uint32_t j = s_chunk * kNT + t;
+    const uint32_t j = it.y * kNT + t;
     SegRec s{};
     if (j < n) s = f.seg[f.list[lstart + j]];
     const uint32_t total = cov_setup(s, j < n, px0, py0, cam.W, cam.H, s_cov, s_own);
-    wave_coverage(s_cov, s_own, total, px0, py0,
-                  [&](int li, int lj, int, int, int) { atomicAdd(&s_cnt[lj * kTile + li], 1u); });
+    wave_coverage(s_cov, s_own, total, [&](int p, int, int, int) { atomicAdd(&s_cnt[p], 1u); });
     __syncthreads();
     const size_t q = (size_t)tile * kTilePix + t;
     uint32_t base = 0;
@@ -1394,22 +1391,13 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam) {
     __shared__ CovSetup s_cov[kNT];
     __shared__ uint8_t s_own[kNT / 64 * kCovLinesPerWave];
     __shared__ float2 s_iz[kNT];
-    __shared__ int s_tile;
-    __shared__ uint32_t s_chunk;
     PHASE_BEGIN();
     const uint32_t n_items = f.item_start[f.T];
     if (blockIdx.x >= n_items || f.ctr->cap_overflow) return;
     const uint32_t item = xcd_contiguous(blockIdx.x, n_items);
     const int t = threadIdx.x;
-    if (t == 0) {
-        int tile;
-        uint32_t chunk;
-        item_of(f.item_start, f.T, item, tile, chunk);
-        s_tile = tile;
-        s_chunk = chunk;
-    }
-    __syncthreads();
-    const int tile = s_tile;
+    const uint2 it = f.item_tab[item];
+    const int tile = (int)it.x;
     const size_t q = (size_t)tile * kTilePix + t;
     s_cur[t] = 0;
     s_kmin[t] = 0xFFFFFFFFu;
@@ -1419,7 +1407,7 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam) {
     const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
     const uint32_t lstart = f.tile_start[tile];
     const uint32_t n = f.tile_start[tile + 1] - lstart;
-    const uint32_t j = s_chunk * kNT + t;
+    const uint32_t j = it.y * kNT + t;
     SegRec s{};
     uint32_t gseg = 0;
     if (j < n) {
@@ -1429,8 +1417,7 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam) {
     s_iz[t] = make_float2(s.iza, s.izb);
     s_id[t] = f.gid ? gseg : j;
     const uint32_t total = cov_setup(s, j < n, px0, py0, cam.W, cam.H, s_cov, s_own);
-    wave_coverage(s_cov, s_own, total, px0, py0, [&](int li, int lj, int tnum, int tden, int o) {
-        const int p = lj * kTile + li;
+    wave_coverage(s_cov, s_own, total, [&](int p, int tnum, int tden, int o) {
         const float2 iz = s_iz[o];
         const uint32_t key = depth_key_iz(iz.x, iz.y, tnum, tden);
         const uint32_t slot = atomicAdd(&s_cur[p], 1u);
@@ -3315,12 +3302,12 @@ hipError_t launch_check_caps(const FrameBufs& f, const FrameCaps& caps, int stag
 }
 
 hipError_t launch_fill_pix(uint32_t* cnt, uint32_t* kmin, uint32_t* kmax, size_t n, float* rgba, size_t n_rgba4,
-                           hipStream_t st) {
-    const size_t m = std::max(n, n_rgba4);
+                           const uint32_t* item_start, int T, uint2* item_tab, uint32_t cap_items, hipStream_t st) {
+    const size_t m = std::max(std::max(n, n_rgba4), (size_t)T);
     if (m == 0) return hipSuccess;
     const int nb = (int)std::min<size_t>((m + 255) / 256, 4096);
     hipLaunchKernelGGL(k_fill_pix, dim3(nb), dim3(256), 0, st, cnt, kmin, kmax, n, reinterpret_cast<float4*>(rgba),
-                       rgba ? n_rgba4 : 0);
+                       rgba ? n_rgba4 : 0, item_start, T, item_tab, cap_items);
     return hipGetLastError();
 }
 
