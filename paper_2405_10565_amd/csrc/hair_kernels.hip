@@ -797,11 +797,14 @@ struct CovSetup {
                  //  bits of 16 |dv| | first pixel (8 bits) << 19 | last minor offset (4 bits) << 27 | steep << 31)
 };
 
-// The largest s with s^2 < R^2 t_den (R^2 t_den >= 64): a double square root, corrected in
-// 64-bit integers, so that |cross| <= s_max is exactly cross^2 < R^2 t_den.
+// The largest s with s^2 < R^2 t_den (R^2 t_den >= 64): a square root, corrected in 64-bit
+// integers, so that |cross| <= s_max is exactly cross^2 < R^2 t_den.  Below 2^48 (every
+// strand) the float square root is within 3 of s (relative error under 2^-22 on s < 2^24),
+// above it the double one.
 __device__ inline int strip_smax(int R, int tden) {
     const unsigned long long lim = (unsigned long long)(unsigned)(R * R) * (unsigned)tden - 1ull;
-    unsigned long long s = (unsigned long long)sqrt((double)lim);
+    unsigned long long s = lim < (1ull << 48) ? (unsigned long long)__builtin_amdgcn_sqrtf((float)lim)
+                                              : (unsigned long long)sqrt((double)lim);
     while (s * s > lim) --s;
     while ((s + 1) * (s + 1) <= lim) ++s;
     return (int)min(s, 0x7FFFFFFFull);
