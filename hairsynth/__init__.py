@@ -19,6 +19,16 @@ Recipe (all float64, stored float32):
   * per step: d <- normalize(d + 0.3 N(0, I3) + (0, -0.2, 0)); x <- x + 0.01 d.
   * width 80e-6 m (a diameter); sigma_a = (0.3, 0.6, 1.2), optionally times exp(0.2 z).
   * material: eta 1.55, longitudinal shift -3 deg, beta_m = beta_n = 0.3 rad.
+
+Clumped grooms (make_asset(..., clumps=K)): strands in K locks that follow a guide, the
+structure of combed or styled hair.  Draws: U[K], V[K] for the guide roots (the cap as above),
+then R[n], A[n] for the members' root offsets, then per step a standard normal (K, 3) block
+for the guides followed by a standard normal (n, 3) block for the members, then the optional
+absorption spread z[n].  Strand s belongs to lock s * K // n (consecutive strands share a
+lock); its root is the guide's root plus an offset of radius clump_radius sqrt(R) at angle
+2 pi A in the guide root's tangent plane, put back on the sphere of radius 0.1; it starts
+along its own outward normal.  Per step the guide turns as above, and each member takes the
+guide's new direction plus clump_noise N(0, I3), normalised, and advances 0.01.
 """
 from __future__ import annotations
 
@@ -139,7 +149,11 @@ def _normalize(v: np.ndarray) -> np.ndarray:
 
 
 def make_asset(n_strands: int, segs: int, cap_deg: float = 90.0, seed: int = 0,
-               sigma_spread: bool = False, material: Material | None = None) -> Asset:
+               sigma_spread: bool = False, material: Material | None = None, clumps: int = 0,
+               clump_radius: float = 1e-3, clump_noise: float = 0.02, flow: float = 0.0) -> Asset:
+    if clumps > 0:
+        return _make_clumped(n_strands, segs, cap_deg, seed, sigma_spread, material, clumps, clump_radius,
+                             clump_noise, flow)
     rng = np.random.Generator(np.random.PCG64(seed))
     n = int(n_strands)
     U = rng.random(n)
@@ -170,27 +184,96 @@ def make_asset(n_strands: int, segs: int, cap_deg: float = 90.0, seed: int = 0,
                  material or Material())
 
 
-def kmeans_assign(asset: Asset, k: int, seed: int, iters: int = 25, init: str = "kmeans++") -> np.ndarray:
+def _cap_points(U: np.ndarray, V: np.ndarray, cap_deg: float) -> np.ndarray:
+    cos_cap = math.cos(math.radians(cap_deg))
+    cos_t = 1.0 - U * (1.0 - cos_cap)
+    sin_t = np.sqrt(np.maximum(0.0, 1.0 - cos_t * cos_t))
+    az = 2.0 * math.pi * V
+    return np.stack([sin_t * np.cos(az), cos_t, sin_t * np.sin(az)], axis=1)
+
+
+def _make_clumped(n_strands, segs, cap_deg, seed, sigma_spread, material, clumps, clump_radius, clump_noise,
+                  flow=0.0, flow_modes=8, flow_wavelength=0.15):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = int(n_strands)
+    K = max(1, min(int(clumps), n))
+    gU = rng.random(K)
+    gV = rng.random(K)
+    g_normal = _cap_points(gU, gV, cap_deg)
+    R = rng.random(n)
+    A = rng.random(n)
+    if flow > 0.0:   # a smooth random field over the scalp: flow_modes plane waves per step
+        w_dir = _normalize(rng.standard_normal((flow_modes, 3)))
+        w_amp = rng.standard_normal((segs, flow_modes, 3)) / math.sqrt(flow_modes)
+        w_phase = 2.0 * math.pi * rng.random((segs, flow_modes))
+        w_proj = (0.1 * g_normal) @ w_dir.T * (2.0 * math.pi / flow_wavelength)   # [K, modes]
+    lock = (np.arange(n, dtype=np.int64) * K) // n
+    # an orthonormal tangent frame at each guide root
+    ref = np.where(np.abs(g_normal[:, 1:2]) < 0.9, np.array([[0.0, 1.0, 0.0]]), np.array([[1.0, 0.0, 0.0]]))
+    t1 = _normalize(np.cross(g_normal, ref))
+    t2 = np.cross(g_normal, t1)
+    rad = clump_radius * np.sqrt(R)
+    ang = 2.0 * math.pi * A
+    root = 0.1 * g_normal[lock] + (rad * np.cos(ang))[:, None] * t1[lock] + (rad * np.sin(ang))[:, None] * t2[lock]
+    normal = _normalize(root)
+    x = 0.1 * normal
+    d = normal.copy()
+    dg = g_normal.copy()
+    verts = np.empty((n, segs + 1, 3), dtype=np.float64)
+    verts[:, 0] = x
+    drift = np.array([0.0, -0.2, 0.0])
+    for k in range(segs):
+        noise = rng.standard_normal((K, 3))
+        if flow > 0.0:
+            smooth = np.cos(w_proj + w_phase[k][None, :]) @ w_amp[k]                    # [K, 3]
+            noise = math.sqrt(1.0 - flow * flow) * noise + flow * math.sqrt(2.0) * smooth
+        dg = _normalize(dg + 0.3 * noise + drift)
+        d = _normalize(dg[lock] + clump_noise * rng.standard_normal((n, 3)))
+        x = x + 0.01 * d
+        verts[:, k + 1] = x
+    xyz = np.ascontiguousarray(verts.reshape(n * (segs + 1), 3).T.astype(np.float32))
+    width = np.full(n, 80e-6, dtype=np.float32)
+    base = np.array([0.3, 0.6, 1.2])
+    if sigma_spread:
+        z = rng.standard_normal(n)
+        sig = base[:, None] * np.exp(0.2 * z)[None, :]
+    else:
+        sig = np.repeat(base[:, None], n, axis=1)
+    return Asset(n, segs, xyz, width, np.ascontiguousarray(sig.astype(np.float32)),
+                 material or Material())
+
+
+def kmeans_assign(asset: Asset, k: int, seed: int, iters: int = 25, init: str = "kmeans++",
+                  features: str = "root") -> np.ndarray:
     """Cluster assignment used as the LoD builder's input (int32 [n_strands], dense labels).
 
-    Features: [root / 0.1, first-segment tangent] (6-D, float64).  Seeding drawn from
+    Features (float64): "root" = [root / 0.1, first-segment tangent] (6-D); "path" = the
+    positions of 4 vertices evenly spaced along the strand (root to tip, 12-D), so that the
+    squared feature distance is the sum of squared distances between corresponding points of
+    two strands (the clustering metric of Sec. 5.1 step 1 with 4 control points).  Seeding drawn from
     PCG64(seed): k-means++ (default) or, for large k, k distinct random strands
     (init="random"); then `iters` Lloyd iterations; distance ties go to the lower centre
     index (argmin; above 512 centres a k-d tree finds the exact nearest centre); empty
     clusters are dropped and labels renumbered densely in order.
     """
-    return _kmeans(strand_features(asset), k, seed, iters, init)
+    return _kmeans(strand_features(asset, features), k, seed, iters, init)
 
 
-def strand_features(asset: Asset) -> np.ndarray:
+def strand_features(asset: Asset, features: str = "root") -> np.ndarray:
+    if features == "path":
+        v = asset.verts_per_strand
+        pts = asset.xyz.reshape(3, asset.n_strands, v).astype(np.float64)
+        idx = np.round(np.linspace(0, v - 1, 4)).astype(np.int64)
+        return np.ascontiguousarray(pts[:, :, idx].transpose(1, 2, 0).reshape(asset.n_strands, 12))
     return np.concatenate([asset.roots() / 0.1, asset.first_tangents()], axis=1)
 
 
-def kmeans_hierarchy(asset: Asset, ks, seed: int, iters: int = 25, init: str = "kmeans++") -> list:
+def kmeans_hierarchy(asset: Asset, ks, seed: int, iters: int = 25, init: str = "kmeans++",
+                     features: str = "root") -> list:
     """Nested assignments for the levels finer -> coarser (ks descending): the finest level is
     k-means on the strand features; each coarser level is k-means on the previous level's
     cluster mean features, so every cluster lies inside one cluster of each coarser level."""
-    feats = strand_features(asset)
+    feats = strand_features(asset, features)
     lab = _kmeans(feats, ks[0], seed, iters, init)
     out = [lab]
     for li, k in enumerate(ks[1:], start=1):

@@ -4,6 +4,7 @@
     python -m paper_2405_10565_amd.experiments fit [--iters N] [--scale S]
     python -m paper_2405_10565_amd.experiments shadow [--iters N]
     python -m paper_2405_10565_amd.experiments curved [--scale S]
+    python -m paper_2405_10565_amd.experiments views [--scale S]
 
 lod-sweep: 150k strands x 64 segments at 1920 x 1080, clustered by k-means on root position
 and first tangent into 10k, 1k and 100 thick hairs (Sec. 5.1); every level is rendered and
@@ -18,6 +19,13 @@ checked against central differences (h = 1e-3 in log space) on 20 random paramet
 curved: the LoD sweep's groom reduced to 1k thick hairs at 1080p, rendered with polyline
 centre lines and with curved ones tessellated to at most 4, 2 and 1 px per step (Sec. 5.2,
 Sec. 6); steps, fragments, frame ms and the RGB difference to the polyline frame.
+
+views: 100k x 32 strands in locks of 16 following a smooth flow (then the random-walk groom of
+the other workloads) with nested levels of 6250 / 1562 / 390 thick hairs (k-means on the
+strands' paths), at the near, middle and far views of Sec. 6 (the bounding sphere covering
+50%, 10% and 0.3% of a 1920 x 1080 image): the strand frame, the level chosen per request at
+eps_w = 2 px and the per-group mixed-level frame; fragments, GPU ms and the RGB error against
+the strand frame.
 
 shadow: the 100k-strand 1080p frame with deep opacity map shadows (1024 x 1024 texels, 4
 layers of 2 cm, Sec. 5.2) rendered N times after two warm-up frames; GPU ms per frame.
@@ -235,9 +243,75 @@ def shadow_frames(hctx: B.Context, iters: int = 20, shadow=(1024, 4, 0.02)):
     return out
 
 
+def view_distances(hctx: B.Context, occupancies=(0.5, 0.1, 0.003), repeats: int = 20, eps_w: float = 2.0,
+                   spec=(100_000, 32), clumped: bool = True, width: int = 1920, height: int = 1080):
+    """The LoD at the near, middle and far views of Sec. 6 (the groom's bounding sphere covering
+    50%, 10% and 0.3% of the image): the strand frame against the level chosen per request
+    (hair_select_level at eps_w) and the per-group mixed-level frame (hair_lod_init at eps_w),
+    each timed and compared with the strand frame of the same view.  The groom: spec strands
+    in locks of 16 that follow a smooth flow (clumped), or the random-walk groom of the other
+    workloads; levels of one thick hair per 16 / 64 / 256 strands (the cross-section growing
+    about fourfold per level, Sec. 5.1), nested k-means on the strands' paths (4 points each,
+    the metric of Sec. 5.1 step 1), the 390 coarsest clusters being the LoD groups."""
+    import torch
+    import hairsynth as hs
+    from . import serve as S
+    n, segs = spec
+    asset = hs.make_asset(n, segs, 90.0, seed=1002, sigma_spread=True, clumps=max(1, n // 16) if clumped else 0,
+                          flow=0.99 if clumped else 0.0)
+    aid = hctx.upload_asset(asset)
+    t0 = time.perf_counter()
+    assigns = hs.kmeans_hierarchy(asset, [max(1, n // d) for d in (16, 64, 256)], seed=1002, iters=20,
+                                  features="path")
+    t_kmeans = time.perf_counter() - t0
+    hctx.build_lod(aid, assigns)
+    _, counts, S_ = hctx.lod_info(aid)
+    a = S.ServedAsset(aid, asset, hs.default_lights(asset, with_point=True), [c * S_ for c in counts],
+                      hctx.lod_groups(aid), assigns)
+    ws = hctx.workspace()
+    out = {"experiment": "views", "groom": "locks of 16 strands, smooth flow" if clumped else "random walk",
+           "strands": a.asset.n_strands, "segments": a.asset.n_segments, "kmeans_s": round(t_kmeans, 2),
+           "thick_hairs_per_level": [int(c) for c in counts[1:]], "width": width,
+           "height": height, "eps_w": eps_w, "views": []}
+
+    def timed(fn):
+        img, st, _ = fn(None)
+        ms = []
+        for _ in range(repeats):
+            _, s2, _ = fn(img)
+            ms.append(s2["ms_total"])
+        torch.cuda.synchronize()
+        return img.clone(), st, round(float(np.percentile(ms, 50)), 4)
+
+    for occ in occupancies:
+        cam = hs.camera_occupancy(a.asset, width, height, occ)
+        ref, st0, ms0 = timed(lambda o: hctx.render(a.aid, 0, cam, a.lights, out=o, ws=ws))
+        level = hctx.select_level(a.aid, cam, eps_w, ws=ws)
+        img1, st1, ms1 = timed(lambda o: hctx.render(a.aid, level, cam, a.lights, out=o, ws=ws))
+        lev = torch.empty((a.groups, a.asset.segs), dtype=torch.int32, device=f"cuda:{hctx.device}")
+        hctx.lod_init(a.aid, cam, eps_w, lev, ws=ws)
+        hist = np.bincount(lev.cpu().numpy().reshape(-1), minlength=len(a.segments_per_level))
+        img2, st2, ms2 = timed(lambda o: hctx.render_mixed(a.aid, cam, a.lights, lev, out=o, ws=ws))
+        v = {"occupancy": occ,
+             "strands": {"segments": int(st0["segments"]), "fragments": int(st0["fragments"]), "frame_ms_p50": ms0},
+             "selected_level": {"level": int(level), "segments": int(st1["segments"]),
+                                "fragments": int(st1["fragments"]), "frame_ms_p50": ms1},
+             "mixed": {"cells_per_level": [round(float(x), 4) for x in hist / hist.sum()],
+                       "segments": int(st2["segments"]), "fragments": int(st2["fragments"]), "frame_ms_p50": ms2}}
+        for key, img in (("selected_level", img1), ("mixed", img2)):
+            rmse, psnr = _rgb_error(img, ref)
+            v[key]["rmse"] = round(rmse, 6)
+            v[key]["psnr_db"] = round(psnr, 2)
+        out["views"].append(v)
+        print(json.dumps({"occupancy": occ, "done": True}), flush=True)
+    ws.close()
+    hctx.release(a.aid)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["lod-sweep", "fit", "shadow", "curved"])
+    ap.add_argument("what", choices=["lod-sweep", "fit", "shadow", "curved", "views"])
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--iters", type=int, default=200)
     args = ap.parse_args()
@@ -248,6 +322,10 @@ def main():
         print(json.dumps(lod_sweep(hctx, args.scale)), flush=True)
     elif args.what == "curved":
         print(json.dumps(curved_frames(hctx, args.scale)), flush=True)
+    elif args.what == "views":
+        spec = (max(1, int(round(100_000 * args.scale))), 32)
+        for clumped in (True, False):
+            print(json.dumps(view_distances(hctx, spec=spec, clumped=clumped)), flush=True)
     elif args.what == "shadow":
         print(json.dumps(shadow_frames(hctx, args.iters if args.iters != 200 else 20)), flush=True)
     else:
