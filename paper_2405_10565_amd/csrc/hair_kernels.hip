@@ -363,19 +363,36 @@ __global__ __launch_bounds__(256) void k_sel_fill(HierDev h, const int32_t* __re
         sel[o + (uint32_t)(i - b)] = ((uint32_t)L << 28) | (uint32_t)(h.grp_owner[L][i] * h.S + k);
 }
 
+// (records staged in LDS and stored as consecutive 16-byte words, as in k_project)
 __global__ __launch_bounds__(256) void k_project_mixed(HierDev h, const uint32_t* __restrict__ sel, int nsel,
                                                        CamConst cam, SegRec* __restrict__ seg,
                                                        ShadeRec* __restrict__ shade) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nsel) return;
-    const uint32_t e = sel[i];
-    const int L = (int)(e >> 28), g = (int)(e & 0x0FFFFFFFu);
-    SegRec r = project_segment(h.lv[L], g, cam, shade + i);
-    if (h.lv[L].kind == 1) r.hwfx |= kFlagThick;
-    // (a strand row's q3 is otherwise unused: its world radius, and -1 marking a strand, for
-    // the shadow pass, which reads the rows' world data from these records)
-    else shade[i].q3 = make_float4(0.5f * h.lv[L].width[g / h.lv[L].S], 0.0f, 0.0f, -1.0f);
-    seg[i] = r;
+    __shared__ float4 s_seg[2 * 256];
+    __shared__ float4 s_sh[4 * 256];
+    const int t = threadIdx.x, i0 = blockIdx.x * 256, i = i0 + t;
+    if (i < nsel) {
+        const uint32_t e = sel[i];
+        const int L = (int)(e >> 28), g = (int)(e & 0x0FFFFFFFu);
+        ShadeRec sr;
+        sr.q3 = make_float4(0.f, 0.f, 0.f, 0.f);
+        SegRec r = project_segment(h.lv[L], g, cam, &sr);
+        if (h.lv[L].kind == 1) r.hwfx |= kFlagThick;
+        // (a strand row's q3 is otherwise unused: its world radius, and -1 marking a strand, for
+        // the shadow pass, which reads the rows' world data from these records)
+        else sr.q3 = make_float4(0.5f * h.lv[L].width[g / h.lv[L].S], 0.0f, 0.0f, -1.0f);
+        s_seg[2 * t] = make_float4(__int_as_float(r.xa), __int_as_float(r.ya), __int_as_float(r.xb), __int_as_float(r.yb));
+        s_seg[2 * t + 1] = make_float4(__int_as_float(r.hwfx), r.iza, r.izb, r.hw);
+        s_sh[4 * t] = sr.q0;
+        s_sh[4 * t + 1] = sr.q1;
+        s_sh[4 * t + 2] = sr.q2;
+        s_sh[4 * t + 3] = sr.q3;
+    }
+    __syncthreads();
+    const int n = min(256, nsel - i0);
+    float4* dseg = reinterpret_cast<float4*>(seg + i0);
+    for (int k = t; k < 2 * n; k += 256) dseg[k] = s_seg[k];
+    float4* dsh = reinterpret_cast<float4*>(shade + i0);
+    for (int k = t; k < 4 * n; k += 256) dsh[k] = s_sh[k];
 }
 
 // Exclusive scan of n counts by one 1024-thread block in coalesced chunks of 4096 (four
@@ -1662,9 +1679,51 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
     // each fragment's segment inputs are fetched one fragment ahead, so that the gathers
     // overlap the shading arithmetic.  (Not for the R / TT / TRT thick-hair shading: its
     // registers would then exceed the budget of three waves per SIMD.)
-    constexpr bool kAhead = KIND == 0 || MODEL == 1;
+    constexpr bool kAhead = KIND != 2 && (KIND == 0 || MODEL == 1);
     const uint32_t run = (Fb + kNT - 1) / kNT;   // at most kPerThread
     const uint32_t rb = min(Fb, t * run), re = min(Fb, rb + run);
+    // Mixed frames shade before they blend: a wave whose lanes held both strand and thick-hair
+    // fragments would run both shading paths in turn, so the batch's fragments are listed
+    // strands first, thick hairs after, shaded kNT at a time down that list (only the wave at
+    // the boundary holds both kinds), and each one's (alpha, L) is staged in LDS for the blend.
+    // (Not with the debug dump, which also records h, nor in a batch of strands alone.)
+    bool staged = false;
+    float4* s_res = reinterpret_cast<float4*>(s_A);   // free once the batch is ordered
+    if (KIND == 2 && !has_dbg) {
+        uint16_t* s_lst = reinterpret_cast<uint16_t*>(reinterpret_cast<uint32_t*>(s_A) + 4 * kCap);
+        uint32_t thick = 0, ns = 0;
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+            const uint32_t i = t + k * kNT;
+            if (i < Fb) {
+                if (a.seg[seg_of(s_B[i].y, list, gid)].hwfx & kFlagThick) thick |= 1u << k;
+                else ++ns;
+            }
+        }
+        uint32_t ex;
+        const uint32_t tot = block_exscan_u32(ns | (uint32_t)__popc(thick) << 16, s_tmp, ex);
+        const uint32_t n_s = tot & 0xFFFFu;
+        staged = (tot >> 16) > 0;   // uniform across the block
+        if (staged) {
+            uint32_t ps = ex & 0xFFFFu, pt = n_s + (ex >> 16);
+#pragma unroll
+            for (int k = 0; k < kPerThread; ++k) {
+                const uint32_t i = t + k * kNT;
+                if (i < Fb) s_lst[((thick >> k) & 1u) ? pt++ : ps++] = (uint16_t)i;
+            }
+            __syncthreads();
+            for (uint32_t jj = t; jj < Fb; jj += kNT) {
+                const uint32_t i = s_lst[jj];
+                const uint2 rec = s_B[i];
+                const uint32_t p = rec.y >> 24;
+                float al, hh, L[3];
+                shade_inputs<KIND, MODEL, SHADOW>(a, fetch_segment<KIND>(a, seg_of(rec.y, list, gid)),
+                                                  px0 + (int)(p % kTile), py0 + (int)(p / kTile), al, hh, L);
+                s_res[i] = make_float4(al, L[0], L[1], L[2]);
+            }
+            __syncthreads();
+        }
+    }
     uint32_t gs[kAhead ? kPerThread : 1];
     SegInputs nxt{};
     if (kAhead) {
@@ -1688,21 +1747,28 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
         }
     };
     for (uint32_t i = rb; i < re; ++i) {
-        if (!kAhead) gs[0] = seg_of(s_B[i].y, list, gid);
-        const SegInputs cur = kAhead ? nxt : fetch_segment<KIND>(a, gs[0]);
-        const uint32_t gseg = gs[0];
-        if (kAhead) {
-#pragma unroll
-            for (int j = 0; j + 1 < (kAhead ? kPerThread : 1); ++j) gs[j] = gs[j + 1];
-            if (i + 1 < re) nxt = fetch_segment<KIND>(a, gs[0]);
-        }
         const uint2 rec = s_B[i];
         const uint32_t p = rec.y >> 24;
         const uint32_t p_beg = s_off[p], p_end = s_off[p + 1];
         if (i == p_beg) { C0 = C1 = C2 = 0.f; T = 1.f; head = 1; }
         const int gx = px0 + (int)(p % kTile), gy = py0 + (int)(p / kTile);
         float al, hh, L[3];
-        shade_inputs<KIND, MODEL, SHADOW>(a, cur, gx, gy, al, hh, L);
+        uint32_t gseg = 0;
+        if (KIND == 2 && staged) {
+            const float4 r = s_res[i];
+            al = r.x; L[0] = r.y; L[1] = r.z; L[2] = r.w;
+            hh = 0.f;
+        } else {
+            if (!kAhead) gs[0] = seg_of(rec.y, list, gid);
+            const SegInputs cur = kAhead ? nxt : fetch_segment<KIND>(a, gs[0]);
+            gseg = gs[0];
+            if (kAhead) {
+#pragma unroll
+                for (int j = 0; j + 1 < (kAhead ? kPerThread : 1); ++j) gs[j] = gs[j + 1];
+                if (i + 1 < re) nxt = fetch_segment<KIND>(a, gs[0]);
+            }
+            shade_inputs<KIND, MODEL, SHADOW>(a, cur, gx, gy, al, hh, L);
+        }
         C0 += T * (al * L[0]);
         C1 += T * (al * L[1]);
         C2 += T * (al * L[2]);
@@ -1870,7 +1936,9 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 &
     __shared__ float s_scale[kTilePix];   // count / (key range + 1): the bucket map of the ordering
     __shared__ uint32_t s_tmp[kNT];
     __shared__ __align__(16) uint2 s_B[kCap];
-    __shared__ __align__(16) uint32_t s_work[3 * kCap];   // staged records (2 words) + bucket counters
+    // staged records (2 words) + bucket counters; in mixed frames also, after the ordering, each
+    // fragment's (alpha, L) and the batch's fragments listed strands first (kCap 16-bit entries)
+    __shared__ __align__(16) uint32_t s_work[KIND == 2 ? 4 * kCap + kCap / 2 : 3 * kCap];
     __shared__ float s_agg[kNT / 64 * 4];     // wave aggregates of the blend scan (C rgb, T)
     __shared__ uint32_t s_aggh[kNT / 64];
     __shared__ float s_slice[4];
