@@ -110,7 +110,7 @@ struct hair_ws {
     uint64_t held = 0;
     DevBuf seg, shade, scan_tmp, tile_cnt, tile_start, bin_m, bin_blk, list, ctr, sel_cnt, sel_start, sel, sel_tmp;
     DevBuf pieces;                            // rows of a frame drawn with long segments as pieces
-    DevBuf items, item_start, item_tab, item_base, pix_cnt, pix_kmin, pix_kmax, pix_off;
+    DevBuf items, item_start, item_tab, item_base, pix_cnt, pix_kmin, pix_kmax, pix_off, pix_thick, thick_list;
     DevBuf tile_tot, frag_base, tile_nb, batch_mask, batch_start, batches, frags;
     DevBuf dom_tex, dom_grid, dom_part;      // shadow pass: texels, grids, bounds partials
     int32_t dom_R = 0, dom_K = 0, dom_n = 0;  // last shadowed render: resolution, layers, maps
@@ -191,10 +191,10 @@ void ctx_free(hair_ctx* ctx, DevBuf& b, hair_ws* ws = nullptr) {
 }
 
 // Every device buffer a workspace can hold.
-std::array<DevBuf*, 32> ws_buffers(hair_ws* ws) {
+std::array<DevBuf*, 34> ws_buffers(hair_ws* ws) {
     return {{&ws->seg, &ws->shade, &ws->scan_tmp, &ws->tile_cnt, &ws->tile_start, &ws->bin_m, &ws->bin_blk,
             &ws->sel_cnt, &ws->sel_start, &ws->sel, &ws->sel_tmp, &ws->list, &ws->ctr, &ws->items,
-            &ws->item_start, &ws->item_tab, &ws->item_base, &ws->pix_cnt, &ws->pix_kmin, &ws->pix_kmax, &ws->pix_off,
+            &ws->item_start, &ws->item_tab, &ws->item_base, &ws->pix_cnt, &ws->pix_kmin, &ws->pix_kmax, &ws->pix_off, &ws->pix_thick, &ws->thick_list,
             &ws->tile_tot, &ws->frag_base, &ws->tile_nb, &ws->batch_mask, &ws->batch_start, &ws->batches,
             &ws->frags, &ws->dom_tex, &ws->dom_grid, &ws->dom_part, &ws->pieces}};
 }
@@ -595,6 +595,7 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     if ((rc = ws_need(ws, ws->item_tab, 8ull * caps.items))) return rc;
     for (DevBuf* b : {&ws->pix_cnt, &ws->pix_kmin, &ws->pix_kmax, &ws->pix_off})
         if ((rc = ws_need(ws, *b, 4 * TP))) return rc;
+    if (lv.kind == 2 && (rc = ws_need(ws, ws->pix_thick, TP))) return rc;
     for (DevBuf* b : {&ws->tile_tot, &ws->tile_nb})
         if ((rc = ws_need(ws, *b, 4ull * T))) return rc;
     if ((rc = ws_need(ws, ws->batch_mask, 4ull * T * (kTilePix / 32)))) return rc;
@@ -615,6 +616,7 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     f.pix_kmin = ws->pix_kmin.as<uint32_t>();
     f.pix_kmax = ws->pix_kmax.as<uint32_t>();
     f.pix_off = ws->pix_off.as<uint32_t>();
+    f.pix_thick = lv.kind == 2 ? ws->pix_thick.as<uint8_t>() : nullptr;
     f.tile_tot = ws->tile_tot.as<uint32_t>();
     f.tile_nb = ws->tile_nb.as<uint32_t>();
     f.batch_mask = ws->batch_mask.as<uint32_t>();
@@ -629,7 +631,7 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
             "k_scatter");
     // (a static-scratch frame clears the image only once every buffer has been carved, so that
     // a frame too large for the scratch fails with the caller's image untouched)
-    HIP_TRY(ctx, launch_fill_pix(f.pix_cnt, f.pix_kmin, f.pix_kmax, TP, ws->arena ? nullptr : rgba,
+    HIP_TRY(ctx, launch_fill_pix(f.pix_cnt, f.pix_kmin, f.pix_kmax, f.pix_thick, TP, ws->arena ? nullptr : rgba,
                                  (size_t)cam->width * cam->height, f.item_start, T, ws->item_tab.as<uint2>(),
                                  caps.items, st),
             "fill");
@@ -659,14 +661,17 @@ int run_frame(hair_ctx* ctx, hair_ws* ws, const Asset& a, const LevelDev& lv, co
     }
     if ((rc = ws_need(ws, ws->frags, 8ull * caps.frags))) return rc;
     if ((rc = ws_need(ws, ws->batches, 16ull * caps.batches))) return rc;
+    if (lv.kind == 2 && (rc = ws_need(ws, ws->thick_list, 4ull * caps.batches))) return rc;
     f.frags = ws->frags.as<uint2>();
     f.batches = ws->batches.as<uint4>();
+    f.thick_list = lv.kind == 2 ? ws->thick_list.as<uint32_t>() : nullptr;
     if (ws->arena && rgba)
         HIP_TRY(ctx, launch_fill_f32(rgba, 0.0f, 4ull * cam->width * cam->height, st), "fill");
     if (!fused) HIP_TRY(ctx, launch_check_caps(f, caps, 2, st), "k_check_caps");
     const uint32_t batch_grid = warm ? caps.batches : n_batches;
-    HIP_TRY(ctx, launch_batch_records(f, st), "k_batch_records");
+    // (the batch records follow the emit pass, which marks a mixed frame's thick-hair pixels)
     HIP_TRY(ctx, launch_emit(f, cc, item_grid, st), "k_emit");
+    HIP_TRY(ctx, launch_batch_records(f, st), "k_batch_records");
     HIP_TRY(ctx, hipEventRecord(ws->ev[5], st), "hipEventRecord");
     LightsConst lc = lights_const(lights, n_lights);
     if (views)
@@ -915,10 +920,10 @@ uint64_t hair_ws_estimate(int64_t n_segments, int32_t width, int32_t height, int
     const uint64_t bin_nb = (uint64_t)bin_plan((int32_t)std::min<int64_t>(n_segments, INT32_MAX), (int32_t)T).nb;
     const uint64_t raw = (sizeof(SegRec) + sizeof(ShadeRec)) * (uint64_t)std::max<int64_t>(n_segments, 1) +
                          4ull * (2 * T + 1) + 20ull * bin_nb * T +
-                         4ull * (2 * T + 2) + 4 * P + (4ull * kTilePix + 8) * items +
-                         4ull * 4 * T * kTilePix + 4ull * 4 * (T + 1) + 32 * T + 8 * frags + 16 * (T + frags / 512) +
+                         4ull * (2 * T + 2) + 4 * P + (4ull * kTilePix + 8) * items + 1ull * T * kTilePix +
+                         4ull * 4 * T * kTilePix + 4ull * 4 * (T + 1) + 32 * T + 8 * frags + 20 * (T + frags / 512) +
                          sizeof(Counters) + 4 * exscan_scratch_words(T);
-    return raw + raw / 4 + 25 * 256;
+    return raw + raw / 4 + 27 * 256;
 }
 
 int hair_upload(hair_ctx* ctx, int32_t n_strands, int32_t verts_per_strand, const float* xyz_soa,

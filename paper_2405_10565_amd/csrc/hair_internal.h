@@ -152,6 +152,7 @@ struct Counters {
     uint32_t cap_overflow;   // a frame size exceeded its buffer: the later passes did nothing
     uint32_t split_needed;   // segments culled as too long that pieces can draw (the frame is drawn again)
     uint32_t sizes[4];       // list entries, work items, fragments, batches of the frame
+    uint32_t thick_batches;  // mixed frames: batches holding thick-hair fragments (listed in thick_list)
     unsigned long long phase[8];  // per-phase cycle sums (instrumented builds only)
 };
 
@@ -194,6 +195,10 @@ struct FrameBufs {
     uint32_t* pix_kmin;           // [T][kTilePix] smallest depth key per pixel
     uint32_t* pix_kmax;           // [T][kTilePix] largest depth key per pixel
     uint32_t* pix_off;            // [T][kTilePix] exclusive prefix of pix_cnt within the tile
+    uint8_t* pix_thick;           // [T][kTilePix] mixed frames: the pixel holds a thick-hair fragment
+                                  // (nullptr in frames of one level)
+    uint32_t* thick_list;         // [batches] mixed frames: table positions of the batches holding
+                                  // thick-hair fragments (Counters::thick_batches of them)
     uint32_t* tile_tot;           // [T] fragments per tile
     uint32_t* tile_nb;            // [T] batches per tile
     uint32_t* batch_mask;         // [T][kTilePix / 32] pixels that start a batch
@@ -296,8 +301,9 @@ hipError_t launch_dom_resolve(const FrameBufs& f, const LevelDev& lv, const Shad
                               int32_t R, uint32_t n_blocks, float4* tex, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
 // The frame's per-pixel counters: n counts set to 0, key minima to ~0, key maxima to 0.
-hipError_t launch_fill_pix(uint32_t* cnt, uint32_t* kmin, uint32_t* kmax, size_t n, float* rgba, size_t n_rgba4,
-                           const uint32_t* item_start, int T, uint2* item_tab, uint32_t cap_items, hipStream_t st);   // also clears rgba (n_rgba4 pixels) when given
+hipError_t launch_fill_pix(uint32_t* cnt, uint32_t* kmin, uint32_t* kmax, uint8_t* thick, size_t n, float* rgba,
+                           size_t n_rgba4, const uint32_t* item_start, int T, uint2* item_tab, uint32_t cap_items,
+                           hipStream_t st);   // also clears rgba (n_rgba4 pixels) when given
 hipError_t launch_fill_f32(float* p, float v, size_t n, hipStream_t st);
 hipError_t launch_probe_rate(int kind, int blocks, int iters, float* out, hipStream_t st);
 

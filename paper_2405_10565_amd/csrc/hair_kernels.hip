@@ -70,12 +70,17 @@ struct BatchRec {
     int tile, p0, p1;
     bool over;
     uint32_t frag0, nfrag;
+    bool thick;   // mixed frames: a pixel of the batch holds a thick-hair fragment
 };
-__device__ inline uint4 pack_batch(int tile, int p0, int p1, bool over, uint32_t frag0, uint32_t nfrag) {
-    return make_uint4((uint32_t)tile, (uint32_t)p0 | ((uint32_t)p1 << 9) | (over ? 1u << 18 : 0u), frag0, nfrag);
+__device__ inline uint4 pack_batch(int tile, int p0, int p1, bool over, uint32_t frag0, uint32_t nfrag,
+                                   bool thick = false) {
+    return make_uint4((uint32_t)tile,
+                      (uint32_t)p0 | ((uint32_t)p1 << 9) | (over ? 1u << 18 : 0u) | (thick ? 1u << 19 : 0u), frag0,
+                      nfrag);
 }
 __device__ inline BatchRec unpack_batch(const uint4 r) {
-    return BatchRec{(int)r.x, (int)(r.y & 511u), (int)((r.y >> 9) & 511u), ((r.y >> 18) & 1u) != 0, r.z, r.w};
+    return BatchRec{(int)r.x, (int)(r.y & 511u), (int)((r.y >> 9) & 511u), ((r.y >> 18) & 1u) != 0, r.z, r.w,
+                    ((r.y >> 19) & 1u) != 0};
 }
 
 // ---------------------------------------------------------------------------------------
@@ -522,12 +527,14 @@ __global__ __launch_bounds__(1024) void k_tile_scans(const uint32_t* __restrict_
 // ... and the work-item table of the count and emit passes: item i of tile t (its list chunk
 // i - item_start[t]), for the items within the table's capacity.
 __global__ void k_fill_pix(uint32_t* __restrict__ cnt, uint32_t* __restrict__ kmin, uint32_t* __restrict__ kmax,
-                           size_t n, float4* __restrict__ rgba, size_t n_rgba, const uint32_t* __restrict__ item_start,
-                           int T, uint2* __restrict__ item_tab, uint32_t cap_items) {
+                           uint8_t* __restrict__ thick, size_t n, float4* __restrict__ rgba, size_t n_rgba,
+                           const uint32_t* __restrict__ item_start, int T, uint2* __restrict__ item_tab,
+                           uint32_t cap_items) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         cnt[i] = 0u;
         kmin[i] = 0xFFFFFFFFu;
         kmax[i] = 0u;
+        if (thick) thick[i] = 0;
     }
     // (and the frame's image, transparent black, when one is given)
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_rgba; i += (size_t)gridDim.x * blockDim.x)
@@ -1217,7 +1224,7 @@ template <int KIND, int MODEL, bool SHADOW = false>
 __device__ inline void shade_inputs(const ShadeArgs& a, const SegInputs& in, int pxg, int pyg, float& alpha,
                                     float& hoff, float L[3]) {
     const float sig[3] = {in.q0.w, in.q1.w, in.q2.w};
-    if (KIND == 0 || (KIND == 2 && !(in.s.hwfx & kFlagThick))) {
+    if (KIND == 0 || KIND == 3 || (KIND == 2 && !(in.s.hwfx & kFlagThick))) {
         shade_core<0, MODEL, float, SHADOW>(a, in.s, in.q0, in.q1, in.q2, 1.0f, pxg, pyg, in.s.hw, 0.f, 0.f, 0.f, sig, alpha,
                                     hoff, L);
     } else {
@@ -1374,10 +1381,16 @@ __global__ __launch_bounds__(kNT) void k_tile_prep(FrameBufs f) {
 // The batch table: one record (tile, first pixel, end pixel, oversized) per marked start, in
 // pixel order, at the tile's batch offset.
 __global__ __launch_bounds__(kNT) void k_batch_records(FrameBufs f) {
-    __shared__ uint32_t s_mask[kTilePix / 32];
+    __shared__ uint32_t s_mask[kTilePix / 32], s_thk[kTilePix / 32];
     if (f.ctr->cap_overflow) return;
     const int tile = blockIdx.x, t = threadIdx.x;
     if (t < kTilePix / 32) s_mask[t] = f.batch_mask[(size_t)tile * (kTilePix / 32) + t];
+    // (mixed frames: which pixels hold a thick-hair fragment, as bits)
+    const unsigned long long tb = __ballot(f.pix_thick && f.pix_thick[(size_t)tile * kTilePix + t] != 0);
+    if ((t & 63) == 0) {
+        s_thk[t >> 5] = (uint32_t)tb;
+        s_thk[(t >> 5) + 1] = (uint32_t)(tb >> 32);
+    }
     __syncthreads();
     const int w = t >> 5, b = t & 31;
     if (!((s_mask[w] >> b) & 1u)) return;
@@ -1398,8 +1411,16 @@ __global__ __launch_bounds__(kNT) void k_batch_records(FrameBufs f) {
     const bool oversized = f.pix_cnt[tq + t] > (uint32_t)kCap;
     const uint32_t off0 = f.pix_off[tq + t];
     const uint32_t off1 = end < kTilePix ? f.pix_off[tq + end] : f.tile_tot[tile];
-    f.batches[xcd_block_of(f.batch_start[tile] + idx, f.batch_start[f.T])] =
-        pack_batch(tile, t, end, oversized, f.frag_base[tile] + off0, off1 - off0);
+    bool thick = false;   // a thick-hair fragment in pixels [t, end)
+    for (int k = w; k <= (end - 1) >> 5; ++k) {
+        uint32_t m = s_thk[k];
+        if (k == w) m &= ~((1u << b) - 1u);
+        if (k == (end - 1) >> 5 && ((end - 1) & 31) != 31) m &= (2u << ((end - 1) & 31)) - 1u;
+        thick |= m != 0u;
+    }
+    const uint32_t pos = xcd_block_of(f.batch_start[tile] + idx, f.batch_start[f.T]);
+    f.batches[pos] = pack_batch(tile, t, end, oversized, f.frag_base[tile] + off0, off1 - off0, thick);
+    if (thick) f.thick_list[atomicAdd(&f.ctr->thick_batches, 1u)] = pos;
 }
 
 // Emit pass: every fragment into the frame's fragment buffer at
@@ -1407,7 +1428,9 @@ __global__ __launch_bounds__(kNT) void k_batch_records(FrameBufs f) {
 // pixel's depth-key range (LDS-aggregated per item).
 __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam) {
     __shared__ uint32_t s_cur[kTilePix], s_pos[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix];
-    __shared__ uint32_t s_id[kNT];   // each owner's record word: global segment id or list index
+    __shared__ uint32_t s_id[kNT];   // each owner's record word: global segment id or list index,
+                                     // bit 31: a thick hair of a mixed frame
+    __shared__ uint8_t s_thk[kTilePix];   // mixed frames: the pixel holds a thick-hair fragment
     __shared__ CovSetup s_cov[kNT];
     __shared__ uint8_t s_own[kNT / 64 * kCovLinesPerWave];
     __shared__ float2 s_iz[kNT];
@@ -1422,6 +1445,7 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam) {
     s_cur[t] = 0;
     s_kmin[t] = 0xFFFFFFFFu;
     s_kmax[t] = 0;
+    s_thk[t] = 0;
     s_pos[t] = f.frag_base[tile] + f.pix_off[q] + f.item_base[(size_t)item * kTilePix + t];
     __syncthreads();
     const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
@@ -1435,7 +1459,7 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam) {
         s = f.seg[gseg];
     }
     s_iz[t] = make_float2(s.iza, s.izb);
-    s_id[t] = f.gid ? gseg : j;
+    s_id[t] = (f.gid ? gseg : j) | (f.pix_thick && (s.hwfx & kFlagThick) ? 0x80000000u : 0u);
     const uint32_t total = cov_setup(s, j < n, px0, py0, cam.W, cam.H, s_cov, s_own);
     wave_coverage(s_cov, s_own, total, [&](int p, int tnum, int tden, int o) {
         const float2 iz = s_iz[o];
@@ -1443,12 +1467,15 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam) {
         const uint32_t slot = atomicAdd(&s_cur[p], 1u);
         atomicMin(&s_kmin[p], key);
         atomicMax(&s_kmax[p], key);
-        f.frags[s_pos[p] + slot] = make_uint2(key, s_id[o] | ((uint32_t)p << 24));
+        const uint32_t id = s_id[o];
+        if (id >> 31) s_thk[p] = 1;
+        f.frags[s_pos[p] + slot] = make_uint2(key, (id & 0xFFFFFFu) | ((uint32_t)p << 24));
     });
     __syncthreads();
     if (s_cur[t]) {
         atomicMin(&f.pix_kmin[q], s_kmin[t]);
         atomicMax(&f.pix_kmax[q], s_kmax[t]);
+        if (s_thk[t]) f.pix_thick[q] = 1;
     }
     PHASE_END(f.ctr, 1);
 }
@@ -1679,7 +1706,7 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
     // each fragment's segment inputs are fetched one fragment ahead, so that the gathers
     // overlap the shading arithmetic.  (Not for the R / TT / TRT thick-hair shading: its
     // registers would then exceed the budget of three waves per SIMD.)
-    constexpr bool kAhead = KIND != 2 && (KIND == 0 || MODEL == 1);
+    constexpr bool kAhead = KIND == 0 || KIND == 3 || (KIND == 1 && MODEL == 1);
     const uint32_t run = (Fb + kNT - 1) / kNT;   // at most kPerThread
     const uint32_t rb = min(Fb, t * run), re = min(Fb, rb + run);
     // Mixed frames shade before they blend: a wave whose lanes held both strand and thick-hair
@@ -1930,7 +1957,7 @@ __device__ inline uint32_t refine_slice(uint32_t k, const uint2* __restrict__ sr
 // (LDS holds four blocks per CU; unshadowed strand instances keep their registers within four waves
 // per SIMD, the heavier shading (thick hairs, shadowed strands) within three.)
 template <int KIND, int MODEL, bool SHADOW>
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 && !SHADOW ? 4 : 3))) void k_batch(
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu((KIND == 0 || KIND == 3) && !SHADOW ? 4 : 3))) void k_batch(
     FrameBufs f, ShadeArgs a, float* __restrict__ rgba, DebugDump dbg, int has_dbg) {
     __shared__ uint32_t s_cnt[kTilePix], s_kmin[kTilePix], s_off[kTilePix + 1];
     __shared__ float s_scale[kTilePix];   // count / (key range + 1): the bucket map of the ordering
@@ -1949,9 +1976,25 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(KIND == 0 &
     PHASE_BEGIN();
 
     const uint32_t n_batches = f.batch_start[f.T];
-    const uint4 br = f.batches[blockIdx.x];   // in the table's capacity; used only below n_batches
-    if (blockIdx.x >= n_batches || f.ctr->cap_overflow) return;
+    // Mixed frames take two launches.  When at most an eighth of the batches hold thick-hair
+    // fragments, the strand-only kernel (KIND 3, four waves per SIMD) takes the batches of
+    // strands alone and this one (KIND 2) those holding thick hairs, block b the b-th of their
+    // list (spread over the grid, and so over the XCDs, wherever on screen the thick hairs lie).
+    // Otherwise KIND 2 takes every batch, so that its long thick-hair batches interleave with
+    // the rest, and KIND 3 does nothing.
+    uint32_t bi = blockIdx.x;
+    if (KIND == 2 || KIND == 3) {
+        const bool one = f.thick_list == nullptr || 8u * f.ctr->thick_batches > n_batches;
+        if (KIND == 3 && one) return;
+        if (KIND == 2 && !one) {
+            if (blockIdx.x >= f.ctr->thick_batches) return;
+            bi = f.thick_list[blockIdx.x];
+        }
+    }
+    const uint4 br = f.batches[bi];   // in the table's capacity; used only below n_batches
+    if (bi >= n_batches || f.ctr->cap_overflow) return;
     const BatchRec b = unpack_batch(br);
+    if (KIND == 3 && b.thick) return;
     const int tile = b.tile, p0 = b.p0, p1 = b.p1;
     const int t = threadIdx.x;
     const int px0 = (tile % f.ntx) * kTile, py0 = (tile / f.ntx) * kTile;
@@ -3275,24 +3318,40 @@ hipError_t launch_batches(const FrameBufs& f, const LevelDev& lv, const CamConst
     const dim3 g(n_batches), b(kNT);
     bool shadow = false;
     for (int i = 0; i < lights.n; ++i) shadow |= lights.dom[i].grid != nullptr;
+    if (lv.kind != 2) {
+        if (shadow) {
+            if (mat.model == 0) {
+                if (lv.kind == 0) hipLaunchKernelGGL((k_batch<0, 0, true>), g, b, 0, st, f, a, rgba, d, hd);
+                else hipLaunchKernelGGL((k_batch<1, 0, true>), g, b, 0, st, f, a, rgba, d, hd);
+            } else {
+                if (lv.kind == 0) hipLaunchKernelGGL((k_batch<0, 1, true>), g, b, 0, st, f, a, rgba, d, hd);
+                else hipLaunchKernelGGL((k_batch<1, 1, true>), g, b, 0, st, f, a, rgba, d, hd);
+            }
+        } else if (mat.model == 0) {
+            if (lv.kind == 0) hipLaunchKernelGGL((k_batch<0, 0, false>), g, b, 0, st, f, a, rgba, d, hd);
+            else hipLaunchKernelGGL((k_batch<1, 0, false>), g, b, 0, st, f, a, rgba, d, hd);
+        } else {
+            if (lv.kind == 0) hipLaunchKernelGGL((k_batch<0, 1, false>), g, b, 0, st, f, a, rgba, d, hd);
+            else hipLaunchKernelGGL((k_batch<1, 1, false>), g, b, 0, st, f, a, rgba, d, hd);
+        }
+        return hipGetLastError();
+    }
+    // A mixed frame: the strand-only batches (KIND 3), then those holding thick-hair fragments
+    // (KIND 2); the kernels choose between them on the device (see k_batch).
     if (shadow) {
         if (mat.model == 0) {
-            if (lv.kind == 0) hipLaunchKernelGGL((k_batch<0, 0, true>), g, b, 0, st, f, a, rgba, d, hd);
-            else if (lv.kind == 1) hipLaunchKernelGGL((k_batch<1, 0, true>), g, b, 0, st, f, a, rgba, d, hd);
-            else hipLaunchKernelGGL((k_batch<2, 0, true>), g, b, 0, st, f, a, rgba, d, hd);
+            hipLaunchKernelGGL((k_batch<3, 0, true>), g, b, 0, st, f, a, rgba, d, hd);
+            hipLaunchKernelGGL((k_batch<2, 0, true>), g, b, 0, st, f, a, rgba, d, hd);
         } else {
-            if (lv.kind == 0) hipLaunchKernelGGL((k_batch<0, 1, true>), g, b, 0, st, f, a, rgba, d, hd);
-            else if (lv.kind == 1) hipLaunchKernelGGL((k_batch<1, 1, true>), g, b, 0, st, f, a, rgba, d, hd);
-            else hipLaunchKernelGGL((k_batch<2, 1, true>), g, b, 0, st, f, a, rgba, d, hd);
+            hipLaunchKernelGGL((k_batch<3, 1, true>), g, b, 0, st, f, a, rgba, d, hd);
+            hipLaunchKernelGGL((k_batch<2, 1, true>), g, b, 0, st, f, a, rgba, d, hd);
         }
     } else if (mat.model == 0) {
-        if (lv.kind == 0) hipLaunchKernelGGL((k_batch<0, 0, false>), g, b, 0, st, f, a, rgba, d, hd);
-        else if (lv.kind == 1) hipLaunchKernelGGL((k_batch<1, 0, false>), g, b, 0, st, f, a, rgba, d, hd);
-        else hipLaunchKernelGGL((k_batch<2, 0, false>), g, b, 0, st, f, a, rgba, d, hd);
+        hipLaunchKernelGGL((k_batch<3, 0, false>), g, b, 0, st, f, a, rgba, d, hd);
+        hipLaunchKernelGGL((k_batch<2, 0, false>), g, b, 0, st, f, a, rgba, d, hd);
     } else {
-        if (lv.kind == 0) hipLaunchKernelGGL((k_batch<0, 1, false>), g, b, 0, st, f, a, rgba, d, hd);
-        else if (lv.kind == 1) hipLaunchKernelGGL((k_batch<1, 1, false>), g, b, 0, st, f, a, rgba, d, hd);
-        else hipLaunchKernelGGL((k_batch<2, 1, false>), g, b, 0, st, f, a, rgba, d, hd);
+        hipLaunchKernelGGL((k_batch<3, 1, false>), g, b, 0, st, f, a, rgba, d, hd);
+        hipLaunchKernelGGL((k_batch<2, 1, false>), g, b, 0, st, f, a, rgba, d, hd);
     }
     return hipGetLastError();
 }
@@ -3372,13 +3431,14 @@ hipError_t launch_check_caps(const FrameBufs& f, const FrameCaps& caps, int stag
     return hipGetLastError();
 }
 
-hipError_t launch_fill_pix(uint32_t* cnt, uint32_t* kmin, uint32_t* kmax, size_t n, float* rgba, size_t n_rgba4,
-                           const uint32_t* item_start, int T, uint2* item_tab, uint32_t cap_items, hipStream_t st) {
+hipError_t launch_fill_pix(uint32_t* cnt, uint32_t* kmin, uint32_t* kmax, uint8_t* thick, size_t n, float* rgba,
+                           size_t n_rgba4, const uint32_t* item_start, int T, uint2* item_tab, uint32_t cap_items,
+                           hipStream_t st) {
     const size_t m = std::max(std::max(n, n_rgba4), (size_t)T);
     if (m == 0) return hipSuccess;
     const int nb = (int)std::min<size_t>((m + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_fill_pix, dim3(nb), dim3(256), 0, st, cnt, kmin, kmax, n, reinterpret_cast<float4*>(rgba),
-                       rgba ? n_rgba4 : 0, item_start, T, item_tab, cap_items);
+    hipLaunchKernelGGL(k_fill_pix, dim3(nb), dim3(256), 0, st, cnt, kmin, kmax, thick, n,
+                       reinterpret_cast<float4*>(rgba), rgba ? n_rgba4 : 0, item_start, T, item_tab, cap_items);
     return hipGetLastError();
 }
 

@@ -87,6 +87,28 @@ def test_mixed_frame_matches_oracle_and_updates_levels(hip, scene):
     ws.close()
 
 
+def test_mixed_frame_with_few_thick_cells_matches_oracle(hip, scene):
+    """A frame of strands with a few coarse cells: few batches hold thick-hair fragments, so the
+    strand-only kernel takes most batches and the mixed one takes the listed rest."""
+    print("case: mixed frame, few thick cells", flush=True)
+    ctx, asset, aid, assigns, geoms, grps, cam, lights, eps = scene
+    G, S = ctx.lod_groups(aid), asset.segs
+    rng = np.random.default_rng(11)
+    levels = np.zeros((G, S), dtype=np.int32)
+    pick = rng.choice(G * S, size=max(1, G * S // 150), replace=False)
+    levels.reshape(-1)[pick] = rng.integers(1, 4, size=pick.size)
+    lev = torch.tensor(levels, device="cuda:0")
+    img, st, _ = ctx.render_mixed(aid, cam, lights, lev)
+    torch.cuda.synchronize()
+    mixed = M.mixed_geometry(geoms, grps, levels)
+    assert mixed.thick.any() and mixed.thick.mean() < 0.05
+    ref, ras = R.render(mixed, cam, lights, tuple(float(v) for v in asset.material.as_array()))
+    assert st["fragments"] == len(ras.seg)
+    got = img.cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref) - (RTOL * np.abs(ref) + ATOL)
+    assert int((err > 0).sum()) == 0
+
+
 def test_uniform_mixed_equals_level_render(hip, scene):
     print("case: uniform mixed", flush=True)
     ctx, asset, aid, assigns, geoms, grps, cam, lights, eps = scene
