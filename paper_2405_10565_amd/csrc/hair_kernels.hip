@@ -1426,6 +1426,8 @@ __global__ __launch_bounds__(kNT) void k_batch_records(FrameBufs f) {
 // Emit pass: every fragment into the frame's fragment buffer at
 // frag_base[tile] + pix_off[pixel] + (the item's slice of the pixel) + local slot, and each
 // pixel's depth-key range (LDS-aggregated per item).
+// MIXED: a mixed-level frame, whose thick-hair pixels are marked in f.pix_thick.
+template <bool MIXED>
 __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam) {
     __shared__ uint32_t s_cur[kTilePix], s_pos[kTilePix], s_kmin[kTilePix], s_kmax[kTilePix];
     __shared__ uint32_t s_id[kNT];   // each owner's record word: global segment id or list index,
@@ -1459,7 +1461,7 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam) {
         s = f.seg[gseg];
     }
     s_iz[t] = make_float2(s.iza, s.izb);
-    s_id[t] = (f.gid ? gseg : j) | (f.pix_thick && (s.hwfx & kFlagThick) ? 0x80000000u : 0u);
+    s_id[t] = (f.gid ? gseg : j) | (MIXED && (s.hwfx & kFlagThick) ? 0x80000000u : 0u);
     const uint32_t total = cov_setup(s, j < n, px0, py0, cam.W, cam.H, s_cov, s_own);
     wave_coverage(s_cov, s_own, total, [&](int p, int tnum, int tden, int o) {
         const float2 iz = s_iz[o];
@@ -1468,14 +1470,14 @@ __global__ __launch_bounds__(kNT) void k_emit(FrameBufs f, CamConst cam) {
         atomicMin(&s_kmin[p], key);
         atomicMax(&s_kmax[p], key);
         const uint32_t id = s_id[o];
-        if (id >> 31) s_thk[p] = 1;
+        if (MIXED && (id >> 31)) s_thk[p] = 1;
         f.frags[s_pos[p] + slot] = make_uint2(key, (id & 0xFFFFFFu) | ((uint32_t)p << 24));
     });
     __syncthreads();
     if (s_cur[t]) {
         atomicMin(&f.pix_kmin[q], s_kmin[t]);
         atomicMax(&f.pix_kmax[q], s_kmax[t]);
-        if (s_thk[t]) f.pix_thick[q] = 1;
+        if (MIXED && s_thk[t]) f.pix_thick[q] = 1;
     }
     PHASE_END(f.ctr, 1);
 }
@@ -1774,26 +1776,29 @@ __device__ inline void sort_shade_blend(const FrameBufs& f, const ShadeArgs& a, 
         }
     };
     for (uint32_t i = rb; i < re; ++i) {
-        const uint2 rec = s_B[i];
-        const uint32_t p = rec.y >> 24;
-        const uint32_t p_beg = s_off[p], p_end = s_off[p + 1];
-        if (i == p_beg) { C0 = C1 = C2 = 0.f; T = 1.f; head = 1; }
-        const int gx = px0 + (int)(p % kTile), gy = py0 + (int)(p / kTile);
-        float al, hh, L[3];
+        SegInputs cur{};
         uint32_t gseg = 0;
-        if (KIND == 2 && staged) {
-            const float4 r = s_res[i];
-            al = r.x; L[0] = r.y; L[1] = r.z; L[2] = r.w;
-            hh = 0.f;
-        } else {
-            if (!kAhead) gs[0] = seg_of(rec.y, list, gid);
-            const SegInputs cur = kAhead ? nxt : fetch_segment<KIND>(a, gs[0]);
+        if (!(KIND == 2 && staged)) {   // (the next fragment's inputs are requested first)
+            if (!kAhead) gs[0] = seg_of(s_B[i].y, list, gid);
+            cur = kAhead ? nxt : fetch_segment<KIND>(a, gs[0]);
             gseg = gs[0];
             if (kAhead) {
 #pragma unroll
                 for (int j = 0; j + 1 < (kAhead ? kPerThread : 1); ++j) gs[j] = gs[j + 1];
                 if (i + 1 < re) nxt = fetch_segment<KIND>(a, gs[0]);
             }
+        }
+        const uint2 rec = s_B[i];
+        const uint32_t p = rec.y >> 24;
+        const uint32_t p_beg = s_off[p], p_end = s_off[p + 1];
+        if (i == p_beg) { C0 = C1 = C2 = 0.f; T = 1.f; head = 1; }
+        const int gx = px0 + (int)(p % kTile), gy = py0 + (int)(p / kTile);
+        float al, hh, L[3];
+        if (KIND == 2 && staged) {
+            const float4 r = s_res[i];
+            al = r.x; L[0] = r.y; L[1] = r.z; L[2] = r.w;
+            hh = 0.f;
+        } else {
             shade_inputs<KIND, MODEL, SHADOW>(a, cur, gx, gy, al, hh, L);
         }
         C0 += T * (al * L[0]);
@@ -3299,7 +3304,8 @@ hipError_t launch_batch_records(const FrameBufs& f, hipStream_t st) {
 
 hipError_t launch_emit(const FrameBufs& f, const CamConst& cam, uint32_t grid, hipStream_t st) {
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_emit, dim3(grid), dim3(kNT), 0, st, f, cam);
+    if (f.pix_thick) hipLaunchKernelGGL(k_emit<true>, dim3(grid), dim3(kNT), 0, st, f, cam);
+    else hipLaunchKernelGGL(k_emit<false>, dim3(grid), dim3(kNT), 0, st, f, cam);
     return hipGetLastError();
 }
 
