@@ -197,3 +197,39 @@ def test_mixed_frame_full_size_sampled(hip):
     ws.close()
     ctx.release(aid)
     ctx.close()
+
+
+def test_far_view_lod_frame_matches_oracle(hip):
+    """The regime the LoD is for: a groom of locks (20k strands x 32 segments in locks of 16, a
+    smooth flow; 1250 / 312 / 78 thick hairs by k-means on the strands' paths) at the paper's
+    far view (its bounding sphere covering 0.3% of 1920x1080).  The initial per-(group,
+    segment) levels at eps_w = 2 px equal the oracle's and go mostly coarse, and the whole
+    frame (fragment count and every pixel) matches the oracle."""
+    print("case: far-view LoD frame", flush=True)
+    ctx = hip.Context(0)
+    n = 20000
+    asset = hs.make_asset(n, 32, 90.0, seed=41, sigma_spread=True, clumps=n // 16, flow=0.99)
+    assigns = hs.kmeans_hierarchy(asset, (n // 16, n // 64, n // 256), seed=41, iters=20, features="path")
+    aid = ctx.upload_asset(asset)
+    lods = oracle_levels(ctx, aid, asset, assigns)
+    geoms = M.level_geoms(asset, lods)
+    grps = M.groups(assigns)
+    cam = hs.camera_occupancy(asset, 1920, 1080, 0.003)
+    lights = hs.default_lights(asset, with_point=True)
+    G, S = ctx.lod_groups(aid), asset.segs
+    lev = torch.empty((G, S), dtype=torch.int32, device="cuda:0")
+    ctx.lod_init(aid, cam, 2.0, lev)
+    levels = M.init_levels(geoms, grps, cam, 2.0)
+    assert np.array_equal(lev.cpu().numpy(), levels)
+    assert (levels > 0).mean() > 0.5
+    img, st, _ = ctx.render_mixed(aid, cam, lights, lev)
+    torch.cuda.synchronize()
+    mixed = M.mixed_geometry(geoms, grps, levels)
+    ref, ras = R.render(mixed, cam, lights, tuple(float(v) for v in asset.material.as_array()))
+    assert st["fragments"] == len(ras.seg)
+    got = img.cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref) - (RTOL * np.abs(ref) + ATOL)
+    print(f"far view: {(levels > 0).mean():.3f} of the cells coarse, {len(ras.seg)} fragments, max rel err "
+          f"{float((np.abs(got - ref) / np.maximum(np.abs(ref), 1e-7)).max()):.3e}", flush=True)
+    assert int((err > 0).sum()) == 0
+    ctx.close()
