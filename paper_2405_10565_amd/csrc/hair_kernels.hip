@@ -40,6 +40,20 @@ __device__ inline int wave_max(int v) {
     return v;
 }
 
+// Inclusive prefix sum of x over the 64 lanes of a wave, in lane order, with DPP moves: shifts
+// by 1, 2, 4 and 8 lanes inside each row of 16 (lanes shifted in from outside the row add 0),
+// then the last lane of rows 0 and 2 added to rows 1 and 3, and lane 31 added to rows 2 and 3.
+// (No LDS permutes: six adds with a moved operand.)
+__device__ inline uint32_t wave_inclusive_sum(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);   // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);   // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);   // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);   // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);   // row_bcast:15 -> rows 1, 3
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);   // row_bcast:31 -> rows 2, 3
+    return x;
+}
+
 // Workgroups are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).  Map block b to
 // work index w so that each XCD takes one contiguous range of work: neighbouring work units
 // (batches of one tile, chunks of one list) then share that XCD's L2.
@@ -417,11 +431,7 @@ __global__ __launch_bounds__(1024) void k_scan1(const uint32_t* __restrict__ cnt
             sum += v[k];
         }
         uint32_t x = sum;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(x, off);
-            if (lane >= off) x += y;
-        }
+        x = wave_inclusive_sum(x);
         if (lane == 63) s_w[w] = x;
         __syncthreads();
         uint32_t wbase = 0, total = 0;
@@ -458,11 +468,7 @@ __device__ inline uint32_t block_scan_1024(int n, G get, P put, uint32_t* s_w) {
             sum += v[k];
         }
         uint32_t x = sum;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(x, off);
-            if (lane >= off) x += y;
-        }
+        x = wave_inclusive_sum(x);
         if (lane == 63) s_w[w] = x;
         __syncthreads();
         uint32_t wbase = 0, total = 0;
@@ -883,11 +889,7 @@ __device__ inline uint32_t cov_setup(const SegRec& s, bool valid, int px0, int p
         }
     }
     uint32_t x = nl;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off);
-        if (lane >= off) x += y;
-    }
+    x = wave_inclusive_sum(x);
     const uint32_t excl = x - nl;
     c.g1.w = -(int)excl;     // line index = g1.w + the wave-wide line number
     s_cov[t] = c;
@@ -1243,11 +1245,7 @@ __device__ inline void shade_fragment(const ShadeArgs& a, uint32_t gseg, int pxg
 __device__ inline uint32_t block_exscan_u32(uint32_t v, uint32_t* s_tmp, uint32_t& excl) {
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     uint32_t x = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off);
-        if (lane >= off) x += y;
-    }
+    x = wave_inclusive_sum(x);
     if (lane == 63) s_tmp[wv] = x;
     __syncthreads();
     uint32_t base = 0, total = 0;
