@@ -1,7 +1,7 @@
 """LoD experiments on the GPU library (JSON lines on stdout).
 
     python -m paper_2405_10565_amd.experiments lod-sweep [--scale S]
-    python -m paper_2405_10565_amd.experiments fit [--iters N] [--scale S]
+    python -m paper_2405_10565_amd.experiments fit [--iters N] [--scale S] [--locks]
     python -m paper_2405_10565_amd.experiments shadow [--iters N]
     python -m paper_2405_10565_amd.experiments curved [--scale S]
     python -m paper_2405_10565_amd.experiments views [--scale S]
@@ -88,16 +88,22 @@ def lod_sweep(hctx: B.Context, scale: float = 1.0, repeats: int = 20):
     return out
 
 
-def fit_report(hctx: B.Context, iters: int = 200, scale: float = 1.0, n_fd: int = 20, seed: int = 4004):
+def fit_report(hctx: B.Context, iters: int = 200, scale: float = 1.0, n_fd: int = 20, seed: int = 4004,
+               locks: bool = False):
+    """locks: the groom in 500 locks following a smooth flow (one lock per thick hair, k-means
+    on the strands' paths) instead of the random-walk groom."""
     import torch
     import hairsynth as hs
     from . import fit as F
     from .autograd import render_lod
     c = hs.CONFIGS[4]
     asset, _, lights = hs.config(4, scale)
+    k = max(1, int(round(c["levels"][0] * scale)))
+    if locks:
+        asset = hs.make_asset(asset.n_strands, asset.segs, c["cap"], seed=1004, clumps=k, flow=0.99)
     cams = hs.ring_cameras(asset, c["views"], *c["res"])
     aid = hctx.upload_asset(asset)
-    hctx.build_lod(aid, [hs.kmeans_assign(asset, max(1, int(round(c["levels"][0] * scale))), seed=1004)])
+    hctx.build_lod(aid, [hs.kmeans_assign(asset, k, seed=1004, features="path" if locks else "root")])
     ws = hctx.workspace()
     dev = torch.device(f"cuda:{hctx.device}")
     targets = F.strand_targets(hctx, aid, cams, lights, ws)
@@ -148,7 +154,8 @@ def fit_report(hctx: B.Context, iters: int = 200, scale: float = 1.0, n_fd: int 
     scale_g = max(abs(r[3]) for r in results) if results else 0.0
     passed = sum(abs(fd - an) <= 2e-2 * abs(an) + 5e-3 * scale_g for _, _, fd, an in results)
     res = F.fit_level(hctx, aid, 1, cams, lights, iters=iters, lr=1e-2, ws=ws, targets=targets)
-    out = {"experiment": "fit", "strands": asset.n_strands, "segments": asset.n_segments,
+    out = {"experiment": "fit", "groom": "500 locks, smooth flow" if locks else "random walk",
+           "strands": asset.n_strands, "segments": asset.n_segments,
            "clusters": int(lod0.r.shape[0]), "views": len(cams), "resolution": list(c["res"]),
            "iters": iters, "loss_before": res.loss_history[0], "loss_after": res.loss_history[-1],
            "loss_ratio": res.loss_history[-1] / res.loss_history[0],
@@ -314,6 +321,7 @@ def main():
     ap.add_argument("what", choices=["lod-sweep", "fit", "shadow", "curved", "views"])
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--iters", type=int, default=200)
+    ap.add_argument("--locks", action="store_true", help="fit: a groom of locks instead of the random walk")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available()
@@ -329,7 +337,7 @@ def main():
     elif args.what == "shadow":
         print(json.dumps(shadow_frames(hctx, args.iters if args.iters != 200 else 20)), flush=True)
     else:
-        print(json.dumps(fit_report(hctx, args.iters, args.scale)), flush=True)
+        print(json.dumps(fit_report(hctx, args.iters, args.scale, locks=args.locks)), flush=True)
     hctx.close()
 
 
