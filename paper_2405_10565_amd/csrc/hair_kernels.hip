@@ -545,9 +545,13 @@ __global__ void k_fill_pix(uint32_t* __restrict__ cnt, uint32_t* __restrict__ km
     // (and the frame's image, transparent black, when one is given)
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_rgba; i += (size_t)gridDim.x * blockDim.x)
         rgba[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < T; t += gridDim.x * blockDim.x) {
+    // (one wave per tile, its lanes taking the tile's items in turn: a tile can hold thousands
+    // of items when a whole groom falls into a few tiles)
+    const int lane = threadIdx.x & 63;
+    const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), n_waves = (int)((gridDim.x * blockDim.x) >> 6);
+    for (int t = wave; t < T; t += n_waves) {
         const uint32_t i0 = item_start[t], i1 = min(item_start[t + 1], cap_items);
-        for (uint32_t i = i0; i < i1; ++i) item_tab[i] = make_uint2((uint32_t)t, i - i0);
+        for (uint32_t i = i0 + lane; i < i1; i += 64) item_tab[i] = make_uint2((uint32_t)t, i - i0);
     }
 }
 
@@ -3438,7 +3442,7 @@ hipError_t launch_check_caps(const FrameBufs& f, const FrameCaps& caps, int stag
 hipError_t launch_fill_pix(uint32_t* cnt, uint32_t* kmin, uint32_t* kmax, uint8_t* thick, size_t n, float* rgba,
                            size_t n_rgba4, const uint32_t* item_start, int T, uint2* item_tab, uint32_t cap_items,
                            hipStream_t st) {
-    const size_t m = std::max(std::max(n, n_rgba4), (size_t)T);
+    const size_t m = std::max(std::max(n, n_rgba4), (size_t)T * 64);
     if (m == 0) return hipSuccess;
     const int nb = (int)std::min<size_t>((m + 255) / 256, 4096);
     hipLaunchKernelGGL(k_fill_pix, dim3(nb), dim3(256), 0, st, cnt, kmin, kmax, thick, n,
