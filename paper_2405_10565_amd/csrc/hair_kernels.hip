@@ -1324,13 +1324,15 @@ __global__ __launch_bounds__(kNT) void k_count(FrameBufs f, CamConst cam) {
 // Greedy batch packing of whole pixels: from p0 skip empty pixels, then take the longest run
 // [p0, p1) whose fragments fit one LDS batch; a pixel deeper than a batch is "oversized" and
 // forms a batch of its own.  Every lane finds, in parallel, the next non-empty pixel at or
-// after it and the end of a batch that would start at it; one lane then follows the chain of
-// batch starts and marks them in a 256-bit mask of the tile.  k_batch_records turns the mask
+// after it and the end of a batch that would start at it; the chain of batch starts is then
+// followed (by one lane when it is short, by pointer doubling over all lanes when it is long)
+// and marked in a 256-bit mask of the tile.  k_batch_records turns the mask
 // into the batch table in parallel (a batch runs to the next start, or to the tile's end: the
 // pixels in between are empty).
 __global__ __launch_bounds__(kNT) void k_tile_prep(FrameBufs f) {
     __shared__ uint32_t s_cnt[kTilePix], s_off[kTilePix + 1], s_tmp[kNT];
-    __shared__ uint16_t s_nxt[kTilePix + 1], s_end[kTilePix];
+    __shared__ uint16_t s_nxt[kTilePix + 1], s_end[kTilePix], s_jump[kTilePix + 1];
+    __shared__ uint8_t s_on[kTilePix + 1];
     __shared__ uint32_t s_mask[kTilePix / 32];
     const int tile = blockIdx.x, t = threadIdx.x;
     const size_t q = (size_t)tile * kTilePix + t;
@@ -1365,16 +1367,59 @@ __global__ __launch_bounds__(kNT) void k_tile_prep(FrameBufs f) {
     }
     if (t == 0) s_nxt[kTilePix] = (uint16_t)kTilePix;
     __syncthreads();
-    if (t == 0) {
-        uint32_t nb = 0, over = 0;
-        for (int p = s_nxt[0]; p < kTilePix; p = s_nxt[s_end[p]]) {
-            s_mask[p >> 5] |= 1u << (p & 31);
-            ++nb;
-            over += s_cnt[p] > (uint32_t)kCap;
+    if (total <= 16u * kCap) {   // a short chain (at most ~32 batches): one lane follows it
+        if (t == 0) {
+            uint32_t nb = 0, over = 0;
+            for (int p = s_nxt[0]; p < kTilePix; p = s_nxt[s_end[p]]) {
+                s_mask[p >> 5] |= 1u << (p & 31);
+                ++nb;
+                over += s_cnt[p] > (uint32_t)kCap;
+            }
+            f.tile_tot[tile] = total;
+            f.tile_nb[tile] = nb;
+            if (over) atomicAdd(&f.ctr->deep_pixels, over);
         }
-        f.tile_tot[tile] = total;
-        f.tile_nb[tile] = nb;
-        if (over) atomicAdd(&f.ctr->deep_pixels, over);
+    } else {
+        // a long chain: every pixel marks where its batch's successor starts, and the marks
+        // spread from the first start by pointer doubling (after step k, every start within
+        // 2^(k+1) batches of the first; a tile has at most kTilePix = 2^8 batches).  A mark
+        // seen early only spreads further along the same chain.
+        s_jump[t] = s_nxt[s_end[t]];
+        s_on[t] = 0;
+        if (t == 0) {
+            s_jump[kTilePix] = (uint16_t)kTilePix;
+            s_on[kTilePix] = 0;
+        }
+        __syncthreads();
+        if (t == 0) s_on[s_nxt[0]] = 1;
+        __syncthreads();
+#pragma unroll 1
+        for (int k = 0; k < 8; ++k) {
+            const int j = s_jump[t];
+            if (s_on[t]) s_on[j] = 1;
+            const uint16_t jj = s_jump[j];
+            __syncthreads();
+            s_jump[t] = jj;
+            __syncthreads();
+        }
+        const bool on = s_on[t] != 0;
+        const unsigned long long bm = __ballot(on), om = __ballot(on && c > (uint32_t)kCap);
+        if ((t & 63) == 0) {
+            s_mask[t >> 5] = (uint32_t)bm;
+            s_mask[(t >> 5) + 1] = (uint32_t)(bm >> 32);
+            s_tmp[t >> 6] = (uint32_t)__popcll(bm) | (uint32_t)__popcll(om) << 16;
+        }
+        __syncthreads();
+        if (t == 0) {
+            uint32_t nb = 0, over = 0;
+            for (int w2 = 0; w2 < kNT / 64; ++w2) {
+                nb += s_tmp[w2] & 0xFFFFu;
+                over += s_tmp[w2] >> 16;
+            }
+            f.tile_tot[tile] = total;
+            f.tile_nb[tile] = nb;
+            if (over) atomicAdd(&f.ctr->deep_pixels, over);
+        }
     }
     __syncthreads();
     if (t < kTilePix / 32) f.batch_mask[(size_t)tile * (kTilePix / 32) + t] = s_mask[t];
