@@ -995,6 +995,28 @@ __device__ inline float texel_c(const float4& A, const float4& B, int i) {
     return v;
 }
 
+// delta = |cross| / (16 sqrt(t_den)), the pixel centre's distance from the centre line in pixels,
+// in double: the hardware reciprocal square root refined by one Newton step (relative error
+// near 2^-46).
+__device__ inline double delta_d(int cr, int tden) {
+    const double x = (double)tden;
+    double r = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x * r;
+    r = fma(r, fma(-hx, r, 0.5), r);
+    return fabs((double)cr) * r * 0.0625;
+}
+
+// A strand's coverage alpha = min(hw + delta, 1/2) - max(delta - hw, -1/2), clamped to [0, 1]:
+// at an edge pixel of low coverage it is a small difference of numbers near 1/2, so it is
+// evaluated in double and rounded to float once, and its relative error stays at float
+// precision however small the coverage.
+__device__ inline float strand_alpha(int cr, int tden, float hw, float& delta) {
+    const double dd = delta_d(cr, tden);
+    delta = (float)dd;
+    const double h = (double)hw;
+    return (float)fmin(fmax(fmin(h + dd, 0.5) - fmax(dd - h, -0.5), 0.0), 1.0);
+}
+
 // Hairs in front of (x, y, z): per texel, x_l = (iz0 - iz) / delta - 1 layers behind the first
 // hit (one layer of bias), C_{j-1} + (x_l - j)(C_j - C_{j-1}) inside layer j, C_{K-1} beyond;
 // bilinear over the four nearest texel centres; outside the grid or on empty texels 0.
@@ -1049,23 +1071,19 @@ __device__ inline void shade_core(const ShadeArgs& a, const SegRec& s, const flo
     // (the coverage decision was taken exactly when the fragment was emitted; what follows is
     // continuous, so it uses the hardware reciprocal and reciprocal square root)
     float delta;
-    T d_minus, d_plus;   // delta - hw, delta + hw
-    if (KIND == 1) {
+    if constexpr (KIND == 1) {
         // a thick hair is many pixels wide, so at its footprint's edge alpha = 1/2 - (delta - hw)
         // is a small difference of large numbers; delta is carried as a float pair (hi + lo) from
         // a double evaluation, and hi - hw is exact there (Sterbenz), which keeps alpha's
         // absolute error at the level of a strand's instead of an ulp of the hair width
-        const double dd = fabs((double)cr) / sqrt((double)tden) * (1.0 / 16.0);
+        const double dd = delta_d(cr, tden);
         delta = (float)dd;
         const float dlo = (float)(dd - (double)delta);
-        d_minus = (delta - hw) + dlo;
-        d_plus = (hw + delta) + dlo;
+        const T d_minus = (delta - hw) + dlo, d_plus = (hw + delta) + dlo;
+        alpha = m_min(m_max(m_min(d_plus, T(0.5f)) - m_max(d_minus, T(-0.5f)), T(0.0f)), T(1.0f));
     } else {
-        delta = fabsf((float)cr) * m_rsqrt((float)tden) * (1.0f / 16.0f);
-        d_minus = delta - hw;
-        d_plus = hw + delta;
+        alpha = strand_alpha(cr, tden, hw, delta);
     }
-    alpha = m_min(m_max(m_min(d_plus, T(0.5f)) - m_max(d_minus, T(-0.5f)), T(0.0f)), T(1.0f));
     float sgn = cr > 0 ? 1.0f : (cr < 0 ? -1.0f : 0.0f);
     if (s.hwfx & kFlagNegSide) sgn = -sgn;
     const T h = m_min(m_max((sgn * delta) * m_rcp(hw + 0.5f), T(-1.0f)), T(1.0f));
