@@ -123,6 +123,31 @@ def test_fragment_order_bit_exact(hip, ctx):
     assert counts.max() > 10
 
 
+def test_strand_alpha_at_float_rounding(hip, ctx):
+    """Every fragment of the config-1 frame: the strand coverage alpha (the 1-D box overlap of
+    the pixel with the strand's width at the pixel centre's distance from the centre line)
+    within two float32 roundings of the oracle's float64 value, relative, also at edge pixels
+    of low coverage, where alpha is a small difference of numbers near 1/2."""
+    print("case: strand alpha precision, 1k strands at 256x256, whole frame", flush=True)
+    asset, cam, lights = hs.config(1)
+    aid = ctx.upload_asset(asset)
+    ras = R.rasterize(R.strand_level(asset), cam)
+    W, H = cam.width, cam.height
+    counts, keys, segs, alpha, hoff = ctx.debug_fragments(aid, 0, cam, lights, 0, 0, W, H, cap=len(ras.seg) + 16)
+    rc, rk, rsg, idx = _oracle_lists(ras, 0, 0, W, H, W)
+    assert np.array_equal(counts, rc) and np.array_equal(keys, rk) and np.array_equal(segs, rsg)
+    hw = ras.hw[ras.seg].astype(np.float64)[idx]
+    a_ref = R.fragment_alpha_h(ras, R._t(ras.hw[ras.seg]))[0].numpy()[idx]
+    delta = (np.abs(ras.cross.astype(np.float64)) / np.sqrt(ras.t_den.astype(np.float64)) / 16.0)[idx]
+    err = np.abs(alpha.astype(np.float64) - a_ref)
+    rel = err / np.maximum(a_ref, 1e-30)
+    edge = (delta + hw > 0.5) & (a_ref > 0)   # alpha = 1/2 - (delta - hw): the cancelling form
+    print(f"alpha: {len(a_ref)} fragments, {int(edge.sum())} at the strands' edges, max rel err "
+          f"{float(rel[a_ref > 0].max()):.3e} (edges {float(rel[edge].max()):.3e})", flush=True)
+    assert int(edge.sum()) > 1000
+    assert np.all(err <= 2.0 ** -23 * a_ref + 1e-30)
+
+
 @pytest.mark.parametrize("W,H", [(17, 9), (1, 1), (33, 47)])
 def test_ragged_and_tiny_images(hip, ctx, W, H):
     print(f"case: ragged {W}x{H}", flush=True)
